@@ -1,0 +1,269 @@
+"""Plain FP64 CPU oracle for the cubed-sphere shell solver (test infrastructure).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It wraps ``csdyn_ref.c`` (plain C, no
+shared code with the HIP path) through ctypes, plus a few NumPy helpers.
+
+Every function follows a passage of Yin et al., arXiv 2009.02171:
+the grid and metric (Sec. 3.2), the finite-volume operators (Sec. 3.2,
+eq. divdiscretization), the two systems of the approximate factorization
+(Sec. 3.1), the RAS / two-level preconditioners (Sec. 3.3, eq. onelevel,
+twolevel) and right-preconditioned restarted GMRES (Sec. 3.3).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "csdyn_ref.c")
+_LIB = os.path.join(_HERE, "libcsdyn_ref.so")
+
+OK, ENOTCONV, EINVAL, EZEROPIVOT, ENOMEM, EBREAKDOWN = 0, 1, -1, -3, -4, -5
+RI, RO = 7.0 / 13.0, 20.0 / 13.0   # Sec. 2: r_i = 7/13, r_o = 20/13
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", _LIB, _SRC, "-lm"])
+    return _LIB
+
+
+class Grid(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nr", C.c_int32), ("ri", C.c_double), ("ro", C.c_double)]
+
+
+class Op(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dt", C.c_double), ("ekman", C.c_double), ("pm", C.c_double)]
+
+
+class RasOpts(C.Structure):
+    _fields_ = [("sub", C.c_int32 * 3), ("overlap", C.c_int32), ("levels", C.c_int32),
+                ("coarse_rtol", C.c_double), ("coarse_restart", C.c_int32), ("coarse_maxit", C.c_int32),
+                ("precision", C.c_int32)]
+
+
+class GmresOpts(C.Structure):
+    _fields_ = [("restart", C.c_int32), ("maxit", C.c_int32), ("flexible", C.c_int32),
+                ("rtol", C.c_double), ("atol", C.c_double)]
+
+
+class GmresStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("inner_iters", C.c_int64),
+                ("relres_true", C.c_double), ("relres_est", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        P = C.POINTER
+        d, i32, i64 = P(C.c_double), P(C.c_int32), P(C.c_int64)
+        _lib.ref_cell_geometry.argtypes = [P(Grid), d, d]
+        _lib.ref_metric.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, d, d, d]
+        _lib.ref_seam_tables.argtypes = [P(Grid), i32, i32, i32, i32, d, i32, i32, i32]
+        _lib.ref_operator_apply.argtypes = [P(Grid), P(Op), d, d]
+        _lib.ref_operator_rows.argtypes = [P(Grid), P(Op), d, C.c_int64, i64, d]
+        _lib.ref_assemble.argtypes = [P(Grid), P(Op), i64, i32, d]
+        _lib.ref_pc_setup.argtypes = [P(Grid), P(Op), P(RasOpts), P(C.c_void_p)]
+        _lib.ref_pc_destroy.argtypes = [C.c_void_p]
+        _lib.ref_pc_destroy.restype = None
+        _lib.ref_pc_apply.argtypes = [C.c_void_p, d, d]
+        _lib.ref_pc_subdomain.argtypes = [C.c_void_p, C.c_int, C.c_int, i64, i64, i64, i32, i64, i32, d]
+        _lib.ref_pc_count.argtypes = [C.c_void_p, C.c_int]
+        _lib.ref_ilu0_csr.argtypes = [C.c_int64, i64, i32, d]
+        _lib.ref_gmres_solve.argtypes = [P(Grid), P(Op), C.c_void_p, P(GmresOpts), d, d, P(GmresStats)]
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _lp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int64))
+
+
+def _check(rc, what):
+    if rc < 0:
+        raise RuntimeError(f"oracle {what} failed with status {rc}")
+    return rc
+
+
+@dataclass(frozen=True)
+class Problem:
+    """A grid (N x N x Nr cells per panel, Sec. 3.2) and one of the two systems."""
+    n: int
+    nr: int
+    kind: int = 0            # 0 velocity-pressure, 1 magnetic / pseudo-pressure
+    dt: float = 1e-4
+    ekman: float = 1e-3
+    pm: float = 5.0
+    ri: float = RI
+    ro: float = RO
+
+    def grid(self):
+        return Grid(self.n, self.nr, self.ri, self.ro)
+
+    def op(self):
+        return Op(self.kind, self.dt, self.ekman, self.pm)
+
+    @property
+    def ncell(self):
+        return 6 * self.n * self.n * self.nr
+
+    @property
+    def nunk(self):
+        return 4 * self.ncell
+
+    def shape(self):
+        return (6, self.nr, self.n, self.n, 4)
+
+
+def cell_geometry(pb: Problem):
+    """Cell-centre Cartesian coordinates [6,Nr,N,N,3] and volumes V = sqrt(g) hs^2 hr."""
+    xyz = np.zeros((6, pb.nr, pb.n, pb.n, 3))
+    vol = np.zeros((6, pb.nr, pb.n, pb.n))
+    _check(lib().ref_cell_geometry(C.byref(pb.grid()), _dp(xyz), _dp(vol)), "geometry")
+    return xyz, vol
+
+
+def metric(p: int, xi: float, eta: float, r: float):
+    sg = C.c_double()
+    gcov = np.zeros(9)
+    gcon = np.zeros(9)
+    lib().ref_metric(p, xi, eta, r, C.byref(sg), _dp(gcov), _dp(gcon))
+    return sg.value, gcov.reshape(3, 3), gcon.reshape(3, 3)
+
+
+def seam_tables(pb: Problem):
+    n = pb.n
+    gq, gfix, gidx, gm0 = (np.zeros(24 * n, np.int32) for _ in range(4))
+    gw = np.zeros(24 * n * 4)
+    fq, feq, ftq = (np.zeros(24 * n, np.int32) for _ in range(3))
+    _check(lib().ref_seam_tables(C.byref(pb.grid()), _ip(gq), _ip(gfix), _ip(gidx), _ip(gm0), _dp(gw),
+                                 _ip(fq), _ip(feq), _ip(ftq)), "seam tables")
+    sh = (6, 4, n)
+    return dict(q=gq.reshape(sh), fix_i=gfix.reshape(sh), idx=gidx.reshape(sh), m0=gm0.reshape(sh),
+                w=gw.reshape(6, 4, n, 4), face_q=fq.reshape(sh), face_e=feq.reshape(sh), face_t=ftq.reshape(sh))
+
+
+def apply(pb: Problem, x: np.ndarray) -> np.ndarray:
+    """y = A x row by row from the stencil definition (Sec. 3.2)."""
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
+    y = np.zeros_like(x)
+    _check(lib().ref_operator_apply(C.byref(pb.grid()), C.byref(pb.op()), _dp(x), _dp(y)), "apply")
+    return y.reshape(pb.shape())
+
+
+def apply_rows(pb: Problem, x: np.ndarray, rows: np.ndarray) -> np.ndarray:
+    """(A x)[rows] for selected flat row indices (sampled checks at full size)."""
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    y = np.zeros(rows.size)
+    _check(lib().ref_operator_rows(C.byref(pb.grid()), C.byref(pb.op()), _dp(x), rows.size, _lp(rows), _dp(y)),
+           "apply_rows")
+    return y
+
+
+def assemble(pb: Problem):
+    """Global CSR (scipy) of A with the structural pattern."""
+    import scipy.sparse as sp
+    nrow = pb.nunk
+    rp = np.zeros(nrow + 1, np.int64)
+    _check(lib().ref_assemble(C.byref(pb.grid()), C.byref(pb.op()), _lp(rp), None, None), "assemble")
+    ci = np.zeros(rp[-1], np.int32)
+    v = np.zeros(rp[-1])
+    _check(lib().ref_assemble(C.byref(pb.grid()), C.byref(pb.op()), _lp(rp), _ip(ci), _dp(v)), "assemble")
+    return sp.csr_matrix((v, ci, rp), shape=(nrow, nrow))
+
+
+class Preconditioner:
+    """One-level RAS / two-level hybrid RAS with ILU(0) (Sec. 3.3)."""
+
+    def __init__(self, pb: Problem, sub=(4, 4, 4), overlap=1, levels=1, coarse_rtol=0.1,
+                 coarse_restart=30, coarse_maxit=200, precision=0):
+        self.pb = pb
+        o = RasOpts((C.c_int32 * 3)(*sub), overlap, levels, coarse_rtol, coarse_restart, coarse_maxit, precision)
+        h = C.c_void_p()
+        rc = lib().ref_pc_setup(C.byref(pb.grid()), C.byref(pb.op()), C.byref(o), C.byref(h))
+        self.status = rc
+        _check(rc, "pc setup")
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            lib().ref_pc_destroy(h)
+            self.h = None
+
+    def apply(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
+        y = np.zeros_like(x)
+        lib().ref_pc_apply(self.h, _dp(x), _dp(y))
+        return y.reshape(self.pb.shape())
+
+    def count(self, coarse=False):
+        return lib().ref_pc_count(self.h, int(coarse))
+
+    def subdomain(self, s, coarse=False):
+        """Local cells, owned flags and the ILU(0) factors (L strictly lower, U upper) as CSR."""
+        import scipy.sparse as sp
+        nloc, nnz = C.c_int64(), C.c_int64()
+        _check(lib().ref_pc_subdomain(self.h, int(coarse), s, C.byref(nloc), C.byref(nnz), None, None, None, None,
+                                      None), "subdomain")
+        gcell = np.zeros(nloc.value, np.int64)
+        owned = np.zeros(nloc.value, np.int32)
+        rp = np.zeros(4 * nloc.value + 1, np.int64)
+        ci = np.zeros(nnz.value, np.int32)
+        v = np.zeros(nnz.value)
+        lib().ref_pc_subdomain(self.h, int(coarse), s, C.byref(nloc), C.byref(nnz), _lp(gcell), _ip(owned), _lp(rp),
+                               _ip(ci), _dp(v))
+        m = 4 * nloc.value
+        return gcell, owned.astype(bool), sp.csr_matrix((v, ci, rp), shape=(m, m))
+
+
+def gmres(pb: Problem, b, x0=None, pc: Preconditioner | None = None, restart=30, maxit=1000, flexible=False,
+          rtol=1e-8, atol=0.0):
+    """Right-preconditioned restarted (F)GMRES (Sec. 3.3).  Returns (x, stats, status)."""
+    b = np.ascontiguousarray(b, dtype=np.float64).reshape(-1)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64).reshape(-1)
+    st = GmresStats()
+    o = GmresOpts(restart, maxit, int(flexible), rtol, atol)
+    rc = lib().ref_gmres_solve(C.byref(pb.grid()), C.byref(pb.op()), pc.h if pc else None, C.byref(o), _dp(b),
+                               _dp(x), C.byref(st))
+    stats = dict(iters=st.iters, restarts=st.restarts, inner_iters=st.inner_iters, relres_true=st.relres_true,
+                 relres_est=st.relres_est)
+    return x.reshape(pb.shape()), stats, rc
+
+
+def ilu0(a):
+    """ILU(0) of a scipy CSR matrix (sorted indices); returns (status, factors as CSR)."""
+    a = a.tocsr().copy()
+    a.sort_indices()
+    rp = a.indptr.astype(np.int64)
+    ci = a.indices.astype(np.int32)
+    v = a.data.astype(np.float64).copy()
+    rc = lib().ref_ilu0_csr(a.shape[0], _lp(rp), _ip(ci), _dp(v))
+    import scipy.sparse as sp
+    return rc, sp.csr_matrix((v, ci, rp), shape=a.shape)
+
+
+def project_pressure(pb: Problem, b):
+    """Zero volume-weighted mean of the scalar component (Neumann solvability)."""
+    _, vol = cell_geometry(pb)
+    b = np.array(b, dtype=np.float64).reshape(pb.shape())
+    b[..., 3] -= (vol * b[..., 3]).sum() / vol.sum()
+    return b

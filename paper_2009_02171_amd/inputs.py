@@ -1,0 +1,77 @@
+"""Seeded synthetic inputs shared by the HIP path and the oracle.
+
+This module holds none of the solver's arithmetic: it only samples a smooth
+random field on the cubed-sphere cell centres.  Right-hand side recipe per
+component c: a sum of real orthonormal spherical harmonics Y_lm (l <= 8) times
+Chebyshev polynomials T_q (q <= 4) of the normalised radius, with N(0,1)
+coefficients, plus U(-1e-3, 1e-3) noise per unknown.  All coefficients are
+drawn first, then the noise, from numpy's PCG64 ``default_rng(seed)``.
+
+Cell centres follow the grid of Sec. 3.2 (xi_i = -pi/4 + (i+1/2) h_s,
+r_k = r_i + (k+1/2) h_r) with panels 0-3 equatorial (+x, +y, -x, -y),
+4 = +z and 5 = -z.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+LMAX, QMAX = 8, 4
+RI, RO = 7.0 / 13.0, 20.0 / 13.0
+
+# global = M[p] @ (1, tan xi, tan eta)
+_PANELS = np.array([
+    [[1, 0, 0], [0, 1, 0], [0, 0, 1]],
+    [[0, -1, 0], [1, 0, 0], [0, 0, 1]],
+    [[-1, 0, 0], [0, -1, 0], [0, 0, 1]],
+    [[0, 1, 0], [-1, 0, 0], [0, 0, 1]],
+    [[0, 0, -1], [0, 1, 0], [1, 0, 0]],
+    [[0, 0, 1], [0, 1, 0], [-1, 0, 0]],
+], dtype=np.float64)
+
+
+def cell_directions(n: int) -> np.ndarray:
+    """Unit vectors to the (xi, eta) cell centres, [6, N, N, 3] indexed [p, j, i]."""
+    h = np.pi / (2 * n)
+    a = -np.pi / 4 + (np.arange(n) + 0.5) * h
+    X = np.tan(a)[None, :]
+    Y = np.tan(a)[:, None]
+    loc = np.stack([np.ones((n, n)), np.broadcast_to(X, (n, n)), np.broadcast_to(Y, (n, n))], -1)
+    loc /= np.linalg.norm(loc, axis=-1, keepdims=True)
+    return np.einsum("pab,jib->pjia", _PANELS, loc)
+
+
+def _real_sph(lmax: int, theta: np.ndarray, phi: np.ndarray) -> np.ndarray:
+    from scipy.special import sph_harm_y
+    cols = []
+    for l in range(lmax + 1):
+        for m in range(-l, l + 1):
+            y = sph_harm_y(l, abs(m), theta, phi)
+            if m > 0:
+                cols.append(np.sqrt(2.0) * (-1) ** m * y.real)
+            elif m < 0:
+                cols.append(np.sqrt(2.0) * (-1) ** m * y.imag)
+            else:
+                cols.append(y.real)
+    return np.stack(cols, -1)
+
+
+def rhs(n: int, nr: int, seed: int, ri: float = RI, ro: float = RO, noise: float = 1e-3) -> np.ndarray:
+    """Seeded right-hand side, float64 [6, Nr, N, N, 4] (panel, k, j, i, component)."""
+    rng = np.random.default_rng(seed)
+    nlm = (LMAX + 1) ** 2
+    coef = rng.standard_normal((4, nlm, QMAX + 1))
+    d = cell_directions(n)
+    theta = np.arccos(np.clip(d[..., 2], -1.0, 1.0))
+    phi = np.arctan2(d[..., 1], d[..., 0])
+    Y = _real_sph(LMAX, theta, phi)                       # [6, N, N, nlm]
+    r = ri + (np.arange(nr) + 0.5) * (ro - ri) / nr
+    s = 2.0 * (r - ri) / (ro - ri) - 1.0
+    T = np.polynomial.chebyshev.chebvander(s, QMAX)       # [Nr, 5]
+    b = np.einsum("pjil,kq,clq->pkjic", Y, T, coef, optimize=True)
+    b += rng.uniform(-noise, noise, size=b.shape)
+    return np.ascontiguousarray(b)
+
+
+def random_field(shape, seed: int) -> np.ndarray:
+    """Plain seeded N(0,1) array (operator and preconditioner probes)."""
+    return np.random.default_rng(seed).standard_normal(shape)
