@@ -1,0 +1,171 @@
+/*
+ * csdyn.h -- C ABI of libcsdyn, an MI355X (gfx950) solver for the two linear
+ * systems that the approximate-factorization time step of the spherical-shell
+ * dynamo produces (Yin et al., arXiv 2009.02171, Sec. 3.1-3.3).
+ *
+ * Problem statement (Sec. 3.3, eq. newlinear and the stopping rule after it):
+ * solve A x = b by restarted GMRES, right-preconditioned (A M^{-1} x' = b,
+ * x = M^{-1} x'), starting from a caller-supplied x0, until
+ * ||b - A x|| <= max(atol, rtol * ||b - A x0||).  M^{-1} is restricted
+ * additive Schwarz with ILU(0) subdomain solves (eq. onelevel), optionally
+ * combined with a coarse-grid solve as the hybrid two-level preconditioner
+ * (eq. twolevel, coarsesolve, finesolve).
+ *
+ * Grid (Sec. 3.2): six panels of N x N x Nr cells of the equiangular gnomonic
+ * cubed-sphere shell r_i <= r <= r_o, cell centres
+ *   xi_i = -pi/4 + (i+1/2) h_s,  eta_j = -pi/4 + (j+1/2) h_s,
+ *   r_k = r_i + (k+1/2) h_r,  h_s = pi/(2N),  h_r = (r_o - r_i)/Nr.
+ * Panels 0-3 are centred on +x, +y, -x, -y (xi eastward, eta northward),
+ * panel 4 on +z and panel 5 on -z.
+ *
+ * Vector layout (every x, y, b): double v[6][Nr][N][N][4], contiguous, i
+ * fastest within a row, then j, then k, then panel; the 4 components of a
+ * cell are its Cartesian vector (x, y, z) and its scalar:
+ *   kind VP: (u~, P)   -- velocity-pressure system,
+ *   kind BP: (B~, P_b) -- magnetic-field / pseudo-pressure system.
+ * Rows of A (E = Ekman number, Pm = magnetic Prandtl number):
+ *   VP: u - dt (E lap u - 2 zhat x u);   D(u) - dt lap_N P   (Neumann P)
+ *   BP: B - dt (E/Pm) lap B;             D(B) - dt lap_D P_b (Dirichlet P_b)
+ * with finite-volume lap and D (eq. divdiscretization), no-slip u, and the
+ * pseudo-vacuum condition on B (eq. pvc: tangential B = 0,
+ * d(r^2 B_r)/dr = 0 at the walls).
+ *
+ * Memory: the caller owns every device buffer.  Each *_setup takes a device
+ * workspace of at least *_workspace_bytes() bytes; handles are small host
+ * structs that point into it, so the workspace must outlive the handle.  No
+ * entry point allocates device memory after setup.
+ * Streams: `stream` is a hipStream_t (NULL = the null stream).  Apply calls
+ * are asynchronous on it; csdyn_gmres_solve returns after the solve.
+ * Errors: every call returns an int32 status; csdyn_last_error() gives a
+ * thread-local message for the last failure on the calling thread.
+ */
+#ifndef CSDYN_H
+#define CSDYN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CSDYN_OK 0
+#define CSDYN_ENOTCONV 1      /* outputs valid, tolerance not reached within maxit */
+#define CSDYN_EINVAL (-1)     /* null/aliased pointer, bad shape or option */
+#define CSDYN_EHIP (-2)       /* a HIP runtime call failed */
+#define CSDYN_EZEROPIVOT (-3) /* |pivot| < 1e-300 in an ILU(0) factorization */
+#define CSDYN_ENOMEM (-4)     /* workspace smaller than *_workspace_bytes() */
+#define CSDYN_EBREAKDOWN (-5) /* NaN or Inf met in the solve */
+
+#define CSDYN_VP 0
+#define CSDYN_BP 1
+
+typedef struct {
+    int32_t n;   /* cells per panel edge, N >= 4 */
+    int32_t nr;  /* radial cells, Nr >= 1 */
+    double ri;   /* inner radius (the paper uses 7/13) */
+    double ro;   /* outer radius (the paper uses 20/13) */
+} csdyn_grid;
+
+typedef struct {
+    int32_t kind;  /* CSDYN_VP or CSDYN_BP */
+    double dt;     /* time-step factor of the rows above (> 0 for a nonsingular ILU) */
+    double ekman;  /* E */
+    double pm;     /* Pm (BP only) */
+} csdyn_op;
+
+/* ---------------------------------------------------------------- operator
+ * Matrix-free y = A x (Sec. 3.2): ghost fill across panel edges (cubic
+ * interpolation along the neighbour's first cell layer), conservative
+ * edge fluxes (mean of the two panels' one-sided fluxes), wall ghosts, and
+ * the 11-point finite-volume stencil.  The workspace holds the metric tables
+ * (r-independent 2-D tables shared by the six panels) and the edge buffers.
+ * csdyn_op_setup uploads the tables (synchronous); csdyn_operator_apply
+ * launches three kernels on `stream`.  x and y are device pointers of
+ * 24*N*N*Nr doubles and must not alias (CSDYN_EINVAL). */
+typedef struct csdyn_opctx csdyn_opctx;
+int32_t csdyn_op_workspace_bytes(const csdyn_grid *g, size_t *bytes);
+int32_t csdyn_op_setup(const csdyn_grid *g, const csdyn_op *op, void *ws, size_t ws_bytes, void *stream,
+                       csdyn_opctx **out);
+int32_t csdyn_operator_apply(const csdyn_opctx *ctx, const double *x, double *y, void *stream);
+void csdyn_op_destroy(csdyn_opctx *ctx);
+
+/* ---------------------------------------------------------- preconditioner
+ * Restricted additive Schwarz (eq. onelevel): each panel is cut into
+ * (N/sub[0]) x (N/sub[1]) x (Nr/sub[2]) boxes; each box is extended by
+ * `overlap` (0 or 1) cell layers, across panel edges into the neighbour's
+ * first layer; A_i = R_i A R_i^T with the structural stencil pattern is
+ * factored by point-wise ILU(0) in box-lexicographic order (i fastest, cell-
+ * major, component-minor); the apply gathers x on each extended box, runs the
+ * L and U sweeps, and writes y on the owned box only.
+ * levels = 2 adds the hybrid coarse correction (eq. twolevel):
+ *   w = I_c^f A_c^{-1} I_f^c x  (I_f^c: mean of 8 children, I_c^f: copy;
+ *        A_c re-discretised on N/2 x N/2 x Nr/2; A_c^{-1} by GMRES(coarse_restart)
+ *        to relative tolerance coarse_rtol from 0, preconditioned by one-level
+ *        RAS with sub/2 boxes),
+ *   y = w + M_one^{-1}(x - A_f w).
+ * For VP the coarse right-hand side's pressure part is projected to zero
+ * volume-weighted mean (the coarse Neumann problem's solvability condition).
+ * precision = 1 stores the factors in FP32 and runs every operation inside
+ * M^{-1} in FP32; x and y stay FP64.
+ * Setup assembles and factors on the host, then uploads (synchronous).
+ * Errors: CSDYN_EINVAL if N or Nr is not divisible by sub (or by 2*sub for
+ * levels = 2); CSDYN_EZEROPIVOT from the factorization. */
+typedef struct {
+    int32_t sub[3];          /* owned box size in cells (xi, eta, r) */
+    int32_t overlap;         /* 0 or 1 */
+    int32_t levels;          /* 1 or 2 */
+    double coarse_rtol;      /* 0.1 in the paper */
+    int32_t coarse_restart;  /* 30 */
+    int32_t coarse_maxit;    /* cap on inner iterations per coarse solve */
+    int32_t precision;       /* 0 FP64, 1 FP32 inside the preconditioner */
+} csdyn_ras_opts;
+
+typedef struct csdyn_ras csdyn_ras;
+int32_t csdyn_ras_workspace_bytes(const csdyn_opctx *ctx, const csdyn_ras_opts *o, size_t *bytes);
+int32_t csdyn_ras_setup(const csdyn_opctx *ctx, const csdyn_ras_opts *o, void *ws, size_t ws_bytes, void *stream,
+                        csdyn_ras **out);
+/* y = M^{-1} x; x, y device pointers (FP64), must not alias.  One-level is
+ * asynchronous; two-level synchronises with the host once per inner
+ * iteration (convergence test of the coarse GMRES). */
+int32_t csdyn_ras_apply(const csdyn_ras *pc, const double *x, double *y, void *stream);
+void csdyn_ras_destroy(csdyn_ras *pc);
+
+/* ------------------------------------------------------------------- GMRES
+ * Right-preconditioned restarted GMRES(restart) (Sec. 3.3); flexible = 1 is
+ * FGMRES, required when M^{-1} contains an inner Krylov solve or FP32
+ * arithmetic.  Orthogonalisation: classical Gram-Schmidt with one
+ * re-orthogonalisation pass when the norm drops below 1/sqrt(2) of its value
+ * (same Krylov space as modified Gram-Schmidt).  Stops when the residual
+ * estimate <= max(atol, rtol * ||b - A x0||); then recomputes the true
+ * residual.  For VP, b's pressure part is first projected to zero
+ * volume-weighted mean and the solution's pressure is returned with zero
+ * volume-weighted mean (the Neumann null space).
+ * b: device, const; x: device, in x0 / out solution.  pc may be NULL.
+ * Blocks until done; returns CSDYN_ENOTCONV if maxit was reached. */
+typedef struct {
+    int32_t restart;   /* 30 */
+    int32_t maxit;     /* total Arnoldi steps */
+    int32_t flexible;  /* 0 GMRES, 1 FGMRES */
+    double rtol, atol;
+} csdyn_gmres_opts;
+
+typedef struct {
+    int32_t iters, restarts;
+    int64_t inner_iters;     /* coarse GMRES iterations summed over the solve */
+    double relres_true;      /* ||b - A x|| / ||b - A x0|| recomputed at the end */
+    double relres_est;       /* the GMRES estimate at exit */
+    double t_ms[8];          /* operator, pc-fine, pc-coarse, pc-intermediate, orthogonalisation, other */
+} csdyn_gmres_stats;
+
+int32_t csdyn_gmres_workspace_bytes(const csdyn_opctx *ctx, const csdyn_gmres_opts *o, size_t *bytes);
+int32_t csdyn_gmres_solve(const csdyn_opctx *ctx, const csdyn_ras *pc, const csdyn_gmres_opts *o, const double *b,
+                          double *x, void *ws, size_t ws_bytes, void *stream, csdyn_gmres_stats *st);
+
+/* Thread-local text of the last error on this thread ("" if none). */
+const char *csdyn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,196 @@
+"""Thin ctypes binding of libcsdyn (include/csdyn.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  PyTorch provides device memory (workspaces, vectors) and the
+current stream.  The library must be built (``python -m
+paper_2009_02171_amd.build``); importing this module on a machine where it
+is missing raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcsdyn.so")
+
+OK, ENOTCONV, EINVAL, EHIP, EZEROPIVOT, ENOMEM, EBREAKDOWN = 0, 1, -1, -2, -3, -4, -5
+VP, BP = 0, 1
+RI, RO = 7.0 / 13.0, 20.0 / 13.0
+
+
+class Grid(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nr", C.c_int32), ("ri", C.c_double), ("ro", C.c_double)]
+
+
+class OpDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dt", C.c_double), ("ekman", C.c_double), ("pm", C.c_double)]
+
+
+class RasOpts(C.Structure):
+    _fields_ = [("sub", C.c_int32 * 3), ("overlap", C.c_int32), ("levels", C.c_int32),
+                ("coarse_rtol", C.c_double), ("coarse_restart", C.c_int32), ("coarse_maxit", C.c_int32),
+                ("precision", C.c_int32)]
+
+
+class GmresOpts(C.Structure):
+    _fields_ = [("restart", C.c_int32), ("maxit", C.c_int32), ("flexible", C.c_int32),
+                ("rtol", C.c_double), ("atol", C.c_double)]
+
+
+class GmresStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("inner_iters", C.c_int64),
+                ("relres_true", C.c_double), ("relres_est", C.c_double), ("t_ms", C.c_double * 8)]
+
+
+# Exported symbols and their signatures, as declared in include/csdyn.h.
+_P = C.POINTER
+SIGNATURES = {
+    "csdyn_op_workspace_bytes": (C.c_int32, [_P(Grid), _P(C.c_size_t)]),
+    "csdyn_op_setup": (C.c_int32, [_P(Grid), _P(OpDesc), C.c_void_p, C.c_size_t, C.c_void_p, _P(C.c_void_p)]),
+    "csdyn_operator_apply": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "csdyn_op_destroy": (None, [C.c_void_p]),
+    "csdyn_ras_workspace_bytes": (C.c_int32, [C.c_void_p, _P(RasOpts), _P(C.c_size_t)]),
+    "csdyn_ras_setup": (C.c_int32, [C.c_void_p, _P(RasOpts), C.c_void_p, C.c_size_t, C.c_void_p, _P(C.c_void_p)]),
+    "csdyn_ras_apply": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "csdyn_ras_destroy": (None, [C.c_void_p]),
+    "csdyn_gmres_workspace_bytes": (C.c_int32, [C.c_void_p, _P(GmresOpts), _P(C.c_size_t)]),
+    "csdyn_gmres_solve": (C.c_int32, [C.c_void_p, C.c_void_p, _P(GmresOpts), C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_size_t, C.c_void_p, _P(GmresStats)]),
+    "csdyn_last_error": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib(path: str = LIB_PATH):
+    """Load libcsdyn.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError(f"libcsdyn.so not built at {path}: run python -m paper_2009_02171_amd.build")
+        L = C.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class CsdynError(RuntimeError):
+    def __init__(self, status, what):
+        msg = lib().csdyn_last_error().decode()
+        super().__init__(f"{what}: status {status}: {msg}")
+        self.status = status
+
+
+def _check(rc, what):
+    if rc < 0:
+        raise CsdynError(rc, what)
+    return rc
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    assert t.is_cuda and t.is_contiguous()
+    return C.c_void_p(t.data_ptr())
+
+
+def _workspace(nbytes: int, device):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+class Operator:
+    """y = A x for one system on one grid (csdyn_op_setup / csdyn_operator_apply)."""
+
+    def __init__(self, n, nr, kind=VP, dt=1e-4, ekman=1e-3, pm=5.0, ri=RI, ro=RO, device="cuda"):
+        self.n, self.nr, self.kind = n, nr, kind
+        self.dt, self.ekman, self.pm = dt, ekman, pm
+        self.device = torch.device(device)
+        self.grid = Grid(n, nr, ri, ro)
+        self.desc = OpDesc(kind, dt, ekman, pm)
+        nb = C.c_size_t()
+        _check(lib().csdyn_op_workspace_bytes(C.byref(self.grid), C.byref(nb)), "csdyn_op_workspace_bytes")
+        self.ws = _workspace(nb.value, self.device)
+        h = C.c_void_p()
+        _check(lib().csdyn_op_setup(C.byref(self.grid), C.byref(self.desc), _ptr(self.ws), nb.value, _stream(),
+                                    C.byref(h)), "csdyn_op_setup")
+        self.h = h
+
+    @property
+    def shape(self):
+        return (6, self.nr, self.n, self.n, 4)
+
+    def empty(self):
+        return torch.empty(self.shape, dtype=torch.float64, device=self.device)
+
+    def apply(self, x: torch.Tensor, y: torch.Tensor | None = None, stream=None):
+        y = self.empty() if y is None else y
+        _check(lib().csdyn_operator_apply(self.h, _ptr(x), _ptr(y), _stream(stream)), "csdyn_operator_apply")
+        return y
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h and _lib is not None:
+            _lib.csdyn_op_destroy(h)
+            self.h = None
+
+
+class RAS:
+    """One- or two-level RAS / ILU(0) preconditioner (csdyn_ras_setup / csdyn_ras_apply)."""
+
+    def __init__(self, op: Operator, sub=(4, 4, 4), overlap=1, levels=1, coarse_rtol=0.1, coarse_restart=30,
+                 coarse_maxit=200, precision=0):
+        self.op = op
+        self.opts = RasOpts((C.c_int32 * 3)(*sub), overlap, levels, coarse_rtol, coarse_restart, coarse_maxit,
+                            precision)
+        nb = C.c_size_t()
+        _check(lib().csdyn_ras_workspace_bytes(op.h, C.byref(self.opts), C.byref(nb)), "csdyn_ras_workspace_bytes")
+        self.ws = _workspace(nb.value, op.device)
+        h = C.c_void_p()
+        _check(lib().csdyn_ras_setup(op.h, C.byref(self.opts), _ptr(self.ws), nb.value, _stream(), C.byref(h)),
+               "csdyn_ras_setup")
+        self.h = h
+
+    def apply(self, x: torch.Tensor, y: torch.Tensor | None = None, stream=None):
+        y = self.op.empty() if y is None else y
+        _check(lib().csdyn_ras_apply(self.h, _ptr(x), _ptr(y), _stream(stream)), "csdyn_ras_apply")
+        return y
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h and _lib is not None:
+            _lib.csdyn_ras_destroy(h)
+            self.h = None
+
+
+class Solver:
+    """Restarted (F)GMRES with a workspace kept across solves (csdyn_gmres_solve)."""
+
+    def __init__(self, op: Operator, pc: RAS | None = None, restart=30, maxit=1000, flexible=False, rtol=1e-8,
+                 atol=0.0):
+        self.op, self.pc = op, pc
+        self.opts = GmresOpts(restart, maxit, int(flexible), rtol, atol)
+        nb = C.c_size_t()
+        _check(lib().csdyn_gmres_workspace_bytes(op.h, C.byref(self.opts), C.byref(nb)),
+               "csdyn_gmres_workspace_bytes")
+        self.ws = _workspace(nb.value, op.device)
+        self.nbytes = nb.value
+
+    def solve(self, b: torch.Tensor, x: torch.Tensor | None = None, stream=None):
+        """Solves in place into x (x holds x0 on entry).  Returns (x, stats dict, status)."""
+        x = torch.zeros_like(b) if x is None else x
+        st = GmresStats()
+        rc = lib().csdyn_gmres_solve(self.op.h, self.pc.h if self.pc else None, C.byref(self.opts), _ptr(b), _ptr(x),
+                                     _ptr(self.ws), self.nbytes, _stream(stream), C.byref(st))
+        _check(rc, "csdyn_gmres_solve")
+        stats = dict(iters=st.iters, restarts=st.restarts, inner_iters=st.inner_iters, relres_true=st.relres_true,
+                     relres_est=st.relres_est, t_ms=list(st.t_ms))
+        return x, stats, rc

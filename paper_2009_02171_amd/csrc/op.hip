@@ -1,0 +1,368 @@
+// Matrix-free finite-volume operator y = A x on the cubed-sphere shell
+// (Sec. 3.2, eq. divdiscretization; the two systems of Sec. 3.1).
+//
+// Three kernels per apply:
+//   k_ghost     ghost values one cell beyond every panel edge: cubic
+//               interpolation along the neighbour panel's first cell layer;
+//   k_edgeflux  for every panel-edge face, the mean of the two panels'
+//               one-sided outward fluxes (Laplacian of the 4 components and
+//               the divergence flux), which makes the scheme conservative;
+//   k_op_main   the 11-point stencil: each workgroup owns a TX x TY column
+//               tile of one panel and marches over a chunk of k; plane k
+//               (with a one-cell halo) is staged in LDS, planes k-1 and k+1
+//               of the own column live in registers, and the r-independent
+//               metric of the column is loaded once before the march.
+#include <algorithm>
+
+#include "common.h"
+
+namespace csd {
+
+template <class T>
+struct V4 {
+    T c[4];
+};
+
+template <class T>
+__device__ __forceinline__ V4<T> ld4(const T *p) {
+    V4<T> v;
+    if constexpr (sizeof(T) == 8) {
+        const double2 a = reinterpret_cast<const double2 *>(p)[0];
+        const double2 b = reinterpret_cast<const double2 *>(p)[1];
+        v.c[0] = a.x; v.c[1] = a.y; v.c[2] = b.x; v.c[3] = b.y;
+    } else {
+        const float4 a = *reinterpret_cast<const float4 *>(p);
+        v.c[0] = a.x; v.c[1] = a.y; v.c[2] = a.z; v.c[3] = a.w;
+    }
+    return v;
+}
+
+template <class T>
+__device__ __forceinline__ void st4(T *p, const V4<T> &v) {
+    if constexpr (sizeof(T) == 8) {
+        reinterpret_cast<double2 *>(p)[0] = make_double2(v.c[0], v.c[1]);
+        reinterpret_cast<double2 *>(p)[1] = make_double2(v.c[2], v.c[3]);
+    } else {
+        *reinterpret_cast<float4 *>(p) = make_float4(v.c[0], v.c[1], v.c[2], v.c[3]);
+    }
+}
+
+__device__ __forceinline__ int64_t cell_ix(int n, int nr, int p, int i, int j, int k) {
+    return ((int64_t(p) * nr + k) * n + j) * n + i;
+}
+
+__device__ __forceinline__ int64_t ghost_ix(int n, int nr, int p, int e, int k, int t) {
+    return ((int64_t(p * 4 + e) * nr + k) * n + t);
+}
+
+// Value at an extended position of panel X (one cell beyond an edge: the
+// ghost; both beyond: the cube-corner rule f(-1,0) + f(0,-1) - f(0,0)).
+template <class T>
+__device__ V4<T> fetch_ext(const DevGeom &g, const T *x, const T *G, int X, int i, int j, int k) {
+    const int n = g.n, nr = g.nr;
+    const bool iin = i >= 0 && i < n, jin = j >= 0 && j < n;
+    if (iin && jin) return ld4(x + 4 * cell_ix(n, nr, X, i, j, k));
+    if (!iin && !jin) {
+        const int ic = i < 0 ? 0 : n - 1, jc = j < 0 ? 0 : n - 1;
+        V4<T> a = ld4(G + 4 * ghost_ix(n, nr, X, i < 0 ? 0 : 1, k, jc));
+        V4<T> b = ld4(G + 4 * ghost_ix(n, nr, X, j < 0 ? 2 : 3, k, ic));
+        V4<T> c = ld4(x + 4 * cell_ix(n, nr, X, ic, jc, k));
+        V4<T> r;
+        for (int q = 0; q < 4; ++q) r.c[q] = a.c[q] + b.c[q] - c.c[q];
+        return r;
+    }
+    if (!iin) return ld4(G + 4 * ghost_ix(n, nr, X, i < 0 ? 0 : 1, k, j));
+    return ld4(G + 4 * ghost_ix(n, nr, X, j < 0 ? 2 : 3, k, i));
+}
+
+template <class T>
+__global__ void k_ghost(DevGeom g, const T *__restrict__ x, T *__restrict__ G) {
+    const int n = g.n, nr = g.nr;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y, pe = blockIdx.z;
+    if (t >= n) return;
+    const int a = pe * n + t;
+    const int q = g.gh_i[4 * a], fix = g.gh_i[4 * a + 1], idx = g.gh_i[4 * a + 2], m0 = g.gh_i[4 * a + 3];
+    V4<T> acc = {};
+    for (int m = 0; m < 4; ++m) {
+        const T w = T(g.gh_w[4 * a + m]);
+        const int64_t c = fix ? cell_ix(n, nr, q, idx, m0 + m, k) : cell_ix(n, nr, q, m0 + m, idx, k);
+        const V4<T> v = ld4(x + 4 * c);
+        for (int s = 0; s < 4; ++s) acc.c[s] += w * v.c[s];
+    }
+    st4(G + 4 * ghost_ix(n, nr, pe / 4, pe % 4, k, t), acc);
+}
+
+// One-sided outward fluxes of panel X's first-layer cell at edge e,
+// tangential index t, plane k, from X's own extended values:
+// out[0..3] Laplacian flux sqrt(g) g^{mn} d_n f of each component,
+// out[4] divergence flux (sqrt(g) g^m / r) . (v_c + v_nb)/2.
+template <class T>
+__device__ void one_sided(const DevGeom &g, const T *x, const T *G, int X, int e, int t, int k, T out[5]) {
+    const int n = g.n;
+    const size_t nf = size_t(n) * (n + 1);
+    const T ih = T(1.0 / g.hs), i4h = T(0.25 / g.hs);
+    if (e <= 1) {
+        const int j = t, fi = e == 0 ? 0 : n, il = fi - 1, ir = fi;
+        const size_t a = size_t(j) * (n + 1) + fi;
+        const T a11 = T(g.a11x[a]), a12 = T(g.a12x[a]);
+        const V4<T> fl = fetch_ext(g, x, G, X, il, j, k), fr = fetch_ext(g, x, G, X, ir, j, k);
+        const V4<T> flp = fetch_ext(g, x, G, X, il, j + 1, k), frp = fetch_ext(g, x, G, X, ir, j + 1, k);
+        const V4<T> flm = fetch_ext(g, x, G, X, il, j - 1, k), frm = fetch_ext(g, x, G, X, ir, j - 1, k);
+        const T sg = e == 1 ? T(1) : T(-1);
+        for (int c = 0; c < 4; ++c)
+            out[c] = sg * (a11 * (fr.c[c] - fl.c[c]) * ih + a12 * (flp.c[c] + frp.c[c] - flm.c[c] - frm.c[c]) * i4h);
+        const double *tv = g.t1 + (X * nf + a) * 3;
+        out[4] = sg * T(0.5) * (T(tv[0]) * (fl.c[0] + fr.c[0]) + T(tv[1]) * (fl.c[1] + fr.c[1]) + T(tv[2]) * (fl.c[2] + fr.c[2]));
+    } else {
+        const int i = t, fj = e == 2 ? 0 : n, jl = fj - 1, jr = fj;
+        const size_t a = size_t(fj) * n + i;
+        const T a22 = T(g.a22y[a]), a12 = T(g.a12y[a]);
+        const V4<T> fl = fetch_ext(g, x, G, X, i, jl, k), fr = fetch_ext(g, x, G, X, i, jr, k);
+        const V4<T> fpl = fetch_ext(g, x, G, X, i + 1, jl, k), fpr = fetch_ext(g, x, G, X, i + 1, jr, k);
+        const V4<T> fml = fetch_ext(g, x, G, X, i - 1, jl, k), fmr = fetch_ext(g, x, G, X, i - 1, jr, k);
+        const T sg = e == 3 ? T(1) : T(-1);
+        for (int c = 0; c < 4; ++c)
+            out[c] = sg * (a22 * (fr.c[c] - fl.c[c]) * ih + a12 * (fpl.c[c] + fpr.c[c] - fml.c[c] - fmr.c[c]) * i4h);
+        const double *tv = g.t2 + (X * nf + a) * 3;
+        out[4] = sg * T(0.5) * (T(tv[0]) * (fl.c[0] + fr.c[0]) + T(tv[1]) * (fl.c[1] + fr.c[1]) + T(tv[2]) * (fl.c[2] + fr.c[2]));
+    }
+}
+
+template <class T>
+__global__ void k_edgeflux(DevGeom g, const T *__restrict__ x, const T *__restrict__ G, T *__restrict__ SF) {
+    const int n = g.n, nr = g.nr;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = blockIdx.y, pe = blockIdx.z;
+    if (t >= n) return;
+    const int p = pe / 4, e = pe % 4;
+    T oa[5], ob[5];
+    one_sided(g, x, G, p, e, t, k, oa);
+    const int a = pe * n + t;
+    one_sided(g, x, G, g.fc[4 * a], g.fc[4 * a + 1], g.fc[4 * a + 2], k, ob);
+    T *o = SF + 8 * ghost_ix(n, nr, p, e, k, t);
+    for (int c = 0; c < 5; ++c) o[c] = T(0.5) * (oa[c] - ob[c]);
+}
+
+struct RowCoef {
+    int kind;      // CSDYN_VP or CSDYN_BP
+    double c_lap;  // dt*E (VP) or dt*E/Pm (BP)
+    double c_cor;  // 2 dt (VP), 0 (BP)
+    double dt;
+};
+
+// Wall ghost of a boundary cell (no-slip u, Neumann P; pseudo-vacuum B,
+// Dirichlet P_b).  q = (r_in / r_ghost)^2.
+template <class T>
+__device__ __forceinline__ V4<T> wall_ghost(const V4<T> &xin, int kind, const T nv[3], T q) {
+    V4<T> gv;
+    if (kind == CSDYN_VP) {
+        gv.c[0] = -xin.c[0]; gv.c[1] = -xin.c[1]; gv.c[2] = -xin.c[2]; gv.c[3] = xin.c[3];
+    } else {
+        const T nb = (T(1) + q) * (nv[0] * xin.c[0] + nv[1] * xin.c[1] + nv[2] * xin.c[2]);
+        gv.c[0] = -xin.c[0] + nb * nv[0];
+        gv.c[1] = -xin.c[1] + nb * nv[1];
+        gv.c[2] = -xin.c[2] + nb * nv[2];
+        gv.c[3] = -xin.c[3];
+    }
+    return gv;
+}
+
+template <class T, int TX, int TY>
+__global__ __launch_bounds__(TX *TY) void k_op_main(DevGeom g, RowCoef rc, int kchunk, int nkc,
+                                                    const T *__restrict__ x, const T *__restrict__ G,
+                                                    const T *__restrict__ SF, T *__restrict__ y) {
+    constexpr int HX = TX + 2, HY = TY + 2, HC = HX * HY;
+    __shared__ T lds[4 * HC];
+    const int n = g.n, nr = g.nr;
+    const int tilesx = (n + TX - 1) / TX;
+    const int bx = blockIdx.x % tilesx, by = blockIdx.x / tilesx;
+    const int p = blockIdx.y / nkc, kc = blockIdx.y % nkc;
+    const int k0 = kc * kchunk, k1 = min(nr, k0 + kchunk);
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int i = bx * TX + tx, j = by * TY + ty;
+    const bool act = i < n && j < n;
+    const int ic = min(i, n - 1), jc = min(j, n - 1);
+    const size_t nf = size_t(n) * (n + 1);
+
+    // r-independent metric of this column, loaded once
+    const T a11W = T(g.a11x[size_t(jc) * (n + 1) + ic]), a11E = T(g.a11x[size_t(jc) * (n + 1) + ic + 1]);
+    const T a12W = T(g.a12x[size_t(jc) * (n + 1) + ic]), a12E = T(g.a12x[size_t(jc) * (n + 1) + ic + 1]);
+    const T a22S = T(g.a22y[size_t(jc) * n + ic]), a22N = T(g.a22y[size_t(jc + 1) * n + ic]);
+    const T a12S = T(g.a12y[size_t(jc) * n + ic]), a12N = T(g.a12y[size_t(jc + 1) * n + ic]);
+    const T scc = T(g.sc[size_t(jc) * n + ic]);
+    T tW[3], tE[3], tS[3], tN[3], nv[3];
+    for (int d = 0; d < 3; ++d) {
+        tW[d] = T(g.t1[(p * nf + size_t(jc) * (n + 1) + ic) * 3 + d]);
+        tE[d] = T(g.t1[(p * nf + size_t(jc) * (n + 1) + ic + 1) * 3 + d]);
+        tS[d] = T(g.t2[(p * nf + size_t(jc) * n + ic) * 3 + d]);
+        tN[d] = T(g.t2[(p * nf + size_t(jc + 1) * n + ic) * 3 + d]);
+        nv[d] = T(g.nrm[((size_t(p) * n + jc) * n + ic) * 3 + d]);
+    }
+    const bool sW = i == 0, sE = i == n - 1, sS = j == 0, sN = j == n - 1;
+    const T ih = T(1.0 / g.hs), i4h = T(0.25 / g.hs);
+    const T rbot = T(g.rf[0] - 0.5 * g.hr), rtop = T(g.rf[nr] + 0.5 * g.hr);
+    const T clap = T(rc.c_lap), ccor = T(rc.c_cor), cdt = T(rc.dt);
+
+    const int64_t col0 = cell_ix(n, nr, p, ic, jc, 0);
+    const int64_t kstride = int64_t(n) * n;
+    V4<T> xc = ld4(x + 4 * (col0 + k0 * kstride)), xm;
+    if (k0 > 0) xm = ld4(x + 4 * (col0 + (k0 - 1) * kstride));
+    else { const T q = T(g.rk[0]) / rbot; xm = wall_ghost(xc, rc.kind, nv, q * q); }
+
+    for (int k = k0; k < k1; ++k) {
+        V4<T> xp;
+        if (k + 1 < nr) xp = ld4(x + 4 * (col0 + (k + 1) * kstride));
+        else { const T q = T(g.rk[nr - 1]) / rtop; xp = wall_ghost(xc, rc.kind, nv, q * q); }
+        __syncthreads();
+        for (int h = threadIdx.x; h < HC; h += TX * TY) {
+            const int hx = h % HX, hy = h / HX;
+            const int ii = bx * TX + hx - 1, jj = by * TY + hy - 1;
+            const bool iin = ii >= 0 && ii < n, jin = jj >= 0 && jj < n;
+            V4<T> v = {};
+            if (iin && jin) v = ld4(x + 4 * cell_ix(n, nr, p, ii, jj, k));
+            else if (jin && (ii == -1 || ii == n)) v = ld4(G + 4 * ghost_ix(n, nr, p, ii < 0 ? 0 : 1, k, jj));
+            else if (iin && (jj == -1 || jj == n)) v = ld4(G + 4 * ghost_ix(n, nr, p, jj < 0 ? 2 : 3, k, ii));
+            for (int c = 0; c < 4; ++c) lds[c * HC + h] = v.c[c];
+        }
+        __syncthreads();
+        if (act) {
+            const int hc = (ty + 1) * HX + tx + 1;
+            auto V = [&](int c, int di, int dj) -> T { return lds[c * HC + hc + dj * HX + di]; };
+            const T rk = T(g.rk[k]);
+            const T rp2 = T(g.rf[k + 1]) * T(g.rf[k + 1]), rm2 = T(g.rf[k]) * T(g.rf[k]);
+            const T inv_lat = T(1) / (rk * rk * scc) * ih;
+            const T inv_rad = T(1) / (rk * rk * T(g.hr) * T(g.hr));
+            const T *sfW = SF + 8 * ghost_ix(n, nr, p, 0, k, jc), *sfE = SF + 8 * ghost_ix(n, nr, p, 1, k, jc);
+            const T *sfS = SF + 8 * ghost_ix(n, nr, p, 2, k, ic), *sfN = SF + 8 * ghost_ix(n, nr, p, 3, k, ic);
+            T lap[4];
+            for (int c = 0; c < 4; ++c) {
+                const T v00 = V(c, 0, 0);
+                T oE = a11E * (V(c, 1, 0) - v00) * ih + a12E * (V(c, 0, 1) + V(c, 1, 1) - V(c, 0, -1) - V(c, 1, -1)) * i4h;
+                T oW = -(a11W * (v00 - V(c, -1, 0)) * ih + a12W * (V(c, -1, 1) + V(c, 0, 1) - V(c, -1, -1) - V(c, 0, -1)) * i4h);
+                T oN = a22N * (V(c, 0, 1) - v00) * ih + a12N * (V(c, 1, 0) + V(c, 1, 1) - V(c, -1, 0) - V(c, -1, 1)) * i4h;
+                T oS = -(a22S * (v00 - V(c, 0, -1)) * ih + a12S * (V(c, 1, -1) + V(c, 1, 0) - V(c, -1, -1) - V(c, -1, 0)) * i4h);
+                if (sE) oE = sfE[c];
+                if (sW) oW = sfW[c];
+                if (sN) oN = sfN[c];
+                if (sS) oS = sfS[c];
+                lap[c] = (oE + oW + oN + oS) * inv_lat +
+                         (rp2 * (xp.c[c] - xc.c[c]) - rm2 * (xc.c[c] - xm.c[c])) * inv_rad;
+            }
+            T dE = 0, dW = 0, dN = 0, dS = 0, rup = 0, rdn = 0;
+            for (int d = 0; d < 3; ++d) {
+                const T v00 = V(d, 0, 0);
+                dE += tE[d] * (v00 + V(d, 1, 0));
+                dW += tW[d] * (V(d, -1, 0) + v00);
+                dN += tN[d] * (v00 + V(d, 0, 1));
+                dS += tS[d] * (V(d, 0, -1) + v00);
+                rup += nv[d] * (xc.c[d] + xp.c[d]);
+                rdn += nv[d] * (xm.c[d] + xc.c[d]);
+            }
+            dE *= T(0.5); dW *= T(-0.5); dN *= T(0.5); dS *= T(-0.5);
+            if (sE) dE = sfE[4];
+            if (sW) dW = sfW[4];
+            if (sN) dN = sfN[4];
+            if (sS) dS = sfS[4];
+            const T div = (dE + dW + dN + dS) * rk * inv_lat + T(0.5) * (rp2 * rup - rm2 * rdn) * inv_rad * T(g.hr);
+            V4<T> out;
+            out.c[0] = xc.c[0] - clap * lap[0] - ccor * xc.c[1];
+            out.c[1] = xc.c[1] - clap * lap[1] + ccor * xc.c[0];
+            out.c[2] = xc.c[2] - clap * lap[2];
+            out.c[3] = div - cdt * lap[3];
+            st4(y + 4 * (col0 + k * kstride), out);
+        }
+        xm = xc;
+        xc = xp;
+    }
+}
+
+template <class T>
+static int32_t launch_all(const csdyn_opctx *ctx, const T *x, T *y, T *G, T *SF, hipStream_t s) {
+    const DevGeom &g = ctx->dg;
+    const int n = g.n, nr = g.nr;
+    RowCoef rc;
+    rc.kind = ctx->op.kind;
+    rc.dt = ctx->op.dt;
+    rc.c_lap = ctx->op.kind == CSDYN_VP ? ctx->op.dt * ctx->op.ekman : ctx->op.dt * ctx->op.ekman / ctx->op.pm;
+    rc.c_cor = ctx->op.kind == CSDYN_VP ? 2.0 * ctx->op.dt : 0.0;
+    const dim3 eb(64), eg((n + 63) / 64, nr, 24);
+    hipLaunchKernelGGL(k_ghost<T>, eg, eb, 0, s, g, x, G);
+    hipLaunchKernelGGL(k_edgeflux<T>, eg, eb, 0, s, g, x, (const T *)G, SF);
+    if (n >= 32) {
+        constexpr int TX = 32, TY = 8;
+        const int tiles = ((n + TX - 1) / TX) * ((n + TY - 1) / TY);
+        int nkc = std::max(1, std::min(nr, (2048 + 6 * tiles - 1) / (6 * tiles)));
+        const int kchunk = (nr + nkc - 1) / nkc;
+        nkc = (nr + kchunk - 1) / kchunk;
+        hipLaunchKernelGGL((k_op_main<T, TX, TY>), dim3(tiles, 6 * nkc), dim3(TX * TY), 0, s, g, rc, kchunk, nkc, x,
+                           (const T *)G, (const T *)SF, y);
+    } else {
+        constexpr int TX = 16, TY = 16;
+        const int tiles = ((n + TX - 1) / TX) * ((n + TY - 1) / TY);
+        int nkc = std::max(1, std::min(nr, (2048 + 6 * tiles - 1) / (6 * tiles)));
+        const int kchunk = (nr + nkc - 1) / nkc;
+        nkc = (nr + kchunk - 1) / kchunk;
+        hipLaunchKernelGGL((k_op_main<T, TX, TY>), dim3(tiles, 6 * nkc), dim3(TX * TY), 0, s, g, rc, kchunk, nkc, x,
+                           (const T *)G, (const T *)SF, y);
+    }
+    CSD_HIP(hipGetLastError());
+    return CSDYN_OK;
+}
+
+int32_t op_launch(const csdyn_opctx *ctx, const double *x, double *y, hipStream_t s) {
+    return launch_all<double>(ctx, x, y, ctx->dg.G, ctx->dg.SF, s);
+}
+
+int32_t op_launch_f32(const csdyn_opctx *ctx, const float *x, float *y, float *G32, float *SF32, hipStream_t s) {
+    return launch_all<float>(ctx, x, y, G32, SF32, s);
+}
+
+}  // namespace csd
+
+// ------------------------------------------------------------------ C ABI
+using namespace csd;
+
+extern "C" int32_t csdyn_op_workspace_bytes(const csdyn_grid *g, size_t *bytes) {
+    clear_error();
+    if (!g || !bytes) { set_error("csdyn_op_workspace_bytes: null argument"); return CSDYN_EINVAL; }
+    if (g->n < 4 || g->nr < 1) { set_error("csdyn_op_workspace_bytes: need n >= 4, nr >= 1"); return CSDYN_EINVAL; }
+    *bytes = devgeom_bytes(g->n, g->nr);
+    return CSDYN_OK;
+}
+
+extern "C" int32_t csdyn_op_setup(const csdyn_grid *g, const csdyn_op *op, void *ws, size_t ws_bytes, void *stream,
+                                  csdyn_opctx **out) {
+    clear_error();
+    if (!g || !op || !ws || !out) { set_error("csdyn_op_setup: null argument"); return CSDYN_EINVAL; }
+    *out = nullptr;
+    if (op->kind != CSDYN_VP && op->kind != CSDYN_BP) { set_error("csdyn_op_setup: kind must be VP or BP"); return CSDYN_EINVAL; }
+    if (!(op->dt >= 0) || !(op->ekman > 0) || (op->kind == CSDYN_BP && !(op->pm > 0))) {
+        set_error("csdyn_op_setup: need dt >= 0, ekman > 0, pm > 0"); return CSDYN_EINVAL;
+    }
+    auto *ctx = new csdyn_opctx();
+    ctx->g = *g; ctx->op = *op; ctx->ws = ws; ctx->ws_bytes = ws_bytes;
+    int32_t rc = ctx->hg.build(*g);
+    if (rc == CSDYN_OK && ws_bytes < devgeom_bytes(g->n, g->nr)) {
+        set_error("csdyn_op_setup: workspace %zu < %zu bytes", ws_bytes, devgeom_bytes(g->n, g->nr));
+        rc = CSDYN_ENOMEM;
+    }
+    if (rc == CSDYN_OK) rc = devgeom_setup(ctx->hg, ws, &ctx->dg);
+    if (rc == CSDYN_OK && stream) {
+        if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) { set_error("csdyn_op_setup: stream sync failed"); rc = CSDYN_EHIP; }
+    }
+    if (rc != CSDYN_OK) { delete ctx; return rc; }
+    *out = ctx;
+    return CSDYN_OK;
+}
+
+extern "C" int32_t csdyn_operator_apply(const csdyn_opctx *ctx, const double *x, double *y, void *stream) {
+    clear_error();
+    if (!ctx || !x || !y) { set_error("csdyn_operator_apply: null argument"); return CSDYN_EINVAL; }
+    const size_t nb = size_t(24) * ctx->g.n * ctx->g.n * ctx->g.nr * sizeof(double);
+    const char *xa = (const char *)x, *ya = (const char *)y;
+    if (xa < ya + nb && ya < xa + nb) { set_error("csdyn_operator_apply: x and y alias"); return CSDYN_EINVAL; }
+    return op_launch(ctx, x, y, (hipStream_t)stream);
+}
+
+extern "C" void csdyn_op_destroy(csdyn_opctx *ctx) { delete ctx; }
