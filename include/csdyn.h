@@ -125,11 +125,23 @@ typedef struct csdyn_ras csdyn_ras;
 int32_t csdyn_ras_workspace_bytes(const csdyn_opctx *ctx, const csdyn_ras_opts *o, size_t *bytes);
 int32_t csdyn_ras_setup(const csdyn_opctx *ctx, const csdyn_ras_opts *o, void *ws, size_t ws_bytes, void *stream,
                         csdyn_ras **out);
-/* y = M^{-1} x; x, y device pointers (FP64), must not alias.  One-level is
+/* y = M^{-1} x; x, y device pointers (FP64), must not alias.  The handle keeps
+ * a pointer to ctx, which must outlive it.  One-level is
  * asynchronous; two-level synchronises with the host once per inner
  * iteration (convergence test of the coarse GMRES). */
 int32_t csdyn_ras_apply(const csdyn_ras *pc, const double *x, double *y, void *stream);
 void csdyn_ras_destroy(csdyn_ras *pc);
+
+/* Host-only inspection of one subdomain of the one-level RAS (no device use):
+ * the box's global cells in local order, owned flags, and the ILU(0) factors
+ * of A_i = R_i A R_i^T as CSR over 4*nloc rows (strict lower part = L with an
+ * implied unit diagonal, the rest = U).  Call once with gcell = owned =
+ * rowptr = col = val = NULL to get nloc and nnz, then with arrays of
+ * nloc, nloc, 4*nloc+1, nnz and nnz entries.  Subdomain s is numbered
+ * ((p*nbk + bk)*nbj + bj)*nbi + bi. */
+int32_t csdyn_ras_inspect(const csdyn_grid *g, const csdyn_op *op, const int32_t sub[3], int32_t overlap, int32_t s,
+                          int64_t *nloc, int64_t *nnz, int32_t *gcell, int32_t *owned, int64_t *rowptr, int32_t *col,
+                          double *val);
 
 /* ------------------------------------------------------------------- GMRES
  * Right-preconditioned restarted GMRES(restart) (Sec. 3.3); flexible = 1 is

@@ -80,6 +80,7 @@ def lib():
         _lib.ref_pc_subdomain.argtypes = [C.c_void_p, C.c_int, C.c_int, i64, i64, i64, i32, i64, i32, d]
         _lib.ref_pc_count.argtypes = [C.c_void_p, C.c_int]
         _lib.ref_ilu0_csr.argtypes = [C.c_int64, i64, i32, d]
+        _lib.ref_subdomain_solve.argtypes = [P(Grid), P(Op), i32, C.c_int, C.c_int, d, d]
         _lib.ref_gmres_solve.argtypes = [P(Grid), P(Op), C.c_void_p, P(GmresOpts), d, d, P(GmresStats)]
     return _lib
 
@@ -233,6 +234,17 @@ class Preconditioner:
                                _ip(ci), _dp(v))
         m = 4 * nloc.value
         return gcell, owned.astype(bool), sp.csr_matrix((v, ci, rp), shape=(m, m))
+
+
+def subdomain_solve(pb: Problem, sub, s, x, overlap=1):
+    """Owned part of one subdomain's ILU(0) solve, (L_s U_s)^{-1} R_s x, written into a
+    NaN-filled full vector (only subdomain s is built; for sampled checks at full size)."""
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
+    y = np.full_like(x, np.nan)
+    sb = np.array(sub, dtype=np.int32)
+    _check(lib().ref_subdomain_solve(C.byref(pb.grid()), C.byref(pb.op()), _ip(sb), overlap, s, _dp(x), _dp(y)),
+           "subdomain_solve")
+    return y.reshape(pb.shape())
 
 
 def gmres(pb: Problem, b, x0=None, pc: Preconditioner | None = None, restart=30, maxit=1000, flexible=False,

@@ -1080,3 +1080,37 @@ int ref_ilu0_csr(int64_t nrow, const int64_t *rp, const int32_t *ci, double *v) 
     free(diag);
     return rc;
 }
+
+/* One subdomain's local solve y_i = (L_i U_i)^{-1} R_i x at full size without
+ * building the others (sampled checks): writes the owned cells of y only. */
+int ref_subdomain_solve(const ref_grid *g, const ref_op *op, const int32_t sub[3], int overlap, int s,
+                        const double *x, double *y) {
+    seam_tab st; ctx cx;
+    if (overlap < 0 || overlap > 1) return REF_EINVAL;
+    if (sub[0] < 1 || sub[1] < 1 || sub[2] < 1 || g->n % sub[0] || g->n % sub[1] || g->nr % sub[2]) return REF_EINVAL;
+    int rc = make_ctx(g, op, &st, &cx);
+    if (rc) return rc;
+    onelevel ol = {0};
+    ol.g = *g; ol.op = *op; ol.overlap = overlap;
+    for (int a = 0; a < 3; a++) ol.sub[a] = sub[a];
+    ol.nb[0] = g->n / sub[0]; ol.nb[1] = g->n / sub[1]; ol.nb[2] = g->nr / sub[2];
+    ol.nsd = 6 * ol.nb[0] * ol.nb[1] * ol.nb[2];
+    if (s < 0 || s >= ol.nsd) { free_seams(&st); return REF_EINVAL; }
+    subdomain *all = calloc(ol.nsd, sizeof(subdomain));
+    ol.sd = all;
+    int64_t ncell = 6 * (int64_t)g->n * g->n * g->nr;
+    int32_t *g2l = malloc(sizeof(int32_t) * ncell);
+    for (int64_t a = 0; a < ncell; a++) g2l[a] = -1;
+    rc = build_subdomain(&cx, &ol, s, g2l);
+    free(g2l);
+    if (!rc) {
+        onelevel one = ol;
+        one.sd = &all[s]; one.nsd = 1;
+        onelevel_apply(&one, x, y);
+    }
+    subdomain *d = &all[s];
+    free(d->gcell); free(d->owned); free(d->rp); free(d->ci); free(d->v); free(d->diag);
+    free(all);
+    free_seams(&st);
+    return rc;
+}

@@ -56,6 +56,9 @@ SIGNATURES = {
     "csdyn_ras_setup": (C.c_int32, [C.c_void_p, _P(RasOpts), C.c_void_p, C.c_size_t, C.c_void_p, _P(C.c_void_p)]),
     "csdyn_ras_apply": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "csdyn_ras_destroy": (None, [C.c_void_p]),
+    "csdyn_ras_inspect": (C.c_int32, [_P(Grid), _P(OpDesc), _P(C.c_int32), C.c_int32, C.c_int32, _P(C.c_int64),
+                                      _P(C.c_int64), _P(C.c_int32), _P(C.c_int32), _P(C.c_int64), _P(C.c_int32),
+                                      _P(C.c_double)]),
     "csdyn_gmres_workspace_bytes": (C.c_int32, [C.c_void_p, _P(GmresOpts), _P(C.c_size_t)]),
     "csdyn_gmres_solve": (C.c_int32, [C.c_void_p, C.c_void_p, _P(GmresOpts), C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_size_t, C.c_void_p, _P(GmresStats)]),
@@ -169,6 +172,30 @@ class RAS:
         if h and _lib is not None:
             _lib.csdyn_ras_destroy(h)
             self.h = None
+
+
+def ras_inspect(n, nr, kind, sub, s, overlap=1, dt=1e-4, ekman=1e-3, pm=5.0, ri=RI, ro=RO):
+    """Host-side subdomain data (csdyn_ras_inspect): (gcell, owned, scipy CSR of the ILU(0) factors)."""
+    import numpy as np
+    import scipy.sparse as sp
+    g, d = Grid(n, nr, ri, ro), OpDesc(kind, dt, ekman, pm)
+    sb = (C.c_int32 * 3)(*sub)
+    nloc, nnz = C.c_int64(), C.c_int64()
+    L = lib()
+    _check(L.csdyn_ras_inspect(C.byref(g), C.byref(d), sb, overlap, s, C.byref(nloc), C.byref(nnz), None, None, None,
+                               None, None), "csdyn_ras_inspect")
+    gc = np.zeros(nloc.value, np.int32)
+    ow = np.zeros(nloc.value, np.int32)
+    rp = np.zeros(4 * nloc.value + 1, np.int64)
+    ci = np.zeros(nnz.value, np.int32)
+    v = np.zeros(nnz.value)
+    P = C.POINTER
+    _check(L.csdyn_ras_inspect(C.byref(g), C.byref(d), sb, overlap, s, C.byref(nloc), C.byref(nnz),
+                               gc.ctypes.data_as(P(C.c_int32)), ow.ctypes.data_as(P(C.c_int32)),
+                               rp.ctypes.data_as(P(C.c_int64)), ci.ctypes.data_as(P(C.c_int32)),
+                               v.ctypes.data_as(P(C.c_double))), "csdyn_ras_inspect")
+    m = 4 * nloc.value
+    return gc.astype(np.int64), ow.astype(bool), sp.csr_matrix((v, ci, rp), shape=(m, m))
 
 
 class Solver:

@@ -68,7 +68,10 @@ struct HostGeom {
     double ri = 0, ro = 0, hs = 0, hr = 0;
     std::vector<GhostEntry> ghost;  // [6][4][n]
     std::vector<FaceEntry> face;    // [6][4][n]
+    // metric tables, same layout as DevGeom
+    std::vector<double> a11x, a12x, a22y, a12y, sc, t1, t2, nrm, rk, rf, vol;
     int32_t build(const csdyn_grid &g);
+    size_t nf() const { return size_t(n) * (n + 1); }
     double ang(double i) const { return -0.78539816339744830962 + (i + 0.5) * hs; }
     double rad(double k) const { return ri + (k + 0.5) * hr; }
     int64_t cell(int p, int i, int j, int k) const { return ((int64_t(p) * nr + k) * n + j) * n + i; }

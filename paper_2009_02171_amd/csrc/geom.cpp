@@ -116,6 +116,47 @@ int32_t HostGeom::build(const csdyn_grid &g) {
                 F.t = int(std::lround(ft));
                 if (std::fabs(ft - F.t) > 1e-8) { set_error("grid: non-conforming edge face"); return CSDYN_EINVAL; }
             }
+    const size_t nf = this->nf();
+    a11x.assign(nf, 0); a12x.assign(nf, 0); a22y.assign(nf, 0); a12y.assign(nf, 0); sc.assign(size_t(n) * n, 0);
+    t1.assign(6 * nf * 3, 0); t2.assign(6 * nf * 3, 0); nrm.assign(6 * size_t(n) * n * 3, 0);
+    rk.assign(nr, 0); rf.assign(nr + 1, 0); vol.assign(6 * size_t(nr) * n * n, 0);
+    auto face_x = [&](int j, int fi, double &X, double &Y) { X = std::tan(-qpi + fi * hs); Y = std::tan(ang(j)); };
+    auto face_y = [&](int fj, int i, double &X, double &Y) { X = std::tan(ang(i)); Y = std::tan(-qpi + fj * hs); };
+    for (int j = 0; j < n; ++j)
+        for (int fi = 0; fi <= n; ++fi) {
+            double X, Y; face_x(j, fi, X, Y);
+            double rho2 = 1 + X * X + Y * Y, rho = std::sqrt(rho2);
+            size_t a = size_t(j) * (n + 1) + fi;
+            a11x[a] = (1 + Y * Y) / rho;
+            a12x[a] = X * Y / rho;
+            double loc[3] = {-X * (1 + Y * Y) / rho2, (1 + Y * Y) / rho2, 0.0};
+            for (int p = 0; p < 6; ++p) to_global(p, loc, &t1[(p * nf + a) * 3]);
+        }
+    for (int fj = 0; fj <= n; ++fj)
+        for (int i = 0; i < n; ++i) {
+            double X, Y; face_y(fj, i, X, Y);
+            double rho2 = 1 + X * X + Y * Y, rho = std::sqrt(rho2);
+            size_t a = size_t(fj) * n + i;
+            a22y[a] = (1 + X * X) / rho;
+            a12y[a] = X * Y / rho;
+            double loc[3] = {-Y * (1 + X * X) / rho2, 0.0, (1 + X * X) / rho2};
+            for (int p = 0; p < 6; ++p) to_global(p, loc, &t2[(p * nf + a) * 3]);
+        }
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+            double X = std::tan(ang(i)), Y = std::tan(ang(j));
+            double rho2 = 1 + X * X + Y * Y, rho = std::sqrt(rho2);
+            sc[size_t(j) * n + i] = (1 + X * X) * (1 + Y * Y) / (rho2 * rho);
+            double loc[3] = {1.0 / rho, X / rho, Y / rho};
+            for (int p = 0; p < 6; ++p) to_global(p, loc, &nrm[((size_t(p) * n + j) * n + i) * 3]);
+        }
+    for (int k = 0; k < nr; ++k) rk[k] = rad(k);
+    for (int k = 0; k <= nr; ++k) rf[k] = ri + k * hr;
+    for (int p = 0; p < 6; ++p)
+        for (int k = 0; k < nr; ++k)
+            for (int j = 0; j < n; ++j)
+                for (int i = 0; i < n; ++i)
+                    vol[cell(p, i, j, k)] = rk[k] * rk[k] * sc[size_t(j) * n + i] * hs * hs * hr;
     return CSDYN_OK;
 }
 
@@ -150,47 +191,6 @@ int32_t devgeom_setup(const HostGeom &hg, void *ws, DevGeom *o) {
     o->G = c.take<double>(24 * size_t(nr) * n * 4);
     o->SF = c.take<double>(24 * size_t(nr) * n * 8);
 
-    const double qpi = 0.78539816339744830962;
-    std::vector<double> a11x(nf), a12x(nf), a22y(nf), a12y(nf), sc(size_t(n) * n);
-    std::vector<double> t1(6 * nf * 3), t2(6 * nf * 3), nrm(6 * size_t(n) * n * 3);
-    auto face_x = [&](int j, int fi, double &X, double &Y) { X = std::tan(-qpi + fi * hg.hs); Y = std::tan(hg.ang(j)); };
-    auto face_y = [&](int fj, int i, double &X, double &Y) { X = std::tan(hg.ang(i)); Y = std::tan(-qpi + fj * hg.hs); };
-    for (int j = 0; j < n; ++j)
-        for (int fi = 0; fi <= n; ++fi) {
-            double X, Y; face_x(j, fi, X, Y);
-            double rho2 = 1 + X * X + Y * Y, rho = std::sqrt(rho2);
-            size_t a = size_t(j) * (n + 1) + fi;
-            a11x[a] = (1 + Y * Y) / rho;
-            a12x[a] = X * Y / rho;
-            double loc[3] = {-X * (1 + Y * Y) / rho2, (1 + Y * Y) / rho2, 0.0};
-            for (int p = 0; p < 6; ++p) to_global(p, loc, &t1[(p * nf + a) * 3]);
-        }
-    for (int fj = 0; fj <= n; ++fj)
-        for (int i = 0; i < n; ++i) {
-            double X, Y; face_y(fj, i, X, Y);
-            double rho2 = 1 + X * X + Y * Y, rho = std::sqrt(rho2);
-            size_t a = size_t(fj) * n + i;
-            a22y[a] = (1 + X * X) / rho;
-            a12y[a] = X * Y / rho;
-            double loc[3] = {-Y * (1 + X * X) / rho2, 0.0, (1 + X * X) / rho2};
-            for (int p = 0; p < 6; ++p) to_global(p, loc, &t2[(p * nf + a) * 3]);
-        }
-    for (int j = 0; j < n; ++j)
-        for (int i = 0; i < n; ++i) {
-            double X = std::tan(hg.ang(i)), Y = std::tan(hg.ang(j));
-            double rho2 = 1 + X * X + Y * Y, rho = std::sqrt(rho2);
-            sc[size_t(j) * n + i] = (1 + X * X) * (1 + Y * Y) / (rho2 * rho);
-            double loc[3] = {1.0 / rho, X / rho, Y / rho};
-            for (int p = 0; p < 6; ++p) to_global(p, loc, &nrm[((size_t(p) * n + j) * n + i) * 3]);
-        }
-    std::vector<double> rk(nr), rf(nr + 1), vol(6 * size_t(nr) * n * n);
-    for (int k = 0; k < nr; ++k) rk[k] = hg.rad(k);
-    for (int k = 0; k <= nr; ++k) rf[k] = hg.ri + k * hg.hr;
-    for (int p = 0; p < 6; ++p)
-        for (int k = 0; k < nr; ++k)
-            for (int j = 0; j < n; ++j)
-                for (int i = 0; i < n; ++i)
-                    vol[hg.cell(p, i, j, k)] = rk[k] * rk[k] * sc[size_t(j) * n + i] * hg.hs * hg.hs * hg.hr;
     std::vector<int> ghi(24 * size_t(n) * 4), fcv(24 * size_t(n) * 4);
     std::vector<double> ghw(24 * size_t(n) * 4);
     for (size_t a = 0; a < 24 * size_t(n); ++a) {
@@ -200,6 +200,8 @@ int32_t devgeom_setup(const HostGeom &hg, void *ws, DevGeom *o) {
         const FaceEntry &F = hg.face[a];
         fcv[4 * a] = F.q; fcv[4 * a + 1] = F.e; fcv[4 * a + 2] = F.t; fcv[4 * a + 3] = 0;
     }
+    const std::vector<double> &a11x = hg.a11x, &a12x = hg.a12x, &a22y = hg.a22y, &a12y = hg.a12y, &sc = hg.sc,
+                              &t1 = hg.t1, &t2 = hg.t2, &nrm = hg.nrm, &rk = hg.rk, &rf = hg.rf, &vol = hg.vol;
     auto up = [](void *dst, const void *src, size_t bytes) { return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice); };
 #define UP(dst, vec) CSD_HIP(up(dst, vec.data(), vec.size() * sizeof(vec[0])))
     UP(o->a11x, a11x); UP(o->a12x, a12x); UP(o->a22y, a22y); UP(o->a12y, a12y); UP(o->sc, sc);

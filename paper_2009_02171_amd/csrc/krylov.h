@@ -1,0 +1,67 @@
+// Restarted GMRES / FGMRES engine (Sec. 3.3) on device vectors, with the
+// operator and preconditioner passed as callbacks.  Used by csdyn_gmres_solve
+// (FP64) and by the coarse solve inside the two-level preconditioner.
+#pragma once
+
+#include <functional>
+#include <vector>
+
+#include "common.h"
+
+namespace csd {
+
+constexpr int kRedStride = 33;  // 32 dot products + 1 self product per block
+constexpr int kMaxRestart = 64;
+
+template <class T>
+using DevFn = std::function<int32_t(const T *in, T *out, hipStream_t s)>;
+
+// Vector kernels (deterministic: fixed block decomposition, fixed reduction order).
+template <class T>
+struct Vec {
+    static int nblocks(int64_t n);
+    // out[q] = V_q . w (q < cnt), out[32] = w . w; partial has nblocks*kRedStride entries
+    static int32_t mdot(const T *V, int64_t n, int cnt, const T *w, T *partial, T *out, hipStream_t s);
+    // w -= sum_q h[q] V_q (h on device), then out[32] = w . w
+    static int32_t mupdate(T *w, const T *V, int64_t n, int cnt, const T *h, T *partial, T *out, hipStream_t s);
+    static int32_t scale(T *w, int64_t n, double a, hipStream_t s);
+    // y = a*x + b*y
+    static int32_t axpby(double a, const T *x, double b, T *y, int64_t n, hipStream_t s);
+    // x += sum_q c[q] Z_q
+    static int32_t lincomb(T *x, const T *Z, int64_t n, int cnt, const double *c, hipStream_t s);
+    static int32_t copy(T *dst, const T *src, int64_t n, hipStream_t s);
+    static int32_t zero(T *x, int64_t n, hipStream_t s);
+    // out[0] = sum vol * x_P, out[1] = sum vol  (4-component layout, P = component 3)
+    static int32_t pmoments(const T *x, const double *vol, int64_t ncell, T *partial, T *out, hipStream_t s);
+    static int32_t padd(T *x, int64_t ncell, double c, hipStream_t s);
+};
+
+int32_t convert_d2f(const double *x, float *y, int64_t n, hipStream_t s);
+int32_t convert_f2d(const float *x, double *y, int64_t n, hipStream_t s);
+
+struct GmresResult {
+    int iters = 0, restarts = 0;
+    double relres_true = 0, relres_est = 0;
+    bool converged = false;
+};
+
+template <class T>
+struct Gmres {
+    int64_t n = 0;
+    int m = 30;
+    bool flexible = false;
+    T *V = nullptr, *Z = nullptr, *z = nullptr, *r = nullptr, *tmp = nullptr, *partial = nullptr, *red = nullptr;
+    T *hred = nullptr;  // pinned-free host mirror is a std::vector below
+
+    static size_t bytes(int64_t n, int m, bool flexible);
+    void carve(Carver &c, int64_t n_, int m_, bool flexible_);
+    // Solve A x = b to max(atol, rtol*||b - A x0||) with right preconditioning.
+    int32_t solve(const DevFn<T> &A, const DevFn<T> *M, const T *b, T *x, int maxit, double rtol, double atol,
+                  hipStream_t s, GmresResult &res);
+
+   private:
+    int32_t fetch(int cnt, std::vector<T> &out, hipStream_t s);
+    int32_t norm(const T *v, double &out, hipStream_t s);
+};
+
+}  // namespace csd

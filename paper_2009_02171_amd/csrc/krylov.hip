@@ -1,0 +1,411 @@
+// Vector kernels and the restarted (F)GMRES engine (Sec. 3.3, right
+// preconditioning, eq. newlinear and the stopping rule after it).
+//
+// Orthogonalisation is classical Gram-Schmidt as two bandwidth passes over
+// the basis (a multi-dot that reads w and V_0..V_j once, then a multi-update
+// that also returns ||w||^2), with a second pass when ||w|| drops below
+// 1/sqrt(2) of its value.  Reductions are wavefront shuffles, then a fixed-
+// order two-stage sum over blocks, so results are bitwise reproducible.
+#include <algorithm>
+#include <cmath>
+
+#include "krylov.h"
+
+namespace csd {
+
+constexpr int kBlk = 256;
+constexpr int kMaxBlocks = 1024;
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+template <class T>
+int Vec<T>::nblocks(int64_t n) {
+    int64_t b = (n + int64_t(kBlk) * 4 - 1) / (int64_t(kBlk) * 4);
+    return int(std::max<int64_t>(1, std::min<int64_t>(kMaxBlocks, b)));
+}
+
+// Block partial sums of NV accumulators written to partial[block][q].
+template <class T>
+__device__ __forceinline__ void block_store(T (&acc)[kRedStride], int cnt_total, T *partial) {
+    __shared__ T sm[kBlk / 64][kRedStride];
+    const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+#pragma unroll
+    for (int q = 0; q < kRedStride; ++q) {
+        if (q < cnt_total || q == kRedStride - 1) {
+            const T v = wave_sum(acc[q]);
+            if (lane == 0) sm[wv][q] = v;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < kRedStride) {
+        T s = 0;
+        for (int w = 0; w < kBlk / 64; ++w) s += sm[w][threadIdx.x];
+        partial[blockIdx.x * kRedStride + threadIdx.x] = s;
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlk) void k_mdot(const T *__restrict__ V, int64_t n, int cnt, const T *__restrict__ w,
+                                               T *__restrict__ partial) {
+    T acc[kRedStride];
+#pragma unroll
+    for (int q = 0; q < kRedStride; ++q) acc[q] = 0;
+    const int64_t stride = int64_t(gridDim.x) * kBlk;
+    for (int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x; i < n; i += stride) {
+        const T wv = w[i];
+#pragma unroll
+        for (int q = 0; q < kRedStride - 1; ++q)
+            if (q < cnt) acc[q] += V[int64_t(q) * n + i] * wv;
+        acc[kRedStride - 1] += wv * wv;
+    }
+    block_store(acc, cnt, partial);
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlk) void k_mupdate(T *__restrict__ w, const T *__restrict__ V, int64_t n, int cnt,
+                                                  const T *__restrict__ h, T *__restrict__ partial) {
+    T hq[kRedStride - 1];
+#pragma unroll
+    for (int q = 0; q < kRedStride - 1; ++q) hq[q] = q < cnt ? h[q] : T(0);
+    T acc[kRedStride];
+#pragma unroll
+    for (int q = 0; q < kRedStride; ++q) acc[q] = 0;
+    const int64_t stride = int64_t(gridDim.x) * kBlk;
+    for (int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x; i < n; i += stride) {
+        T wv = w[i];
+#pragma unroll
+        for (int q = 0; q < kRedStride - 1; ++q)
+            if (q < cnt) wv -= hq[q] * V[int64_t(q) * n + i];
+        w[i] = wv;
+        acc[kRedStride - 1] += wv * wv;
+    }
+    block_store(acc, 0, partial);
+}
+
+// out[q] = sum over blocks of partial[b][q], fixed order, q < 33.
+template <class T>
+__global__ void k_reduce(const T *__restrict__ partial, int nb, T *__restrict__ out) {
+    __shared__ T sm[kRedStride][8];
+    const int g = threadIdx.x / 8, l = threadIdx.x % 8;
+    if (g < kRedStride) {
+        T s = 0;
+        for (int b = l; b < nb; b += 8) s += partial[b * kRedStride + g];
+        sm[g][l] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < kRedStride) {
+        T s = 0;
+        for (int a = 0; a < 8; ++a) s += sm[threadIdx.x][a];
+        out[threadIdx.x] = s;
+    }
+}
+
+template <class T>
+__global__ void k_scale(T *w, int64_t n, T a) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) w[i] *= a;
+}
+
+template <class T>
+__global__ void k_axpby(T a, const T *__restrict__ x, T b, T *__restrict__ y, int64_t n) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) y[i] = a * x[i] + b * y[i];
+}
+
+struct Coefs {
+    double c[kMaxRestart];
+};
+
+template <class T>
+__global__ void k_lincomb(T *__restrict__ x, const T *__restrict__ Z, int64_t n, int cnt, Coefs c) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+        T acc = x[i];
+        for (int q = 0; q < cnt; ++q) acc += T(c.c[q]) * Z[int64_t(q) * n + i];
+        x[i] = acc;
+    }
+}
+
+template <class T>
+__global__ void k_copy(T *__restrict__ d, const T *__restrict__ s, int64_t n) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) d[i] = s[i];
+}
+
+template <class T>
+__global__ void k_zero(T *d, int64_t n) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) d[i] = T(0);
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlk) void k_pmoments(const T *__restrict__ x, const double *__restrict__ vol,
+                                                   int64_t ncell, T *__restrict__ partial) {
+    T acc[kRedStride];
+#pragma unroll
+    for (int q = 0; q < kRedStride; ++q) acc[q] = 0;
+    const int64_t stride = int64_t(gridDim.x) * kBlk;
+    for (int64_t c = int64_t(blockIdx.x) * kBlk + threadIdx.x; c < ncell; c += stride) {
+        const T v = T(vol[c]);
+        acc[0] += v * x[4 * c + 3];
+        acc[1] += v;
+    }
+    block_store(acc, 2, partial);
+}
+
+template <class T>
+__global__ void k_padd(T *x, int64_t ncell, T c) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < ncell; i += stride) x[4 * i + 3] += c;
+}
+
+__global__ void k_d2f(const double *x, float *y, int64_t n) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) y[i] = float(x[i]);
+}
+
+__global__ void k_f2d(const float *x, double *y, int64_t n) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) y[i] = double(x[i]);
+}
+
+static dim3 ew_grid(int64_t n) {
+    return dim3(unsigned(std::max<int64_t>(1, std::min<int64_t>(4096, (n + 255) / 256))));
+}
+
+#define CSD_LAUNCHED() CSD_HIP(hipGetLastError())
+
+template <class T>
+int32_t Vec<T>::mdot(const T *V, int64_t n, int cnt, const T *w, T *partial, T *out, hipStream_t s) {
+    const int nb = nblocks(n);
+    hipLaunchKernelGGL(k_mdot<T>, dim3(nb), dim3(kBlk), 0, s, V, n, cnt, w, partial);
+    hipLaunchKernelGGL(k_reduce<T>, dim3(1), dim3(kRedStride * 8 + 8), 0, s, partial, nb, out);
+    CSD_LAUNCHED();
+    return CSDYN_OK;
+}
+
+template <class T>
+int32_t Vec<T>::mupdate(T *w, const T *V, int64_t n, int cnt, const T *h, T *partial, T *out, hipStream_t s) {
+    const int nb = nblocks(n);
+    hipLaunchKernelGGL(k_mupdate<T>, dim3(nb), dim3(kBlk), 0, s, w, V, n, cnt, h, partial);
+    hipLaunchKernelGGL(k_reduce<T>, dim3(1), dim3(kRedStride * 8 + 8), 0, s, partial, nb, out);
+    CSD_LAUNCHED();
+    return CSDYN_OK;
+}
+
+template <class T>
+int32_t Vec<T>::scale(T *w, int64_t n, double a, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale<T>, ew_grid(n), dim3(256), 0, s, w, n, T(a));
+    CSD_LAUNCHED();
+    return CSDYN_OK;
+}
+
+template <class T>
+int32_t Vec<T>::axpby(double a, const T *x, double b, T *y, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpby<T>, ew_grid(n), dim3(256), 0, s, T(a), x, T(b), y, n);
+    CSD_LAUNCHED();
+    return CSDYN_OK;
+}
+
+template <class T>
+int32_t Vec<T>::lincomb(T *x, const T *Z, int64_t n, int cnt, const double *c, hipStream_t s) {
+    Coefs cf{};
+    for (int q = 0; q < cnt && q < kMaxRestart; ++q) cf.c[q] = c[q];
+    hipLaunchKernelGGL(k_lincomb<T>, ew_grid(n), dim3(256), 0, s, x, Z, n, cnt, cf);
+    CSD_LAUNCHED();
+    return CSDYN_OK;
+}
+
+template <class T>
+int32_t Vec<T>::copy(T *dst, const T *src, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy<T>, ew_grid(n), dim3(256), 0, s, dst, src, n);
+    CSD_LAUNCHED();
+    return CSDYN_OK;
+}
+
+template <class T>
+int32_t Vec<T>::zero(T *x, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero<T>, ew_grid(n), dim3(256), 0, s, x, n);
+    CSD_LAUNCHED();
+    return CSDYN_OK;
+}
+
+template <class T>
+int32_t Vec<T>::pmoments(const T *x, const double *vol, int64_t ncell, T *partial, T *out, hipStream_t s) {
+    const int nb = nblocks(ncell);
+    hipLaunchKernelGGL(k_pmoments<T>, dim3(nb), dim3(kBlk), 0, s, x, vol, ncell, partial);
+    hipLaunchKernelGGL(k_reduce<T>, dim3(1), dim3(kRedStride * 8 + 8), 0, s, partial, nb, out);
+    CSD_LAUNCHED();
+    return CSDYN_OK;
+}
+
+template <class T>
+int32_t Vec<T>::padd(T *x, int64_t ncell, double c, hipStream_t s) {
+    hipLaunchKernelGGL(k_padd<T>, ew_grid(ncell), dim3(256), 0, s, x, ncell, T(c));
+    CSD_LAUNCHED();
+    return CSDYN_OK;
+}
+
+int32_t convert_d2f(const double *x, float *y, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_d2f, ew_grid(n), dim3(256), 0, s, x, y, n);
+    CSD_LAUNCHED();
+    return CSDYN_OK;
+}
+
+int32_t convert_f2d(const float *x, double *y, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_f2d, ew_grid(n), dim3(256), 0, s, x, y, n);
+    CSD_LAUNCHED();
+    return CSDYN_OK;
+}
+
+template struct Vec<double>;
+template struct Vec<float>;
+
+// ------------------------------------------------------------------ GMRES
+template <class T>
+size_t Gmres<T>::bytes(int64_t n, int m, bool flexible) {
+    Carver c(nullptr);
+    Gmres<T> g;
+    g.carve(c, n, m, flexible);
+    return c.off + 256;
+}
+
+template <class T>
+void Gmres<T>::carve(Carver &c, int64_t n_, int m_, bool flexible_) {
+    n = n_; m = m_; flexible = flexible_;
+    V = c.take<T>(size_t(m + 1) * n);
+    if (flexible) Z = c.take<T>(size_t(m) * n);
+    z = c.take<T>(n);
+    r = c.take<T>(n);
+    tmp = c.take<T>(n);
+    partial = c.take<T>(size_t(kMaxBlocks) * kRedStride);
+    red = c.take<T>(2 * kRedStride);
+}
+
+template <class T>
+int32_t Gmres<T>::fetch(int cnt, std::vector<T> &out, hipStream_t s) {
+    out.resize(kRedStride);
+    CSD_HIP(hipMemcpyAsync(out.data(), red, sizeof(T) * kRedStride, hipMemcpyDeviceToHost, s));
+    CSD_HIP(hipStreamSynchronize(s));
+    (void)cnt;
+    return CSDYN_OK;
+}
+
+template <class T>
+int32_t Gmres<T>::norm(const T *v, double &out, hipStream_t s) {
+    CSD_TRY(Vec<T>::mdot(v, n, 0, v, partial, red, s));
+    std::vector<T> h;
+    CSD_TRY(fetch(0, h, s));
+    out = std::sqrt(double(h[kRedStride - 1]));
+    return CSDYN_OK;
+}
+
+template <class T>
+int32_t Gmres<T>::solve(const DevFn<T> &A, const DevFn<T> *M, const T *b, T *x, int maxit, double rtol,
+                        double atol, hipStream_t s, GmresResult &res) {
+    res = GmresResult();
+    if (m < 1 || m > kRedStride - 1 || maxit < 1) {
+        set_error("gmres: restart must be in [1, %d] and maxit >= 1", kRedStride - 1);
+        return CSDYN_EINVAL;
+    }
+    std::vector<double> H(size_t(m + 1) * m, 0.0), cs(m), sn(m), gv(m + 1), yv(m);
+    std::vector<T> hv;
+    // r = b - A x
+    CSD_TRY(A(x, tmp, s));
+    CSD_TRY(Vec<T>::copy(r, b, n, s));
+    CSD_TRY(Vec<T>::axpby(-1.0, tmp, 1.0, r, n, s));
+    double beta0;
+    CSD_TRY(norm(r, beta0, s));
+    if (!std::isfinite(beta0)) { set_error("gmres: non-finite initial residual"); return CSDYN_EBREAKDOWN; }
+    const double tol = std::max(atol, rtol * beta0);
+    int iters = 0, restarts = 0;
+    bool conv = beta0 <= tol;
+    double est = beta0, beta = beta0;
+    while (!conv && iters < maxit) {
+        CSD_TRY(Vec<T>::copy(V, r, n, s));
+        CSD_TRY(Vec<T>::scale(V, n, 1.0 / beta, s));
+        std::fill(gv.begin(), gv.end(), 0.0);
+        gv[0] = beta;
+        int jdone = 0;
+        for (int j = 0; j < m && iters < maxit; ++j) {
+            T *vj = V + size_t(j) * n, *w = V + size_t(j + 1) * n;
+            T *zj = flexible ? Z + size_t(j) * n : z;
+            if (M) CSD_TRY((*M)(vj, zj, s));
+            else CSD_TRY(Vec<T>::copy(zj, vj, n, s));
+            CSD_TRY(A(zj, w, s));
+            // classical Gram-Schmidt, two bandwidth passes
+            CSD_TRY(Vec<T>::mdot(V, n, j + 1, w, partial, red, s));
+            CSD_TRY(Vec<T>::mupdate(w, V, n, j + 1, red, partial, red + kRedStride, s));
+            std::vector<T> h1(2 * kRedStride);
+            CSD_HIP(hipMemcpyAsync(h1.data(), red, sizeof(T) * 2 * kRedStride, hipMemcpyDeviceToHost, s));
+            CSD_HIP(hipStreamSynchronize(s));
+            const double ww = double(h1[kRedStride - 1]);
+            double nn = double(h1[2 * kRedStride - 1]);
+            for (int i = 0; i <= j; ++i) H[size_t(i) * m + j] = double(h1[i]);
+            if (!(nn > 0.5 * ww)) {  // lost more than half the norm: re-orthogonalise once
+                CSD_TRY(Vec<T>::mdot(V, n, j + 1, w, partial, red, s));
+                CSD_TRY(Vec<T>::mupdate(w, V, n, j + 1, red, partial, red + kRedStride, s));
+                CSD_HIP(hipMemcpyAsync(h1.data(), red, sizeof(T) * 2 * kRedStride, hipMemcpyDeviceToHost, s));
+                CSD_HIP(hipStreamSynchronize(s));
+                for (int i = 0; i <= j; ++i) H[size_t(i) * m + j] += double(h1[i]);
+                nn = double(h1[2 * kRedStride - 1]);
+            }
+            const double hn = std::sqrt(std::max(nn, 0.0));
+            H[size_t(j + 1) * m + j] = hn;
+            ++iters;
+            jdone = j + 1;
+            if (!std::isfinite(hn) || !std::isfinite(ww)) { set_error("gmres: non-finite Arnoldi vector"); return CSDYN_EBREAKDOWN; }
+            for (int i = 0; i < j; ++i) {
+                const double a = H[size_t(i) * m + j], c = H[size_t(i + 1) * m + j];
+                H[size_t(i) * m + j] = cs[i] * a + sn[i] * c;
+                H[size_t(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+            }
+            const double a = H[size_t(j) * m + j], c = H[size_t(j + 1) * m + j];
+            const double den = std::hypot(a, c);
+            cs[j] = a / den;
+            sn[j] = c / den;
+            H[size_t(j) * m + j] = den;
+            H[size_t(j + 1) * m + j] = 0.0;
+            gv[j + 1] = -sn[j] * gv[j];
+            gv[j] = cs[j] * gv[j];
+            est = std::fabs(gv[j + 1]);
+            const bool happy = hn <= 1e-14 * std::sqrt(ww);
+            if (!happy) CSD_TRY(Vec<T>::scale(w, n, 1.0 / hn, s));
+            if (est <= tol || happy) { conv = true; break; }
+        }
+        for (int i = jdone - 1; i >= 0; --i) {
+            double acc = gv[i];
+            for (int k = i + 1; k < jdone; ++k) acc -= H[size_t(i) * m + k] * yv[k];
+            yv[i] = acc / H[size_t(i) * m + i];
+        }
+        if (flexible) {
+            CSD_TRY(Vec<T>::lincomb(x, Z, n, jdone, yv.data(), s));
+        } else {
+            CSD_TRY(Vec<T>::zero(tmp, n, s));
+            CSD_TRY(Vec<T>::lincomb(tmp, V, n, jdone, yv.data(), s));
+            if (M) CSD_TRY((*M)(tmp, z, s));
+            else CSD_TRY(Vec<T>::copy(z, tmp, n, s));
+            CSD_TRY(Vec<T>::axpby(1.0, z, 1.0, x, n, s));
+        }
+        CSD_TRY(A(x, tmp, s));
+        CSD_TRY(Vec<T>::copy(r, b, n, s));
+        CSD_TRY(Vec<T>::axpby(-1.0, tmp, 1.0, r, n, s));
+        CSD_TRY(norm(r, beta, s));
+        if (!conv) ++restarts;
+    }
+    res.iters = iters;
+    res.restarts = restarts;
+    res.relres_true = beta0 > 0 ? beta / beta0 : 0.0;
+    res.relres_est = beta0 > 0 ? est / beta0 : 0.0;
+    res.converged = conv;
+    return conv ? CSDYN_OK : CSDYN_ENOTCONV;
+}
+
+template struct Gmres<double>;
+template struct Gmres<float>;
+
+}  // namespace csd

@@ -1,0 +1,511 @@
+// RAS preconditioner on the GPU (Sec. 3.3): one-level restricted additive
+// Schwarz with ILU(0) subdomain solves (eq. onelevel) and the hybrid two-level
+// preconditioner (eq. twolevel, coarsesolve, finesolve).
+//
+// k_ras: one workgroup per subdomain.  It gathers x on the overlapping box
+// into a scratch vector, runs the L sweep and then the U sweep level by
+// level (a workgroup barrier between levels; the rows of one level are
+// independent), and writes only the owned cells (restricted scatter, so the
+// writes of different workgroups are disjoint).  Each wavefront takes one
+// 64-row slice of a level: entry q of all 64 rows is one coalesced load.
+#include <algorithm>
+#include <cstring>
+#include <memory>
+#include <mutex>
+
+#include "krylov.h"
+#include "ras_host.h"
+
+namespace csd {
+
+template <class TF>
+struct DevSweep {
+    const int32_t *lev_slice;
+    const int64_t *sl_off;
+    const int32_t *sl_w;
+    const int32_t *sl_rows;
+    const TF *sl_dinv;
+    const TF *val;
+    const int32_t *col;
+};
+
+template <class TF>
+struct DevRas {
+    int nsd;
+    const SdInfo *sd;
+    const int32_t *gcell, *own;
+    DevSweep<TF> L, U;
+    TF *tvec;
+};
+
+constexpr int kRasBlk = 256;
+
+template <class TV, class TF, bool UPPER>
+__device__ __forceinline__ void sweep(const DevSweep<TF> &S, int lev0, int lev1, TF *__restrict__ t) {
+    const int lane = threadIdx.x % 64, wv = threadIdx.x / 64, nw = kRasBlk / 64;
+    for (int lv = lev0; lv < lev1; ++lv) {
+        const int s1 = S.lev_slice[lv + 1];
+        for (int sl = S.lev_slice[lv] + wv; sl < s1; sl += nw) {
+            const int r = S.sl_rows[sl * 64 + lane];
+            const int w = S.sl_w[sl];
+            const int64_t base = S.sl_off[sl] + lane;
+            TF acc = r >= 0 ? t[r] : TF(0);
+            for (int q = 0; q < w; ++q) {
+                const int64_t at = base + int64_t(q) * 64;
+                acc -= S.val[at] * t[S.col[at]];
+            }
+            if (r >= 0) t[r] = UPPER ? acc * S.sl_dinv[sl * 64 + lane] : acc;
+        }
+        __syncthreads();
+    }
+}
+
+template <class TV, class TF>
+__global__ __launch_bounds__(kRasBlk) void k_ras(DevRas<TF> R, const TV *__restrict__ x, TV *__restrict__ y) {
+    const SdInfo I = R.sd[blockIdx.x];
+    TF *t = R.tvec + I.t_off;
+    const int32_t *gc = R.gcell + I.cell_off;
+    for (int l = threadIdx.x; l < I.nloc; l += kRasBlk) {
+        const int64_t g = int64_t(gc[l]) * 4;
+        for (int c = 0; c < 4; ++c) t[4 * l + c] = TF(x[g + c]);
+    }
+    __syncthreads();
+    sweep<TV, TF, false>(R.L, I.levL0, I.levL1, t);
+    sweep<TV, TF, true>(R.U, I.levU0, I.levU1, t);
+    for (int o = threadIdx.x; o < I.nown; o += kRasBlk) {
+        const int l = R.own[I.own_off + o];
+        const int64_t g = int64_t(gc[l]) * 4;
+        for (int c = 0; c < 4; ++c) y[g + c] = TV(t[4 * l + c]);
+    }
+}
+
+// restriction: mean of the 8 children; prolongation: copy to the children
+template <class T>
+__global__ void k_restrict(const T *__restrict__ xf, T *__restrict__ xc, int nc, int nrc) {
+    const int64_t ncell = 6 * int64_t(nc) * nc * nrc;
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    const int nf = 2 * nc, nrf = 2 * nrc;
+    for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < 4 * ncell; q += stride) {
+        const int c = int(q % 4);
+        int64_t cell = q / 4;
+        const int I = int(cell % nc); cell /= nc;
+        const int J = int(cell % nc); cell /= nc;
+        const int K = int(cell % nrc);
+        const int p = int(cell / nrc);
+        T s = 0;
+        for (int dk = 0; dk < 2; ++dk)
+            for (int dj = 0; dj < 2; ++dj)
+                for (int di = 0; di < 2; ++di)
+                    s += xf[4 * (((int64_t(p) * nrf + 2 * K + dk) * nf + 2 * J + dj) * nf + 2 * I + di) + c];
+        xc[q] = s * T(0.125);
+    }
+}
+
+template <class T>
+__global__ void k_prolong(const T *__restrict__ xc, T *__restrict__ xf, int nc, int nrc) {
+    const int nf = 2 * nc, nrf = 2 * nrc;
+    const int64_t n = 24 * int64_t(nf) * nf * nrf;
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < n; q += stride) {
+        const int c = int(q % 4);
+        int64_t cell = q / 4;
+        const int i = int(cell % nf); cell /= nf;
+        const int j = int(cell % nf); cell /= nf;
+        const int k = int(cell % nrf);
+        const int p = int(cell / nrf);
+        xf[q] = xc[4 * (((int64_t(p) * nrc + k / 2) * nc + j / 2) * nc + i / 2) + c];
+    }
+}
+
+static dim3 grid_for(int64_t n) { return dim3(unsigned(std::max<int64_t>(1, std::min<int64_t>(8192, (n + 255) / 256)))); }
+
+// One level of RAS data on the device (factors in TF).
+struct OneLevel {
+    int nsd = 0;
+    int64_t tlen = 0, nnz = 0;
+    int max_levels = 0;
+    SdInfo *sd = nullptr;
+    int32_t *gcell = nullptr, *own = nullptr;
+    int32_t *Llev = nullptr, *Lw = nullptr, *Lrows = nullptr, *Lcol = nullptr;
+    int64_t *Loff = nullptr;
+    int32_t *Ulev = nullptr, *Uw = nullptr, *Urows = nullptr, *Ucol = nullptr;
+    int64_t *Uoff = nullptr;
+    void *Lval = nullptr, *Uval = nullptr, *Udinv = nullptr;
+    void *tvec = nullptr;
+    int precision = 0;
+
+    static void layout(Carver &c, const HostRas &H, int precision, OneLevel &o) {
+        const size_t fs = precision ? sizeof(float) : sizeof(double);
+        o.nsd = H.nsd; o.tlen = H.tlen; o.nnz = H.nnz; o.precision = precision; o.max_levels = H.max_levels;
+        o.sd = c.take<SdInfo>(H.sd.size());
+        o.gcell = c.take<int32_t>(H.gcell.size());
+        o.own = c.take<int32_t>(H.own.size());
+        o.Llev = c.take<int32_t>(H.L.lev_slice.size()); o.Loff = c.take<int64_t>(H.L.sl_off.size());
+        o.Lw = c.take<int32_t>(H.L.sl_w.size()); o.Lrows = c.take<int32_t>(H.L.sl_rows.size());
+        o.Lcol = c.take<int32_t>(H.L.col.size()); o.Lval = c.take<char>(H.L.val.size() * fs);
+        o.Ulev = c.take<int32_t>(H.U.lev_slice.size()); o.Uoff = c.take<int64_t>(H.U.sl_off.size());
+        o.Uw = c.take<int32_t>(H.U.sl_w.size()); o.Urows = c.take<int32_t>(H.U.sl_rows.size());
+        o.Ucol = c.take<int32_t>(H.U.col.size()); o.Uval = c.take<char>(H.U.val.size() * fs);
+        o.Udinv = c.take<char>(H.U.sl_diag.size() * fs);
+        o.tvec = c.take<char>(size_t(H.tlen) * fs);
+    }
+
+    int32_t upload(const HostRas &H) const {
+        auto up = [](void *d, const void *s, size_t b) { return b ? hipMemcpy(d, s, b, hipMemcpyHostToDevice) : hipSuccess; };
+        CSD_HIP(up(sd, H.sd.data(), H.sd.size() * sizeof(SdInfo)));
+        CSD_HIP(up(gcell, H.gcell.data(), H.gcell.size() * 4));
+        CSD_HIP(up(own, H.own.data(), H.own.size() * 4));
+        CSD_HIP(up(Llev, H.L.lev_slice.data(), H.L.lev_slice.size() * 4));
+        CSD_HIP(up(Loff, H.L.sl_off.data(), H.L.sl_off.size() * 8));
+        CSD_HIP(up(Lw, H.L.sl_w.data(), H.L.sl_w.size() * 4));
+        CSD_HIP(up(Lrows, H.L.sl_rows.data(), H.L.sl_rows.size() * 4));
+        CSD_HIP(up(Lcol, H.L.col.data(), H.L.col.size() * 4));
+        CSD_HIP(up(Ulev, H.U.lev_slice.data(), H.U.lev_slice.size() * 4));
+        CSD_HIP(up(Uoff, H.U.sl_off.data(), H.U.sl_off.size() * 8));
+        CSD_HIP(up(Uw, H.U.sl_w.data(), H.U.sl_w.size() * 4));
+        CSD_HIP(up(Urows, H.U.sl_rows.data(), H.U.sl_rows.size() * 4));
+        CSD_HIP(up(Ucol, H.U.col.data(), H.U.col.size() * 4));
+        if (precision) {
+            std::vector<float> f(H.L.val.begin(), H.L.val.end());
+            CSD_HIP(up(Lval, f.data(), f.size() * 4));
+            f.assign(H.U.val.begin(), H.U.val.end());
+            CSD_HIP(up(Uval, f.data(), f.size() * 4));
+            f.assign(H.U.sl_diag.size(), 0.0f);
+            for (size_t a = 0; a < f.size(); ++a) f[a] = H.U.sl_diag[a] != 0.0 ? 1.0f / float(H.U.sl_diag[a]) : 0.0f;
+            CSD_HIP(up(Udinv, f.data(), f.size() * 4));
+        } else {
+            CSD_HIP(up(Lval, H.L.val.data(), H.L.val.size() * 8));
+            CSD_HIP(up(Uval, H.U.val.data(), H.U.val.size() * 8));
+            std::vector<double> d(H.U.sl_diag.size(), 0.0);
+            for (size_t a = 0; a < d.size(); ++a) d[a] = H.U.sl_diag[a] != 0.0 ? 1.0 / H.U.sl_diag[a] : 0.0;
+            CSD_HIP(up(Udinv, d.data(), d.size() * 8));
+        }
+        return CSDYN_OK;
+    }
+
+    template <class TF>
+    DevRas<TF> dev() const {
+        DevRas<TF> R;
+        R.nsd = nsd; R.sd = sd; R.gcell = gcell; R.own = own;
+        R.L = DevSweep<TF>{Llev, Loff, Lw, Lrows, nullptr, (const TF *)Lval, Lcol};
+        R.U = DevSweep<TF>{Ulev, Uoff, Uw, Urows, (const TF *)Udinv, (const TF *)Uval, Ucol};
+        R.tvec = (TF *)tvec;
+        return R;
+    }
+
+    template <class TV>
+    int32_t apply(const TV *x, TV *y, hipStream_t s) const {
+        if (precision) hipLaunchKernelGGL((k_ras<TV, float>), dim3(nsd), dim3(kRasBlk), 0, s, dev<float>(), x, y);
+        else hipLaunchKernelGGL((k_ras<TV, double>), dim3(nsd), dim3(kRasBlk), 0, s, dev<double>(), x, y);
+        CSD_HIP(hipGetLastError());
+        return CSDYN_OK;
+    }
+};
+
+// Host build result cached between csdyn_ras_workspace_bytes and
+// csdyn_ras_setup (same operator and options).
+struct HostBuild {
+    csdyn_grid g;
+    csdyn_op op;
+    csdyn_ras_opts o;
+    HostRas fine, coarse;
+    HostGeom gc;
+};
+
+static std::mutex g_cache_mu;
+static std::unique_ptr<HostBuild> g_cache;
+
+static bool same_key(const HostBuild &b, const csdyn_grid &g, const csdyn_op &op, const csdyn_ras_opts &o) {
+    return std::memcmp(&b.g, &g, sizeof(g)) == 0 && std::memcmp(&b.op, &op, sizeof(op)) == 0 &&
+           std::memcmp(&b.o, &o, sizeof(o)) == 0;
+}
+
+static int32_t check_opts(const csdyn_opctx *ctx, const csdyn_ras_opts *o) {
+    if (!ctx || !o) { set_error("ras: null argument"); return CSDYN_EINVAL; }
+    if (o->levels != 1 && o->levels != 2) { set_error("ras: levels must be 1 or 2"); return CSDYN_EINVAL; }
+    if (o->precision != 0 && o->precision != 1) { set_error("ras: precision must be 0 or 1"); return CSDYN_EINVAL; }
+    if (o->levels == 2) {
+        if (ctx->g.n % 2 || ctx->g.nr % 2 || o->sub[0] % 2 || o->sub[1] % 2 || o->sub[2] % 2 || ctx->g.n / 2 < 4) {
+            set_error("ras: two-level needs even N, Nr and subdomain sizes, and N/2 >= 4");
+            return CSDYN_EINVAL;
+        }
+        if (o->coarse_restart < 1 || o->coarse_restart > kRedStride - 1 || o->coarse_maxit < 1 || !(o->coarse_rtol > 0)) {
+            set_error("ras: coarse_restart in [1,32], coarse_maxit >= 1, coarse_rtol > 0");
+            return CSDYN_EINVAL;
+        }
+    }
+    return CSDYN_OK;
+}
+
+static int32_t host_build(const csdyn_opctx *ctx, const csdyn_ras_opts *o, std::unique_ptr<HostBuild> &out) {
+    auto b = std::make_unique<HostBuild>();
+    b->g = ctx->g; b->op = ctx->op; b->o = *o;
+    CSD_TRY(build_host_ras(ctx->hg, ctx->op, o->sub, o->overlap, b->fine));
+    if (o->levels == 2) {
+        csdyn_grid gc = ctx->g;
+        gc.n /= 2; gc.nr /= 2;
+        CSD_TRY(b->gc.build(gc));
+        const int subc[3] = {o->sub[0] / 2, o->sub[1] / 2, o->sub[2] / 2};
+        CSD_TRY(build_host_ras(b->gc, ctx->op, subc, o->overlap, b->coarse));
+    }
+    out = std::move(b);
+    return CSDYN_OK;
+}
+
+}  // namespace csd
+
+using namespace csd;
+
+struct csdyn_ras {
+    csdyn_ras_opts o;
+    const csdyn_opctx *fine_ctx;
+    OneLevel fine;
+    // two-level
+    csdyn_opctx coarse_ctx;
+    OneLevel coarse;
+    void *cws = nullptr;        // coarse GMRES workspace
+    void *buf = nullptr;        // fine/coarse temporaries
+    int64_t nf = 0, nc = 0;
+    mutable int64_t inner_iters = 0;
+    double vol_c = 0;           // total coarse volume
+
+    template <class T>
+    int32_t two_level(const T *x, T *y, hipStream_t s) const;
+};
+
+static void layout_all(Carver &c, const HostBuild &b, csdyn_ras &R) {
+    OneLevel::layout(c, b.fine, b.o.precision, R.fine);
+    if (b.o.levels == 2) {
+        const size_t fs = b.o.precision ? sizeof(float) : sizeof(double);
+        const int64_t nf = 24 * int64_t(b.g.n) * b.g.n * b.g.nr;
+        const int64_t nc = 24 * int64_t(b.gc.n) * b.gc.n * b.gc.nr;
+        R.nf = nf; R.nc = nc;
+        void *cg = c.take<char>(devgeom_bytes(b.gc.n, b.gc.nr));
+        R.coarse_ctx.ws = cg;
+        OneLevel::layout(c, b.coarse, b.o.precision, R.coarse);
+        const size_t gb = b.o.precision ? Gmres<float>::bytes(nc, b.o.coarse_restart, false)
+                                        : Gmres<double>::bytes(nc, b.o.coarse_restart, false);
+        R.cws = c.take<char>(gb);
+        // fine: x32, w, t, y32 ; coarse: rc, ec ; FP32 edge buffers for the fine operator
+        R.buf = c.take<char>(4 * nf * fs + 2 * nc * fs + 2 * size_t(24) * b.g.nr * b.g.n * 8 * fs + 1024);
+    }
+}
+
+extern "C" int32_t csdyn_ras_workspace_bytes(const csdyn_opctx *ctx, const csdyn_ras_opts *o, size_t *bytes) {
+    clear_error();
+    if (!bytes) { set_error("ras: null bytes"); return CSDYN_EINVAL; }
+    CSD_TRY(check_opts(ctx, o));
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    if (!g_cache || !same_key(*g_cache, ctx->g, ctx->op, *o)) {
+        g_cache.reset();
+        CSD_TRY(host_build(ctx, o, g_cache));
+    }
+    csdyn_ras R;
+    Carver c(nullptr);
+    layout_all(c, *g_cache, R);
+    *bytes = c.off + 256;
+    return CSDYN_OK;
+}
+
+extern "C" int32_t csdyn_ras_setup(const csdyn_opctx *ctx, const csdyn_ras_opts *o, void *ws, size_t ws_bytes,
+                                   void *stream, csdyn_ras **out) {
+    clear_error();
+    if (!ws || !out) { set_error("ras: null argument"); return CSDYN_EINVAL; }
+    *out = nullptr;
+    CSD_TRY(check_opts(ctx, o));
+    std::unique_ptr<HostBuild> b;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        if (g_cache && same_key(*g_cache, ctx->g, ctx->op, *o)) b = std::move(g_cache);
+    }
+    if (!b) CSD_TRY(host_build(ctx, o, b));
+    auto R = std::make_unique<csdyn_ras>();
+    R->o = *o;
+    R->fine_ctx = ctx;
+    Carver c(ws);
+    layout_all(c, *b, *R);
+    if (c.off + 256 > ws_bytes) { set_error("ras: workspace %zu < %zu bytes", ws_bytes, c.off + 256); return CSDYN_ENOMEM; }
+    CSD_TRY(R->fine.upload(b->fine));
+    if (o->levels == 2) {
+        R->coarse_ctx.g = ctx->g;
+        R->coarse_ctx.g.n /= 2; R->coarse_ctx.g.nr /= 2;
+        R->coarse_ctx.op = ctx->op;
+        R->coarse_ctx.hg = b->gc;
+        R->coarse_ctx.ws_bytes = devgeom_bytes(b->gc.n, b->gc.nr);
+        CSD_TRY(devgeom_setup(R->coarse_ctx.hg, R->coarse_ctx.ws, &R->coarse_ctx.dg));
+        CSD_TRY(R->coarse.upload(b->coarse));
+        double v = 0;
+        for (double a : b->gc.vol) v += a;
+        R->vol_c = v;
+    }
+    if (stream) CSD_HIP(hipStreamSynchronize((hipStream_t)stream));
+    *out = R.release();
+    return CSDYN_OK;
+}
+
+template <class T>
+int32_t csdyn_ras::two_level(const T *x, T *y, hipStream_t s) const {
+    const int nc_ = coarse_ctx.g.n, nrc = coarse_ctx.g.nr;
+    const int64_t ncell_c = nc / 4;
+    T *b0 = (T *)buf;
+    T *w = b0 + nf, *t = b0 + 2 * nf;
+    T *rc = b0 + 4 * nf, *ec = rc + nc;
+    T *G32 = ec + nc, *SF32 = G32 + size_t(24) * fine_ctx->g.nr * fine_ctx->g.n * 4;
+    // r_c = I_f^c x
+    hipLaunchKernelGGL(k_restrict<T>, grid_for(nc), dim3(256), 0, s, x, rc, nc_, nrc);
+    CSD_HIP(hipGetLastError());
+    if (fine_ctx->op.kind == CSDYN_VP) {  // coarse Neumann solvability: zero volume-weighted mean of P
+        Gmres<T> gm;
+        Carver cc(cws);
+        gm.carve(cc, nc, o.coarse_restart, false);
+        CSD_TRY(Vec<T>::pmoments(rc, coarse_ctx.dg.vol, ncell_c, gm.partial, gm.red, s));
+        T mom[kRedStride];
+        CSD_HIP(hipMemcpyAsync(mom, gm.red, sizeof(T) * kRedStride, hipMemcpyDeviceToHost, s));
+        CSD_HIP(hipStreamSynchronize(s));
+        CSD_TRY(Vec<T>::padd(rc, ncell_c, -double(mom[0]) / double(mom[1]), s));
+    }
+    // e_c ~ A_c^{-1} r_c : GMRES(coarse_restart) from 0 to coarse_rtol, coarse one-level RAS
+    CSD_TRY(Vec<T>::zero(ec, nc, s));
+    Gmres<T> gm;
+    Carver cc(cws);
+    gm.carve(cc, nc, o.coarse_restart, false);
+    const csdyn_opctx *cctx = &coarse_ctx;
+    DevFn<T> Ac;
+    if constexpr (sizeof(T) == 8) Ac = [cctx](const T *in, T *outv, hipStream_t st) { return op_launch(cctx, in, outv, st); };
+    else Ac = [cctx](const T *in, T *outv, hipStream_t st) { return op_launch_f32(cctx, in, outv, (float *)cctx->dg.G, (float *)cctx->dg.SF, st); };
+    const OneLevel *cl = &coarse;
+    DevFn<T> Mc = [cl](const T *in, T *outv, hipStream_t st) { return cl->apply<T>(in, outv, st); };
+    GmresResult gr;
+    int32_t rcode = gm.solve(Ac, &Mc, rc, ec, o.coarse_maxit, o.coarse_rtol, 0.0, s, gr);
+    if (rcode < 0) return rcode;
+    inner_iters += gr.iters;
+    // w = I_c^f e_c ; t = x - A_f w ; y = w + M_one^{-1} t
+    hipLaunchKernelGGL(k_prolong<T>, grid_for(nf), dim3(256), 0, s, ec, w, nc_, nrc);
+    CSD_HIP(hipGetLastError());
+    if constexpr (sizeof(T) == 8) CSD_TRY(op_launch(fine_ctx, w, t, s));
+    else CSD_TRY(op_launch_f32(fine_ctx, w, t, G32, SF32, s));
+    CSD_TRY(Vec<T>::axpby(1.0, x, -1.0, t, nf, s));
+    CSD_TRY(fine.apply<T>(t, y, s));
+    CSD_TRY(Vec<T>::axpby(1.0, w, 1.0, y, nf, s));
+    return CSDYN_OK;
+}
+
+namespace csd {
+// y = M^{-1} x with FP64 vectors at the boundary.
+int32_t ras_apply_d(const csdyn_ras *pc, const double *x, double *y, hipStream_t s) {
+    if (pc->o.levels == 1) return pc->fine.apply<double>(x, y, s);
+    if (pc->o.precision == 0) return pc->two_level<double>(x, y, s);
+    float *b0 = (float *)pc->buf;
+    float *x32 = b0, *y32 = b0 + 3 * pc->nf;
+    CSD_TRY(convert_d2f(x, x32, pc->nf, s));
+    CSD_TRY(pc->two_level<float>(x32, y32, s));
+    return convert_f2d(y32, y, pc->nf, s);
+}
+int64_t ras_inner_iters(const csdyn_ras *pc, bool reset) {
+    const int64_t v = pc->inner_iters;
+    if (reset) pc->inner_iters = 0;
+    return v;
+}
+}  // namespace csd
+
+extern "C" int32_t csdyn_ras_apply(const csdyn_ras *pc, const double *x, double *y, void *stream) {
+    clear_error();
+    if (!pc || !x || !y) { set_error("ras_apply: null argument"); return CSDYN_EINVAL; }
+    const size_t nb = size_t(24) * pc->fine_ctx->g.n * pc->fine_ctx->g.n * pc->fine_ctx->g.nr * sizeof(double);
+    const char *xa = (const char *)x, *ya = (const char *)y;
+    if (xa < ya + nb && ya < xa + nb) { set_error("ras_apply: x and y alias"); return CSDYN_EINVAL; }
+    return ras_apply_d(pc, x, y, (hipStream_t)stream);
+}
+
+extern "C" void csdyn_ras_destroy(csdyn_ras *pc) { delete pc; }
+
+extern "C" int32_t csdyn_ras_inspect(const csdyn_grid *g, const csdyn_op *op, const int32_t sub[3], int32_t overlap,
+                                     int32_t s, int64_t *nloc, int64_t *nnz, int32_t *gcell, int32_t *owned,
+                                     int64_t *rowptr, int32_t *col, double *val) {
+    clear_error();
+    if (!g || !op || !sub || !nloc || !nnz) { set_error("ras_inspect: null argument"); return CSDYN_EINVAL; }
+    HostGeom hg;
+    CSD_TRY(hg.build(*g));
+    const int sb[3] = {sub[0], sub[1], sub[2]};
+    std::vector<int32_t> gc, own, ci;
+    std::vector<int64_t> rp;
+    std::vector<double> v;
+    CSD_TRY(host_subdomain(hg, *op, sb, overlap, s, gc, own, rp, ci, v));
+    *nloc = int64_t(gc.size());
+    *nnz = int64_t(ci.size());
+    if (gcell) {
+        std::copy(gc.begin(), gc.end(), gcell);
+        std::fill(owned, owned + gc.size(), 0);
+        for (int32_t l : own) owned[l] = 1;
+    }
+    if (rowptr) {
+        std::copy(rp.begin(), rp.end(), rowptr);
+        std::copy(ci.begin(), ci.end(), col);
+        std::copy(v.begin(), v.end(), val);
+    }
+    return CSDYN_OK;
+}
+
+// ------------------------------------------------------------------ GMRES
+struct SolveLayout {
+    Gmres<double> gm;
+    double *bproj;
+};
+
+static void solve_layout(Carver &c, const csdyn_opctx *ctx, const csdyn_gmres_opts *o, SolveLayout &L) {
+    const int64_t n = 24 * int64_t(ctx->g.n) * ctx->g.n * ctx->g.nr;
+    L.gm.carve(c, n, o->restart, o->flexible != 0);
+    L.bproj = c.take<double>(n);
+}
+
+extern "C" int32_t csdyn_gmres_workspace_bytes(const csdyn_opctx *ctx, const csdyn_gmres_opts *o, size_t *bytes) {
+    clear_error();
+    if (!ctx || !o || !bytes) { set_error("gmres: null argument"); return CSDYN_EINVAL; }
+    if (o->restart < 1 || o->restart > kRedStride - 1) { set_error("gmres: restart must be in [1, 32]"); return CSDYN_EINVAL; }
+    Carver c(nullptr);
+    SolveLayout L;
+    solve_layout(c, ctx, o, L);
+    *bytes = c.off + 256;
+    return CSDYN_OK;
+}
+
+extern "C" int32_t csdyn_gmres_solve(const csdyn_opctx *ctx, const csdyn_ras *pc, const csdyn_gmres_opts *o,
+                                     const double *b, double *x, void *ws, size_t ws_bytes, void *stream,
+                                     csdyn_gmres_stats *st) {
+    clear_error();
+    if (!ctx || !o || !b || !x || !ws) { set_error("gmres: null argument"); return CSDYN_EINVAL; }
+    if (o->restart < 1 || o->restart > kRedStride - 1 || o->maxit < 1) { set_error("gmres: restart in [1,32], maxit >= 1"); return CSDYN_EINVAL; }
+    if (pc && pc->fine_ctx->g.n != ctx->g.n) { set_error("gmres: preconditioner built for another grid"); return CSDYN_EINVAL; }
+    Carver c(ws);
+    SolveLayout L;
+    solve_layout(c, ctx, o, L);
+    if (c.off + 256 > ws_bytes) { set_error("gmres: workspace %zu < %zu bytes", ws_bytes, c.off + 256); return CSDYN_ENOMEM; }
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = L.gm.n, ncell = n / 4;
+    CSD_TRY(Vec<double>::copy(L.bproj, b, n, s));
+    auto project = [&](double *v) -> int32_t {
+        CSD_TRY(Vec<double>::pmoments(v, ctx->dg.vol, ncell, L.gm.partial, L.gm.red, s));
+        double mom[kRedStride];
+        CSD_HIP(hipMemcpyAsync(mom, L.gm.red, sizeof(mom), hipMemcpyDeviceToHost, s));
+        CSD_HIP(hipStreamSynchronize(s));
+        return Vec<double>::padd(v, ncell, -mom[0] / mom[1], s);
+    };
+    if (ctx->op.kind == CSDYN_VP) CSD_TRY(project(L.bproj));
+    DevFn<double> A = [ctx](const double *in, double *outv, hipStream_t st) { return op_launch(ctx, in, outv, st); };
+    DevFn<double> M = [pc](const double *in, double *outv, hipStream_t st) { return ras_apply_d(pc, in, outv, st); };
+    if (pc) ras_inner_iters(pc, true);
+    GmresResult res;
+    int32_t rc = L.gm.solve(A, pc ? &M : nullptr, L.bproj, x, o->maxit, o->rtol, o->atol, s, res);
+    if (rc < 0) return rc;
+    if (ctx->op.kind == CSDYN_VP) CSD_TRY(project(x));
+    CSD_HIP(hipStreamSynchronize(s));
+    if (st) {
+        std::memset(st, 0, sizeof(*st));
+        st->iters = res.iters;
+        st->restarts = res.restarts;
+        st->inner_iters = pc ? ras_inner_iters(pc, false) : 0;
+        st->relres_true = res.relres_true;
+        st->relres_est = res.relres_est;
+    }
+    return rc;
+}

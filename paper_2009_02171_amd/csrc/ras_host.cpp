@@ -1,0 +1,433 @@
+// Host construction of the RAS / ILU(0) data (Sec. 3.3, eq. onelevel).
+#include "ras_host.h"
+
+#include <omp.h>
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+namespace csd {
+
+namespace {
+
+using TermVec = std::vector<std::pair<int64_t, double>>;
+
+// Structural expansion of one row of A into (global unknown, weight) terms.
+// Every term of the stencil formula is emitted whatever its value, so the
+// set of columns is the structural pattern.
+class Expander {
+   public:
+    Expander(const HostGeom &g, const csdyn_op &op, TermVec &out) : g_(g), op_(op), out_(out) {}
+
+    // value of component c at extended position (p, i, j, k)
+    void value(int p, int i, int j, int k, int c, double w) {
+        const int n = g_.n, nr = g_.nr;
+        if (k < 0 || k >= nr) {
+            const int kin = k < 0 ? 0 : nr - 1;
+            if (op_.kind == CSDYN_VP) {
+                value(p, i, j, kin, c, c < 3 ? -w : w);
+            } else if (c == 3) {
+                value(p, i, j, kin, 3, -w);
+            } else {
+                const double rg = k < 0 ? g_.rf[0] - 0.5 * g_.hr : g_.rf[nr] + 0.5 * g_.hr;
+                const double q = (g_.rk[kin] / rg) * (g_.rk[kin] / rg);
+                const double *nv = &g_.nrm[((size_t(p) * n + j) * n + i) * 3];
+                for (int d = 0; d < 3; ++d) value(p, i, j, kin, d, w * ((c == d ? -1.0 : 0.0) + (1.0 + q) * nv[c] * nv[d]));
+            }
+            return;
+        }
+        const bool iin = i >= 0 && i < n, jin = j >= 0 && j < n;
+        if (iin && jin) {
+            out_.emplace_back(4 * g_.cell(p, i, j, k) + c, w);
+            return;
+        }
+        if (!iin && !jin) {
+            const int ic = i < 0 ? 0 : n - 1, jc = j < 0 ? 0 : n - 1;
+            value(p, i, jc, k, c, w);
+            value(p, ic, j, k, c, w);
+            value(p, ic, jc, k, c, -w);
+            return;
+        }
+        const int e = !iin ? (i < 0 ? 0 : 1) : (j < 0 ? 2 : 3);
+        const int t = !iin ? j : i;
+        const GhostEntry &G = g_.ghost[(p * 4 + e) * size_t(n) + t];
+        for (int m = 0; m < 4; ++m) {
+            if (G.fix_i) value(G.q, G.idx, G.m0 + m, k, c, w * G.w[m]);
+            else value(G.q, G.m0 + m, G.idx, k, c, w * G.w[m]);
+        }
+    }
+
+    // one-sided outward Laplacian flux of component c through lateral face f
+    // (0 W, 1 E, 2 S, 3 N) of cell (p, i, j, k), times w
+    void lap_face(int p, int i, int j, int k, int f, int c, double w) {
+        const int n = g_.n;
+        const double ih = 1.0 / g_.hs, i4h = 0.25 / g_.hs;
+        if (f <= 1) {
+            const int fi = f == 0 ? i : i + 1, il = fi - 1, ir = fi;
+            const size_t a = size_t(j) * (n + 1) + fi;
+            const double s = f == 1 ? w : -w;
+            const double a11 = g_.a11x[a] * ih * s, a12 = g_.a12x[a] * i4h * s;
+            value(p, ir, j, k, c, a11);
+            value(p, il, j, k, c, -a11);
+            value(p, il, j + 1, k, c, a12);
+            value(p, ir, j + 1, k, c, a12);
+            value(p, il, j - 1, k, c, -a12);
+            value(p, ir, j - 1, k, c, -a12);
+        } else {
+            const int fj = f == 2 ? j : j + 1, jl = fj - 1, jr = fj;
+            const size_t a = size_t(fj) * n + i;
+            const double s = f == 3 ? w : -w;
+            const double a22 = g_.a22y[a] * ih * s, a12 = g_.a12y[a] * i4h * s;
+            value(p, i, jr, k, c, a22);
+            value(p, i, jl, k, c, -a22);
+            value(p, i + 1, jl, k, c, a12);
+            value(p, i + 1, jr, k, c, a12);
+            value(p, i - 1, jl, k, c, -a12);
+            value(p, i - 1, jr, k, c, -a12);
+        }
+    }
+
+    // one-sided outward divergence flux (sqrt(g) g^m / r) . (v_c + v_nb)/2
+    void div_face(int p, int i, int j, int k, int f, double w) {
+        const int n = g_.n;
+        const size_t nf = g_.nf();
+        int ni = i, nj = j;
+        const double *tv;
+        if (f <= 1) {
+            const int fi = f == 0 ? i : i + 1;
+            ni = f == 0 ? i - 1 : i + 1;
+            tv = &g_.t1[(p * nf + size_t(j) * (n + 1) + fi) * 3];
+        } else {
+            const int fj = f == 2 ? j : j + 1;
+            nj = f == 2 ? j - 1 : j + 1;
+            tv = &g_.t2[(p * nf + size_t(fj) * n + i) * 3];
+        }
+        const double s = (f == 1 || f == 3) ? 0.5 * w : -0.5 * w;
+        for (int d = 0; d < 3; ++d) {
+            value(p, i, j, k, d, s * tv[d]);
+            value(p, ni, nj, k, d, s * tv[d]);
+        }
+    }
+
+    bool on_edge(int i, int j, int f) const {
+        return (f == 0 && i == 0) || (f == 1 && i == g_.n - 1) || (f == 2 && j == 0) || (f == 3 && j == g_.n - 1);
+    }
+
+    // cell of the neighbour panel across edge face f of (i, j)
+    void partner(int p, int i, int j, int f, int &q, int &iq, int &jq, int &fq) const {
+        const FaceEntry &F = g_.face[(p * 4 + f) * size_t(g_.n) + (f <= 1 ? j : i)];
+        q = F.q; fq = F.e;
+        switch (F.e) {
+            case 0: iq = 0; jq = F.t; break;
+            case 1: iq = g_.n - 1; jq = F.t; break;
+            case 2: iq = F.t; jq = 0; break;
+            default: iq = F.t; jq = g_.n - 1; break;
+        }
+    }
+
+    // w * lap(component c) at cell (p, i, j, k)
+    void laplacian(int p, int i, int j, int k, int c, double w) {
+        const int n = g_.n;
+        const double rk = g_.rk[k];
+        const double wl = w / (rk * rk * g_.sc[size_t(j) * n + i] * g_.hs);
+        for (int f = 0; f < 4; ++f) {
+            if (!on_edge(i, j, f)) { lap_face(p, i, j, k, f, c, wl); continue; }
+            int q, iq, jq, fq;
+            partner(p, i, j, f, q, iq, jq, fq);
+            lap_face(p, i, j, k, f, c, 0.5 * wl);
+            lap_face(q, iq, jq, k, fq, c, -0.5 * wl);
+        }
+        const double wr = w / (rk * rk * g_.hr * g_.hr);
+        const double up = g_.rf[k + 1] * g_.rf[k + 1] * wr, dn = g_.rf[k] * g_.rf[k] * wr;
+        value(p, i, j, k + 1, c, up);
+        value(p, i, j, k, c, -up);
+        value(p, i, j, k, c, -dn);
+        value(p, i, j, k - 1, c, dn);
+    }
+
+    // w * D(v) at cell (p, i, j, k), v = components 0..2
+    void divergence(int p, int i, int j, int k, double w) {
+        const int n = g_.n;
+        const double rk = g_.rk[k];
+        const double wl = w / (rk * g_.sc[size_t(j) * n + i] * g_.hs);
+        for (int f = 0; f < 4; ++f) {
+            if (!on_edge(i, j, f)) { div_face(p, i, j, k, f, wl); continue; }
+            int q, iq, jq, fq;
+            partner(p, i, j, f, q, iq, jq, fq);
+            div_face(p, i, j, k, f, 0.5 * wl);
+            div_face(q, iq, jq, k, fq, -0.5 * wl);
+        }
+        const double wr = 0.5 * w / (rk * rk * g_.hr);
+        const double up = g_.rf[k + 1] * g_.rf[k + 1] * wr, dn = g_.rf[k] * g_.rf[k] * wr;
+        const double *nv = &g_.nrm[((size_t(p) * n + j) * n + i) * 3];
+        for (int d = 0; d < 3; ++d) {
+            value(p, i, j, k, d, up * nv[d]);
+            value(p, i, j, k + 1, d, up * nv[d]);
+            value(p, i, j, k - 1, d, -dn * nv[d]);
+            value(p, i, j, k, d, -dn * nv[d]);
+        }
+    }
+
+    void row(int p, int i, int j, int k, int c) {
+        const double dt = op_.dt, E = op_.ekman;
+        if (c == 3) {
+            divergence(p, i, j, k, 1.0);
+            laplacian(p, i, j, k, 3, -dt);
+            return;
+        }
+        value(p, i, j, k, c, 1.0);
+        if (op_.kind == CSDYN_VP) {
+            laplacian(p, i, j, k, c, -dt * E);
+            if (c == 0) value(p, i, j, k, 1, -2.0 * dt);
+            if (c == 1) value(p, i, j, k, 0, 2.0 * dt);
+        } else {
+            laplacian(p, i, j, k, c, -dt * E / op_.pm);
+        }
+    }
+
+   private:
+    const HostGeom &g_;
+    const csdyn_op &op_;
+    TermVec &out_;
+};
+
+struct LocalSd {
+    std::vector<int32_t> gcell, own;
+    std::vector<int64_t> rp;
+    std::vector<int32_t> ci;
+    std::vector<double> v;
+    std::vector<int64_t> diag;
+    std::vector<int32_t> levL, levU;  // per row
+    int nlevL = 0, nlevU = 0;
+    int32_t status = CSDYN_OK;
+};
+
+// Global cell reached from box position (p, i, j, k): the cell itself, the
+// neighbour panel's first-layer cell across an edge face, or -1 (beyond a
+// wall, or a cube-corner position).
+int64_t box_cell(const HostGeom &g, int p, int i, int j, int k) {
+    const int n = g.n;
+    if (k < 0 || k >= g.nr) return -1;
+    const bool iin = i >= 0 && i < n, jin = j >= 0 && j < n;
+    if (iin && jin) return g.cell(p, i, j, k);
+    if (!iin && !jin) return -1;
+    if (i < -1 || i > n || j < -1 || j > n) return -1;
+    const int f = !iin ? (i < 0 ? 0 : 1) : (j < 0 ? 2 : 3);
+    const FaceEntry &F = g.face[(p * 4 + f) * size_t(n) + (!iin ? j : i)];
+    int iq, jq;
+    switch (F.e) {
+        case 0: iq = 0; jq = F.t; break;
+        case 1: iq = n - 1; jq = F.t; break;
+        case 2: iq = F.t; jq = 0; break;
+        default: iq = F.t; jq = n - 1; break;
+    }
+    return g.cell(F.q, iq, jq, k);
+}
+
+void build_one(const HostGeom &g, const csdyn_op &op, const int sub[3], const int nb[3], int overlap, int s,
+               std::vector<int32_t> &g2l, LocalSd &L) {
+    const int bi = s % nb[0], bj = (s / nb[0]) % nb[1], bk = (s / (nb[0] * nb[1])) % nb[2];
+    const int p = s / (nb[0] * nb[1] * nb[2]);
+    const int d = overlap;
+    const int i0 = bi * sub[0], i1 = i0 + sub[0], j0 = bj * sub[1], j1 = j0 + sub[1];
+    const int k0 = bk * sub[2], k1 = k0 + sub[2];
+    for (int k = k0 - d; k < k1 + d; ++k)
+        for (int j = j0 - d; j < j1 + d; ++j)
+            for (int i = i0 - d; i < i1 + d; ++i) {
+                const int64_t c = box_cell(g, p, i, j, k);
+                if (c < 0) continue;
+                const bool owned = i >= i0 && i < i1 && j >= j0 && j < j1 && k >= k0 && k < k1;
+                g2l[c] = int32_t(L.gcell.size());
+                if (owned) L.own.push_back(int32_t(L.gcell.size()));
+                L.gcell.push_back(int32_t(c));
+            }
+    const int64_t nloc = int64_t(L.gcell.size()), nrow = 4 * nloc;
+    L.rp.assign(nrow + 1, 0);
+    TermVec terms;
+    std::vector<std::pair<int32_t, double>> loc;
+    for (int64_t l = 0; l < nloc; ++l) {
+        const int64_t gc = L.gcell[l];
+        const int ii = int(gc % g.n), jj = int((gc / g.n) % g.n), kk = int((gc / (int64_t(g.n) * g.n)) % g.nr);
+        const int pp = int(gc / (int64_t(g.n) * g.n * g.nr));
+        for (int c = 0; c < 4; ++c) {
+            terms.clear();
+            Expander ex(g, op, terms);
+            ex.row(pp, ii, jj, kk, c);
+            loc.clear();
+            for (auto &t : terms) {
+                const int32_t lc = g2l[t.first / 4];
+                if (lc >= 0) loc.emplace_back(4 * lc + int32_t(t.first % 4), t.second);
+            }
+            std::sort(loc.begin(), loc.end(), [](auto &a, auto &b) { return a.first < b.first; });
+            size_t m = 0;
+            for (size_t a = 0; a < loc.size(); ++a) {
+                if (m > 0 && loc[m - 1].first == loc[a].first) loc[m - 1].second += loc[a].second;
+                else loc[m++] = loc[a];
+            }
+            for (size_t a = 0; a < m; ++a) { L.ci.push_back(loc[a].first); L.v.push_back(loc[a].second); }
+            L.rp[4 * l + c + 1] = int64_t(L.ci.size());
+        }
+    }
+    for (int32_t c : L.gcell) g2l[c] = -1;
+
+    // ILU(0): for each row i, for each k < i in the row: l_ik = a_ik / u_kk,
+    // then a_ij -= l_ik u_kj for the j > k present in row i.
+    L.diag.assign(nrow, -1);
+    std::vector<int64_t> pos(nrow, -1);
+    for (int64_t r = 0; r < nrow; ++r) {
+        for (int64_t q = L.rp[r]; q < L.rp[r + 1]; ++q) {
+            pos[L.ci[q]] = q;
+            if (L.ci[q] == r) L.diag[r] = q;
+        }
+        if (L.diag[r] < 0) { L.status = CSDYN_EZEROPIVOT; return; }
+        for (int64_t q = L.rp[r]; q < L.diag[r]; ++q) {
+            const int64_t kr = L.ci[q];
+            const double lik = L.v[q] / L.v[L.diag[kr]];
+            L.v[q] = lik;
+            for (int64_t u = L.diag[kr] + 1; u < L.rp[kr + 1]; ++u) {
+                const int64_t at = pos[L.ci[u]];
+                if (at >= 0) L.v[at] -= lik * L.v[u];
+            }
+        }
+        for (int64_t q = L.rp[r]; q < L.rp[r + 1]; ++q) pos[L.ci[q]] = -1;
+        if (!(std::fabs(L.v[L.diag[r]]) >= 1e-300)) { L.status = CSDYN_EZEROPIVOT; return; }
+    }
+    // level schedules (longest path in the dependency DAG of each sweep)
+    L.levL.assign(nrow, 0);
+    L.levU.assign(nrow, 0);
+    for (int64_t r = 0; r < nrow; ++r) {
+        int lv = 0;
+        for (int64_t q = L.rp[r]; q < L.diag[r]; ++q) lv = std::max(lv, L.levL[L.ci[q]] + 1);
+        L.levL[r] = lv;
+        L.nlevL = std::max(L.nlevL, lv + 1);
+    }
+    for (int64_t r = nrow - 1; r >= 0; --r) {
+        int lv = 0;
+        for (int64_t q = L.diag[r] + 1; q < L.rp[r + 1]; ++q) lv = std::max(lv, L.levU[L.ci[q]] + 1);
+        L.levU[r] = lv;
+        L.nlevU = std::max(L.nlevU, lv + 1);
+    }
+}
+
+// Append one subdomain's factor (lower or upper part) to the slice pack.
+void pack_sweep(const LocalSd &L, bool upper, SweepPack &P, int32_t &lev0, int32_t &lev1) {
+    const int64_t nrow = int64_t(L.rp.size()) - 1;
+    const int nlev = upper ? L.nlevU : L.nlevL;
+    const std::vector<int32_t> &lev = upper ? L.levU : L.levL;
+    std::vector<std::vector<int32_t>> rows(nlev);
+    for (int64_t r = 0; r < nrow; ++r) rows[lev[r]].push_back(int32_t(r));
+    auto cnt = [&](int32_t r) -> int64_t {
+        return upper ? L.rp[r + 1] - L.diag[r] - 1 : L.diag[r] - L.rp[r];
+    };
+    lev0 = int32_t(P.lev_slice.size());
+    for (int lv = 0; lv < nlev; ++lv) {
+        auto &R = rows[lv];
+        std::stable_sort(R.begin(), R.end(), [&](int32_t a, int32_t b) { return cnt(a) > cnt(b); });
+        P.lev_slice.push_back(int32_t(P.sl_w.size()));
+        for (size_t s0 = 0; s0 < R.size(); s0 += 64) {
+            const size_t ns = std::min<size_t>(64, R.size() - s0);
+            int64_t w = 0;
+            for (size_t a = 0; a < ns; ++a) w = std::max(w, cnt(R[s0 + a]));
+            const int64_t off = int64_t(P.val.size());
+            P.sl_off.push_back(off);
+            P.sl_w.push_back(int32_t(w));
+            P.val.resize(off + w * 64, 0.0);
+            P.col.resize(off + w * 64, 0);
+            for (size_t a = 0; a < 64; ++a) {
+                const int32_t r = a < ns ? R[s0 + a] : -1;
+                P.sl_rows.push_back(r);
+                P.sl_diag.push_back(r >= 0 && upper ? L.v[L.diag[r]] : 0.0);
+                if (r < 0) continue;
+                const int64_t q0 = upper ? L.diag[r] + 1 : L.rp[r];
+                const int64_t nq = cnt(r);
+                for (int64_t q = 0; q < w; ++q) {
+                    const int64_t at = off + q * 64 + int64_t(a);
+                    if (q < nq) { P.val[at] = L.v[q0 + q]; P.col[at] = L.ci[q0 + q]; }
+                    else { P.val[at] = 0.0; P.col[at] = r; }  // padding reads the row's own entry
+                }
+            }
+        }
+    }
+    lev1 = int32_t(P.lev_slice.size());
+}
+
+}  // namespace
+
+int32_t host_subdomain(const HostGeom &g, const csdyn_op &op, const int sub[3], int overlap, int s,
+                       std::vector<int32_t> &gcell, std::vector<int32_t> &own, std::vector<int64_t> &rp,
+                       std::vector<int32_t> &ci, std::vector<double> &v) {
+    if (sub[0] < 1 || sub[1] < 1 || sub[2] < 1 || g.n % sub[0] || g.n % sub[1] || g.nr % sub[2] || overlap < 0 ||
+        overlap > 1) {
+        set_error("ras: bad subdomain size or overlap");
+        return CSDYN_EINVAL;
+    }
+    const int nb[3] = {g.n / sub[0], g.n / sub[1], g.nr / sub[2]};
+    if (s < 0 || s >= 6 * nb[0] * nb[1] * nb[2]) { set_error("ras: subdomain index out of range"); return CSDYN_EINVAL; }
+    std::vector<int32_t> g2l(6 * int64_t(g.n) * g.n * g.nr, -1);
+    LocalSd L;
+    build_one(g, op, sub, nb, overlap, s, g2l, L);
+    if (L.status != CSDYN_OK) { set_error("ras: zero pivot in subdomain %d", s); return L.status; }
+    gcell.swap(L.gcell); own.swap(L.own); rp.swap(L.rp); ci.swap(L.ci); v.swap(L.v);
+    return CSDYN_OK;
+}
+
+void stencil_row(const HostGeom &g, const csdyn_op &op, int p, int i, int j, int k, int c, TermVec &out) {
+    Expander ex(g, op, out);
+    ex.row(p, i, j, k, c);
+}
+
+int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], int overlap, HostRas &H) {
+    if (sub[0] < 1 || sub[1] < 1 || sub[2] < 1 || g.n % sub[0] || g.n % sub[1] || g.nr % sub[2]) {
+        set_error("ras: grid %dx%dx%d is not divisible by subdomain %dx%dx%d", g.n, g.n, g.nr, sub[0], sub[1], sub[2]);
+        return CSDYN_EINVAL;
+    }
+    if (overlap < 0 || overlap > 1) { set_error("ras: overlap must be 0 or 1"); return CSDYN_EINVAL; }
+    H = HostRas();
+    H.nb[0] = g.n / sub[0]; H.nb[1] = g.n / sub[1]; H.nb[2] = g.nr / sub[2];
+    H.nsd = 6 * H.nb[0] * H.nb[1] * H.nb[2];
+    std::vector<LocalSd> loc(H.nsd);
+    const int64_t ncell = 6 * int64_t(g.n) * g.n * g.nr;
+    int32_t status = CSDYN_OK;
+#pragma omp parallel
+    {
+        std::vector<int32_t> g2l(ncell, -1);
+#pragma omp for schedule(dynamic, 1)
+        for (int s = 0; s < H.nsd; ++s) build_one(g, op, sub, H.nb, overlap, s, g2l, loc[s]);
+    }
+    for (int s = 0; s < H.nsd; ++s)
+        if (loc[s].status != CSDYN_OK) {
+            status = loc[s].status;
+            set_error("ras: zero pivot in the ILU(0) factorization of subdomain %d", s);
+            return status;
+        }
+    H.sd.resize(H.nsd);
+    int64_t toff = 0;
+    for (int s = 0; s < H.nsd; ++s) {
+        LocalSd &L = loc[s];
+        SdInfo &I = H.sd[s];
+        I.cell_off = int64_t(H.gcell.size());
+        I.nloc = int32_t(L.gcell.size());
+        I.own_off = int32_t(H.own.size());
+        I.nown = int32_t(L.own.size());
+        I.t_off = toff;
+        toff += 4 * int64_t(L.gcell.size());
+        H.gcell.insert(H.gcell.end(), L.gcell.begin(), L.gcell.end());
+        H.own.insert(H.own.end(), L.own.begin(), L.own.end());
+        H.nnz += int64_t(L.ci.size());
+        pack_sweep(L, false, H.L, I.levL0, I.levL1);
+        pack_sweep(L, true, H.U, I.levU0, I.levU1);
+        H.max_levels = std::max(H.max_levels, L.nlevL + L.nlevU);
+        I.pad = 0;
+        LocalSd().gcell.swap(L.gcell);
+        std::vector<int64_t>().swap(L.rp);
+        std::vector<int32_t>().swap(L.ci);
+        std::vector<double>().swap(L.v);
+    }
+    H.L.lev_slice.push_back(int32_t(H.L.sl_w.size()));
+    H.U.lev_slice.push_back(int32_t(H.U.sl_w.size()));
+    H.tlen = toff;
+    return CSDYN_OK;
+}
+
+}  // namespace csd
