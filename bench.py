@@ -1,0 +1,198 @@
+#!/usr/bin/env python
+"""Benchmark: GMRES solves per second to relative residual 1e-8 on one MI355X.
+
+Workload (default, "large"): both systems of the approximate-factorization
+step -- velocity-pressure (E = 1e-3, dt = 1e-4) and magnetic / pseudo-
+pressure (Pm = 5) -- on the cubed-sphere shell with N = Nr = 96 (5,308,416
+cells, 21.2M unknowns per system), preconditioned by the hybrid two-level
+RAS (384 subdomains of 24^3 cells, overlap 1, ILU(0); coarse grid 48^3 x 6
+solved by GMRES(30) to 0.1 with a one-level RAS of 384 subdomains of 12^3),
+flexible GMRES(30) from x0 = 0 to relative residual 1e-8, FP64 throughout.
+Right-hand sides: seeded spherical-harmonic x Chebyshev fields plus noise
+(seeds 1 and 2), already resident in HBM when timing starts.
+
+One step = one velocity-pressure solve + one magnetic solve.  The timed
+region is bracketed by torch.cuda.synchronize(); every launch inside it is
+also timed with HIP events on its own stream (csdyn_profile_*), which gives
+each kernel's average duration and achieved algorithmic bandwidth.
+
+The CPU baseline is the plain C oracle (single thread), timed on a bounded
+sample: the same two solves with the same solver and subdomain count at
+N = Nr = 32, scaled by the cell-count ratio (27x) to N = 96.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GMRES solves/s to rel.res 1e-8 (plain FP64 vs mixed+learned); operator HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "large": dict(n=96, nr=96, sub=(24, 24, 24), levels=2, flexible=True,
+                  desc="VP+BP solves, N=Nr=96 (5.31M cells), two-level RAS 384x24^3 + coarse 48^3x6, FGMRES(30)"),
+    "small": dict(n=16, nr=16, sub=(16, 16, 16), levels=1, flexible=False,
+                  desc="VP+BP solves, N=Nr=16 (24,576 cells), one-level RAS 6x16^3, GMRES(30)"),
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wl_name: str, gpu_iters: dict):
+    """Oracle (plain C, one thread) on a bounded sample of the workload."""
+    import numpy as np  # noqa: F401
+    import oracle as O
+    from paper_2009_02171_amd import inputs
+    wl = WORKLOADS[wl_name]
+    if wl_name == "large":
+        n, sub = 32, (8, 8, 8)
+    else:
+        n, sub = wl["n"], wl["sub"]
+    scale = (wl["n"] / n) ** 2 * (wl["nr"] / n)
+    t_total, iters = 0.0, {}
+    for kind, seed in ((0, 1), (1, 2)):
+        pb = O.Problem(n, n, kind=kind)
+        pc = O.Preconditioner(pb, sub=sub, levels=wl["levels"])
+        b = inputs.rhs(n, n, seed)
+        t0 = time.perf_counter()
+        _, st, rc = O.gmres(pb, b, pc=pc, flexible=wl["flexible"], rtol=1e-8, maxit=2000)
+        t_total += time.perf_counter() - t0
+        iters["VP" if kind == 0 else "BP"] = [st["iters"], int(st["inner_iters"])]
+        log(f"oracle sample N={n} kind={kind}: {st['iters']} iters, {time.perf_counter() - t0:.2f} s")
+    est = t_total * scale
+    return {
+        "value": 2.0 / est, "unit": "solves/s", "cores": 1, "kind": "oracle",
+        "sample": (f"VP+BP solves at N=Nr={n} with the same solver and subdomain count "
+                   f"({t_total:.2f} s measured, one thread), scaled by the cell ratio {scale:.0f}x to "
+                   f"N=Nr={wl['n']}; oracle iterations [outer, inner] {iters}, GPU at full size {gpu_iters}"),
+        "cpu": _cpu_model(),
+    }
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip() + f" ({os.cpu_count()} logical cpus)"
+    except OSError:
+        pass
+    return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="large")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the solver is single-GPU)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2009_02171_amd import csdyn, inputs
+
+    wl = WORKLOADS[args.workload]
+    n, nr = wl["n"], wl["nr"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    systems = {"VP": dict(kind=csdyn.VP, seed=1), "BP": dict(kind=csdyn.BP, seed=2)}
+    state = {}
+    for name, s in systems.items():
+        t0 = time.perf_counter()
+        op = csdyn.Operator(n, nr, kind=s["kind"], dt=1e-4, ekman=1e-3, pm=5.0)
+        pc = csdyn.RAS(op, sub=wl["sub"], levels=wl["levels"], coarse_rtol=0.1, coarse_restart=30, coarse_maxit=200)
+        sol = csdyn.Solver(op, pc, restart=30, maxit=2000, flexible=wl["flexible"], rtol=1e-8)
+        b = torch.from_numpy(inputs.rhs(n, nr, s["seed"])).to(dev)
+        x = torch.zeros_like(b)
+        state[name] = dict(op=op, pc=pc, sol=sol, b=b, x=x, info=pc.info())
+        log(f"setup {name}: {time.perf_counter() - t0:.1f} s, info {state[name]['info']}")
+    torch.cuda.synchronize()
+
+    iters = {}
+
+    def step():
+        for name, s in state.items():
+            s["x"].zero_()
+            _, st, rc = s["sol"].solve(s["b"], s["x"])
+            if rc != 0 or not st["relres_true"] <= 1.0001e-8:
+                raise RuntimeError(f"{name} solve did not converge: rc={rc} {st}")
+            iters[name] = [st["iters"], st["inner_iters"], st["relres_true"]]
+
+    for w in range(args.warmup):
+        t0 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup step {w}: {time.perf_counter() - t0:.3f} s, iters {iters}")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with csdyn.Profile() as prof:
+        for k in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    log(f"timed {args.steps} steps in {elapsed:.3f} s, iters {iters}")
+
+    kernels = {}
+    for (name, size), e in sorted(prof.result.items(), key=lambda kv: -kv[1]["ms"]):
+        avg_ms = e["ms"] / max(e["count"], 1)
+        gbs = e["bytes"] / (e["ms"] * 1e-3) / 1e9 if e["ms"] > 0 else 0.0
+        kernels[f"{name}@{size}"] = dict(launches=e["count"], total_ms=round(e["ms"], 3), avg_us=round(avg_ms * 1e3, 2),
+                                         alg_GBs=round(gbs, 1), share=round(e["ms"] / (elapsed * 1e3), 4))
+    dom_name, dom = max(prof.result.items(), key=lambda kv: kv[1]["ms"])
+    dom_gbs = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
+    op_key = [k for k in prof.result if k[0] == "op_main" and k[1] == 6 * n * n * nr]
+    operator = None
+    if op_key:
+        e = prof.result[op_key[0]]
+        g = e["bytes"] / (e["ms"] * 1e-3) / 1e9
+        operator = dict(kernel="op_main", cells=6 * n * n * nr, avg_us=round(e["ms"] / e["count"] * 1e3, 2),
+                        achieved=round(g, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(g / HBM_PEAK_GBS, 4),
+                        bytes_per_cell=64)
+
+    out = {
+        "metric": METRIC,
+        "value": round(2 * args.steps / elapsed, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl["desc"], "n": n, "nr": nr, "systems": ["VP", "BP"], "subdomain": list(wl["sub"]),
+                   "levels": wl["levels"], "krylov": "FGMRES(30)" if wl["flexible"] else "GMRES(30)",
+                   "rtol": 1e-8, "form": "plain FP64"},
+        "iters": {k: {"outer": v[0], "inner": v[1], "relres": v[2]} for k, v in iters.items()},
+        "roofline": {"kernel": f"{dom_name[0]}@{dom_name[1]}", "bound": "hbm", "achieved": round(dom_gbs, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4),
+                     "traffic": None,
+                     "avg_us": round(dom["ms"] / dom["count"] * 1e3, 2),
+                     "alg_bytes_per_launch": round(dom["bytes"] / dom["count"])},
+        "operator": operator,
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.workload, {k: v[:2] for k, v in iters.items()})
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -174,6 +174,40 @@ int32_t csdyn_gmres_workspace_bytes(const csdyn_opctx *ctx, const csdyn_gmres_op
 int32_t csdyn_gmres_solve(const csdyn_opctx *ctx, const csdyn_ras *pc, const csdyn_gmres_opts *o, const double *b,
                           double *x, void *ws, size_t ws_bytes, void *stream, csdyn_gmres_stats *st);
 
+/* Size summary of a preconditioner (for bandwidth accounting).  Entries are
+ * ILU(0) factor entries (L and U, diagonal included) before padding. */
+typedef struct {
+    int32_t nsd_fine, nsd_coarse;
+    int64_t nnz_fine, nnz_coarse;             /* factor entries */
+    int64_t box_cells_fine, box_cells_coarse; /* cells of all overlapping boxes */
+    int64_t owned_cells_fine, owned_cells_coarse;
+    int64_t stored_fine, stored_coarse;       /* stored entries incl. slice padding */
+    int32_t max_levels_fine, max_levels_coarse; /* L + U sweep levels of the deepest subdomain */
+    int32_t precision;
+} csdyn_ras_info;
+int32_t csdyn_ras_get_info(const csdyn_ras *pc, csdyn_ras_info *info);
+
+/* ----------------------------------------------------------------- profile
+ * Optional timing of every kernel launch by HIP events recorded on the launch
+ * stream.  begin() creates a pool of max_launches event pairs; until end(),
+ * each launch records a pair (launches beyond the pool are not timed).
+ * end() waits for the recorded events and returns, per kernel name and
+ * problem size (cells for the operator, subdomains for RAS, vector length for
+ * the Krylov kernels), the launch count, the summed duration and the summed
+ * algorithmic bytes (the HBM traffic the launches must cause: operands read
+ * once and results written once, no cache effects, no index or padding
+ * bytes).  Not thread-safe with concurrent
+ * solves on other threads. */
+typedef struct {
+    char name[32];
+    int64_t size;
+    int64_t count;
+    double total_ms;
+    double bytes;
+} csdyn_profile_entry;
+int32_t csdyn_profile_begin(int32_t max_launches);
+int32_t csdyn_profile_end(csdyn_profile_entry *out, int32_t max_entries, int32_t *n_entries);
+
 /* Thread-local text of the last error on this thread ("" if none). */
 const char *csdyn_last_error(void);
 

@@ -45,6 +45,19 @@ class GmresStats(C.Structure):
                 ("relres_true", C.c_double), ("relres_est", C.c_double), ("t_ms", C.c_double * 8)]
 
 
+class RasInfo(C.Structure):
+    _fields_ = [("nsd_fine", C.c_int32), ("nsd_coarse", C.c_int32), ("nnz_fine", C.c_int64),
+                ("nnz_coarse", C.c_int64), ("box_cells_fine", C.c_int64), ("box_cells_coarse", C.c_int64),
+                ("owned_cells_fine", C.c_int64), ("owned_cells_coarse", C.c_int64), ("stored_fine", C.c_int64),
+                ("stored_coarse", C.c_int64), ("max_levels_fine", C.c_int32), ("max_levels_coarse", C.c_int32),
+                ("precision", C.c_int32)]
+
+
+class ProfileEntry(C.Structure):
+    _fields_ = [("name", C.c_char * 32), ("size", C.c_int64), ("count", C.c_int64), ("total_ms", C.c_double),
+                ("bytes", C.c_double)]
+
+
 # Exported symbols and their signatures, as declared in include/csdyn.h.
 _P = C.POINTER
 SIGNATURES = {
@@ -62,6 +75,9 @@ SIGNATURES = {
     "csdyn_gmres_workspace_bytes": (C.c_int32, [C.c_void_p, _P(GmresOpts), _P(C.c_size_t)]),
     "csdyn_gmres_solve": (C.c_int32, [C.c_void_p, C.c_void_p, _P(GmresOpts), C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_size_t, C.c_void_p, _P(GmresStats)]),
+    "csdyn_ras_get_info": (C.c_int32, [C.c_void_p, _P(RasInfo)]),
+    "csdyn_profile_begin": (C.c_int32, [C.c_int32]),
+    "csdyn_profile_end": (C.c_int32, [_P(ProfileEntry), C.c_int32, _P(C.c_int32)]),
     "csdyn_last_error": (C.c_char_p, []),
 }
 
@@ -167,6 +183,11 @@ class RAS:
         _check(lib().csdyn_ras_apply(self.h, _ptr(x), _ptr(y), _stream(stream)), "csdyn_ras_apply")
         return y
 
+    def info(self):
+        inf = RasInfo()
+        _check(lib().csdyn_ras_get_info(self.h, C.byref(inf)), "csdyn_ras_get_info")
+        return {k: getattr(inf, k) for k, _ in RasInfo._fields_}
+
     def __del__(self):
         h = getattr(self, "h", None)
         if h and _lib is not None:
@@ -221,3 +242,25 @@ class Solver:
         stats = dict(iters=st.iters, restarts=st.restarts, inner_iters=st.inner_iters, relres_true=st.relres_true,
                      relres_est=st.relres_est, t_ms=list(st.t_ms))
         return x, stats, rc
+
+
+class Profile:
+    """Context manager around csdyn_profile_begin/end: per-kernel launch counts
+    and summed HIP-event durations, recorded on the launch streams."""
+
+    def __init__(self, max_launches=200000):
+        self.max_launches = max_launches
+        self.result = {}
+
+    def __enter__(self):
+        _check(lib().csdyn_profile_begin(self.max_launches), "csdyn_profile_begin")
+        return self
+
+    def __exit__(self, *exc):
+        buf = (ProfileEntry * 64)()
+        n = C.c_int32()
+        _check(lib().csdyn_profile_end(buf, 64, C.byref(n)), "csdyn_profile_end")
+        self.result = {(buf[i].name.decode(), buf[i].size): dict(count=buf[i].count, ms=buf[i].total_ms,
+                                                                  bytes=buf[i].bytes)
+                       for i in range(min(n.value, 64))}
+        return False

@@ -10,6 +10,7 @@
 #include <cmath>
 
 #include "krylov.h"
+#include "profile.h"
 
 namespace csd {
 
@@ -182,6 +183,7 @@ static dim3 ew_grid(int64_t n) {
 template <class T>
 int32_t Vec<T>::mdot(const T *V, int64_t n, int cnt, const T *w, T *partial, T *out, hipStream_t s) {
     const int nb = nblocks(n);
+    ProfScope ps(sizeof(T) == 8 ? "mdot" : "mdot_f32", n, double(cnt + 1) * n * sizeof(T), s);
     hipLaunchKernelGGL(k_mdot<T>, dim3(nb), dim3(kBlk), 0, s, V, n, cnt, w, partial);
     hipLaunchKernelGGL(k_reduce<T>, dim3(1), dim3(kRedStride * 8 + 8), 0, s, partial, nb, out);
     CSD_LAUNCHED();
@@ -191,6 +193,7 @@ int32_t Vec<T>::mdot(const T *V, int64_t n, int cnt, const T *w, T *partial, T *
 template <class T>
 int32_t Vec<T>::mupdate(T *w, const T *V, int64_t n, int cnt, const T *h, T *partial, T *out, hipStream_t s) {
     const int nb = nblocks(n);
+    ProfScope ps(sizeof(T) == 8 ? "mupdate" : "mupdate_f32", n, double(cnt + 2) * n * sizeof(T), s);
     hipLaunchKernelGGL(k_mupdate<T>, dim3(nb), dim3(kBlk), 0, s, w, V, n, cnt, h, partial);
     hipLaunchKernelGGL(k_reduce<T>, dim3(1), dim3(kRedStride * 8 + 8), 0, s, partial, nb, out);
     CSD_LAUNCHED();
@@ -215,6 +218,7 @@ template <class T>
 int32_t Vec<T>::lincomb(T *x, const T *Z, int64_t n, int cnt, const double *c, hipStream_t s) {
     Coefs cf{};
     for (int q = 0; q < cnt && q < kMaxRestart; ++q) cf.c[q] = c[q];
+    ProfScope ps("lincomb", n, double(cnt + 2) * n * sizeof(T), s);
     hipLaunchKernelGGL(k_lincomb<T>, ew_grid(n), dim3(256), 0, s, x, Z, n, cnt, cf);
     CSD_LAUNCHED();
     return CSDYN_OK;

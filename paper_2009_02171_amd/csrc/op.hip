@@ -15,6 +15,7 @@
 #include <algorithm>
 
 #include "common.h"
+#include "profile.h"
 
 namespace csd {
 
@@ -287,8 +288,15 @@ static int32_t launch_all(const csdyn_opctx *ctx, const T *x, T *y, T *G, T *SF,
     rc.c_lap = ctx->op.kind == CSDYN_VP ? ctx->op.dt * ctx->op.ekman : ctx->op.dt * ctx->op.ekman / ctx->op.pm;
     rc.c_cor = ctx->op.kind == CSDYN_VP ? 2.0 * ctx->op.dt : 0.0;
     const dim3 eb(64), eg((n + 63) / 64, nr, 24);
-    hipLaunchKernelGGL(k_ghost<T>, eg, eb, 0, s, g, x, G);
-    hipLaunchKernelGGL(k_edgeflux<T>, eg, eb, 0, s, g, x, (const T *)G, SF);
+    {
+        // ghost: 4 neighbour cells read, 1 written; edge flux: 12 cells read, 5 values written
+        const double eb_bytes = 24.0 * n * nr * sizeof(T) * (4 * 4 + 4 + 12 * 4 + 5);
+        ProfScope ps(sizeof(T) == 8 ? "op_edges" : "op_edges_f32", 6 * int64_t(n) * n * nr, eb_bytes, s);
+        hipLaunchKernelGGL(k_ghost<T>, eg, eb, 0, s, g, x, G);
+        hipLaunchKernelGGL(k_edgeflux<T>, eg, eb, 0, s, g, x, (const T *)G, SF);
+    }
+    ProfScope ps(sizeof(T) == 8 ? "op_main" : "op_main_f32", 6 * int64_t(n) * n * nr,
+                 6.0 * n * n * nr * 8 * sizeof(T), s);  // x read once, y written once
     if (n >= 32) {
         constexpr int TX = 32, TY = 8;
         const int tiles = ((n + TX - 1) / TX) * ((n + TY - 1) / TY);

@@ -14,6 +14,7 @@
 #include <mutex>
 
 #include "krylov.h"
+#include "profile.h"
 #include "ras_host.h"
 
 namespace csd {
@@ -122,7 +123,7 @@ static dim3 grid_for(int64_t n) { return dim3(unsigned(std::max<int64_t>(1, std:
 // One level of RAS data on the device (factors in TF).
 struct OneLevel {
     int nsd = 0;
-    int64_t tlen = 0, nnz = 0;
+    int64_t tlen = 0, nnz = 0, nown = 0;
     int max_levels = 0;
     SdInfo *sd = nullptr;
     int32_t *gcell = nullptr, *own = nullptr;
@@ -136,7 +137,7 @@ struct OneLevel {
 
     static void layout(Carver &c, const HostRas &H, int precision, OneLevel &o) {
         const size_t fs = precision ? sizeof(float) : sizeof(double);
-        o.nsd = H.nsd; o.tlen = H.tlen; o.nnz = H.nnz; o.precision = precision; o.max_levels = H.max_levels;
+        o.nsd = H.nsd; o.tlen = H.tlen; o.nnz = H.nnz; o.nown = int64_t(H.own.size()); o.precision = precision; o.max_levels = H.max_levels;
         o.sd = c.take<SdInfo>(H.sd.size());
         o.gcell = c.take<int32_t>(H.gcell.size());
         o.own = c.take<int32_t>(H.own.size());
@@ -195,6 +196,9 @@ struct OneLevel {
 
     template <class TV>
     int32_t apply(const TV *x, TV *y, hipStream_t s) const {
+        // factor values once, x gathered on the boxes, y written on the owned cells
+        const double bytes = double(nnz) * (precision ? 4 : 8) + double(tlen + 4 * nown) * sizeof(TV);
+        ProfScope ps(precision ? "ras_f32" : "ras", tlen / 4, bytes, s);
         if (precision) hipLaunchKernelGGL((k_ras<TV, float>), dim3(nsd), dim3(kRasBlk), 0, s, dev<float>(), x, y);
         else hipLaunchKernelGGL((k_ras<TV, double>), dim3(nsd), dim3(kRasBlk), 0, s, dev<double>(), x, y);
         CSD_HIP(hipGetLastError());
@@ -268,6 +272,7 @@ struct csdyn_ras {
     int64_t nf = 0, nc = 0;
     mutable int64_t inner_iters = 0;
     double vol_c = 0;           // total coarse volume
+    csdyn_ras_info info{};
 
     template <class T>
     int32_t two_level(const T *x, T *y, hipStream_t s) const;
@@ -325,6 +330,17 @@ extern "C" int32_t csdyn_ras_setup(const csdyn_opctx *ctx, const csdyn_ras_opts 
     Carver c(ws);
     layout_all(c, *b, *R);
     if (c.off + 256 > ws_bytes) { set_error("ras: workspace %zu < %zu bytes", ws_bytes, c.off + 256); return CSDYN_ENOMEM; }
+    R->info = csdyn_ras_info{};
+    auto fill = [](const HostRas &H, int32_t &nsd, int64_t &nnz, int64_t &box, int64_t &own, int64_t &stored, int32_t &lv) {
+        nsd = H.nsd; nnz = H.nnz; box = int64_t(H.gcell.size()); own = int64_t(H.own.size());
+        stored = int64_t(H.L.val.size() + H.U.val.size() + H.U.sl_diag.size()); lv = H.max_levels;
+    };
+    fill(b->fine, R->info.nsd_fine, R->info.nnz_fine, R->info.box_cells_fine, R->info.owned_cells_fine,
+         R->info.stored_fine, R->info.max_levels_fine);
+    if (o->levels == 2)
+        fill(b->coarse, R->info.nsd_coarse, R->info.nnz_coarse, R->info.box_cells_coarse, R->info.owned_cells_coarse,
+             R->info.stored_coarse, R->info.max_levels_coarse);
+    R->info.precision = o->precision;
     CSD_TRY(R->fine.upload(b->fine));
     if (o->levels == 2) {
         R->coarse_ctx.g = ctx->g;
@@ -352,8 +368,11 @@ int32_t csdyn_ras::two_level(const T *x, T *y, hipStream_t s) const {
     T *rc = b0 + 4 * nf, *ec = rc + nc;
     T *G32 = ec + nc, *SF32 = G32 + size_t(24) * fine_ctx->g.nr * fine_ctx->g.n * 4;
     // r_c = I_f^c x
-    hipLaunchKernelGGL(k_restrict<T>, grid_for(nc), dim3(256), 0, s, x, rc, nc_, nrc);
-    CSD_HIP(hipGetLastError());
+    {
+        ProfScope ps("restrict", nc, double(nf + nc) * sizeof(T), s);
+        hipLaunchKernelGGL(k_restrict<T>, grid_for(nc), dim3(256), 0, s, x, rc, nc_, nrc);
+        CSD_HIP(hipGetLastError());
+    }
     if (fine_ctx->op.kind == CSDYN_VP) {  // coarse Neumann solvability: zero volume-weighted mean of P
         Gmres<T> gm;
         Carver cc(cws);
@@ -380,8 +399,11 @@ int32_t csdyn_ras::two_level(const T *x, T *y, hipStream_t s) const {
     if (rcode < 0) return rcode;
     inner_iters += gr.iters;
     // w = I_c^f e_c ; t = x - A_f w ; y = w + M_one^{-1} t
-    hipLaunchKernelGGL(k_prolong<T>, grid_for(nf), dim3(256), 0, s, ec, w, nc_, nrc);
-    CSD_HIP(hipGetLastError());
+    {
+        ProfScope ps("prolong", nf, double(nf + nc) * sizeof(T), s);
+        hipLaunchKernelGGL(k_prolong<T>, grid_for(nf), dim3(256), 0, s, ec, w, nc_, nrc);
+        CSD_HIP(hipGetLastError());
+    }
     if constexpr (sizeof(T) == 8) CSD_TRY(op_launch(fine_ctx, w, t, s));
     else CSD_TRY(op_launch_f32(fine_ctx, w, t, G32, SF32, s));
     CSD_TRY(Vec<T>::axpby(1.0, x, -1.0, t, nf, s));
@@ -418,6 +440,13 @@ extern "C" int32_t csdyn_ras_apply(const csdyn_ras *pc, const double *x, double 
 }
 
 extern "C" void csdyn_ras_destroy(csdyn_ras *pc) { delete pc; }
+
+extern "C" int32_t csdyn_ras_get_info(const csdyn_ras *pc, csdyn_ras_info *info) {
+    clear_error();
+    if (!pc || !info) { set_error("ras_get_info: null argument"); return CSDYN_EINVAL; }
+    *info = pc->info;
+    return CSDYN_OK;
+}
 
 extern "C" int32_t csdyn_ras_inspect(const csdyn_grid *g, const csdyn_op *op, const int32_t sub[3], int32_t overlap,
                                      int32_t s, int64_t *nloc, int64_t *nnz, int32_t *gcell, int32_t *owned,
