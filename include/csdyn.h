@@ -146,9 +146,12 @@ int32_t csdyn_ras_inspect(const csdyn_grid *g, const csdyn_op *op, const int32_t
 /* ------------------------------------------------------------------- GMRES
  * Right-preconditioned restarted GMRES(restart) (Sec. 3.3); flexible = 1 is
  * FGMRES, required when M^{-1} contains an inner Krylov solve or FP32
- * arithmetic.  Orthogonalisation: classical Gram-Schmidt with one
- * re-orthogonalisation pass when the norm drops below 1/sqrt(2) of its value
- * (same Krylov space as modified Gram-Schmidt).  Stops when the residual
+ * arithmetic.  Orthogonalisation (same Krylov space as modified Gram-Schmidt):
+ * orth = 0, classical Gram-Schmidt, one pass for the projections and one for
+ * the update and norm (PETSc's default GMRES orthogonalisation); orth = 1,
+ * classical Gram-Schmidt with one re-orthogonalisation, whose projections are
+ * fused into the first update pass (three passes).  The coarse solve inside
+ * the two-level preconditioner always uses orth = 0.  Stops when the residual
  * estimate <= max(atol, rtol * ||b - A x0||); then recomputes the true
  * residual.  For VP, b's pressure part is first projected to zero
  * volume-weighted mean and the solution's pressure is returned with zero
@@ -160,6 +163,7 @@ typedef struct {
     int32_t maxit;     /* total Arnoldi steps */
     int32_t flexible;  /* 0 GMRES, 1 FGMRES */
     double rtol, atol;
+    int32_t orth;      /* 0 CGS, 1 CGS2 */
 } csdyn_gmres_opts;
 
 typedef struct {
@@ -184,6 +188,8 @@ typedef struct {
     int64_t stored_fine, stored_coarse;       /* stored entries incl. slice padding */
     int32_t max_levels_fine, max_levels_coarse; /* L + U sweep levels of the deepest subdomain */
     int32_t precision;
+    int32_t lds_fine, lds_coarse;             /* dynamic LDS bytes per workgroup of the sweep kernel */
+    int32_t box_in_lds_fine, box_in_lds_coarse; /* 1: the box vector is held in LDS */
 } csdyn_ras_info;
 int32_t csdyn_ras_get_info(const csdyn_ras *pc, csdyn_ras_info *info);
 

@@ -37,7 +37,7 @@ class RasOpts(C.Structure):
 
 class GmresOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("maxit", C.c_int32), ("flexible", C.c_int32),
-                ("rtol", C.c_double), ("atol", C.c_double)]
+                ("rtol", C.c_double), ("atol", C.c_double), ("orth", C.c_int32)]
 
 
 class GmresStats(C.Structure):
@@ -50,7 +50,8 @@ class RasInfo(C.Structure):
                 ("nnz_coarse", C.c_int64), ("box_cells_fine", C.c_int64), ("box_cells_coarse", C.c_int64),
                 ("owned_cells_fine", C.c_int64), ("owned_cells_coarse", C.c_int64), ("stored_fine", C.c_int64),
                 ("stored_coarse", C.c_int64), ("max_levels_fine", C.c_int32), ("max_levels_coarse", C.c_int32),
-                ("precision", C.c_int32)]
+                ("precision", C.c_int32), ("lds_fine", C.c_int32), ("lds_coarse", C.c_int32),
+                ("box_in_lds_fine", C.c_int32), ("box_in_lds_coarse", C.c_int32)]
 
 
 class ProfileEntry(C.Structure):
@@ -223,9 +224,9 @@ class Solver:
     """Restarted (F)GMRES with a workspace kept across solves (csdyn_gmres_solve)."""
 
     def __init__(self, op: Operator, pc: RAS | None = None, restart=30, maxit=1000, flexible=False, rtol=1e-8,
-                 atol=0.0):
+                 atol=0.0, orth=0):
         self.op, self.pc = op, pc
-        self.opts = GmresOpts(restart, maxit, int(flexible), rtol, atol)
+        self.opts = GmresOpts(restart, maxit, int(flexible), rtol, atol, orth)
         nb = C.c_size_t()
         _check(lib().csdyn_gmres_workspace_bytes(op.h, C.byref(self.opts), C.byref(nb)),
                "csdyn_gmres_workspace_bytes")

@@ -24,6 +24,8 @@ struct Vec {
     static int32_t mdot(const T *V, int64_t n, int cnt, const T *w, T *partial, T *out, hipStream_t s);
     // w -= sum_q h[q] V_q (h on device), then out[32] = w . w
     static int32_t mupdate(T *w, const T *V, int64_t n, int cnt, const T *h, T *partial, T *out, hipStream_t s);
+    // w -= sum_q h[q] V_q; out[q] = V_q . w_new (q < cnt), out[32] = ||w_new||^2
+    static int32_t mupdate_dot(T *w, const T *V, int64_t n, int cnt, const T *h, T *partial, T *out, hipStream_t s);
     static int32_t scale(T *w, int64_t n, double a, hipStream_t s);
     // y = a*x + b*y
     static int32_t axpby(double a, const T *x, double b, T *y, int64_t n, hipStream_t s);
@@ -50,6 +52,7 @@ struct Gmres {
     int64_t n = 0;
     int m = 30;
     bool flexible = false;
+    int orth = 0;  // 0: classical Gram-Schmidt, 1: with one re-orthogonalisation pass
     T *V = nullptr, *Z = nullptr, *z = nullptr, *r = nullptr, *tmp = nullptr, *partial = nullptr, *red = nullptr;
     T *hred = nullptr;  // pinned-free host mirror is a std::vector below
 

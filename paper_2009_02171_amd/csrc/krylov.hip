@@ -29,7 +29,8 @@ int Vec<T>::nblocks(int64_t n) {
     return int(std::max<int64_t>(1, std::min<int64_t>(kMaxBlocks, b)));
 }
 
-// Block partial sums of NV accumulators written to partial[block][q].
+// Block sums of the kRedStride accumulators (wavefront shuffles, then the
+// waves in order), written to partial[q][block] (q-major).
 template <class T>
 __device__ __forceinline__ void block_store(T (&acc)[kRedStride], int cnt_total, T *partial) {
     __shared__ T sm[kBlk / 64][kRedStride];
@@ -45,7 +46,7 @@ __device__ __forceinline__ void block_store(T (&acc)[kRedStride], int cnt_total,
     if (threadIdx.x < kRedStride) {
         T s = 0;
         for (int w = 0; w < kBlk / 64; ++w) s += sm[w][threadIdx.x];
-        partial[blockIdx.x * kRedStride + threadIdx.x] = s;
+        partial[size_t(threadIdx.x) * kMaxBlocks + blockIdx.x] = s;
     }
 }
 
@@ -85,24 +86,6 @@ __global__ __launch_bounds__(kBlk) void k_mupdate(T *__restrict__ w, const T *__
         acc[kRedStride - 1] += wv * wv;
     }
     block_store(acc, 0, partial);
-}
-
-// out[q] = sum over blocks of partial[b][q], fixed order, q < 33.
-template <class T>
-__global__ void k_reduce(const T *__restrict__ partial, int nb, T *__restrict__ out) {
-    __shared__ T sm[kRedStride][8];
-    const int g = threadIdx.x / 8, l = threadIdx.x % 8;
-    if (g < kRedStride) {
-        T s = 0;
-        for (int b = l; b < nb; b += 8) s += partial[b * kRedStride + g];
-        sm[g][l] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x < kRedStride) {
-        T s = 0;
-        for (int a = 0; a < 8; ++a) s += sm[threadIdx.x][a];
-        out[threadIdx.x] = s;
-    }
 }
 
 template <class T>
@@ -174,6 +157,61 @@ __global__ void k_f2d(const float *x, double *y, int64_t n) {
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) y[i] = double(x[i]);
 }
 
+// w -= sum_q h[q] V_q, and in the same pass h2[q] = V_q . w_new (the
+// re-orthogonalisation dot products of classical Gram-Schmidt, second pass).
+template <class T>
+__global__ __launch_bounds__(kBlk) void k_mupdate_dot(T *__restrict__ w, const T *__restrict__ V, int64_t n, int cnt,
+                                                      const T *__restrict__ h, T *__restrict__ partial) {
+    T hq[kRedStride - 1];
+#pragma unroll
+    for (int q = 0; q < kRedStride - 1; ++q) hq[q] = q < cnt ? h[q] : T(0);
+    T acc[kRedStride];
+#pragma unroll
+    for (int q = 0; q < kRedStride; ++q) acc[q] = 0;
+    const int64_t stride = int64_t(gridDim.x) * kBlk;
+    for (int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x; i < n; i += stride) {
+        T vq[kRedStride - 1];
+        T wv = w[i];
+#pragma unroll
+        for (int q = 0; q < kRedStride - 1; ++q) {
+            vq[q] = q < cnt ? V[int64_t(q) * n + i] : T(0);
+            wv -= hq[q] * vq[q];
+        }
+        w[i] = wv;
+#pragma unroll
+        for (int q = 0; q < kRedStride - 1; ++q) acc[q] += vq[q] * wv;
+        acc[kRedStride - 1] += wv * wv;
+    }
+    block_store(acc, cnt, partial);
+}
+
+// out[q] = sum over blocks b < nb of partial[q][b] for q < cnt and q = 32, in a
+// fixed order (one thread per block index, then the block reduction).
+template <class T>
+__global__ __launch_bounds__(1024) void k_reduce(const T *__restrict__ partial, int nb, int cnt, T *__restrict__ out) {
+    __shared__ T sm[1024 / 64][kRedStride];
+    T acc[kRedStride];
+#pragma unroll
+    for (int q = 0; q < kRedStride; ++q) {
+        acc[q] = 0;
+        if ((q < cnt || q == kRedStride - 1) && int(threadIdx.x) < nb) acc[q] = partial[size_t(q) * kMaxBlocks + threadIdx.x];
+    }
+    const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+#pragma unroll
+    for (int q = 0; q < kRedStride; ++q) {
+        if (q < cnt || q == kRedStride - 1) {
+            const T v = wave_sum(acc[q]);
+            if (lane == 0) sm[wv][q] = v;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < kRedStride && (int(threadIdx.x) < cnt || threadIdx.x == kRedStride - 1)) {
+        T s = 0;
+        for (int w = 0; w < 1024 / 64; ++w) s += sm[w][threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
 static dim3 ew_grid(int64_t n) {
     return dim3(unsigned(std::max<int64_t>(1, std::min<int64_t>(4096, (n + 255) / 256))));
 }
@@ -185,7 +223,7 @@ int32_t Vec<T>::mdot(const T *V, int64_t n, int cnt, const T *w, T *partial, T *
     const int nb = nblocks(n);
     ProfScope ps(sizeof(T) == 8 ? "mdot" : "mdot_f32", n, double(cnt + 1) * n * sizeof(T), s);
     hipLaunchKernelGGL(k_mdot<T>, dim3(nb), dim3(kBlk), 0, s, V, n, cnt, w, partial);
-    hipLaunchKernelGGL(k_reduce<T>, dim3(1), dim3(kRedStride * 8 + 8), 0, s, partial, nb, out);
+    hipLaunchKernelGGL(k_reduce<T>, dim3(1), dim3(1024), 0, s, partial, nb, cnt, out);
     CSD_LAUNCHED();
     return CSDYN_OK;
 }
@@ -195,7 +233,17 @@ int32_t Vec<T>::mupdate(T *w, const T *V, int64_t n, int cnt, const T *h, T *par
     const int nb = nblocks(n);
     ProfScope ps(sizeof(T) == 8 ? "mupdate" : "mupdate_f32", n, double(cnt + 2) * n * sizeof(T), s);
     hipLaunchKernelGGL(k_mupdate<T>, dim3(nb), dim3(kBlk), 0, s, w, V, n, cnt, h, partial);
-    hipLaunchKernelGGL(k_reduce<T>, dim3(1), dim3(kRedStride * 8 + 8), 0, s, partial, nb, out);
+    hipLaunchKernelGGL(k_reduce<T>, dim3(1), dim3(1024), 0, s, partial, nb, 0, out);
+    CSD_LAUNCHED();
+    return CSDYN_OK;
+}
+
+template <class T>
+int32_t Vec<T>::mupdate_dot(T *w, const T *V, int64_t n, int cnt, const T *h, T *partial, T *out, hipStream_t s) {
+    const int nb = nblocks(n);
+    ProfScope ps(sizeof(T) == 8 ? "mupdate_dot" : "mupdate_dot_f32", n, double(cnt + 2) * n * sizeof(T), s);
+    hipLaunchKernelGGL(k_mupdate_dot<T>, dim3(nb), dim3(kBlk), 0, s, w, V, n, cnt, h, partial);
+    hipLaunchKernelGGL(k_reduce<T>, dim3(1), dim3(1024), 0, s, partial, nb, cnt, out);
     CSD_LAUNCHED();
     return CSDYN_OK;
 }
@@ -242,7 +290,7 @@ template <class T>
 int32_t Vec<T>::pmoments(const T *x, const double *vol, int64_t ncell, T *partial, T *out, hipStream_t s) {
     const int nb = nblocks(ncell);
     hipLaunchKernelGGL(k_pmoments<T>, dim3(nb), dim3(kBlk), 0, s, x, vol, ncell, partial);
-    hipLaunchKernelGGL(k_reduce<T>, dim3(1), dim3(kRedStride * 8 + 8), 0, s, partial, nb, out);
+    hipLaunchKernelGGL(k_reduce<T>, dim3(1), dim3(1024), 0, s, partial, nb, 2, out);
     CSD_LAUNCHED();
     return CSDYN_OK;
 }
@@ -287,7 +335,7 @@ void Gmres<T>::carve(Carver &c, int64_t n_, int m_, bool flexible_) {
     r = c.take<T>(n);
     tmp = c.take<T>(n);
     partial = c.take<T>(size_t(kMaxBlocks) * kRedStride);
-    red = c.take<T>(2 * kRedStride);
+    red = c.take<T>(3 * kRedStride);
 }
 
 template <class T>
@@ -341,23 +389,26 @@ int32_t Gmres<T>::solve(const DevFn<T> &A, const DevFn<T> *M, const T *b, T *x, 
             if (M) CSD_TRY((*M)(vj, zj, s));
             else CSD_TRY(Vec<T>::copy(zj, vj, n, s));
             CSD_TRY(A(zj, w, s));
-            // classical Gram-Schmidt, two bandwidth passes
-            CSD_TRY(Vec<T>::mdot(V, n, j + 1, w, partial, red, s));
-            CSD_TRY(Vec<T>::mupdate(w, V, n, j + 1, red, partial, red + kRedStride, s));
+            // classical Gram-Schmidt: h = V^T w, then w -= V h with ||w||^2 in the same
+            // pass; CGS2 re-orthogonalises once, the second dot fused into the update
             std::vector<T> h1(2 * kRedStride);
-            CSD_HIP(hipMemcpyAsync(h1.data(), red, sizeof(T) * 2 * kRedStride, hipMemcpyDeviceToHost, s));
-            CSD_HIP(hipStreamSynchronize(s));
-            const double ww = double(h1[kRedStride - 1]);
-            double nn = double(h1[2 * kRedStride - 1]);
-            for (int i = 0; i <= j; ++i) H[size_t(i) * m + j] = double(h1[i]);
-            if (!(nn > 0.5 * ww)) {  // lost more than half the norm: re-orthogonalise once
-                CSD_TRY(Vec<T>::mdot(V, n, j + 1, w, partial, red, s));
+            CSD_TRY(Vec<T>::mdot(V, n, j + 1, w, partial, red, s));
+            double ww, nn;
+            if (orth == 0) {
                 CSD_TRY(Vec<T>::mupdate(w, V, n, j + 1, red, partial, red + kRedStride, s));
                 CSD_HIP(hipMemcpyAsync(h1.data(), red, sizeof(T) * 2 * kRedStride, hipMemcpyDeviceToHost, s));
                 CSD_HIP(hipStreamSynchronize(s));
-                for (int i = 0; i <= j; ++i) H[size_t(i) * m + j] += double(h1[i]);
-                nn = double(h1[2 * kRedStride - 1]);
+                for (int i = 0; i <= j; ++i) H[size_t(i) * m + j] = double(h1[i]);
+            } else {
+                CSD_TRY(Vec<T>::mupdate_dot(w, V, n, j + 1, red, partial, red + kRedStride, s));
+                CSD_TRY(Vec<T>::mupdate(w, V, n, j + 1, red + kRedStride, partial, red + 2 * kRedStride, s));
+                h1.resize(3 * kRedStride);
+                CSD_HIP(hipMemcpyAsync(h1.data(), red, sizeof(T) * 3 * kRedStride, hipMemcpyDeviceToHost, s));
+                CSD_HIP(hipStreamSynchronize(s));
+                for (int i = 0; i <= j; ++i) H[size_t(i) * m + j] = double(h1[i]) + double(h1[kRedStride + i]);
             }
+            ww = double(h1[kRedStride - 1]);
+            nn = double(h1[(orth == 0 ? 2 : 3) * kRedStride - 1]);
             const double hn = std::sqrt(std::max(nn, 0.0));
             H[size_t(j + 1) * m + j] = hn;
             ++iters;

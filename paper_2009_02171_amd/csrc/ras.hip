@@ -21,63 +21,189 @@ namespace csd {
 
 template <class TF>
 struct DevSweep {
-    const int32_t *lev_slice;
-    const int64_t *sl_off;
-    const int32_t *sl_w;
-    const int32_t *sl_rows;
-    const TF *sl_dinv;
-    const TF *val;
-    const int32_t *col;
+    const int32_t *lev_slice;  // [nlev + 1] first slice of each level
+    const int32_t *sl_w;       // [nslice] entries per lane
+    const int64_t *sl_off;     // [nslice]
+    const int32_t *lane_io;    // [nslice*64] L: x index; U: y index of owned rows; else -1
+    const int32_t *lane_next;  // [nslice*64] L: U-sweep position of the row
+    const TF *lane_dinv;       // [nslice*64] U: 1/u_ii (0 on padding lanes)
+    const TF *val;             // [entries]
+    const uint16_t *addr;      // [entries] ring slot of the dependency
 };
 
 template <class TF>
 struct DevRas {
-    int nsd;
     const SdInfo *sd;
-    const int32_t *gcell, *own;
     DevSweep<TF> L, U;
-    TF *tvec;
+    TF *lin;    // [L slices * 64] gathered inputs of the L sweep
+    TF *lout;   // [U slices * 64] L-sweep results in U-sweep order
+    TF *ring;   // [nsd][depth * width] when the ring is not in LDS
+    int depth, width;
 };
 
-constexpr int kRasBlk = 256;
+constexpr int kChunk = 16;  // factor entries per lane held in registers at once
 
-template <class TV, class TF, bool UPPER>
-__device__ __forceinline__ void sweep(const DevSweep<TF> &S, int lev0, int lev1, TF *__restrict__ t) {
-    const int lane = threadIdx.x % 64, wv = threadIdx.x / 64, nw = kRasBlk / 64;
-    for (int lv = lev0; lv < lev1; ++lv) {
-        const int s1 = S.lev_slice[lv + 1];
-        for (int sl = S.lev_slice[lv] + wv; sl < s1; sl += nw) {
-            const int r = S.sl_rows[sl * 64 + lane];
-            const int w = S.sl_w[sl];
-            const int64_t base = S.sl_off[sl] + lane;
-            TF acc = r >= 0 ? t[r] : TF(0);
-            for (int q = 0; q < w; ++q) {
-                const int64_t at = base + int64_t(q) * 64;
-                acc -= S.val[at] * t[S.col[at]];
-            }
-            if (r >= 0) t[r] = UPPER ? acc * S.sl_dinv[sl * 64 + lane] : acc;
+// Per-lane data of one slice.  None of it depends on values computed in the
+// sweep (inputs were gathered before, addresses and factors are constant), so
+// the next level's is requested before the barrier that ends a level.
+template <class TF>
+struct Lane {
+    int w;
+    int64_t base;
+    int32_t io;      // L: U position of the row; U: y index or -1
+    TF v0, dinv;
+    int32_t addr[kChunk];
+    TF val[kChunk];
+};
+
+template <class TF>
+__device__ __forceinline__ void load_entries(const DevSweep<TF> &S, int q0, Lane<TF> &L) {
+#pragma unroll
+    for (int q = 0; q < kChunk; ++q) {
+        if (q0 + q < L.w) {
+            const int64_t at = L.base + int64_t(q0 + q) * 64;
+            L.addr[q] = S.addr[at];
+            L.val[q] = S.val[at];
+        } else {
+            L.addr[q] = 0;
+            L.val[q] = TF(0);
         }
+    }
+}
+
+template <class TF, bool UPPER>
+__device__ __forceinline__ void fetch_lane(const DevSweep<TF> &S, const int32_t *mw, const int64_t *moff, int sl0,
+                                           int sl, const TF *in, Lane<TF> &L) {
+    const int lane = threadIdx.x % 64;
+    const int64_t gpos = int64_t(sl0 + sl) * 64 + lane;
+    L.w = mw[sl];
+    L.base = moff[sl] + lane;
+    L.v0 = in[gpos];
+    if constexpr (UPPER) {
+        L.io = S.lane_io[gpos];
+        L.dinv = S.lane_dinv[gpos];
+    } else {
+        L.io = S.lane_next[gpos];
+    }
+    load_entries(S, 0, L);
+}
+
+template <class TF>
+__device__ __forceinline__ TF consume(const Lane<TF> &L, int q0, const TF *ring, TF acc) {
+    TF tv[kChunk];
+#pragma unroll
+    for (int q = 0; q < kChunk; ++q) tv[q] = q0 + q < L.w ? ring[L.addr[q]] : TF(0);
+#pragma unroll
+    for (int q = 0; q < kChunk; ++q) acc -= L.val[q] * tv[q];
+    return acc;
+}
+
+// Barrier between levels.  When the ring is in LDS only LDS traffic has to be
+// complete, so the fence is LDS-scoped: global loads issued before it (the
+// next level's data) stay in flight.  On this GPU family a full fence would
+// also wait for every outstanding global load.
+template <bool LDS_ONLY>
+__device__ __forceinline__ void level_barrier() {
+    if constexpr (LDS_ONLY) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    } else {
         __syncthreads();
     }
 }
 
-template <class TV, class TF>
-__global__ __launch_bounds__(kRasBlk) void k_ras(DevRas<TF> R, const TV *__restrict__ x, TV *__restrict__ y) {
+// One triangular sweep of one subdomain, level by level (the rows of a level
+// are independent; a barrier separates levels).  Wavefront wv takes the
+// slices wv, wv + nwaves, ... of a level.  A row's result goes to its ring
+// slot and, in the L sweep, to its U-sweep position; the U sweep writes the
+// owned rows to y (restricted scatter).
+template <class TV, class TF, bool UPPER, bool LDS, int NT>
+__device__ __forceinline__ void sweep(const DevSweep<TF> &S, const int32_t *mlev, const int32_t *mw,
+                                      const int64_t *moff, int sl0, int nlev, TF *ring, int depth, int width,
+                                      const TF *in, TF *lout, TV *y) {
+    const int lane = threadIdx.x % 64, wv = threadIdx.x / 64, nw = NT / 64;
+    Lane<TF> L;
+    bool have = false;
+    if (nlev > 0 && mlev[0] + wv < mlev[1]) { fetch_lane<TF, UPPER>(S, mw, moff, sl0, mlev[0] + wv, in, L); have = true; }
+    for (int lv = 0; lv < nlev; ++lv) {
+        const int s0 = mlev[lv], s1 = mlev[lv + 1];
+        TF *slot_base = ring + (lv % depth) * width + lane;
+        for (int sl = s0 + wv; sl < s1; sl += nw) {
+            if (!have) fetch_lane<TF, UPPER>(S, mw, moff, sl0, sl, in, L);
+            have = false;
+            TF acc = consume(L, 0, ring, L.v0);
+            for (int q0 = kChunk; q0 < L.w; q0 += kChunk) {
+                load_entries(S, q0, L);
+                acc = consume(L, q0, ring, acc);
+            }
+            if constexpr (UPPER) acc *= L.dinv;
+            slot_base[(sl - s0) * 64] = acc;
+            if constexpr (UPPER) {
+                if (L.io >= 0) y[L.io] = TV(acc);
+            } else {
+                if (L.io >= 0) lout[L.io] = acc;
+            }
+        }
+        if (lv + 1 < nlev && mlev[lv + 1] + wv < mlev[lv + 2]) {
+            fetch_lane<TF, UPPER>(S, mw, moff, sl0, mlev[lv + 1] + wv, in, L);
+            have = true;
+        }
+        level_barrier<LDS>();
+    }
+}
+
+// LDS bytes of one sweep's slice metadata: per level 4, per slice 4 + 8.
+__host__ __device__ constexpr size_t meta_bytes_for(int nsl, int nlev) {
+    return ((size_t(nlev) + 1) * 4 + 7) / 8 * 8 + size_t(nsl) * 12 + 15 & ~size_t(15);
+}
+
+template <class TF, int NT>
+__device__ __forceinline__ int stage_meta(const DevSweep<TF> &S, int lev0, int lev1, int meta_lev, int meta_sl,
+                                          unsigned char *base, int32_t *&mlev, int32_t *&mw, int64_t *&moff) {
+    mlev = reinterpret_cast<int32_t *>(base);
+    moff = reinterpret_cast<int64_t *>(base + ((size_t(meta_lev) + 1) * 4 + 7) / 8 * 8);
+    mw = reinterpret_cast<int32_t *>(moff + meta_sl);
+    const int sl0 = S.lev_slice[lev0];
+    const int nlev = lev1 - lev0, nsl = S.lev_slice[lev1] - sl0;
+    for (int a = threadIdx.x; a <= nlev; a += NT) mlev[a] = S.lev_slice[lev0 + a] - sl0;
+    for (int a = threadIdx.x; a < nsl; a += NT) {
+        mw[a] = S.sl_w[sl0 + a];
+        moff[a] = S.sl_off[sl0 + a];
+    }
+    return sl0;
+}
+
+// One workgroup per subdomain: gather x (coalesced over the L-sweep order),
+// L sweep, U sweep with restricted scatter.  The ring of the last `depth`
+// levels is in LDS when LDS = true, else in the workspace.
+template <class TV, class TF, bool LDS, int NT>
+__global__ __launch_bounds__(NT) void k_ras(DevRas<TF> R, int meta_lev, int meta_sl, const TV *__restrict__ x,
+                                            TV *__restrict__ y) {
+    extern __shared__ __align__(16) unsigned char ras_smem[];
     const SdInfo I = R.sd[blockIdx.x];
-    TF *t = R.tvec + I.t_off;
-    const int32_t *gc = R.gcell + I.cell_off;
-    for (int l = threadIdx.x; l < I.nloc; l += kRasBlk) {
-        const int64_t g = int64_t(gc[l]) * 4;
-        for (int c = 0; c < 4; ++c) t[4 * l + c] = TF(x[g + c]);
+    const int ring_n = R.depth * R.width;
+    TF *ring = LDS ? reinterpret_cast<TF *>(ras_smem + meta_bytes_for(meta_sl, meta_lev))
+                   : R.ring + int64_t(blockIdx.x) * ring_n;
+    for (int a = threadIdx.x; a < ring_n; a += NT) ring[a] = TF(0);
+    int32_t *mlev, *mw;
+    int64_t *moff;
+    int sl0 = stage_meta<TF, NT>(R.L, I.levL0, I.levL1, meta_lev, meta_sl, ras_smem, mlev, mw, moff);
+    {
+        const int64_t p0 = int64_t(sl0) * 64, p1 = int64_t(R.L.lev_slice[I.levL1]) * 64;
+        for (int64_t p = p0 + threadIdx.x; p < p1; p += NT) {
+            const int32_t io = R.L.lane_io[p];
+            R.lin[p] = io >= 0 ? TF(x[io]) : TF(0);
+        }
     }
     __syncthreads();
-    sweep<TV, TF, false>(R.L, I.levL0, I.levL1, t);
-    sweep<TV, TF, true>(R.U, I.levU0, I.levU1, t);
-    for (int o = threadIdx.x; o < I.nown; o += kRasBlk) {
-        const int l = R.own[I.own_off + o];
-        const int64_t g = int64_t(gc[l]) * 4;
-        for (int c = 0; c < 4; ++c) y[g + c] = TV(t[4 * l + c]);
-    }
+    sweep<TV, TF, false, LDS, NT>(R.L, mlev, mw, moff, sl0, I.levL1 - I.levL0, ring, R.depth, R.width, R.lin,
+                                  R.lout, y);
+    __syncthreads();  // L results visible; the U metadata replaces the L metadata
+    sl0 = stage_meta<TF, NT>(R.U, I.levU0, I.levU1, meta_lev, meta_sl, ras_smem, mlev, mw, moff);
+    __syncthreads();
+    sweep<TV, TF, true, LDS, NT>(R.U, mlev, mw, moff, sl0, I.levU1 - I.levU0, ring, R.depth, R.width, R.lout,
+                                 R.lout, y);
 }
 
 // restriction: mean of the 8 children; prolongation: copy to the children
@@ -123,62 +249,69 @@ static dim3 grid_for(int64_t n) { return dim3(unsigned(std::max<int64_t>(1, std:
 // One level of RAS data on the device (factors in TF).
 struct OneLevel {
     int nsd = 0;
-    int64_t tlen = 0, nnz = 0, nown = 0;
-    int max_levels = 0;
-    SdInfo *sd = nullptr;
-    int32_t *gcell = nullptr, *own = nullptr;
-    int32_t *Llev = nullptr, *Lw = nullptr, *Lrows = nullptr, *Lcol = nullptr;
-    int64_t *Loff = nullptr;
-    int32_t *Ulev = nullptr, *Uw = nullptr, *Urows = nullptr, *Ucol = nullptr;
-    int64_t *Uoff = nullptr;
-    void *Lval = nullptr, *Uval = nullptr, *Udinv = nullptr;
-    void *tvec = nullptr;
+    int64_t nnz = 0, box_cells = 0, owned_cells = 0;
+    int depth = 0, width = 0, meta_lev = 0, meta_sl = 0, max_total_levels = 0;
+    int threads = 256;
+    size_t lds_bytes = 0;
+    bool lds_ring = false;
     int precision = 0;
+    SdInfo *sd = nullptr;
+    int32_t *Llev = nullptr, *Lw = nullptr, *Lio = nullptr, *Lnext = nullptr;
+    int64_t *Loff = nullptr;
+    uint16_t *Laddr = nullptr;
+    int32_t *Ulev = nullptr, *Uw = nullptr, *Uio = nullptr;
+    int64_t *Uoff = nullptr;
+    uint16_t *Uaddr = nullptr;
+    void *Lval = nullptr, *Uval = nullptr, *Udinv = nullptr, *lin = nullptr, *lout = nullptr, *ring = nullptr;
 
     static void layout(Carver &c, const HostRas &H, int precision, OneLevel &o) {
         const size_t fs = precision ? sizeof(float) : sizeof(double);
-        o.nsd = H.nsd; o.tlen = H.tlen; o.nnz = H.nnz; o.nown = int64_t(H.own.size()); o.precision = precision; o.max_levels = H.max_levels;
+        o.nsd = H.nsd; o.nnz = H.nnz; o.box_cells = H.box_cells; o.owned_cells = H.owned_cells;
+        o.depth = H.ring_depth; o.width = H.ring_width; o.meta_lev = H.max_levels; o.meta_sl = H.max_slices;
+        o.max_total_levels = H.max_total_levels; o.precision = precision;
         o.sd = c.take<SdInfo>(H.sd.size());
-        o.gcell = c.take<int32_t>(H.gcell.size());
-        o.own = c.take<int32_t>(H.own.size());
-        o.Llev = c.take<int32_t>(H.L.lev_slice.size()); o.Loff = c.take<int64_t>(H.L.sl_off.size());
-        o.Lw = c.take<int32_t>(H.L.sl_w.size()); o.Lrows = c.take<int32_t>(H.L.sl_rows.size());
-        o.Lcol = c.take<int32_t>(H.L.col.size()); o.Lval = c.take<char>(H.L.val.size() * fs);
-        o.Ulev = c.take<int32_t>(H.U.lev_slice.size()); o.Uoff = c.take<int64_t>(H.U.sl_off.size());
-        o.Uw = c.take<int32_t>(H.U.sl_w.size()); o.Urows = c.take<int32_t>(H.U.sl_rows.size());
-        o.Ucol = c.take<int32_t>(H.U.col.size()); o.Uval = c.take<char>(H.U.val.size() * fs);
-        o.Udinv = c.take<char>(H.U.sl_diag.size() * fs);
-        o.tvec = c.take<char>(size_t(H.tlen) * fs);
+        o.Llev = c.take<int32_t>(H.L.lev_slice.size()); o.Lw = c.take<int32_t>(H.L.sl_w.size());
+        o.Loff = c.take<int64_t>(H.L.sl_off.size()); o.Lio = c.take<int32_t>(H.L.lane_io.size());
+        o.Lnext = c.take<int32_t>(H.L.lane_next.size()); o.Laddr = c.take<uint16_t>(H.L.addr.size());
+        o.Lval = c.take<char>(H.L.val.size() * fs);
+        o.Ulev = c.take<int32_t>(H.U.lev_slice.size()); o.Uw = c.take<int32_t>(H.U.sl_w.size());
+        o.Uoff = c.take<int64_t>(H.U.sl_off.size()); o.Uio = c.take<int32_t>(H.U.lane_io.size());
+        o.Udinv = c.take<char>(H.U.lane_diag.size() * fs); o.Uaddr = c.take<uint16_t>(H.U.addr.size());
+        o.Uval = c.take<char>(H.U.val.size() * fs);
+        o.lin = c.take<char>(H.L.lane_io.size() * fs);
+        o.lout = c.take<char>(H.U.lane_io.size() * fs);
+        o.ring = c.take<char>(size_t(H.nsd) * H.ring_depth * H.ring_width * fs);
     }
 
     int32_t upload(const HostRas &H) const {
         auto up = [](void *d, const void *s, size_t b) { return b ? hipMemcpy(d, s, b, hipMemcpyHostToDevice) : hipSuccess; };
         CSD_HIP(up(sd, H.sd.data(), H.sd.size() * sizeof(SdInfo)));
-        CSD_HIP(up(gcell, H.gcell.data(), H.gcell.size() * 4));
-        CSD_HIP(up(own, H.own.data(), H.own.size() * 4));
         CSD_HIP(up(Llev, H.L.lev_slice.data(), H.L.lev_slice.size() * 4));
-        CSD_HIP(up(Loff, H.L.sl_off.data(), H.L.sl_off.size() * 8));
         CSD_HIP(up(Lw, H.L.sl_w.data(), H.L.sl_w.size() * 4));
-        CSD_HIP(up(Lrows, H.L.sl_rows.data(), H.L.sl_rows.size() * 4));
-        CSD_HIP(up(Lcol, H.L.col.data(), H.L.col.size() * 4));
+        CSD_HIP(up(Loff, H.L.sl_off.data(), H.L.sl_off.size() * 8));
+        CSD_HIP(up(Lio, H.L.lane_io.data(), H.L.lane_io.size() * 4));
+        CSD_HIP(up(Lnext, H.L.lane_next.data(), H.L.lane_next.size() * 4));
+        CSD_HIP(up(Laddr, H.L.addr.data(), H.L.addr.size() * 2));
         CSD_HIP(up(Ulev, H.U.lev_slice.data(), H.U.lev_slice.size() * 4));
-        CSD_HIP(up(Uoff, H.U.sl_off.data(), H.U.sl_off.size() * 8));
         CSD_HIP(up(Uw, H.U.sl_w.data(), H.U.sl_w.size() * 4));
-        CSD_HIP(up(Urows, H.U.sl_rows.data(), H.U.sl_rows.size() * 4));
-        CSD_HIP(up(Ucol, H.U.col.data(), H.U.col.size() * 4));
+        CSD_HIP(up(Uoff, H.U.sl_off.data(), H.U.sl_off.size() * 8));
+        CSD_HIP(up(Uio, H.U.lane_io.data(), H.U.lane_io.size() * 4));
+        CSD_HIP(up(Uaddr, H.U.addr.data(), H.U.addr.size() * 2));
+        // padding lanes of the U sweep read L results that are never written: keep them 0
+        CSD_HIP(hipMemset(lout, 0, H.U.lane_io.size() * (precision ? sizeof(float) : sizeof(double))));
         if (precision) {
             std::vector<float> f(H.L.val.begin(), H.L.val.end());
             CSD_HIP(up(Lval, f.data(), f.size() * 4));
             f.assign(H.U.val.begin(), H.U.val.end());
             CSD_HIP(up(Uval, f.data(), f.size() * 4));
-            f.assign(H.U.sl_diag.size(), 0.0f);
-            for (size_t a = 0; a < f.size(); ++a) f[a] = H.U.sl_diag[a] != 0.0 ? 1.0f / float(H.U.sl_diag[a]) : 0.0f;
+            f.assign(H.U.lane_diag.size(), 0.0f);
+            for (size_t a = 0; a < f.size(); ++a) f[a] = H.U.lane_diag[a] != 0.0 ? 1.0f / float(H.U.lane_diag[a]) : 0.0f;
             CSD_HIP(up(Udinv, f.data(), f.size() * 4));
         } else {
             CSD_HIP(up(Lval, H.L.val.data(), H.L.val.size() * 8));
             CSD_HIP(up(Uval, H.U.val.data(), H.U.val.size() * 8));
-            std::vector<double> d(H.U.sl_diag.size(), 0.0);
-            for (size_t a = 0; a < d.size(); ++a) d[a] = H.U.sl_diag[a] != 0.0 ? 1.0 / H.U.sl_diag[a] : 0.0;
+            std::vector<double> d(H.U.lane_diag.size(), 0.0);
+            for (size_t a = 0; a < d.size(); ++a) d[a] = H.U.lane_diag[a] != 0.0 ? 1.0 / H.U.lane_diag[a] : 0.0;
             CSD_HIP(up(Udinv, d.data(), d.size() * 8));
         }
         return CSDYN_OK;
@@ -187,20 +320,75 @@ struct OneLevel {
     template <class TF>
     DevRas<TF> dev() const {
         DevRas<TF> R;
-        R.nsd = nsd; R.sd = sd; R.gcell = gcell; R.own = own;
-        R.L = DevSweep<TF>{Llev, Loff, Lw, Lrows, nullptr, (const TF *)Lval, Lcol};
-        R.U = DevSweep<TF>{Ulev, Uoff, Uw, Urows, (const TF *)Udinv, (const TF *)Uval, Ucol};
-        R.tvec = (TF *)tvec;
+        R.sd = sd;
+        R.L = DevSweep<TF>{Llev, Lw, Loff, Lio, Lnext, nullptr, (const TF *)Lval, Laddr};
+        R.U = DevSweep<TF>{Ulev, Uw, Uoff, Uio, nullptr, (const TF *)Udinv, (const TF *)Uval, Uaddr};
+        R.lin = (TF *)lin;
+        R.lout = (TF *)lout;
+        R.ring = (TF *)ring;
+        R.depth = depth;
+        R.width = width;
         return R;
+    }
+
+    template <class TV, class TF, bool LDS, int NT>
+    static const void *kernel() { return (const void *)k_ras<TV, TF, LDS, NT>; }
+
+    template <class TV, class TF>
+    int32_t set_attr() const {
+        const hipFuncAttribute at = hipFuncAttributeMaxDynamicSharedMemorySize;
+        const int lb = int(lds_bytes);
+        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, 256>(), at, lb));
+        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, 512>(), at, lb));
+        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, 1024>(), at, lb));
+        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, false, 256>(), at, lb));
+        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, false, 512>(), at, lb));
+        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, false, 1024>(), at, lb));
+        return CSDYN_OK;
+    }
+
+    // The ring goes to LDS when it fits next to the metadata; the workgroup
+    // size covers one level's slices with one wavefront each (256..1024).
+    int32_t choose_memory() {
+        int dev = 0, maxs = 0;
+        CSD_HIP(hipGetDevice(&dev));
+        CSD_HIP(hipDeviceGetAttribute(&maxs, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        const size_t meta = meta_bytes_for(meta_sl, meta_lev);
+        const size_t rb = size_t(depth) * width * (precision ? sizeof(float) : sizeof(double));
+        if (meta > size_t(maxs)) { set_error("ras: subdomain schedule too large for LDS"); return CSDYN_EINVAL; }
+        lds_ring = meta + rb <= size_t(maxs);
+        lds_bytes = meta + (lds_ring ? rb : 0);
+        threads = width <= 256 ? 256 : (width <= 512 ? 512 : 1024);
+        if (precision) {
+            CSD_TRY((set_attr<double, float>()));
+            CSD_TRY((set_attr<float, float>()));
+        } else {
+            CSD_TRY((set_attr<double, double>()));
+        }
+        return CSDYN_OK;
+    }
+
+    template <class TV, class TF, bool LDS>
+    void launch_nt(const TV *x, TV *y, hipStream_t s) const {
+        const dim3 g(nsd);
+        if (threads == 256) hipLaunchKernelGGL((k_ras<TV, TF, LDS, 256>), g, dim3(256), lds_bytes, s, dev<TF>(), meta_lev, meta_sl, x, y);
+        else if (threads == 512) hipLaunchKernelGGL((k_ras<TV, TF, LDS, 512>), g, dim3(512), lds_bytes, s, dev<TF>(), meta_lev, meta_sl, x, y);
+        else hipLaunchKernelGGL((k_ras<TV, TF, LDS, 1024>), g, dim3(1024), lds_bytes, s, dev<TF>(), meta_lev, meta_sl, x, y);
+    }
+
+    template <class TV, class TF>
+    void launch(const TV *x, TV *y, hipStream_t s) const {
+        if (lds_ring) launch_nt<TV, TF, true>(x, y, s);
+        else launch_nt<TV, TF, false>(x, y, s);
     }
 
     template <class TV>
     int32_t apply(const TV *x, TV *y, hipStream_t s) const {
         // factor values once, x gathered on the boxes, y written on the owned cells
-        const double bytes = double(nnz) * (precision ? 4 : 8) + double(tlen + 4 * nown) * sizeof(TV);
-        ProfScope ps(precision ? "ras_f32" : "ras", tlen / 4, bytes, s);
-        if (precision) hipLaunchKernelGGL((k_ras<TV, float>), dim3(nsd), dim3(kRasBlk), 0, s, dev<float>(), x, y);
-        else hipLaunchKernelGGL((k_ras<TV, double>), dim3(nsd), dim3(kRasBlk), 0, s, dev<double>(), x, y);
+        const double bytes = double(nnz) * (precision ? 4 : 8) + double(4 * (box_cells + owned_cells)) * sizeof(TV);
+        ProfScope ps(precision ? "ras_f32" : "ras", box_cells, bytes, s);
+        if (precision) launch<TV, float>(x, y, s);
+        else if constexpr (sizeof(TV) == 8) launch<TV, double>(x, y, s);
         CSD_HIP(hipGetLastError());
         return CSDYN_OK;
     }
@@ -332,8 +520,8 @@ extern "C" int32_t csdyn_ras_setup(const csdyn_opctx *ctx, const csdyn_ras_opts 
     if (c.off + 256 > ws_bytes) { set_error("ras: workspace %zu < %zu bytes", ws_bytes, c.off + 256); return CSDYN_ENOMEM; }
     R->info = csdyn_ras_info{};
     auto fill = [](const HostRas &H, int32_t &nsd, int64_t &nnz, int64_t &box, int64_t &own, int64_t &stored, int32_t &lv) {
-        nsd = H.nsd; nnz = H.nnz; box = int64_t(H.gcell.size()); own = int64_t(H.own.size());
-        stored = int64_t(H.L.val.size() + H.U.val.size() + H.U.sl_diag.size()); lv = H.max_levels;
+        nsd = H.nsd; nnz = H.nnz; box = H.box_cells; own = H.owned_cells;
+        stored = int64_t(H.L.val.size() + H.U.val.size() + H.U.lane_diag.size()); lv = H.max_total_levels;
     };
     fill(b->fine, R->info.nsd_fine, R->info.nnz_fine, R->info.box_cells_fine, R->info.owned_cells_fine,
          R->info.stored_fine, R->info.max_levels_fine);
@@ -341,6 +529,7 @@ extern "C" int32_t csdyn_ras_setup(const csdyn_opctx *ctx, const csdyn_ras_opts 
         fill(b->coarse, R->info.nsd_coarse, R->info.nnz_coarse, R->info.box_cells_coarse, R->info.owned_cells_coarse,
              R->info.stored_coarse, R->info.max_levels_coarse);
     R->info.precision = o->precision;
+    CSD_TRY(R->fine.choose_memory());
     CSD_TRY(R->fine.upload(b->fine));
     if (o->levels == 2) {
         R->coarse_ctx.g = ctx->g;
@@ -349,11 +538,17 @@ extern "C" int32_t csdyn_ras_setup(const csdyn_opctx *ctx, const csdyn_ras_opts 
         R->coarse_ctx.hg = b->gc;
         R->coarse_ctx.ws_bytes = devgeom_bytes(b->gc.n, b->gc.nr);
         CSD_TRY(devgeom_setup(R->coarse_ctx.hg, R->coarse_ctx.ws, &R->coarse_ctx.dg));
+        CSD_TRY(R->coarse.choose_memory());
         CSD_TRY(R->coarse.upload(b->coarse));
         double v = 0;
         for (double a : b->gc.vol) v += a;
         R->vol_c = v;
+
     }
+    R->info.lds_fine = int32_t(R->fine.lds_bytes);
+    R->info.box_in_lds_fine = R->fine.lds_ring;
+    R->info.lds_coarse = int32_t(R->coarse.lds_bytes);
+    R->info.box_in_lds_coarse = R->coarse.lds_ring;
     if (stream) CSD_HIP(hipStreamSynchronize((hipStream_t)stream));
     *out = R.release();
     return CSDYN_OK;
@@ -504,6 +699,7 @@ extern "C" int32_t csdyn_gmres_solve(const csdyn_opctx *ctx, const csdyn_ras *pc
     clear_error();
     if (!ctx || !o || !b || !x || !ws) { set_error("gmres: null argument"); return CSDYN_EINVAL; }
     if (o->restart < 1 || o->restart > kRedStride - 1 || o->maxit < 1) { set_error("gmres: restart in [1,32], maxit >= 1"); return CSDYN_EINVAL; }
+    if (o->orth != 0 && o->orth != 1) { set_error("gmres: orth must be 0 (CGS) or 1 (CGS2)"); return CSDYN_EINVAL; }
     if (pc && pc->fine_ctx->g.n != ctx->g.n) { set_error("gmres: preconditioner built for another grid"); return CSDYN_EINVAL; }
     Carver c(ws);
     SolveLayout L;
@@ -511,6 +707,7 @@ extern "C" int32_t csdyn_gmres_solve(const csdyn_opctx *ctx, const csdyn_ras *pc
     if (c.off + 256 > ws_bytes) { set_error("gmres: workspace %zu < %zu bytes", ws_bytes, c.off + 256); return CSDYN_ENOMEM; }
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = L.gm.n, ncell = n / 4;
+    L.gm.orth = o->orth;
     CSD_TRY(Vec<double>::copy(L.bproj, b, n, s));
     auto project = [&](double *v) -> int32_t {
         CSD_TRY(Vec<double>::pmoments(v, ctx->dg.vol, ncell, L.gm.partial, L.gm.red, s));

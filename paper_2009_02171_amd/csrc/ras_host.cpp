@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <numeric>
 
 namespace csd {
@@ -194,6 +195,7 @@ class Expander {
 
 struct LocalSd {
     std::vector<int32_t> gcell, own;
+    std::vector<uint8_t> owned_row;  // per local cell
     std::vector<int64_t> rp;
     std::vector<int32_t> ci;
     std::vector<double> v;
@@ -270,6 +272,8 @@ void build_one(const HostGeom &g, const csdyn_op &op, const int sub[3], const in
         }
     }
     for (int32_t c : L.gcell) g2l[c] = -1;
+    L.owned_row.assign(L.gcell.size(), 0);
+    for (int32_t l : L.own) L.owned_row[l] = 1;
 
     // ILU(0): for each row i, for each k < i in the row: l_ik = a_ik / u_kk,
     // then a_ij -= l_ik u_kj for the j > k present in row i.
@@ -310,46 +314,107 @@ void build_one(const HostGeom &g, const csdyn_op &op, const int sub[3], const in
     }
 }
 
-// Append one subdomain's factor (lower or upper part) to the slice pack.
-void pack_sweep(const LocalSd &L, bool upper, SweepPack &P, int32_t &lev0, int32_t &lev1) {
+// Row schedule of one sweep of one subdomain: rows by level, within a level
+// by decreasing width, cut into slices of 64.
+struct Schedule {
+    std::vector<int32_t> lev_first;   // [nlev + 1] first slice (relative) of each level
+    std::vector<int32_t> slice_rows;  // [nslice * 64] row or -1
+    std::vector<int32_t> pos;         // [nrow] slice*64 + lane (relative)
+    std::vector<int32_t> slot;        // [nrow] ring slot
+};
+
+void make_schedule(const LocalSd &L, bool upper, int depth, int width, Schedule &S) {
     const int64_t nrow = int64_t(L.rp.size()) - 1;
     const int nlev = upper ? L.nlevU : L.nlevL;
     const std::vector<int32_t> &lev = upper ? L.levU : L.levL;
+    auto cnt = [&](int64_t r) -> int64_t { return upper ? L.rp[r + 1] - L.diag[r] - 1 : L.diag[r] - L.rp[r]; };
     std::vector<std::vector<int32_t>> rows(nlev);
     for (int64_t r = 0; r < nrow; ++r) rows[lev[r]].push_back(int32_t(r));
-    auto cnt = [&](int32_t r) -> int64_t {
-        return upper ? L.rp[r + 1] - L.diag[r] - 1 : L.diag[r] - L.rp[r];
-    };
-    lev0 = int32_t(P.lev_slice.size());
+    S.lev_first.assign(1, 0);
+    S.slice_rows.clear();
+    S.pos.assign(nrow, -1);
+    S.slot.assign(nrow, -1);
     for (int lv = 0; lv < nlev; ++lv) {
         auto &R = rows[lv];
         std::stable_sort(R.begin(), R.end(), [&](int32_t a, int32_t b) { return cnt(a) > cnt(b); });
-        P.lev_slice.push_back(int32_t(P.sl_w.size()));
-        for (size_t s0 = 0; s0 < R.size(); s0 += 64) {
-            const size_t ns = std::min<size_t>(64, R.size() - s0);
-            int64_t w = 0;
-            for (size_t a = 0; a < ns; ++a) w = std::max(w, cnt(R[s0 + a]));
-            const int64_t off = int64_t(P.val.size());
-            P.sl_off.push_back(off);
-            P.sl_w.push_back(int32_t(w));
-            P.val.resize(off + w * 64, 0.0);
-            P.col.resize(off + w * 64, 0);
-            for (size_t a = 0; a < 64; ++a) {
-                const int32_t r = a < ns ? R[s0 + a] : -1;
-                P.sl_rows.push_back(r);
-                P.sl_diag.push_back(r >= 0 && upper ? L.v[L.diag[r]] : 0.0);
-                if (r < 0) continue;
-                const int64_t q0 = upper ? L.diag[r] + 1 : L.rp[r];
-                const int64_t nq = cnt(r);
-                for (int64_t q = 0; q < w; ++q) {
-                    const int64_t at = off + q * 64 + int64_t(a);
-                    if (q < nq) { P.val[at] = L.v[q0 + q]; P.col[at] = L.ci[q0 + q]; }
-                    else { P.val[at] = 0.0; P.col[at] = r; }  // padding reads the row's own entry
+        const int first = S.lev_first.back();
+        const int nsl = int((R.size() + 63) / 64);
+        for (int a = 0; a < nsl * 64; ++a) {
+            const int32_t r = a < int(R.size()) ? R[a] : -1;
+            S.slice_rows.push_back(r);
+            if (r < 0) continue;
+            S.pos[r] = first * 64 + a;
+            S.slot[r] = depth > 0 ? (lv % depth) * width + a : -1;
+        }
+        S.lev_first.push_back(first + nsl);
+    }
+}
+
+// Append one subdomain's sweep to the pack.  sched_other is the U schedule
+// (for the L sweep's lane_next); base_other its first global U slice.
+void pack_sweep(const LocalSd &L, bool upper, const Schedule &S, const Schedule *U_sched, int64_t base_u,
+                SweepPack &P, int32_t &lev0, int32_t &lev1) {
+    auto first = [&](int64_t r) { return upper ? L.diag[r] + 1 : L.rp[r]; };
+    auto cnt = [&](int64_t r) -> int64_t { return upper ? L.rp[r + 1] - L.diag[r] - 1 : L.diag[r] - L.rp[r]; };
+    const int64_t base = int64_t(P.sl_w.size());
+    lev0 = int32_t(P.lev_slice.size());
+    for (size_t lv = 0; lv + 1 < S.lev_first.size(); ++lv) P.lev_slice.push_back(int32_t(base + S.lev_first[lv]));
+    lev1 = int32_t(P.lev_slice.size());
+    const int nsl = S.lev_first.back();
+    for (int sl = 0; sl < nsl; ++sl) {
+        int64_t w = 0;
+        for (int a = 0; a < 64; ++a) {
+            const int32_t r = S.slice_rows[sl * 64 + a];
+            if (r >= 0) w = std::max(w, cnt(r));
+        }
+        const int64_t off = int64_t(P.val.size());
+        P.sl_w.push_back(int32_t(w));
+        P.sl_off.push_back(off);
+        P.val.resize(off + w * 64, 0.0);
+        P.addr.resize(off + w * 64, 0);
+        for (int a = 0; a < 64; ++a) {
+            const int32_t r = S.slice_rows[sl * 64 + a];
+            int32_t io = -1, nxt = -1;
+            double dg = 0.0;
+            if (r >= 0) {
+                const int64_t gunk = 4 * int64_t(L.gcell[r / 4]) + r % 4;
+                if (!upper) {
+                    io = int32_t(gunk);
+                    nxt = int32_t(base_u * 64 + U_sched->pos[r]);
+                } else {
+                    dg = L.v[L.diag[r]];
+                    if (L.owned_row[r / 4]) io = int32_t(gunk);
                 }
+                const int64_t q0 = first(r);
+                for (int64_t q = 0; q < cnt(r); ++q) {
+                    P.val[off + q * 64 + a] = L.v[q0 + q];
+                    P.addr[off + q * 64 + a] = uint16_t(S.slot[L.ci[q0 + q]]);
+                }
+                for (int64_t q = cnt(r); q < w; ++q) P.addr[off + q * 64 + a] = uint16_t(S.slot[r]);  // zero value
             }
+            P.lane_io.push_back(io);
+            if (!upper) P.lane_next.push_back(nxt);
+            else P.lane_diag.push_back(dg);
         }
     }
-    lev1 = int32_t(P.lev_slice.size());
+}
+
+// Longest distance in levels between a row and its dependencies, and the
+// largest number of rows in one level, over both sweeps.
+void sweep_stats(const LocalSd &L, int &span, int &rows) {
+    const int64_t nrow = int64_t(L.rp.size()) - 1;
+    span = 0;
+    rows = 0;
+    for (int upper = 0; upper < 2; ++upper) {
+        const std::vector<int32_t> &lev = upper ? L.levU : L.levL;
+        std::vector<int32_t> count(upper ? L.nlevU : L.nlevL, 0);
+        for (int64_t r = 0; r < nrow; ++r) {
+            ++count[lev[r]];
+            const int64_t a = upper ? L.diag[r] + 1 : L.rp[r], b = upper ? L.rp[r + 1] : L.diag[r];
+            for (int64_t q = a; q < b; ++q) span = std::max(span, lev[r] - lev[L.ci[q]]);
+        }
+        for (int32_t c : count) rows = std::max(rows, int(c));
+    }
 }
 
 }  // namespace
@@ -401,24 +466,38 @@ int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], 
             set_error("ras: zero pivot in the ILU(0) factorization of subdomain %d", s);
             return status;
         }
+    // ring geometry shared by all subdomains
+    int span = 0, rows = 0;
+    for (int s = 0; s < H.nsd; ++s) {
+        int sp, rw;
+        sweep_stats(loc[s], sp, rw);
+        span = std::max(span, sp);
+        rows = std::max(rows, rw);
+    }
+    H.ring_depth = span + 1;
+    H.ring_width = ((rows + 63) / 64) * 64;
+    if (int64_t(H.ring_depth) * H.ring_width > 65536) {
+        set_error("ras: subdomain too large for the level ring (%d levels x %d rows)", H.ring_depth, H.ring_width);
+        return CSDYN_EINVAL;
+    }
     H.sd.resize(H.nsd);
-    int64_t toff = 0;
     for (int s = 0; s < H.nsd; ++s) {
         LocalSd &L = loc[s];
         SdInfo &I = H.sd[s];
-        I.cell_off = int64_t(H.gcell.size());
         I.nloc = int32_t(L.gcell.size());
-        I.own_off = int32_t(H.own.size());
         I.nown = int32_t(L.own.size());
-        I.t_off = toff;
-        toff += 4 * int64_t(L.gcell.size());
-        H.gcell.insert(H.gcell.end(), L.gcell.begin(), L.gcell.end());
-        H.own.insert(H.own.end(), L.own.begin(), L.own.end());
+        H.box_cells += I.nloc;
+        H.owned_cells += I.nown;
         H.nnz += int64_t(L.ci.size());
-        pack_sweep(L, false, H.L, I.levL0, I.levL1);
-        pack_sweep(L, true, H.U, I.levU0, I.levU1);
-        H.max_levels = std::max(H.max_levels, L.nlevL + L.nlevU);
-        I.pad = 0;
+        Schedule SL, SU;
+        make_schedule(L, false, H.ring_depth, H.ring_width, SL);
+        make_schedule(L, true, H.ring_depth, H.ring_width, SU);
+        const int64_t base_u = int64_t(H.U.sl_w.size());
+        pack_sweep(L, true, SU, nullptr, 0, H.U, I.levU0, I.levU1);
+        pack_sweep(L, false, SL, &SU, base_u, H.L, I.levL0, I.levL1);
+        H.max_slices = std::max(H.max_slices, std::max(SL.lev_first.back(), SU.lev_first.back()));
+        H.max_levels = std::max(H.max_levels, std::max(L.nlevL, L.nlevU));
+        H.max_total_levels = std::max(H.max_total_levels, L.nlevL + L.nlevU);
         LocalSd().gcell.swap(L.gcell);
         std::vector<int64_t>().swap(L.rp);
         std::vector<int32_t>().swap(L.ci);
@@ -426,7 +505,12 @@ int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], 
     }
     H.L.lev_slice.push_back(int32_t(H.L.sl_w.size()));
     H.U.lev_slice.push_back(int32_t(H.U.sl_w.size()));
-    H.tlen = toff;
+    // tail padding: the sweep kernel may read a fixed number of entries past a
+    // slice's width; keep those reads inside the arrays
+    for (SweepPack *P : {&H.L, &H.U}) {
+        P->val.resize(P->val.size() + 64 * 64, 0.0);
+        P->addr.resize(P->addr.size() + 64 * 64, 0);
+    }
     return CSDYN_OK;
 }
 

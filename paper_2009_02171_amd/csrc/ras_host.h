@@ -12,38 +12,41 @@
 
 namespace csd {
 
-// One triangular factor (L strictly lower, or U upper with 1/diag split off)
-// of all subdomains, in the slice layout the sweep kernel reads: the rows of
-// one level are grouped in slices of 64 lanes; entry q of lane l of slice s
-// is at off[s] + q*64 + l.
+// One triangular sweep (the L sweep or the U sweep) of all subdomains, in
+// the order the sweep kernel processes it.  The rows of a subdomain are
+// ordered by level; within a level they form slices of 64 lanes (one row per
+// lane).  Entry q of lane l of slice s is at sl_off[s] + q*64 + l.  A
+// dependency is addressed by its ring slot: rows only depend on rows of the
+// previous ring_depth - 1 levels, so the sweep keeps the results of the last
+// ring_depth levels in a ring of ring_depth x ring_width values, slot =
+// (level mod ring_depth) * ring_width + 64 * (slice - first slice of the
+// level) + lane.
 struct SweepPack {
     std::vector<int32_t> lev_slice;  // [nlev_total + 1] first slice of each level
-    std::vector<int64_t> sl_off;     // [nslice]
     std::vector<int32_t> sl_w;       // [nslice] entries per lane
-    std::vector<int32_t> sl_rows;    // [nslice * 64] local row, -1 = padding lane
-    std::vector<double> sl_diag;     // [nslice * 64] u_ii (U only; 0 on padding lanes)
+    std::vector<int64_t> sl_off;     // [nslice]
+    std::vector<int32_t> lane_io;    // [nslice*64] L: x index of the row; U: y index of an owned row; else -1
+    std::vector<int32_t> lane_next;  // [nslice*64] L only: U-sweep position (slice*64 + lane) of the row
+    std::vector<double> lane_diag;   // [nslice*64] U only: u_ii (0 on padding lanes)
     std::vector<double> val;         // [entries]
-    std::vector<int32_t> col;        // [entries] local row index
+    std::vector<uint16_t> addr;      // [entries] ring slot of the dependency
 };
 
 struct SdInfo {
-    int64_t cell_off;  // into gcell
-    int64_t t_off;     // into the local-vector scratch (in components)
-    int32_t nloc, own_off, nown;
-    int32_t levL0, levL1, levU0, levU1;
-    int32_t pad;
+    int32_t levL0, levL1, levU0, levU1;  // level ranges of the two sweeps
+    int32_t nloc, nown;
 };
 
 struct HostRas {
     int nsd = 0;
     int nb[3] = {0, 0, 0};
     std::vector<SdInfo> sd;
-    std::vector<int32_t> gcell;  // local cell -> global cell
-    std::vector<int32_t> own;    // owned local cells (indices relative to the subdomain)
     SweepPack L, U;
-    int64_t tlen = 0;            // total local-vector length (components)
-    int64_t nnz = 0;             // factor entries before padding
-    int max_levels = 0;
+    int ring_depth = 0, ring_width = 0;  // levels kept, lanes per level
+    int max_slices = 0, max_levels = 0;  // per sweep of one subdomain (LDS metadata sizing)
+    int64_t nnz = 0;                     // factor entries (L and U, diagonal included)
+    int64_t box_cells = 0, owned_cells = 0;
+    int max_total_levels = 0;            // L + U levels of the deepest subdomain
 };
 
 // Build and factor.  Returns CSDYN_EZEROPIVOT / CSDYN_EINVAL on failure.

@@ -13,12 +13,13 @@ from paper_2009_02171_amd import inputs
 pytestmark = pytest.mark.gpu
 
 
-def _gpu_solve(n, nr, kind, b, sub=None, levels=1, flexible=False, restart=30, maxit=2000, rtol=1e-8, **opkw):
+def _gpu_solve(n, nr, kind, b, sub=None, levels=1, flexible=False, restart=30, maxit=2000, rtol=1e-8, orth=0,
+               **opkw):
     import torch
     from paper_2009_02171_amd import csdyn
     op = csdyn.Operator(n, nr, kind=kind, **opkw)
     pc = csdyn.RAS(op, sub=sub, levels=levels) if sub else None
-    sol = csdyn.Solver(op, pc, restart=restart, maxit=maxit, flexible=flexible, rtol=rtol)
+    sol = csdyn.Solver(op, pc, restart=restart, maxit=maxit, flexible=flexible, rtol=rtol, orth=orth)
     bt = torch.from_numpy(np.ascontiguousarray(b)).cuda()
     x, st, rc = sol.solve(bt)
     torch.cuda.synchronize()
@@ -26,24 +27,25 @@ def _gpu_solve(n, nr, kind, b, sub=None, levels=1, flexible=False, restart=30, m
 
 
 CASES = [
-    # n, nr, kind, sub, levels, flexible
-    (16, 16, 0, (16, 16, 16), 1, False),   # the small configuration: one subdomain per panel
-    (16, 16, 1, (16, 16, 16), 1, False),
-    (16, 16, 0, (8, 8, 8), 2, True),       # two-level hybrid, flexible GMRES
-    (16, 16, 1, (8, 8, 8), 2, True),
-    (8, 8, 1, None, 1, False),             # unpreconditioned
+    # n, nr, kind, sub, levels, flexible, orth
+    (16, 16, 0, (16, 16, 16), 1, False, 0),   # the small configuration: one subdomain per panel
+    (16, 16, 0, (16, 16, 16), 1, False, 1),
+    (16, 16, 1, (16, 16, 16), 1, False, 0),
+    (16, 16, 0, (8, 8, 8), 2, True, 0),       # two-level hybrid, flexible GMRES
+    (16, 16, 1, (8, 8, 8), 2, True, 1),
+    (8, 8, 1, None, 1, False, 0),             # unpreconditioned
 ]
 
 
-@pytest.mark.parametrize("n,nr,kind,sub,levels,flexible", CASES)
-def test_solve_matches_oracle(n, nr, kind, sub, levels, flexible):
-    print(f"[gmres parity] n={n} kind={kind} sub={sub} levels={levels}", flush=True)
+@pytest.mark.parametrize("n,nr,kind,sub,levels,flexible,orth", CASES)
+def test_solve_matches_oracle(n, nr, kind, sub, levels, flexible, orth):
+    print(f"[gmres parity] n={n} kind={kind} sub={sub} levels={levels} orth={orth}", flush=True)
     pb = O.Problem(n, nr, kind=kind)
     b = inputs.rhs(n, nr, seed=0)
     pc = O.Preconditioner(pb, sub=sub, levels=levels) if sub else None
     x_ref, st_ref, rc_ref = O.gmres(pb, b, pc=pc, flexible=flexible, maxit=2000)
     assert rc_ref == 0
-    x, st, rc = _gpu_solve(n, nr, kind, b, sub=sub, levels=levels, flexible=flexible)
+    x, st, rc = _gpu_solve(n, nr, kind, b, sub=sub, levels=levels, flexible=flexible, orth=orth)
     assert rc == 0, st
     assert st["relres_true"] <= 1.0001e-8
     assert abs(st["iters"] - st_ref["iters"]) <= 1, (st, st_ref)
