@@ -109,43 +109,60 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     systems = {"VP": dict(kind=csdyn.VP, seed=1), "BP": dict(kind=csdyn.BP, seed=2)}
-    state = {}
+    forms = {"plain_fp64": 0, "mixed_fp32_pc": 1}
+    state = {f: {} for f in forms}
     for name, s in systems.items():
         t0 = time.perf_counter()
         op = csdyn.Operator(n, nr, kind=s["kind"], dt=1e-4, ekman=1e-3, pm=5.0)
-        pc = csdyn.RAS(op, sub=wl["sub"], levels=wl["levels"], coarse_rtol=0.1, coarse_restart=30, coarse_maxit=200)
-        sol = csdyn.Solver(op, pc, restart=30, maxit=2000, flexible=wl["flexible"], rtol=1e-8)
         b = torch.from_numpy(inputs.rhs(n, nr, s["seed"])).to(dev)
-        x = torch.zeros_like(b)
-        state[name] = dict(op=op, pc=pc, sol=sol, b=b, x=x, info=pc.info())
-        log(f"setup {name}: {time.perf_counter() - t0:.1f} s, info {state[name]['info']}")
+        for form, prec in forms.items():
+            pc = csdyn.RAS(op, sub=wl["sub"], levels=wl["levels"], coarse_rtol=0.1, coarse_restart=30,
+                           coarse_maxit=200, precision=prec)
+            flexible = wl["flexible"] or prec == 1
+            sol = csdyn.Solver(op, pc, restart=30, maxit=2000, flexible=flexible, rtol=1e-8)
+            state[form][name] = dict(op=op, pc=pc, sol=sol, b=b, x=torch.zeros_like(b), info=pc.info())
+        log(f"setup {name}: {time.perf_counter() - t0:.1f} s, info {state['plain_fp64'][name]['info']}")
     torch.cuda.synchronize()
 
-    iters = {}
+    iters = {f: {} for f in forms}
 
-    def step():
-        for name, s in state.items():
+    def step(form):
+        for name, s in state[form].items():
             s["x"].zero_()
             _, st, rc = s["sol"].solve(s["b"], s["x"])
             if rc != 0 or not st["relres_true"] <= 1.0001e-8:
-                raise RuntimeError(f"{name} solve did not converge: rc={rc} {st}")
-            iters[name] = [st["iters"], st["inner_iters"], st["relres_true"]]
+                raise RuntimeError(f"{form} {name} solve did not converge: rc={rc} {st}")
+            iters[form][name] = [st["iters"], st["inner_iters"], st["relres_true"]]
 
-    for w in range(args.warmup):
-        t0 = time.perf_counter()
-        step()
-        torch.cuda.synchronize()
-        log(f"warmup step {w}: {time.perf_counter() - t0:.3f} s, iters {iters}")
+    for form in forms:
+        for w in range(args.warmup):
+            t0 = time.perf_counter()
+            step(form)
+            torch.cuda.synchronize()
+            log(f"warmup {form} step {w}: {time.perf_counter() - t0:.3f} s, iters {iters[form]}")
 
+    # the headline form: plain FP64, every launch timed with HIP events
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     with csdyn.Profile() as prof:
         for k in range(args.steps):
-            step()
+            step("plain_fp64")
         torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    log(f"timed {args.steps} steps in {elapsed:.3f} s, iters {iters}")
+    elapsed = time.perf_counter() - t0
+    log(f"timed plain_fp64: {args.steps} steps in {elapsed:.3f} s, iters {iters['plain_fp64']}")
+    # the mixed-precision form (FP32 inside the preconditioner, FP64 FGMRES)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step("mixed_fp32_pc")
+    torch.cuda.synchronize()
+    elapsed_mixed = time.perf_counter() - t0
+    log(f"timed mixed_fp32_pc: {args.steps} steps in {elapsed_mixed:.3f} s, iters {iters['mixed_fp32_pc']}")
+    err = {}
+    for name in systems:
+        xp, xm = state["plain_fp64"][name]["x"], state["mixed_fp32_pc"][name]["x"]
+        err[name] = float(torch.linalg.norm(xm - xp) / torch.linalg.norm(xp))
+    iters_plain = iters["plain_fp64"]
 
     kernels = {}
     for (name, size), e in sorted(prof.result.items(), key=lambda kv: -kv[1]["ms"]):
@@ -180,7 +197,16 @@ def main():
         "config": {"workload": wl["desc"], "n": n, "nr": nr, "systems": ["VP", "BP"], "subdomain": list(wl["sub"]),
                    "levels": wl["levels"], "krylov": "FGMRES(30)" if wl["flexible"] else "GMRES(30)",
                    "rtol": 1e-8, "form": "plain FP64"},
-        "iters": {k: {"outer": v[0], "inner": v[1], "relres": v[2]} for k, v in iters.items()},
+        "iters": {k: {"outer": v[0], "inner": v[1], "relres": v[2]} for k, v in iters_plain.items()},
+        "forms": {
+            "plain_fp64": {"solves_per_s": round(2 * args.steps / elapsed, 4),
+                           "ms_per_step": round(elapsed / args.steps * 1e3, 3)},
+            "mixed_fp32_pc": {"solves_per_s": round(2 * args.steps / elapsed_mixed, 4),
+                              "ms_per_step": round(elapsed_mixed / args.steps * 1e3, 3),
+                              "iters": {k: {"outer": v[0], "inner": v[1], "relres": v[2]}
+                                        for k, v in iters["mixed_fp32_pc"].items()},
+                              "rel_err_vs_fp64_solution": err},
+        },
         "roofline": {"kernel": f"{dom_name[0]}@{dom_name[1]}", "bound": "hbm", "achieved": round(dom_gbs, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4),
                      "traffic": None,
@@ -190,7 +216,7 @@ def main():
         "kernels": kernels,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.workload, {k: v[:2] for k, v in iters.items()})
+        out["cpu_baseline"] = cpu_baseline(args.workload, {k: v[:2] for k, v in iters_plain.items()})
     print(json.dumps(out))
 
 

@@ -985,11 +985,159 @@ static void twolevel_apply(ref_pc *pc, const double *x, double *y) {
     free(rc); free(ec); free(wv); free(t);
 }
 
+/* ---------------------------------------------- FP32 preconditioner path
+ * Reading for the mixed-precision form: every operation inside M^{-1} runs in
+ * FP32 (C float, FP32 accumulation): the ILU(0) factors are computed in FP64
+ * and rounded to FP32, the sweeps, the restriction and prolongation, the
+ * preconditioner-internal A_f w (matrix entries rounded to FP32) and the
+ * vector operations of the inner coarse GMRES; the inner GMRES's small
+ * Hessenberg least-squares problem stays in FP64.  Input and output of
+ * M^{-1} are FP64. */
+static void csr_mv_f(const csr *a, const float *x, float *y) {
+    for (int64_t i = 0; i < a->nrow; i++) {
+        float acc = 0.0f;
+        for (int64_t q = a->rp[i]; q < a->rp[i + 1]; q++) acc += (float)a->v[q] * x[a->ci[q]];
+        y[i] = acc;
+    }
+}
+
+static void onelevel_apply_f(const onelevel *ol, const float *x, float *y) {
+    int64_t maxrow = 0;
+    for (int s = 0; s < ol->nsd; s++) if (4 * (int64_t)ol->sd[s].nloc > maxrow) maxrow = 4 * (int64_t)ol->sd[s].nloc;
+    float *t = malloc(sizeof(float) * (maxrow + 1));
+    for (int s = 0; s < ol->nsd; s++) {
+        const subdomain *d = &ol->sd[s];
+        int64_t nrow = 4 * (int64_t)d->nloc;
+        for (int l = 0; l < d->nloc; l++)
+            for (int c = 0; c < 4; c++) t[4 * l + c] = x[4 * d->gcell[l] + c];
+        for (int64_t i = 0; i < nrow; i++) {
+            float acc = t[i];
+            for (int64_t q = d->rp[i]; q < d->diag[i]; q++) acc -= (float)d->v[q] * t[d->ci[q]];
+            t[i] = acc;
+        }
+        for (int64_t i = nrow - 1; i >= 0; i--) {
+            float acc = t[i];
+            for (int64_t q = d->diag[i] + 1; q < d->rp[i + 1]; q++) acc -= (float)d->v[q] * t[d->ci[q]];
+            t[i] = acc / (float)d->v[d->diag[i]];
+        }
+        for (int l = 0; l < d->nloc; l++)
+            if (d->owned[l])
+                for (int c = 0; c < 4; c++) y[4 * d->gcell[l] + c] = t[4 * l + c];
+    }
+    free(t);
+}
+
+static float dotf(int64_t n, const float *x, const float *y) { float s = 0.0f; for (int64_t i = 0; i < n; i++) s += x[i] * y[i]; return s; }
+
+/* GMRES(m) right-preconditioned by the FP32 one-level RAS, FP32 vectors
+ * (the coarse solve of the mixed-precision two-level preconditioner). */
+static int gmres_core_f(const csr *A, const onelevel *M, int m, int maxit, double rtol, const float *b, float *x,
+                        int *iters_out) {
+    int64_t n = A->nrow;
+    float *V = malloc(sizeof(float) * n * (m + 1)), *w = malloc(sizeof(float) * n), *z = malloc(sizeof(float) * n);
+    float *r = malloc(sizeof(float) * n);
+    double *H = calloc((size_t)(m + 1) * m, sizeof(double)), *cs = malloc(sizeof(double) * m), *sn = malloc(sizeof(double) * m);
+    double *gv = malloc(sizeof(double) * (m + 1)), *yv = malloc(sizeof(double) * m);
+    csr_mv_f(A, x, r);
+    for (int64_t i = 0; i < n; i++) r[i] = b[i] - r[i];
+    double beta0 = sqrt((double)dotf(n, r, r)), tol = rtol * beta0;
+    int iters = 0, conv = beta0 <= tol;
+    while (!conv && iters < maxit) {
+        double beta = sqrt((double)dotf(n, r, r));
+        for (int64_t i = 0; i < n; i++) V[i] = (float)(r[i] / beta);
+        for (int a = 0; a <= m; a++) gv[a] = 0.0;
+        gv[0] = beta;
+        int jdone = 0;
+        for (int j = 0; j < m && iters < maxit; j++) {
+            onelevel_apply_f(M, V + (int64_t)j * n, z);
+            csr_mv_f(A, z, w);
+            double anorm = sqrt((double)dotf(n, w, w));
+            for (int i = 0; i <= j; i++) {
+                float h = dotf(n, w, V + (int64_t)i * n);
+                H[i * m + j] = h;
+                for (int64_t q = 0; q < n; q++) w[q] -= h * V[(int64_t)i * n + q];
+            }
+            double hn = sqrt((double)dotf(n, w, w));
+            H[(j + 1) * m + j] = hn;
+            iters++;
+            jdone = j + 1;
+            for (int i = 0; i < j; i++) {
+                double t1 = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
+                double t2 = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
+                H[i * m + j] = t1; H[(i + 1) * m + j] = t2;
+            }
+            double a = H[j * m + j], bb = H[(j + 1) * m + j], den = hypot(a, bb);
+            cs[j] = a / den; sn[j] = bb / den;
+            H[j * m + j] = den; H[(j + 1) * m + j] = 0.0;
+            gv[j + 1] = -sn[j] * gv[j];
+            gv[j] = cs[j] * gv[j];
+            int happy = hn <= 1e-14 * anorm;
+            if (!happy) for (int64_t q = 0; q < n; q++) V[(int64_t)(j + 1) * n + q] = (float)(w[q] / hn);
+            if (fabs(gv[j + 1]) <= tol || happy) { conv = 1; break; }
+        }
+        for (int i = jdone - 1; i >= 0; i--) {
+            double s2 = gv[i];
+            for (int k = i + 1; k < jdone; k++) s2 -= H[i * m + k] * yv[k];
+            yv[i] = s2 / H[i * m + i];
+        }
+        for (int64_t q = 0; q < n; q++) w[q] = 0.0f;
+        for (int i = 0; i < jdone; i++) for (int64_t q = 0; q < n; q++) w[q] += (float)yv[i] * V[(int64_t)i * n + q];
+        onelevel_apply_f(M, w, z);
+        for (int64_t q = 0; q < n; q++) x[q] += z[q];
+        csr_mv_f(A, x, r);
+        for (int64_t i = 0; i < n; i++) r[i] = b[i] - r[i];
+    }
+    *iters_out = iters;
+    free(V); free(w); free(z); free(r); free(H); free(cs); free(sn); free(gv); free(yv);
+    return conv ? REF_OK : REF_ENOTCONV;
+}
+
+static void twolevel_apply_f(ref_pc *pc, const double *xd, double *yd) {
+    const ref_grid *g = &pc->g, *gc = &pc->gc;
+    int n = g->n, nc = gc->n;
+    int64_t ncc = 6 * (int64_t)nc * nc * gc->nr, nf = 24 * (int64_t)n * n * g->nr;
+    float *x = malloc(sizeof(float) * nf), *y = malloc(sizeof(float) * nf);
+    float *rc = calloc(4 * ncc, sizeof(float)), *ec = calloc(4 * ncc, sizeof(float));
+    float *wv = malloc(sizeof(float) * nf), *t = malloc(sizeof(float) * nf);
+    for (int64_t q = 0; q < nf; q++) x[q] = (float)xd[q];
+    for (int p = 0; p < 6; p++)
+        for (int K = 0; K < gc->nr; K++)
+            for (int J = 0; J < nc; J++)
+                for (int I = 0; I < nc; I++)
+                    for (int c = 0; c < 4; c++) {
+                        float s2 = 0.0f;
+                        for (int dk = 0; dk < 2; dk++) for (int dj = 0; dj < 2; dj++) for (int di = 0; di < 2; di++)
+                            s2 += x[unk(g, p, 2 * I + di, 2 * J + dj, 2 * K + dk, c)];
+                        rc[unk(gc, p, I, J, K, c)] = s2 * 0.125f;
+                    }
+    if (pc->op.kind == 0) {
+        float sv = 0.0f, v = 0.0f;
+        for (int64_t c = 0; c < ncc; c++) { sv += (float)pc->vc[c] * rc[4 * c + 3]; v += (float)pc->vc[c]; }
+        float mean = sv / v;
+        for (int64_t c = 0; c < ncc; c++) rc[4 * c + 3] -= mean;
+    }
+    int it = 0;
+    gmres_core_f(&pc->Ac, pc->coarse, pc->coarse_restart, pc->coarse_maxit, pc->coarse_rtol, rc, ec, &it);
+    pc->inner_iters += it;
+    for (int p = 0; p < 6; p++)
+        for (int k = 0; k < g->nr; k++)
+            for (int j = 0; j < n; j++)
+                for (int i = 0; i < n; i++)
+                    for (int c = 0; c < 4; c++)
+                        wv[unk(g, p, i, j, k, c)] = ec[unk(gc, p, i / 2, j / 2, k / 2, c)];
+    csr_mv_f(&pc->Af, wv, t);
+    for (int64_t q = 0; q < nf; q++) t[q] = x[q] - t[q];
+    onelevel_apply_f(pc->fine, t, y);
+    for (int64_t q = 0; q < nf; q++) yd[q] = (double)(y[q] + wv[q]);
+    free(x); free(y); free(rc); free(ec); free(wv); free(t);
+}
+
 static void pc_apply(ref_pc *pc, const double *x, double *y) {
     int64_t n = 24 * (int64_t)pc->g.n * pc->g.n * pc->g.nr;
     if (pc->levels == 0) { memcpy(y, x, sizeof(double) * n); return; }
     if (pc->levels == 1) { onelevel_apply(pc->fine, x, y); return; }
-    twolevel_apply(pc, x, y);
+    if (pc->precision == 1) twolevel_apply_f(pc, x, y);
+    else twolevel_apply(pc, x, y);
 }
 
 /* ------------------------------------------------- exported: preconditioner */

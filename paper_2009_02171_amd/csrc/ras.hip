@@ -404,12 +404,16 @@ struct HostBuild {
     HostGeom gc;
 };
 
+// One cached host build; the key ignores the precision (the FP64 and FP32
+// preconditioners of one operator share the assembly and factorization).
 static std::mutex g_cache_mu;
-static std::unique_ptr<HostBuild> g_cache;
+static std::shared_ptr<HostBuild> g_cache;
 
 static bool same_key(const HostBuild &b, const csdyn_grid &g, const csdyn_op &op, const csdyn_ras_opts &o) {
+    csdyn_ras_opts a = b.o, c = o;
+    a.precision = c.precision = 0;
     return std::memcmp(&b.g, &g, sizeof(g)) == 0 && std::memcmp(&b.op, &op, sizeof(op)) == 0 &&
-           std::memcmp(&b.o, &o, sizeof(o)) == 0;
+           std::memcmp(&a, &c, sizeof(a)) == 0;
 }
 
 static int32_t check_opts(const csdyn_opctx *ctx, const csdyn_ras_opts *o) {
@@ -429,8 +433,8 @@ static int32_t check_opts(const csdyn_opctx *ctx, const csdyn_ras_opts *o) {
     return CSDYN_OK;
 }
 
-static int32_t host_build(const csdyn_opctx *ctx, const csdyn_ras_opts *o, std::unique_ptr<HostBuild> &out) {
-    auto b = std::make_unique<HostBuild>();
+static int32_t host_build(const csdyn_opctx *ctx, const csdyn_ras_opts *o, std::shared_ptr<HostBuild> &out) {
+    auto b = std::make_shared<HostBuild>();
     b->g = ctx->g; b->op = ctx->op; b->o = *o;
     CSD_TRY(build_host_ras(ctx->hg, ctx->op, o->sub, o->overlap, b->fine));
     if (o->levels == 2) {
@@ -466,18 +470,18 @@ struct csdyn_ras {
     int32_t two_level(const T *x, T *y, hipStream_t s) const;
 };
 
-static void layout_all(Carver &c, const HostBuild &b, csdyn_ras &R) {
-    OneLevel::layout(c, b.fine, b.o.precision, R.fine);
-    if (b.o.levels == 2) {
-        const size_t fs = b.o.precision ? sizeof(float) : sizeof(double);
+static void layout_all(Carver &c, const HostBuild &b, const csdyn_ras_opts &o, csdyn_ras &R) {
+    OneLevel::layout(c, b.fine, o.precision, R.fine);
+    if (o.levels == 2) {
+        const size_t fs = o.precision ? sizeof(float) : sizeof(double);
         const int64_t nf = 24 * int64_t(b.g.n) * b.g.n * b.g.nr;
         const int64_t nc = 24 * int64_t(b.gc.n) * b.gc.n * b.gc.nr;
         R.nf = nf; R.nc = nc;
         void *cg = c.take<char>(devgeom_bytes(b.gc.n, b.gc.nr));
         R.coarse_ctx.ws = cg;
-        OneLevel::layout(c, b.coarse, b.o.precision, R.coarse);
-        const size_t gb = b.o.precision ? Gmres<float>::bytes(nc, b.o.coarse_restart, false)
-                                        : Gmres<double>::bytes(nc, b.o.coarse_restart, false);
+        OneLevel::layout(c, b.coarse, o.precision, R.coarse);
+        const size_t gb = o.precision ? Gmres<float>::bytes(nc, o.coarse_restart, false)
+                                        : Gmres<double>::bytes(nc, o.coarse_restart, false);
         R.cws = c.take<char>(gb);
         // fine: x32, w, t, y32 ; coarse: rc, ec ; FP32 edge buffers for the fine operator
         R.buf = c.take<char>(4 * nf * fs + 2 * nc * fs + 2 * size_t(24) * b.g.nr * b.g.n * 8 * fs + 1024);
@@ -495,7 +499,7 @@ extern "C" int32_t csdyn_ras_workspace_bytes(const csdyn_opctx *ctx, const csdyn
     }
     csdyn_ras R;
     Carver c(nullptr);
-    layout_all(c, *g_cache, R);
+    layout_all(c, *g_cache, *o, R);
     *bytes = c.off + 256;
     return CSDYN_OK;
 }
@@ -506,17 +510,20 @@ extern "C" int32_t csdyn_ras_setup(const csdyn_opctx *ctx, const csdyn_ras_opts 
     if (!ws || !out) { set_error("ras: null argument"); return CSDYN_EINVAL; }
     *out = nullptr;
     CSD_TRY(check_opts(ctx, o));
-    std::unique_ptr<HostBuild> b;
+    std::shared_ptr<HostBuild> b;
     {
         std::lock_guard<std::mutex> lk(g_cache_mu);
-        if (g_cache && same_key(*g_cache, ctx->g, ctx->op, *o)) b = std::move(g_cache);
+        if (!g_cache || !same_key(*g_cache, ctx->g, ctx->op, *o)) {
+            g_cache.reset();
+            CSD_TRY(host_build(ctx, o, g_cache));
+        }
+        b = g_cache;
     }
-    if (!b) CSD_TRY(host_build(ctx, o, b));
     auto R = std::make_unique<csdyn_ras>();
     R->o = *o;
     R->fine_ctx = ctx;
     Carver c(ws);
-    layout_all(c, *b, *R);
+    layout_all(c, *b, *o, *R);
     if (c.off + 256 > ws_bytes) { set_error("ras: workspace %zu < %zu bytes", ws_bytes, c.off + 256); return CSDYN_ENOMEM; }
     R->info = csdyn_ras_info{};
     auto fill = [](const HostRas &H, int32_t &nsd, int64_t &nnz, int64_t &box, int64_t &own, int64_t &stored, int32_t &lv) {

@@ -14,11 +14,11 @@ pytestmark = pytest.mark.gpu
 
 
 def _gpu_solve(n, nr, kind, b, sub=None, levels=1, flexible=False, restart=30, maxit=2000, rtol=1e-8, orth=0,
-               **opkw):
+               precision=0, **opkw):
     import torch
     from paper_2009_02171_amd import csdyn
     op = csdyn.Operator(n, nr, kind=kind, **opkw)
-    pc = csdyn.RAS(op, sub=sub, levels=levels) if sub else None
+    pc = csdyn.RAS(op, sub=sub, levels=levels, precision=precision) if sub else None
     sol = csdyn.Solver(op, pc, restart=restart, maxit=maxit, flexible=flexible, rtol=rtol, orth=orth)
     bt = torch.from_numpy(np.ascontiguousarray(b)).cuda()
     x, st, rc = sol.solve(bt)
@@ -67,3 +67,21 @@ def test_solve_status_codes():
     with pytest.raises(csdyn.CsdynError) as e:
         _gpu_solve(8, 4, 1, bn)
     assert e.value.status == csdyn.EBREAKDOWN
+
+
+@pytest.mark.parametrize("kind,levels", [(0, 1), (0, 2), (1, 2)])
+def test_mixed_precision_solve(kind, levels):
+    """FP32 preconditioner inside FP64 FGMRES(30): still reaches 1e-8; iterations
+    within one of the oracle's mixed solve; solution within 1e-7 of the FP64 oracle."""
+    n, nr, sub = 16, 16, (8, 8, 8)
+    print(f"[mixed solve] kind={kind} levels={levels}", flush=True)
+    pb = O.Problem(n, nr, kind=kind)
+    b = inputs.rhs(n, nr, seed=0)
+    x64, _, _ = O.gmres(pb, b, pc=O.Preconditioner(pb, sub=sub, levels=levels), flexible=True)
+    xm, stm, _ = O.gmres(pb, b, pc=O.Preconditioner(pb, sub=sub, levels=levels, precision=1), flexible=True)
+    x, st, rc = _gpu_solve(n, nr, kind, b, sub=sub, levels=levels, flexible=True, precision=1)
+    assert rc == 0 and st["relres_true"] <= 1.0001e-8
+    assert abs(st["iters"] - stm["iters"]) <= 1, (st, stm)
+    err = np.linalg.norm(x - x64) / np.linalg.norm(x64)
+    print(f"  iterations {st['iters']} (oracle mixed {stm['iters']}), error vs FP64 oracle {err:.2e}")
+    assert err <= 1e-7

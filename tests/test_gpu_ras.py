@@ -85,3 +85,27 @@ def test_ras_rejects_bad_options():
         csdyn.RAS(op, sub=(5, 4, 3))
     with pytest.raises(csdyn.CsdynError):
         csdyn.RAS(op, sub=(6, 6, 3), levels=2)   # odd subdomain size for two levels
+
+
+@pytest.mark.parametrize("n,nr,kind,sub", [(8, 4, 0, (4, 4, 2)), (16, 16, 1, (16, 16, 16)), (24, 8, 0, (8, 8, 4))])
+def test_one_level_fp32_matches_oracle_emulation(n, nr, kind, sub):
+    """FP32 factors and sweeps: GPU against the oracle's FP32 emulation."""
+    print(f"[ras fp32 parity] n={n} nr={nr} kind={kind}", flush=True)
+    pb = O.Problem(n, nr, kind=kind)
+    x = inputs.random_field(pb.shape(), seed=51 + n)
+    y_ref = O.Preconditioner(pb, sub=sub, levels=1, precision=1).apply(x)
+    _, pc = _setup(n, nr, kind, sub, precision=1)
+    y = _apply(pc, x)
+    assert np.abs(y - y_ref).max() / np.abs(y_ref).max() <= 1e-5
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_two_level_fp32_matches_oracle_emulation(kind):
+    n, nr, sub = 16, 8, (8, 8, 4)
+    print(f"[two-level fp32 parity] kind={kind}", flush=True)
+    pb = O.Problem(n, nr, kind=kind)
+    x = inputs.random_field(pb.shape(), seed=61 + kind)
+    y_ref = O.Preconditioner(pb, sub=sub, levels=2, precision=1).apply(x)
+    _, pc = _setup(n, nr, kind, sub, levels=2, precision=1)
+    y = _apply(pc, x)
+    assert np.abs(y - y_ref).max() / np.abs(y_ref).max() <= 1e-4

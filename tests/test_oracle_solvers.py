@@ -153,3 +153,20 @@ def test_fgmres_two_level_reaches_tolerance():
     bb = O.project_pressure(pb, b)
     r = bb - O.apply(pb, x)
     assert np.linalg.norm(r) <= 1.01e-8 * np.linalg.norm(bb)
+
+
+def test_fp32_preconditioner_emulation():
+    """FP32 inside M^{-1}: the one-level apply stays within FP32 rounding of the
+    FP64 apply, and the flexible solve still reaches 1e-8 at the FP64 solution."""
+    pb = O.Problem(8, 8, kind=0)
+    x = inputs.random_field(pb.shape(), seed=4)
+    y64 = O.Preconditioner(pb, sub=(4, 4, 4), levels=1).apply(x)
+    y32 = O.Preconditioner(pb, sub=(4, 4, 4), levels=1, precision=1).apply(x)
+    rel = np.abs(y32 - y64).max() / np.abs(y64).max()
+    assert 1e-9 < rel < 1e-4
+    b = inputs.rhs(8, 8, seed=0)
+    x64, s64, _ = O.gmres(pb, b, pc=O.Preconditioner(pb, sub=(4, 4, 4), levels=2), flexible=True)
+    x32, s32, rc = O.gmres(pb, b, pc=O.Preconditioner(pb, sub=(4, 4, 4), levels=2, precision=1), flexible=True)
+    assert rc == 0 and s32["relres_true"] <= 1.0001e-8
+    assert abs(s32["iters"] - s64["iters"]) <= 1
+    assert np.linalg.norm(x32 - x64) <= 1e-7 * np.linalg.norm(x64)
