@@ -90,6 +90,19 @@ int32_t csdyn_op_setup(const csdyn_grid *g, const csdyn_op *op, void *ws, size_t
 int32_t csdyn_operator_apply(const csdyn_opctx *ctx, const double *x, double *y, void *stream);
 void csdyn_op_destroy(csdyn_opctx *ctx);
 
+/* Step 3 of the time step (Sec. 3.1, eq. ubtilde) from a solution
+ * x = (u~, P) of the VP system (or (B~, P_b) of BP):
+ *   out[c] = x[c] - dt (grad_h P)[c],  c = 0..2  (cell-centred gradient:
+ *            sum_m g^m dP/dq^m with central differences; panel-edge ghosts
+ *            and wall ghosts as in the operator),
+ *   out[3] = D_f F: the finite-volume divergence of the corrected face
+ *            fluxes F = (flux of u~) - dt (face gradient flux of P), which is
+ *            the pressure row of A x; it is zero at faces when the pressure
+ *            rows of A x = b hold with b_P = 0.
+ * x and out are device vectors in the layout above and must not alias;
+ * asynchronous on `stream`. */
+int32_t csdyn_project(const csdyn_opctx *ctx, const double *x, double *out, void *stream);
+
 /* ---------------------------------------------------------- preconditioner
  * Restricted additive Schwarz (eq. onelevel): each panel is cut into
  * (N/sub[0]) x (N/sub[1]) x (Nr/sub[2]) boxes; each box is extended by

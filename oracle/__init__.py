@@ -81,6 +81,7 @@ def lib():
         _lib.ref_pc_count.argtypes = [C.c_void_p, C.c_int]
         _lib.ref_ilu0_csr.argtypes = [C.c_int64, i64, i32, d]
         _lib.ref_subdomain_solve.argtypes = [P(Grid), P(Op), i32, C.c_int, C.c_int, d, d]
+        _lib.ref_project.argtypes = [P(Grid), P(Op), d, d]
         _lib.ref_gmres_solve.argtypes = [P(Grid), P(Op), C.c_void_p, P(GmresOpts), d, d, P(GmresStats)]
     return _lib
 
@@ -177,6 +178,14 @@ def apply_rows(pb: Problem, x: np.ndarray, rows: np.ndarray) -> np.ndarray:
     _check(lib().ref_operator_rows(C.byref(pb.grid()), C.byref(pb.op()), _dp(x), rows.size, _lp(rows), _dp(y)),
            "apply_rows")
     return y
+
+
+def project(pb: Problem, x: np.ndarray) -> np.ndarray:
+    """Step 3 (Sec. 3.1): (u~ - dt grad_h P, D_f F) from a solution x = (u~, P)."""
+    x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
+    out = np.zeros_like(x)
+    _check(lib().ref_project(C.byref(pb.grid()), C.byref(pb.op()), _dp(x), _dp(out)), "project")
+    return out.reshape(pb.shape())
 
 
 def assemble(pb: Problem):

@@ -1262,3 +1262,38 @@ int ref_subdomain_solve(const ref_grid *g, const ref_op *op, const int32_t sub[3
     free_seams(&st);
     return rc;
 }
+
+/* Step 3 of the time step (Sec. 3.1, eq. ubtilde): from a solution x = (u~, P)
+ * return out = (u~ - dt * grad_h P, D_f F) where grad_h P at a cell centre is
+ * sum_m g^m (dP/dq^m) with central differences (ghosts across panel edges and
+ * walls as in the operator), and D_f F is the finite-volume divergence of the
+ * corrected face fluxes F = (flux of u~) - dt (face gradient flux of P), i.e.
+ * the pressure row of A x; it vanishes when the P-rows of A x = b hold with
+ * b_P = 0 (discrete divergence-free at faces). */
+int ref_project(const ref_grid *g, const ref_op *op, const double *x, double *out) {
+    seam_tab st; ctx cx;
+    int rc = make_ctx(g, op, &st, &cx);
+    if (rc) return rc;
+    sink s = {0}; s.mode = 1; s.x = x;
+    int n = g->n;
+    double h = hs_of(g), hr = hr_of(g);
+    for (int p = 0; p < 6; p++)
+        for (int k = 0; k < g->nr; k++)
+            for (int j = 0; j < n; j++)
+                for (int i = 0; i < n; i++) {
+                    double d[3];
+                    s.acc = 0; emit_x(&cx, &s, p, i + 1, j, k, 3, 0.5 / h); emit_x(&cx, &s, p, i - 1, j, k, 3, -0.5 / h); d[0] = s.acc;
+                    s.acc = 0; emit_x(&cx, &s, p, i, j + 1, k, 3, 0.5 / h); emit_x(&cx, &s, p, i, j - 1, k, 3, -0.5 / h); d[1] = s.acc;
+                    s.acc = 0; emit_x(&cx, &s, p, i, j, k + 1, 3, 0.5 / hr); emit_x(&cx, &s, p, i, j, k - 1, 3, -0.5 / hr); d[2] = s.acc;
+                    metric m; metric_at(p, xi_of(g, i), xi_of(g, j), r_of(g, k), &m);
+                    for (int c = 0; c < 3; c++) {
+                        double gr = d[0] * m.gcon[0][c] + d[1] * m.gcon[1][c] + d[2] * m.gcon[2][c];
+                        out[unk(g, p, i, j, k, c)] = x[unk(g, p, i, j, k, c)] - op->dt * gr;
+                    }
+                    s.acc = 0;
+                    emit_row(&cx, &s, p, i, j, k, 3);
+                    out[unk(g, p, i, j, k, 3)] = s.acc;
+                }
+    free_seams(&st);
+    return REF_OK;
+}

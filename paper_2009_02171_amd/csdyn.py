@@ -66,6 +66,7 @@ SIGNATURES = {
     "csdyn_op_setup": (C.c_int32, [_P(Grid), _P(OpDesc), C.c_void_p, C.c_size_t, C.c_void_p, _P(C.c_void_p)]),
     "csdyn_operator_apply": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "csdyn_op_destroy": (None, [C.c_void_p]),
+    "csdyn_project": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "csdyn_ras_workspace_bytes": (C.c_int32, [C.c_void_p, _P(RasOpts), _P(C.c_size_t)]),
     "csdyn_ras_setup": (C.c_int32, [C.c_void_p, _P(RasOpts), C.c_void_p, C.c_size_t, C.c_void_p, _P(C.c_void_p)]),
     "csdyn_ras_apply": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -155,6 +156,12 @@ class Operator:
         y = self.empty() if y is None else y
         _check(lib().csdyn_operator_apply(self.h, _ptr(x), _ptr(y), _stream(stream)), "csdyn_operator_apply")
         return y
+
+    def project(self, x: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+        """Step 3: (u~ - dt grad_h P, divergence of the corrected face fluxes)."""
+        out = self.empty() if out is None else out
+        _check(lib().csdyn_project(self.h, _ptr(x), _ptr(out), _stream(stream)), "csdyn_project")
+        return out
 
     def __del__(self):
         h = getattr(self, "h", None)

@@ -69,7 +69,7 @@ struct HostGeom {
     std::vector<GhostEntry> ghost;  // [6][4][n]
     std::vector<FaceEntry> face;    // [6][4][n]
     // metric tables, same layout as DevGeom
-    std::vector<double> a11x, a12x, a22y, a12y, sc, t1, t2, nrm, rk, rf, vol;
+    std::vector<double> a11x, a12x, a22y, a12y, sc, t1, t2, nrm, gc1, gc2, rk, rf, vol;
     int32_t build(const csdyn_grid &g);
     size_t nf() const { return size_t(n) * (n + 1); }
     double ang(double i) const { return -0.78539816339744830962 + (i + 0.5) * hs; }
@@ -88,6 +88,7 @@ struct DevGeom {
     double *t1;           // [6][n][n+1][3]  sqrt(g) g^1 / r at xi-faces, global frame
     double *t2;           // [6][n+1][n][3]  sqrt(g) g^2 / r at eta-faces
     double *nrm;          // [6][n][n][3]    unit radial at cell centres
+    double *gc1, *gc2;    // [6][n][n][3]    r g^1, r g^2 at cell centres (dual basis, global frame)
     double *rk;           // [nr]     r_k
     double *rf;           // [nr+1]   r_{k-1/2}
     int *gh_i;            // [6][4][n][4]  q, fix_i, idx, m0

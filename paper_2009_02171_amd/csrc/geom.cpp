@@ -9,7 +9,8 @@
 //   sqrt(g) g^12       = X Y / rho                          (r-independent)
 //   sqrt(g) g^1        = r (1+Y^2)(-X, 1, 0)/rho^2
 //   sqrt(g) g^2        = r (1+X^2)(-Y, 0, 1)/rho^2
-//   g^3 = g_3          = (1, X, Y)/rho.
+//   g^3 = g_3          = (1, X, Y)/rho,
+//   r g^1 = rho (-X, 1, 0)/(1+X^2),  r g^2 = rho (-Y, 0, 1)/(1+Y^2).
 // All six panels share the scalar tables; the vector tables are rotated by
 // the panel's orientation.
 #include <cmath>
@@ -119,6 +120,7 @@ int32_t HostGeom::build(const csdyn_grid &g) {
     const size_t nf = this->nf();
     a11x.assign(nf, 0); a12x.assign(nf, 0); a22y.assign(nf, 0); a12y.assign(nf, 0); sc.assign(size_t(n) * n, 0);
     t1.assign(6 * nf * 3, 0); t2.assign(6 * nf * 3, 0); nrm.assign(6 * size_t(n) * n * 3, 0);
+    gc1.assign(6 * size_t(n) * n * 3, 0); gc2.assign(6 * size_t(n) * n * 3, 0);
     rk.assign(nr, 0); rf.assign(nr + 1, 0); vol.assign(6 * size_t(nr) * n * n, 0);
     auto face_x = [&](int j, int fi, double &X, double &Y) { X = std::tan(-qpi + fi * hs); Y = std::tan(ang(j)); };
     auto face_y = [&](int fj, int i, double &X, double &Y) { X = std::tan(ang(i)); Y = std::tan(-qpi + fj * hs); };
@@ -148,7 +150,14 @@ int32_t HostGeom::build(const csdyn_grid &g) {
             double rho2 = 1 + X * X + Y * Y, rho = std::sqrt(rho2);
             sc[size_t(j) * n + i] = (1 + X * X) * (1 + Y * Y) / (rho2 * rho);
             double loc[3] = {1.0 / rho, X / rho, Y / rho};
-            for (int p = 0; p < 6; ++p) to_global(p, loc, &nrm[((size_t(p) * n + j) * n + i) * 3]);
+            double l1[3] = {-X * rho / (1 + X * X), rho / (1 + X * X), 0.0};
+            double l2[3] = {-Y * rho / (1 + Y * Y), 0.0, rho / (1 + Y * Y)};
+            for (int p = 0; p < 6; ++p) {
+                const size_t a = ((size_t(p) * n + j) * n + i) * 3;
+                to_global(p, loc, &nrm[a]);
+                to_global(p, l1, &gc1[a]);
+                to_global(p, l2, &gc2[a]);
+            }
         }
     for (int k = 0; k < nr; ++k) rk[k] = rad(k);
     for (int k = 0; k <= nr; ++k) rf[k] = ri + k * hr;
@@ -166,6 +175,7 @@ size_t devgeom_bytes(int n, int nr) {
     c.take<double>(nf); c.take<double>(nf); c.take<double>(nf); c.take<double>(nf);
     c.take<double>(size_t(n) * n);
     c.take<double>(6 * nf * 3); c.take<double>(6 * nf * 3); c.take<double>(6 * size_t(n) * n * 3);
+    c.take<double>(6 * size_t(n) * n * 3); c.take<double>(6 * size_t(n) * n * 3);
     c.take<double>(nr); c.take<double>(nr + 1);
     c.take<int>(24 * size_t(n) * 4); c.take<double>(24 * size_t(n) * 4); c.take<int>(24 * size_t(n) * 4);
     c.take<double>(6 * size_t(nr) * n * n);
@@ -184,6 +194,8 @@ int32_t devgeom_setup(const HostGeom &hg, void *ws, DevGeom *o) {
     o->sc = c.take<double>(size_t(n) * n);
     o->t1 = c.take<double>(6 * nf * 3); o->t2 = c.take<double>(6 * nf * 3);
     o->nrm = c.take<double>(6 * size_t(n) * n * 3);
+    o->gc1 = c.take<double>(6 * size_t(n) * n * 3);
+    o->gc2 = c.take<double>(6 * size_t(n) * n * 3);
     o->rk = c.take<double>(nr); o->rf = c.take<double>(nr + 1);
     o->gh_i = c.take<int>(24 * size_t(n) * 4); o->gh_w = c.take<double>(24 * size_t(n) * 4);
     o->fc = c.take<int>(24 * size_t(n) * 4);
@@ -201,11 +213,12 @@ int32_t devgeom_setup(const HostGeom &hg, void *ws, DevGeom *o) {
         fcv[4 * a] = F.q; fcv[4 * a + 1] = F.e; fcv[4 * a + 2] = F.t; fcv[4 * a + 3] = 0;
     }
     const std::vector<double> &a11x = hg.a11x, &a12x = hg.a12x, &a22y = hg.a22y, &a12y = hg.a12y, &sc = hg.sc,
-                              &t1 = hg.t1, &t2 = hg.t2, &nrm = hg.nrm, &rk = hg.rk, &rf = hg.rf, &vol = hg.vol;
+                              &t1 = hg.t1, &t2 = hg.t2, &nrm = hg.nrm, &rk = hg.rk, &rf = hg.rf, &vol = hg.vol,
+                              &gc1 = hg.gc1, &gc2 = hg.gc2;
     auto up = [](void *dst, const void *src, size_t bytes) { return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice); };
 #define UP(dst, vec) CSD_HIP(up(dst, vec.data(), vec.size() * sizeof(vec[0])))
     UP(o->a11x, a11x); UP(o->a12x, a12x); UP(o->a22y, a22y); UP(o->a12y, a12y); UP(o->sc, sc);
-    UP(o->t1, t1); UP(o->t2, t2); UP(o->nrm, nrm); UP(o->rk, rk); UP(o->rf, rf);
+    UP(o->t1, t1); UP(o->t2, t2); UP(o->nrm, nrm); UP(o->rk, rk); UP(o->rf, rf); UP(o->gc1, gc1); UP(o->gc2, gc2);
     UP(o->gh_i, ghi); UP(o->gh_w, ghw); UP(o->fc, fcv); UP(o->vol, vol);
 #undef UP
     return CSDYN_OK;

@@ -318,6 +318,33 @@ static int32_t launch_all(const csdyn_opctx *ctx, const T *x, T *y, T *G, T *SF,
     return CSDYN_OK;
 }
 
+// Step 3 (Sec. 3.1): out_c = x_c - dt (grad_h P)_c for c < 3, with central
+// differences of P (ghosts from the operator's edge buffer, wall ghosts by the
+// operator's rules) and the dual basis at the cell centre; out_3 was set by the
+// operator (the divergence of the corrected face fluxes).
+__global__ void k_project(DevGeom g, int kind, double dt, const double *__restrict__ x, const double *__restrict__ G,
+                          double *__restrict__ out) {
+    const int n = g.n, nr = g.nr;
+    const int64_t ncell = 6 * int64_t(n) * n * nr;
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    const int i = int(c % n), j = int((c / n) % n), k = int((c / (int64_t(n) * n)) % nr);
+    const int p = int(c / (int64_t(n) * n * nr));
+    const double pc = x[4 * c + 3];
+    const double pip = fetch_ext(g, x, G, p, i + 1, j, k).c[3], pim = fetch_ext(g, x, G, p, i - 1, j, k).c[3];
+    const double pjp = fetch_ext(g, x, G, p, i, j + 1, k).c[3], pjm = fetch_ext(g, x, G, p, i, j - 1, k).c[3];
+    const double wall = kind == CSDYN_VP ? pc : -pc;
+    const double pkp = k + 1 < nr ? x[4 * (c + int64_t(n) * n) + 3] : wall;
+    const double pkm = k > 0 ? x[4 * (c - int64_t(n) * n) + 3] : wall;
+    const double d1 = (pip - pim) * 0.5 / g.hs, d2 = (pjp - pjm) * 0.5 / g.hs, d3 = (pkp - pkm) * 0.5 / g.hr;
+    const double ir = 1.0 / g.rk[k];
+    const size_t a = ((size_t(p) * n + j) * n + i) * 3;
+    for (int d = 0; d < 3; ++d) {
+        const double gr = (d1 * g.gc1[a + d] + d2 * g.gc2[a + d]) * ir + d3 * g.nrm[a + d];
+        out[4 * c + d] = x[4 * c + d] - dt * gr;
+    }
+}
+
 int32_t op_launch(const csdyn_opctx *ctx, const double *x, double *y, hipStream_t s) {
     return launch_all<double>(ctx, x, y, ctx->dg.G, ctx->dg.SF, s);
 }
@@ -371,6 +398,21 @@ extern "C" int32_t csdyn_operator_apply(const csdyn_opctx *ctx, const double *x,
     const char *xa = (const char *)x, *ya = (const char *)y;
     if (xa < ya + nb && ya < xa + nb) { set_error("csdyn_operator_apply: x and y alias"); return CSDYN_EINVAL; }
     return op_launch(ctx, x, y, (hipStream_t)stream);
+}
+
+extern "C" int32_t csdyn_project(const csdyn_opctx *ctx, const double *x, double *out, void *stream) {
+    clear_error();
+    if (!ctx || !x || !out) { set_error("csdyn_project: null argument"); return CSDYN_EINVAL; }
+    const size_t nb = size_t(24) * ctx->g.n * ctx->g.n * ctx->g.nr * sizeof(double);
+    const char *xa = (const char *)x, *oa = (const char *)out;
+    if (xa < oa + nb && oa < xa + nb) { set_error("csdyn_project: x and out alias"); return CSDYN_EINVAL; }
+    hipStream_t s = (hipStream_t)stream;
+    CSD_TRY(op_launch(ctx, x, out, s));  // out_3 = divergence of the corrected fluxes; fills the ghost buffer
+    const int64_t ncell = 6 * int64_t(ctx->g.n) * ctx->g.n * ctx->g.nr;
+    hipLaunchKernelGGL(k_project, dim3(unsigned((ncell + 255) / 256)), dim3(256), 0, s, ctx->dg, ctx->op.kind,
+                       ctx->op.dt, x, (const double *)ctx->dg.G, out);
+    CSD_HIP(hipGetLastError());
+    return CSDYN_OK;
 }
 
 extern "C" void csdyn_op_destroy(csdyn_opctx *ctx) { delete ctx; }

@@ -74,3 +74,17 @@ def test_operator_rejects_aliasing():
     x = torch.zeros(op.shape, dtype=torch.float64, device="cuda")
     with pytest.raises(csdyn.CsdynError):
         op.apply(x, x)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_project_matches_oracle(kind):
+    """Step 3 (Sec. 3.1): u~ - dt grad_h P and the corrected face divergence."""
+    import torch
+    from paper_2009_02171_amd import csdyn
+    n, nr = 16, 8
+    pb = O.Problem(n, nr, kind=kind, dt=1e-2)
+    x = inputs.random_field(pb.shape(), seed=70 + kind)
+    ref = O.project(pb, x)
+    op = csdyn.Operator(n, nr, kind=kind, dt=1e-2)
+    out = op.project(torch.from_numpy(x).cuda()).cpu().numpy()
+    assert np.abs(out - ref).max() / np.abs(ref).max() <= 1e-12
