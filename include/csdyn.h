@@ -202,9 +202,89 @@ typedef struct {
     int32_t max_levels_fine, max_levels_coarse; /* L + U sweep levels of the deepest subdomain */
     int32_t precision;
     int32_t lds_fine, lds_coarse;             /* dynamic LDS bytes per workgroup of the sweep kernel */
-    int32_t box_in_lds_fine, box_in_lds_coarse; /* 1: the box vector is held in LDS */
+    int32_t box_in_lds_fine, box_in_lds_coarse; /* 1: the sweep's ring of recent levels is held in LDS */
 } csdyn_ras_info;
 int32_t csdyn_ras_get_info(const csdyn_ras *pc, csdyn_ras_info *info);
+
+/* ------------------------------------------------- learned initial guess
+ * The paper starts each time step's GMRES solve from the previous step's
+ * solution (Sec. 3.3).  These entries build a panel-wise 3-D convolutional
+ * network that predicts the initial guess from the previous two solutions,
+ * and train it online on the solutions the solver produces.
+ *
+ * BF16 tensors are uint16_t bit patterns, channels-last per panel:
+ * t[batch][d][h][w][c8] with c8 = round_up(c, 8) and the padded channels
+ * zero (the solver's vector layout [6][Nr][N][N][4] is this with 4 FP64
+ * channels).  Weights are FP32 w[cout][27][cin], tap t = 9(dz+1) + 3(dy+1) +
+ * (dx+1), correlation with zero padding inside each batch entry:
+ *   y[b,d,h,w,o] = bias[o] + sum_{t,i} x[b,d+dz,h+dy,w+dx,i] w[o,t,i].
+ * Accumulation is FP32 on the matrix cores; outputs are rounded to BF16
+ * (round to nearest even) or written as FP32.  cout <= 128 and cin <= 128
+ * for the data gradient.  All pointers are device pointers; every call is
+ * asynchronous on `stream` and returns CSDYN_EINVAL for null pointers or bad
+ * shapes. */
+typedef struct {
+    int32_t batch, d, h, w; /* batch entries (the six panels) and volume */
+    int32_t cin, cout;
+} csdyn_conv_shape;
+
+/* Element counts of the two packed BF16 weight copies and the workspace of
+ * the weight gradient (host call). */
+int32_t csdyn_conv3d_sizes(const csdyn_conv_shape *s, int64_t *wf_elems, int64_t *wb_elems,
+                           size_t *bwd_weight_ws_bytes);
+/* Pack w into wf (forward) and wb (flipped, transposed: the data gradient's
+ * forward weights).  Either output may be NULL. */
+int32_t csdyn_conv3d_pack(const csdyn_conv_shape *s, const float *w, uint16_t *wf, uint16_t *wb, void *stream);
+/* y = act(conv(x) + bias [+ residual]) with act = relu if relu != 0; y (BF16,
+ * cout8 channels) and/or y32 (FP32, cout channels); bias and residual may be
+ * NULL. */
+int32_t csdyn_conv3d_fwd(const csdyn_conv_shape *s, const uint16_t *x, const uint16_t *wf, const float *bias,
+                         const uint16_t *residual, int32_t relu, uint16_t *y, float *y32, void *stream);
+/* dx = d loss / d x given dy = d loss / d y (BF16 [..][cout8] -> [..][cin8]);
+ * where mask != NULL, dx is zeroed wherever mask <= 0 (the derivative of a
+ * relu whose output is mask). */
+int32_t csdyn_conv3d_bwd_data(const csdyn_conv_shape *s, const uint16_t *dy, const uint16_t *wb,
+                              const uint16_t *mask, uint16_t *dx, void *stream);
+/* dw = d loss / d w (FP32 [cout][27][cin], overwritten) and, if db != NULL,
+ * db = sum of dy over all voxels; sums run in a fixed order (deterministic).
+ * ws: csdyn_conv3d_sizes' bwd_weight_ws_bytes, else CSDYN_ENOMEM. */
+int32_t csdyn_conv3d_bwd_weight(const csdyn_conv_shape *s, const uint16_t *x, const uint16_t *dy, float *dw,
+                                float *db, void *ws, size_t ws_bytes, void *stream);
+/* One Adam step (Kingma and Ba, with bias correction; step >= 1 is the step
+ * number): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps), elementwise FP32. */
+int32_t csdyn_adam_step(float *param, const float *grad, float *m, float *v, int64_t n, int32_t step, float lr,
+                        float beta1, float beta2, float eps, void *stream);
+
+/* The network: widths (c0, c1, c2, c3), four resolution levels (N and Nr
+ * multiples of 8), additive skips:
+ *   e0 = relu(conv0(x)), e1 = relu(conv1(pool e0)), e2 = relu(conv2(pool e1)),
+ *   e3 = relu(conv3(pool e2)), d2 = relu(conv4(up e3) + e2),
+ *   d1 = relu(conv5(up d2) + e1), d0 = relu(conv6(up d1) + e0), y = conv7(d0)
+ * (pool: mean of 2x2x2 children; up: copy to them), 8 -> c0 -> c1 -> c2 -> c3
+ * -> c2 -> c1 -> c0 -> 4 channels.  Inputs x = (x1 / s, (x1 - x2) / sd), s and
+ * sd the per-component RMS of x1 and x1 - x2 over all cells; guess =
+ * 2 x1 - x2 + sd * y; loss = mean over cells and components of
+ * (y - (xn - 2 x1 + x2) / sd)^2.  x1, x2, xn, guess: FP64 solver vectors.
+ * Parameters: FP32, flat, layer by layer w[cout][27][cin] then bias[cout]. */
+typedef struct csdyn_net csdyn_net;
+int32_t csdyn_net_param_count(const int32_t *widths, int64_t *count);
+int32_t csdyn_net_workspace_bytes(int32_t n, int32_t nr, const int32_t *widths, size_t *bytes);
+/* params: device FP32 initial parameters (copied); Adam moments start at 0. */
+int32_t csdyn_net_setup(int32_t n, int32_t nr, const int32_t *widths, const float *params, void *ws,
+                        size_t ws_bytes, void *stream, csdyn_net **out);
+int32_t csdyn_net_get_params(const csdyn_net *net, float *params, void *stream);
+/* guess = 2 x1 - x2 + sd * net(x1, x2); x1 is the latest solution. */
+int32_t csdyn_net_predict(csdyn_net *net, const double *x1, const double *x2, double *guess, void *stream);
+/* Loss of the sample (x2, x1) -> xn and its gradient (FP32, flat, device;
+ * may be NULL).  loss: host pointer or NULL; when given, the call waits for
+ * the stream. */
+int32_t csdyn_net_loss_grad(csdyn_net *net, const double *x2, const double *x1, const double *xn, float *grads,
+                            double *loss, void *stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on that sample. */
+int32_t csdyn_net_train_step(csdyn_net *net, const double *x2, const double *x1, const double *xn, float lr,
+                             double *loss, void *stream);
+void csdyn_net_destroy(csdyn_net *net);
 
 /* ----------------------------------------------------------------- profile
  * Optional timing of every kernel launch by HIP events recorded on the launch
@@ -215,14 +295,16 @@ int32_t csdyn_ras_get_info(const csdyn_ras *pc, csdyn_ras_info *info);
  * the Krylov kernels), the launch count, the summed duration and the summed
  * algorithmic bytes (the HBM traffic the launches must cause: operands read
  * once and results written once, no cache effects, no index or padding
- * bytes).  Not thread-safe with concurrent
- * solves on other threads. */
+ * bytes) and, for the matrix-core kernels of the network, the summed
+ * algorithmic flops (2 per multiply-add of the convolution's definition, no
+ * padding).  Not thread-safe with concurrent solves on other threads. */
 typedef struct {
     char name[32];
     int64_t size;
     int64_t count;
     double total_ms;
     double bytes;
+    double flops;
 } csdyn_profile_entry;
 int32_t csdyn_profile_begin(int32_t max_launches);
 int32_t csdyn_profile_end(csdyn_profile_entry *out, int32_t max_entries, int32_t *n_entries);

@@ -104,19 +104,21 @@ def param_count(widths=WIDTHS):
     return sum(co * 27 * ci + co for co, ci in layer_shapes(widths))
 
 
-def init_params(seed, widths=WIDTHS):
-    """He-uniform weights (bound sqrt(6 / fan_in)), zero biases; the last
-    layer is scaled by 0.1 so the initial correction is small."""
-    rng = np.random.default_rng(seed)
-    params = []
-    shapes = layer_shapes(widths)
-    for li, (co, ci) in enumerate(shapes):
-        bound = np.sqrt(6.0 / (27 * ci))
-        w = rng.uniform(-bound, bound, (co, 27, ci))
-        if li == len(shapes) - 1:
-            w *= 0.1
-        params.append([w, np.zeros(co)])
-    return params
+def unflatten(flat, widths=WIDTHS):
+    """[(W, b)] in FP64 from the flat layout: per layer W[co][27][ci], then b[co]."""
+    out, off = [], 0
+    for co, ci in layer_shapes(widths):
+        w = np.asarray(flat[off:off + co * 27 * ci], dtype=np.float64).reshape(co, 27, ci)
+        off += co * 27 * ci
+        b = np.asarray(flat[off:off + co], dtype=np.float64).copy()
+        off += co
+        out.append([w, b])
+    assert off == len(flat)
+    return out
+
+
+def flatten(params):
+    return np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in params])
 
 
 def forward(params, x):

@@ -54,9 +54,14 @@ class RasInfo(C.Structure):
                 ("box_in_lds_fine", C.c_int32), ("box_in_lds_coarse", C.c_int32)]
 
 
+class ConvShape(C.Structure):
+    _fields_ = [("batch", C.c_int32), ("d", C.c_int32), ("h", C.c_int32), ("w", C.c_int32), ("cin", C.c_int32),
+                ("cout", C.c_int32)]
+
+
 class ProfileEntry(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("size", C.c_int64), ("count", C.c_int64), ("total_ms", C.c_double),
-                ("bytes", C.c_double)]
+                ("bytes", C.c_double), ("flops", C.c_double)]
 
 
 # Exported symbols and their signatures, as declared in include/csdyn.h.
@@ -80,6 +85,27 @@ SIGNATURES = {
     "csdyn_ras_get_info": (C.c_int32, [C.c_void_p, _P(RasInfo)]),
     "csdyn_profile_begin": (C.c_int32, [C.c_int32]),
     "csdyn_profile_end": (C.c_int32, [_P(ProfileEntry), C.c_int32, _P(C.c_int32)]),
+    "csdyn_conv3d_sizes": (C.c_int32, [_P(ConvShape), _P(C.c_int64), _P(C.c_int64), _P(C.c_size_t)]),
+    "csdyn_conv3d_pack": (C.c_int32, [_P(ConvShape), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "csdyn_conv3d_fwd": (C.c_int32, [_P(ConvShape), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                     C.c_void_p, C.c_void_p, C.c_void_p]),
+    "csdyn_conv3d_bwd_data": (C.c_int32, [_P(ConvShape), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.c_void_p]),
+    "csdyn_conv3d_bwd_weight": (C.c_int32, [_P(ConvShape), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                            C.c_void_p, C.c_size_t, C.c_void_p]),
+    "csdyn_adam_step": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
+                                    C.c_float, C.c_float, C.c_float, C.c_float, C.c_void_p]),
+    "csdyn_net_param_count": (C.c_int32, [_P(C.c_int32), _P(C.c_int64)]),
+    "csdyn_net_workspace_bytes": (C.c_int32, [C.c_int32, C.c_int32, _P(C.c_int32), _P(C.c_size_t)]),
+    "csdyn_net_setup": (C.c_int32, [C.c_int32, C.c_int32, _P(C.c_int32), C.c_void_p, C.c_void_p, C.c_size_t,
+                                    C.c_void_p, _P(C.c_void_p)]),
+    "csdyn_net_get_params": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "csdyn_net_predict": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "csdyn_net_loss_grad": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        _P(C.c_double), C.c_void_p]),
+    "csdyn_net_train_step": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_float,
+                                         _P(C.c_double), C.c_void_p]),
+    "csdyn_net_destroy": (None, [C.c_void_p]),
     "csdyn_last_error": (C.c_char_p, []),
 }
 
@@ -265,10 +291,134 @@ class Profile:
         return self
 
     def __exit__(self, *exc):
-        buf = (ProfileEntry * 64)()
+        buf = (ProfileEntry * 256)()
         n = C.c_int32()
-        _check(lib().csdyn_profile_end(buf, 64, C.byref(n)), "csdyn_profile_end")
+        _check(lib().csdyn_profile_end(buf, 256, C.byref(n)), "csdyn_profile_end")
         self.result = {(buf[i].name.decode(), buf[i].size): dict(count=buf[i].count, ms=buf[i].total_ms,
-                                                                  bytes=buf[i].bytes)
-                       for i in range(min(n.value, 64))}
+                                                                  bytes=buf[i].bytes, flops=buf[i].flops)
+                       for i in range(min(n.value, 256))}
         return False
+
+
+# ------------------------------------------------------- learned initial guess
+def _need(t, dtype, what):
+    if t is not None and t.dtype != dtype:
+        raise TypeError(f"{what}: expected {dtype}, got {t.dtype}")
+    return t
+
+
+def conv_sizes(shape):
+    s = ConvShape(*shape)
+    wf, wb, ws = C.c_int64(), C.c_int64(), C.c_size_t()
+    _check(lib().csdyn_conv3d_sizes(C.byref(s), C.byref(wf), C.byref(wb), C.byref(ws)), "csdyn_conv3d_sizes")
+    return wf.value, wb.value, ws.value
+
+
+def conv_pack(shape, w: torch.Tensor, stream=None):
+    """Packed BF16 forward and data-gradient weights of FP32 w [cout][27][cin]."""
+    s = ConvShape(*shape)
+    _need(w, torch.float32, "conv_pack weights")
+    nf, nb, _ = conv_sizes(shape)
+    wf = torch.empty(nf, dtype=torch.bfloat16, device=w.device)
+    wb = torch.empty(nb, dtype=torch.bfloat16, device=w.device)
+    _check(lib().csdyn_conv3d_pack(C.byref(s), _ptr(w), _ptr(wf), _ptr(wb), _stream(stream)), "csdyn_conv3d_pack")
+    return wf, wb
+
+
+def conv_fwd(shape, x, wf, bias=None, residual=None, relu=False, out32=False, stream=None):
+    """shape = (batch, d, h, w, cin, cout); x BF16 [batch, d, h, w, cin8]."""
+    s = ConvShape(*shape)
+    _need(x, torch.bfloat16, "conv_fwd input"), _need(wf, torch.bfloat16, "conv_fwd weights")
+    _need(bias, torch.float32, "conv_fwd bias"), _need(residual, torch.bfloat16, "conv_fwd residual")
+    b, d, h, w_, ci, co = shape
+    co8 = (co + 7) // 8 * 8
+    if out32:
+        y, y32 = None, torch.empty((b, d, h, w_, co), dtype=torch.float32, device=x.device)
+    else:
+        y, y32 = torch.empty((b, d, h, w_, co8), dtype=torch.bfloat16, device=x.device), None
+    _check(lib().csdyn_conv3d_fwd(C.byref(s), _ptr(x), _ptr(wf), _ptr(bias) if bias is not None else None,
+                                  _ptr(residual) if residual is not None else None, int(relu),
+                                  _ptr(y) if y is not None else None, _ptr(y32) if y32 is not None else None,
+                                  _stream(stream)), "csdyn_conv3d_fwd")
+    return y32 if out32 else y
+
+
+def conv_bwd_data(shape, dy, wb, mask=None, stream=None):
+    s = ConvShape(*shape)
+    _need(dy, torch.bfloat16, "conv_bwd_data dy"), _need(wb, torch.bfloat16, "conv_bwd_data weights")
+    _need(mask, torch.bfloat16, "conv_bwd_data mask")
+    b, d, h, w_, ci, co = shape
+    dx = torch.empty((b, d, h, w_, (ci + 7) // 8 * 8), dtype=torch.bfloat16, device=dy.device)
+    _check(lib().csdyn_conv3d_bwd_data(C.byref(s), _ptr(dy), _ptr(wb), _ptr(mask) if mask is not None else None,
+                                       _ptr(dx), _stream(stream)), "csdyn_conv3d_bwd_data")
+    return dx
+
+
+def conv_bwd_weight(shape, x, dy, stream=None):
+    s = ConvShape(*shape)
+    _need(x, torch.bfloat16, "conv_bwd_weight x"), _need(dy, torch.bfloat16, "conv_bwd_weight dy")
+    b, d, h, w_, ci, co = shape
+    _, _, nws = conv_sizes(shape)
+    ws = _workspace(nws, x.device)
+    dw = torch.empty((co, 27, ci), dtype=torch.float32, device=x.device)
+    db = torch.empty(co, dtype=torch.float32, device=x.device)
+    _check(lib().csdyn_conv3d_bwd_weight(C.byref(s), _ptr(x), _ptr(dy), _ptr(dw), _ptr(db), _ptr(ws), nws,
+                                         _stream(stream)), "csdyn_conv3d_bwd_weight")
+    return dw, db
+
+
+def adam_step(p, g, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    for t in (p, g, m, v):
+        _need(t, torch.float32, "adam_step")
+    _check(lib().csdyn_adam_step(_ptr(p), _ptr(g), _ptr(m), _ptr(v), p.numel(), step, lr, beta1, beta2, eps,
+                                 _stream(stream)), "csdyn_adam_step")
+
+
+class Net:
+    """The learned-guess network on an N x N x Nr shell (csdyn_net_*)."""
+
+    def __init__(self, n, nr, params: torch.Tensor, widths=(32, 48, 64, 128), stream=None):
+        self.n, self.nr = n, nr
+        self.widths = (C.c_int32 * 4)(*widths)
+        cnt = C.c_int64()
+        _check(lib().csdyn_net_param_count(self.widths, C.byref(cnt)), "csdyn_net_param_count")
+        self.nparam = cnt.value
+        if params.numel() != self.nparam or params.dtype != torch.float32:
+            raise ValueError(f"expected {self.nparam} FP32 parameters")
+        nb = C.c_size_t()
+        _check(lib().csdyn_net_workspace_bytes(n, nr, self.widths, C.byref(nb)), "csdyn_net_workspace_bytes")
+        self.ws = _workspace(nb.value, params.device)
+        h = C.c_void_p()
+        _check(lib().csdyn_net_setup(n, nr, self.widths, _ptr(params), _ptr(self.ws), nb.value, _stream(stream),
+                                     C.byref(h)), "csdyn_net_setup")
+        self.h = h
+
+    def params(self, stream=None):
+        out = torch.empty(self.nparam, dtype=torch.float32, device=self.ws.device)
+        _check(lib().csdyn_net_get_params(self.h, _ptr(out), _stream(stream)), "csdyn_net_get_params")
+        return out
+
+    def predict(self, x1, x2, out=None, stream=None):
+        _need(x1, torch.float64, "predict"), _need(x2, torch.float64, "predict")
+        out = torch.empty_like(x1) if out is None else out
+        _check(lib().csdyn_net_predict(self.h, _ptr(x1), _ptr(x2), _ptr(out), _stream(stream)), "csdyn_net_predict")
+        return out
+
+    def loss_grad(self, x2, x1, xn, stream=None):
+        g = torch.empty(self.nparam, dtype=torch.float32, device=self.ws.device)
+        loss = C.c_double()
+        _check(lib().csdyn_net_loss_grad(self.h, _ptr(x2), _ptr(x1), _ptr(xn), _ptr(g), C.byref(loss),
+                                         _stream(stream)), "csdyn_net_loss_grad")
+        return loss.value, g
+
+    def train_step(self, x2, x1, xn, lr=1e-3, want_loss=True, stream=None):
+        loss = C.c_double()
+        _check(lib().csdyn_net_train_step(self.h, _ptr(x2), _ptr(x1), _ptr(xn), lr,
+                                          C.byref(loss) if want_loss else None, _stream(stream)),
+               "csdyn_net_train_step")
+        return loss.value if want_loss else None
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h and _lib is not None:
+            _lib.csdyn_net_destroy(h)

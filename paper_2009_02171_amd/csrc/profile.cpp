@@ -15,7 +15,7 @@ namespace {
 struct Pair {
     const char *name;
     int64_t size;
-    double bytes;
+    double bytes, flops;
     hipEvent_t a, b;
 };
 std::mutex g_mu;
@@ -25,7 +25,7 @@ size_t g_next = 0;
 int64_t g_dropped = 0;
 }  // namespace
 
-ProfScope::ProfScope(const char *name, int64_t size, double bytes, hipStream_t s) : s_(s) {
+ProfScope::ProfScope(const char *name, int64_t size, double bytes, hipStream_t s, double flops) : s_(s) {
     if (!g_on.load(std::memory_order_relaxed)) return;
     std::lock_guard<std::mutex> lk(g_mu);
     if (g_next >= g_pool.size()) { ++g_dropped; return; }
@@ -33,6 +33,7 @@ ProfScope::ProfScope(const char *name, int64_t size, double bytes, hipStream_t s
     g_pool[slot_].name = name;
     g_pool[slot_].size = size;
     g_pool[slot_].bytes = bytes;
+    g_pool[slot_].flops = flops;
     hipEventRecord(g_pool[slot_].a, s_);
 }
 
@@ -67,7 +68,7 @@ extern "C" int32_t csdyn_profile_end(csdyn_profile_entry *out, int32_t max_entri
     std::lock_guard<std::mutex> lk(g_mu);
     if (!g_on) { set_error("profile: not active"); return CSDYN_EINVAL; }
     g_on = false;
-    struct Acc { int64_t count = 0; double ms = 0, bytes = 0; };
+    struct Acc { int64_t count = 0; double ms = 0, bytes = 0, flops = 0; };
     std::map<std::pair<std::string, int64_t>, Acc> agg;
     int32_t rc = CSDYN_OK;
     for (size_t i = 0; i < g_next; ++i) {
@@ -82,6 +83,7 @@ extern "C" int32_t csdyn_profile_end(csdyn_profile_entry *out, int32_t max_entri
         e.count += 1;
         e.ms += ms;
         e.bytes += g_pool[i].bytes;
+        e.flops += g_pool[i].flops;
     }
     for (auto &p : g_pool) {
         hipEventDestroy(p.a);
@@ -97,6 +99,7 @@ extern "C" int32_t csdyn_profile_end(csdyn_profile_entry *out, int32_t max_entri
             out[k].count = kv.second.count;
             out[k].total_ms = kv.second.ms;
             out[k].bytes = kv.second.bytes;
+            out[k].flops = kv.second.flops;
         }
         ++k;
     }

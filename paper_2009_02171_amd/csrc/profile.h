@@ -11,7 +11,7 @@ class ProfScope {
     // size: the launch's problem size (cells, box cells or vector length);
     // bytes: the algorithmic HBM bytes the launch must move.  Timings and
     // bytes are aggregated per (name, size).
-    ProfScope(const char *name, int64_t size, double bytes, hipStream_t s);
+    ProfScope(const char *name, int64_t size, double bytes, hipStream_t s, double flops = 0.0);
     ~ProfScope();
     ProfScope(const ProfScope &) = delete;
     ProfScope &operator=(const ProfScope &) = delete;

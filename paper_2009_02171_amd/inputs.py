@@ -75,3 +75,28 @@ def rhs(n: int, nr: int, seed: int, ri: float = RI, ro: float = RO, noise: float
 def random_field(shape, seed: int) -> np.ndarray:
     """Plain seeded N(0,1) array (operator and preconditioner probes)."""
     return np.random.default_rng(seed).standard_normal(shape)
+
+
+NET_WIDTHS = (32, 48, 64, 128)
+
+
+def net_layer_shapes(widths=NET_WIDTHS, cin=8, cout=4):
+    """(cout, cin) of the eight 3x3x3 convolutions of the learned-guess network."""
+    c0, c1, c2, c3 = widths
+    return [(c0, cin), (c1, c0), (c2, c1), (c3, c2), (c2, c3), (c1, c2), (c0, c1), (cout, c0)]
+
+
+def net_params(seed, widths=NET_WIDTHS):
+    """Initial network parameters, flat FP32, layer by layer w[cout][27][cin]
+    then bias[cout]: He-uniform weights (bound sqrt(6 / (27 cin))), the last
+    layer scaled by 0.1 so the initial correction is small, zero biases."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    shapes = net_layer_shapes(widths)
+    for li, (co, ci) in enumerate(shapes):
+        bound = np.sqrt(6.0 / (27 * ci))
+        w = rng.uniform(-bound, bound, (co, 27, ci))
+        if li == len(shapes) - 1:
+            w *= 0.1
+        parts += [w.ravel(), np.zeros(co)]
+    return np.concatenate(parts).astype(np.float32)

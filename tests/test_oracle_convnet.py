@@ -15,6 +15,7 @@ import pytest
 import scipy.ndimage as ndi
 
 from oracle import convnet as CN
+from paper_2009_02171_amd import inputs
 
 
 def _rand(shape, seed):
@@ -70,7 +71,7 @@ def test_backward_passes_are_adjoints():
 
 def test_network_gradient_finite_differences():
     widths = (4, 5, 6, 7)
-    params = CN.init_params(11, widths)
+    params = CN.unflatten(inputs.net_params(11, widths), widths)
     for li in range(8):  # non-zero biases so every branch is exercised
         params[li][1] = 0.1 * _rand(params[li][1].shape, 20 + li)
     x = _rand((6, 8, 8, 8, 8), 12)
@@ -121,7 +122,7 @@ def test_bf16_round_matches_torch():
 
 
 def test_zero_network_is_linear_extrapolation():
-    params = CN.init_params(21, (4, 4, 4, 4))
+    params = CN.unflatten(inputs.net_params(21, (4, 4, 4, 4)), (4, 4, 4, 4))
     for p in params:
         p[0][:] = 0
         p[1][:] = 0
@@ -133,3 +134,5 @@ def test_parameter_count():
     assert CN.param_count() == 27 * (8 * 32 + 32 * 48 + 48 * 64 + 64 * 128 + 128 * 64 + 64 * 48 + 48 * 32
                                      + 32 * 4) + (32 + 48 + 64 + 128 + 64 + 48 + 32 + 4)
     assert CN.param_count() == 701988
+    assert len(inputs.net_params(0)) == 701988
+    np.testing.assert_array_equal(CN.flatten(CN.unflatten(inputs.net_params(0))), inputs.net_params(0))
