@@ -39,6 +39,9 @@ WORKLOADS = {
                   desc="VP+BP solves, N=Nr=96 (5.31M cells), two-level RAS 384x24^3 + coarse 48^3x6, FGMRES(30)"),
     "small": dict(n=16, nr=16, sub=(16, 16, 16), levels=1, flexible=False,
                   desc="VP+BP solves, N=Nr=16 (24,576 cells), one-level RAS 6x16^3, GMRES(30)"),
+    "learned": dict(n=64, nr=64, sub=(16, 16, 16), levels=2, flexible=True,
+                    desc="200-step VP+BP march, N=Nr=64 (1.57M cells), two-level RAS 384x16^3 + coarse 32^3x6, "
+                         "FGMRES(30) to ||r|| <= 1e-8 ||b||; train on steps 1-100, evaluate 101-200"),
 }
 
 
@@ -95,6 +98,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="large")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--train-steps", type=int, default=100, help="learned workload: training steps")
+    ap.add_argument("--eval-steps", type=int, default=100, help="learned workload: evaluation steps")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the solver is single-GPU)",
@@ -108,6 +113,8 @@ def main():
     n, nr = wl["n"], wl["nr"]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "learned":
+        return learned(args, wl)
     systems = {"VP": dict(kind=csdyn.VP, seed=1), "BP": dict(kind=csdyn.BP, seed=2)}
     forms = {"plain_fp64": 0, "mixed_fp32_pc": 1}
     state = {f: {} for f in forms}
@@ -217,6 +224,69 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, {k: v[:2] for k, v in iters_plain.items()})
+    print(json.dumps(out))
+
+
+def learned(args, wl):
+    """The learned-guess comparison: plain FP64 solves from the previous
+    solution against FP32-preconditioned solves from the network's guess."""
+    import torch
+    from paper_2009_02171_amd import csdyn, inputs, march
+    t0 = time.perf_counter()
+    res = march.run(n=wl["n"], nr=wl["nr"], sub=wl["sub"], levels=wl["levels"], train_steps=args.train_steps,
+                    eval_steps=args.eval_steps, log=log)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    # the network's kernels, each launch timed with HIP events: 3 inferences and 3 training steps
+    n, nr = wl["n"], wl["nr"]
+    net = csdyn.Net(n, nr, torch.from_numpy(inputs.net_params(5)).cuda())
+    xs = [torch.from_numpy(inputs.rhs(n, nr, seed)).cuda() for seed in (41, 42, 43)]
+    net.predict(xs[1], xs[0])
+    net.train_step(*xs, lr=1e-4)
+    torch.cuda.synchronize()
+    with csdyn.Profile() as prof:
+        for _ in range(3):
+            net.predict(xs[1], xs[0])
+        for _ in range(3):
+            net.train_step(*xs, lr=1e-4, want_loss=False)
+        torch.cuda.synchronize()
+    conv = {k: v for k, v in prof.result.items() if k[0].startswith("conv_")}
+    fl = sum(v["flops"] for v in conv.values())
+    ms = sum(v["ms"] for v in conv.values())
+    dom_name, dom = max(conv.items(), key=lambda kv: kv[1]["ms"]) if conv else (("none", 0), None)
+    kernels = {f"{k[0]}@{k[1]}": dict(launches=v["count"], total_ms=round(v["ms"], 3),
+                                      avg_us=round(v["ms"] / v["count"] * 1e3, 2),
+                                      TFLOPs=round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 2) if v["ms"] else None)
+               for k, v in sorted(conv.items(), key=lambda kv: -kv[1]["ms"])}
+    sp = res["solves_per_s"]
+    out = {
+        "metric": METRIC,
+        "value": round(sp["mixed_c"], 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.eval_steps,
+        "warmup": args.train_steps,
+        "ms_per_step": round(2e3 / sp["mixed_c"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 solve, f32 preconditioner, bf16 network",
+        "data": "synthetic",
+        "config": {"workload": wl["desc"], "n": wl["n"], "nr": wl["nr"], "subdomain": list(wl["sub"]),
+                   "levels": wl["levels"], "drift_rad_per_step": res["drift_rad_per_step"],
+                   "network_params": res["param_count"]},
+        "forms": {v: round(x, 4) for v, x in sp.items()},
+        "speedup_mixed_learned_vs_plain": round(res["speedup_mixed_c_vs_plain_a"], 4),
+        "systems": res["systems"],
+        "train_s": round(res["train_s"], 2),
+        "wall_s": round(elapsed, 1),
+        "roofline": {"kernel": f"{dom_name[0]}@{dom_name[1]}", "bound": "mfma",
+                     "achieved": round(dom["flops"] / (dom["ms"] * 1e-3) / 1e12, 2) if dom else None,
+                     "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": round(dom["flops"] / (dom["ms"] * 1e-3) / 1e12 / 2500.0, 4) if dom else None,
+                     "traffic": None, "all_conv_TFLOPs": round(fl / (ms * 1e-3) / 1e12, 2) if ms else None},
+        "kernels": kernels,
+    }
     print(json.dumps(out))
 
 

@@ -177,6 +177,8 @@ typedef struct {
     int32_t flexible;  /* 0 GMRES, 1 FGMRES */
     double rtol, atol;
     int32_t orth;      /* 0 CGS, 1 CGS2 */
+    int32_t rhs_relative; /* 0: stop at max(atol, rtol ||b - A x0||) (Sec. 3.3);
+                             1: stop at max(atol, rtol ||b||) */
 } csdyn_gmres_opts;
 
 typedef struct {
@@ -184,10 +186,19 @@ typedef struct {
     int64_t inner_iters;     /* coarse GMRES iterations summed over the solve */
     double relres_true;      /* ||b - A x|| / ||b - A x0|| recomputed at the end */
     double relres_est;       /* the GMRES estimate at exit */
-    double t_ms[8];          /* operator, pc-fine, pc-coarse, pc-intermediate, orthogonalisation, other */
+    double res0;             /* ||b - A x0|| */
+    double res_true;         /* ||b - A x|| recomputed at the end */
+    double bnorm;            /* ||b|| */
 } csdyn_gmres_stats;
 
 int32_t csdyn_gmres_workspace_bytes(const csdyn_opctx *ctx, const csdyn_gmres_opts *o, size_t *bytes);
+
+/* ||b - A x|| (b with its pressure part projected for VP, as the solve does):
+ * the residual of a candidate initial guess.  ws: at least
+ * csdyn_residual_workspace_bytes; blocks until the norm is on the host. */
+int32_t csdyn_residual_workspace_bytes(const csdyn_opctx *ctx, size_t *bytes);
+int32_t csdyn_residual_norm(const csdyn_opctx *ctx, const double *b, const double *x, void *ws, size_t ws_bytes,
+                            void *stream, double *norm);
 int32_t csdyn_gmres_solve(const csdyn_opctx *ctx, const csdyn_ras *pc, const csdyn_gmres_opts *o, const double *b,
                           double *x, void *ws, size_t ws_bytes, void *stream, csdyn_gmres_stats *st);
 

@@ -37,12 +37,13 @@ class RasOpts(C.Structure):
 
 class GmresOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("maxit", C.c_int32), ("flexible", C.c_int32),
-                ("rtol", C.c_double), ("atol", C.c_double), ("orth", C.c_int32)]
+                ("rtol", C.c_double), ("atol", C.c_double), ("orth", C.c_int32), ("rhs_relative", C.c_int32)]
 
 
 class GmresStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("inner_iters", C.c_int64),
-                ("relres_true", C.c_double), ("relres_est", C.c_double), ("t_ms", C.c_double * 8)]
+                ("relres_true", C.c_double), ("relres_est", C.c_double), ("res0", C.c_double),
+                ("res_true", C.c_double), ("bnorm", C.c_double)]
 
 
 class RasInfo(C.Structure):
@@ -80,6 +81,9 @@ SIGNATURES = {
                                       _P(C.c_int64), _P(C.c_int32), _P(C.c_int32), _P(C.c_int64), _P(C.c_int32),
                                       _P(C.c_double)]),
     "csdyn_gmres_workspace_bytes": (C.c_int32, [C.c_void_p, _P(GmresOpts), _P(C.c_size_t)]),
+    "csdyn_residual_workspace_bytes": (C.c_int32, [C.c_void_p, _P(C.c_size_t)]),
+    "csdyn_residual_norm": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p,
+                                        _P(C.c_double)]),
     "csdyn_gmres_solve": (C.c_int32, [C.c_void_p, C.c_void_p, _P(GmresOpts), C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_size_t, C.c_void_p, _P(GmresStats)]),
     "csdyn_ras_get_info": (C.c_int32, [C.c_void_p, _P(RasInfo)]),
@@ -257,9 +261,9 @@ class Solver:
     """Restarted (F)GMRES with a workspace kept across solves (csdyn_gmres_solve)."""
 
     def __init__(self, op: Operator, pc: RAS | None = None, restart=30, maxit=1000, flexible=False, rtol=1e-8,
-                 atol=0.0, orth=0):
+                 atol=0.0, orth=0, rhs_relative=False):
         self.op, self.pc = op, pc
-        self.opts = GmresOpts(restart, maxit, int(flexible), rtol, atol, orth)
+        self.opts = GmresOpts(restart, maxit, int(flexible), rtol, atol, orth, int(rhs_relative))
         nb = C.c_size_t()
         _check(lib().csdyn_gmres_workspace_bytes(op.h, C.byref(self.opts), C.byref(nb)),
                "csdyn_gmres_workspace_bytes")
@@ -274,8 +278,25 @@ class Solver:
                                      _ptr(self.ws), self.nbytes, _stream(stream), C.byref(st))
         _check(rc, "csdyn_gmres_solve")
         stats = dict(iters=st.iters, restarts=st.restarts, inner_iters=st.inner_iters, relres_true=st.relres_true,
-                     relres_est=st.relres_est, t_ms=list(st.t_ms))
+                     relres_est=st.relres_est, res0=st.res0, res_true=st.res_true, bnorm=st.bnorm)
         return x, stats, rc
+
+
+class Residual:
+    """||b - A x|| of a candidate initial guess (csdyn_residual_norm)."""
+
+    def __init__(self, op: Operator):
+        self.op = op
+        nb = C.c_size_t()
+        _check(lib().csdyn_residual_workspace_bytes(op.h, C.byref(nb)), "csdyn_residual_workspace_bytes")
+        self.ws = _workspace(nb.value, op.device)
+        self.nbytes = nb.value
+
+    def __call__(self, b, x, stream=None):
+        out = C.c_double()
+        _check(lib().csdyn_residual_norm(self.op.h, _ptr(b), _ptr(x), _ptr(self.ws), self.nbytes, _stream(stream),
+                                         C.byref(out)), "csdyn_residual_norm")
+        return out.value
 
 
 class Profile:

@@ -11,6 +11,10 @@
 namespace csd {
 
 constexpr int kRedStride = 33;  // 32 dot products + 1 self product per block
+constexpr int kMaxBlocks = 1024;  // blocks of the reduction kernels
+// Entries of a reduction partial buffer: partial[q * kMaxBlocks + block],
+// q < kRedStride, whatever the vector length.
+constexpr size_t kPartialElems = size_t(kMaxBlocks) * kRedStride;
 constexpr int kMaxRestart = 64;
 
 template <class T>
@@ -44,6 +48,7 @@ int32_t convert_f2d(const float *x, double *y, int64_t n, hipStream_t s);
 struct GmresResult {
     int iters = 0, restarts = 0;
     double relres_true = 0, relres_est = 0;
+    double res0 = 0, res_true = 0, bnorm = 0;
     bool converged = false;
 };
 
@@ -58,13 +63,14 @@ struct Gmres {
 
     static size_t bytes(int64_t n, int m, bool flexible);
     void carve(Carver &c, int64_t n_, int m_, bool flexible_);
-    // Solve A x = b to max(atol, rtol*||b - A x0||) with right preconditioning.
+    // Solve A x = b to max(atol, rtol * ref) with right preconditioning, ref =
+    // ||b - A x0|| (or ||b|| when rhs_relative).
     int32_t solve(const DevFn<T> &A, const DevFn<T> *M, const T *b, T *x, int maxit, double rtol, double atol,
-                  hipStream_t s, GmresResult &res);
+                  hipStream_t s, GmresResult &res, bool rhs_relative = false);
+    int32_t norm(const T *v, double &out, hipStream_t s);
 
    private:
     int32_t fetch(int cnt, std::vector<T> &out, hipStream_t s);
-    int32_t norm(const T *v, double &out, hipStream_t s);
 };
 
 }  // namespace csd

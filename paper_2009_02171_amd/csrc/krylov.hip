@@ -15,7 +15,6 @@
 namespace csd {
 
 constexpr int kBlk = 256;
-constexpr int kMaxBlocks = 1024;
 
 template <class T>
 __device__ __forceinline__ T wave_sum(T v) {
@@ -334,7 +333,7 @@ void Gmres<T>::carve(Carver &c, int64_t n_, int m_, bool flexible_) {
     z = c.take<T>(n);
     r = c.take<T>(n);
     tmp = c.take<T>(n);
-    partial = c.take<T>(size_t(kMaxBlocks) * kRedStride);
+    partial = c.take<T>(kPartialElems);
     red = c.take<T>(3 * kRedStride);
 }
 
@@ -358,7 +357,7 @@ int32_t Gmres<T>::norm(const T *v, double &out, hipStream_t s) {
 
 template <class T>
 int32_t Gmres<T>::solve(const DevFn<T> &A, const DevFn<T> *M, const T *b, T *x, int maxit, double rtol,
-                        double atol, hipStream_t s, GmresResult &res) {
+                        double atol, hipStream_t s, GmresResult &res, bool rhs_relative) {
     res = GmresResult();
     if (m < 1 || m > kRedStride - 1 || maxit < 1) {
         set_error("gmres: restart must be in [1, %d] and maxit >= 1", kRedStride - 1);
@@ -373,7 +372,9 @@ int32_t Gmres<T>::solve(const DevFn<T> &A, const DevFn<T> *M, const T *b, T *x, 
     double beta0;
     CSD_TRY(norm(r, beta0, s));
     if (!std::isfinite(beta0)) { set_error("gmres: non-finite initial residual"); return CSDYN_EBREAKDOWN; }
-    const double tol = std::max(atol, rtol * beta0);
+    double bnorm = beta0;
+    if (rhs_relative) CSD_TRY(norm(b, bnorm, s));
+    const double tol = std::max(atol, rtol * (rhs_relative ? bnorm : beta0));
     int iters = 0, restarts = 0;
     bool conv = beta0 <= tol;
     double est = beta0, beta = beta0;
@@ -456,6 +457,9 @@ int32_t Gmres<T>::solve(const DevFn<T> &A, const DevFn<T> *M, const T *b, T *x, 
     res.restarts = restarts;
     res.relres_true = beta0 > 0 ? beta / beta0 : 0.0;
     res.relres_est = beta0 > 0 ? est / beta0 : 0.0;
+    res.res0 = beta0;
+    res.res_true = beta;
+    res.bnorm = bnorm;
     res.converged = conv;
     return conv ? CSDYN_OK : CSDYN_ENOTCONV;
 }

@@ -728,7 +728,8 @@ extern "C" int32_t csdyn_gmres_solve(const csdyn_opctx *ctx, const csdyn_ras *pc
     DevFn<double> M = [pc](const double *in, double *outv, hipStream_t st) { return ras_apply_d(pc, in, outv, st); };
     if (pc) ras_inner_iters(pc, true);
     GmresResult res;
-    int32_t rc = L.gm.solve(A, pc ? &M : nullptr, L.bproj, x, o->maxit, o->rtol, o->atol, s, res);
+    if (o->rhs_relative != 0 && o->rhs_relative != 1) { set_error("gmres: rhs_relative must be 0 or 1"); return CSDYN_EINVAL; }
+    int32_t rc = L.gm.solve(A, pc ? &M : nullptr, L.bproj, x, o->maxit, o->rtol, o->atol, s, res, o->rhs_relative != 0);
     if (rc < 0) return rc;
     if (ctx->op.kind == CSDYN_VP) CSD_TRY(project(x));
     CSD_HIP(hipStreamSynchronize(s));
@@ -739,6 +740,57 @@ extern "C" int32_t csdyn_gmres_solve(const csdyn_opctx *ctx, const csdyn_ras *pc
         st->inner_iters = pc ? ras_inner_iters(pc, false) : 0;
         st->relres_true = res.relres_true;
         st->relres_est = res.relres_est;
+        st->res0 = res.res0;
+        st->res_true = res.res_true;
+        st->bnorm = res.bnorm;
     }
     return rc;
+}
+
+// ------------------------------------------------------- residual of a guess
+struct ResidualLayout {
+    double *r, *t, *partial, *red;
+};
+static void residual_layout(Carver &c, int64_t n, ResidualLayout &L) {
+    L.r = c.take<double>(n);
+    L.t = c.take<double>(n);
+    L.partial = c.take<double>(kPartialElems);
+    L.red = c.take<double>(kRedStride);
+}
+
+extern "C" int32_t csdyn_residual_workspace_bytes(const csdyn_opctx *ctx, size_t *bytes) {
+    clear_error();
+    if (!ctx || !bytes) { set_error("residual: null argument"); return CSDYN_EINVAL; }
+    Carver c(nullptr);
+    ResidualLayout L;
+    residual_layout(c, 24 * int64_t(ctx->g.n) * ctx->g.n * ctx->g.nr, L);
+    *bytes = c.off + 256;
+    return CSDYN_OK;
+}
+
+extern "C" int32_t csdyn_residual_norm(const csdyn_opctx *ctx, const double *b, const double *x, void *ws,
+                                       size_t ws_bytes, void *stream, double *norm) {
+    clear_error();
+    if (!ctx || !b || !x || !ws || !norm) { set_error("residual: null argument"); return CSDYN_EINVAL; }
+    const int64_t n = 24 * int64_t(ctx->g.n) * ctx->g.n * ctx->g.nr, ncell = n / 4;
+    Carver c(ws);
+    ResidualLayout L;
+    residual_layout(c, n, L);
+    if (c.off + 256 > ws_bytes) { set_error("residual: workspace %zu < %zu bytes", ws_bytes, c.off + 256); return CSDYN_ENOMEM; }
+    hipStream_t s = (hipStream_t)stream;
+    CSD_TRY(Vec<double>::copy(L.r, b, n, s));
+    double h[kRedStride];
+    if (ctx->op.kind == CSDYN_VP) {
+        CSD_TRY(Vec<double>::pmoments(L.r, ctx->dg.vol, ncell, L.partial, L.red, s));
+        CSD_HIP(hipMemcpyAsync(h, L.red, sizeof(h), hipMemcpyDeviceToHost, s));
+        CSD_HIP(hipStreamSynchronize(s));
+        CSD_TRY(Vec<double>::padd(L.r, ncell, -h[0] / h[1], s));
+    }
+    CSD_TRY(op_launch(ctx, x, L.t, s));
+    CSD_TRY(Vec<double>::axpby(-1.0, L.t, 1.0, L.r, n, s));
+    CSD_TRY(Vec<double>::mdot(L.r, n, 0, L.r, L.partial, L.red, s));
+    CSD_HIP(hipMemcpyAsync(h, L.red, sizeof(h), hipMemcpyDeviceToHost, s));
+    CSD_HIP(hipStreamSynchronize(s));
+    *norm = std::sqrt(h[kRedStride - 1]);
+    return CSDYN_OK;
 }

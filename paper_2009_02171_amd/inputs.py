@@ -100,3 +100,26 @@ def net_params(seed, widths=NET_WIDTHS):
             w *= 0.1
         parts += [w.ravel(), np.zeros(co)]
     return np.concatenate(parts).astype(np.float32)
+
+
+class DriftingField:
+    """The smooth part of ``rhs(n, nr, seed)`` (no noise) drifted in longitude:
+    F_alpha(r, theta, phi) = F(r, theta, phi - alpha), each component treated
+    as a scalar field.  ``angular(alpha)`` gives A[p, j, i, c, q] and
+    ``radial`` T[k, q] with F_alpha[p, k, j, i, c] = sum_q A[p, j, i, c, q] T[k, q]."""
+
+    def __init__(self, n: int, nr: int, seed: int, ri: float = RI, ro: float = RO):
+        rng = np.random.default_rng(seed)
+        self.coef = rng.standard_normal((4, (LMAX + 1) ** 2, QMAX + 1))
+        d = cell_directions(n)
+        self.theta = np.arccos(np.clip(d[..., 2], -1.0, 1.0))
+        self.phi = np.arctan2(d[..., 1], d[..., 0])
+        r = ri + (np.arange(nr) + 0.5) * (ro - ri) / nr
+        self.radial = np.polynomial.chebyshev.chebvander(2.0 * (r - ri) / (ro - ri) - 1.0, QMAX)
+
+    def angular(self, alpha: float) -> np.ndarray:
+        Y = _real_sph(LMAX, self.theta, self.phi - alpha)
+        return np.einsum("pjil,clq->pjicq", Y, self.coef, optimize=True)
+
+    def field(self, alpha: float) -> np.ndarray:
+        return np.ascontiguousarray(np.einsum("pjicq,kq->pkjic", self.angular(alpha), self.radial, optimize=True))

@@ -1,0 +1,191 @@
+"""Time march that feeds the learned initial guess (a stand-in for the
+paper's time loop, Sec. 3.1 Steps 1-3, without the nonlinear terms).
+
+Per step n and per system (VP: velocity / pressure, BP: magnetic field /
+pseudo-pressure), with a longitudinally drifting forcing
+f^n = F(r, theta, phi - n * drift):
+
+    b^n = (v^{n-1} + dt f^n, 0)          v = u (VP) or B (BP), projected
+    A x^n = b^n                          FGMRES(30) + two-level RAS, to
+                                         ||b - A x|| <= 1e-8 ||b||
+    v^n = Step 3 of x^n                  csdyn_project
+
+The solve's initial guess is one of
+    (a) x^{n-1}                          (the paper's choice, Sec. 3.3)
+    (b) 2 x^{n-1} - x^{n-2}              (linear extrapolation)
+    (c) the network's guess, or (b) when (b) has the smaller ||b - A x0||.
+Steps 1..train_steps advance with guess (b) and train one network per
+system online (Adam on a replay buffer of the latest samples); the network
+is then frozen and steps train_steps+1.. are solved from the same state with
+every guess, the FP64 preconditioner for (a) ("plain") and the FP32 one for
+(a), (b), (c); the plain solution advances the state.  Every solve must
+reach the tolerance whatever its guess.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import torch
+
+from . import csdyn, inputs
+
+DRIFT = 0.02  # rad per step, fixed before training (about one cell per step at N = 64)
+
+
+def _sync():
+    torch.cuda.synchronize()
+
+
+class _System:
+    def __init__(self, kind, n, nr, sub, levels, dt, ekman, pm, net_seed, widths, dev):
+        self.kind = kind
+        self.op = csdyn.Operator(n, nr, kind=kind, dt=dt, ekman=ekman, pm=pm, device=dev)
+        self.pc = {p: csdyn.RAS(self.op, sub=sub, levels=levels, coarse_rtol=0.1, coarse_restart=30,
+                                coarse_maxit=200, precision=p) for p in (0, 1)}
+        self.sol = {p: csdyn.Solver(self.op, self.pc[p], restart=30, maxit=3000, flexible=True, rtol=1e-8,
+                                    rhs_relative=True) for p in (0, 1)}
+        self.res = csdyn.Residual(self.op)
+        self.net = csdyn.Net(n, nr, torch.from_numpy(inputs.net_params(net_seed, widths)).to(dev), widths=widths)
+        self.state = self.op.empty().zero_()
+        self.hist = []  # latest solutions, newest last
+
+    def rhs(self, f, dt):
+        b = self.state.clone()
+        b[..., :3] += dt * f[..., :3]
+        b[..., 3] = 0.0
+        return b
+
+
+def run(n=64, nr=64, sub=(16, 16, 16), levels=2, train_steps=100, eval_steps=100, train_iters=8, replay=16,
+        lr=5e-4, dt=1e-4, ekman=1e-3, pm=5.0, forcing_seed=4, widths=inputs.NET_WIDTHS, log=print,
+        dev="cuda"):
+    dev = torch.device(dev)
+    systems = {"VP": _System(csdyn.VP, n, nr, sub, levels, dt, ekman, pm, 5, widths, dev),
+               "BP": _System(csdyn.BP, n, nr, sub, levels, dt, ekman, pm, 6, widths, dev)}
+    forcing = inputs.DriftingField(n, nr, forcing_seed)
+    radial = torch.from_numpy(forcing.radial).to(dev)
+    rng = np.random.default_rng(forcing_seed + 1000)
+
+    def force(step):
+        a = torch.from_numpy(forcing.angular(DRIFT * step)).to(dev)
+        return torch.einsum("pjicq,kq->pkjic", a, radial).contiguous()
+
+    variants = ("plain_a", "mixed_a", "mixed_b", "mixed_c")
+    acc = {name: {v: dict(iters=0, inner=0, solve_s=0.0, guess_s=0.0, res0_rel=[], solves=0, relres=[])
+                  for v in variants} for name in systems}
+    chosen_net = {name: 0 for name in systems}
+    netd = {name: {k: [] for k in ("err_net", "err_extrap", "err_prev", "res_net", "res_extrap")} for name in systems}
+    div = {name: [] for name in systems}
+    train_s, losses = 0.0, {name: [] for name in systems}
+
+    def solve(s, b, x0, prec):
+        x = x0.clone()
+        _sync()
+        t0 = time.perf_counter()
+        _, st, rc = s.sol[prec].solve(b, x)
+        _sync()
+        el = time.perf_counter() - t0
+        if rc != 0 or not st["res_true"] <= 1.0001e-8 * st["bnorm"]:
+            raise RuntimeError(f"solve did not reach 1e-8: rc={rc} {st}")
+        return x, st, el
+
+    def advance(s, x, name, bnorm):
+        out = s.op.project(x)
+        s.state.copy_(out)
+        div[name].append(float(torch.linalg.norm(out[..., 3])) / bnorm)
+        s.hist.append(x)
+        del s.hist[:-(replay + 2)]
+
+    total = train_steps + eval_steps
+    for step in range(1, total + 1):
+        f = force(step)
+        for name, s in systems.items():
+            b = s.rhs(f, dt)
+            h = s.hist
+            if step <= train_steps:
+                x0 = (2 * h[-1] - h[-2]) if len(h) >= 2 else (h[-1].clone() if h else torch.zeros_like(b))
+                x, st, _ = solve(s, b, x0, 1)
+                advance(s, x, name, st["bnorm"])
+                if len(s.hist) >= 3:
+                    _sync()
+                    t0 = time.perf_counter()
+                    nsamp = len(s.hist) - 2
+                    for _ in range(train_iters):
+                        i = int(rng.integers(0, nsamp))
+                        s.net.train_step(s.hist[i], s.hist[i + 1], s.hist[i + 2], lr=lr, want_loss=False)
+                    losses[name].append(s.net.train_step(s.hist[-3], s.hist[-2], s.hist[-1], lr=lr))
+                    _sync()
+                    train_s += time.perf_counter() - t0
+                continue
+            # evaluation: the same b^n from every guess
+            A = acc[name]
+            bn = None
+            xg = None
+            for v in variants:
+                _sync()
+                t0 = time.perf_counter()
+                if v in ("plain_a", "mixed_a"):
+                    x0 = h[-1].clone()
+                elif v == "mixed_b":
+                    x0 = 2 * h[-1] - h[-2]
+                else:
+                    xe = 2 * h[-1] - h[-2]
+                    xg = s.net.predict(h[-1], h[-2])
+                    rg, re = s.res(b, xg), s.res(b, xe)
+                    if rg < re:
+                        x0 = xg
+                        chosen_net[name] += 1
+                    else:
+                        x0 = xe
+                _sync()
+                tg = time.perf_counter() - t0
+                x, st, el = solve(s, b, x0, 0 if v == "plain_a" else 1)
+                A[v]["iters"] += st["iters"]
+                A[v]["inner"] += st["inner_iters"]
+                A[v]["solve_s"] += el
+                A[v]["guess_s"] += tg
+                A[v]["solves"] += 1
+                A[v]["res0_rel"].append(st["res0"] / st["bnorm"])
+                A[v]["relres"].append(st["res_true"] / st["bnorm"])
+                if v == "plain_a":
+                    bn = x
+            # what the network's own guess gains before the fallback: its error
+            # against the solution and its residual, next to extrapolation's
+            nrm = float(torch.linalg.norm(bn))
+            xe = 2 * h[-1] - h[-2]
+            netd[name]["err_net"].append(float(torch.linalg.norm(xg - bn)) / nrm)
+            netd[name]["err_extrap"].append(float(torch.linalg.norm(xe - bn)) / nrm)
+            netd[name]["err_prev"].append(float(torch.linalg.norm(h[-1] - bn)) / nrm)
+            netd[name]["res_net"].append(rg / st["bnorm"])
+            netd[name]["res_extrap"].append(re / st["bnorm"])
+            advance(s, bn, name, st["bnorm"])
+        if step % 10 == 0 or step == total:
+            log(f"step {step}/{total} done")
+
+    out = {"n": n, "nr": nr, "train_steps": train_steps, "eval_steps": eval_steps, "drift_rad_per_step": DRIFT,
+           "train_s": train_s, "param_count": systems["VP"].net.nparam, "systems": {}}
+    for name in systems:
+        r = {}
+        for v in variants:
+            a = acc[name][v]
+            t = a["solve_s"] + a["guess_s"]
+            r[v] = dict(solves=a["solves"], iters_mean=a["iters"] / max(a["solves"], 1),
+                        inner_mean=a["inner"] / max(a["solves"], 1), solves_per_s=a["solves"] / t if t else None,
+                        solve_s=a["solve_s"], guess_s=a["guess_s"],
+                        res0_rel_median=float(np.median(a["res0_rel"])) if a["res0_rel"] else None,
+                        relres_max=float(max(a["relres"])) if a["relres"] else None)
+        r["net_chosen"] = chosen_net[name]
+        r["guess_quality_median"] = {k: float(np.median(v)) for k, v in netd[name].items() if v}
+        r["loss_first"] = losses[name][0] if losses[name] else None
+        r["loss_last"] = losses[name][-1] if losses[name] else None
+        r["face_div_rel_max"] = max(div[name]) if div[name] else None
+        out["systems"][name] = r
+    tot = {}
+    for v in variants:
+        s_ = sum(out["systems"][k][v]["solves"] for k in systems)
+        t_ = sum(out["systems"][k][v]["solve_s"] + out["systems"][k][v]["guess_s"] for k in systems)
+        tot[v] = s_ / t_ if t_ else None
+    out["solves_per_s"] = tot
+    out["speedup_mixed_c_vs_plain_a"] = tot["mixed_c"] / tot["plain_a"] if tot["plain_a"] else None
+    return out

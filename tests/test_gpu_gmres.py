@@ -85,3 +85,20 @@ def test_mixed_precision_solve(kind, levels):
     err = np.linalg.norm(x - x64) / np.linalg.norm(x64)
     print(f"  iterations {st['iters']} (oracle mixed {stm['iters']}), error vs FP64 oracle {err:.2e}")
     assert err <= 1e-7
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_residual_norm_of_a_guess(kind):
+    """||P b - A x|| of a candidate guess (P: the solve's VP pressure
+    projection) on a grid whose reduction uses fewer than the maximum blocks."""
+    import torch
+    from paper_2009_02171_amd import csdyn
+    n, nr = 16, 16
+    pb = O.Problem(n, nr, kind=kind)
+    b = inputs.rhs(n, nr, seed=51)
+    x = inputs.random_field(pb.shape(), seed=52)
+    bb = O.project_pressure(pb, b) if kind == 0 else b
+    ref = np.linalg.norm(bb - O.apply(pb, x))
+    op = csdyn.Operator(n, nr, kind=kind)
+    got = csdyn.Residual(op)(torch.from_numpy(b).cuda(), torch.from_numpy(x).cuda())
+    assert abs(got - ref) <= 1e-12 * ref

@@ -130,3 +130,17 @@ def test_seam_faces_conform_and_pair_up(n):
                 assert (st["face_q"][q, eq, tq], st["face_e"][q, eq, tq], st["face_t"][q, eq, tq]) == (p, e, t)
                 pairs.add(frozenset([(p, e, t), (q, eq, tq)]))
     assert len(pairs) == 12 * n   # 12 cube edges, n faces each
+
+
+def test_drifting_field_is_the_rhs_field_rotated():
+    """The march's forcing: at alpha = 0 it is rhs() without noise, and a drift
+    by alpha equals the field sampled at the cell centres rotated by -alpha
+    about z (checked where a quarter turn maps cells onto cells)."""
+    from paper_2009_02171_amd import inputs
+    n, nr = 8, 4
+    F = inputs.DriftingField(n, nr, seed=4)
+    np.testing.assert_allclose(F.field(0.0), inputs.rhs(n, nr, 4, noise=0.0), rtol=0, atol=1e-12)
+    # panel 0 (+x) drifted by pi/2 equals panel 3 (-y): F(phi - pi/2) at +x is F at -y
+    f = F.field(np.pi / 2)
+    f0 = F.field(0.0)
+    np.testing.assert_allclose(f[0], f0[3], rtol=0, atol=1e-10)
