@@ -90,6 +90,10 @@ int32_t csdyn_op_setup(const csdyn_grid *g, const csdyn_op *op, void *ws, size_t
 int32_t csdyn_operator_apply(const csdyn_opctx *ctx, const double *x, double *y, void *stream);
 void csdyn_op_destroy(csdyn_opctx *ctx);
 
+/* Workgroup shape of the stencil kernel (a tuning knob; results are
+ * identical): 0 = chosen by N, 1 = 32x8, 2 = 16x16, 3 = 64x4 cells. */
+int32_t csdyn_op_set_tile(csdyn_opctx *ctx, int32_t tile);
+
 /* Step 3 of the time step (Sec. 3.1, eq. ubtilde) from a solution
  * x = (u~, P) of the VP system (or (B~, P_b) of BP):
  *   out[c] = x[c] - dt (grad_h P)[c],  c = 0..2  (cell-centred gradient:
@@ -192,6 +196,29 @@ typedef struct {
 } csdyn_gmres_stats;
 
 int32_t csdyn_gmres_workspace_bytes(const csdyn_opctx *ctx, const csdyn_gmres_opts *o, size_t *bytes);
+
+/* Batched solves: nshell (<= 64) independent systems, each with its own
+ * operator (any grid size) and optional one-level preconditioner (the
+ * two-level one synchronises with the host inside), solved by FGMRES
+ * (restart = o->restart, CGS orthogonalisation, o->orth must be 0) in lock
+ * step: one Arnoldi step of all active shells at a time, shells on their own
+ * streams, one host synchronisation per step for the batch.  With
+ * use_graph != 0 each step is a hipGraph captured once per (active set, step
+ * index) and kept in the handle for later solves.  Stopping rule, projection
+ * of the VP pressure and statistics per shell as for csdyn_gmres_solve.
+ * b, x: host arrays of nshell device pointers (x holds x0 on entry).  The
+ * workspace (csdyn_batch_workspace_bytes) holds every shell's Krylov basis and
+ * must outlive the handle; the handle owns its streams, events, graphs and a
+ * small pinned host buffer.  Calls on one handle must not overlap.  Returns
+ * CSDYN_ENOTCONV if any shell missed its tolerance within maxit. */
+typedef struct csdyn_batch csdyn_batch;
+int32_t csdyn_batch_workspace_bytes(int32_t nshell, const csdyn_opctx *const *ops, const csdyn_gmres_opts *o,
+                                    size_t *bytes);
+int32_t csdyn_batch_setup(int32_t nshell, const csdyn_opctx *const *ops, const csdyn_ras *const *pcs,
+                          const csdyn_gmres_opts *o, void *ws, size_t ws_bytes, csdyn_batch **out);
+int32_t csdyn_gmres_solve_batched(csdyn_batch *batch, const double *const *b, double *const *x, int32_t use_graph,
+                                  void *stream, csdyn_gmres_stats *stats);
+void csdyn_batch_destroy(csdyn_batch *batch);
 
 /* ||b - A x|| (b with its pressure part projected for VP, as the solve does):
  * the residual of a candidate initial guess.  ws: at least

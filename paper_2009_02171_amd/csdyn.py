@@ -73,6 +73,7 @@ SIGNATURES = {
     "csdyn_operator_apply": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "csdyn_op_destroy": (None, [C.c_void_p]),
     "csdyn_project": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "csdyn_op_set_tile": (C.c_int32, [C.c_void_p, C.c_int32]),
     "csdyn_ras_workspace_bytes": (C.c_int32, [C.c_void_p, _P(RasOpts), _P(C.c_size_t)]),
     "csdyn_ras_setup": (C.c_int32, [C.c_void_p, _P(RasOpts), C.c_void_p, C.c_size_t, C.c_void_p, _P(C.c_void_p)]),
     "csdyn_ras_apply": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -82,6 +83,12 @@ SIGNATURES = {
                                       _P(C.c_double)]),
     "csdyn_gmres_workspace_bytes": (C.c_int32, [C.c_void_p, _P(GmresOpts), _P(C.c_size_t)]),
     "csdyn_residual_workspace_bytes": (C.c_int32, [C.c_void_p, _P(C.c_size_t)]),
+    "csdyn_batch_workspace_bytes": (C.c_int32, [C.c_int32, _P(C.c_void_p), _P(GmresOpts), _P(C.c_size_t)]),
+    "csdyn_batch_setup": (C.c_int32, [C.c_int32, _P(C.c_void_p), _P(C.c_void_p), _P(GmresOpts), C.c_void_p,
+                                      C.c_size_t, _P(C.c_void_p)]),
+    "csdyn_gmres_solve_batched": (C.c_int32, [C.c_void_p, _P(C.c_void_p), _P(C.c_void_p), C.c_int32, C.c_void_p,
+                                              _P(GmresStats)]),
+    "csdyn_batch_destroy": (None, [C.c_void_p]),
     "csdyn_residual_norm": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p,
                                         _P(C.c_double)]),
     "csdyn_gmres_solve": (C.c_int32, [C.c_void_p, C.c_void_p, _P(GmresOpts), C.c_void_p, C.c_void_p, C.c_void_p,
@@ -187,6 +194,10 @@ class Operator:
         _check(lib().csdyn_operator_apply(self.h, _ptr(x), _ptr(y), _stream(stream)), "csdyn_operator_apply")
         return y
 
+    def set_tile(self, tile: int):
+        """Stencil workgroup shape: 0 by N, 1: 32x8, 2: 16x16, 3: 64x4."""
+        _check(lib().csdyn_op_set_tile(self.h, tile), "csdyn_op_set_tile")
+
     def project(self, x: torch.Tensor, out: torch.Tensor | None = None, stream=None):
         """Step 3: (u~ - dt grad_h P, divergence of the corrected face fluxes)."""
         out = self.empty() if out is None else out
@@ -280,6 +291,43 @@ class Solver:
         stats = dict(iters=st.iters, restarts=st.restarts, inner_iters=st.inner_iters, relres_true=st.relres_true,
                      relres_est=st.relres_est, res0=st.res0, res_true=st.res_true, bnorm=st.bnorm)
         return x, stats, rc
+
+
+class Batch:
+    """Lock-step batched FGMRES over shells of different sizes (csdyn_batch_*)."""
+
+    def __init__(self, ops, pcs=None, restart=30, maxit=1000, rtol=1e-8, atol=0.0, rhs_relative=False):
+        self.ops, self.pcs = list(ops), list(pcs) if pcs is not None else None
+        ns = len(self.ops)
+        self.opts = GmresOpts(restart, maxit, 1, rtol, atol, 0, int(rhs_relative))
+        self._oh = (C.c_void_p * ns)(*[o.h for o in self.ops])
+        self._ph = (C.c_void_p * ns)(*[p.h if p is not None else None for p in self.pcs]) if self.pcs else None
+        nb = C.c_size_t()
+        _check(lib().csdyn_batch_workspace_bytes(ns, self._oh, C.byref(self.opts), C.byref(nb)),
+               "csdyn_batch_workspace_bytes")
+        self.ws = _workspace(nb.value, self.ops[0].device)
+        h = C.c_void_p()
+        _check(lib().csdyn_batch_setup(ns, self._oh, self._ph, C.byref(self.opts), _ptr(self.ws), nb.value,
+                                       C.byref(h)), "csdyn_batch_setup")
+        self.h = h
+
+    def solve(self, bs, xs, use_graph=True, stream=None):
+        ns = len(self.ops)
+        for t in list(bs) + list(xs):
+            _need(t, torch.float64, "batch vectors")
+        bp = (C.c_void_p * ns)(*[_ptr(t).value for t in bs])
+        xp = (C.c_void_p * ns)(*[_ptr(t).value for t in xs])
+        st = (GmresStats * ns)()
+        rc = lib().csdyn_gmres_solve_batched(self.h, bp, xp, int(use_graph), _stream(stream), st)
+        _check(rc, "csdyn_gmres_solve_batched")
+        stats = [dict(iters=s.iters, restarts=s.restarts, relres_true=s.relres_true, relres_est=s.relres_est,
+                      res0=s.res0, res_true=s.res_true, bnorm=s.bnorm) for s in st]
+        return stats, rc
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h and _lib is not None:
+            _lib.csdyn_batch_destroy(h)
 
 
 class Residual:

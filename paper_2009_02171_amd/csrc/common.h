@@ -111,9 +111,14 @@ struct csdyn_opctx {
     csd::DevGeom dg;
     void *ws;
     size_t ws_bytes;
+    int32_t tile = 0;  // stencil workgroup shape: 0 by N, 1: 32x8, 2: 16x16, 3: 64x4
 };
 
 namespace csd {
+// Preconditioner apply (FP64 in and out) and its properties (ras.hip).
+int32_t ras_apply_d(const csdyn_ras *pc, const double *x, double *y, hipStream_t s);
+int ras_levels(const csdyn_ras *pc);
+const csdyn_opctx *ras_fine_ctx(const csdyn_ras *pc);
 // Launch the three operator kernels (ghost fill, edge fluxes, stencil).
 int32_t op_launch(const csdyn_opctx *ctx, const double *x, double *y, hipStream_t s);
 // FP32 variant used inside the FP32 preconditioner.

@@ -14,6 +14,8 @@
 //               metric of the column is loaded once before the march.
 #include <algorithm>
 
+#include <type_traits>
+
 #include "common.h"
 #include "profile.h"
 
@@ -297,23 +299,19 @@ static int32_t launch_all(const csdyn_opctx *ctx, const T *x, T *y, T *G, T *SF,
     }
     ProfScope ps(sizeof(T) == 8 ? "op_main" : "op_main_f32", 6 * int64_t(n) * n * nr,
                  6.0 * n * n * nr * 8 * sizeof(T), s);  // x read once, y written once
-    if (n >= 32) {
-        constexpr int TX = 32, TY = 8;
+    const int tile = ctx->tile ? ctx->tile : (n >= 32 ? 1 : 2);
+    auto go = [&](auto tx_c, auto ty_c) {
+        constexpr int TX = decltype(tx_c)::value, TY = decltype(ty_c)::value;
         const int tiles = ((n + TX - 1) / TX) * ((n + TY - 1) / TY);
         int nkc = std::max(1, std::min(nr, (2048 + 6 * tiles - 1) / (6 * tiles)));
         const int kchunk = (nr + nkc - 1) / nkc;
         nkc = (nr + kchunk - 1) / kchunk;
         hipLaunchKernelGGL((k_op_main<T, TX, TY>), dim3(tiles, 6 * nkc), dim3(TX * TY), 0, s, g, rc, kchunk, nkc, x,
                            (const T *)G, (const T *)SF, y);
-    } else {
-        constexpr int TX = 16, TY = 16;
-        const int tiles = ((n + TX - 1) / TX) * ((n + TY - 1) / TY);
-        int nkc = std::max(1, std::min(nr, (2048 + 6 * tiles - 1) / (6 * tiles)));
-        const int kchunk = (nr + nkc - 1) / nkc;
-        nkc = (nr + kchunk - 1) / kchunk;
-        hipLaunchKernelGGL((k_op_main<T, TX, TY>), dim3(tiles, 6 * nkc), dim3(TX * TY), 0, s, g, rc, kchunk, nkc, x,
-                           (const T *)G, (const T *)SF, y);
-    }
+    };
+    if (tile == 1) go(std::integral_constant<int, 32>(), std::integral_constant<int, 8>());
+    else if (tile == 2) go(std::integral_constant<int, 16>(), std::integral_constant<int, 16>());
+    else go(std::integral_constant<int, 64>(), std::integral_constant<int, 4>());
     CSD_HIP(hipGetLastError());
     return CSDYN_OK;
 }
@@ -412,6 +410,13 @@ extern "C" int32_t csdyn_project(const csdyn_opctx *ctx, const double *x, double
     hipLaunchKernelGGL(k_project, dim3(unsigned((ncell + 255) / 256)), dim3(256), 0, s, ctx->dg, ctx->op.kind,
                        ctx->op.dt, x, (const double *)ctx->dg.G, out);
     CSD_HIP(hipGetLastError());
+    return CSDYN_OK;
+}
+
+extern "C" int32_t csdyn_op_set_tile(csdyn_opctx *ctx, int32_t tile) {
+    clear_error();
+    if (!ctx || tile < 0 || tile > 3) { set_error("csdyn_op_set_tile: tile must be 0..3"); return CSDYN_EINVAL; }
+    ctx->tile = tile;
     return CSDYN_OK;
 }
 

@@ -23,10 +23,13 @@ std::atomic<bool> g_on{false};
 std::vector<Pair> g_pool;
 size_t g_next = 0;
 int64_t g_dropped = 0;
+thread_local bool t_suspended = false;
 }  // namespace
 
+void prof_suspend(bool on) { t_suspended = on; }
+
 ProfScope::ProfScope(const char *name, int64_t size, double bytes, hipStream_t s, double flops) : s_(s) {
-    if (!g_on.load(std::memory_order_relaxed)) return;
+    if (!g_on.load(std::memory_order_relaxed) || t_suspended) return;
     std::lock_guard<std::mutex> lk(g_mu);
     if (g_next >= g_pool.size()) { ++g_dropped; return; }
     slot_ = int64_t(g_next++);

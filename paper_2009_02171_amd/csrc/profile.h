@@ -21,4 +21,8 @@ class ProfScope {
     int64_t slot_ = -1;
 };
 
+// While a thread captures a graph its launches are not timed (an event pair
+// recorded during capture would become graph nodes).
+void prof_suspend(bool on);
+
 }  // namespace csd

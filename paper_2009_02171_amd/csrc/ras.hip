@@ -625,6 +625,8 @@ int32_t ras_apply_d(const csdyn_ras *pc, const double *x, double *y, hipStream_t
     CSD_TRY(pc->two_level<float>(x32, y32, s));
     return convert_f2d(y32, y, pc->nf, s);
 }
+int ras_levels(const csdyn_ras *pc) { return pc->o.levels; }
+const csdyn_opctx *ras_fine_ctx(const csdyn_ras *pc) { return pc->fine_ctx; }
 int64_t ras_inner_iters(const csdyn_ras *pc, bool reset) {
     const int64_t v = pc->inner_iters;
     if (reset) pc->inner_iters = 0;

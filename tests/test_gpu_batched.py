@@ -1,0 +1,86 @@
+"""Batched lock-step FGMRES over shells of different sizes, eager and
+hipGraph-captured, against one solve per shell (itself pinned to the oracle),
+and the operator's workgroup shapes against each other."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2009_02171_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+SHELLS = [(8, 0.0008), (16, 0.0003), (24, 0.0001), (16, 0.001)]  # (N = Nr, Ekman number)
+
+
+def _setup(kind=0):
+    import torch
+    from paper_2009_02171_amd import csdyn
+    ops, pcs, bs = [], [], []
+    for s, (n, ek) in enumerate(SHELLS):
+        op = csdyn.Operator(n, n, kind=kind, dt=1e-4, ekman=ek, pm=5.0)
+        ops.append(op)
+        pcs.append(csdyn.RAS(op, sub=(8, 8, 8), levels=1, precision=1))
+        bs.append(torch.from_numpy(inputs.rhs(n, n, seed=100 + s)).cuda())
+    return ops, pcs, bs
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_batched_matches_single_solves(kind):
+    import torch
+    from paper_2009_02171_amd import csdyn
+    ops, pcs, bs = _setup(kind)
+    ref = []
+    for op, pc, b in zip(ops, pcs, bs):
+        x, st, rc = csdyn.Solver(op, pc, restart=30, maxit=2000, flexible=True, rtol=1e-8).solve(b)
+        assert rc == 0
+        ref.append((x.clone(), st))
+    batch = csdyn.Batch(ops, pcs, restart=30, maxit=2000, rtol=1e-8)
+    results = {}
+    for mode in ("eager", "graph", "graph_again"):
+        xs = [torch.zeros_like(b) for b in bs]
+        stats, rc = batch.solve(bs, xs, use_graph=mode != "eager")
+        assert rc == 0
+        results[mode] = xs
+        for (xr, sr), x, st in zip(ref, xs, stats):
+            assert abs(st["iters"] - sr["iters"]) <= 1, (mode, st, sr)
+            assert st["res_true"] <= 1.0001e-8 * st["res0"]
+            assert float(torch.linalg.norm(x - xr) / torch.linalg.norm(xr)) <= 1e-9
+        torch.cuda.synchronize()
+    # a replay of the cached graphs reproduces the first graph solve exactly
+    for a, b in zip(results["graph"], results["graph_again"]):
+        assert torch.equal(a, b)
+
+
+def test_batched_small_shell_matches_oracle():
+    import torch
+    from paper_2009_02171_amd import csdyn
+    ops, pcs, bs = _setup(0)
+    xs = [torch.zeros_like(b) for b in bs]
+    stats, rc = csdyn.Batch(ops, pcs, restart=30, maxit=2000, rtol=1e-8).solve(bs, xs)
+    n, ek = SHELLS[0]
+    pb = O.Problem(n, n, kind=0, dt=1e-4, ekman=ek, pm=5.0)
+    xo, so, rco = O.gmres(pb, bs[0].cpu().numpy(), pc=O.Preconditioner(pb, sub=(8, 8, 8), levels=1, precision=1),
+                          flexible=True, rtol=1e-8)
+    assert rco == 0 and abs(so["iters"] - stats[0]["iters"]) <= 1
+    x = xs[0].cpu().numpy()
+    assert np.linalg.norm(x - xo) <= 1e-7 * np.linalg.norm(xo)
+
+
+def test_batched_rejects_two_level():
+    from paper_2009_02171_amd import csdyn
+    op = csdyn.Operator(16, 16)
+    pc = csdyn.RAS(op, sub=(8, 8, 8), levels=2)
+    with pytest.raises(csdyn.CsdynError):
+        csdyn.Batch([op], [pc])
+
+
+@pytest.mark.parametrize("tile", [1, 2, 3])
+def test_operator_tiles_agree(tile):
+    import torch
+    from paper_2009_02171_amd import csdyn
+    for n, nr in ((40, 6), (24, 5), (17, 3)):
+        op = csdyn.Operator(n, nr, kind=1, dt=1e-2)
+        x = torch.from_numpy(inputs.random_field((6, nr, n, n, 4), seed=n)).cuda()
+        y0 = op.apply(x).clone()
+        op.set_tile(tile)
+        assert torch.equal(op.apply(x), y0)
