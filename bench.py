@@ -39,6 +39,10 @@ WORKLOADS = {
                   desc="VP+BP solves, N=Nr=96 (5.31M cells), two-level RAS 384x24^3 + coarse 48^3x6, FGMRES(30)"),
     "small": dict(n=16, nr=16, sub=(16, 16, 16), levels=1, flexible=False,
                   desc="VP+BP solves, N=Nr=16 (24,576 cells), one-level RAS 6x16^3, GMRES(30)"),
+    "batched": dict(n=80, nr=80, ns=(24, 32, 40, 48, 56, 64, 72, 80),
+                    desc="8 VP shells, N=Nr in {24,...,80} (9.27M cells), E log-uniform in [1e-4, 1e-3], one-level FP32 "
+                         "RAS with autotuned subdomains and stencil tiles, FGMRES(30) to 1e-8, lock-step batch, one "
+                         "hipGraph per Arnoldi step"),
     "learned": dict(n=64, nr=64, sub=(16, 16, 16), levels=2, flexible=True,
                     desc="200-step VP+BP march, N=Nr=64 (1.57M cells), two-level RAS 384x16^3 + coarse 32^3x6, "
                          "FGMRES(30) to ||r|| <= 1e-8 ||b||; train on steps 1-100, evaluate 101-200"),
@@ -115,6 +119,8 @@ def main():
     torch.cuda.set_device(dev)
     if args.workload == "learned":
         return learned(args, wl)
+    if args.workload == "batched":
+        return batched(args, wl)
     systems = {"VP": dict(kind=csdyn.VP, seed=1), "BP": dict(kind=csdyn.BP, seed=2)}
     forms = {"plain_fp64": 0, "mixed_fp32_pc": 1}
     state = {f: {} for f in forms}
@@ -224,6 +230,81 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, {k: v[:2] for k, v in iters_plain.items()})
+    print(json.dumps(out))
+
+
+def batched(args, wl):
+    """Eight uneven shells solved as one batch (hipGraph per Arnoldi step)
+    against the same eight solves one after another."""
+    import torch
+    from paper_2009_02171_amd import autotune, csdyn, inputs
+    ops, pcs, bs, tuned = [], [], [], {}
+    t0 = time.perf_counter()
+    for s, n in enumerate(wl["ns"]):
+        ek, b = inputs.shell_case(s, n, n)
+        op = csdyn.Operator(n, n, kind=csdyn.VP, dt=1e-4, ekman=ek, pm=5.0)
+        bt = torch.from_numpy(b).cuda()
+        tn = autotune.tune_shell(op, bt, precision=1, log=log)
+        ops.append(op)
+        bs.append(bt)
+        pcs.append(csdyn.RAS(op, sub=(tn["sub"],) * 3, levels=1, precision=1))
+        tuned[f"N={n}"] = dict(ekman=round(ek, 7), tile=autotune.TILES[tn["tile"]], sub=tn["sub"],
+                               tiles_us=tn["tiles_us"], subdomains=tn["subdomains"])
+        log(f"shell {s}: N={n} E={ek:.3e} tile {autotune.TILES[tn['tile']]} sub {tn['sub']}")
+    tune_s = time.perf_counter() - t0
+    solvers = [csdyn.Solver(op, pc, restart=30, maxit=5000, flexible=True, rtol=1e-8) for op, pc in zip(ops, pcs)]
+    batch = csdyn.Batch(ops, pcs, restart=30, maxit=5000, rtol=1e-8)
+    iters = {}
+
+    def sequential():
+        for i, (sol, b) in enumerate(zip(solvers, bs)):
+            _, st, rc = sol.solve(b, torch.zeros_like(b))
+            if rc != 0:
+                raise RuntimeError(f"shell {i} did not converge: {st}")
+
+    def run_batch(graph):
+        xs = [torch.zeros_like(b) for b in bs]
+        stats, rc = batch.solve(bs, xs, use_graph=graph)
+        if rc != 0 or any(not st["res_true"] <= 1.0001e-8 * st["res0"] for st in stats):
+            raise RuntimeError(f"batch did not converge: {stats}")
+        iters["graph" if graph else "eager"] = [st["iters"] for st in stats]
+
+    forms = {"sequential": sequential, "batched_eager": lambda: run_batch(False),
+             "batched_graph": lambda: run_batch(True)}
+    timing = {}
+    for name, fn in forms.items():
+        for _ in range(max(args.warmup, 1)):
+            fn()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        timing[name] = (time.perf_counter() - t1) / args.steps
+        log(f"{name}: {timing[name] * 1e3:.1f} ms per batch of 8 solves")
+    with csdyn.Profile() as prof:
+        run_batch(False)
+        torch.cuda.synchronize()
+    dom_name, dom = max(prof.result.items(), key=lambda kv: kv[1]["ms"])
+    dom_gbs = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
+    kernels = {f"{k[0]}@{k[1]}": dict(launches=v["count"], total_ms=round(v["ms"], 3),
+                                      avg_us=round(v["ms"] / v["count"] * 1e3, 2),
+                                      alg_GBs=round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] else None)
+               for k, v in sorted(prof.result.items(), key=lambda kv: -kv[1]["ms"])[:16]}
+    tg = timing["batched_graph"]
+    out = {
+        "metric": METRIC, "value": round(8 / tg, 4), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(tg * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64 solve, f32 preconditioner", "data": "synthetic",
+        "config": {"workload": wl["desc"], "shells": list(wl["ns"]), "krylov": "FGMRES(30)", "rtol": 1e-8},
+        "forms": {k: {"solves_per_s": round(8 / v, 4), "ms_per_batch": round(v * 1e3, 2)} for k, v in timing.items()},
+        "speedup_graph_vs_sequential": round(timing["sequential"] / tg, 4),
+        "iters": {f"N={n}": it for n, it in zip(wl["ns"], iters["graph"])},
+        "autotune": tuned, "autotune_s": round(tune_s, 1),
+        "roofline": {"kernel": f"{dom_name[0]}@{dom_name[1]}", "bound": "hbm", "achieved": round(dom_gbs, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4), "traffic": None},
+        "kernels": kernels,
+    }
     print(json.dumps(out))
 
 

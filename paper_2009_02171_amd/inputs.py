@@ -57,7 +57,19 @@ def _real_sph(lmax: int, theta: np.ndarray, phi: np.ndarray) -> np.ndarray:
 
 def rhs(n: int, nr: int, seed: int, ri: float = RI, ro: float = RO, noise: float = 1e-3) -> np.ndarray:
     """Seeded right-hand side, float64 [6, Nr, N, N, 4] (panel, k, j, i, component)."""
-    rng = np.random.default_rng(seed)
+    return _rhs(n, nr, np.random.default_rng(seed), ri, ro, noise)
+
+
+def shell_case(s: int, n: int, nr: int, ri: float = RI, ro: float = RO):
+    """Shell s of the uneven-size batch: (Ekman number, right-hand side), both
+    from the stream default_rng(100 + s), the Ekman number drawn first,
+    log-uniform in [1e-4, 1e-3]."""
+    rng = np.random.default_rng(100 + s)
+    ekman = 10.0 ** rng.uniform(-4.0, -3.0)
+    return ekman, _rhs(n, nr, rng, ri, ro, 1e-3)
+
+
+def _rhs(n, nr, rng, ri, ro, noise):
     nlm = (LMAX + 1) ** 2
     coef = rng.standard_normal((4, nlm, QMAX + 1))
     d = cell_directions(n)
