@@ -91,7 +91,8 @@ int32_t csdyn_operator_apply(const csdyn_opctx *ctx, const double *x, double *y,
 void csdyn_op_destroy(csdyn_opctx *ctx);
 
 /* Workgroup shape of the stencil kernel (a tuning knob; results are
- * identical): 0 = chosen by N, 1 = 32x8, 2 = 16x16, 3 = 64x4 cells. */
+ * identical): 0 = default (16x8), 1 = 32x8, 2 = 16x16, 3 = 64x4, 4 = 16x8,
+ * 5 = 32x4 cells. */
 int32_t csdyn_op_set_tile(csdyn_opctx *ctx, int32_t tile);
 
 /* Step 3 of the time step (Sec. 3.1, eq. ubtilde) from a solution

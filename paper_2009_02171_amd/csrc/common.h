@@ -70,6 +70,8 @@ struct HostGeom {
     std::vector<FaceEntry> face;    // [6][4][n]
     // metric tables, same layout as DevGeom
     std::vector<double> a11x, a12x, a22y, a12y, sc, t1, t2, nrm, gc1, gc2, rk, rf, vol;
+    // lay[k]: r_k, 1/r_k^2, r_{k-1/2}^2, r_{k+1/2}^2, 1/(r_k h_r)^2, 1/(2 r_k^2 h_r), 1/r_k, 0
+    std::vector<double> lay, isc;
     int32_t build(const csdyn_grid &g);
     size_t nf() const { return size_t(n) * (n + 1); }
     double ang(double i) const { return -0.78539816339744830962 + (i + 0.5) * hs; }
@@ -91,6 +93,11 @@ struct DevGeom {
     double *gc1, *gc2;    // [6][n][n][3]    r g^1, r g^2 at cell centres (dual basis, global frame)
     double *rk;           // [nr]     r_k
     double *rf;           // [nr+1]   r_{k-1/2}
+    double *lay;          // [nr][8]  per-layer stencil factors (see HostGeom::lay)
+    double *isc;          // [n][n]   1 / (h_s sqrt(g)/r^2) at cell centres
+    double wq2_bot, wq2_top;  // (r_in / r_ghost)^2 at the inner and outer wall
+    double *zero;         // [64] zeros: the source of loads that must read 0
+    double *sink;         // [2048] written by threads whose result is discarded
     int *gh_i;            // [6][4][n][4]  q, fix_i, idx, m0
     double *gh_w;         // [6][4][n][4]
     int *fc;              // [6][4][n][4]  q, e, t, pad
@@ -111,7 +118,7 @@ struct csdyn_opctx {
     csd::DevGeom dg;
     void *ws;
     size_t ws_bytes;
-    int32_t tile = 0;  // stencil workgroup shape: 0 by N, 1: 32x8, 2: 16x16, 3: 64x4
+    int32_t tile = 0;  // stencil workgroup shape: 0 default (16x8), 1: 32x8, 2: 16x16, 3: 64x4, 4: 16x8, 5: 32x4
 };
 
 namespace csd {

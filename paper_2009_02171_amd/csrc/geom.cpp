@@ -161,6 +161,19 @@ int32_t HostGeom::build(const csdyn_grid &g) {
         }
     for (int k = 0; k < nr; ++k) rk[k] = rad(k);
     for (int k = 0; k <= nr; ++k) rf[k] = ri + k * hr;
+    lay.assign(size_t(nr) * 8, 0.0);
+    for (int k = 0; k < nr; ++k) {
+        double *L = &lay[size_t(k) * 8];
+        L[0] = rk[k];
+        L[1] = 1.0 / (rk[k] * rk[k]);
+        L[2] = rf[k] * rf[k];
+        L[3] = rf[k + 1] * rf[k + 1];
+        L[4] = 1.0 / (rk[k] * rk[k] * hr * hr);
+        L[5] = 0.5 / (rk[k] * rk[k] * hr);
+        L[6] = 1.0 / rk[k];
+    }
+    isc.assign(size_t(n) * n, 0.0);
+    for (size_t a = 0; a < size_t(n) * n; ++a) isc[a] = 1.0 / (hs * sc[a]);
     for (int p = 0; p < 6; ++p)
         for (int k = 0; k < nr; ++k)
             for (int j = 0; j < n; ++j)
@@ -177,10 +190,13 @@ size_t devgeom_bytes(int n, int nr) {
     c.take<double>(6 * nf * 3); c.take<double>(6 * nf * 3); c.take<double>(6 * size_t(n) * n * 3);
     c.take<double>(6 * size_t(n) * n * 3); c.take<double>(6 * size_t(n) * n * 3);
     c.take<double>(nr); c.take<double>(nr + 1);
+    c.take<double>(size_t(nr) * 8); c.take<double>(size_t(n) * n);
     c.take<int>(24 * size_t(n) * 4); c.take<double>(24 * size_t(n) * 4); c.take<int>(24 * size_t(n) * 4);
     c.take<double>(6 * size_t(nr) * n * n);
     c.take<double>(24 * size_t(nr) * n * 4);
     c.take<double>(24 * size_t(nr) * n * 8);
+    c.take<double>(64);
+    c.take<double>(2048);
     return c.off + 256;
 }
 
@@ -197,11 +213,20 @@ int32_t devgeom_setup(const HostGeom &hg, void *ws, DevGeom *o) {
     o->gc1 = c.take<double>(6 * size_t(n) * n * 3);
     o->gc2 = c.take<double>(6 * size_t(n) * n * 3);
     o->rk = c.take<double>(nr); o->rf = c.take<double>(nr + 1);
+    o->lay = c.take<double>(size_t(nr) * 8); o->isc = c.take<double>(size_t(n) * n);
+    {
+        const double rbot = hg.rf[0] - 0.5 * hg.hr, rtop = hg.rf[nr] + 0.5 * hg.hr;
+        o->wq2_bot = (hg.rk[0] / rbot) * (hg.rk[0] / rbot);
+        o->wq2_top = (hg.rk[nr - 1] / rtop) * (hg.rk[nr - 1] / rtop);
+    }
     o->gh_i = c.take<int>(24 * size_t(n) * 4); o->gh_w = c.take<double>(24 * size_t(n) * 4);
     o->fc = c.take<int>(24 * size_t(n) * 4);
     o->vol = c.take<double>(6 * size_t(nr) * n * n);
     o->G = c.take<double>(24 * size_t(nr) * n * 4);
     o->SF = c.take<double>(24 * size_t(nr) * n * 8);
+    o->zero = c.take<double>(64);
+    o->sink = c.take<double>(2048);
+    CSD_HIP(hipMemset(o->zero, 0, 64 * sizeof(double)));
 
     std::vector<int> ghi(24 * size_t(n) * 4), fcv(24 * size_t(n) * 4);
     std::vector<double> ghw(24 * size_t(n) * 4);
@@ -214,11 +239,12 @@ int32_t devgeom_setup(const HostGeom &hg, void *ws, DevGeom *o) {
     }
     const std::vector<double> &a11x = hg.a11x, &a12x = hg.a12x, &a22y = hg.a22y, &a12y = hg.a12y, &sc = hg.sc,
                               &t1 = hg.t1, &t2 = hg.t2, &nrm = hg.nrm, &rk = hg.rk, &rf = hg.rf, &vol = hg.vol,
-                              &gc1 = hg.gc1, &gc2 = hg.gc2;
+                              &gc1 = hg.gc1, &gc2 = hg.gc2, &lay = hg.lay, &isc = hg.isc;
     auto up = [](void *dst, const void *src, size_t bytes) { return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice); };
 #define UP(dst, vec) CSD_HIP(up(dst, vec.data(), vec.size() * sizeof(vec[0])))
     UP(o->a11x, a11x); UP(o->a12x, a12x); UP(o->a22y, a22y); UP(o->a12y, a12y); UP(o->sc, sc);
     UP(o->t1, t1); UP(o->t2, t2); UP(o->nrm, nrm); UP(o->rk, rk); UP(o->rf, rf); UP(o->gc1, gc1); UP(o->gc2, gc2);
+    UP(o->lay, lay); UP(o->isc, isc);
     UP(o->gh_i, ghi); UP(o->gh_w, ghw); UP(o->fc, fcv); UP(o->vol, vol);
 #undef UP
     return CSDYN_OK;

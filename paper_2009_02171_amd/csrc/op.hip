@@ -171,113 +171,222 @@ __device__ __forceinline__ V4<T> wall_ghost(const V4<T> &xin, int kind, const T 
     return gv;
 }
 
-template <class T, int TX, int TY>
-__global__ __launch_bounds__(TX *TY) void k_op_main(DevGeom g, RowCoef rc, int kchunk, int nkc,
-                                                    const T *__restrict__ x, const T *__restrict__ G,
-                                                    const T *__restrict__ SF, T *__restrict__ y) {
-    constexpr int HX = TX + 2, HY = TY + 2, HC = HX * HY;
-    __shared__ T lds[4 * HC];
+// The stencil: one workgroup owns a TX x TY tile of columns of one panel and
+// marches over a chunk of radial layers, one thread per column.  The halo of
+// three layers sits in LDS (layer k for the lateral stencil, k+1 for the
+// radial neighbour, k+2 being written) while layers k+3 and k+4 are in flight
+// in registers; one barrier per layer, which orders LDS only so that the global
+// loads stay in flight.  Every iteration issues the same loads in the same
+// order (cells outside the panel read a zero page), so the compiler's
+// in-order memory counters wait only for what a layer uses.
+constexpr int kMaxChunk = 64;  // radial layers per workgroup
+
+// Workgroup barrier that orders LDS only (__syncthreads would also wait for
+// every global load in flight).
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+template <class T>
+struct Column {  // r-independent metric of one column
+    T a11W, a11E, a12W, a12E, a22S, a22N, a12S, a12N, isc;
+    T tW[3], tE[3], tS[3], tN[3], nv[3];
+};
+
+template <class T, int TX, int TY, bool EDGE>
+__device__ __forceinline__ void op_march(const DevGeom &g, const RowCoef &rc, int p, int bx, int by, int k0, int k1,
+                                         const T *__restrict__ x, const T *__restrict__ G,
+                                         const T *__restrict__ SF, T *__restrict__ y, T (*lds)[4][(TX + 2) * (TY + 2)],
+                                         T (*layf)[8]) {
+    constexpr int NT = TX * TY, HX = TX + 2, HY = TY + 2, HC = HX * HY, NRING = HC - NT;
+    static_assert(NRING <= NT, "one border cell per thread");
     const int n = g.n, nr = g.nr;
-    const int tilesx = (n + TX - 1) / TX;
-    const int bx = blockIdx.x % tilesx, by = blockIdx.x / tilesx;
-    const int p = blockIdx.y / nkc, kc = blockIdx.y % nkc;
-    const int k0 = kc * kchunk, k1 = min(nr, k0 + kchunk);
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     const int i = bx * TX + tx, j = by * TY + ty;
     const bool act = i < n && j < n;
     const int ic = min(i, n - 1), jc = min(j, n - 1);
     const size_t nf = size_t(n) * (n + 1);
+    const int64_t kstride = int64_t(n) * n;
+    const T *zp = reinterpret_cast<const T *>(g.zero);
 
-    // r-independent metric of this column, loaded once
-    const T a11W = T(g.a11x[size_t(jc) * (n + 1) + ic]), a11E = T(g.a11x[size_t(jc) * (n + 1) + ic + 1]);
-    const T a12W = T(g.a12x[size_t(jc) * (n + 1) + ic]), a12E = T(g.a12x[size_t(jc) * (n + 1) + ic + 1]);
-    const T a22S = T(g.a22y[size_t(jc) * n + ic]), a22N = T(g.a22y[size_t(jc + 1) * n + ic]);
-    const T a12S = T(g.a12y[size_t(jc) * n + ic]), a12N = T(g.a12y[size_t(jc + 1) * n + ic]);
-    const T scc = T(g.sc[size_t(jc) * n + ic]);
-    T tW[3], tE[3], tS[3], tN[3], nv[3];
+    Column<T> m;
+    m.a11W = T(g.a11x[size_t(jc) * (n + 1) + ic]); m.a11E = T(g.a11x[size_t(jc) * (n + 1) + ic + 1]);
+    m.a12W = T(g.a12x[size_t(jc) * (n + 1) + ic]); m.a12E = T(g.a12x[size_t(jc) * (n + 1) + ic + 1]);
+    m.a22S = T(g.a22y[size_t(jc) * n + ic]); m.a22N = T(g.a22y[size_t(jc + 1) * n + ic]);
+    m.a12S = T(g.a12y[size_t(jc) * n + ic]); m.a12N = T(g.a12y[size_t(jc + 1) * n + ic]);
+    m.isc = T(g.isc[size_t(jc) * n + ic]);
     for (int d = 0; d < 3; ++d) {
-        tW[d] = T(g.t1[(p * nf + size_t(jc) * (n + 1) + ic) * 3 + d]);
-        tE[d] = T(g.t1[(p * nf + size_t(jc) * (n + 1) + ic + 1) * 3 + d]);
-        tS[d] = T(g.t2[(p * nf + size_t(jc) * n + ic) * 3 + d]);
-        tN[d] = T(g.t2[(p * nf + size_t(jc + 1) * n + ic) * 3 + d]);
-        nv[d] = T(g.nrm[((size_t(p) * n + jc) * n + ic) * 3 + d]);
+        m.tW[d] = T(g.t1[(p * nf + size_t(jc) * (n + 1) + ic) * 3 + d]);
+        m.tE[d] = T(g.t1[(p * nf + size_t(jc) * (n + 1) + ic + 1) * 3 + d]);
+        m.tS[d] = T(g.t2[(p * nf + size_t(jc) * n + ic) * 3 + d]);
+        m.tN[d] = T(g.t2[(p * nf + size_t(jc + 1) * n + ic) * 3 + d]);
+        m.nv[d] = T(g.nrm[((size_t(p) * n + jc) * n + ic) * 3 + d]);
     }
     const bool sW = i == 0, sE = i == n - 1, sS = j == 0, sN = j == n - 1;
     const T ih = T(1.0 / g.hs), i4h = T(0.25 / g.hs);
-    const T rbot = T(g.rf[0] - 0.5 * g.hr), rtop = T(g.rf[nr] + 0.5 * g.hr);
     const T clap = T(rc.c_lap), ccor = T(rc.c_cor), cdt = T(rc.dt);
 
-    const int64_t col0 = cell_ix(n, nr, p, ic, jc, 0);
-    const int64_t kstride = int64_t(n) * n;
-    V4<T> xc = ld4(x + 4 * (col0 + k0 * kstride)), xm;
-    if (k0 > 0) xm = ld4(x + 4 * (col0 + (k0 - 1) * kstride));
-    else { const T q = T(g.rk[0]) / rbot; xm = wall_ghost(xc, rc.kind, nv, q * q); }
+    // halo sources: each thread owns its cell and at most one border-ring cell
+    auto source = [&](int hx, int hy, const T *&src, int64_t &step) {
+        const int ii = bx * TX + hx - 1, jj = by * TY + hy - 1;
+        const bool iin = ii >= 0 && ii < n, jin = jj >= 0 && jj < n;
+        src = zp;
+        step = 0;
+        if (iin && jin) { src = x + 4 * cell_ix(n, nr, p, ii, jj, k0); step = 4 * kstride; }
+        else if (jin && (ii == -1 || ii == n)) { src = G + 4 * ghost_ix(n, nr, p, ii < 0 ? 0 : 1, k0, jj); step = 4 * n; }
+        else if (iin && (jj == -1 || jj == n)) { src = G + 4 * ghost_ix(n, nr, p, jj < 0 ? 2 : 3, k0, ii); step = 4 * n; }
+    };
+    const int r = threadIdx.x;
+    int rhx = 0, rhy = 0;
+    if (r < HX) { rhx = r; rhy = 0; }
+    else if (r < 2 * HX) { rhx = r - HX; rhy = HY - 1; }
+    else if (r < 2 * HX + HY - 2) { rhx = 0; rhy = 1 + r - 2 * HX; }
+    else { rhx = HX - 1; rhy = 1 + r - 2 * HX - (HY - 2); }
+    const bool has_ring = r < NRING;
+    const int own_h = (ty + 1) * HX + tx + 1, ring_h = rhy * HX + rhx;
+    const T *own_src, *ring_src = zp;
+    int64_t own_step, ring_step = 0;
+    source(tx + 1, ty + 1, own_src, own_step);
+    if (has_ring) source(rhx, rhy, ring_src, ring_step);
+    // two layers in flight: (own, ring) is the next to go to LDS, (own2, ring2) the one after
+    V4<T> own, ring, own2, ring2;
+    auto fetch = [&](bool real) {
+        own2 = ld4(real ? own_src : zp);
+        ring2 = ld4(real ? ring_src : zp);
+        own_src += own_step;
+        ring_src += ring_step;
+    };
+    auto put = [&](int b) {
+        for (int c = 0; c < 4; ++c) lds[b][c][own_h] = own.c[c];
+        if (has_ring)
+            for (int c = 0; c < 4; ++c) lds[b][c][ring_h] = ring.c[c];
+    };
+    auto shift = [&]() {
+        own = own2;
+        ring = ring2;
+    };
+    // panel-edge faces (edge tiles only): at most one xi edge (slot A) and one
+    // eta edge (slot B) per column, each the face's 4 averaged Laplacian fluxes
+    // and its divergence flux
+    const T *slA = zp, *slB = zp;
+    int64_t stA = 0, stB = 0;
+    if (EDGE) {
+        if (sE || sW) { slA = SF + 8 * ghost_ix(n, nr, p, sE ? 1 : 0, k0, jc); stA = 8 * int64_t(n); }
+        if (sN || sS) { slB = SF + 8 * ghost_ix(n, nr, p, sN ? 3 : 2, k0, ic); stB = 8 * int64_t(n); }
+    }
+    const T *xcol = x + 4 * cell_ix(n, nr, p, ic, jc, 0);
+    T *ycol = y + 4 * cell_ix(n, nr, p, ic, jc, k0);
+    T *sink = reinterpret_cast<T *>(g.sink) + 4 * threadIdx.x;
+
+    // prologue: per-layer factors and layers k0, k0+1 into LDS, k0+2 and k0+3 in flight
+    for (int t = threadIdx.x; t < (k1 - k0) * 8; t += NT) layf[t >> 3][t & 7] = T(g.lay[8 * k0 + t]);
+    fetch(true);
+    shift();
+    put(0);
+    fetch(k0 + 1 < k1);
+    shift();
+    put(1);
+    fetch(k0 + 2 < k1);
+    shift();
+    fetch(k0 + 3 < k1);
+    lds_barrier();
+    V4<T> xc, xm;
+    for (int c = 0; c < 4; ++c) xc.c[c] = lds[0][c][own_h];
+    if (k0 > 0) xm = ld4(xcol + 4 * (k0 - 1) * kstride);
+    else xm = wall_ghost(xc, rc.kind, m.nv, T(g.wq2_bot));
 
     for (int k = k0; k < k1; ++k) {
+        const int b = (k - k0) % 3;
+        if (k + 2 < k1) put((b + 2) % 3);  // buffer of layer k-1, free since the last barrier
+        shift();
+        V4<T> la, lb;
+        T da = 0, db = 0;
+        if (EDGE) {
+            la = ld4(slA); da = slA[4];
+            lb = ld4(slB); db = slB[4];
+            slA += stA; slB += stB;
+        }
+        const bool tail = k + 1 == k1 && k + 1 < nr;
+        const V4<T> xg = ld4(tail ? xcol + 4 * (k + 1) * kstride : zp);
+        __builtin_amdgcn_sched_barrier(0);  // the prefetch goes after the loads this layer uses
+        fetch(k + 4 < k1);
+        __builtin_amdgcn_sched_barrier(0);
+        const int b1 = (b + 1) % 3;
         V4<T> xp;
-        if (k + 1 < nr) xp = ld4(x + 4 * (col0 + (k + 1) * kstride));
-        else { const T q = T(g.rk[nr - 1]) / rtop; xp = wall_ghost(xc, rc.kind, nv, q * q); }
-        __syncthreads();
-        for (int h = threadIdx.x; h < HC; h += TX * TY) {
-            const int hx = h % HX, hy = h / HX;
-            const int ii = bx * TX + hx - 1, jj = by * TY + hy - 1;
-            const bool iin = ii >= 0 && ii < n, jin = jj >= 0 && jj < n;
-            V4<T> v = {};
-            if (iin && jin) v = ld4(x + 4 * cell_ix(n, nr, p, ii, jj, k));
-            else if (jin && (ii == -1 || ii == n)) v = ld4(G + 4 * ghost_ix(n, nr, p, ii < 0 ? 0 : 1, k, jj));
-            else if (iin && (jj == -1 || jj == n)) v = ld4(G + 4 * ghost_ix(n, nr, p, jj < 0 ? 2 : 3, k, ii));
-            for (int c = 0; c < 4; ++c) lds[c * HC + h] = v.c[c];
-        }
-        __syncthreads();
-        if (act) {
-            const int hc = (ty + 1) * HX + tx + 1;
-            auto V = [&](int c, int di, int dj) -> T { return lds[c * HC + hc + dj * HX + di]; };
-            const T rk = T(g.rk[k]);
-            const T rp2 = T(g.rf[k + 1]) * T(g.rf[k + 1]), rm2 = T(g.rf[k]) * T(g.rf[k]);
-            const T inv_lat = T(1) / (rk * rk * scc) * ih;
-            const T inv_rad = T(1) / (rk * rk * T(g.hr) * T(g.hr));
-            const T *sfW = SF + 8 * ghost_ix(n, nr, p, 0, k, jc), *sfE = SF + 8 * ghost_ix(n, nr, p, 1, k, jc);
-            const T *sfS = SF + 8 * ghost_ix(n, nr, p, 2, k, ic), *sfN = SF + 8 * ghost_ix(n, nr, p, 3, k, ic);
-            T lap[4];
-            for (int c = 0; c < 4; ++c) {
-                const T v00 = V(c, 0, 0);
-                T oE = a11E * (V(c, 1, 0) - v00) * ih + a12E * (V(c, 0, 1) + V(c, 1, 1) - V(c, 0, -1) - V(c, 1, -1)) * i4h;
-                T oW = -(a11W * (v00 - V(c, -1, 0)) * ih + a12W * (V(c, -1, 1) + V(c, 0, 1) - V(c, -1, -1) - V(c, 0, -1)) * i4h);
-                T oN = a22N * (V(c, 0, 1) - v00) * ih + a12N * (V(c, 1, 0) + V(c, 1, 1) - V(c, -1, 0) - V(c, -1, 1)) * i4h;
-                T oS = -(a22S * (v00 - V(c, 0, -1)) * ih + a12S * (V(c, 1, -1) + V(c, 1, 0) - V(c, -1, -1) - V(c, -1, 0)) * i4h);
-                if (sE) oE = sfE[c];
-                if (sW) oW = sfW[c];
-                if (sN) oN = sfN[c];
-                if (sS) oS = sfS[c];
-                lap[c] = (oE + oW + oN + oS) * inv_lat +
-                         (rp2 * (xp.c[c] - xc.c[c]) - rm2 * (xc.c[c] - xm.c[c])) * inv_rad;
+        for (int c = 0; c < 4; ++c) xp.c[c] = k + 1 < k1 ? lds[b1][c][own_h] : xg.c[c];
+        if (k + 1 == nr) xp = wall_ghost(xc, rc.kind, m.nv, T(g.wq2_top));
+        const T *L = layf[k - k0];
+        const T irk2 = L[1], rm2 = L[2], rp2 = L[3], irad = L[4], hrad = L[5], ir = L[6];
+        auto V = [&](int c, int di, int dj) -> T { return lds[b][c][own_h + dj * HX + di]; };
+        const T inv_lat = irk2 * m.isc;
+        V4<T> out;
+        T lap[4];
+        for (int c = 0; c < 4; ++c) {
+            const T v00 = xc.c[c];
+            T oE = m.a11E * (V(c, 1, 0) - v00) * ih + m.a12E * (V(c, 0, 1) + V(c, 1, 1) - V(c, 0, -1) - V(c, 1, -1)) * i4h;
+            T oW = -(m.a11W * (v00 - V(c, -1, 0)) * ih + m.a12W * (V(c, -1, 1) + V(c, 0, 1) - V(c, -1, -1) - V(c, 0, -1)) * i4h);
+            T oN = m.a22N * (V(c, 0, 1) - v00) * ih + m.a12N * (V(c, 1, 0) + V(c, 1, 1) - V(c, -1, 0) - V(c, -1, 1)) * i4h;
+            T oS = -(m.a22S * (v00 - V(c, 0, -1)) * ih + m.a12S * (V(c, 1, -1) + V(c, 1, 0) - V(c, -1, -1) - V(c, -1, 0)) * i4h);
+            if (EDGE) {  // conservative averaged fluxes on panel-edge faces (selects)
+                oE = sE ? la.c[c] : oE;
+                oW = sW ? la.c[c] : oW;
+                oN = sN ? lb.c[c] : oN;
+                oS = sS ? lb.c[c] : oS;
             }
-            T dE = 0, dW = 0, dN = 0, dS = 0, rup = 0, rdn = 0;
-            for (int d = 0; d < 3; ++d) {
-                const T v00 = V(d, 0, 0);
-                dE += tE[d] * (v00 + V(d, 1, 0));
-                dW += tW[d] * (V(d, -1, 0) + v00);
-                dN += tN[d] * (v00 + V(d, 0, 1));
-                dS += tS[d] * (V(d, 0, -1) + v00);
-                rup += nv[d] * (xc.c[d] + xp.c[d]);
-                rdn += nv[d] * (xm.c[d] + xc.c[d]);
-            }
-            dE *= T(0.5); dW *= T(-0.5); dN *= T(0.5); dS *= T(-0.5);
-            if (sE) dE = sfE[4];
-            if (sW) dW = sfW[4];
-            if (sN) dN = sfN[4];
-            if (sS) dS = sfS[4];
-            const T div = (dE + dW + dN + dS) * rk * inv_lat + T(0.5) * (rp2 * rup - rm2 * rdn) * inv_rad * T(g.hr);
-            V4<T> out;
-            out.c[0] = xc.c[0] - clap * lap[0] - ccor * xc.c[1];
-            out.c[1] = xc.c[1] - clap * lap[1] + ccor * xc.c[0];
-            out.c[2] = xc.c[2] - clap * lap[2];
-            out.c[3] = div - cdt * lap[3];
-            st4(y + 4 * (col0 + k * kstride), out);
+            lap[c] = (oE + oW + oN + oS) * inv_lat + (rp2 * (xp.c[c] - v00) - rm2 * (v00 - xm.c[c])) * irad;
         }
+        T dE = 0, dW = 0, dN = 0, dS = 0, rad = 0;
+        for (int d = 0; d < 3; ++d) {
+            const T v00 = xc.c[d];
+            dE += m.tE[d] * (v00 + V(d, 1, 0));
+            dW += m.tW[d] * (V(d, -1, 0) + v00);
+            dN += m.tN[d] * (v00 + V(d, 0, 1));
+            dS += m.tS[d] * (V(d, 0, -1) + v00);
+            rad += m.nv[d] * (rp2 * (v00 + xp.c[d]) - rm2 * (xm.c[d] + v00));
+        }
+        dE *= T(0.5); dW *= T(-0.5); dN *= T(0.5); dS *= T(-0.5);
+        if (EDGE) {
+            dE = sE ? da : dE;
+            dW = sW ? da : dW;
+            dN = sN ? db : dN;
+            dS = sS ? db : dS;
+        }
+        const T div = (dE + dW + dN + dS) * ir * m.isc + rad * hrad;
+        out.c[0] = xc.c[0] - clap * lap[0] - ccor * xc.c[1];
+        out.c[1] = xc.c[1] - clap * lap[1] + ccor * xc.c[0];
+        out.c[2] = xc.c[2] - clap * lap[2];
+        out.c[3] = div - cdt * lap[3];
+        st4(act ? ycol : sink, out);
+        ycol += 4 * kstride;
         xm = xc;
         xc = xp;
+        lds_barrier();  // layer k+2 visible; every read of buffer b done
     }
+}
+
+template <class T, int TX, int TY>
+__global__ __launch_bounds__(TX *TY) void k_op_main(DevGeom g, RowCoef rc, int kchunk, int nkc,
+                                                    const T *__restrict__ x, const T *__restrict__ G,
+                                                    const T *__restrict__ SF, T *__restrict__ y) {
+    constexpr int HC = (TX + 2) * (TY + 2);
+    __shared__ T lds[3][4][HC];
+    __shared__ T layf[kMaxChunk][8];
+    const int n = g.n, nr = g.nr;
+    const int tilesx = (n + TX - 1) / TX, tiles = tilesx * ((n + TY - 1) / TY);
+    // XCD-aware order: workgroups are dealt round-robin over the 8 XCDs; each
+    // XCD takes a contiguous range of (panel, chunk, tile), so neighbouring
+    // tiles, which share halo cells, meet in the same L2
+    const int nblk = gridDim.x, xcd = blockIdx.x % 8, per = nblk / 8, rem = nblk % 8;
+    const int lid = xcd * per + min(xcd, rem) + blockIdx.x / 8;
+    const int tile = lid % tiles, slab = lid / tiles;
+    const int bx = tile % tilesx, by = tile / tilesx;
+    const int p = slab / nkc, kc = slab % nkc;
+    const int k0 = kc * kchunk, k1 = min(nr, k0 + kchunk);
+    const bool edge_tile = bx == 0 || by == 0 || (bx + 1) * TX >= n || (by + 1) * TY >= n;
+    if (edge_tile) op_march<T, TX, TY, true>(g, rc, p, bx, by, k0, k1, x, G, SF, y, lds, layf);
+    else op_march<T, TX, TY, false>(g, rc, p, bx, by, k0, k1, x, G, SF, y, lds, layf);
 }
 
 template <class T>
@@ -299,19 +408,24 @@ static int32_t launch_all(const csdyn_opctx *ctx, const T *x, T *y, T *G, T *SF,
     }
     ProfScope ps(sizeof(T) == 8 ? "op_main" : "op_main_f32", 6 * int64_t(n) * n * nr,
                  6.0 * n * n * nr * 8 * sizeof(T), s);  // x read once, y written once
-    const int tile = ctx->tile ? ctx->tile : (n >= 32 ? 1 : 2);
+    const int tile = ctx->tile ? ctx->tile : 4;
     auto go = [&](auto tx_c, auto ty_c) {
         constexpr int TX = decltype(tx_c)::value, TY = decltype(ty_c)::value;
         const int tiles = ((n + TX - 1) / TX) * ((n + TY - 1) / TY);
-        int nkc = std::max(1, std::min(nr, (2048 + 6 * tiles - 1) / (6 * tiles)));
+        const int target = 2048 * 256 / (TX * TY);  // workgroups over the k-chunks
+        int nkc = std::max(1, std::min(nr, (target + 6 * tiles - 1) / (6 * tiles)));
+        nkc = std::max(nkc, (nr + kMaxChunk - 1) / kMaxChunk);
         const int kchunk = (nr + nkc - 1) / nkc;
         nkc = (nr + kchunk - 1) / kchunk;
-        hipLaunchKernelGGL((k_op_main<T, TX, TY>), dim3(tiles, 6 * nkc), dim3(TX * TY), 0, s, g, rc, kchunk, nkc, x,
-                           (const T *)G, (const T *)SF, y);
+        hipLaunchKernelGGL((k_op_main<T, TX, TY>), dim3(tiles * 6 * nkc), dim3(TX * TY), 0, s, g, rc, kchunk, nkc,
+                           x, (const T *)G, (const T *)SF, y);
     };
-    if (tile == 1) go(std::integral_constant<int, 32>(), std::integral_constant<int, 8>());
-    else if (tile == 2) go(std::integral_constant<int, 16>(), std::integral_constant<int, 16>());
-    else go(std::integral_constant<int, 64>(), std::integral_constant<int, 4>());
+    using std::integral_constant;
+    if (tile == 1) go(integral_constant<int, 32>(), integral_constant<int, 8>());
+    else if (tile == 2) go(integral_constant<int, 16>(), integral_constant<int, 16>());
+    else if (tile == 3) go(integral_constant<int, 64>(), integral_constant<int, 4>());
+    else if (tile == 4) go(integral_constant<int, 16>(), integral_constant<int, 8>());
+    else go(integral_constant<int, 32>(), integral_constant<int, 4>());
     CSD_HIP(hipGetLastError());
     return CSDYN_OK;
 }
@@ -415,7 +529,7 @@ extern "C" int32_t csdyn_project(const csdyn_opctx *ctx, const double *x, double
 
 extern "C" int32_t csdyn_op_set_tile(csdyn_opctx *ctx, int32_t tile) {
     clear_error();
-    if (!ctx || tile < 0 || tile > 3) { set_error("csdyn_op_set_tile: tile must be 0..3"); return CSDYN_EINVAL; }
+    if (!ctx || tile < 0 || tile > 5) { set_error("csdyn_op_set_tile: tile must be 0..5"); return CSDYN_EINVAL; }
     ctx->tile = tile;
     return CSDYN_OK;
 }

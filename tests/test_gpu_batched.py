@@ -74,7 +74,7 @@ def test_batched_rejects_two_level():
         csdyn.Batch([op], [pc])
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5])
 def test_operator_tiles_agree(tile):
     import torch
     from paper_2009_02171_amd import csdyn
