@@ -53,6 +53,24 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel_key):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs (profiles/traffic.json, calibrated); None when the kernel's
+    sources have changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path)).get(kernel_key)
+    except (OSError, ValueError):
+        return None
+    if not rec:
+        return None
+    h = hashlib.sha1()
+    for f in rec["sources"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return rec["hbm_bytes_per_launch"] if h.hexdigest() == rec["sources_sha1"] else None
+
+
 def cpu_baseline(wl_name: str, gpu_iters: dict):
     """Oracle (plain C, one thread) on a bounded sample of the workload."""
     import numpy as np  # noqa: F401
@@ -222,7 +240,7 @@ def main():
         },
         "roofline": {"kernel": f"{dom_name[0]}@{dom_name[1]}", "bound": "hbm", "achieved": round(dom_gbs, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(dom_gbs / HBM_PEAK_GBS, 4),
-                     "traffic": None,
+                     "traffic": measured_traffic(f"{dom_name[0]}@{dom_name[1]}"),
                      "avg_us": round(dom["ms"] / dom["count"] * 1e3, 2),
                      "alg_bytes_per_launch": round(dom["bytes"] / dom["count"])},
         "operator": operator,
