@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "common.h"
 #include "conv.h"
@@ -56,32 +57,54 @@ __device__ inline Vox decode(int64_t v, const ConvDims &a) {
 }
 
 // --------------------------------------------------------------- forward
-// One wave: 32 voxels (two 16-row fragments) x all 16*NB output channels.
-template <int NB>
+// One workgroup: 4 waves x (16 MF voxels) x all 16 NB output channels.  The
+// weights of each 32-wide K slab are staged once per workgroup in LDS (double
+// buffered) and shared by the four waves; the input fragments come straight
+// from the channels-last tensor (16 bytes per lane).
+constexpr int kFwSW = 32 + 8;  // LDS row stride of a weight slab (16-bit elements)
+
+template <int NB, int MF>
 __global__ __launch_bounds__(256) void k_conv_fwd(ConvDims a, const uint16_t *__restrict__ x,
                                                   const uint16_t *__restrict__ wf, const float *__restrict__ bias,
                                                   const uint16_t *__restrict__ res, const uint16_t *__restrict__ mask,
                                                   int relu, uint16_t *__restrict__ y, float *__restrict__ y32) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __shared__ __align__(16) uint16_t sW[2][16 * NB * kFwSW];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, g = lane >> 4;
-    const int64_t base = (int64_t(blockIdx.x) * 4 + wave) * 32;
-    Vox vx[2];
-    bool ok[2];
-    for (int f = 0; f < 2; ++f) {
+    const int64_t base = (int64_t(blockIdx.x) * 4 + wave) * (16 * MF);
+    Vox vx[MF];
+    bool ok[MF];
+#pragma unroll
+    for (int f = 0; f < MF; ++f) {
         const int64_t v = base + f * 16 + r;
         ok[f] = v < a.nvox;
         vx[f] = decode(ok[f] ? v : 0, a);
     }
-    f32x4 acc[2][NB];
-    for (int f = 0; f < 2; ++f)
+    f32x4 acc[MF][NB];
+#pragma unroll
+    for (int f = 0; f < MF; ++f)
+#pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[f][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-    for (int k0 = 0; k0 < a.kpad; k0 += 32) {
-        const int k = k0 + 8 * g;
+    // slab loader: 16 NB rows x 32 k = 4 NB 16-byte pieces
+    auto stage = [&](int buf, int k0) {
+        for (int e = tid; e < 64 * NB; e += 256) {
+            const int row = e >> 2, piece = e & 3;
+            *reinterpret_cast<u32x4 *>(&sW[buf][row * kFwSW + 8 * piece]) =
+                *reinterpret_cast<const u32x4 *>(wf + size_t(row) * a.kpad + k0 + 8 * piece);
+        }
+    };
+    const int nk = a.kpad / 32;
+    stage(0, 0);
+    __syncthreads();
+    for (int kc = 0; kc < nk; ++kc) {
+        const int buf = kc & 1;
+        if (kc + 1 < nk) stage(buf ^ 1, (kc + 1) * 32);  // next slab, read only after the barrier below
+        const int k = kc * 32 + 8 * g;
         const int tap = k / a.ci8, c = k - tap * a.ci8;
-        u32x4 af[2];
         const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-        for (int f = 0; f < 2; ++f) {
+        u32x4 af[MF];
+#pragma unroll
+        for (int f = 0; f < MF; ++f) {
             const int d = vx[f].d + dz, h = vx[f].h + dy, w = vx[f].w + dx;
             const bool in = ok[f] && tap < 27 && d >= 0 && d < a.d && h >= 0 && h < a.h && w >= 0 && w < a.w;
             af[f] = u32x4{0u, 0u, 0u, 0u};
@@ -90,17 +113,22 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvDims a, const uint16_t *__
                 af[f] = *reinterpret_cast<const u32x4 *>(x + src * a.ci8 + c);
             }
         }
+#pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-            const u32x4 bf = *reinterpret_cast<const u32x4 *>(wf + size_t(nb * 16 + r) * a.kpad + k);
-            acc[0][nb] = mfma(af[0], bf, acc[0][nb]);
-            acc[1][nb] = mfma(af[1], bf, acc[1][nb]);
+            const u32x4 bf = *reinterpret_cast<const u32x4 *>(&sW[buf][(nb * 16 + r) * kFwSW + 8 * g]);
+#pragma unroll
+            for (int f = 0; f < MF; ++f) acc[f][nb] = mfma(af[f], bf, acc[f][nb]);
         }
+        __syncthreads();  // slab kc consumed by every wave; slab kc+1 complete
     }
 
-    for (int f = 0; f < 2; ++f)
+#pragma unroll
+    for (int f = 0; f < MF; ++f)
+#pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int64_t v = base + f * 16 + 4 * g + i;
             if (v >= a.nvox) continue;
+#pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
                 const int co = nb * 16 + r;
                 float val = 0.f;
@@ -118,66 +146,74 @@ __global__ __launch_bounds__(256) void k_conv_fwd(ConvDims a, const uint16_t *__
 }
 
 // -------------------------------------------------------- weight gradient
-// One wave: 16*MF rows (cout) x 64 columns (t, c) of dW, summed over the
-// 32-voxel chunks chunk = split, split + nsplit, ...
-template <int MF>
-__global__ __launch_bounds__(64) void k_conv_bwdw(ConvDims a, const uint16_t *__restrict__ x,
-                                                  const uint16_t *__restrict__ dy, int kcols, int nsplit,
-                                                  float *__restrict__ partial) {
-    const int lane = threadIdx.x;
-    const int r = lane & 15, g = lane >> 4;
-    const int rowbase = blockIdx.y * 16 * MF, colbase = blockIdx.x * 64;
-    const int copad = gridDim.y * 16 * MF;
-    int tap[4], cc[4], odz[4], ody[4], odx[4];
-    for (int nf = 0; nf < 4; ++nf) {
-        const int col = colbase + nf * 16 + r;
-        tap[nf] = col / a.ci8;
-        cc[nf] = col - tap[nf] * a.ci8;
-        odz[nf] = tap[nf] / 9 - 1;
-        ody[nf] = (tap[nf] / 3) % 3 - 1;
-        odx[nf] = tap[nf] % 3 - 1;
-    }
-    f32x4 acc[MF][4];
-    for (int mf = 0; mf < MF; ++mf)
-        for (int nf = 0; nf < 4; ++nf) acc[mf][nf] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int64_t nchunks = (a.nvox + 31) / 32;
+// dW[co][k] = sum_v dY[v][co] X[v + off(t(k))][c(k)]: a GEMM over voxels.  One
+// workgroup owns all output-channel rows x 64 consecutive K columns and sums a
+// strided set of 64-voxel chunks.  Each chunk is staged through LDS transposed
+// ([row][voxel], voxels contiguous), so every MFMA operand is one 16-byte LDS
+// read; wave w takes column fragment w and all row fragments.
+constexpr int kBwVC = 64;          // voxels per chunk
+constexpr int kBwSA = kBwVC + 8;   // LDS row stride in 16-bit elements (spreads banks)
+
+template <int NRF>
+__global__ __launch_bounds__(256) void k_conv_bwdw(ConvDims a, const uint16_t *__restrict__ x,
+                                                   const uint16_t *__restrict__ dy, int kcols, int nsplit,
+                                                   float *__restrict__ partial) {
+    constexpr int COPAD = 16 * NRF;
+    __shared__ __align__(16) uint16_t sA[COPAD * kBwSA];  // dY^T  [co][v]
+    __shared__ __align__(16) uint16_t sB[64 * kBwSA];     // X_k^T [col][v]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, r = lane & 15, g = lane >> 4;
+    const int colbase = blockIdx.x * 64;
+    // rows beyond the tensor's channels stay zero
+    for (int e = tid; e < (COPAD - a.co8) * kBwSA; e += 256) sA[a.co8 * kBwSA + e] = 0;
+    f32x4 acc[NRF];
+    for (int f = 0; f < NRF; ++f) acc[f] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int cgA = a.co8 / 8;  // 8-channel groups of dY
+    const int64_t nchunks = (a.nvox + kBwVC - 1) / kBwVC;
     for (int64_t chunk = blockIdx.z; chunk < nchunks; chunk += nsplit) {
-        const int64_t v0 = chunk * 32 + 8 * g;
-        Vox q = decode(v0 < a.nvox ? v0 : 0, a);
-        uint16_t av[MF][8], bv[4][8];
-        for (int j = 0; j < 8; ++j) {
-            const int64_t v = v0 + j;
-            const bool ok = v < a.nvox;
-            for (int mf = 0; mf < MF; ++mf) {
-                const int co = rowbase + mf * 16 + r;
-                av[mf][j] = (ok && co < a.co8) ? dy[v * a.co8 + co] : uint16_t(0);
-            }
-            for (int nf = 0; nf < 4; ++nf) {
-                const int d = q.d + odz[nf], h = q.h + ody[nf], w = q.w + odx[nf];
-                const bool in = ok && tap[nf] < 27 && d >= 0 && d < a.d && h >= 0 && h < a.h && w >= 0 && w < a.w;
-                bv[nf][j] = in ? x[(((int64_t(q.p) * a.d + d) * a.h + h) * a.w + w) * a.ci8 + cc[nf]] : uint16_t(0);
-            }
-            if (++q.w == a.w) {
-                q.w = 0;
-                if (++q.h == a.h) {
-                    q.h = 0;
-                    if (++q.d == a.d) { q.d = 0; ++q.p; }
-                }
+        const int64_t v0 = chunk * kBwVC;
+        for (int e = tid; e < kBwVC * cgA; e += 256) {
+            const int vv = e / cgA, cg = e - vv * cgA;
+            const int64_t v = v0 + vv;
+            u32x4 q = u32x4{0u, 0u, 0u, 0u};
+            if (v < a.nvox) q = *reinterpret_cast<const u32x4 *>(dy + v * a.co8 + cg * 8);
+            for (int h = 0; h < 4; ++h) {
+                sA[(cg * 8 + 2 * h) * kBwSA + vv] = uint16_t(q[h] & 0xFFFFu);
+                sA[(cg * 8 + 2 * h + 1) * kBwSA + vv] = uint16_t(q[h] >> 16);
             }
         }
-        u32x4 A[MF], B[4];
-        for (int mf = 0; mf < MF; ++mf)
-            for (int e = 0; e < 4; ++e) A[mf][e] = uint32_t(av[mf][2 * e]) | (uint32_t(av[mf][2 * e + 1]) << 16);
-        for (int nf = 0; nf < 4; ++nf)
-            for (int e = 0; e < 4; ++e) B[nf][e] = uint32_t(bv[nf][2 * e]) | (uint32_t(bv[nf][2 * e + 1]) << 16);
-        for (int mf = 0; mf < MF; ++mf)
-            for (int nf = 0; nf < 4; ++nf) acc[mf][nf] = mfma(A[mf], B[nf], acc[mf][nf]);
+        for (int e = tid; e < kBwVC * 8; e += 256) {
+            const int vv = e >> 3, cg = e & 7;
+            const int col0 = colbase + cg * 8;
+            const int tap = col0 / a.ci8, c = col0 - tap * a.ci8;
+            const int64_t v = v0 + vv;
+            u32x4 q = u32x4{0u, 0u, 0u, 0u};
+            if (v < a.nvox && tap < 27) {
+                const Vox o = decode(v, a);
+                const int d = o.d + tap / 9 - 1, hh = o.h + (tap / 3) % 3 - 1, w = o.w + tap % 3 - 1;
+                if (d >= 0 && d < a.d && hh >= 0 && hh < a.h && w >= 0 && w < a.w)
+                    q = *reinterpret_cast<const u32x4 *>(
+                        x + (((int64_t(o.p) * a.d + d) * a.h + hh) * a.w + w) * a.ci8 + c);
+            }
+            for (int h = 0; h < 4; ++h) {
+                sB[(cg * 8 + 2 * h) * kBwSA + vv] = uint16_t(q[h] & 0xFFFFu);
+                sB[(cg * 8 + 2 * h + 1) * kBwSA + vv] = uint16_t(q[h] >> 16);
+            }
+        }
+        __syncthreads();
+        for (int ks = 0; ks < kBwVC / 32; ++ks) {
+            const int vo = ks * 32 + 8 * g;
+            const u32x4 B = *reinterpret_cast<const u32x4 *>(&sB[(wave * 16 + r) * kBwSA + vo]);
+            for (int f = 0; f < NRF; ++f) {
+                const u32x4 A = *reinterpret_cast<const u32x4 *>(&sA[(f * 16 + r) * kBwSA + vo]);
+                acc[f] = mfma(A, B, acc[f]);
+            }
+        }
+        __syncthreads();
     }
-    float *out = partial + size_t(blockIdx.z) * copad * kcols;
-    for (int mf = 0; mf < MF; ++mf)
-        for (int nf = 0; nf < 4; ++nf)
-            for (int i = 0; i < 4; ++i)
-                out[size_t(rowbase + mf * 16 + 4 * g + i) * kcols + colbase + nf * 16 + r] = acc[mf][nf][i];
+    float *out = partial + size_t(blockIdx.z) * COPAD * kcols;
+    for (int f = 0; f < NRF; ++f)
+        for (int i = 0; i < 4; ++i)
+            out[size_t(f * 16 + 4 * g + i) * kcols + colbase + wave * 16 + r] = acc[f][i];
 }
 
 // dW[co][t][c] = sum over splits, in split order.
@@ -326,14 +362,21 @@ int32_t conv_fwd_launch(const ConvDims &a, const uint16_t *x, const uint16_t *wf
                         const uint16_t *res, const uint16_t *mask, int relu, uint16_t *y, float *y32, hipStream_t s,
                         const char *name) {
     const int nbk = rup(a.co, 16) / 16;
-    const dim3 grid(unsigned((a.nvox + 127) / 128)), block(256);
     ProfScope ps(name, a.nvox, double(a.nvox) * 2.0 * (a.ci + a.co), s, 2.0 * a.nvox * a.co * 27.0 * a.ci);
-#define CONV_CASE(NB)                                                                                    \
-    case NB:                                                                                             \
-        hipLaunchKernelGGL(k_conv_fwd<NB>, grid, block, 0, s, a, x, wf, bias, res, mask, relu, y, y32); \
+    // four row fragments per wave (256 voxels per workgroup), two for the widest outputs
+    auto go = [&](auto nb_c, auto mf_c) {
+        constexpr int NB = decltype(nb_c)::value, MF = decltype(mf_c)::value;
+        const dim3 grid(unsigned((a.nvox + 64 * MF - 1) / (64 * MF)));
+        hipLaunchKernelGGL((k_conv_fwd<NB, MF>), grid, dim3(256), 0, s, a, x, wf, bias, res, mask, relu, y, y32);
+    };
+    using std::integral_constant;
+#define CONV_CASE(NB, MF)                                             \
+    case NB:                                                          \
+        go(integral_constant<int, NB>(), integral_constant<int, MF>()); \
         break;
     switch (nbk) {
-        CONV_CASE(1) CONV_CASE(2) CONV_CASE(3) CONV_CASE(4) CONV_CASE(5) CONV_CASE(6) CONV_CASE(7) CONV_CASE(8)
+        CONV_CASE(1, 4) CONV_CASE(2, 4) CONV_CASE(3, 4) CONV_CASE(4, 4) CONV_CASE(5, 2) CONV_CASE(6, 2)
+        CONV_CASE(7, 2) CONV_CASE(8, 2)
         default: set_error("conv: cout %d unsupported", a.co); return CSDYN_EINVAL;
     }
 #undef CONV_CASE
@@ -349,19 +392,17 @@ int32_t conv_bwd_data_launch(const ConvDims &a, const uint16_t *dy, const uint16
 }
 
 struct BwdwPlan {
-    int mf, rowblocks, colblocks, kcols, copad, nsplit;
+    int nrf, copad, colblocks, kcols, nsplit;
     size_t partial_bytes, colsum_bytes;
 };
 static BwdwPlan bwdw_plan(const ConvDims &a) {
     BwdwPlan p;
-    p.mf = a.co8 > 16 ? 2 : 1;
-    p.copad = rup(a.co8, 16 * p.mf);
-    p.rowblocks = p.copad / (16 * p.mf);
+    p.copad = rup(a.co8, 16);
+    p.nrf = p.copad / 16;
     p.kcols = rup(27 * a.ci8, 64);
     p.colblocks = p.kcols / 64;
-    const int64_t nchunks = (a.nvox + 31) / 32;
-    const int64_t tiles = int64_t(p.rowblocks) * p.colblocks;
-    int64_t ns = std::max<int64_t>(1, 4096 / tiles);
+    const int64_t nchunks = (a.nvox + kBwVC - 1) / kBwVC;
+    int64_t ns = std::max<int64_t>(1, 2048 / p.colblocks);
     ns = std::min<int64_t>(ns, std::max<int64_t>(1, nchunks / 4));
     const size_t per = size_t(p.copad) * p.kcols * sizeof(float);
     ns = std::min<int64_t>(ns, std::max<int64_t>(1, int64_t((size_t(256) << 20) / per)));
@@ -389,11 +430,16 @@ int32_t conv_bwd_weight_launch(const ConvDims &a, const uint16_t *x, const uint1
     {
         ProfScope ps("conv_bwd_weight", a.nvox, double(a.nvox) * 2.0 * (a.ci8 + a.co8), s,
                      2.0 * a.nvox * a.co * 27.0 * a.ci);
-        const dim3 grid(p.colblocks, p.rowblocks, p.nsplit);
-        if (p.mf == 2)
-            hipLaunchKernelGGL(k_conv_bwdw<2>, grid, dim3(64), 0, s, a, x, dy, p.kcols, p.nsplit, partial);
-        else
-            hipLaunchKernelGGL(k_conv_bwdw<1>, grid, dim3(64), 0, s, a, x, dy, p.kcols, p.nsplit, partial);
+        const dim3 grid(p.colblocks, 1, p.nsplit);
+#define BWDW_CASE(NRF)                                                                                 \
+    case NRF:                                                                                          \
+        hipLaunchKernelGGL(k_conv_bwdw<NRF>, grid, dim3(256), 0, s, a, x, dy, p.kcols, p.nsplit, partial); \
+        break;
+        switch (p.nrf) {
+            BWDW_CASE(1) BWDW_CASE(2) BWDW_CASE(3) BWDW_CASE(4) BWDW_CASE(5) BWDW_CASE(6) BWDW_CASE(7) BWDW_CASE(8)
+            default: set_error("conv bwd_weight: cout %d unsupported", a.co); return CSDYN_EINVAL;
+        }
+#undef BWDW_CASE
         CSD_HIP(hipGetLastError());
         const int64_t n = int64_t(a.co) * 27 * a.ci;
         hipLaunchKernelGGL(k_bwdw_reduce, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, a, partial, p.kcols,
