@@ -49,19 +49,48 @@ __device__ __forceinline__ void block_store(T (&acc)[kRedStride], int cnt_total,
     }
 }
 
+// 16-byte vectors of T: the orthogonalisation kernels stream the basis with
+// one 16-byte load per vector and element pair (FP64) or quad (FP32); every
+// vector length is a multiple of 24, so the width always divides it.
+template <class T>
+struct Vec16;
+template <>
+struct Vec16<double> {
+    using type = double2;
+    static constexpr int W = 2;
+    __device__ static double get(const double2 &v, int e) { return e == 0 ? v.x : v.y; }
+    __device__ static void set(double2 &v, int e, double a) { (e == 0 ? v.x : v.y) = a; }
+};
+template <>
+struct Vec16<float> {
+    using type = float4;
+    static constexpr int W = 4;
+    __device__ static float get(const float4 &v, int e) { return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w; }
+    __device__ static void set(float4 &v, int e, float a) { (e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w) = a; }
+};
+
 template <class T>
 __global__ __launch_bounds__(kBlk) void k_mdot(const T *__restrict__ V, int64_t n, int cnt, const T *__restrict__ w,
                                                T *__restrict__ partial) {
+    using VT = typename Vec16<T>::type;
+    constexpr int W = Vec16<T>::W;
     T acc[kRedStride];
 #pragma unroll
     for (int q = 0; q < kRedStride; ++q) acc[q] = 0;
-    const int64_t stride = int64_t(gridDim.x) * kBlk;
-    for (int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x; i < n; i += stride) {
-        const T wv = w[i];
+    const int64_t nv = n / W, stride = int64_t(gridDim.x) * kBlk;
+    const VT *Vv = reinterpret_cast<const VT *>(V);
+    const VT *wv4 = reinterpret_cast<const VT *>(w);
+    for (int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x; i < nv; i += stride) {
+        const VT wv = wv4[i];
 #pragma unroll
         for (int q = 0; q < kRedStride - 1; ++q)
-            if (q < cnt) acc[q] += V[int64_t(q) * n + i] * wv;
-        acc[kRedStride - 1] += wv * wv;
+            if (q < cnt) {
+                const VT v = Vv[int64_t(q) * nv + i];
+#pragma unroll
+                for (int e = 0; e < W; ++e) acc[q] += Vec16<T>::get(v, e) * Vec16<T>::get(wv, e);
+            }
+#pragma unroll
+        for (int e = 0; e < W; ++e) acc[kRedStride - 1] += Vec16<T>::get(wv, e) * Vec16<T>::get(wv, e);
     }
     block_store(acc, cnt, partial);
 }
@@ -69,20 +98,29 @@ __global__ __launch_bounds__(kBlk) void k_mdot(const T *__restrict__ V, int64_t 
 template <class T>
 __global__ __launch_bounds__(kBlk) void k_mupdate(T *__restrict__ w, const T *__restrict__ V, int64_t n, int cnt,
                                                   const T *__restrict__ h, T *__restrict__ partial) {
+    using VT = typename Vec16<T>::type;
+    constexpr int W = Vec16<T>::W;
     T hq[kRedStride - 1];
 #pragma unroll
     for (int q = 0; q < kRedStride - 1; ++q) hq[q] = q < cnt ? h[q] : T(0);
     T acc[kRedStride];
 #pragma unroll
     for (int q = 0; q < kRedStride; ++q) acc[q] = 0;
-    const int64_t stride = int64_t(gridDim.x) * kBlk;
-    for (int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x; i < n; i += stride) {
-        T wv = w[i];
+    const int64_t nv = n / W, stride = int64_t(gridDim.x) * kBlk;
+    const VT *Vv = reinterpret_cast<const VT *>(V);
+    VT *wv4 = reinterpret_cast<VT *>(w);
+    for (int64_t i = int64_t(blockIdx.x) * kBlk + threadIdx.x; i < nv; i += stride) {
+        VT wv = wv4[i];
 #pragma unroll
         for (int q = 0; q < kRedStride - 1; ++q)
-            if (q < cnt) wv -= hq[q] * V[int64_t(q) * n + i];
-        w[i] = wv;
-        acc[kRedStride - 1] += wv * wv;
+            if (q < cnt) {
+                const VT v = Vv[int64_t(q) * nv + i];
+#pragma unroll
+                for (int e = 0; e < W; ++e) Vec16<T>::set(wv, e, Vec16<T>::get(wv, e) - hq[q] * Vec16<T>::get(v, e));
+            }
+        wv4[i] = wv;
+#pragma unroll
+        for (int e = 0; e < W; ++e) acc[kRedStride - 1] += Vec16<T>::get(wv, e) * Vec16<T>::get(wv, e);
     }
     block_store(acc, 0, partial);
 }
