@@ -6,8 +6,11 @@
 // into a scratch vector, runs the L sweep and then the U sweep level by
 // level (a workgroup barrier between levels; the rows of one level are
 // independent), and writes only the owned cells (restricted scatter, so the
-// writes of different workgroups are disjoint).  Each wavefront takes one
-// 64-row slice of a level: entry q of all 64 rows is one coalesced load.
+// writes of different workgroups are disjoint).  A wavefront works on slices
+// of 64 lanes (a lane holds at most eight entries of a row; wider rows are
+// split over adjacent lanes), reads a lane's entries with 16-byte loads, and
+// requests its next slices a group ahead, so that one level's critical path
+// is LDS reads, a short FMA chain and a barrier rather than a memory latency.
 #include <algorithm>
 #include <cstring>
 #include <memory>
@@ -20,88 +23,92 @@
 namespace csd {
 
 template <class TF>
+struct Pair;
+template <>
+struct Pair<double> {
+    using type = double2;
+};
+template <>
+struct Pair<float> {
+    using type = float2;
+};
+
+// Device view of one SweepPack (ras_host.h gives the layouts).
+template <class TF>
 struct DevSweep {
+    using TF2 = typename Pair<TF>::type;
     const int32_t *lev_slice;  // [nlev + 1] first slice of each level
-    const int32_t *sl_w;       // [nslice] entries per lane
-    const int64_t *sl_off;     // [nslice]
+    const int32_t *sl_info;    // [nslice] rows << 10 | (s - 1) << 4 | entries per lane
+    const int64_t *sl_off;     // [nslice] first value pair
+    const int32_t *sl_slot;    // [nslice] ring slot of the first row
     const int32_t *lane_io;    // [nslice*64] L: x index; U: y index of owned rows; else -1
     const int32_t *lane_next;  // [nslice*64] L: U-sweep position of the row
-    const TF *lane_dinv;       // [nslice*64] U: 1/u_ii (0 on padding lanes)
-    const TF *val;             // [entries]
-    const uint16_t *addr;      // [entries] ring slot of the dependency
+    const TF2 *val;            // [pairs] factor entries, two per lane
+    const uint4 *addr;         // [64 * nslice] ring slots of the dependencies, eight per lane
 };
 
 template <class TF>
 struct DevRas {
+    using TF2 = typename Pair<TF>::type;
     const SdInfo *sd;
     DevSweep<TF> L, U;
     TF *lin;    // [L slices * 64] gathered inputs of the L sweep
-    TF *lout;   // [U slices * 64] L-sweep results in U-sweep order
+    TF2 *lout;  // [U slices * 64] {L-sweep result, 1/u_ii} in U-sweep order (0 where never written)
     TF *ring;   // [nsd][depth * width] when the ring is not in LDS
     int depth, width;
 };
 
-constexpr int kChunk = 16;  // factor entries per lane held in registers at once
-
-// Per-lane data of one slice.  None of it depends on values computed in the
-// sweep (inputs were gathered before, addresses and factors are constant), so
-// the next level's is requested before the barrier that ends a level.
+// One item of a sweep: one slice for one lane, i.e. the lane's part (at most
+// eight entries) of its row: values in pairs, 16-bit ring slots two to a
+// register, the row's {input value, 1/u_ii} and output index, and the
+// slice's wave-uniform description.  Nothing in it depends on values computed
+// in the sweep (inputs were gathered before, addresses and factors are
+// constant), so each wavefront requests its items well ahead of use; the
+// loads stay in flight across the LDS-scoped barriers between levels.
 template <class TF>
-struct Lane {
-    int w;
-    int64_t base;
-    int32_t io;      // L: U position of the row; U: y index or -1
-    TF v0, dinv;
-    int32_t addr[kChunk];
-    TF val[kChunk];
+struct Item {
+    using TF2 = typename Pair<TF>::type;
+    uint32_t addr[4];
+    TF2 val[4];
+    TF2 h;
+    int32_t io;    // L: U position of the row; U: y index or -1
+    int32_t wl;    // level << 17 | sl_info; -1 past the wavefront's last slice
+    int32_t slot;  // ring slot of the slice's first row
 };
 
-template <class TF>
-__device__ __forceinline__ void load_entries(const DevSweep<TF> &S, int q0, Lane<TF> &L) {
-#pragma unroll
-    for (int q = 0; q < kChunk; ++q) {
-        if (q0 + q < L.w) {
-            const int64_t at = L.base + int64_t(q0 + q) * 64;
-            L.addr[q] = S.addr[at];
-            L.val[q] = S.val[at];
-        } else {
-            L.addr[q] = 0;
-            L.val[q] = TF(0);
-        }
-    }
-}
-
-template <class TF, bool UPPER>
-__device__ __forceinline__ void fetch_lane(const DevSweep<TF> &S, const int32_t *mw, const int64_t *moff, int sl0,
-                                           int sl, const TF *in, Lane<TF> &L) {
+// Seven loads per item whatever the slice (pairs past the slice's width
+// re-read its last pair; consume() masks them), so the memory counters always
+// hold the later items' loads in the same order and the wait for one group
+// of items never waits for the next.
+// rec: the L sweep's gathered inputs (TF) or the U sweep's records (TF2).
+template <class TF, bool UPPER, class Rec>
+__device__ __forceinline__ void fetch_item(const DevSweep<TF> &S, const Rec *rec, int64_t gpos, int64_t off, int w,
+                                           Item<TF> &X) {
     const int lane = threadIdx.x % 64;
-    const int64_t gpos = int64_t(sl0 + sl) * 64 + lane;
-    L.w = mw[sl];
-    L.base = moff[sl] + lane;
-    L.v0 = in[gpos];
-    if constexpr (UPPER) {
-        L.io = S.lane_io[gpos];
-        L.dinv = S.lane_dinv[gpos];
-    } else {
-        L.io = S.lane_next[gpos];
-    }
-    load_entries(S, 0, L);
+    if constexpr (UPPER) X.h = rec[gpos];
+    else X.h.x = rec[gpos];
+    X.io = UPPER ? S.lane_io[gpos] : S.lane_next[gpos];
+    const int lastp = w > 0 ? (w - 1) / 2 : 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) X.val[j] = S.val[off + int64_t(min(j, lastp)) * 64 + lane];
+    const uint4 a = S.addr[gpos];
+    X.addr[0] = a.x; X.addr[1] = a.y; X.addr[2] = a.z; X.addr[3] = a.w;
 }
 
 template <class TF>
-__device__ __forceinline__ TF consume(const Lane<TF> &L, int q0, const TF *ring, TF acc) {
-    TF tv[kChunk];
+__device__ __forceinline__ TF consume(const Item<TF> &X, int w, const TF *ring, TF acc) {
+    TF tv[8];
 #pragma unroll
-    for (int q = 0; q < kChunk; ++q) tv[q] = q0 + q < L.w ? ring[L.addr[q]] : TF(0);
+    for (int q = 0; q < 8; ++q) tv[q] = ring[(X.addr[q / 2] >> (16 * (q % 2))) & 0xffffu];
 #pragma unroll
-    for (int q = 0; q < kChunk; ++q) acc -= L.val[q] * tv[q];
+    for (int q = 0; q < 8; ++q) acc -= (q < w ? (q % 2 ? X.val[q / 2].y : X.val[q / 2].x) : TF(0)) * tv[q];
     return acc;
 }
 
 // Barrier between levels.  When the ring is in LDS only LDS traffic has to be
-// complete, so the fence is LDS-scoped: global loads issued before it (the
-// next level's data) stay in flight.  On this GPU family a full fence would
-// also wait for every outstanding global load.
+// complete, so the fence is LDS-scoped: global loads issued before it (later
+// items) stay in flight.  On this GPU family a full fence would also wait for
+// every outstanding global load.
 template <bool LDS_ONLY>
 __device__ __forceinline__ void level_barrier() {
     if constexpr (LDS_ONLY) {
@@ -113,64 +120,136 @@ __device__ __forceinline__ void level_barrier() {
     }
 }
 
-// One triangular sweep of one subdomain, level by level (the rows of a level
-// are independent; a barrier separates levels).  Wavefront wv takes the
-// slices wv, wv + nwaves, ... of a level.  A row's result goes to its ring
-// slot and, in the L sweep, to its U-sweep position; the U sweep writes the
-// owned rows to y (restricted scatter).
-template <class TV, class TF, bool UPPER, bool LDS, int NT>
-__device__ __forceinline__ void sweep(const DevSweep<TF> &S, const int32_t *mlev, const int32_t *mw,
-                                      const int64_t *moff, int sl0, int nlev, TF *ring, int depth, int width,
-                                      const TF *in, TF *lout, TV *y) {
-    const int lane = threadIdx.x % 64, wv = threadIdx.x / 64, nw = NT / 64;
-    Lane<TF> L;
-    bool have = false;
-    if (nlev > 0 && mlev[0] + wv < mlev[1]) { fetch_lane<TF, UPPER>(S, mw, moff, sl0, mlev[0] + wv, in, L); have = true; }
-    for (int lv = 0; lv < nlev; ++lv) {
-        const int s0 = mlev[lv], s1 = mlev[lv + 1];
-        TF *slot_base = ring + (lv % depth) * width + lane;
-        for (int sl = s0 + wv; sl < s1; sl += nw) {
-            if (!have) fetch_lane<TF, UPPER>(S, mw, moff, sl0, sl, in, L);
-            have = false;
-            TF acc = consume(L, 0, ring, L.v0);
-            for (int q0 = kChunk; q0 < L.w; q0 += kChunk) {
-                load_entries(S, q0, L);
-                acc = consume(L, q0, ring, acc);
-            }
-            if constexpr (UPPER) acc *= L.dinv;
-            slot_base[(sl - s0) * 64] = acc;
-            if constexpr (UPPER) {
-                if (L.io >= 0) y[L.io] = TV(acc);
-            } else {
-                if (L.io >= 0) lout[L.io] = acc;
-            }
-        }
-        if (lv + 1 < nlev && mlev[lv + 1] + wv < mlev[lv + 2]) {
-            fetch_lane<TF, UPPER>(S, mw, moff, sl0, mlev[lv + 1] + wv, in, L);
-            have = true;
-        }
-        level_barrier<LDS>();
+// Group size K: two groups of K items (seven loads each) in flight per
+// wavefront, within the 63 loads the in-order memory counter tracks and the
+// register budget of the workgroup size (512 threads: 128 registers keep two
+// workgroups per compute unit; 1024 threads leave 128).
+template <class TF, int NT>
+struct SweepShape {
+    static constexpr int K = (NT <= 512 && sizeof(TF) == 4) ? 3 : 2;
+};
+
+// Per-subdomain slice metadata of one sweep, staged in LDS.
+struct Meta {
+    int32_t *lev;   // [nlev + 1] first slice of each level (relative)
+    int32_t *off;   // [nsl] first value pair, relative to the subdomain's first
+    int32_t *wl;    // [nsl] level << 16 | sl_info
+    int32_t *slot;  // [nsl] ring slot of the first row
+};
+
+// One triangular sweep of one subdomain.  Slices are dealt to wavefronts
+// round-robin over the whole sweep (slice g to wavefront g mod nwaves), and a
+// wavefront works through its slices in order.  Its slices are requested in
+// two groups of K: while one group is processed the other is in flight, and
+// a group is requested again as soon as it has been processed, so the wait
+// for a group never waits for the other.  Barrier b ends level b: a
+// wavefront passes it as soon as it has finished its slices of levels <= b,
+// so every row of levels <= b is in the ring before any row of level b + 1
+// reads it.  Every wavefront passes all nlev barriers.  The lanes of a split
+// row add their partial sums in a fixed order; the row's first lane writes
+// the result to its ring slot and, in the L sweep, to its U-sweep record; the
+// U sweep writes the owned rows to y (restricted scatter).
+template <class TV, class TF, bool UPPER, bool LDS, int NT, class Rec>
+__device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int sl0, int nlev, int nsl, TF *ring,
+                                      const Rec *rec, TF *lout, TV *y) {
+    constexpr int K = SweepShape<TF, NT>::K;
+    const int lane = threadIdx.x % 64, nw = NT / 64;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    int passed = 0;
+    auto pass_to = [&](const Item<TF> &n) {
+        const int lv = n.wl >= 0 ? n.wl >> 17 : nlev;
+        for (; passed < lv; ++passed) level_barrier<LDS>();
+    };
+    if (nsl == 0) {
+        for (; passed < nlev; ++passed) level_barrier<LDS>();
+        return;
     }
+    const int64_t off0 = S.sl_off[sl0];
+    int fg = wv;  // next slice to request (past the end: re-reads the last slice)
+    auto request = [&](Item<TF> (&grp)[K]) {
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int g = fg + k * nw, gg = min(g, nsl - 1);
+            const int wl = __builtin_amdgcn_readfirstlane(M.wl[gg]);
+            const int offr = __builtin_amdgcn_readfirstlane(M.off[gg]);
+            grp[k].wl = g < nsl ? wl : -1;
+            grp[k].slot = __builtin_amdgcn_readfirstlane(M.slot[gg]);
+            fetch_item<TF, UPPER>(S, rec, int64_t(sl0 + gg) * 64 + lane, off0 + offr, wl & 15, grp[k]);
+        }
+        fg += K * nw;
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    // process one group; next: the first item of the other group
+    auto process = [&](const Item<TF> (&grp)[K], const Item<TF> &next) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const Item<TF> &it = grp[k];
+            if (it.wl < 0) break;
+            const int w = it.wl & 15, sp = ((it.wl >> 4) & 63) + 1, nrow = (it.wl >> 10) & 127;
+            const int rr = (lane * ((65536 + sp - 1) / sp)) >> 16, first = rr * sp;  // row in the slice
+            TF acc = consume(it, w, ring, it.h.x);
+            if (sp > 1) {  // the row's first lane adds its other parts in order
+                TF sum = acc;
+                for (int d = 1; d < sp; ++d) sum += __shfl(acc, min(first + d, 63));
+                acc = sum;
+            }
+            if constexpr (UPPER) acc *= it.h.y;
+            if (lane == first && rr < nrow) {
+                ring[it.slot + rr] = acc;
+                if constexpr (UPPER) {
+                    if (it.io >= 0) y[it.io] = TV(acc);
+                } else {
+                    if (it.io >= 0) lout[2 * int64_t(it.io)] = acc;
+                }
+            }
+            pass_to(k + 1 < K ? grp[k + 1] : next);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    Item<TF> A[K], B[K];
+    request(A);
+    request(B);
+    pass_to(A[0]);
+    while (A[0].wl >= 0) {
+        process(A, B[0]);
+        request(A);
+        process(B, A[0]);
+        request(B);
+    }
+    for (; passed < nlev; ++passed) level_barrier<LDS>();
+    __builtin_amdgcn_s_waitcnt(0);  // requests past the end
 }
 
-// LDS bytes of one sweep's slice metadata: per level 4, per slice 4 + 8.
+// LDS bytes of one sweep's slice metadata: per level 4, per slice 12.
 __host__ __device__ constexpr size_t meta_bytes_for(int nsl, int nlev) {
-    return ((size_t(nlev) + 1) * 4 + 7) / 8 * 8 + size_t(nsl) * 12 + 15 & ~size_t(15);
+    return ((size_t(nlev) + 1) * 4 + 15) / 16 * 16 + (size_t(nsl) * 12 + 15) / 16 * 16;
 }
 
+// Stage one subdomain's slice metadata of one sweep in LDS; returns its
+// first slice and sets nsl.  Ends with a workgroup barrier.
 template <class TF, int NT>
 __device__ __forceinline__ int stage_meta(const DevSweep<TF> &S, int lev0, int lev1, int meta_lev, int meta_sl,
-                                          unsigned char *base, int32_t *&mlev, int32_t *&mw, int64_t *&moff) {
-    mlev = reinterpret_cast<int32_t *>(base);
-    moff = reinterpret_cast<int64_t *>(base + ((size_t(meta_lev) + 1) * 4 + 7) / 8 * 8);
-    mw = reinterpret_cast<int32_t *>(moff + meta_sl);
+                                          unsigned char *base, Meta &M, int &nsl) {
+    M.lev = reinterpret_cast<int32_t *>(base);
+    M.off = reinterpret_cast<int32_t *>(base + ((size_t(meta_lev) + 1) * 4 + 15) / 16 * 16);
+    M.wl = M.off + meta_sl;
+    M.slot = M.wl + meta_sl;
     const int sl0 = S.lev_slice[lev0];
-    const int nlev = lev1 - lev0, nsl = S.lev_slice[lev1] - sl0;
-    for (int a = threadIdx.x; a <= nlev; a += NT) mlev[a] = S.lev_slice[lev0 + a] - sl0;
-    for (int a = threadIdx.x; a < nsl; a += NT) {
-        mw[a] = S.sl_w[sl0 + a];
-        moff[a] = S.sl_off[sl0 + a];
+    const int nlev = lev1 - lev0;
+    nsl = S.lev_slice[lev1] - sl0;
+    for (int a = threadIdx.x; a <= nlev; a += NT) M.lev[a] = S.lev_slice[lev0 + a] - sl0;
+    __syncthreads();
+    for (int a = threadIdx.x; a < nlev; a += NT)  // level of each slice
+        for (int s = M.lev[a]; s < M.lev[a + 1]; ++s) M.wl[s] = a << 17;
+    __syncthreads();
+    const int64_t off0 = S.sl_off[sl0];
+    for (int s = threadIdx.x; s < nsl; s += NT) {
+        M.off[s] = int32_t(S.sl_off[sl0 + s] - off0);
+        M.wl[s] |= S.sl_info[sl0 + s];
+        M.slot[s] = S.sl_slot[sl0 + s];
     }
+    __syncthreads();
     return sl0;
 }
 
@@ -186,24 +265,32 @@ __global__ __launch_bounds__(NT) void k_ras(DevRas<TF> R, int meta_lev, int meta
     TF *ring = LDS ? reinterpret_cast<TF *>(ras_smem + meta_bytes_for(meta_sl, meta_lev))
                    : R.ring + int64_t(blockIdx.x) * ring_n;
     for (int a = threadIdx.x; a < ring_n; a += NT) ring[a] = TF(0);
-    int32_t *mlev, *mw;
-    int64_t *moff;
-    int sl0 = stage_meta<TF, NT>(R.L, I.levL0, I.levL1, meta_lev, meta_sl, ras_smem, mlev, mw, moff);
+    Meta M;
+    int nsl;
+    int sl0 = stage_meta<TF, NT>(R.L, I.levL0, I.levL1, meta_lev, meta_sl, ras_smem, M, nsl);
     {
-        const int64_t p0 = int64_t(sl0) * 64, p1 = int64_t(R.L.lev_slice[I.levL1]) * 64;
-        for (int64_t p = p0 + threadIdx.x; p < p1; p += NT) {
-            const int32_t io = R.L.lane_io[p];
-            R.lin[p] = io >= 0 ? TF(x[io]) : TF(0);
+        // eight rows per thread per round: the index loads, then the value
+        // loads, are in flight together
+        constexpr int U = 8;
+        const int64_t p0 = int64_t(sl0) * 64, p1 = int64_t(sl0 + nsl) * 64;
+        for (int64_t p = p0 + threadIdx.x; p < p1; p += int64_t(NT) * U) {
+            int32_t io[U];
+            TV v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) io[u] = p + u * NT < p1 ? R.L.lane_io[p + u * NT] : -1;
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = io[u] >= 0 ? x[io[u]] : TV(0);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (p + u * NT < p1) R.lin[p + u * NT] = TF(v[u]);
         }
     }
     __syncthreads();
-    sweep<TV, TF, false, LDS, NT>(R.L, mlev, mw, moff, sl0, I.levL1 - I.levL0, ring, R.depth, R.width, R.lin,
-                                  R.lout, y);
+    sweep<TV, TF, false, LDS, NT>(R.L, M, sl0, I.levL1 - I.levL0, nsl, ring, R.lin, reinterpret_cast<TF *>(R.lout),
+                                  y);
     __syncthreads();  // L results visible; the U metadata replaces the L metadata
-    sl0 = stage_meta<TF, NT>(R.U, I.levU0, I.levU1, meta_lev, meta_sl, ras_smem, mlev, mw, moff);
-    __syncthreads();
-    sweep<TV, TF, true, LDS, NT>(R.U, mlev, mw, moff, sl0, I.levU1 - I.levU0, ring, R.depth, R.width, R.lout,
-                                 R.lout, y);
+    sl0 = stage_meta<TF, NT>(R.U, I.levU0, I.levU1, meta_lev, meta_sl, ras_smem, M, nsl);
+    sweep<TV, TF, true, LDS, NT>(R.U, M, sl0, I.levU1 - I.levU0, nsl, ring, R.lout, nullptr, y);
 }
 
 // restriction: mean of the 8 children; prolongation: copy to the children
@@ -256,13 +343,13 @@ struct OneLevel {
     bool lds_ring = false;
     int precision = 0;
     SdInfo *sd = nullptr;
-    int32_t *Llev = nullptr, *Lw = nullptr, *Lio = nullptr, *Lnext = nullptr;
+    int32_t *Llev = nullptr, *Lw = nullptr, *Lslot = nullptr, *Lio = nullptr, *Lnext = nullptr;
     int64_t *Loff = nullptr;
     uint16_t *Laddr = nullptr;
-    int32_t *Ulev = nullptr, *Uw = nullptr, *Uio = nullptr;
+    int32_t *Ulev = nullptr, *Uw = nullptr, *Uslot = nullptr, *Uio = nullptr;
     int64_t *Uoff = nullptr;
     uint16_t *Uaddr = nullptr;
-    void *Lval = nullptr, *Uval = nullptr, *Udinv = nullptr, *lin = nullptr, *lout = nullptr, *ring = nullptr;
+    void *Lval = nullptr, *Uval = nullptr, *lin = nullptr, *lout = nullptr, *ring = nullptr;
 
     static void layout(Carver &c, const HostRas &H, int precision, OneLevel &o) {
         const size_t fs = precision ? sizeof(float) : sizeof(double);
@@ -270,16 +357,18 @@ struct OneLevel {
         o.depth = H.ring_depth; o.width = H.ring_width; o.meta_lev = H.max_levels; o.meta_sl = H.max_slices;
         o.max_total_levels = H.max_total_levels; o.precision = precision;
         o.sd = c.take<SdInfo>(H.sd.size());
-        o.Llev = c.take<int32_t>(H.L.lev_slice.size()); o.Lw = c.take<int32_t>(H.L.sl_w.size());
-        o.Loff = c.take<int64_t>(H.L.sl_off.size()); o.Lio = c.take<int32_t>(H.L.lane_io.size());
+        o.Llev = c.take<int32_t>(H.L.lev_slice.size()); o.Lw = c.take<int32_t>(H.L.sl_info.size());
+        o.Loff = c.take<int64_t>(H.L.sl_off.size()); o.Lslot = c.take<int32_t>(H.L.sl_slot.size());
+        o.Lio = c.take<int32_t>(H.L.lane_io.size());
         o.Lnext = c.take<int32_t>(H.L.lane_next.size()); o.Laddr = c.take<uint16_t>(H.L.addr.size());
         o.Lval = c.take<char>(H.L.val.size() * fs);
-        o.Ulev = c.take<int32_t>(H.U.lev_slice.size()); o.Uw = c.take<int32_t>(H.U.sl_w.size());
-        o.Uoff = c.take<int64_t>(H.U.sl_off.size()); o.Uio = c.take<int32_t>(H.U.lane_io.size());
-        o.Udinv = c.take<char>(H.U.lane_diag.size() * fs); o.Uaddr = c.take<uint16_t>(H.U.addr.size());
+        o.Ulev = c.take<int32_t>(H.U.lev_slice.size()); o.Uw = c.take<int32_t>(H.U.sl_info.size());
+        o.Uoff = c.take<int64_t>(H.U.sl_off.size()); o.Uslot = c.take<int32_t>(H.U.sl_slot.size());
+        o.Uio = c.take<int32_t>(H.U.lane_io.size());
+        o.Uaddr = c.take<uint16_t>(H.U.addr.size());
         o.Uval = c.take<char>(H.U.val.size() * fs);
         o.lin = c.take<char>(H.L.lane_io.size() * fs);
-        o.lout = c.take<char>(H.U.lane_io.size() * fs);
+        o.lout = c.take<char>(2 * H.U.lane_io.size() * fs);
         o.ring = c.take<char>(size_t(H.nsd) * H.ring_depth * H.ring_width * fs);
     }
 
@@ -287,44 +376,44 @@ struct OneLevel {
         auto up = [](void *d, const void *s, size_t b) { return b ? hipMemcpy(d, s, b, hipMemcpyHostToDevice) : hipSuccess; };
         CSD_HIP(up(sd, H.sd.data(), H.sd.size() * sizeof(SdInfo)));
         CSD_HIP(up(Llev, H.L.lev_slice.data(), H.L.lev_slice.size() * 4));
-        CSD_HIP(up(Lw, H.L.sl_w.data(), H.L.sl_w.size() * 4));
+        CSD_HIP(up(Lw, H.L.sl_info.data(), H.L.sl_info.size() * 4));
         CSD_HIP(up(Loff, H.L.sl_off.data(), H.L.sl_off.size() * 8));
+        CSD_HIP(up(Lslot, H.L.sl_slot.data(), H.L.sl_slot.size() * 4));
         CSD_HIP(up(Lio, H.L.lane_io.data(), H.L.lane_io.size() * 4));
         CSD_HIP(up(Lnext, H.L.lane_next.data(), H.L.lane_next.size() * 4));
         CSD_HIP(up(Laddr, H.L.addr.data(), H.L.addr.size() * 2));
         CSD_HIP(up(Ulev, H.U.lev_slice.data(), H.U.lev_slice.size() * 4));
-        CSD_HIP(up(Uw, H.U.sl_w.data(), H.U.sl_w.size() * 4));
+        CSD_HIP(up(Uw, H.U.sl_info.data(), H.U.sl_info.size() * 4));
         CSD_HIP(up(Uoff, H.U.sl_off.data(), H.U.sl_off.size() * 8));
+        CSD_HIP(up(Uslot, H.U.sl_slot.data(), H.U.sl_slot.size() * 4));
         CSD_HIP(up(Uio, H.U.lane_io.data(), H.U.lane_io.size() * 4));
         CSD_HIP(up(Uaddr, H.U.addr.data(), H.U.addr.size() * 2));
-        // padding lanes of the U sweep read L results that are never written: keep them 0
-        CSD_HIP(hipMemset(lout, 0, H.U.lane_io.size() * (precision ? sizeof(float) : sizeof(double))));
-        if (precision) {
-            std::vector<float> f(H.L.val.begin(), H.L.val.end());
-            CSD_HIP(up(Lval, f.data(), f.size() * 4));
+        // U-sweep records {L result, 1/u_ii}: the L sweep writes the first
+        // half; padding lanes read results that are never written, so start at 0
+        auto upload_as = [&](auto zero) -> int32_t {
+            using T = decltype(zero);
+            std::vector<T> f(H.L.val.begin(), H.L.val.end());
+            CSD_HIP(up(Lval, f.data(), f.size() * sizeof(T)));
             f.assign(H.U.val.begin(), H.U.val.end());
-            CSD_HIP(up(Uval, f.data(), f.size() * 4));
-            f.assign(H.U.lane_diag.size(), 0.0f);
-            for (size_t a = 0; a < f.size(); ++a) f[a] = H.U.lane_diag[a] != 0.0 ? 1.0f / float(H.U.lane_diag[a]) : 0.0f;
-            CSD_HIP(up(Udinv, f.data(), f.size() * 4));
-        } else {
-            CSD_HIP(up(Lval, H.L.val.data(), H.L.val.size() * 8));
-            CSD_HIP(up(Uval, H.U.val.data(), H.U.val.size() * 8));
-            std::vector<double> d(H.U.lane_diag.size(), 0.0);
-            for (size_t a = 0; a < d.size(); ++a) d[a] = H.U.lane_diag[a] != 0.0 ? 1.0 / H.U.lane_diag[a] : 0.0;
-            CSD_HIP(up(Udinv, d.data(), d.size() * 8));
-        }
-        return CSDYN_OK;
+            CSD_HIP(up(Uval, f.data(), f.size() * sizeof(T)));
+            f.assign(2 * H.U.lane_diag.size(), T(0));
+            for (size_t a = 0; a < H.U.lane_diag.size(); ++a)
+                f[2 * a + 1] = H.U.lane_diag[a] != 0.0 ? T(1.0 / H.U.lane_diag[a]) : T(0);
+            CSD_HIP(up(lout, f.data(), f.size() * sizeof(T)));
+            return CSDYN_OK;
+        };
+        return precision ? upload_as(0.0f) : upload_as(0.0);
     }
 
     template <class TF>
     DevRas<TF> dev() const {
         DevRas<TF> R;
         R.sd = sd;
-        R.L = DevSweep<TF>{Llev, Lw, Loff, Lio, Lnext, nullptr, (const TF *)Lval, Laddr};
-        R.U = DevSweep<TF>{Ulev, Uw, Uoff, Uio, nullptr, (const TF *)Udinv, (const TF *)Uval, Uaddr};
+        using TF2 = typename Pair<TF>::type;
+        R.L = DevSweep<TF>{Llev, Lw, Loff, Lslot, Lio, Lnext, (const TF2 *)Lval, (const uint4 *)Laddr};
+        R.U = DevSweep<TF>{Ulev, Uw, Uoff, Uslot, Uio, nullptr, (const TF2 *)Uval, (const uint4 *)Uaddr};
         R.lin = (TF *)lin;
-        R.lout = (TF *)lout;
+        R.lout = (TF2 *)lout;
         R.ring = (TF *)ring;
         R.depth = depth;
         R.width = width;

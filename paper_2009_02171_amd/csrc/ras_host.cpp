@@ -315,11 +315,19 @@ void build_one(const HostGeom &g, const csdyn_op &op, const int sub[3], const in
 }
 
 // Row schedule of one sweep of one subdomain: rows by level, within a level
-// by decreasing width, cut into slices of 64.
+// by decreasing width, cut into slices of 64 lanes.  A row with more than
+// kLaneEntries entries is split over s = ceil(width / kLaneEntries) adjacent
+// lanes in parts of ceil(width / s) entries (lane j of the row takes entries
+// [j * part, (j + 1) * part)); a slice holds floor(64 / s) rows of one split.
+constexpr int kLaneEntries = 8;
+
 struct Schedule {
     std::vector<int32_t> lev_first;   // [nlev + 1] first slice (relative) of each level
-    std::vector<int32_t> slice_rows;  // [nslice * 64] row or -1
-    std::vector<int32_t> pos;         // [nrow] slice*64 + lane (relative)
+    std::vector<int32_t> slice_rows;  // [nslice * 64] row held by each lane or -1
+    std::vector<int32_t> slice_s;     // [nslice] lanes per row
+    std::vector<int32_t> slice_nrow;  // [nslice] rows in the slice
+    std::vector<int32_t> slice_slot;  // [nslice] ring slot of the slice's first row
+    std::vector<int32_t> pos;         // [nrow] slice*64 + first lane of the row (relative)
     std::vector<int32_t> slot;        // [nrow] ring slot
 };
 
@@ -332,71 +340,94 @@ void make_schedule(const LocalSd &L, bool upper, int depth, int width, Schedule 
     for (int64_t r = 0; r < nrow; ++r) rows[lev[r]].push_back(int32_t(r));
     S.lev_first.assign(1, 0);
     S.slice_rows.clear();
+    S.slice_s.clear();
+    S.slice_nrow.clear();
+    S.slice_slot.clear();
     S.pos.assign(nrow, -1);
     S.slot.assign(nrow, -1);
     for (int lv = 0; lv < nlev; ++lv) {
         auto &R = rows[lv];
         std::stable_sort(R.begin(), R.end(), [&](int32_t a, int32_t b) { return cnt(a) > cnt(b); });
-        const int first = S.lev_first.back();
-        const int nsl = int((R.size() + 63) / 64);
-        for (int a = 0; a < nsl * 64; ++a) {
-            const int32_t r = a < int(R.size()) ? R[a] : -1;
-            S.slice_rows.push_back(r);
-            if (r < 0) continue;
-            S.pos[r] = first * 64 + a;
-            S.slot[r] = depth > 0 ? (lv % depth) * width + a : -1;
+        int nsl = 0;
+        for (size_t a = 0; a < R.size();) {
+            const int sp = int(std::min<int64_t>(64, std::max<int64_t>(1, (cnt(R[a]) + kLaneEntries - 1) / kLaneEntries)));
+            const int nr = int(std::min<size_t>(size_t(64 / sp), R.size() - a));
+            const int sl = int(S.slice_s.size());
+            S.slice_s.push_back(sp);
+            S.slice_nrow.push_back(nr);
+            S.slice_slot.push_back(depth > 0 ? (lv % depth) * width + int(a) : -1);
+            for (int l = 0; l < 64; ++l) {
+                const int rr = l / sp;
+                S.slice_rows.push_back(rr < nr ? R[a + rr] : -1);
+            }
+            for (int rr = 0; rr < nr; ++rr) {
+                S.pos[R[a + rr]] = sl * 64 + rr * sp;
+                S.slot[R[a + rr]] = depth > 0 ? (lv % depth) * width + int(a) + rr : -1;
+            }
+            a += nr;
+            ++nsl;
         }
-        S.lev_first.push_back(first + nsl);
+        S.lev_first.push_back(S.lev_first.back() + nsl);
     }
 }
 
-// Append one subdomain's sweep to the pack.  sched_other is the U schedule
-// (for the L sweep's lane_next); base_other its first global U slice.
-void pack_sweep(const LocalSd &L, bool upper, const Schedule &S, const Schedule *U_sched, int64_t base_u,
-                SweepPack &P, int32_t &lev0, int32_t &lev1) {
+// Append one subdomain's sweep to the pack.  U_sched is the U schedule (for
+// the L sweep's lane_next); base_u its first global U slice.
+int32_t pack_sweep(const LocalSd &L, bool upper, const Schedule &S, const Schedule *U_sched, int64_t base_u,
+                   SweepPack &P, int32_t &lev0, int32_t &lev1) {
     auto first = [&](int64_t r) { return upper ? L.diag[r] + 1 : L.rp[r]; };
     auto cnt = [&](int64_t r) -> int64_t { return upper ? L.rp[r + 1] - L.diag[r] - 1 : L.diag[r] - L.rp[r]; };
-    const int64_t base = int64_t(P.sl_w.size());
+    const int64_t base = int64_t(P.sl_info.size());
     lev0 = int32_t(P.lev_slice.size());
     for (size_t lv = 0; lv + 1 < S.lev_first.size(); ++lv) P.lev_slice.push_back(int32_t(base + S.lev_first[lv]));
     lev1 = int32_t(P.lev_slice.size());
     const int nsl = S.lev_first.back();
     for (int sl = 0; sl < nsl; ++sl) {
-        int64_t w = 0;
-        for (int a = 0; a < 64; ++a) {
-            const int32_t r = S.slice_rows[sl * 64 + a];
-            if (r >= 0) w = std::max(w, cnt(r));
+        const int sp = S.slice_s[sl];
+        const int32_t r0 = S.slice_rows[sl * 64];
+        const int w = int((cnt(r0) + sp - 1) / sp);  // entries per lane
+        if (w > kLaneEntries) {
+            set_error("ras: a factor row has more than %d entries", 64 * kLaneEntries);
+            return CSDYN_EINVAL;
         }
-        const int64_t off = int64_t(P.val.size());
-        P.sl_w.push_back(int32_t(w));
+        const int64_t off = int64_t(P.val.size()) / 2, aoff = int64_t(P.addr.size()) / 8;
+        P.sl_info.push_back(S.slice_nrow[sl] << 10 | (sp - 1) << 4 | w);
         P.sl_off.push_back(off);
-        P.val.resize(off + w * 64, 0.0);
-        P.addr.resize(off + w * 64, 0);
+        P.sl_slot.push_back(S.slice_slot[sl]);
+        P.val.resize(P.val.size() + (w + 1) / 2 * 128, 0.0);
+        P.addr.resize(P.addr.size() + 512, 0);
+        auto vat = [&](int64_t q, int a) { return 2 * (off + (q / 2) * 64 + a) + q % 2; };
+        auto aat = [&](int64_t q, int a) { return 8 * (aoff + a) + q; };
         for (int a = 0; a < 64; ++a) {
             const int32_t r = S.slice_rows[sl * 64 + a];
             int32_t io = -1, nxt = -1;
             double dg = 0.0;
             if (r >= 0) {
-                const int64_t gunk = 4 * int64_t(L.gcell[r / 4]) + r % 4;
-                if (!upper) {
-                    io = int32_t(gunk);
-                    nxt = int32_t(base_u * 64 + U_sched->pos[r]);
-                } else {
+                const int j = a % sp;  // part of the row on this lane
+                if (upper) {
                     dg = L.v[L.diag[r]];
-                    if (L.owned_row[r / 4]) io = int32_t(gunk);
+                    if (j == 0 && L.owned_row[r / 4]) io = int32_t(4 * int64_t(L.gcell[r / 4]) + r % 4);
+                } else if (j == 0) {
+                    io = int32_t(4 * int64_t(L.gcell[r / 4]) + r % 4);
+                    nxt = int32_t(base_u * 64 + U_sched->pos[r]);
                 }
-                const int64_t q0 = first(r);
-                for (int64_t q = 0; q < cnt(r); ++q) {
-                    P.val[off + q * 64 + a] = L.v[q0 + q];
-                    P.addr[off + q * 64 + a] = uint16_t(S.slot[L.ci[q0 + q]]);
+                const int64_t q0 = first(r), n = cnt(r);
+                for (int e = 0; e < kLaneEntries; ++e) {
+                    const int64_t t = int64_t(j) * w + e;
+                    if (e < w && t < n) {
+                        P.val[vat(e, a)] = L.v[q0 + t];
+                        P.addr[aat(e, a)] = uint16_t(S.slot[L.ci[q0 + t]]);
+                    } else {
+                        P.addr[aat(e, a)] = uint16_t(S.slot[r]);  // zero value
+                    }
                 }
-                for (int64_t q = cnt(r); q < w; ++q) P.addr[off + q * 64 + a] = uint16_t(S.slot[r]);  // zero value
             }
             P.lane_io.push_back(io);
             if (!upper) P.lane_next.push_back(nxt);
             else P.lane_diag.push_back(dg);
         }
     }
+    return CSDYN_OK;
 }
 
 // Longest distance in levels between a row and its dependencies, and the
@@ -492,9 +523,9 @@ int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], 
         Schedule SL, SU;
         make_schedule(L, false, H.ring_depth, H.ring_width, SL);
         make_schedule(L, true, H.ring_depth, H.ring_width, SU);
-        const int64_t base_u = int64_t(H.U.sl_w.size());
-        pack_sweep(L, true, SU, nullptr, 0, H.U, I.levU0, I.levU1);
-        pack_sweep(L, false, SL, &SU, base_u, H.L, I.levL0, I.levL1);
+        const int64_t base_u = int64_t(H.U.sl_info.size());
+        if (int32_t e = pack_sweep(L, true, SU, nullptr, 0, H.U, I.levU0, I.levU1)) return e;
+        if (int32_t e = pack_sweep(L, false, SL, &SU, base_u, H.L, I.levL0, I.levL1)) return e;
         H.max_slices = std::max(H.max_slices, std::max(SL.lev_first.back(), SU.lev_first.back()));
         H.max_levels = std::max(H.max_levels, std::max(L.nlevL, L.nlevU));
         H.max_total_levels = std::max(H.max_total_levels, L.nlevL + L.nlevU);
@@ -503,8 +534,12 @@ int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], 
         std::vector<int32_t>().swap(L.ci);
         std::vector<double>().swap(L.v);
     }
-    H.L.lev_slice.push_back(int32_t(H.L.sl_w.size()));
-    H.U.lev_slice.push_back(int32_t(H.U.sl_w.size()));
+    if (H.max_levels >= 1 << 14) {
+        set_error("ras: %d levels in one triangular sweep (at most 16383)", H.max_levels);
+        return CSDYN_EINVAL;
+    }
+    H.L.lev_slice.push_back(int32_t(H.L.sl_info.size()));
+    H.U.lev_slice.push_back(int32_t(H.U.sl_info.size()));
     // tail padding: the sweep kernel may read a fixed number of entries past a
     // slice's width; keep those reads inside the arrays
     for (SweepPack *P : {&H.L, &H.U}) {

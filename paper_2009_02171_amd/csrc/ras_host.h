@@ -14,22 +14,30 @@ namespace csd {
 
 // One triangular sweep (the L sweep or the U sweep) of all subdomains, in
 // the order the sweep kernel processes it.  The rows of a subdomain are
-// ordered by level; within a level they form slices of 64 lanes (one row per
-// lane).  Entry q of lane l of slice s is at sl_off[s] + q*64 + l.  A
-// dependency is addressed by its ring slot: rows only depend on rows of the
-// previous ring_depth - 1 levels, so the sweep keeps the results of the last
-// ring_depth levels in a ring of ring_depth x ring_width values, slot =
-// (level mod ring_depth) * ring_width + 64 * (slice - first slice of the
-// level) + lane.
+// ordered by level; within a level they form slices of 64 lanes.  A slice
+// holds floor(64 / s) rows, each on s adjacent lanes (s = ceil(width / 8) for
+// the slice's widest row; lane j of a row takes entries [j * w, (j + 1) * w)
+// with w = ceil(width / s)), so a lane holds at most eight entries.  A lane's entries are stored in pairs
+// (values) and as one group of eight (addresses), lanes side by side, so
+// that one 16-byte load per lane fetches a pair of values (FP64) or all eight
+// addresses: entry e of lane l of slice s has value
+// val[2 * (sl_off[s] + (e / 2) * 64 + l) + e % 2] and address
+// addr[8 * (64 * s + l) + e].  Entries past a lane's part of its row have
+// value 0.  A dependency is addressed by its ring slot: rows only depend on
+// rows of the previous ring_depth - 1 levels, so the sweep keeps the results
+// of the last ring_depth levels in a ring of ring_depth x ring_width values,
+// slot = (level mod ring_depth) * ring_width + position of the row in its
+// level; the rows of a slice have consecutive positions from sl_slot[s].
 struct SweepPack {
     std::vector<int32_t> lev_slice;  // [nlev_total + 1] first slice of each level
-    std::vector<int32_t> sl_w;       // [nslice] entries per lane
-    std::vector<int64_t> sl_off;     // [nslice]
-    std::vector<int32_t> lane_io;    // [nslice*64] L: x index of the row; U: y index of an owned row; else -1
-    std::vector<int32_t> lane_next;  // [nslice*64] L only: U-sweep position (slice*64 + lane) of the row
+    std::vector<int32_t> sl_info;    // [nslice] rows << 10 | (s - 1) << 4 | entries per lane
+    std::vector<int64_t> sl_off;     // [nslice] first value pair
+    std::vector<int32_t> sl_slot;    // [nslice] ring slot of the first row
+    std::vector<int32_t> lane_io;    // [nslice*64] L: x index; U: y index of an owned row (first lane of a row); else -1
+    std::vector<int32_t> lane_next;  // [nslice*64] L only: U-sweep position (slice*64 + first lane) of the row
     std::vector<double> lane_diag;   // [nslice*64] U only: u_ii (0 on padding lanes)
-    std::vector<double> val;         // [entries]
-    std::vector<uint16_t> addr;      // [entries] ring slot of the dependency
+    std::vector<double> val;         // [2 * pairs]
+    std::vector<uint16_t> addr;      // [8 * 64 * nslice] ring slot of the dependency
 };
 
 struct SdInfo {
