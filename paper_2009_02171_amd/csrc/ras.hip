@@ -79,18 +79,21 @@ struct Item {
 // Seven loads per item whatever the slice (pairs past the slice's width
 // re-read its last pair; consume() masks them), so the memory counters always
 // hold the later items' loads in the same order and the wait for one group
-// of items never waits for the next.
-// rec: the L sweep's gathered inputs (TF) or the U sweep's records (TF2).
+// of items never waits for the next.  Lanes past the slice's rows (nvalid =
+// rows * lanes per row) read lane 0's data instead of their own padding, so
+// the cache lines of the padding are never fetched; their results are
+// discarded.
 template <class TF, bool UPPER, class Rec>
-__device__ __forceinline__ void fetch_item(const DevSweep<TF> &S, const Rec *rec, int64_t gpos, int64_t off, int w,
-                                           Item<TF> &X) {
-    const int lane = threadIdx.x % 64;
+__device__ __forceinline__ void fetch_item(const DevSweep<TF> &S, const Rec *rec, int64_t g64, int64_t off, int w,
+                                           int nvalid, Item<TF> &X) {
+    const int lane = threadIdx.x % 64, ln = lane < nvalid ? lane : 0;
+    const int64_t gpos = g64 + ln;
     if constexpr (UPPER) X.h = rec[gpos];
     else X.h.x = rec[gpos];
     X.io = UPPER ? S.lane_io[gpos] : S.lane_next[gpos];
     const int lastp = w > 0 ? (w - 1) / 2 : 0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) X.val[j] = S.val[off + int64_t(min(j, lastp)) * 64 + lane];
+    for (int j = 0; j < 4; ++j) X.val[j] = S.val[off + int64_t(min(j, lastp)) * 64 + ln];
     const uint4 a = S.addr[gpos];
     X.addr[0] = a.x; X.addr[1] = a.y; X.addr[2] = a.z; X.addr[3] = a.w;
 }
@@ -133,7 +136,7 @@ struct SweepShape {
 struct Meta {
     int32_t *lev;   // [nlev + 1] first slice of each level (relative)
     int32_t *off;   // [nsl] first value pair, relative to the subdomain's first
-    int32_t *wl;    // [nsl] level << 16 | sl_info
+    int32_t *wl;    // [nsl] level << 17 | sl_info
     int32_t *slot;  // [nsl] ring slot of the first row
 };
 
@@ -175,7 +178,8 @@ __device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int 
             const int offr = __builtin_amdgcn_readfirstlane(M.off[gg]);
             grp[k].wl = g < nsl ? wl : -1;
             grp[k].slot = __builtin_amdgcn_readfirstlane(M.slot[gg]);
-            fetch_item<TF, UPPER>(S, rec, int64_t(sl0 + gg) * 64 + lane, off0 + offr, wl & 15, grp[k]);
+            fetch_item<TF, UPPER>(S, rec, int64_t(sl0 + gg) * 64, off0 + offr, wl & 15,
+                                  ((wl >> 10) & 127) * (((wl >> 4) & 63) + 1), grp[k]);
         }
         fg += K * nw;
         __builtin_amdgcn_sched_barrier(0);

@@ -382,6 +382,7 @@ int32_t pack_sweep(const LocalSd &L, bool upper, const Schedule &S, const Schedu
     for (size_t lv = 0; lv + 1 < S.lev_first.size(); ++lv) P.lev_slice.push_back(int32_t(base + S.lev_first[lv]));
     lev1 = int32_t(P.lev_slice.size());
     const int nsl = S.lev_first.back();
+    const int64_t pair0 = int64_t(P.val.size()) / 2;
     for (int sl = 0; sl < nsl; ++sl) {
         const int sp = S.slice_s[sl];
         const int32_t r0 = S.slice_rows[sl * 64];
@@ -426,6 +427,10 @@ int32_t pack_sweep(const LocalSd &L, bool upper, const Schedule &S, const Schedu
             if (!upper) P.lane_next.push_back(nxt);
             else P.lane_diag.push_back(dg);
         }
+    }
+    if (int64_t(P.val.size()) / 2 - pair0 > INT32_MAX) {  // the sweep kernel keeps 32-bit offsets per subdomain
+        set_error("ras: subdomain too large (more than 2^31 value pairs in one sweep)");
+        return CSDYN_EINVAL;
     }
     return CSDYN_OK;
 }
