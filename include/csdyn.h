@@ -346,6 +346,13 @@ typedef struct {
     double flops;
 } csdyn_profile_entry;
 int32_t csdyn_profile_begin(int32_t max_launches);
+/* Restrict the timing of the next begin() .. end() to the launches whose
+ * kernel names (as end() reports them) appear in names, a comma-separated
+ * list, and of those to one launch in `every` per name (the first, then every
+ * every-th); NULL or "" times every launch (the default, every is then
+ * ignored).  Fewer timed launches disturb the timed work less.  Returns
+ * CSDYN_EINVAL while profiling is active or if every < 1. */
+int32_t csdyn_profile_select(const char *names, int32_t every);
 int32_t csdyn_profile_end(csdyn_profile_entry *out, int32_t max_entries, int32_t *n_entries);
 
 /* Thread-local text of the last error on this thread ("" if none). */

@@ -95,6 +95,7 @@ SIGNATURES = {
                                       C.c_size_t, C.c_void_p, _P(GmresStats)]),
     "csdyn_ras_get_info": (C.c_int32, [C.c_void_p, _P(RasInfo)]),
     "csdyn_profile_begin": (C.c_int32, [C.c_int32]),
+    "csdyn_profile_select": (C.c_int32, [C.c_char_p, C.c_int32]),
     "csdyn_profile_end": (C.c_int32, [_P(ProfileEntry), C.c_int32, _P(C.c_int32)]),
     "csdyn_conv3d_sizes": (C.c_int32, [_P(ConvShape), _P(C.c_int64), _P(C.c_int64), _P(C.c_size_t)]),
     "csdyn_conv3d_pack": (C.c_int32, [_P(ConvShape), C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -349,13 +350,19 @@ class Residual:
 
 class Profile:
     """Context manager around csdyn_profile_begin/end: per-kernel launch counts
-    and summed HIP-event durations, recorded on the launch streams."""
+    and summed HIP-event durations, recorded on the launch streams.  select:
+    kernel names to time, every: one launch in `every` of each of them
+    (csdyn_profile_select); select=None times every launch."""
 
-    def __init__(self, max_launches=200000):
+    def __init__(self, max_launches=200000, select=None, every=1):
         self.max_launches = max_launches
+        self.select = select
+        self.every = every
         self.result = {}
 
     def __enter__(self):
+        names = ",".join(self.select).encode() if self.select else None
+        _check(lib().csdyn_profile_select(names, self.every), "csdyn_profile_select")
         _check(lib().csdyn_profile_begin(self.max_launches), "csdyn_profile_begin")
         return self
 

@@ -58,8 +58,10 @@ struct Gmres {
     int m = 30;
     bool flexible = false;
     int orth = 0;  // 0: classical Gram-Schmidt, 1: with one re-orthogonalisation pass
+    // Enqueue Arnoldi step j + 1 before reading back step j (for solves whose
+    // steps are short device work; a step enqueued past convergence is wasted)
+    bool lookahead = false;
     T *V = nullptr, *Z = nullptr, *z = nullptr, *r = nullptr, *tmp = nullptr, *partial = nullptr, *red = nullptr;
-    T *hred = nullptr;  // pinned-free host mirror is a std::vector below
 
     static size_t bytes(int64_t n, int m, bool flexible);
     void carve(Carver &c, int64_t n_, int m_, bool flexible_);

@@ -8,6 +8,8 @@
 // order two-stage sum over blocks, so results are bitwise reproducible.
 #include <algorithm>
 #include <cmath>
+#include <deque>
+#include <utility>
 
 #include "krylov.h"
 #include "profile.h"
@@ -127,6 +129,19 @@ __global__ __launch_bounds__(kBlk) void k_mupdate(T *__restrict__ w, const T *__
 
 template <class T>
 __global__ void k_scale(T *w, int64_t n, T a) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) w[i] *= a;
+}
+
+// v_{j+1} = w / ||w|| with the norms the reduction left on the device (ww:
+// ||w||^2 before the projection, nn: after it), the same arithmetic as the
+// host's; on a happy breakdown (||w|| <= 1e-14 of its norm before the
+// projection) w is left as it is.
+template <class T>
+__global__ void k_scale_arnoldi(T *w, int64_t n, const T *ww, const T *nn) {
+    const double hn = sqrt(fmax(double(*nn), 0.0));
+    if (hn <= 1e-14 * sqrt(double(*ww))) return;
+    const T a = T(1.0 / hn);
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) w[i] *= a;
 }
@@ -393,6 +408,36 @@ int32_t Gmres<T>::norm(const T *v, double &out, hipStream_t s) {
     return CSDYN_OK;
 }
 
+// Pinned host buffers and events for the Arnoldi read-backs: two per solve
+// nesting depth on this thread and device (the two-level preconditioner runs
+// a coarse solve inside an iteration of the outer solve), kept until the
+// process ends.
+struct ReadBack {
+    void *buf[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
+static int32_t readback_for(int depth, ReadBack *&rb) {
+    // (device * 64 + depth, buffers); a deque keeps the entries in place while
+    // a nested solve appends its own
+    static thread_local std::deque<std::pair<int, ReadBack>> pool;
+    int dev = 0;
+    CSD_HIP(hipGetDevice(&dev));
+    const int key = dev * 64 + depth;
+    for (auto &e : pool)
+        if (e.first == key) { rb = &e.second; return CSDYN_OK; }
+    ReadBack r;
+    for (int i = 0; i < 2; ++i) {
+        CSD_HIP(hipHostMalloc(&r.buf[i], sizeof(double) * 3 * kRedStride, hipHostMallocDefault));
+        CSD_HIP(hipEventCreateWithFlags(&r.ev[i], hipEventDisableTiming));
+    }
+    pool.emplace_back(key, r);
+    rb = &pool.back().second;
+    return CSDYN_OK;
+}
+
+static thread_local int t_solve_depth = 0;
+
 template <class T>
 int32_t Gmres<T>::solve(const DevFn<T> &A, const DevFn<T> *M, const T *b, T *x, int maxit, double rtol,
                         double atol, hipStream_t s, GmresResult &res, bool rhs_relative) {
@@ -401,8 +446,14 @@ int32_t Gmres<T>::solve(const DevFn<T> &A, const DevFn<T> *M, const T *b, T *x, 
         set_error("gmres: restart must be in [1, %d] and maxit >= 1", kRedStride - 1);
         return CSDYN_EINVAL;
     }
+    if (t_solve_depth >= 64) { set_error("gmres: solves nested too deeply"); return CSDYN_EINVAL; }
+    ReadBack *rb = nullptr;
+    CSD_TRY(readback_for(t_solve_depth, rb));
+    struct Depth {
+        Depth() { ++t_solve_depth; }
+        ~Depth() { --t_solve_depth; }
+    } depth_guard;
     std::vector<double> H(size_t(m + 1) * m, 0.0), cs(m), sn(m), gv(m + 1), yv(m);
-    std::vector<T> hv;
     // r = b - A x
     CSD_TRY(A(x, tmp, s));
     CSD_TRY(Vec<T>::copy(r, b, n, s));
@@ -413,6 +464,31 @@ int32_t Gmres<T>::solve(const DevFn<T> &A, const DevFn<T> *M, const T *b, T *x, 
     double bnorm = beta0;
     if (rhs_relative) CSD_TRY(norm(b, bnorm, s));
     const double tol = std::max(atol, rtol * (rhs_relative ? bnorm : beta0));
+    const int nred = orth == 0 ? 2 : 3;  // reduction blocks read back per iteration
+    // Arnoldi step j on the device: z_j = M v_j, w = A z_j, classical
+    // Gram-Schmidt (h = V^T w, then w -= V h with ||w||^2 in the same pass;
+    // CGS2 re-orthogonalises once, the second dot fused into the update),
+    // read-back of h and the norms, v_{j+1} = w / ||w|| from the device norms.
+    auto launch_step = [&](int j) -> int32_t {
+        T *vj = V + size_t(j) * n, *w = V + size_t(j + 1) * n;
+        T *zj = flexible ? Z + size_t(j) * n : z;
+        if (M) CSD_TRY((*M)(vj, zj, s));
+        else CSD_TRY(Vec<T>::copy(zj, vj, n, s));
+        CSD_TRY(A(zj, w, s));
+        CSD_TRY(Vec<T>::mdot(V, n, j + 1, w, partial, red, s));
+        if (orth == 0) {
+            CSD_TRY(Vec<T>::mupdate(w, V, n, j + 1, red, partial, red + kRedStride, s));
+        } else {
+            CSD_TRY(Vec<T>::mupdate_dot(w, V, n, j + 1, red, partial, red + kRedStride, s));
+            CSD_TRY(Vec<T>::mupdate(w, V, n, j + 1, red + kRedStride, partial, red + 2 * kRedStride, s));
+        }
+        CSD_HIP(hipMemcpyAsync(rb->buf[j % 2], red, sizeof(T) * nred * kRedStride, hipMemcpyDeviceToHost, s));
+        CSD_HIP(hipEventRecord(rb->ev[j % 2], s));
+        hipLaunchKernelGGL(k_scale_arnoldi<T>, ew_grid(n), dim3(256), 0, s, w, n, red + kRedStride - 1,
+                           red + nred * kRedStride - 1);
+        CSD_LAUNCHED();
+        return CSDYN_OK;
+    };
     int iters = 0, restarts = 0;
     bool conv = beta0 <= tol;
     double est = beta0, beta = beta0;
@@ -422,32 +498,26 @@ int32_t Gmres<T>::solve(const DevFn<T> &A, const DevFn<T> *M, const T *b, T *x, 
         std::fill(gv.begin(), gv.end(), 0.0);
         gv[0] = beta;
         int jdone = 0;
+        // With lookahead, step j + 1 is enqueued before the host waits for
+        // step j's numbers (unless the convergence rate so far says step j
+        // will be the last), so the device does not idle between steps; a
+        // step enqueued past convergence is discarded.
+        CSD_TRY(launch_step(0));  // step j is always enqueued when the loop reaches j
+        double est_prev = est;
         for (int j = 0; j < m && iters < maxit; ++j) {
-            T *vj = V + size_t(j) * n, *w = V + size_t(j + 1) * n;
-            T *zj = flexible ? Z + size_t(j) * n : z;
-            if (M) CSD_TRY((*M)(vj, zj, s));
-            else CSD_TRY(Vec<T>::copy(zj, vj, n, s));
-            CSD_TRY(A(zj, w, s));
-            // classical Gram-Schmidt: h = V^T w, then w -= V h with ||w||^2 in the same
-            // pass; CGS2 re-orthogonalises once, the second dot fused into the update
-            std::vector<T> h1(2 * kRedStride);
-            CSD_TRY(Vec<T>::mdot(V, n, j + 1, w, partial, red, s));
-            double ww, nn;
-            if (orth == 0) {
-                CSD_TRY(Vec<T>::mupdate(w, V, n, j + 1, red, partial, red + kRedStride, s));
-                CSD_HIP(hipMemcpyAsync(h1.data(), red, sizeof(T) * 2 * kRedStride, hipMemcpyDeviceToHost, s));
-                CSD_HIP(hipStreamSynchronize(s));
-                for (int i = 0; i <= j; ++i) H[size_t(i) * m + j] = double(h1[i]);
-            } else {
-                CSD_TRY(Vec<T>::mupdate_dot(w, V, n, j + 1, red, partial, red + kRedStride, s));
-                CSD_TRY(Vec<T>::mupdate(w, V, n, j + 1, red + kRedStride, partial, red + 2 * kRedStride, s));
-                h1.resize(3 * kRedStride);
-                CSD_HIP(hipMemcpyAsync(h1.data(), red, sizeof(T) * 3 * kRedStride, hipMemcpyDeviceToHost, s));
-                CSD_HIP(hipStreamSynchronize(s));
-                for (int i = 0; i <= j; ++i) H[size_t(i) * m + j] = double(h1[i]) + double(h1[kRedStride + i]);
+            const bool more = j + 1 < m && iters + 1 < maxit;
+            const double rate = j > 0 && est_prev > 0 ? est / est_prev : 1.0;
+            bool ahead = false;
+            if (lookahead && more && est * rate > tol) {
+                CSD_TRY(launch_step(j + 1));
+                ahead = true;
             }
-            ww = double(h1[kRedStride - 1]);
-            nn = double(h1[(orth == 0 ? 2 : 3) * kRedStride - 1]);
+            CSD_HIP(hipEventSynchronize(rb->ev[j % 2]));
+            const T *h1 = static_cast<const T *>(rb->buf[j % 2]);
+            for (int i = 0; i <= j; ++i)
+                H[size_t(i) * m + j] = orth == 0 ? double(h1[i]) : double(h1[i]) + double(h1[kRedStride + i]);
+            const double ww = double(h1[kRedStride - 1]);
+            const double nn = double(h1[nred * kRedStride - 1]);
             const double hn = std::sqrt(std::max(nn, 0.0));
             H[size_t(j + 1) * m + j] = hn;
             ++iters;
@@ -466,10 +536,12 @@ int32_t Gmres<T>::solve(const DevFn<T> &A, const DevFn<T> *M, const T *b, T *x, 
             H[size_t(j + 1) * m + j] = 0.0;
             gv[j + 1] = -sn[j] * gv[j];
             gv[j] = cs[j] * gv[j];
+            est_prev = est;
             est = std::fabs(gv[j + 1]);
             const bool happy = hn <= 1e-14 * std::sqrt(ww);
-            if (!happy) CSD_TRY(Vec<T>::scale(w, n, 1.0 / hn, s));
             if (est <= tol || happy) { conv = true; break; }
+            if (!more) break;
+            if (!ahead) CSD_TRY(launch_step(j + 1));
         }
         for (int i = jdone - 1; i >= 0; --i) {
             double acc = gv[i];

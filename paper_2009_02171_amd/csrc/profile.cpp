@@ -6,6 +6,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "profile.h"
 
@@ -23,6 +24,9 @@ std::atomic<bool> g_on{false};
 std::vector<Pair> g_pool;
 size_t g_next = 0;
 int64_t g_dropped = 0;
+std::vector<std::string> g_select;  // kernel names to time; empty: all
+std::vector<int64_t> g_seen;         // launches of each selected name so far
+int g_every = 1;                     // time one launch in g_every of each selected name
 thread_local bool t_suspended = false;
 }  // namespace
 
@@ -31,6 +35,11 @@ void prof_suspend(bool on) { t_suspended = on; }
 ProfScope::ProfScope(const char *name, int64_t size, double bytes, hipStream_t s, double flops) : s_(s) {
     if (!g_on.load(std::memory_order_relaxed) || t_suspended) return;
     std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_select.empty()) {
+        size_t k = 0;
+        while (k < g_select.size() && g_select[k] != name) ++k;
+        if (k == g_select.size() || g_seen[k]++ % g_every != 0) return;
+    }
     if (g_next >= g_pool.size()) { ++g_dropped; return; }
     slot_ = int64_t(g_next++);
     g_pool[slot_].name = name;
@@ -63,6 +72,28 @@ extern "C" int32_t csdyn_profile_begin(int32_t max_launches) {
     g_next = 0;
     g_dropped = 0;
     g_on = true;
+    return CSDYN_OK;
+}
+
+extern "C" int32_t csdyn_profile_select(const char *names, int32_t every) {
+    clear_error();
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_on) { set_error("profile: select before begin"); return CSDYN_EINVAL; }
+    if (every < 1) { set_error("profile: every must be >= 1"); return CSDYN_EINVAL; }
+    g_select.clear();
+    g_every = every;
+    if (!names) return CSDYN_OK;
+    std::string cur;
+    for (const char *c = names;; ++c) {
+        if (*c == ',' || *c == 0) {
+            if (!cur.empty()) g_select.push_back(cur);
+            cur.clear();
+            if (*c == 0) break;
+        } else {
+            cur += *c;
+        }
+    }
+    g_seen.assign(g_select.size(), 0);
     return CSDYN_OK;
 }
 

@@ -683,6 +683,7 @@ int32_t csdyn_ras::two_level(const T *x, T *y, hipStream_t s) const {
     Gmres<T> gm;
     Carver cc(cws);
     gm.carve(cc, nc, o.coarse_restart, false);
+    gm.lookahead = true;  // a coarse step is a few hundred microseconds of device work
     const csdyn_opctx *cctx = &coarse_ctx;
     DevFn<T> Ac;
     if constexpr (sizeof(T) == 8) Ac = [cctx](const T *in, T *outv, hipStream_t st) { return op_launch(cctx, in, outv, st); };

@@ -88,3 +88,26 @@ def test_project_matches_oracle(kind):
     op = csdyn.Operator(n, nr, kind=kind, dt=1e-2)
     out = op.project(torch.from_numpy(x).cuda()).cpu().numpy()
     assert np.abs(out - ref).max() / np.abs(ref).max() <= 1e-12
+
+
+def test_profile_select_times_only_the_named_kernels():
+    """csdyn_profile_select: only the listed kernels are timed; the default times every launch."""
+    import torch
+    from paper_2009_02171_amd import csdyn
+    op = csdyn.Operator(16, 8)
+    x = torch.zeros(op.shape, dtype=torch.float64, device="cuda")
+    with csdyn.Profile(select=["op_main"]) as p:
+        op.apply(x)
+        op.apply(x)
+        torch.cuda.synchronize()
+    assert {k[0] for k in p.result} == {"op_main"}
+    assert sum(e["count"] for e in p.result.values()) == 2
+    with csdyn.Profile() as q:
+        op.apply(x)
+        torch.cuda.synchronize()
+    assert "op_main" in {k[0] for k in q.result} and len(q.result) >= 2
+    with csdyn.Profile(select=["op_main"], every=3) as r:
+        for _ in range(7):
+            op.apply(x)
+        torch.cuda.synchronize()
+    assert sum(e["count"] for e in r.result.values()) == 3  # launches 0, 3 and 6
