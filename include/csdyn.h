@@ -137,6 +137,10 @@ typedef struct {
     int32_t coarse_restart;  /* 30 */
     int32_t coarse_maxit;    /* cap on inner iterations per coarse solve */
     int32_t precision;       /* 0 FP64, 1 FP32 inside the preconditioner */
+    int32_t storage;         /* where a sweep keeps computed values: 0 automatic (the whole subdomain
+                                vector in LDS when its FP64 size is at most 90 KiB, else a ring of
+                                recent levels), 1 the ring, 2 the subdomain vector (CSDYN_EINVAL if it
+                                does not fit in LDS); the results do not depend on it */
 } csdyn_ras_opts;
 
 typedef struct csdyn_ras csdyn_ras;
@@ -241,7 +245,9 @@ typedef struct {
     int32_t max_levels_fine, max_levels_coarse; /* L + U sweep levels of the deepest subdomain */
     int32_t precision;
     int32_t lds_fine, lds_coarse;             /* dynamic LDS bytes per workgroup of the sweep kernel */
-    int32_t box_in_lds_fine, box_in_lds_coarse; /* 1: the sweep's ring of recent levels is held in LDS */
+    int32_t box_in_lds_fine, box_in_lds_coarse; /* where the sweep keeps computed values: 0 a ring of recent
+                                                   levels in device memory, 1 that ring in LDS, 2 the whole
+                                                   subdomain vector in LDS */
 } csdyn_ras_info;
 int32_t csdyn_ras_get_info(const csdyn_ras *pc, csdyn_ras_info *info);
 

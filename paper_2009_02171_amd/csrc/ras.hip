@@ -71,7 +71,8 @@ struct Item {
     uint32_t addr[4];
     TF2 val[4];
     TF2 h;
-    int32_t io;    // L: U position of the row; U: y index or -1
+    int32_t io;    // ring, L: U position of the row; U: y index or -1
+    int32_t row;   // box vector, U: position of the row in the box vector (first lane of a row) or -1
     int32_t wl;    // level << 17 | sl_info; -1 past the wavefront's last slice
     int32_t slot;  // ring slot of the slice's first row
 };
@@ -83,14 +84,22 @@ struct Item {
 // rows * lanes per row) read lane 0's data instead of their own padding, so
 // the cache lines of the padding are never fetched; their results are
 // discarded.
-template <class TF, bool UPPER, class Rec>
+// With the box vector in LDS (VEC) the L sweep's inputs and results live there
+// (five loads per item) and the U sweep reads its record only for 1/u_ii and
+// its row's position (eight loads).
+template <class TF, bool UPPER, bool VEC, class Rec>
 __device__ __forceinline__ void fetch_item(const DevSweep<TF> &S, const Rec *rec, int64_t g64, int64_t off, int w,
                                            int nvalid, Item<TF> &X) {
     const int lane = threadIdx.x % 64, ln = lane < nvalid ? lane : 0;
     const int64_t gpos = g64 + ln;
-    if constexpr (UPPER) X.h = rec[gpos];
-    else X.h.x = rec[gpos];
-    X.io = UPPER ? S.lane_io[gpos] : S.lane_next[gpos];
+    if constexpr (UPPER) {
+        X.h = rec[gpos];
+        X.io = S.lane_io[gpos];
+        if constexpr (VEC) X.row = S.lane_next[gpos];
+    } else if constexpr (!VEC) {
+        X.h.x = rec[gpos];
+        X.io = S.lane_next[gpos];
+    }
     const int lastp = w > 0 ? (w - 1) / 2 : 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) X.val[j] = S.val[off + int64_t(min(j, lastp)) * 64 + ln];
@@ -152,7 +161,7 @@ struct Meta {
 // row add their partial sums in a fixed order; the row's first lane writes
 // the result to its ring slot and, in the L sweep, to its U-sweep record; the
 // U sweep writes the owned rows to y (restricted scatter).
-template <class TV, class TF, bool UPPER, bool LDS, int NT, class Rec>
+template <class TV, class TF, bool UPPER, bool LDS, bool VEC, int NT, class Rec>
 __device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int sl0, int nlev, int nsl, TF *ring,
                                       const Rec *rec, TF *lout, TV *y) {
     constexpr int K = SweepShape<TF, NT>::K;
@@ -178,7 +187,7 @@ __device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int 
             const int offr = __builtin_amdgcn_readfirstlane(M.off[gg]);
             grp[k].wl = g < nsl ? wl : -1;
             grp[k].slot = __builtin_amdgcn_readfirstlane(M.slot[gg]);
-            fetch_item<TF, UPPER>(S, rec, int64_t(sl0 + gg) * 64, off0 + offr, wl & 15,
+            fetch_item<TF, UPPER, VEC>(S, rec, int64_t(sl0 + gg) * 64, off0 + offr, wl & 15,
                                   ((wl >> 10) & 127) * (((wl >> 4) & 63) + 1), grp[k]);
         }
         fg += K * nw;
@@ -192,18 +201,24 @@ __device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int 
             if (it.wl < 0) break;
             const int w = it.wl & 15, sp = ((it.wl >> 4) & 63) + 1, nrow = (it.wl >> 10) & 127;
             const int rr = (lane * ((65536 + sp - 1) / sp)) >> 16, first = rr * sp;  // row in the slice
-            TF acc = consume(it, w, ring, it.h.x);
+            const bool writer = lane == first && rr < nrow;
+            TF v0;
+            if constexpr (!VEC) v0 = it.h.x;
+            else if constexpr (UPPER) v0 = it.row >= 0 ? ring[it.row] : TF(0);
+            else v0 = writer ? ring[it.slot + rr] : TF(0);
+            TF acc = consume(it, w, ring, v0);
             if (sp > 1) {  // the row's first lane adds its other parts in order
                 TF sum = acc;
                 for (int d = 1; d < sp; ++d) sum += __shfl(acc, min(first + d, 63));
                 acc = sum;
             }
             if constexpr (UPPER) acc *= it.h.y;
-            if (lane == first && rr < nrow) {
-                ring[it.slot + rr] = acc;
+            if (writer) {
+                if constexpr (VEC && UPPER) ring[it.row] = acc;
+                else ring[it.slot + rr] = acc;
                 if constexpr (UPPER) {
                     if (it.io >= 0) y[it.io] = TV(acc);
-                } else {
+                } else if constexpr (!VEC) {
                     if (it.io >= 0) lout[2 * int64_t(it.io)] = acc;
                 }
             }
@@ -259,16 +274,20 @@ __device__ __forceinline__ int stage_meta(const DevSweep<TF> &S, int lev0, int l
 
 // One workgroup per subdomain: gather x (coalesced over the L-sweep order),
 // L sweep, U sweep with restricted scatter.  The ring of the last `depth`
-// levels is in LDS when LDS = true, else in the workspace.
-template <class TV, class TF, bool LDS, int NT>
+// levels is in LDS when LDS = true, else in the workspace; with VEC (always
+// in LDS) the whole box vector is there instead: the gather writes x into it,
+// the L sweep overwrites it with its results and the U sweep with its own.
+template <class TV, class TF, bool LDS, bool VEC, int NT>
 __global__ __launch_bounds__(NT) void k_ras(DevRas<TF> R, int meta_lev, int meta_sl, const TV *__restrict__ x,
                                             TV *__restrict__ y) {
+    static_assert(LDS || !VEC, "the box vector lives in LDS");
     extern __shared__ __align__(16) unsigned char ras_smem[];
     const SdInfo I = R.sd[blockIdx.x];
     const int ring_n = R.depth * R.width;
     TF *ring = LDS ? reinterpret_cast<TF *>(ras_smem + meta_bytes_for(meta_sl, meta_lev))
                    : R.ring + int64_t(blockIdx.x) * ring_n;
-    for (int a = threadIdx.x; a < ring_n; a += NT) ring[a] = TF(0);
+    if constexpr (!VEC)
+        for (int a = threadIdx.x; a < ring_n; a += NT) ring[a] = TF(0);
     Meta M;
     int nsl;
     int sl0 = stage_meta<TF, NT>(R.L, I.levL0, I.levL1, meta_lev, meta_sl, ras_smem, M, nsl);
@@ -278,23 +297,31 @@ __global__ __launch_bounds__(NT) void k_ras(DevRas<TF> R, int meta_lev, int meta
         constexpr int U = 8;
         const int64_t p0 = int64_t(sl0) * 64, p1 = int64_t(sl0 + nsl) * 64;
         for (int64_t p = p0 + threadIdx.x; p < p1; p += int64_t(NT) * U) {
-            int32_t io[U];
+            int32_t io[U], pos[U];
             TV v[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) io[u] = p + u * NT < p1 ? R.L.lane_io[p + u * NT] : -1;
+            for (int u = 0; u < U; ++u) {
+                io[u] = p + u * NT < p1 ? R.L.lane_io[p + u * NT] : -1;
+                if constexpr (VEC) pos[u] = p + u * NT < p1 ? R.L.lane_next[p + u * NT] : -1;
+            }
 #pragma unroll
             for (int u = 0; u < U; ++u) v[u] = io[u] >= 0 ? x[io[u]] : TV(0);
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (p + u * NT < p1) R.lin[p + u * NT] = TF(v[u]);
+            for (int u = 0; u < U; ++u) {
+                if constexpr (VEC) {
+                    if (pos[u] >= 0) ring[pos[u]] = TF(v[u]);
+                } else if (p + u * NT < p1) {
+                    R.lin[p + u * NT] = TF(v[u]);
+                }
+            }
         }
     }
     __syncthreads();
-    sweep<TV, TF, false, LDS, NT>(R.L, M, sl0, I.levL1 - I.levL0, nsl, ring, R.lin, reinterpret_cast<TF *>(R.lout),
-                                  y);
+    sweep<TV, TF, false, LDS, VEC, NT>(R.L, M, sl0, I.levL1 - I.levL0, nsl, ring, R.lin,
+                                       reinterpret_cast<TF *>(R.lout), y);
     __syncthreads();  // L results visible; the U metadata replaces the L metadata
     sl0 = stage_meta<TF, NT>(R.U, I.levU0, I.levU1, meta_lev, meta_sl, ras_smem, M, nsl);
-    sweep<TV, TF, true, LDS, NT>(R.U, M, sl0, I.levU1 - I.levU0, nsl, ring, R.lout, nullptr, y);
+    sweep<TV, TF, true, LDS, VEC, NT>(R.U, M, sl0, I.levU1 - I.levU0, nsl, ring, R.lout, nullptr, y);
 }
 
 // restriction: mean of the 8 children; prolongation: copy to the children
@@ -342,6 +369,8 @@ struct OneLevel {
     int nsd = 0;
     int64_t nnz = 0, box_cells = 0, owned_cells = 0;
     int depth = 0, width = 0, meta_lev = 0, meta_sl = 0, max_total_levels = 0;
+    bool vec = false;  // box vector in LDS instead of the level ring
+    int box_rows = 0;
     int threads = 256;
     size_t lds_bytes = 0;
     bool lds_ring = false;
@@ -350,7 +379,7 @@ struct OneLevel {
     int32_t *Llev = nullptr, *Lw = nullptr, *Lslot = nullptr, *Lio = nullptr, *Lnext = nullptr;
     int64_t *Loff = nullptr;
     uint16_t *Laddr = nullptr;
-    int32_t *Ulev = nullptr, *Uw = nullptr, *Uslot = nullptr, *Uio = nullptr;
+    int32_t *Ulev = nullptr, *Uw = nullptr, *Uslot = nullptr, *Uio = nullptr, *Unext = nullptr;
     int64_t *Uoff = nullptr;
     uint16_t *Uaddr = nullptr;
     void *Lval = nullptr, *Uval = nullptr, *lin = nullptr, *lout = nullptr, *ring = nullptr;
@@ -360,6 +389,7 @@ struct OneLevel {
         o.nsd = H.nsd; o.nnz = H.nnz; o.box_cells = H.box_cells; o.owned_cells = H.owned_cells;
         o.depth = H.ring_depth; o.width = H.ring_width; o.meta_lev = H.max_levels; o.meta_sl = H.max_slices;
         o.max_total_levels = H.max_total_levels; o.precision = precision;
+        o.vec = H.box_vector; o.box_rows = H.box_rows;
         o.sd = c.take<SdInfo>(H.sd.size());
         o.Llev = c.take<int32_t>(H.L.lev_slice.size()); o.Lw = c.take<int32_t>(H.L.sl_info.size());
         o.Loff = c.take<int64_t>(H.L.sl_off.size()); o.Lslot = c.take<int32_t>(H.L.sl_slot.size());
@@ -369,6 +399,7 @@ struct OneLevel {
         o.Ulev = c.take<int32_t>(H.U.lev_slice.size()); o.Uw = c.take<int32_t>(H.U.sl_info.size());
         o.Uoff = c.take<int64_t>(H.U.sl_off.size()); o.Uslot = c.take<int32_t>(H.U.sl_slot.size());
         o.Uio = c.take<int32_t>(H.U.lane_io.size());
+        o.Unext = c.take<int32_t>(H.U.lane_next.size());
         o.Uaddr = c.take<uint16_t>(H.U.addr.size());
         o.Uval = c.take<char>(H.U.val.size() * fs);
         o.lin = c.take<char>(H.L.lane_io.size() * fs);
@@ -391,6 +422,7 @@ struct OneLevel {
         CSD_HIP(up(Uoff, H.U.sl_off.data(), H.U.sl_off.size() * 8));
         CSD_HIP(up(Uslot, H.U.sl_slot.data(), H.U.sl_slot.size() * 4));
         CSD_HIP(up(Uio, H.U.lane_io.data(), H.U.lane_io.size() * 4));
+        CSD_HIP(up(Unext, H.U.lane_next.data(), H.U.lane_next.size() * 4));
         CSD_HIP(up(Uaddr, H.U.addr.data(), H.U.addr.size() * 2));
         // U-sweep records {L result, 1/u_ii}: the L sweep writes the first
         // half; padding lanes read results that are never written, so start at 0
@@ -415,41 +447,47 @@ struct OneLevel {
         R.sd = sd;
         using TF2 = typename Pair<TF>::type;
         R.L = DevSweep<TF>{Llev, Lw, Loff, Lslot, Lio, Lnext, (const TF2 *)Lval, (const uint4 *)Laddr};
-        R.U = DevSweep<TF>{Ulev, Uw, Uoff, Uslot, Uio, nullptr, (const TF2 *)Uval, (const uint4 *)Uaddr};
+        R.U = DevSweep<TF>{Ulev, Uw, Uoff, Uslot, Uio, Unext, (const TF2 *)Uval, (const uint4 *)Uaddr};
         R.lin = (TF *)lin;
         R.lout = (TF2 *)lout;
         R.ring = (TF *)ring;
-        R.depth = depth;
-        R.width = width;
+        R.depth = vec ? 1 : depth;
+        R.width = vec ? box_rows : width;
         return R;
     }
 
-    template <class TV, class TF, bool LDS, int NT>
-    static const void *kernel() { return (const void *)k_ras<TV, TF, LDS, NT>; }
+    template <class TV, class TF, bool LDS, bool VEC, int NT>
+    static const void *kernel() { return (const void *)k_ras<TV, TF, LDS, VEC, NT>; }
 
     template <class TV, class TF>
     int32_t set_attr() const {
         const hipFuncAttribute at = hipFuncAttributeMaxDynamicSharedMemorySize;
         const int lb = int(lds_bytes);
-        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, 256>(), at, lb));
-        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, 512>(), at, lb));
-        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, 1024>(), at, lb));
-        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, false, 256>(), at, lb));
-        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, false, 512>(), at, lb));
-        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, false, 1024>(), at, lb));
+        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, false, 256>(), at, lb));
+        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, false, 512>(), at, lb));
+        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, false, 1024>(), at, lb));
+        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, false, false, 256>(), at, lb));
+        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, false, false, 512>(), at, lb));
+        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, false, false, 1024>(), at, lb));
+        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, true, 256>(), at, lb));
+        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, true, 512>(), at, lb));
+        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, true, 1024>(), at, lb));
         return CSDYN_OK;
     }
 
-    // The ring goes to LDS when it fits next to the metadata; the workgroup
-    // size covers one level's slices with one wavefront each (256..1024).
+    // The ring (or the box vector) goes to LDS when it fits next to the
+    // metadata; the workgroup size covers one level's slices with one
+    // wavefront each (256..1024).
     int32_t choose_memory() {
         int dev = 0, maxs = 0;
         CSD_HIP(hipGetDevice(&dev));
         CSD_HIP(hipDeviceGetAttribute(&maxs, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
         const size_t meta = meta_bytes_for(meta_sl, meta_lev);
-        const size_t rb = size_t(depth) * width * (precision ? sizeof(float) : sizeof(double));
+        const size_t fs = precision ? sizeof(float) : sizeof(double);
+        const size_t rb = vec ? size_t(box_rows) * fs : size_t(depth) * width * fs;
         if (meta > size_t(maxs)) { set_error("ras: subdomain schedule too large for LDS"); return CSDYN_EINVAL; }
         lds_ring = meta + rb <= size_t(maxs);
+        if (vec && !lds_ring) { set_error("ras: subdomain vector does not fit in LDS"); return CSDYN_EINVAL; }
         lds_bytes = meta + (lds_ring ? rb : 0);
         threads = width <= 256 ? 256 : (width <= 512 ? 512 : 1024);
         if (precision) {
@@ -461,18 +499,19 @@ struct OneLevel {
         return CSDYN_OK;
     }
 
-    template <class TV, class TF, bool LDS>
+    template <class TV, class TF, bool LDS, bool VEC>
     void launch_nt(const TV *x, TV *y, hipStream_t s) const {
         const dim3 g(nsd);
-        if (threads == 256) hipLaunchKernelGGL((k_ras<TV, TF, LDS, 256>), g, dim3(256), lds_bytes, s, dev<TF>(), meta_lev, meta_sl, x, y);
-        else if (threads == 512) hipLaunchKernelGGL((k_ras<TV, TF, LDS, 512>), g, dim3(512), lds_bytes, s, dev<TF>(), meta_lev, meta_sl, x, y);
-        else hipLaunchKernelGGL((k_ras<TV, TF, LDS, 1024>), g, dim3(1024), lds_bytes, s, dev<TF>(), meta_lev, meta_sl, x, y);
+        if (threads == 256) hipLaunchKernelGGL((k_ras<TV, TF, LDS, VEC, 256>), g, dim3(256), lds_bytes, s, dev<TF>(), meta_lev, meta_sl, x, y);
+        else if (threads == 512) hipLaunchKernelGGL((k_ras<TV, TF, LDS, VEC, 512>), g, dim3(512), lds_bytes, s, dev<TF>(), meta_lev, meta_sl, x, y);
+        else hipLaunchKernelGGL((k_ras<TV, TF, LDS, VEC, 1024>), g, dim3(1024), lds_bytes, s, dev<TF>(), meta_lev, meta_sl, x, y);
     }
 
     template <class TV, class TF>
     void launch(const TV *x, TV *y, hipStream_t s) const {
-        if (lds_ring) launch_nt<TV, TF, true>(x, y, s);
-        else launch_nt<TV, TF, false>(x, y, s);
+        if (vec) launch_nt<TV, TF, true, true>(x, y, s);
+        else if (lds_ring) launch_nt<TV, TF, true, false>(x, y, s);
+        else launch_nt<TV, TF, false, false>(x, y, s);
     }
 
     template <class TV>
@@ -529,13 +568,13 @@ static int32_t check_opts(const csdyn_opctx *ctx, const csdyn_ras_opts *o) {
 static int32_t host_build(const csdyn_opctx *ctx, const csdyn_ras_opts *o, std::shared_ptr<HostBuild> &out) {
     auto b = std::make_shared<HostBuild>();
     b->g = ctx->g; b->op = ctx->op; b->o = *o;
-    CSD_TRY(build_host_ras(ctx->hg, ctx->op, o->sub, o->overlap, b->fine));
+    CSD_TRY(build_host_ras(ctx->hg, ctx->op, o->sub, o->overlap, o->storage, b->fine));
     if (o->levels == 2) {
         csdyn_grid gc = ctx->g;
         gc.n /= 2; gc.nr /= 2;
         CSD_TRY(b->gc.build(gc));
         const int subc[3] = {o->sub[0] / 2, o->sub[1] / 2, o->sub[2] / 2};
-        CSD_TRY(build_host_ras(b->gc, ctx->op, subc, o->overlap, b->coarse));
+        CSD_TRY(build_host_ras(b->gc, ctx->op, subc, o->overlap, o->storage, b->coarse));
     }
     out = std::move(b);
     return CSDYN_OK;
@@ -646,9 +685,9 @@ extern "C" int32_t csdyn_ras_setup(const csdyn_opctx *ctx, const csdyn_ras_opts 
 
     }
     R->info.lds_fine = int32_t(R->fine.lds_bytes);
-    R->info.box_in_lds_fine = R->fine.lds_ring;
+    R->info.box_in_lds_fine = R->fine.vec ? 2 : R->fine.lds_ring;
     R->info.lds_coarse = int32_t(R->coarse.lds_bytes);
-    R->info.box_in_lds_coarse = R->coarse.lds_ring;
+    R->info.box_in_lds_coarse = R->coarse.vec ? 2 : R->coarse.lds_ring;
     if (stream) CSD_HIP(hipStreamSynchronize((hipStream_t)stream));
     *out = R.release();
     return CSDYN_OK;

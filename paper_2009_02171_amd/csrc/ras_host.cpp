@@ -331,7 +331,12 @@ struct Schedule {
     std::vector<int32_t> slot;        // [nrow] ring slot
 };
 
-void make_schedule(const LocalSd &L, bool upper, int depth, int width, Schedule &S) {
+// Ring addressing (depth > 0): slot = (level mod depth) * width + position in
+// the level.  Box-vector addressing (depth == 0): the L sweep's slot is the
+// row's position in the L sweep's order (levels one after another), and the U
+// sweep addresses rows by the L sweep's slots (lslot).
+void make_schedule(const LocalSd &L, bool upper, int depth, int width, const std::vector<int32_t> *lslot,
+                   Schedule &S) {
     const int64_t nrow = int64_t(L.rp.size()) - 1;
     const int nlev = upper ? L.nlevU : L.nlevL;
     const std::vector<int32_t> &lev = upper ? L.levU : L.levL;
@@ -345,6 +350,11 @@ void make_schedule(const LocalSd &L, bool upper, int depth, int width, Schedule 
     S.slice_slot.clear();
     S.pos.assign(nrow, -1);
     S.slot.assign(nrow, -1);
+    int64_t cum = 0;  // rows of the previous levels
+    auto slot_of = [&](int lv, int64_t a, int32_t r) -> int32_t {
+        if (depth > 0) return int32_t((lv % depth) * width + a);
+        return lslot ? (*lslot)[r] : int32_t(cum + a);
+    };
     for (int lv = 0; lv < nlev; ++lv) {
         auto &R = rows[lv];
         std::stable_sort(R.begin(), R.end(), [&](int32_t a, int32_t b) { return cnt(a) > cnt(b); });
@@ -355,26 +365,29 @@ void make_schedule(const LocalSd &L, bool upper, int depth, int width, Schedule 
             const int sl = int(S.slice_s.size());
             S.slice_s.push_back(sp);
             S.slice_nrow.push_back(nr);
-            S.slice_slot.push_back(depth > 0 ? (lv % depth) * width + int(a) : -1);
+            S.slice_slot.push_back(lslot ? -1 : slot_of(lv, int64_t(a), R[a]));
             for (int l = 0; l < 64; ++l) {
                 const int rr = l / sp;
                 S.slice_rows.push_back(rr < nr ? R[a + rr] : -1);
             }
             for (int rr = 0; rr < nr; ++rr) {
                 S.pos[R[a + rr]] = sl * 64 + rr * sp;
-                S.slot[R[a + rr]] = depth > 0 ? (lv % depth) * width + int(a) + rr : -1;
+                S.slot[R[a + rr]] = slot_of(lv, int64_t(a) + rr, R[a + rr]);
             }
             a += nr;
             ++nsl;
         }
         S.lev_first.push_back(S.lev_first.back() + nsl);
+        cum += int64_t(R.size());
     }
 }
 
-// Append one subdomain's sweep to the pack.  U_sched is the U schedule (for
-// the L sweep's lane_next); base_u its first global U slice.
+// Append one subdomain's sweep to the pack.  Ring addressing: U_sched is the
+// U schedule (for the L sweep's lane_next), base_u its first global U slice.
+// Box-vector addressing (box_vector): lane_next is the row's position in the
+// box vector (its L-sweep slot) in both sweeps.
 int32_t pack_sweep(const LocalSd &L, bool upper, const Schedule &S, const Schedule *U_sched, int64_t base_u,
-                   SweepPack &P, int32_t &lev0, int32_t &lev1) {
+                   bool box_vector, SweepPack &P, int32_t &lev0, int32_t &lev1) {
     auto first = [&](int64_t r) { return upper ? L.diag[r] + 1 : L.rp[r]; };
     auto cnt = [&](int64_t r) -> int64_t { return upper ? L.rp[r + 1] - L.diag[r] - 1 : L.diag[r] - L.rp[r]; };
     const int64_t base = int64_t(P.sl_info.size());
@@ -408,9 +421,10 @@ int32_t pack_sweep(const LocalSd &L, bool upper, const Schedule &S, const Schedu
                 if (upper) {
                     dg = L.v[L.diag[r]];
                     if (j == 0 && L.owned_row[r / 4]) io = int32_t(4 * int64_t(L.gcell[r / 4]) + r % 4);
+                    if (j == 0 && box_vector) nxt = S.slot[r];
                 } else if (j == 0) {
                     io = int32_t(4 * int64_t(L.gcell[r / 4]) + r % 4);
-                    nxt = int32_t(base_u * 64 + U_sched->pos[r]);
+                    nxt = box_vector ? S.slot[r] : int32_t(base_u * 64 + U_sched->pos[r]);
                 }
                 const int64_t q0 = first(r), n = cnt(r);
                 for (int e = 0; e < kLaneEntries; ++e) {
@@ -424,8 +438,8 @@ int32_t pack_sweep(const LocalSd &L, bool upper, const Schedule &S, const Schedu
                 }
             }
             P.lane_io.push_back(io);
-            if (!upper) P.lane_next.push_back(nxt);
-            else P.lane_diag.push_back(dg);
+            if (!upper || box_vector) P.lane_next.push_back(nxt);
+            if (upper) P.lane_diag.push_back(dg);
         }
     }
     if (int64_t(P.val.size()) / 2 - pair0 > INT32_MAX) {  // the sweep kernel keeps 32-bit offsets per subdomain
@@ -478,7 +492,8 @@ void stencil_row(const HostGeom &g, const csdyn_op &op, int p, int i, int j, int
     ex.row(p, i, j, k, c);
 }
 
-int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], int overlap, HostRas &H) {
+int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], int overlap, int storage,
+                       HostRas &H) {
     if (sub[0] < 1 || sub[1] < 1 || sub[2] < 1 || g.n % sub[0] || g.n % sub[1] || g.nr % sub[2]) {
         set_error("ras: grid %dx%dx%d is not divisible by subdomain %dx%dx%d", g.n, g.n, g.nr, sub[0], sub[1], sub[2]);
         return CSDYN_EINVAL;
@@ -512,7 +527,14 @@ int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], 
     }
     H.ring_depth = span + 1;
     H.ring_width = ((rows + 63) / 64) * 64;
-    if (int64_t(H.ring_depth) * H.ring_width > 65536) {
+    for (int s = 0; s < H.nsd; ++s) H.box_rows = std::max(H.box_rows, int(loc[s].rp.size()) - 1);
+    if (storage < 0 || storage > 2) { set_error("ras: storage must be 0, 1 or 2"); return CSDYN_EINVAL; }
+    H.box_vector = storage == 2 || (storage == 0 && int64_t(H.box_rows) * int64_t(sizeof(double)) <= kBoxVectorBytes);
+    if (H.box_vector && H.box_rows > 65535) {
+        set_error("ras: subdomain of %d rows too large for 16-bit vector addresses", H.box_rows);
+        return CSDYN_EINVAL;
+    }
+    if (!H.box_vector && int64_t(H.ring_depth) * H.ring_width > 65536) {
         set_error("ras: subdomain too large for the level ring (%d levels x %d rows)", H.ring_depth, H.ring_width);
         return CSDYN_EINVAL;
     }
@@ -526,11 +548,12 @@ int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], 
         H.owned_cells += I.nown;
         H.nnz += int64_t(L.ci.size());
         Schedule SL, SU;
-        make_schedule(L, false, H.ring_depth, H.ring_width, SL);
-        make_schedule(L, true, H.ring_depth, H.ring_width, SU);
+        const int depth = H.box_vector ? 0 : H.ring_depth;
+        make_schedule(L, false, depth, H.ring_width, nullptr, SL);
+        make_schedule(L, true, depth, H.ring_width, H.box_vector ? &SL.slot : nullptr, SU);
         const int64_t base_u = int64_t(H.U.sl_info.size());
-        if (int32_t e = pack_sweep(L, true, SU, nullptr, 0, H.U, I.levU0, I.levU1)) return e;
-        if (int32_t e = pack_sweep(L, false, SL, &SU, base_u, H.L, I.levL0, I.levL1)) return e;
+        if (int32_t e = pack_sweep(L, true, SU, nullptr, 0, H.box_vector, H.U, I.levU0, I.levU1)) return e;
+        if (int32_t e = pack_sweep(L, false, SL, &SU, base_u, H.box_vector, H.L, I.levL0, I.levL1)) return e;
         H.max_slices = std::max(H.max_slices, std::max(SL.lev_first.back(), SU.lev_first.back()));
         H.max_levels = std::max(H.max_levels, std::max(L.nlevL, L.nlevU));
         H.max_total_levels = std::max(H.max_total_levels, L.nlevL + L.nlevU);

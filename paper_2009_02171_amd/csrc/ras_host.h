@@ -34,7 +34,8 @@ struct SweepPack {
     std::vector<int64_t> sl_off;     // [nslice] first value pair
     std::vector<int32_t> sl_slot;    // [nslice] ring slot of the first row
     std::vector<int32_t> lane_io;    // [nslice*64] L: x index; U: y index of an owned row (first lane of a row); else -1
-    std::vector<int32_t> lane_next;  // [nslice*64] L only: U-sweep position (slice*64 + first lane) of the row
+    std::vector<int32_t> lane_next;  // [nslice*64] ring: L only, U-sweep position (slice*64 + first lane) of the
+                                     // row; box vector: both sweeps, the row's position in the box vector
     std::vector<double> lane_diag;   // [nslice*64] U only: u_ii (0 on padding lanes)
     std::vector<double> val;         // [2 * pairs]
     std::vector<uint16_t> addr;      // [8 * 64 * nslice] ring slot of the dependency
@@ -45,12 +46,20 @@ struct SdInfo {
     int32_t nloc, nown;
 };
 
+constexpr int64_t kBoxVectorBytes = 90 * 1024;
+
 struct HostRas {
     int nsd = 0;
     int nb[3] = {0, 0, 0};
     std::vector<SdInfo> sd;
     SweepPack L, U;
     int ring_depth = 0, ring_width = 0;  // levels kept, lanes per level
+    // Box-vector addressing: when a subdomain's whole FP64 vector fits the
+    // budget below, the sweep keeps it in LDS (the gathered input, then the L
+    // results, then the U results, in place) and addresses dependencies by the
+    // row's position in the L sweep's order instead of a ring slot.
+    bool box_vector = false;
+    int box_rows = 0;  // rows of the largest subdomain
     int max_slices = 0, max_levels = 0;  // per sweep of one subdomain (LDS metadata sizing)
     int64_t nnz = 0;                     // factor entries (L and U, diagonal included)
     int64_t box_cells = 0, owned_cells = 0;
@@ -58,7 +67,10 @@ struct HostRas {
 };
 
 // Build and factor.  Returns CSDYN_EZEROPIVOT / CSDYN_EINVAL on failure.
-int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], int overlap, HostRas &out);
+// storage: 0 automatic (box vector when its FP64 size fits kBoxVectorBytes),
+// 1 ring, 2 box vector.
+int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], int overlap, int storage,
+                       HostRas &out);
 
 // One subdomain's box cells, owned cells and ILU(0) factors as CSR (L strictly
 // lower with unit diagonal implied, U upper), for inspection.

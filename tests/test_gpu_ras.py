@@ -24,14 +24,21 @@ def _apply(pc, x):
     return y.cpu().numpy()
 
 
-@pytest.mark.parametrize("n,nr,kind,sub", [(8, 4, 0, (4, 4, 2)), (8, 4, 1, (4, 4, 2)), (16, 16, 0, (16, 16, 16)),
-                                           (16, 16, 1, (16, 16, 16)), (12, 6, 1, (6, 4, 3)), (24, 8, 0, (8, 8, 4))])
-def test_one_level_matches_oracle(n, nr, kind, sub):
-    print(f"[ras parity] n={n} nr={nr} kind={kind} sub={sub}", flush=True)
+# storage 1: ring of recent levels; 2: whole subdomain vector in LDS (too large
+# for the 16^3 boxes in FP64)
+ONE_LEVEL_CASES = [(8, 4, 0, (4, 4, 2), 1), (8, 4, 1, (4, 4, 2), 1), (16, 16, 0, (16, 16, 16), 1),
+                   (16, 16, 1, (16, 16, 16), 1), (12, 6, 1, (6, 4, 3), 1), (24, 8, 0, (8, 8, 4), 1),
+                   (8, 4, 0, (4, 4, 2), 2), (8, 4, 1, (4, 4, 2), 2), (12, 6, 1, (6, 4, 3), 2), (24, 8, 0, (8, 8, 4), 2)]
+
+
+@pytest.mark.parametrize("n,nr,kind,sub,storage", ONE_LEVEL_CASES)
+def test_one_level_matches_oracle(n, nr, kind, sub, storage):
+    print(f"[ras parity] n={n} nr={nr} kind={kind} sub={sub} storage={storage}", flush=True)
     pb = O.Problem(n, nr, kind=kind)
     x = inputs.random_field(pb.shape(), seed=21 + n)
     y_ref = O.Preconditioner(pb, sub=sub, levels=1).apply(x)
-    _, pc = _setup(n, nr, kind, sub)
+    _, pc = _setup(n, nr, kind, sub, storage=storage)
+    assert pc.info()["box_in_lds_fine"] == storage
     y = _apply(pc, x)
     assert np.abs(y - y_ref).max() / np.abs(y_ref).max() <= 1e-12
 
@@ -53,16 +60,16 @@ def test_one_level_full_size_sampled(kind):
         assert np.abs(y[m] - ys[m]).max() / np.abs(ys[m]).max() <= 1e-12, s
 
 
-@pytest.mark.parametrize("kind", [0, 1])
-def test_two_level_matches_oracle(kind):
+@pytest.mark.parametrize("kind,storage", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_two_level_matches_oracle(kind, storage):
     """Hybrid two-level apply; the inner coarse GMRES runs to rtol 0.1 on both
     sides, so the Krylov paths agree to rounding."""
     n, nr, sub = 16, 8, (8, 8, 4)
-    print(f"[two-level parity] kind={kind}", flush=True)
+    print(f"[two-level parity] kind={kind} storage={storage}", flush=True)
     pb = O.Problem(n, nr, kind=kind)
     x = inputs.random_field(pb.shape(), seed=31 + kind)
     y_ref = O.Preconditioner(pb, sub=sub, levels=2).apply(x)
-    _, pc = _setup(n, nr, kind, sub, levels=2)
+    _, pc = _setup(n, nr, kind, sub, levels=2, storage=storage)
     y = _apply(pc, x)
     assert np.abs(y - y_ref).max() / np.abs(y_ref).max() <= 1e-9
 
@@ -85,16 +92,23 @@ def test_ras_rejects_bad_options():
         csdyn.RAS(op, sub=(5, 4, 3))
     with pytest.raises(csdyn.CsdynError):
         csdyn.RAS(op, sub=(6, 6, 3), levels=2)   # odd subdomain size for two levels
+    with pytest.raises(csdyn.CsdynError):
+        csdyn.RAS(op, sub=(6, 6, 3), storage=3)
+    big = csdyn.Operator(16, 16)
+    with pytest.raises(csdyn.CsdynError):       # a 16^3 box's FP64 vector does not fit in LDS
+        csdyn.RAS(big, sub=(16, 16, 16), storage=2)
 
 
-@pytest.mark.parametrize("n,nr,kind,sub", [(8, 4, 0, (4, 4, 2)), (16, 16, 1, (16, 16, 16)), (24, 8, 0, (8, 8, 4))])
-def test_one_level_fp32_matches_oracle_emulation(n, nr, kind, sub):
+@pytest.mark.parametrize("n,nr,kind,sub,storage", [(8, 4, 0, (4, 4, 2), 1), (16, 16, 1, (16, 16, 16), 1),
+                                                   (24, 8, 0, (8, 8, 4), 1), (8, 4, 0, (4, 4, 2), 2),
+                                                   (24, 8, 0, (8, 8, 4), 2)])
+def test_one_level_fp32_matches_oracle_emulation(n, nr, kind, sub, storage):
     """FP32 factors and sweeps: GPU against the oracle's FP32 emulation."""
-    print(f"[ras fp32 parity] n={n} nr={nr} kind={kind}", flush=True)
+    print(f"[ras fp32 parity] n={n} nr={nr} kind={kind} storage={storage}", flush=True)
     pb = O.Problem(n, nr, kind=kind)
     x = inputs.random_field(pb.shape(), seed=51 + n)
     y_ref = O.Preconditioner(pb, sub=sub, levels=1, precision=1).apply(x)
-    _, pc = _setup(n, nr, kind, sub, precision=1)
+    _, pc = _setup(n, nr, kind, sub, precision=1, storage=storage)
     y = _apply(pc, x)
     assert np.abs(y - y_ref).max() / np.abs(y_ref).max() <= 1e-5
 
