@@ -40,11 +40,11 @@ struct DevSweep {
     const int32_t *lev_slice;  // [nlev + 1] first slice of each level
     const int32_t *sl_info;    // [nslice] rows << 10 | (s - 1) << 4 | entries per lane
     const int64_t *sl_off;     // [nslice] first value pair
-    const int32_t *sl_slot;    // [nslice] ring slot of the first row
+    const int32_t *sl_slot;    // [nslice] ring slot (box vector: L-sweep position) of the first row
     const int32_t *lane_io;    // [nslice*64] L: x index; U: y index of owned rows; else -1
-    const int32_t *lane_next;  // [nslice*64] L: U-sweep position of the row
+    const int32_t *lane_next;  // [nslice*64] ring: L, U-sweep position of the row; box vector: the row's position
     const TF2 *val;            // [pairs] factor entries, two per lane
-    const uint4 *addr;         // [64 * nslice] ring slots of the dependencies, eight per lane
+    const uint4 *addr;         // [64 * nslice] addresses of the dependencies (ring slots or positions), eight per lane
 };
 
 template <class TF>
@@ -52,15 +52,15 @@ struct DevRas {
     using TF2 = typename Pair<TF>::type;
     const SdInfo *sd;
     DevSweep<TF> L, U;
-    TF *lin;    // [L slices * 64] gathered inputs of the L sweep
-    TF2 *lout;  // [U slices * 64] {L-sweep result, 1/u_ii} in U-sweep order (0 where never written)
+    TF *lin;    // [L slices * 64] gathered inputs of the L sweep (ring only)
+    TF2 *lout;  // [U slices * 64] {L-sweep result (ring only), 1/u_ii} in U-sweep order (0 where never written)
     TF *ring;   // [nsd][depth * width] when the ring is not in LDS
     int depth, width;
 };
 
 // One item of a sweep: one slice for one lane, i.e. the lane's part (at most
-// eight entries) of its row: values in pairs, 16-bit ring slots two to a
-// register, the row's {input value, 1/u_ii} and output index, and the
+// eight entries) of its row: values in pairs, 16-bit dependency addresses two
+// to a register, the row's {input value, 1/u_ii} and output index, and the
 // slice's wave-uniform description.  Nothing in it depends on values computed
 // in the sweep (inputs were gathered before, addresses and factors are
 // constant), so each wavefront requests its items well ahead of use; the
@@ -74,7 +74,7 @@ struct Item {
     int32_t io;    // ring, L: U position of the row; U: y index or -1
     int32_t row;   // box vector, U: position of the row in the box vector (first lane of a row) or -1
     int32_t wl;    // level << 17 | sl_info; -1 past the wavefront's last slice
-    int32_t slot;  // ring slot of the slice's first row
+    int32_t slot;  // ring slot (box vector, L: position) of the slice's first row
 };
 
 // Seven loads per item whatever the slice (pairs past the slice's width
@@ -117,10 +117,10 @@ __device__ __forceinline__ TF consume(const Item<TF> &X, int w, const TF *ring, 
     return acc;
 }
 
-// Barrier between levels.  When the ring is in LDS only LDS traffic has to be
-// complete, so the fence is LDS-scoped: global loads issued before it (later
-// items) stay in flight.  On this GPU family a full fence would also wait for
-// every outstanding global load.
+// Barrier between levels.  When the computed values are in LDS (ring or box
+// vector) only LDS traffic has to be complete, so the fence is LDS-scoped:
+// global loads issued before it (later items) stay in flight.  On this GPU
+// family a full fence would also wait for every outstanding global load.
 template <bool LDS_ONLY>
 __device__ __forceinline__ void level_barrier() {
     if constexpr (LDS_ONLY) {
@@ -146,7 +146,7 @@ struct Meta {
     int32_t *lev;   // [nlev + 1] first slice of each level (relative)
     int32_t *off;   // [nsl] first value pair, relative to the subdomain's first
     int32_t *wl;    // [nsl] level << 17 | sl_info
-    int32_t *slot;  // [nsl] ring slot of the first row
+    int32_t *slot;  // [nsl] ring slot (box vector, L: position) of the first row
 };
 
 // One triangular sweep of one subdomain.  Slices are dealt to wavefronts
@@ -156,11 +156,12 @@ struct Meta {
 // a group is requested again as soon as it has been processed, so the wait
 // for a group never waits for the other.  Barrier b ends level b: a
 // wavefront passes it as soon as it has finished its slices of levels <= b,
-// so every row of levels <= b is in the ring before any row of level b + 1
-// reads it.  Every wavefront passes all nlev barriers.  The lanes of a split
-// row add their partial sums in a fixed order; the row's first lane writes
-// the result to its ring slot and, in the L sweep, to its U-sweep record; the
-// U sweep writes the owned rows to y (restricted scatter).
+// so every row of levels <= b is in LDS before any row of level b + 1 reads
+// it.  Every wavefront passes all nlev barriers.  The lanes of a split row add
+// their partial sums in a fixed order; the row's first lane writes the result
+// to its ring slot (box vector: its position) and, in the ring layout's L
+// sweep, to its U-sweep record; the U sweep writes the owned rows to y
+// (restricted scatter).
 template <class TV, class TF, bool UPPER, bool LDS, bool VEC, int NT, class Rec>
 __device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int sl0, int nlev, int nsl, TF *ring,
                                       const Rec *rec, TF *lout, TV *y) {
@@ -188,7 +189,7 @@ __device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int 
             grp[k].wl = g < nsl ? wl : -1;
             grp[k].slot = __builtin_amdgcn_readfirstlane(M.slot[gg]);
             fetch_item<TF, UPPER, VEC>(S, rec, int64_t(sl0 + gg) * 64, off0 + offr, wl & 15,
-                                  ((wl >> 10) & 127) * (((wl >> 4) & 63) + 1), grp[k]);
+                                       ((wl >> 10) & 127) * (((wl >> 4) & 63) + 1), grp[k]);
         }
         fg += K * nw;
         __builtin_amdgcn_sched_barrier(0);
