@@ -42,7 +42,8 @@ struct DevSweep {
     const int64_t *sl_off;     // [nslice] first value pair
     const int32_t *sl_slot;    // [nslice] ring slot (box vector: L-sweep position) of the first row
     const int32_t *lane_io;    // [nslice*64] L: x index; U: y index of owned rows; else -1
-    const int32_t *lane_next;  // [nslice*64] ring: L, U-sweep position of the row; box vector: the row's position
+    const int32_t *lane_next;  // [nslice*64] ring: L, U-sweep position of the row; box vector: L, the row's
+                               // position; U, {position, y index} pairs
     const TF2 *val;            // [pairs] factor entries, two per lane
     const uint4 *addr;         // [64 * nslice] addresses of the dependencies (ring slots or positions), eight per lane
 };
@@ -53,7 +54,8 @@ struct DevRas {
     const SdInfo *sd;
     DevSweep<TF> L, U;
     TF *lin;    // [L slices * 64] gathered inputs of the L sweep (ring only)
-    TF2 *lout;  // [U slices * 64] {L-sweep result (ring only), 1/u_ii} in U-sweep order (0 where never written)
+    TF2 *lout;  // [U slices * 64] ring: {L-sweep result, 1/u_ii} in U-sweep order (0 where never written);
+                // box vector: 1/u_ii per lane (dense, first half)
     TF *ring;   // [nsd][depth * width] when the ring is not in LDS
     int depth, width;
 };
@@ -85,17 +87,21 @@ struct Item {
 // the cache lines of the padding are never fetched; their results are
 // discarded.
 // With the box vector in LDS (VEC) the L sweep's inputs and results live there
-// (five loads per item) and the U sweep reads its record only for 1/u_ii and
-// its row's position (eight loads).
+// (five loads per item) and the U sweep reads 1/u_ii and its row's {position,
+// y index} instead of a record (seven loads).
 template <class TF, bool UPPER, bool VEC, class Rec>
 __device__ __forceinline__ void fetch_item(const DevSweep<TF> &S, const Rec *rec, int64_t g64, int64_t off, int w,
                                            int nvalid, Item<TF> &X) {
     const int lane = threadIdx.x % 64, ln = lane < nvalid ? lane : 0;
     const int64_t gpos = g64 + ln;
-    if constexpr (UPPER) {
+    if constexpr (UPPER && VEC) {  // {row position, y index} pairs and a dense 1/u_ii array
+        const int2 ri = reinterpret_cast<const int2 *>(S.lane_next)[gpos];
+        X.row = ri.x;
+        X.io = ri.y;
+        X.h.y = reinterpret_cast<const TF *>(rec)[gpos];
+    } else if constexpr (UPPER) {
         X.h = rec[gpos];
         X.io = S.lane_io[gpos];
-        if constexpr (VEC) X.row = S.lane_next[gpos];
     } else if constexpr (!VEC) {
         X.h.x = rec[gpos];
         X.io = S.lane_next[gpos];
@@ -400,7 +406,7 @@ struct OneLevel {
         o.Ulev = c.take<int32_t>(H.U.lev_slice.size()); o.Uw = c.take<int32_t>(H.U.sl_info.size());
         o.Uoff = c.take<int64_t>(H.U.sl_off.size()); o.Uslot = c.take<int32_t>(H.U.sl_slot.size());
         o.Uio = c.take<int32_t>(H.U.lane_io.size());
-        o.Unext = c.take<int32_t>(H.U.lane_next.size());
+        o.Unext = c.take<int32_t>(2 * H.U.lane_next.size());
         o.Uaddr = c.take<uint16_t>(H.U.addr.size());
         o.Uval = c.take<char>(H.U.val.size() * fs);
         o.lin = c.take<char>(H.L.lane_io.size() * fs);
@@ -423,7 +429,14 @@ struct OneLevel {
         CSD_HIP(up(Uoff, H.U.sl_off.data(), H.U.sl_off.size() * 8));
         CSD_HIP(up(Uslot, H.U.sl_slot.data(), H.U.sl_slot.size() * 4));
         CSD_HIP(up(Uio, H.U.lane_io.data(), H.U.lane_io.size() * 4));
-        CSD_HIP(up(Unext, H.U.lane_next.data(), H.U.lane_next.size() * 4));
+        if (!H.U.lane_next.empty()) {  // box vector: {position, y index} per U lane
+            std::vector<int32_t> ri(2 * H.U.lane_next.size());
+            for (size_t a = 0; a < H.U.lane_next.size(); ++a) {
+                ri[2 * a] = H.U.lane_next[a];
+                ri[2 * a + 1] = H.U.lane_io[a];
+            }
+            CSD_HIP(up(Unext, ri.data(), ri.size() * 4));
+        }
         CSD_HIP(up(Uaddr, H.U.addr.data(), H.U.addr.size() * 2));
         // U-sweep records {L result, 1/u_ii}: the L sweep writes the first
         // half; padding lanes read results that are never written, so start at 0
@@ -433,9 +446,11 @@ struct OneLevel {
             CSD_HIP(up(Lval, f.data(), f.size() * sizeof(T)));
             f.assign(H.U.val.begin(), H.U.val.end());
             CSD_HIP(up(Uval, f.data(), f.size() * sizeof(T)));
+            // ring: records {L result (written by the L sweep), 1/u_ii}; box vector: 1/u_ii alone
+            const size_t stride = H.box_vector ? 1 : 2;
             f.assign(2 * H.U.lane_diag.size(), T(0));
             for (size_t a = 0; a < H.U.lane_diag.size(); ++a)
-                f[2 * a + 1] = H.U.lane_diag[a] != 0.0 ? T(1.0 / H.U.lane_diag[a]) : T(0);
+                f[stride * a + stride - 1] = H.U.lane_diag[a] != 0.0 ? T(1.0 / H.U.lane_diag[a]) : T(0);
             CSD_HIP(up(lout, f.data(), f.size() * sizeof(T)));
             return CSDYN_OK;
         };
