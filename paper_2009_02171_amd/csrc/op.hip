@@ -250,22 +250,33 @@ __device__ __forceinline__ void op_march(const DevGeom &g, const RowCoef &rc, in
     int64_t own_step, ring_step = 0;
     source(tx + 1, ty + 1, own_src, own_step);
     if (has_ring) source(rhx, rhy, ring_src, ring_step);
-    // two layers in flight: (own, ring) is the next to go to LDS, (own2, ring2) the one after
-    V4<T> own, ring, own2, ring2;
-    auto fetch = [&](bool real) {
-        own2 = ld4(real ? own_src : zp);
-        ring2 = ld4(real ? ring_src : zp);
+    // Layer pipeline.  Layers k0 .. kend-1 go through LDS (kend includes the
+    // layer above the chunk, the radial neighbour of its last layer).  Two
+    // register sets hold the layers in flight: the set of iteration k holds
+    // layer k+2, goes to LDS at the start of the iteration and is reloaded
+    // with layer k+4 at its end.  The loop is unrolled by two so that the sets
+    // alternate without register copies (copying a register that a load is
+    // still writing waits for that load).  The edge-face values of layer k+1
+    // are requested at the end of iteration k, before layer k+4, so waiting
+    // for them leaves the layers in flight.
+    const int kend = min(k1 + 1, nr);
+    struct Lay {
+        V4<T> o, r;  // own cell, border cell
+    };
+    struct Edge {
+        V4<T> a, b;  // averaged Laplacian fluxes on the xi / eta edge face
+        T da, db;    // divergence fluxes
+    };
+    auto fetch = [&](Lay &L, bool real) {
+        L.o = ld4(real ? own_src : zp);
+        L.r = ld4(real ? ring_src : zp);
         own_src += own_step;
         ring_src += ring_step;
     };
-    auto put = [&](int b) {
-        for (int c = 0; c < 4; ++c) lds[b][c][own_h] = own.c[c];
-        if (has_ring)
-            for (int c = 0; c < 4; ++c) lds[b][c][ring_h] = ring.c[c];
-    };
-    auto shift = [&]() {
-        own = own2;
-        ring = ring2;
+    auto put = [&](int b, const Lay &L) {
+        for (int c = 0; c < 4; ++c) lds[b][c][own_h] = L.o.c[c];
+        // threads without a border cell write their own value again
+        for (int c = 0; c < 4; ++c) lds[b][c][has_ring ? ring_h : own_h] = has_ring ? L.r.c[c] : L.o.c[c];
     };
     // panel-edge faces (edge tiles only): at most one xi edge (slot A) and one
     // eta edge (slot B) per column, each the face's 4 averaged Laplacian fluxes
@@ -276,47 +287,52 @@ __device__ __forceinline__ void op_march(const DevGeom &g, const RowCoef &rc, in
         if (sE || sW) { slA = SF + 8 * ghost_ix(n, nr, p, sE ? 1 : 0, k0, jc); stA = 8 * int64_t(n); }
         if (sN || sS) { slB = SF + 8 * ghost_ix(n, nr, p, sN ? 3 : 2, k0, ic); stB = 8 * int64_t(n); }
     }
+    auto fetch_edge = [&](Edge &E, bool real) {
+        const T *pa = real ? slA : zp, *pb = real ? slB : zp;
+        E.a = ld4(pa); E.da = pa[4];
+        E.b = ld4(pb); E.db = pb[4];
+        slA += stA; slB += stB;
+    };
     const T *xcol = x + 4 * cell_ix(n, nr, p, ic, jc, 0);
     T *ycol = y + 4 * cell_ix(n, nr, p, ic, jc, k0);
     T *sink = reinterpret_cast<T *>(g.sink) + 4 * threadIdx.x;
 
-    // prologue: per-layer factors and layers k0, k0+1 into LDS, k0+2 and k0+3 in flight
-    for (int t = threadIdx.x; t < (k1 - k0) * 8; t += NT) layf[t >> 3][t & 7] = T(g.lay[8 * k0 + t]);
-    fetch(true);
-    shift();
-    put(0);
-    fetch(k0 + 1 < k1);
-    shift();
-    put(1);
-    fetch(k0 + 2 < k1);
-    shift();
-    fetch(k0 + 3 < k1);
+    // prologue: every load first (layers k0 .. k0+3, the layer below, the
+    // per-layer factors, the first edge-face values), then the LDS writes
+    constexpr int NLF = (kMaxChunk * 8 + NT - 1) / NT;
+    const int nlf = (k1 - k0) * 8;
+    Lay A0, A1, S0, S1;
+    Edge E0{};
+    fetch(A0, true);
+    fetch(A1, k0 + 1 < kend);
+    fetch(S0, k0 + 2 < kend);
+    fetch(S1, k0 + 3 < kend);
+    const V4<T> xm_raw = ld4(k0 > 0 ? xcol + 4 * (k0 - 1) * kstride : zp);
+    T lf[NLF];
+#pragma unroll
+    for (int q = 0; q < NLF; ++q) lf[q] = T(g.lay[8 * k0 + min(int(threadIdx.x) + q * NT, nlf - 1)]);
+    if (EDGE) fetch_edge(E0, true);
+    put(0, A0);
+    put(1, A1);
+#pragma unroll
+    for (int q = 0; q < NLF; ++q) {
+        const int t = threadIdx.x + q * NT;
+        if (t < nlf) layf[t >> 3][t & 7] = lf[q];
+    }
     lds_barrier();
     V4<T> xc, xm;
     for (int c = 0; c < 4; ++c) xc.c[c] = lds[0][c][own_h];
-    if (k0 > 0) xm = ld4(xcol + 4 * (k0 - 1) * kstride);
-    else xm = wall_ghost(xc, rc.kind, m.nv, T(g.wq2_bot));
+    xm = k0 > 0 ? xm_raw : wall_ghost(xc, rc.kind, m.nv, T(g.wq2_bot));
 
-    for (int k = k0; k < k1; ++k) {
+    auto step = [&](int k, Lay &S) {
         const int b = (k - k0) % 3;
-        if (k + 2 < k1) put((b + 2) % 3);  // buffer of layer k-1, free since the last barrier
-        shift();
-        V4<T> la, lb;
-        T da = 0, db = 0;
-        if (EDGE) {
-            la = ld4(slA); da = slA[4];
-            lb = ld4(slB); db = slB[4];
-            slA += stA; slB += stB;
-        }
-        const bool tail = k + 1 == k1 && k + 1 < nr;
-        const V4<T> xg = ld4(tail ? xcol + 4 * (k + 1) * kstride : zp);
-        __builtin_amdgcn_sched_barrier(0);  // the prefetch goes after the loads this layer uses
-        fetch(k + 4 < k1);
-        __builtin_amdgcn_sched_barrier(0);
+        if (k + 2 < kend) put((b + 2) % 3, S);  // buffer of layer k-1, free since the last barrier
         const int b1 = (b + 1) % 3;
         V4<T> xp;
-        for (int c = 0; c < 4; ++c) xp.c[c] = k + 1 < k1 ? lds[b1][c][own_h] : xg.c[c];
+        for (int c = 0; c < 4; ++c) xp.c[c] = lds[b1][c][own_h];
         if (k + 1 == nr) xp = wall_ghost(xc, rc.kind, m.nv, T(g.wq2_top));
+        const V4<T> la = E0.a, lb = E0.b;
+        const T da = EDGE ? E0.da : T(0), db = EDGE ? E0.db : T(0);
         const T *L = layf[k - k0];
         const T irk2 = L[1], rm2 = L[2], rp2 = L[3], irad = L[4], hrad = L[5], ir = L[6];
         auto V = [&](int c, int di, int dj) -> T { return lds[b][c][own_h + dj * HX + di]; };
@@ -358,11 +374,23 @@ __device__ __forceinline__ void op_march(const DevGeom &g, const RowCoef &rc, in
         out.c[1] = xc.c[1] - clap * lap[1] + ccor * xc.c[0];
         out.c[2] = xc.c[2] - clap * lap[2];
         out.c[3] = div - cdt * lap[3];
+        // requests: the next layer's edge-face values (their registers are
+        // free now), then layer k+4 into the set just written to LDS
+        __builtin_amdgcn_sched_barrier(0);
+        if (EDGE) fetch_edge(E0, k + 1 < k1);
+        fetch(S, k + 4 < kend);
+        __builtin_amdgcn_sched_barrier(0);
         st4(act ? ycol : sink, out);
         ycol += 4 * kstride;
         xm = xc;
         xc = xp;
         lds_barrier();  // layer k+2 visible; every read of buffer b done
+    };
+    for (int k = k0;;) {
+        step(k, S0);
+        if (++k == k1) break;
+        step(k, S1);
+        if (++k == k1) break;
     }
 }
 
