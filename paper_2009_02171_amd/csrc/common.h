@@ -103,7 +103,7 @@ struct DevGeom {
     int *fc;              // [6][4][n][4]  q, e, t, pad
     double *vol;          // [6][nr][n][n] cell volumes (for the Neumann projection)
     double *G;            // [6][4][nr][n][4] ghost values
-    double *SF;           // [6][4][nr][n][8] averaged edge fluxes (4 Laplacian, 1 divergence)
+    double *SF;           // averaged edge fluxes: [6][4][nr][n][4] Laplacian, then [6][4][nr][n padded to 4] divergence
 };
 
 size_t devgeom_bytes(int n, int nr);

@@ -58,6 +58,13 @@ __device__ __forceinline__ int64_t ghost_ix(int n, int nr, int p, int e, int k, 
     return ((int64_t(p * 4 + e) * nr + k) * n + t);
 }
 
+// Edge-flux buffer: the 4 averaged Laplacian fluxes of face (p, e, k, t) at
+// 4 * ghost_ix, then the divergence fluxes, their tangential index padded to
+// a multiple of 4 so that four neighbouring faces are one aligned load.
+__device__ __forceinline__ int64_t fdiv_ix(int n, int nr, int p, int e, int k, int t) {
+    return int64_t(24) * nr * n * 4 + (int64_t(p * 4 + e) * nr + k) * ((n + 3) & ~3) + t;
+}
+
 // Value at an extended position of panel X (one cell beyond an edge: the
 // ghost; both beyond: the cube-corner rule f(-1,0) + f(0,-1) - f(0,0)).
 template <class T>
@@ -143,8 +150,9 @@ __global__ void k_edgeflux(DevGeom g, const T *__restrict__ x, const T *__restri
     one_sided(g, x, G, p, e, t, k, oa);
     const int a = pe * n + t;
     one_sided(g, x, G, g.fc[4 * a], g.fc[4 * a + 1], g.fc[4 * a + 2], k, ob);
-    T *o = SF + 8 * ghost_ix(n, nr, p, e, k, t);
-    for (int c = 0; c < 5; ++c) o[c] = T(0.5) * (oa[c] - ob[c]);
+    T *o = SF + 4 * ghost_ix(n, nr, p, e, k, t);
+    for (int c = 0; c < 4; ++c) o[c] = T(0.5) * (oa[c] - ob[c]);
+    SF[fdiv_ix(n, nr, p, e, k, t)] = T(0.5) * (oa[4] - ob[4]);
 }
 
 struct RowCoef {
@@ -178,7 +186,9 @@ __device__ __forceinline__ V4<T> wall_ghost(const V4<T> &xin, int kind, const T 
 // in registers; one barrier per layer, which orders LDS only so that the global
 // loads stay in flight.  Every iteration issues the same loads in the same
 // order (cells outside the panel read a zero page), so the compiler's
-// in-order memory counters wait only for what a layer uses.
+// in-order memory counters wait only for what a layer uses.  In tiles on a
+// panel edge the averaged edge-face fluxes travel with the layers through LDS,
+// requested by threads that have no border cell, so they hold no registers.
 constexpr int kMaxChunk = 64;  // radial layers per workgroup
 
 // Workgroup barrier that orders LDS only (__syncthreads would also wait for
@@ -195,12 +205,24 @@ struct Column {  // r-independent metric of one column
     T tW[3], tE[3], tS[3], tN[3], nv[3];
 };
 
+// LDS of one stencil workgroup: three halo layers [3][4][HC] (component-major),
+// then for each of the three buffers the records of the tile's panel-edge
+// faces: NF faces x 4 Laplacian fluxes, then NF divergence fluxes.  Face
+// positions are fixed: W edge [0, TY), E edge [TY, 2TY), S edge
+// [2TY, 2TY+TX), N edge [2TY+TX, NF).  Last, a slot per thread where
+// threads without an extra record write it (never read).
+template <int TX, int TY>
+struct OpLds {
+    static constexpr int HC = (TX + 2) * (TY + 2), NF = 2 * TY + 2 * TX, FA = 5 * NF;
+    static constexpr int HALO = 3 * 4 * HC, DUMMY = HALO + 3 * FA, SIZE = DUMMY + 4 * TX * TY;
+};
+
 template <class T, int TX, int TY, bool EDGE>
 __device__ __forceinline__ void op_march(const DevGeom &g, const RowCoef &rc, int p, int bx, int by, int k0, int k1,
                                          const T *__restrict__ x, const T *__restrict__ G,
-                                         const T *__restrict__ SF, T *__restrict__ y, T (*lds)[4][(TX + 2) * (TY + 2)],
-                                         T (*layf)[8]) {
-    constexpr int NT = TX * TY, HX = TX + 2, HY = TY + 2, HC = HX * HY, NRING = HC - NT;
+                                         const T *__restrict__ SF, T *__restrict__ y, T *lds, T (*layf)[8]) {
+    using LL = OpLds<TX, TY>;
+    constexpr int NT = TX * TY, HX = TX + 2, HY = TY + 2, HC = LL::HC, NRING = HC - NT, NF = LL::NF, FA = LL::FA;
     static_assert(NRING <= NT, "one border cell per thread");
     const int n = g.n, nr = g.nr;
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
@@ -228,7 +250,11 @@ __device__ __forceinline__ void op_march(const DevGeom &g, const RowCoef &rc, in
     const T ih = T(1.0 / g.hs), i4h = T(0.25 / g.hs);
     const T clap = T(rc.c_lap), ccor = T(rc.c_cor), cdt = T(rc.dt);
 
-    // halo sources: each thread owns its cell and at most one border-ring cell
+    // Every thread loads its own cell each layer and one more 4-value record:
+    // a cell of the halo's border ring (threads r < NRING), else in edge
+    // tiles a panel-edge face record: one request per face (its Laplacian
+    // fluxes), then one per four faces (their divergence fluxes), edges in the
+    // order W, E, S, N.  The records travel with the layer into LDS.
     auto source = [&](int hx, int hy, const T *&src, int64_t &step) {
         const int ii = bx * TX + hx - 1, jj = by * TY + hy - 1;
         const bool iin = ii >= 0 && ii < n, jin = jj >= 0 && jj < n;
@@ -239,70 +265,86 @@ __device__ __forceinline__ void op_march(const DevGeom &g, const RowCoef &rc, in
         else if (iin && (jj == -1 || jj == n)) { src = G + 4 * ghost_ix(n, nr, p, jj < 0 ? 2 : 3, k0, ii); step = 4 * n; }
     };
     const int r = threadIdx.x;
-    int rhx = 0, rhy = 0;
-    if (r < HX) { rhx = r; rhy = 0; }
-    else if (r < 2 * HX) { rhx = r - HX; rhy = HY - 1; }
-    else if (r < 2 * HX + HY - 2) { rhx = 0; rhy = 1 + r - 2 * HX; }
-    else { rhx = HX - 1; rhy = 1 + r - 2 * HX - (HY - 2); }
-    const bool has_ring = r < NRING;
-    const int own_h = (ty + 1) * HX + tx + 1, ring_h = rhy * HX + rhx;
-    const T *own_src, *ring_src = zp;
-    int64_t own_step, ring_step = 0;
+    const int own_h = (ty + 1) * HX + tx + 1;
+    const T *own_src, *xsrc = zp;
+    int64_t own_step, xstep = 0;
     source(tx + 1, ty + 1, own_src, own_step);
-    if (has_ring) source(rhx, rhy, ring_src, ring_step);
+    // the extra record goes to lds[xoff + b * xbuf + c * xcomp] (buffer b)
+    int xoff = LL::DUMMY + 4 * r, xbuf = 0, xcomp = 1;
+    if (r < NRING) {
+        int rhx, rhy;
+        if (r < HX) { rhx = r; rhy = 0; }
+        else if (r < 2 * HX) { rhx = r - HX; rhy = HY - 1; }
+        else if (r < 2 * HX + HY - 2) { rhx = 0; rhy = 1 + r - 2 * HX; }
+        else { rhx = HX - 1; rhy = 1 + r - 2 * HX - (HY - 2); }
+        source(rhx, rhy, xsrc, xstep);
+        xoff = rhy * HX + rhx;
+        xbuf = 4 * HC;
+        xcomp = HC;
+    } else if (EDGE) {
+        const bool eW = bx == 0, eE = (bx + 1) * TX >= n, eS = by == 0, eN = (by + 1) * TY >= n;
+        const int cA = min(TY, n - by * TY), cB = min(TX, n - bx * TX);
+        const int cnt[4] = {eW ? cA : 0, eE ? cA : 0, eS ? cB : 0, eN ? cB : 0};
+        const int pos[4] = {0, TY, 2 * TY, 2 * TY + TX};
+        const int q = r - NRING, nlap = cnt[0] + cnt[1] + cnt[2] + cnt[3];
+        int lap_before = 0, div_before = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int t0 = e < 2 ? by * TY : bx * TX;
+            const int nd = (cnt[e] + 3) / 4;
+            const int ql = q - lap_before;  // Laplacian fluxes of face t0 + ql
+            if (ql >= 0 && ql < cnt[e]) {
+                xsrc = SF + 4 * ghost_ix(n, nr, p, e, k0, t0 + ql);
+                xstep = 4 * int64_t(n);
+                xoff = LL::HALO + 4 * (pos[e] + ql);
+                xbuf = FA;
+                xcomp = 1;
+            }
+            const int qd = q - nlap - div_before;  // divergence fluxes of faces t0 + 4 qd .. + 3
+            if (qd >= 0 && qd < nd) {
+                xsrc = SF + fdiv_ix(n, nr, p, e, k0, t0 + 4 * qd);
+                xstep = (n + 3) & ~3;
+                xoff = LL::HALO + 4 * NF + pos[e] + 4 * qd;
+                xbuf = FA;
+                xcomp = 1;
+            }
+            lap_before += cnt[e];
+            div_before += nd;
+        }
+    }
     // Layer pipeline.  Layers k0 .. kend-1 go through LDS (kend includes the
     // layer above the chunk, the radial neighbour of its last layer).  Two
     // register sets hold the layers in flight: the set of iteration k holds
     // layer k+2, goes to LDS at the start of the iteration and is reloaded
     // with layer k+4 at its end.  The loop is unrolled by two so that the sets
     // alternate without register copies (copying a register that a load is
-    // still writing waits for that load).  The edge-face values of layer k+1
-    // are requested at the end of iteration k, before layer k+4, so waiting
-    // for them leaves the layers in flight.
+    // still writing waits for that load); an odd chunk runs one more
+    // iteration whose output is discarded, so the loop has a single exit.
     const int kend = min(k1 + 1, nr);
     struct Lay {
-        V4<T> o, r;  // own cell, border cell
-    };
-    struct Edge {
-        V4<T> a, b;  // averaged Laplacian fluxes on the xi / eta edge face
-        T da, db;    // divergence fluxes
+        V4<T> o, r;  // own cell, extra record
     };
     auto fetch = [&](Lay &L, bool real) {
         L.o = ld4(real ? own_src : zp);
-        L.r = ld4(real ? ring_src : zp);
+        L.r = ld4(real ? xsrc : zp);
         own_src += own_step;
-        ring_src += ring_step;
+        xsrc += xstep;
     };
     auto put = [&](int b, const Lay &L) {
-        for (int c = 0; c < 4; ++c) lds[b][c][own_h] = L.o.c[c];
-        // threads without a border cell write their own value again
-        for (int c = 0; c < 4; ++c) lds[b][c][has_ring ? ring_h : own_h] = has_ring ? L.r.c[c] : L.o.c[c];
-    };
-    // panel-edge faces (edge tiles only): at most one xi edge (slot A) and one
-    // eta edge (slot B) per column, each the face's 4 averaged Laplacian fluxes
-    // and its divergence flux
-    const T *slA = zp, *slB = zp;
-    int64_t stA = 0, stB = 0;
-    if (EDGE) {
-        if (sE || sW) { slA = SF + 8 * ghost_ix(n, nr, p, sE ? 1 : 0, k0, jc); stA = 8 * int64_t(n); }
-        if (sN || sS) { slB = SF + 8 * ghost_ix(n, nr, p, sN ? 3 : 2, k0, ic); stB = 8 * int64_t(n); }
-    }
-    auto fetch_edge = [&](Edge &E, bool real) {
-        const T *pa = real ? slA : zp, *pb = real ? slB : zp;
-        E.a = ld4(pa); E.da = pa[4];
-        E.b = ld4(pb); E.db = pb[4];
-        slA += stA; slB += stB;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) lds[b * 4 * HC + c * HC + own_h] = L.o.c[c];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) lds[xoff + b * xbuf + c * xcomp] = L.r.c[c];
     };
     const T *xcol = x + 4 * cell_ix(n, nr, p, ic, jc, 0);
     T *ycol = y + 4 * cell_ix(n, nr, p, ic, jc, k0);
     T *sink = reinterpret_cast<T *>(g.sink) + 4 * threadIdx.x;
 
     // prologue: every load first (layers k0 .. k0+3, the layer below, the
-    // per-layer factors, the first edge-face values), then the LDS writes
+    // per-layer factors), then the LDS writes
     constexpr int NLF = (kMaxChunk * 8 + NT - 1) / NT;
     const int nlf = (k1 - k0) * 8;
     Lay A0, A1, S0, S1;
-    Edge E0{};
     fetch(A0, true);
     fetch(A1, k0 + 1 < kend);
     fetch(S0, k0 + 2 < kend);
@@ -311,7 +353,6 @@ __device__ __forceinline__ void op_march(const DevGeom &g, const RowCoef &rc, in
     T lf[NLF];
 #pragma unroll
     for (int q = 0; q < NLF; ++q) lf[q] = T(g.lay[8 * k0 + min(int(threadIdx.x) + q * NT, nlf - 1)]);
-    if (EDGE) fetch_edge(E0, true);
     put(0, A0);
     put(1, A1);
 #pragma unroll
@@ -321,21 +362,23 @@ __device__ __forceinline__ void op_march(const DevGeom &g, const RowCoef &rc, in
     }
     lds_barrier();
     V4<T> xc, xm;
-    for (int c = 0; c < 4; ++c) xc.c[c] = lds[0][c][own_h];
+    for (int c = 0; c < 4; ++c) xc.c[c] = lds[c * HC + own_h];
     xm = k0 > 0 ? xm_raw : wall_ghost(xc, rc.kind, m.nv, T(g.wq2_bot));
+    // this column's panel-edge faces (edge tiles): xi edge A, eta edge B
+    const int fA = sE ? TY + ty : ty, fB = sN ? 2 * TY + TX + tx : 2 * TY + tx;
 
     auto step = [&](int k, Lay &S) {
         const int b = (k - k0) % 3;
-        if (k + 2 < kend) put((b + 2) % 3, S);  // buffer of layer k-1, free since the last barrier
+        put((b + 2) % 3, S);  // layer k+2 (past kend: unused) into the buffer of layer k-1, free since the last barrier
+        const T *hb = lds + b * 4 * HC;
         const int b1 = (b + 1) % 3;
         V4<T> xp;
-        for (int c = 0; c < 4; ++c) xp.c[c] = lds[b1][c][own_h];
+        for (int c = 0; c < 4; ++c) xp.c[c] = lds[b1 * 4 * HC + c * HC + own_h];
         if (k + 1 == nr) xp = wall_ghost(xc, rc.kind, m.nv, T(g.wq2_top));
-        const V4<T> la = E0.a, lb = E0.b;
-        const T da = EDGE ? E0.da : T(0), db = EDGE ? E0.db : T(0);
+        const T *fb = lds + LL::HALO + b * FA;
         const T *L = layf[k - k0];
         const T irk2 = L[1], rm2 = L[2], rp2 = L[3], irad = L[4], hrad = L[5], ir = L[6];
-        auto V = [&](int c, int di, int dj) -> T { return lds[b][c][own_h + dj * HX + di]; };
+        auto V = [&](int c, int di, int dj) -> T { return hb[c * HC + own_h + dj * HX + di]; };
         const T inv_lat = irk2 * m.isc;
         V4<T> out;
         T lap[4];
@@ -346,10 +389,11 @@ __device__ __forceinline__ void op_march(const DevGeom &g, const RowCoef &rc, in
             T oN = m.a22N * (V(c, 0, 1) - v00) * ih + m.a12N * (V(c, 1, 0) + V(c, 1, 1) - V(c, -1, 0) - V(c, -1, 1)) * i4h;
             T oS = -(m.a22S * (v00 - V(c, 0, -1)) * ih + m.a12S * (V(c, 1, -1) + V(c, 1, 0) - V(c, -1, -1) - V(c, -1, 0)) * i4h);
             if (EDGE) {  // conservative averaged fluxes on panel-edge faces (selects)
-                oE = sE ? la.c[c] : oE;
-                oW = sW ? la.c[c] : oW;
-                oN = sN ? lb.c[c] : oN;
-                oS = sS ? lb.c[c] : oS;
+                const T la = fb[4 * fA + c], lb = fb[4 * fB + c];
+                oE = sE ? la : oE;
+                oW = sW ? la : oW;
+                oN = sN ? lb : oN;
+                oS = sS ? lb : oS;
             }
             lap[c] = (oE + oW + oN + oS) * inv_lat + (rp2 * (xp.c[c] - v00) - rm2 * (v00 - xm.c[c])) * irad;
         }
@@ -364,6 +408,7 @@ __device__ __forceinline__ void op_march(const DevGeom &g, const RowCoef &rc, in
         }
         dE *= T(0.5); dW *= T(-0.5); dN *= T(0.5); dS *= T(-0.5);
         if (EDGE) {
+            const T da = fb[4 * NF + fA], db = fb[4 * NF + fB];
             dE = sE ? da : dE;
             dW = sW ? da : dW;
             dN = sN ? db : dN;
@@ -374,33 +419,29 @@ __device__ __forceinline__ void op_march(const DevGeom &g, const RowCoef &rc, in
         out.c[1] = xc.c[1] - clap * lap[1] + ccor * xc.c[0];
         out.c[2] = xc.c[2] - clap * lap[2];
         out.c[3] = div - cdt * lap[3];
-        // requests: the next layer's edge-face values (their registers are
-        // free now), then layer k+4 into the set just written to LDS
-        __builtin_amdgcn_sched_barrier(0);
-        if (EDGE) fetch_edge(E0, k + 1 < k1);
+        __builtin_amdgcn_sched_barrier(0);  // layer k+4 into the set just written to LDS
         fetch(S, k + 4 < kend);
         __builtin_amdgcn_sched_barrier(0);
-        st4(act ? ycol : sink, out);
+        st4(act && k < k1 ? ycol : sink, out);
         ycol += 4 * kstride;
         xm = xc;
         xc = xp;
         lds_barrier();  // layer k+2 visible; every read of buffer b done
     };
-    for (int k = k0;;) {
+    for (int k = k0; k < k1; k += 2) {
         step(k, S0);
-        if (++k == k1) break;
-        step(k, S1);
-        if (++k == k1) break;
+        step(k + 1, S1);
     }
 }
 
+// At least two wavefronts per SIMD (FP64: 256 registers, the whole layer
+// pipeline in registers without spilling).
 template <class T, int TX, int TY>
-__global__ __launch_bounds__(TX *TY) void k_op_main(DevGeom g, RowCoef rc, int kchunk, int nkc,
+__global__ __launch_bounds__(TX *TY, 2) void k_op_main(DevGeom g, RowCoef rc, int kchunk, int nkc,
                                                     const T *__restrict__ x, const T *__restrict__ G,
                                                     const T *__restrict__ SF, T *__restrict__ y) {
-    constexpr int HC = (TX + 2) * (TY + 2);
-    __shared__ T lds[3][4][HC];
-    __shared__ T layf[kMaxChunk][8];
+    __shared__ T lds[OpLds<TX, TY>::SIZE];
+    __shared__ T layf[kMaxChunk + 1][8];
     const int n = g.n, nr = g.nr;
     const int tilesx = (n + TX - 1) / TX, tiles = tilesx * ((n + TY - 1) / TY);
     // XCD-aware order: workgroups are dealt round-robin over the 8 XCDs; each
@@ -437,14 +478,25 @@ static int32_t launch_all(const csdyn_opctx *ctx, const T *x, T *y, T *G, T *SF,
     ProfScope ps(sizeof(T) == 8 ? "op_main" : "op_main_f32", 6 * int64_t(n) * n * nr,
                  6.0 * n * n * nr * 8 * sizeof(T), s);  // x read once, y written once
     const int tile = ctx->tile ? ctx->tile : 4;
+    int32_t status = CSDYN_OK;
     auto go = [&](auto tx_c, auto ty_c) {
         constexpr int TX = decltype(tx_c)::value, TY = decltype(ty_c)::value;
         const int tiles = ((n + TX - 1) / TX) * ((n + TY - 1) / TY);
-        const int target = 2048 * 256 / (TX * TY);  // workgroups over the k-chunks
+        const int target = 1024 * 256 / (TX * TY);  // workgroups over the k-chunks
         int nkc = std::max(1, std::min(nr, (target + 6 * tiles - 1) / (6 * tiles)));
         nkc = std::max(nkc, (nr + kMaxChunk - 1) / kMaxChunk);
-        const int kchunk = (nr + nkc - 1) / nkc;
+        int kchunk = (nr + nkc - 1) / nkc;
+        kchunk = std::min(kMaxChunk, kchunk + (kchunk & 1));  // even: no discarded iteration
         nkc = (nr + kchunk - 1) / kchunk;
+        // every panel-edge face record of a tile needs a thread outside the border ring
+        constexpr int NT = TX * TY, NRING = (TX + 2) * (TY + 2) - NT;
+        const int fx = std::min(TX, n), fy = std::min(TY, n);
+        const int need = (n <= TX ? 2 : 1) * (fy + (fy + 3) / 4) + (n <= TY ? 2 : 1) * (fx + (fx + 3) / 4);
+        if (need > NT - NRING) {
+            set_error("operator: tile %dx%d has too few threads for the edge faces of N=%d", TX, TY, n);
+            status = CSDYN_EINVAL;
+            return;
+        }
         hipLaunchKernelGGL((k_op_main<T, TX, TY>), dim3(tiles * 6 * nkc), dim3(TX * TY), 0, s, g, rc, kchunk, nkc,
                            x, (const T *)G, (const T *)SF, y);
     };
@@ -454,6 +506,7 @@ static int32_t launch_all(const csdyn_opctx *ctx, const T *x, T *y, T *G, T *SF,
     else if (tile == 3) go(integral_constant<int, 64>(), integral_constant<int, 4>());
     else if (tile == 4) go(integral_constant<int, 16>(), integral_constant<int, 8>());
     else go(integral_constant<int, 32>(), integral_constant<int, 4>());
+    if (status != CSDYN_OK) return status;
     CSD_HIP(hipGetLastError());
     return CSDYN_OK;
 }

@@ -75,11 +75,13 @@ def test_batched_rejects_two_level():
 
 
 @pytest.mark.parametrize("tile", [1, 2, 3, 4, 5])
-def test_operator_tiles_agree(tile):
+@pytest.mark.parametrize("kind", [0, 1])
+def test_operator_tiles_agree(tile, kind):
+    # tiles that hold one, two or four panel edges, odd layer counts
     import torch
     from paper_2009_02171_amd import csdyn
-    for n, nr in ((40, 6), (24, 5), (17, 3)):
-        op = csdyn.Operator(n, nr, kind=1, dt=1e-2)
+    for n, nr in ((40, 6), (24, 5), (17, 3), (5, 3), (8, 9)):
+        op = csdyn.Operator(n, nr, kind=kind, dt=1e-2)
         x = torch.from_numpy(inputs.random_field((6, nr, n, n, 4), seed=n)).cuda()
         y0 = op.apply(x).clone()
         op.set_tile(tile)
