@@ -18,7 +18,10 @@ HIP events on its own stream (csdyn_profile_*), which gives their average
 durations and achieved algorithmic bandwidth.  Timing every launch costs
 about 14% of the step, so the per-kernel breakdown ("kernels") comes from
 one extra untimed step in which every launch is timed; the dominant kernel
-is the one with the largest total time there.
+is the one with the largest total time there.  The event pool is created
+before the clock starts and read after it stops.  The forms "*_two_streams"
+time the same steps with the two systems (independent of each other) solved
+at the same time, each from its own host thread on its own stream.
 
 The CPU baseline is the plain C oracle (single thread), timed on a bounded
 sample: the same two solves with the same solver and subdomain count at
@@ -30,6 +33,7 @@ import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -170,6 +174,30 @@ def main():
                 raise RuntimeError(f"{form} {name} solve did not converge: rc={rc} {st}")
             iters[form][name] = [st["iters"], st["inner_iters"], st["relres_true"]]
 
+    streams = {name: torch.cuda.Stream() for name in systems}  # default priority
+
+    def solve_on_stream(form, name, failures):
+        s = state[form][name]
+        try:
+            with torch.cuda.stream(streams[name]):
+                s["x"].zero_()
+                _, st, rc = s["sol"].solve(s["b"], s["x"], stream=streams[name])
+            if rc != 0 or not st["relres_true"] <= 1.0001e-8:
+                raise RuntimeError(f"{form} {name} solve did not converge: rc={rc} {st}")
+            iters[form][name] = [st["iters"], st["inner_iters"], st["relres_true"]]
+        except Exception as e:  # reported by the caller
+            failures.append(e)
+
+    def step_two_streams(form):
+        failures = []
+        threads = [threading.Thread(target=solve_on_stream, args=(form, name, failures)) for name in state[form]]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        if failures:
+            raise failures[0]
+
     for form in forms:
         for w in range(args.warmup):
             t0 = time.perf_counter()
@@ -186,14 +214,18 @@ def main():
     elapsed_all = time.perf_counter() - t0
     dom_kernel = max(prof_all.result.items(), key=lambda kv: kv[1]["ms"])[0][0]
     log(f"profiled plain_fp64 step: {elapsed_all:.3f} s, dominant kernel {dom_kernel}")
-    # the headline form: plain FP64; the dominant kernel and the operator timed with HIP events
+    # the headline form: plain FP64; the dominant kernel and the operator timed with HIP events.  The
+    # event pool is created before the clock starts and read after it stops (creating and destroying
+    # the events is host work that is not part of a step).
+    prof = csdyn.Profile(max_launches=16384, select=[dom_kernel, "op_main"], every=PROFILE_EVERY)
+    prof.__enter__()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    with csdyn.Profile(select=[dom_kernel, "op_main"], every=PROFILE_EVERY) as prof:
-        for k in range(args.steps):
-            step("plain_fp64")
-        torch.cuda.synchronize()
+    for k in range(args.steps):
+        step("plain_fp64")
+    torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    prof.__exit__(None, None, None)
     log(f"timed plain_fp64: {args.steps} steps in {elapsed:.3f} s, iters {iters['plain_fp64']}")
     # the mixed-precision form (FP32 inside the preconditioner, FP64 FGMRES)
     torch.cuda.synchronize()
@@ -203,6 +235,17 @@ def main():
     torch.cuda.synchronize()
     elapsed_mixed = time.perf_counter() - t0
     log(f"timed mixed_fp32_pc: {args.steps} steps in {elapsed_mixed:.3f} s, iters {iters['mixed_fp32_pc']}")
+    # both forms again with the two systems of a step solved at the same time, each from its own host
+    # thread on its own stream (the systems are independent; results are identical)
+    elapsed_two = {}
+    for form in forms:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            step_two_streams(form)
+        torch.cuda.synchronize()
+        elapsed_two[form] = time.perf_counter() - t0
+        log(f"timed {form} on two streams: {args.steps} steps in {elapsed_two[form]:.3f} s, iters {iters[form]}")
     err = {}
     for name in systems:
         xp, xm = state["plain_fp64"][name]["x"], state["mixed_fp32_pc"][name]["x"]
@@ -251,6 +294,10 @@ def main():
                               "iters": {k: {"outer": v[0], "inner": v[1], "relres": v[2]}
                                         for k, v in iters["mixed_fp32_pc"].items()},
                               "rel_err_vs_fp64_solution": err},
+            "plain_fp64_two_streams": {"solves_per_s": round(2 * args.steps / elapsed_two["plain_fp64"], 4),
+                                       "ms_per_step": round(elapsed_two["plain_fp64"] / args.steps * 1e3, 3)},
+            "mixed_fp32_pc_two_streams": {"solves_per_s": round(2 * args.steps / elapsed_two["mixed_fp32_pc"], 4),
+                                          "ms_per_step": round(elapsed_two["mixed_fp32_pc"] / args.steps * 1e3, 3)},
         },
         "roofline": {"kernel": f"{dom_name[0]}@{dom_name[1]}", "bound": "hbm", "achieved": round(dom_gbs, 1),
                      "timed_launches": dom["count"], "timed_every": PROFILE_EVERY,
