@@ -46,6 +46,7 @@ struct DevSweep {
                                // position; U, {position, y index} pairs
     const TF2 *val;            // [pairs] factor entries, two per lane
     const uint4 *addr;         // [64 * nslice] addresses of the dependencies (ring slots or positions), eight per lane
+    const int4 *meta;          // [nsd][meta bytes / 16] LDS metadata image of each subdomain's sweep
 };
 
 template <class TF>
@@ -57,6 +58,7 @@ struct DevRas {
     TF2 *lout;  // [U slices * 64] ring: {L-sweep result, 1/u_ii} in U-sweep order (0 where never written);
                 // box vector: 1/u_ii per lane (dense, first half)
     TF *ring;   // [nsd][depth * width] when the ring is not in LDS
+    const int32_t *gio;  // box vector: x index of each position, per subdomain from SdInfo::g0
     int depth, width;
 };
 
@@ -169,8 +171,8 @@ struct Meta {
 // sweep, to its U-sweep record; the U sweep writes the owned rows to y
 // (restricted scatter).
 template <class TV, class TF, bool UPPER, bool LDS, bool VEC, int NT, class Rec>
-__device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int sl0, int nlev, int nsl, TF *ring,
-                                      const Rec *rec, TF *lout, TV *y) {
+__device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int sl0, int64_t off0, int nlev, int nsl,
+                                      TF *ring, const Rec *rec, TF *lout, TV *y) {
     constexpr int K = SweepShape<TF, NT>::K;
     const int lane = threadIdx.x % 64, nw = NT / 64;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
@@ -183,7 +185,6 @@ __device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int 
         for (; passed < nlev; ++passed) level_barrier<LDS>();
         return;
     }
-    const int64_t off0 = S.sl_off[sl0];
     int fg = wv;  // next slice to request (past the end: re-reads the last slice)
     auto request = [&](Item<TF> (&grp)[K]) {
         __builtin_amdgcn_sched_barrier(0);
@@ -247,36 +248,14 @@ __device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int 
     __builtin_amdgcn_s_waitcnt(0);  // requests past the end
 }
 
-// LDS bytes of one sweep's slice metadata: per level 4, per slice 12.
-__host__ __device__ constexpr size_t meta_bytes_for(int nsl, int nlev) {
-    return ((size_t(nlev) + 1) * 4 + 15) / 16 * 16 + (size_t(nsl) * 12 + 15) / 16 * 16;
-}
 
-// Stage one subdomain's slice metadata of one sweep in LDS; returns its
-// first slice and sets nsl.  Ends with a workgroup barrier.
-template <class TF, int NT>
-__device__ __forceinline__ int stage_meta(const DevSweep<TF> &S, int lev0, int lev1, int meta_lev, int meta_sl,
-                                          unsigned char *base, Meta &M, int &nsl) {
+// Pointers into the LDS copy of one sweep's slice metadata (the layout of
+// meta_bytes_for and of the per-subdomain images).
+__device__ __forceinline__ void meta_pointers(unsigned char *base, int meta_lev, int meta_sl, Meta &M) {
     M.lev = reinterpret_cast<int32_t *>(base);
     M.off = reinterpret_cast<int32_t *>(base + ((size_t(meta_lev) + 1) * 4 + 15) / 16 * 16);
     M.wl = M.off + meta_sl;
     M.slot = M.wl + meta_sl;
-    const int sl0 = S.lev_slice[lev0];
-    const int nlev = lev1 - lev0;
-    nsl = S.lev_slice[lev1] - sl0;
-    for (int a = threadIdx.x; a <= nlev; a += NT) M.lev[a] = S.lev_slice[lev0 + a] - sl0;
-    __syncthreads();
-    for (int a = threadIdx.x; a < nlev; a += NT)  // level of each slice
-        for (int s = M.lev[a]; s < M.lev[a + 1]; ++s) M.wl[s] = a << 17;
-    __syncthreads();
-    const int64_t off0 = S.sl_off[sl0];
-    for (int s = threadIdx.x; s < nsl; s += NT) {
-        M.off[s] = int32_t(S.sl_off[sl0 + s] - off0);
-        M.wl[s] |= S.sl_info[sl0 + s];
-        M.slot[s] = S.sl_slot[sl0 + s];
-    }
-    __syncthreads();
-    return sl0;
 }
 
 // One workgroup per subdomain: gather x (coalesced over the L-sweep order),
@@ -295,40 +274,68 @@ __global__ __launch_bounds__(NT) void k_ras(DevRas<TF> R, int meta_lev, int meta
                    : R.ring + int64_t(blockIdx.x) * ring_n;
     if constexpr (!VEC)
         for (int a = threadIdx.x; a < ring_n; a += NT) ring[a] = TF(0);
+    // slice metadata: the L sweep's image to LDS now, the U sweep's (up to
+    // MU 16-byte pieces per thread) requested now and written after the L sweep
     Meta M;
-    int nsl;
-    int sl0 = stage_meta<TF, NT>(R.L, I.levL0, I.levL1, meta_lev, meta_sl, ras_smem, M, nsl);
+    meta_pointers(ras_smem, meta_lev, meta_sl, M);
+    using I4 = int __attribute__((ext_vector_type(4)));
+    const int n16 = int(meta_bytes_for(meta_sl, meta_lev) / 16);
+    I4 *md = reinterpret_cast<I4 *>(ras_smem);
     {
-        // eight rows per thread per round: the index loads, then the value
+        const I4 *img = reinterpret_cast<const I4 *>(R.L.meta) + size_t(blockIdx.x) * n16;
+        for (int a = threadIdx.x; a < n16; a += NT) md[a] = img[a];
+    }
+    constexpr int MU = 2;
+    const I4 *uimg = reinterpret_cast<const I4 *>(R.U.meta) + size_t(blockIdx.x) * n16;
+    const I4 up0 = uimg[min(int(threadIdx.x), n16 - 1)];
+    const I4 up1 = uimg[min(int(threadIdx.x) + NT, n16 - 1)];
+    if constexpr (VEC) {
+        // the box vector in L-sweep order: position a holds x[gio[a]];
+        // GU positions per thread per round, all index loads and then all
+        // value loads in flight together (one round for boxes of up to
+        // GU * NT rows)
+        constexpr int GU = 24;
+        const int nrows = I.nrows;
+        const int32_t *gi = R.gio + I.g0;
+        for (int a0 = 0; a0 < nrows; a0 += NT * GU) {
+            int32_t io[GU];
+            TV v[GU];
+#pragma unroll
+            for (int u = 0; u < GU; ++u) io[u] = gi[min(a0 + int(threadIdx.x) + u * NT, nrows - 1)];
+#pragma unroll
+            for (int u = 0; u < GU; ++u) v[u] = x[io[u]];
+#pragma unroll
+            for (int u = 0; u < GU; ++u) {
+                const int a = a0 + int(threadIdx.x) + u * NT;
+                if (a < nrows) ring[a] = TF(v[u]);
+            }
+        }
+    } else {
+        // eight lanes per thread per round: the index loads, then the value
         // loads, are in flight together
         constexpr int U = 8;
-        const int64_t p0 = int64_t(sl0) * 64, p1 = int64_t(sl0 + nsl) * 64;
+        const int64_t p0 = int64_t(I.slL0) * 64, p1 = int64_t(I.slL0 + I.nslL) * 64;
         for (int64_t p = p0 + threadIdx.x; p < p1; p += int64_t(NT) * U) {
-            int32_t io[U], pos[U];
+            int32_t io[U];
             TV v[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                io[u] = p + u * NT < p1 ? R.L.lane_io[p + u * NT] : -1;
-                if constexpr (VEC) pos[u] = p + u * NT < p1 ? R.L.lane_next[p + u * NT] : -1;
-            }
+            for (int u = 0; u < U; ++u) io[u] = p + u * NT < p1 ? R.L.lane_io[p + u * NT] : -1;
 #pragma unroll
             for (int u = 0; u < U; ++u) v[u] = io[u] >= 0 ? x[io[u]] : TV(0);
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if constexpr (VEC) {
-                    if (pos[u] >= 0) ring[pos[u]] = TF(v[u]);
-                } else if (p + u * NT < p1) {
-                    R.lin[p + u * NT] = TF(v[u]);
-                }
-            }
+            for (int u = 0; u < U; ++u)
+                if (p + u * NT < p1) R.lin[p + u * NT] = TF(v[u]);
         }
     }
     __syncthreads();
-    sweep<TV, TF, false, LDS, VEC, NT>(R.L, M, sl0, I.levL1 - I.levL0, nsl, ring, R.lin,
+    sweep<TV, TF, false, LDS, VEC, NT>(R.L, M, I.slL0, I.offL0, I.levL1 - I.levL0, I.nslL, ring, R.lin,
                                        reinterpret_cast<TF *>(R.lout), y);
     __syncthreads();  // L results visible; the U metadata replaces the L metadata
-    sl0 = stage_meta<TF, NT>(R.U, I.levU0, I.levU1, meta_lev, meta_sl, ras_smem, M, nsl);
-    sweep<TV, TF, true, LDS, VEC, NT>(R.U, M, sl0, I.levU1 - I.levU0, nsl, ring, R.lout, nullptr, y);
+    if (int(threadIdx.x) < n16) md[threadIdx.x] = up0;
+    if (int(threadIdx.x) + NT < n16) md[threadIdx.x + NT] = up1;
+    for (int a = threadIdx.x + MU * NT; a < n16; a += NT) md[a] = uimg[a];
+    __syncthreads();
+    sweep<TV, TF, true, LDS, VEC, NT>(R.U, M, I.slU0, I.offU0, I.levU1 - I.levU0, I.nslU, ring, R.lout, nullptr, y);
 }
 
 // restriction: mean of the 8 children; prolongation: copy to the children
@@ -390,6 +397,7 @@ struct OneLevel {
     int64_t *Uoff = nullptr;
     uint16_t *Uaddr = nullptr;
     void *Lval = nullptr, *Uval = nullptr, *lin = nullptr, *lout = nullptr, *ring = nullptr;
+    int32_t *gio = nullptr, *Lmeta = nullptr, *Umeta = nullptr;
 
     static void layout(Carver &c, const HostRas &H, int precision, OneLevel &o) {
         const size_t fs = precision ? sizeof(float) : sizeof(double);
@@ -412,6 +420,9 @@ struct OneLevel {
         o.lin = c.take<char>(H.L.lane_io.size() * fs);
         o.lout = c.take<char>(2 * H.U.lane_io.size() * fs);
         o.ring = c.take<char>(size_t(H.nsd) * H.ring_depth * H.ring_width * fs);
+        o.gio = c.take<int32_t>(H.gio.size());
+        o.Lmeta = c.take<int32_t>(H.L.meta.size());
+        o.Umeta = c.take<int32_t>(H.U.meta.size());
     }
 
     int32_t upload(const HostRas &H) const {
@@ -438,6 +449,9 @@ struct OneLevel {
             CSD_HIP(up(Unext, ri.data(), ri.size() * 4));
         }
         CSD_HIP(up(Uaddr, H.U.addr.data(), H.U.addr.size() * 2));
+        CSD_HIP(up(gio, H.gio.data(), H.gio.size() * 4));
+        CSD_HIP(up(Lmeta, H.L.meta.data(), H.L.meta.size() * 4));
+        CSD_HIP(up(Umeta, H.U.meta.data(), H.U.meta.size() * 4));
         // U-sweep records {L result, 1/u_ii}: the L sweep writes the first
         // half; padding lanes read results that are never written, so start at 0
         auto upload_as = [&](auto zero) -> int32_t {
@@ -462,11 +476,12 @@ struct OneLevel {
         DevRas<TF> R;
         R.sd = sd;
         using TF2 = typename Pair<TF>::type;
-        R.L = DevSweep<TF>{Llev, Lw, Loff, Lslot, Lio, Lnext, (const TF2 *)Lval, (const uint4 *)Laddr};
-        R.U = DevSweep<TF>{Ulev, Uw, Uoff, Uslot, Uio, Unext, (const TF2 *)Uval, (const uint4 *)Uaddr};
+        R.L = DevSweep<TF>{Llev, Lw, Loff, Lslot, Lio, Lnext, (const TF2 *)Lval, (const uint4 *)Laddr, (const int4 *)Lmeta};
+        R.U = DevSweep<TF>{Ulev, Uw, Uoff, Uslot, Uio, Unext, (const TF2 *)Uval, (const uint4 *)Uaddr, (const int4 *)Umeta};
         R.lin = (TF *)lin;
         R.lout = (TF2 *)lout;
         R.ring = (TF *)ring;
+        R.gio = gio;
         R.depth = vec ? 1 : depth;
         R.width = vec ? box_rows : width;
         return R;

@@ -552,6 +552,20 @@ int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], 
         make_schedule(L, false, depth, H.ring_width, nullptr, SL);
         make_schedule(L, true, depth, H.ring_width, H.box_vector ? &SL.slot : nullptr, SU);
         const int64_t base_u = int64_t(H.U.sl_info.size());
+        const int64_t nrow = int64_t(L.rp.size()) - 1;
+        I.nrows = int32_t(nrow);
+        I.g0 = int64_t(H.gio.size());
+        if (H.box_vector) {  // position SL.slot[r] of the box vector holds row r
+            H.gio.resize(size_t(I.g0 + nrow), -1);
+            for (int64_t r = 0; r < nrow; ++r) {
+                const int64_t a = SL.slot[r];
+                if (a < 0 || a >= nrow || H.gio[size_t(I.g0 + a)] >= 0) {
+                    set_error("ras: box-vector positions of subdomain %d are not a permutation", s);
+                    return CSDYN_EINVAL;
+                }
+                H.gio[size_t(I.g0 + a)] = int32_t(4 * int64_t(L.gcell[r / 4]) + r % 4);
+            }
+        }
         if (int32_t e = pack_sweep(L, true, SU, nullptr, 0, H.box_vector, H.U, I.levU0, I.levU1)) return e;
         if (int32_t e = pack_sweep(L, false, SL, &SU, base_u, H.box_vector, H.L, I.levL0, I.levL1)) return e;
         H.max_slices = std::max(H.max_slices, std::max(SL.lev_first.back(), SU.lev_first.back()));
@@ -568,6 +582,30 @@ int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], 
     }
     H.L.lev_slice.push_back(int32_t(H.L.sl_info.size()));
     H.U.lev_slice.push_back(int32_t(H.U.sl_info.size()));
+    // per-subdomain metadata images, laid out as the sweep kernel's LDS copy
+    H.meta_words = int(meta_bytes_for(H.max_slices, H.max_levels) / 4);
+    const int offw = int(((size_t(H.max_levels) + 1) * 4 + 15) / 16 * 16 / 4), msl = H.max_slices;
+    for (int pass = 0; pass < 2; ++pass) {
+        SweepPack &P = pass ? H.U : H.L;
+        P.meta.assign(size_t(H.nsd) * H.meta_words, 0);
+        for (int s = 0; s < H.nsd; ++s) {
+            SdInfo &I = H.sd[s];
+            const int lev0 = pass ? I.levU0 : I.levL0, lev1 = pass ? I.levU1 : I.levL1;
+            const int sl0 = P.lev_slice[lev0], nsl = P.lev_slice[lev1] - sl0;
+            const int64_t off0 = nsl > 0 ? P.sl_off[sl0] : 0;
+            (pass ? I.slU0 : I.slL0) = sl0;
+            (pass ? I.nslU : I.nslL) = nsl;
+            (pass ? I.offU0 : I.offL0) = off0;
+            int32_t *m = P.meta.data() + size_t(s) * H.meta_words;
+            for (int a = 0; a <= lev1 - lev0; ++a) m[a] = P.lev_slice[lev0 + a] - sl0;
+            for (int a = 0; a < lev1 - lev0; ++a)
+                for (int q = m[a]; q < m[a + 1]; ++q) m[offw + msl + q] = a << 17 | P.sl_info[sl0 + q];
+            for (int q = 0; q < nsl; ++q) {
+                m[offw + q] = int32_t(P.sl_off[sl0 + q] - off0);
+                m[offw + 2 * msl + q] = P.sl_slot[sl0 + q];
+            }
+        }
+    }
     // tail padding: the sweep kernel may read a fixed number of entries past a
     // slice's width; keep those reads inside the arrays
     for (SweepPack *P : {&H.L, &H.U}) {

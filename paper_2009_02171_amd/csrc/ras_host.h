@@ -39,12 +39,26 @@ struct SweepPack {
     std::vector<double> lane_diag;   // [nslice*64] U only: u_ii (0 on padding lanes)
     std::vector<double> val;         // [2 * pairs]
     std::vector<uint16_t> addr;      // [8 * 64 * nslice] ring slot of the dependency
+    std::vector<int32_t> meta;       // [nsd][meta words] LDS metadata image of each subdomain's sweep
 };
 
 struct SdInfo {
     int32_t levL0, levL1, levU0, levU1;  // level ranges of the two sweeps
     int32_t nloc, nown;
+    int32_t nrows;                   // rows of the box (4 per cell)
+    int32_t slL0, nslL, slU0, nslU;  // first slice and number of slices of each sweep
+    int64_t g0;                      // box vector: first entry of the subdomain's gather list
+    int64_t offL0, offU0;            // first value pair of each sweep
 };
+
+// Bytes of one sweep's slice metadata as the sweep kernel keeps it in LDS
+// (and as the per-subdomain images are laid out): the first slice of each
+// level (relative), then per slice its first value pair (relative to the
+// subdomain's first), level << 17 | slice info, and ring slot or position;
+// each part 16-byte aligned.
+constexpr size_t meta_bytes_for(int nsl, int nlev) {
+    return ((size_t(nlev) + 1) * 4 + 15) / 16 * 16 + (size_t(nsl) * 12 + 15) / 16 * 16;
+}
 
 constexpr int64_t kBoxVectorBytes = 90 * 1024;
 
@@ -60,10 +74,14 @@ struct HostRas {
     // row's position in the L sweep's order instead of a ring slot.
     bool box_vector = false;
     int box_rows = 0;  // rows of the largest subdomain
+    // box vector: for each subdomain (from SdInfo::g0, SdInfo::nrows entries)
+    // the x index of the row at each position, so the gather is one pass
+    std::vector<int32_t> gio;
     int max_slices = 0, max_levels = 0;  // per sweep of one subdomain (LDS metadata sizing)
     int64_t nnz = 0;                     // factor entries (L and U, diagonal included)
     int64_t box_cells = 0, owned_cells = 0;
     int max_total_levels = 0;            // L + U levels of the deepest subdomain
+    int meta_words = 0;                  // int32 words of one metadata image (meta_bytes_for / 4)
 };
 
 // Build and factor.  Returns CSDYN_EZEROPIVOT / CSDYN_EINVAL on failure.
