@@ -129,6 +129,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="large")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-two-streams", action="store_true",
+                    help="skip the forms with the two systems on two streams (a profiler's per-kernel averages "
+                         "then cover sequential launches only)")
     ap.add_argument("--train-steps", type=int, default=100, help="learned workload: training steps")
     ap.add_argument("--eval-steps", type=int, default=100, help="learned workload: evaluation steps")
     args = ap.parse_args()
@@ -238,7 +241,7 @@ def main():
     # both forms again with the two systems of a step solved at the same time, each from its own host
     # thread on its own stream (the systems are independent; results are identical)
     elapsed_two = {}
-    for form in forms:
+    for form in ([] if args.no_two_streams else forms):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(args.steps):
@@ -294,10 +297,9 @@ def main():
                               "iters": {k: {"outer": v[0], "inner": v[1], "relres": v[2]}
                                         for k, v in iters["mixed_fp32_pc"].items()},
                               "rel_err_vs_fp64_solution": err},
-            "plain_fp64_two_streams": {"solves_per_s": round(2 * args.steps / elapsed_two["plain_fp64"], 4),
-                                       "ms_per_step": round(elapsed_two["plain_fp64"] / args.steps * 1e3, 3)},
-            "mixed_fp32_pc_two_streams": {"solves_per_s": round(2 * args.steps / elapsed_two["mixed_fp32_pc"], 4),
-                                          "ms_per_step": round(elapsed_two["mixed_fp32_pc"] / args.steps * 1e3, 3)},
+            **{f"{form}_two_streams": {"solves_per_s": round(2 * args.steps / el, 4),
+                                       "ms_per_step": round(el / args.steps * 1e3, 3)}
+               for form, el in elapsed_two.items()},
         },
         "roofline": {"kernel": f"{dom_name[0]}@{dom_name[1]}", "bound": "hbm", "achieved": round(dom_gbs, 1),
                      "timed_launches": dom["count"], "timed_every": PROFILE_EVERY,
