@@ -102,3 +102,54 @@ def test_residual_norm_of_a_guess(kind):
     op = csdyn.Operator(n, nr, kind=kind)
     got = csdyn.Residual(op)(torch.from_numpy(b).cuda(), torch.from_numpy(x).cuda())
     assert abs(got - ref) <= 1e-12 * ref
+
+
+def test_two_systems_on_two_streams_match_sequential():
+    """The two systems of a step solved at the same time from two host threads
+    on two streams (as bench.py's *_two_streams forms do) give bit-identical
+    solutions and iteration counts to the same solves one after the other."""
+    import threading
+
+    import torch
+    from paper_2009_02171_amd import csdyn
+    n, nr, sub = 16, 16, (8, 8, 8)
+    print(f"[two streams] n={n} sub={sub} two-level, FP64 and FP32 preconditioners", flush=True)
+    for prec in (0, 1):
+        sys_ = {}
+        for kind, seed in ((csdyn.VP, 1), (csdyn.BP, 2)):
+            op = csdyn.Operator(n, nr, kind=kind)
+            pc = csdyn.RAS(op, sub=sub, levels=2, precision=prec)
+            sol = csdyn.Solver(op, pc, restart=30, maxit=2000, flexible=True, rtol=1e-8)
+            b = torch.from_numpy(inputs.rhs(n, nr, seed)).cuda()
+            sys_[kind] = (op, pc, sol, b, torch.cuda.Stream())
+        seq = {}
+        for kind, (_, _, sol, b, _) in sys_.items():
+            x, st, rc = sol.solve(b, torch.zeros_like(b))
+            torch.cuda.synchronize()
+            assert rc == 0
+            seq[kind] = (x.clone(), st["iters"], st["inner_iters"])
+        par, errors = {}, []
+
+        def run(kind):
+            try:
+                _, _, sol, b, s = sys_[kind]
+                with torch.cuda.stream(s):
+                    x = torch.zeros_like(b)
+                    x, st, rc = sol.solve(b, x, stream=s)
+                s.synchronize()
+                par[kind] = (x, st["iters"], st["inner_iters"], rc)
+            except Exception as e:  # reported below
+                errors.append(e)
+
+        threads = [threading.Thread(target=run, args=(k,)) for k in sys_]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        torch.cuda.synchronize()
+        assert not errors, errors
+        for kind in sys_:
+            x, it, inner, rc = par[kind]
+            assert rc == 0
+            assert (it, inner) == seq[kind][1:], (kind, prec, it, inner, seq[kind][1:])
+            assert torch.equal(x, seq[kind][0]), (kind, prec)
