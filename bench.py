@@ -311,9 +311,56 @@ def main():
         "kernels": kernels,
         "kernels_from": "one untimed plain FP64 step with every launch timed (share = of that step)",
     }
+    outer = sum(v[0] for v in iters_plain.values())
+    out["us_per_outer_iteration"] = round(elapsed / args.steps / outer * 1e6, 2)
+    if args.workload == "large":
+        out["operator_n128"] = operator_rate(128, 128)
+        out["hbm_copy"] = copy_rate()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, {k: v[:2] for k, v in iters_plain.items()})
     print(json.dumps(out))
+
+
+def operator_rate(n, nr, reps=20):
+    """The stencil operator alone at a size no cache holds (N = Nr = 128:
+    805 MB per apply), each launch timed with HIP events."""
+    import torch
+    from paper_2009_02171_amd import csdyn, inputs
+    op = csdyn.Operator(n, nr, kind=csdyn.VP, dt=1e-4, ekman=1e-3)
+    x = torch.from_numpy(inputs.random_field(op.shape, 7)).cuda()
+    y = op.empty()
+    for _ in range(3):
+        op.apply(x, y)
+    prof = csdyn.Profile(max_launches=256, select=["op_main"], every=1)
+    prof.__enter__()
+    for _ in range(reps):
+        op.apply(x, y)
+    torch.cuda.synchronize()
+    prof.__exit__(None, None, None)
+    e = prof.result[("op_main", 6 * n * n * nr)]
+    g = e["bytes"] / (e["ms"] * 1e-3) / 1e9
+    return dict(kernel="op_main", n=n, nr=nr, cells=6 * n * n * nr, avg_us=round(e["ms"] / e["count"] * 1e3, 2),
+                achieved=round(g, 1), peak=HBM_PEAK_GBS, unit="GB/s", frac=round(g / HBM_PEAK_GBS, 4))
+
+
+def copy_rate(nbytes=1 << 30, reps=20):
+    """Achievable HBM bandwidth for reference: a device-to-device copy of
+    1 GiB (read + write counted), timed with events on the current stream."""
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    g = 2 * nbytes / (ms * 1e-3) / 1e9
+    return dict(bytes_per_copy=2 * nbytes, avg_us=round(ms * 1e3, 1), achieved=round(g, 1), peak=HBM_PEAK_GBS,
+                unit="GB/s", frac=round(g / HBM_PEAK_GBS, 4), kernel="torch device copy")
 
 
 def batched(args, wl):
