@@ -37,13 +37,9 @@ struct Pair<float> {
 template <class TF>
 struct DevSweep {
     using TF2 = typename Pair<TF>::type;
-    const int32_t *lev_slice;  // [nlev + 1] first slice of each level
-    const int32_t *sl_info;    // [nslice] rows << 10 | (s - 1) << 4 | entries per lane
-    const int64_t *sl_off;     // [nslice] first value pair
-    const int32_t *sl_slot;    // [nslice] ring slot (box vector: L-sweep position) of the first row
-    const int32_t *lane_io;    // [nslice*64] L: x index; U: y index of owned rows; else -1
-    const int32_t *lane_next;  // [nslice*64] ring: L, U-sweep position of the row; box vector: L, the row's
-                               // position; U, {position, y index} pairs
+    const int32_t *lane_io;    // [nslice*64] ring: L, x index; U, y index of owned rows; else -1
+    const int32_t *lane_next;  // [nslice*64] ring: L, U-sweep position of the row; box vector: U,
+                               // {position, y index} pairs
     const TF2 *val;            // [pairs] factor entries, two per lane
     const uint4 *addr;         // [64 * nslice] addresses of the dependencies (ring slots or positions), eight per lane
     const int4 *meta;          // [nsd][meta bytes / 16] LDS metadata image of each subdomain's sweep
@@ -390,12 +386,8 @@ struct OneLevel {
     bool lds_ring = false;
     int precision = 0;
     SdInfo *sd = nullptr;
-    int32_t *Llev = nullptr, *Lw = nullptr, *Lslot = nullptr, *Lio = nullptr, *Lnext = nullptr;
-    int64_t *Loff = nullptr;
-    uint16_t *Laddr = nullptr;
-    int32_t *Ulev = nullptr, *Uw = nullptr, *Uslot = nullptr, *Uio = nullptr, *Unext = nullptr;
-    int64_t *Uoff = nullptr;
-    uint16_t *Uaddr = nullptr;
+    int32_t *Lio = nullptr, *Lnext = nullptr, *Uio = nullptr, *Unext = nullptr;
+    uint16_t *Laddr = nullptr, *Uaddr = nullptr;
     void *Lval = nullptr, *Uval = nullptr, *lin = nullptr, *lout = nullptr, *ring = nullptr;
     int32_t *gio = nullptr, *Lmeta = nullptr, *Umeta = nullptr;
 
@@ -406,18 +398,18 @@ struct OneLevel {
         o.max_total_levels = H.max_total_levels; o.precision = precision;
         o.vec = H.box_vector; o.box_rows = H.box_rows;
         o.sd = c.take<SdInfo>(H.sd.size());
-        o.Llev = c.take<int32_t>(H.L.lev_slice.size()); o.Lw = c.take<int32_t>(H.L.sl_info.size());
-        o.Loff = c.take<int64_t>(H.L.sl_off.size()); o.Lslot = c.take<int32_t>(H.L.sl_slot.size());
-        o.Lio = c.take<int32_t>(H.L.lane_io.size());
-        o.Lnext = c.take<int32_t>(H.L.lane_next.size()); o.Laddr = c.take<uint16_t>(H.L.addr.size());
+        // the box vector needs no per-lane indices of the L sweep, no U y indices
+        // apart from its pairs and no input records
+        const bool ring = !H.box_vector;
+        o.Lio = c.take<int32_t>(ring ? H.L.lane_io.size() : 0);
+        o.Lnext = c.take<int32_t>(ring ? H.L.lane_next.size() : 0);
+        o.Laddr = c.take<uint16_t>(H.L.addr.size());
         o.Lval = c.take<char>(H.L.val.size() * fs);
-        o.Ulev = c.take<int32_t>(H.U.lev_slice.size()); o.Uw = c.take<int32_t>(H.U.sl_info.size());
-        o.Uoff = c.take<int64_t>(H.U.sl_off.size()); o.Uslot = c.take<int32_t>(H.U.sl_slot.size());
-        o.Uio = c.take<int32_t>(H.U.lane_io.size());
+        o.Uio = c.take<int32_t>(ring ? H.U.lane_io.size() : 0);
         o.Unext = c.take<int32_t>(2 * H.U.lane_next.size());
         o.Uaddr = c.take<uint16_t>(H.U.addr.size());
         o.Uval = c.take<char>(H.U.val.size() * fs);
-        o.lin = c.take<char>(H.L.lane_io.size() * fs);
+        o.lin = c.take<char>(ring ? H.L.lane_io.size() * fs : 0);
         o.lout = c.take<char>(2 * H.U.lane_io.size() * fs);
         o.ring = c.take<char>(size_t(H.nsd) * H.ring_depth * H.ring_width * fs);
         o.gio = c.take<int32_t>(H.gio.size());
@@ -428,18 +420,13 @@ struct OneLevel {
     int32_t upload(const HostRas &H) const {
         auto up = [](void *d, const void *s, size_t b) { return b ? hipMemcpy(d, s, b, hipMemcpyHostToDevice) : hipSuccess; };
         CSD_HIP(up(sd, H.sd.data(), H.sd.size() * sizeof(SdInfo)));
-        CSD_HIP(up(Llev, H.L.lev_slice.data(), H.L.lev_slice.size() * 4));
-        CSD_HIP(up(Lw, H.L.sl_info.data(), H.L.sl_info.size() * 4));
-        CSD_HIP(up(Loff, H.L.sl_off.data(), H.L.sl_off.size() * 8));
-        CSD_HIP(up(Lslot, H.L.sl_slot.data(), H.L.sl_slot.size() * 4));
-        CSD_HIP(up(Lio, H.L.lane_io.data(), H.L.lane_io.size() * 4));
-        CSD_HIP(up(Lnext, H.L.lane_next.data(), H.L.lane_next.size() * 4));
+        const bool ring = !H.box_vector;
+        if (ring) {
+            CSD_HIP(up(Lio, H.L.lane_io.data(), H.L.lane_io.size() * 4));
+            CSD_HIP(up(Lnext, H.L.lane_next.data(), H.L.lane_next.size() * 4));
+            CSD_HIP(up(Uio, H.U.lane_io.data(), H.U.lane_io.size() * 4));
+        }
         CSD_HIP(up(Laddr, H.L.addr.data(), H.L.addr.size() * 2));
-        CSD_HIP(up(Ulev, H.U.lev_slice.data(), H.U.lev_slice.size() * 4));
-        CSD_HIP(up(Uw, H.U.sl_info.data(), H.U.sl_info.size() * 4));
-        CSD_HIP(up(Uoff, H.U.sl_off.data(), H.U.sl_off.size() * 8));
-        CSD_HIP(up(Uslot, H.U.sl_slot.data(), H.U.sl_slot.size() * 4));
-        CSD_HIP(up(Uio, H.U.lane_io.data(), H.U.lane_io.size() * 4));
         if (!H.U.lane_next.empty()) {  // box vector: {position, y index} per U lane
             std::vector<int32_t> ri(2 * H.U.lane_next.size());
             for (size_t a = 0; a < H.U.lane_next.size(); ++a) {
@@ -476,8 +463,8 @@ struct OneLevel {
         DevRas<TF> R;
         R.sd = sd;
         using TF2 = typename Pair<TF>::type;
-        R.L = DevSweep<TF>{Llev, Lw, Loff, Lslot, Lio, Lnext, (const TF2 *)Lval, (const uint4 *)Laddr, (const int4 *)Lmeta};
-        R.U = DevSweep<TF>{Ulev, Uw, Uoff, Uslot, Uio, Unext, (const TF2 *)Uval, (const uint4 *)Uaddr, (const int4 *)Umeta};
+        R.L = DevSweep<TF>{Lio, Lnext, (const TF2 *)Lval, (const uint4 *)Laddr, (const int4 *)Lmeta};
+        R.U = DevSweep<TF>{Uio, Unext, (const TF2 *)Uval, (const uint4 *)Uaddr, (const int4 *)Umeta};
         R.lin = (TF *)lin;
         R.lout = (TF2 *)lout;
         R.ring = (TF *)ring;
