@@ -90,9 +90,13 @@ int32_t csdyn_op_setup(const csdyn_grid *g, const csdyn_op *op, void *ws, size_t
 int32_t csdyn_operator_apply(const csdyn_opctx *ctx, const double *x, double *y, void *stream);
 void csdyn_op_destroy(csdyn_opctx *ctx);
 
-/* Workgroup shape of the stencil kernel (a tuning knob; results are
- * identical): 0 = default (16x8), 1 = 32x8, 2 = 16x16, 3 = 64x4, 4 = 16x8,
- * 5 = 32x4 cells. */
+/* Workgroup shape of the stencil kernel (a tuning knob): 1 = 32x8,
+ * 2 = 16x16, 3 = 64x4, 4 = 16x8, 5 = 32x4 cells (identical results), 6 = the
+ * FP64 kernel that requests its layers straight into LDS (16x16 cells, six
+ * layer buffers; for N > 16, else 16x8; equal to the others up to rounding,
+ * the grouping of the same terms being the compiler's), 0 = default (6 for
+ * FP64 shells of at least 6 x 48^3 cells, else 4).  Returns CSDYN_EINVAL
+ * outside 0..6. */
 int32_t csdyn_op_set_tile(csdyn_opctx *ctx, int32_t tile);
 
 /* Step 3 of the time step (Sec. 3.1, eq. ubtilde) from a solution

@@ -11,7 +11,7 @@ import torch
 
 from . import csdyn
 
-TILES = {1: "32x8", 2: "16x16", 3: "64x4", 4: "16x8", 5: "32x4"}
+TILES = {1: "32x8", 2: "16x16", 3: "64x4", 4: "16x8", 5: "32x4", 6: "16x16 LDS requests"}
 SUBDOMAINS = (8, 12, 16, 20, 24)
 
 _cache: dict = {}

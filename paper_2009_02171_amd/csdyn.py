@@ -196,7 +196,8 @@ class Operator:
         return y
 
     def set_tile(self, tile: int):
-        """Stencil workgroup shape: 0 by N, 1: 32x8, 2: 16x16, 3: 64x4, 4: 16x8, 5: 32x4."""
+        """Stencil workgroup shape: 0 by N, 1: 32x8, 2: 16x16, 3: 64x4, 4: 16x8, 5: 32x4,
+        6: FP64 layers requested straight into LDS (16x16; N > 16)."""
         _check(lib().csdyn_op_set_tile(self.h, tile), "csdyn_op_set_tile")
 
     def project(self, x: torch.Tensor, out: torch.Tensor | None = None, stream=None):

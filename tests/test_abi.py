@@ -62,4 +62,4 @@ def test_autotune_candidates():
     assert autotune.candidate_subdomains(80, 80) == [8, 16, 20]
     assert autotune.candidate_subdomains(72, 72) == [8, 12, 24]
     assert autotune.candidate_subdomains(24, 24) == [8, 12, 24]
-    assert set(autotune.TILES) == {1, 2, 3, 4, 5}
+    assert set(autotune.TILES) == {1, 2, 3, 4, 5, 6}

@@ -74,10 +74,11 @@ def test_batched_rejects_two_level():
         csdyn.Batch([op], [pc])
 
 
-@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("kind", [0, 1])
 def test_operator_tiles_agree(tile, kind):
-    # tiles that hold one, two or four panel edges, odd layer counts
+    # tiles that hold one, two or four panel edges, odd layer counts; tile 6
+    # (its own kernel) equal up to rounding
     import torch
     from paper_2009_02171_amd import csdyn
     for n, nr in ((40, 6), (24, 5), (17, 3), (5, 3), (8, 9)):
@@ -85,4 +86,8 @@ def test_operator_tiles_agree(tile, kind):
         x = torch.from_numpy(inputs.random_field((6, nr, n, n, 4), seed=n)).cuda()
         y0 = op.apply(x).clone()
         op.set_tile(tile)
-        assert torch.equal(op.apply(x), y0)
+        y = op.apply(x)
+        if tile == 6:
+            assert float((y - y0).abs().max()) <= 1e-13 * float(y0.abs().max())
+        else:
+            assert torch.equal(y, y0)

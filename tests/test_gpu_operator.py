@@ -11,10 +11,11 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-12
 
 
-def _gpu_apply(n, nr, kind, x, **kw):
+def _gpu_apply(n, nr, kind, x, tile=0, **kw):
     import torch
     from paper_2009_02171_amd import csdyn
     op = csdyn.Operator(n, nr, kind=kind, **kw)
+    op.set_tile(tile)
     xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
     y = op.apply(xt)
     torch.cuda.synchronize()
@@ -29,6 +30,22 @@ def test_operator_matches_oracle(n, nr, kind):
     x = inputs.random_field(pb.shape(), seed=100 + n + kind)
     y_ref = O.apply(pb, x)
     y = _gpu_apply(n, nr, kind, x)
+    err = np.abs(y - y_ref).max() / np.abs(y_ref).max()
+    assert err <= TOL, err
+
+
+@pytest.mark.parametrize("n,nr", [(17, 9), (40, 13), (33, 4), (64, 96)])
+@pytest.mark.parametrize("kind", [0, 1])
+def test_operator_lds_request_kernel_matches_oracle(n, nr, kind):
+    """The FP64 kernel that requests its layers straight into LDS (tile 6):
+    tiles on one and on two panel edges, layer chunks that end inside the
+    six-step loop (9 = 6 + 3 and 13 = 6 + 6 + 1 layers) and chunks of two
+    whole trips (N = 64, Nr = 96: 12 layers)."""
+    print(f"[operator parity, tile 6] n={n} nr={nr} kind={kind}", flush=True)
+    pb = O.Problem(n, nr, kind=kind)
+    x = inputs.random_field(pb.shape(), seed=200 + n + kind)
+    y_ref = O.apply(pb, x)
+    y = _gpu_apply(n, nr, kind, x, tile=6)
     err = np.abs(y - y_ref).max() / np.abs(y_ref).max()
     assert err <= TOL, err
 
