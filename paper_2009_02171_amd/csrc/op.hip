@@ -504,7 +504,7 @@ __device__ __forceinline__ void op_march_dma(const DevGeom &g, const RowCoef &rc
     using T = double;
     using LL = DmaLds<TX, TY>;
     constexpr int NT = LL::NT, HX = LL::HX, HY = LL::HY, NRING = LL::NRING, NXW = LL::NXW, HALF = LL::HALF;
-    constexpr int BUF = LL::BUF, NB = LL::NB, D = NB - 1;
+    constexpr int NB = LL::NB, D = NB - 1;
     static_assert(NB == 6, "the loop below is unrolled by six");
     const int n = g.n, nr = g.nr;
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
