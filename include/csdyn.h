@@ -95,7 +95,7 @@ void csdyn_op_destroy(csdyn_opctx *ctx);
  * FP64 kernel that requests its layers straight into LDS (16x16 cells, six
  * layer buffers; for N > 16, else 16x8; equal to the others up to rounding,
  * the grouping of the same terms being the compiler's), 0 = default (6 for
- * FP64 shells of at least 6 x 48^3 cells, else 4).  Returns CSDYN_EINVAL
+ * FP64 shells of at least 6 x 96^3 cells, else 4).  Returns CSDYN_EINVAL
  * outside 0..6. */
 int32_t csdyn_op_set_tile(csdyn_opctx *ctx, int32_t tile);
 

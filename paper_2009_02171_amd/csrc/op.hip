@@ -824,10 +824,10 @@ static int32_t launch_all(const csdyn_opctx *ctx, const T *x, T *y, T *G, T *SF,
     }
     ProfScope ps(sizeof(T) == 8 ? "op_main" : "op_main_f32", 6 * int64_t(n) * n * nr,
                  6.0 * n * n * nr * 8 * sizeof(T), s);  // x read once, y written once
-    // default: the LDS-request kernel for FP64 shells of at least 6 x 48^3
-    // cells (below that its per-chunk start-up costs more than it gains),
-    // else 16x8; tile 6 asks for it (FP64, N > 16; otherwise 16x8)
-    const bool big = int64_t(n) * n * nr >= int64_t(48) * 48 * 48;
+    // default: the LDS-request kernel for FP64 shells of at least 6 x 96^3
+    // cells (measured faster there; at N = 64 and 80 the register kernel is
+    // faster), else 16x8; tile 6 asks for it (FP64, N > 16; otherwise 16x8)
+    const bool big = int64_t(n) * n * nr >= int64_t(96) * 96 * 96;
     const int tile = ctx->tile ? ctx->tile : (sizeof(T) == 8 && n > 16 && big ? 6 : 4);
     int32_t status = CSDYN_OK;
     auto go = [&](auto tx_c, auto ty_c) {
