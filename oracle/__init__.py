@@ -83,6 +83,8 @@ def lib():
         _lib.ref_subdomain_solve.argtypes = [P(Grid), P(Op), i32, C.c_int, C.c_int, d, d]
         _lib.ref_project.argtypes = [P(Grid), P(Op), d, d]
         _lib.ref_gmres_solve.argtypes = [P(Grid), P(Op), C.c_void_p, P(GmresOpts), d, d, P(GmresStats)]
+        _lib.ref_gmres_solve_hist.argtypes = [P(Grid), P(Op), C.c_void_p, P(GmresOpts), d, d, P(GmresStats), d,
+                                              C.c_int]
     return _lib
 
 
@@ -257,16 +259,20 @@ def subdomain_solve(pb: Problem, sub, s, x, overlap=1):
 
 
 def gmres(pb: Problem, b, x0=None, pc: Preconditioner | None = None, restart=30, maxit=1000, flexible=False,
-          rtol=1e-8, atol=0.0):
-    """Right-preconditioned restarted (F)GMRES (Sec. 3.3).  Returns (x, stats, status)."""
+          rtol=1e-8, atol=0.0, history=False):
+    """Right-preconditioned restarted (F)GMRES (Sec. 3.3).  Returns (x, stats, status); with
+    history=True, stats["hist"] holds the residual estimate after every Arnoldi step."""
     b = np.ascontiguousarray(b, dtype=np.float64).reshape(-1)
     x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64).reshape(-1)
     st = GmresStats()
     o = GmresOpts(restart, maxit, int(flexible), rtol, atol)
-    rc = lib().ref_gmres_solve(C.byref(pb.grid()), C.byref(pb.op()), pc.h if pc else None, C.byref(o), _dp(b),
-                               _dp(x), C.byref(st))
+    hist = np.full(maxit, np.nan)
+    rc = lib().ref_gmres_solve_hist(C.byref(pb.grid()), C.byref(pb.op()), pc.h if pc else None, C.byref(o), _dp(b),
+                                    _dp(x), C.byref(st), _dp(hist) if history else None, maxit if history else 0)
     stats = dict(iters=st.iters, restarts=st.restarts, inner_iters=st.inner_iters, relres_true=st.relres_true,
                  relres_est=st.relres_est)
+    if history:
+        stats["hist"] = hist[:st.iters].copy()
     return x.reshape(pb.shape()), stats, rc
 
 

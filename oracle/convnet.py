@@ -121,48 +121,60 @@ def flatten(params):
     return np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in params])
 
 
-def forward(params, x):
-    """Network forward; returns y and the activations the backward needs."""
+def _keep(bf16):
+    """Storage rounding of a tensor: identity in FP64, or rounding to BF16 when the
+    network is emulated with BF16 activations and gradients (every tensor that is
+    stored between layers; sums inside a layer stay FP64)."""
+    return bf16_round if bf16 else (lambda v: v)
+
+
+def forward(params, x, bf16=False):
+    """Network forward; returns y and the activations the backward needs.  With
+    bf16=True every stored activation is rounded to BF16 (the output y is not)."""
     relu = lambda v: np.maximum(v, 0.0)
+    k = _keep(bf16)
     (w0, b0), (w1, b1), (w2, b2), (w3, b3), (w4, b4), (w5, b5), (w6, b6), (w7, b7) = params
     a = {"x": x}
-    a["e0"] = relu(conv_fwd(x, w0, b0))
-    a["p0"] = pool(a["e0"])
-    a["e1"] = relu(conv_fwd(a["p0"], w1, b1))
-    a["p1"] = pool(a["e1"])
-    a["e2"] = relu(conv_fwd(a["p1"], w2, b2))
-    a["p2"] = pool(a["e2"])
-    a["e3"] = relu(conv_fwd(a["p2"], w3, b3))
+    a["e0"] = k(relu(conv_fwd(x, w0, b0)))
+    a["p0"] = k(pool(a["e0"]))
+    a["e1"] = k(relu(conv_fwd(a["p0"], w1, b1)))
+    a["p1"] = k(pool(a["e1"]))
+    a["e2"] = k(relu(conv_fwd(a["p1"], w2, b2)))
+    a["p2"] = k(pool(a["e2"]))
+    a["e3"] = k(relu(conv_fwd(a["p2"], w3, b3)))
     a["u3"] = up(a["e3"])
-    a["d2"] = relu(conv_fwd(a["u3"], w4, b4) + a["e2"])
+    a["d2"] = k(relu(conv_fwd(a["u3"], w4, b4) + a["e2"]))
     a["u2"] = up(a["d2"])
-    a["d1"] = relu(conv_fwd(a["u2"], w5, b5) + a["e1"])
+    a["d1"] = k(relu(conv_fwd(a["u2"], w5, b5) + a["e1"]))
     a["u1"] = up(a["d1"])
-    a["d0"] = relu(conv_fwd(a["u1"], w6, b6) + a["e0"])
+    a["d0"] = k(relu(conv_fwd(a["u1"], w6, b6) + a["e0"]))
     y = conv_fwd(a["d0"], w7, b7)
     return y, a
 
 
-def backward(params, a, dy):
-    """Gradients [(dW, db)] of the loss for every layer, given dL/dy."""
+def backward(params, a, dy, bf16=False):
+    """Gradients [(dW, db)] of the loss for every layer, given dL/dy.  With
+    bf16=True, dy and every stored intermediate gradient is rounded to BF16."""
     g = [None] * 8
     mask = lambda v: (v > 0).astype(np.float64)
+    k = _keep(bf16)
+    dy = k(dy)
     g[7] = conv_bwd_weight(a["d0"], dy)
-    dz6 = conv_bwd_data(dy, params[7][0]) * mask(a["d0"])  # pre-activation of d0
+    dz6 = k(conv_bwd_data(dy, params[7][0]) * mask(a["d0"]))  # pre-activation of d0
     g[6] = conv_bwd_weight(a["u1"], dz6)
-    dd1 = pool(conv_bwd_data(dz6, params[6][0])) * 8.0  # adjoint of up = sum over children
-    dz5 = dd1 * mask(a["d1"])
+    dd1 = pool(k(conv_bwd_data(dz6, params[6][0]))) * 8.0  # adjoint of up = sum over children
+    dz5 = k(dd1 * mask(a["d1"]))
     g[5] = conv_bwd_weight(a["u2"], dz5)
-    dz4 = pool(conv_bwd_data(dz5, params[5][0])) * 8.0 * mask(a["d2"])
+    dz4 = k(pool(k(conv_bwd_data(dz5, params[5][0]))) * 8.0 * mask(a["d2"]))
     g[4] = conv_bwd_weight(a["u3"], dz4)
-    dz3 = pool(conv_bwd_data(dz4, params[4][0])) * 8.0 * mask(a["e3"])
+    dz3 = k(pool(k(conv_bwd_data(dz4, params[4][0]))) * 8.0 * mask(a["e3"]))
     g[3] = conv_bwd_weight(a["p2"], dz3)
     # e2 feeds pool -> conv3 and the skip into d2's pre-activation
-    dz2 = (up(conv_bwd_data(dz3, params[3][0])) / 8.0 + dz4) * mask(a["e2"])
+    dz2 = k((up(k(conv_bwd_data(dz3, params[3][0]))) / 8.0 + dz4) * mask(a["e2"]))
     g[2] = conv_bwd_weight(a["p1"], dz2)
-    dz1 = (up(conv_bwd_data(dz2, params[2][0])) / 8.0 + dz5) * mask(a["e1"])
+    dz1 = k((up(k(conv_bwd_data(dz2, params[2][0]))) / 8.0 + dz5) * mask(a["e1"]))
     g[1] = conv_bwd_weight(a["p0"], dz1)
-    dz0 = (up(conv_bwd_data(dz1, params[1][0])) / 8.0 + dz6) * mask(a["e0"])
+    dz0 = k((up(k(conv_bwd_data(dz1, params[1][0]))) / 8.0 + dz6) * mask(a["e0"]))
     g[0] = conv_bwd_weight(a["x"], dz0)
     return [list(t) for t in g]
 

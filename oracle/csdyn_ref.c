@@ -863,7 +863,8 @@ static void project_p(int64_t ncell, const double *vol, double *b) {
  * Gram-Schmidt and Givens rotations; stops when the residual estimate is at
  * most max(atol, rtol * ||b - A x0||) (Sec. 3.3, the stopping rule after
  * eq. newlinear). */
-static int gmres_core(const csr *A, ref_pc *pc, const ref_gmres_opts *o, const double *b, double *x, ref_gmres_stats *stt) {
+static int gmres_core(const csr *A, ref_pc *pc, const ref_gmres_opts *o, const double *b, double *x, ref_gmres_stats *stt,
+                      double *hist, int hist_len) {
     int64_t n = A->nrow;
     int m = o->restart;
     if (m < 1 || o->maxit < 1) return REF_EINVAL;
@@ -914,6 +915,7 @@ static int gmres_core(const csr *A, ref_pc *pc, const ref_gmres_opts *o, const d
             gv[j + 1] = -sn[j] * gv[j];
             gv[j] = cs[j] * gv[j];
             est = fabs(gv[j + 1]);
+            if (hist && iters <= hist_len) hist[iters - 1] = est;   /* residual estimate after each Arnoldi step */
             int happy = hn <= 1e-14 * anorm;
             if (!happy) for (int64_t q = 0; q < n; q++) V[(int64_t)(j + 1) * n + q] = w[q] / hn;
             if (est <= tol || happy) { conv = 1; break; }
@@ -969,7 +971,7 @@ static void twolevel_apply(ref_pc *pc, const double *x, double *y) {
     cpc.levels = 1; cpc.fine = pc->coarse; cpc.g = *gc; cpc.op = pc->op; cpc.precision = pc->precision;
     ref_gmres_opts o = {pc->coarse_restart, pc->coarse_maxit, 0, pc->coarse_rtol, 0.0};
     ref_gmres_stats st = {0};
-    gmres_core(&pc->Ac, &cpc, &o, rc, ec, &st);
+    gmres_core(&pc->Ac, &cpc, &o, rc, ec, &st, NULL, 0);
     pc->inner_iters += st.iters;
     double *wv = malloc(sizeof(double) * nf), *t = malloc(sizeof(double) * nf);
     for (int p = 0; p < 6; p++)
@@ -1197,8 +1199,10 @@ int ref_pc_subdomain(const ref_pc *pc, int coarse, int s, int64_t *nloc, int64_t
 int ref_pc_count(const ref_pc *pc, int coarse) { const onelevel *ol = coarse ? pc->coarse : pc->fine; return ol ? ol->nsd : 0; }
 
 /* --------------------------------------------------------- exported: solve */
-int ref_gmres_solve(const ref_grid *g, const ref_op *op, ref_pc *pc, const ref_gmres_opts *o,
-                    const double *b, double *x, ref_gmres_stats *st) {
+/* As ref_gmres_solve, and hist[k] (k < hist_len) receives the residual
+ * estimate |g_{j+1}| after the solve's (k+1)-th Arnoldi step. */
+int ref_gmres_solve_hist(const ref_grid *g, const ref_op *op, ref_pc *pc, const ref_gmres_opts *o,
+                         const double *b, double *x, ref_gmres_stats *st, double *hist, int hist_len) {
     if (check_grid(g) || !op || !o || !b || !x) return REF_EINVAL;
     csr A;
     int rc = csr_build(g, op, &A);
@@ -1213,12 +1217,17 @@ int ref_gmres_solve(const ref_grid *g, const ref_op *op, ref_pc *pc, const ref_g
     ref_pc *use = pc ? pc : &none;
     use->inner_iters = 0;
     for (int64_t i = 0; i < n; i++) if (!isfinite(bb[i]) || !isfinite(x[i])) { rc = REF_EBREAKDOWN; goto out; }
-    rc = gmres_core(&A, use, o, bb, x, st);
+    rc = gmres_core(&A, use, o, bb, x, st, hist, hist_len);
     if (st) st->inner_iters = use->inner_iters;
     if (op->kind == 0 && rc >= 0) project_p(ncell, vol, x); /* remove the null-space component */
 out:
     free(bb); free(vol); csr_free(&A);
     return rc;
+}
+
+int ref_gmres_solve(const ref_grid *g, const ref_op *op, ref_pc *pc, const ref_gmres_opts *o,
+                    const double *b, double *x, ref_gmres_stats *st) {
+    return ref_gmres_solve_hist(g, op, pc, o, b, x, st, NULL, 0);
 }
 
 /* ILU(0) of an arbitrary CSR matrix with sorted columns (tests). */

@@ -161,10 +161,12 @@ def test_net_forward_matches_oracle():
     net = cs.Net(N, NR, torch.from_numpy(flat).cuda())
     g = net.predict(torch.from_numpy(x1).cuda(), torch.from_numpy(x2).cuda()).cpu().numpy()
     feats, s, sd = CN.features(x1, x2)
-    y_ref, _ = CN.forward(_oracle_params(flat), CN.bf16_round(feats))
+    # the oracle stores its activations in BF16 at the same points as the GPU
+    y_ref, _ = CN.forward(_oracle_params(flat), CN.bf16_round(feats), bf16=True)
     y_gpu = (g - (2 * x1 - x2)) / sd
     rel = np.linalg.norm(y_gpu - y_ref) / np.linalg.norm(y_ref)
-    assert rel <= 2e-2, rel
+    print(f"[net forward] rel {rel:.3e}", flush=True)
+    assert rel <= 1e-2, rel
 
 
 def test_net_zero_parameters_give_extrapolation():
@@ -184,18 +186,22 @@ def test_net_gradient_matches_oracle():
     loss, gg = net.loss_grad(*(torch.from_numpy(a).cuda() for a in (x2, x1, xn)))
     feats, s, sd = CN.features(x1, x2)
     params = _oracle_params(flat)
-    y, a = CN.forward(params, CN.bf16_round(feats))
+    y, a = CN.forward(params, CN.bf16_round(feats), bf16=True)
     rloss, dy = CN.loss_and_grad(y, CN.target(xn, x1, x2, sd))
-    grads = CN.flatten(CN.backward(params, a, dy))
-    assert abs(loss - rloss) <= 2e-2 * rloss
+    grads = CN.flatten(CN.backward(params, a, dy, bf16=True))
+    print(f"[net gradient] loss {loss:.6e} oracle {rloss:.6e}", flush=True)
+    assert abs(loss - rloss) <= 1e-2 * rloss
     gg = gg.cpu().numpy().astype(np.float64)
     off = 0
+    worst = 0.0
     for li, (co, ci) in enumerate(CN.layer_shapes()):
         nw = co * 27 * ci
         for part in (slice(off, off + nw), slice(off + nw, off + nw + co)):
             rel = np.linalg.norm(gg[part] - grads[part]) / np.linalg.norm(grads[part])
-            assert rel <= 6e-2, (li, rel)
+            worst = max(worst, rel)
+            assert rel <= 1e-2, (li, rel)
         off += nw + co
+    print(f"[net gradient] worst layer rel {worst:.3e}", flush=True)
 
 
 def test_net_training_tracks_oracle_and_reduces_loss():

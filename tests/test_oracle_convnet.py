@@ -136,3 +136,25 @@ def test_parameter_count():
     assert CN.param_count() == 701988
     assert len(inputs.net_params(0)) == 701988
     np.testing.assert_array_equal(CN.flatten(CN.unflatten(inputs.net_params(0))), inputs.net_params(0))
+
+
+def test_bf16_storage_emulation_stays_within_bf16_rounding():
+    """The BF16-storage mode of the network oracle (the form the GPU computes) is
+    the FP64 network up to BF16 rounding of the stored tensors: every stored value
+    changes by at most half a BF16 unit (2^-9 relative), and the outputs and
+    gradients move by a few such units, not more."""
+    widths = (8, 8, 8, 8)
+    params = CN.unflatten(inputs.net_params(24, widths), widths)
+    x = CN.bf16_round(_rand((6, 8, 8, 8, 8), 25))
+    y64, a64 = CN.forward(params, x)
+    y16, a16 = CN.forward(params, x, bf16=True)
+    for key in ("e0", "p0", "e1", "d0"):
+        v = a16[key]
+        assert np.array_equal(v, CN.bf16_round(v))            # stored in BF16
+    rel = np.linalg.norm(y16 - y64) / np.linalg.norm(y64)
+    assert 2.0**-12 < rel < 2.0**-5, rel
+    dy = _rand(y64.shape, 26)
+    g64 = CN.flatten(CN.backward(params, a64, dy))
+    g16 = CN.flatten(CN.backward(params, a16, dy, bf16=True))
+    relg = np.linalg.norm(g16 - g64) / np.linalg.norm(g64)
+    assert 2.0**-12 < relg < 2.0**-5, relg
