@@ -33,7 +33,12 @@
  * Memory: the caller owns every device buffer.  Each *_setup takes a device
  * workspace of at least *_workspace_bytes() bytes; handles are small host
  * structs that point into it, so the workspace must outlive the handle.  No
- * entry point allocates device memory after setup.
+ * entry point allocates device memory after setup.  Host-side exceptions:
+ * the first csdyn_gmres_solve (or two-level csdyn_ras_apply) on a thread
+ * allocates, per solve nesting depth (at most two), two small pinned host
+ * buffers and two HIP events for the Arnoldi read-backs, kept until the
+ * process ends; later calls on that thread reuse them.  opts.timing creates
+ * HIP events the same way.
  * Streams: `stream` is a hipStream_t (NULL = the null stream).  Apply calls
  * are asynchronous on it; csdyn_gmres_solve returns after the solve.
  * Errors: every call returns an int32 status; csdyn_last_error() gives a
@@ -192,7 +197,21 @@ typedef struct {
     int32_t orth;      /* 0 CGS, 1 CGS2 */
     int32_t rhs_relative; /* 0: stop at max(atol, rtol ||b - A x0||) (Sec. 3.3);
                              1: stop at max(atol, rtol ||b||) */
+    int32_t timing;       /* 1: fill stats.t_ms from HIP events recorded on `stream` around each
+                             phase (creates the events on first use on a thread); 0: no events */
 } csdyn_gmres_opts;
+
+/* Phases of stats.t_ms (the breakdown of a preconditioned iteration in Sec. 4.3
+ * into the coarse solve, the fine subdomain solves and the fine/coarse
+ * transfers, plus the outer solve's own work). */
+#define CSDYN_T_OP 0     /* outer operator applies (Arnoldi steps, initial and restart residuals) */
+#define CSDYN_T_PCF 1    /* fine one-level RAS sweeps (PC-F) */
+#define CSDYN_T_PCC 2    /* the coarse solve: inner GMRES with its operator, RAS and Gram-Schmidt (PC-C) */
+#define CSDYN_T_PCI 3    /* restriction, coarse projection, prolongation, x - A_f w, y = w + ...,
+                            FP64/FP32 conversions (PC-I) */
+#define CSDYN_T_ORTH 4   /* outer Gram-Schmidt (multi-dot, multi-update, normalisation) */
+#define CSDYN_T_OTHER 5  /* the rest of the span: vector copies and updates, read-back waits, host
+                            Givens steps, launch gaps */
 
 typedef struct {
     int32_t iters, restarts;
@@ -202,6 +221,8 @@ typedef struct {
     double res0;             /* ||b - A x0|| */
     double res_true;         /* ||b - A x|| recomputed at the end */
     double bnorm;            /* ||b|| */
+    double t_ms[6];          /* with opts.timing: stream time per phase (CSDYN_T_*), ms; else 0 */
+    double t_span_ms;        /* with opts.timing: stream time from the solve's first to its last launch */
 } csdyn_gmres_stats;
 
 int32_t csdyn_gmres_workspace_bytes(const csdyn_opctx *ctx, const csdyn_gmres_opts *o, size_t *bytes);
@@ -235,6 +256,7 @@ void csdyn_batch_destroy(csdyn_batch *batch);
 int32_t csdyn_residual_workspace_bytes(const csdyn_opctx *ctx, size_t *bytes);
 int32_t csdyn_residual_norm(const csdyn_opctx *ctx, const double *b, const double *x, void *ws, size_t ws_bytes,
                             void *stream, double *norm);
+
 int32_t csdyn_gmres_solve(const csdyn_opctx *ctx, const csdyn_ras *pc, const csdyn_gmres_opts *o, const double *b,
                           double *x, void *ws, size_t ws_bytes, void *stream, csdyn_gmres_stats *st);
 
@@ -252,6 +274,7 @@ typedef struct {
     int32_t box_in_lds_fine, box_in_lds_coarse; /* where the sweep keeps computed values: 0 a ring of recent
                                                    levels in device memory, 1 that ring in LDS, 2 the whole
                                                    subdomain vector in LDS */
+    int32_t threads_fine, threads_coarse;     /* workgroup size of the sweep kernel (256, 512 or 1024) */
 } csdyn_ras_info;
 int32_t csdyn_ras_get_info(const csdyn_ras *pc, csdyn_ras_info *info);
 

@@ -81,6 +81,7 @@ def lib():
         _lib.ref_pc_count.argtypes = [C.c_void_p, C.c_int]
         _lib.ref_ilu0_csr.argtypes = [C.c_int64, i64, i32, d]
         _lib.ref_subdomain_solve.argtypes = [P(Grid), P(Op), i32, C.c_int, C.c_int, d, d]
+        _lib.ref_subdomain_solve_p.argtypes = [P(Grid), P(Op), i32, C.c_int, C.c_int, C.c_int, d, d]
         _lib.ref_project.argtypes = [P(Grid), P(Op), d, d]
         _lib.ref_gmres_solve.argtypes = [P(Grid), P(Op), C.c_void_p, P(GmresOpts), d, d, P(GmresStats)]
         _lib.ref_gmres_solve_hist.argtypes = [P(Grid), P(Op), C.c_void_p, P(GmresOpts), d, d, P(GmresStats), d,
@@ -247,14 +248,15 @@ class Preconditioner:
         return gcell, owned.astype(bool), sp.csr_matrix((v, ci, rp), shape=(m, m))
 
 
-def subdomain_solve(pb: Problem, sub, s, x, overlap=1):
+def subdomain_solve(pb: Problem, sub, s, x, overlap=1, precision=0):
     """Owned part of one subdomain's ILU(0) solve, (L_s U_s)^{-1} R_s x, written into a
-    NaN-filled full vector (only subdomain s is built; for sampled checks at full size)."""
+    NaN-filled full vector (only subdomain s is built; for sampled checks at full size).
+    precision=1: FP32 factors and FP32 sweeps."""
     x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
     y = np.full_like(x, np.nan)
     sb = np.array(sub, dtype=np.int32)
-    _check(lib().ref_subdomain_solve(C.byref(pb.grid()), C.byref(pb.op()), _ip(sb), overlap, s, _dp(x), _dp(y)),
-           "subdomain_solve")
+    _check(lib().ref_subdomain_solve_p(C.byref(pb.grid()), C.byref(pb.op()), _ip(sb), overlap, s, precision, _dp(x),
+                                       _dp(y)), "subdomain_solve")
     return y.reshape(pb.shape())
 
 

@@ -1239,9 +1239,11 @@ int ref_ilu0_csr(int64_t nrow, const int64_t *rp, const int32_t *ci, double *v) 
 }
 
 /* One subdomain's local solve y_i = (L_i U_i)^{-1} R_i x at full size without
- * building the others (sampled checks): writes the owned cells of y only. */
-int ref_subdomain_solve(const ref_grid *g, const ref_op *op, const int32_t sub[3], int overlap, int s,
-                        const double *x, double *y) {
+ * building the others (sampled checks): writes the owned cells of y only.
+ * precision = 1: factors rounded to FP32 and FP32 sweeps, as in the FP32
+ * one-level preconditioner. */
+int ref_subdomain_solve_p(const ref_grid *g, const ref_op *op, const int32_t sub[3], int overlap, int s,
+                          int precision, const double *x, double *y) {
     seam_tab st; ctx cx;
     if (overlap < 0 || overlap > 1) return REF_EINVAL;
     if (sub[0] < 1 || sub[1] < 1 || sub[2] < 1 || g->n % sub[0] || g->n % sub[1] || g->nr % sub[2]) return REF_EINVAL;
@@ -1263,6 +1265,9 @@ int ref_subdomain_solve(const ref_grid *g, const ref_op *op, const int32_t sub[3
     if (!rc) {
         onelevel one = ol;
         one.sd = &all[s]; one.nsd = 1;
+        one.precision = precision == 1;
+        if (one.precision) /* factors computed in FP64, stored in FP32, as in onelevel_setup */
+            for (int64_t a = 0; a < all[s].rp[4 * (int64_t)all[s].nloc]; a++) all[s].v[a] = (double)(float)all[s].v[a];
         onelevel_apply(&one, x, y);
     }
     subdomain *d = &all[s];
@@ -1270,6 +1275,11 @@ int ref_subdomain_solve(const ref_grid *g, const ref_op *op, const int32_t sub[3
     free(all);
     free_seams(&st);
     return rc;
+}
+
+int ref_subdomain_solve(const ref_grid *g, const ref_op *op, const int32_t sub[3], int overlap, int s,
+                        const double *x, double *y) {
+    return ref_subdomain_solve_p(g, op, sub, overlap, s, 0, x, y);
 }
 
 /* Step 3 of the time step (Sec. 3.1, eq. ubtilde): from a solution x = (u~, P)

@@ -37,13 +37,18 @@ class RasOpts(C.Structure):
 
 class GmresOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("maxit", C.c_int32), ("flexible", C.c_int32),
-                ("rtol", C.c_double), ("atol", C.c_double), ("orth", C.c_int32), ("rhs_relative", C.c_int32)]
+                ("rtol", C.c_double), ("atol", C.c_double), ("orth", C.c_int32), ("rhs_relative", C.c_int32),
+                ("timing", C.c_int32)]
 
 
 class GmresStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("inner_iters", C.c_int64),
                 ("relres_true", C.c_double), ("relres_est", C.c_double), ("res0", C.c_double),
-                ("res_true", C.c_double), ("bnorm", C.c_double)]
+                ("res_true", C.c_double), ("bnorm", C.c_double), ("t_ms", C.c_double * 6),
+                ("t_span_ms", C.c_double)]
+
+# phases of GmresStats.t_ms (CSDYN_T_* in csdyn.h)
+PHASES = ("op", "pc_fine", "pc_coarse", "pc_interp", "orth", "other")
 
 
 class RasInfo(C.Structure):
@@ -52,7 +57,8 @@ class RasInfo(C.Structure):
                 ("owned_cells_fine", C.c_int64), ("owned_cells_coarse", C.c_int64), ("stored_fine", C.c_int64),
                 ("stored_coarse", C.c_int64), ("max_levels_fine", C.c_int32), ("max_levels_coarse", C.c_int32),
                 ("precision", C.c_int32), ("lds_fine", C.c_int32), ("lds_coarse", C.c_int32),
-                ("box_in_lds_fine", C.c_int32), ("box_in_lds_coarse", C.c_int32)]
+                ("box_in_lds_fine", C.c_int32), ("box_in_lds_coarse", C.c_int32), ("threads_fine", C.c_int32),
+                ("threads_coarse", C.c_int32)]
 
 
 class ConvShape(C.Structure):
@@ -274,9 +280,9 @@ class Solver:
     """Restarted (F)GMRES with a workspace kept across solves (csdyn_gmres_solve)."""
 
     def __init__(self, op: Operator, pc: RAS | None = None, restart=30, maxit=1000, flexible=False, rtol=1e-8,
-                 atol=0.0, orth=0, rhs_relative=False):
+                 atol=0.0, orth=0, rhs_relative=False, timing=False):
         self.op, self.pc = op, pc
-        self.opts = GmresOpts(restart, maxit, int(flexible), rtol, atol, orth, int(rhs_relative))
+        self.opts = GmresOpts(restart, maxit, int(flexible), rtol, atol, orth, int(rhs_relative), int(timing))
         nb = C.c_size_t()
         _check(lib().csdyn_gmres_workspace_bytes(op.h, C.byref(self.opts), C.byref(nb)),
                "csdyn_gmres_workspace_bytes")
@@ -292,6 +298,9 @@ class Solver:
         _check(rc, "csdyn_gmres_solve")
         stats = dict(iters=st.iters, restarts=st.restarts, inner_iters=st.inner_iters, relres_true=st.relres_true,
                      relres_est=st.relres_est, res0=st.res0, res_true=st.res_true, bnorm=st.bnorm)
+        if self.opts.timing:
+            stats["t_ms"] = dict(zip(PHASES, list(st.t_ms)))
+            stats["t_span_ms"] = st.t_span_ms
         return x, stats, rc
 
 

@@ -61,6 +61,9 @@ struct Gmres {
     // Enqueue Arnoldi step j + 1 before reading back step j (for solves whose
     // steps are short device work; a step enqueued past convergence is wasted)
     bool lookahead = false;
+    // Phase (profile.h) under which the preconditioner's time is recorded when
+    // the solve is timed; -1: the preconditioner records its own phases.
+    int m_phase = -1;
     T *V = nullptr, *Z = nullptr, *z = nullptr, *r = nullptr, *tmp = nullptr, *partial = nullptr, *red = nullptr;
 
     static size_t bytes(int64_t n, int m, bool flexible);

@@ -3,9 +3,10 @@
 //
 // Orthogonalisation is classical Gram-Schmidt as two bandwidth passes over
 // the basis (a multi-dot that reads w and V_0..V_j once, then a multi-update
-// that also returns ||w||^2), with a second pass when ||w|| drops below
-// 1/sqrt(2) of its value.  Reductions are wavefront shuffles, then a fixed-
-// order two-stage sum over blocks, so results are bitwise reproducible.
+// that also returns ||w||^2); orth = 1 always adds one re-orthogonalisation
+// pass (CGS2, its dot products fused into the first update pass), orth = 0
+// never does.  Reductions are wavefront shuffles, then a fixed-order two-stage
+// sum over blocks, so results are bitwise reproducible.
 #include <algorithm>
 #include <cmath>
 #include <deque>
@@ -455,7 +456,10 @@ int32_t Gmres<T>::solve(const DevFn<T> &A, const DevFn<T> *M, const T *b, T *x, 
     } depth_guard;
     std::vector<double> H(size_t(m + 1) * m, 0.0), cs(m), sn(m), gv(m + 1), yv(m);
     // r = b - A x
-    CSD_TRY(A(x, tmp, s));
+    {
+        PhaseScope ps(PH_OP, s);
+        CSD_TRY(A(x, tmp, s));
+    }
     CSD_TRY(Vec<T>::copy(r, b, n, s));
     CSD_TRY(Vec<T>::axpby(-1.0, tmp, 1.0, r, n, s));
     double beta0;
@@ -469,21 +473,36 @@ int32_t Gmres<T>::solve(const DevFn<T> &A, const DevFn<T> *M, const T *b, T *x, 
     // Gram-Schmidt (h = V^T w, then w -= V h with ||w||^2 in the same pass;
     // CGS2 re-orthogonalises once, the second dot fused into the update),
     // read-back of h and the norms, v_{j+1} = w / ||w|| from the device norms.
+    auto apply_M = [&](const T *in, T *outv) -> int32_t {
+        if (m_phase >= 0) {
+            PhaseScope ps(Phase(m_phase), s);
+            return (*M)(in, outv, s);
+        }
+        return (*M)(in, outv, s);
+    };
+    auto apply_A = [&](const T *in, T *outv) -> int32_t {
+        PhaseScope ps(PH_OP, s);
+        return A(in, outv, s);
+    };
     auto launch_step = [&](int j) -> int32_t {
         T *vj = V + size_t(j) * n, *w = V + size_t(j + 1) * n;
         T *zj = flexible ? Z + size_t(j) * n : z;
-        if (M) CSD_TRY((*M)(vj, zj, s));
+        if (M) CSD_TRY(apply_M(vj, zj));
         else CSD_TRY(Vec<T>::copy(zj, vj, n, s));
-        CSD_TRY(A(zj, w, s));
-        CSD_TRY(Vec<T>::mdot(V, n, j + 1, w, partial, red, s));
-        if (orth == 0) {
-            CSD_TRY(Vec<T>::mupdate(w, V, n, j + 1, red, partial, red + kRedStride, s));
-        } else {
-            CSD_TRY(Vec<T>::mupdate_dot(w, V, n, j + 1, red, partial, red + kRedStride, s));
-            CSD_TRY(Vec<T>::mupdate(w, V, n, j + 1, red + kRedStride, partial, red + 2 * kRedStride, s));
+        CSD_TRY(apply_A(zj, w));
+        {
+            PhaseScope ps(PH_ORTH, s);
+            CSD_TRY(Vec<T>::mdot(V, n, j + 1, w, partial, red, s));
+            if (orth == 0) {
+                CSD_TRY(Vec<T>::mupdate(w, V, n, j + 1, red, partial, red + kRedStride, s));
+            } else {
+                CSD_TRY(Vec<T>::mupdate_dot(w, V, n, j + 1, red, partial, red + kRedStride, s));
+                CSD_TRY(Vec<T>::mupdate(w, V, n, j + 1, red + kRedStride, partial, red + 2 * kRedStride, s));
+            }
         }
         CSD_HIP(hipMemcpyAsync(rb->buf[j % 2], red, sizeof(T) * nred * kRedStride, hipMemcpyDeviceToHost, s));
         CSD_HIP(hipEventRecord(rb->ev[j % 2], s));
+        PhaseScope ps(PH_ORTH, s);
         hipLaunchKernelGGL(k_scale_arnoldi<T>, ew_grid(n), dim3(256), 0, s, w, n, red + kRedStride - 1,
                            red + nred * kRedStride - 1);
         CSD_LAUNCHED();
@@ -553,11 +572,11 @@ int32_t Gmres<T>::solve(const DevFn<T> &A, const DevFn<T> *M, const T *b, T *x, 
         } else {
             CSD_TRY(Vec<T>::zero(tmp, n, s));
             CSD_TRY(Vec<T>::lincomb(tmp, V, n, jdone, yv.data(), s));
-            if (M) CSD_TRY((*M)(tmp, z, s));
+            if (M) CSD_TRY(apply_M(tmp, z));
             else CSD_TRY(Vec<T>::copy(z, tmp, n, s));
             CSD_TRY(Vec<T>::axpby(1.0, z, 1.0, x, n, s));
         }
-        CSD_TRY(A(x, tmp, s));
+        CSD_TRY(apply_A(x, tmp));
         CSD_TRY(Vec<T>::copy(r, b, n, s));
         CSD_TRY(Vec<T>::axpby(-1.0, tmp, 1.0, r, n, s));
         CSD_TRY(norm(r, beta, s));

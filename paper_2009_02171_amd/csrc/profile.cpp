@@ -54,6 +54,77 @@ ProfScope::~ProfScope() {
     hipEventRecord(g_pool[slot_].b, s_);
 }
 
+// ---------------------------------------------------------------- phases
+namespace {
+struct PhaseTimer {
+    std::vector<hipEvent_t> ev;               // event pool, reused by later timed solves on this thread
+    std::vector<std::pair<int, int>> recs;    // (phase, first event of its pair)
+    size_t used = 0;
+    int open = 0;                             // PhaseScopes currently open
+};
+thread_local PhaseTimer t_phase;
+thread_local bool t_phase_on = false;
+
+int take_events(PhaseTimer &T, int count) {
+    while (T.ev.size() < T.used + count) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return -1;
+        T.ev.push_back(e);
+    }
+    const int k = int(T.used);
+    T.used += count;
+    return k;
+}
+}  // namespace
+
+PhaseScope::PhaseScope(Phase ph, hipStream_t s) : s_(s) {
+    if (!t_phase_on) return;
+    counted_ = true;
+    if (t_phase.open++ > 0) return;  // inside another phase
+    slot_ = take_events(t_phase, 2);
+    if (slot_ < 0) return;
+    t_phase.recs.emplace_back(int(ph), slot_);
+    hipEventRecord(t_phase.ev[slot_], s_);
+}
+
+PhaseScope::~PhaseScope() {
+    if (!counted_) return;
+    --t_phase.open;
+    if (slot_ >= 0) hipEventRecord(t_phase.ev[slot_ + 1], s_);
+}
+
+int32_t phase_timer_begin(hipStream_t s) {
+    t_phase.recs.clear();
+    t_phase.used = 0;
+    t_phase.open = 0;
+    const int k = take_events(t_phase, 2);  // span start and end
+    if (k != 0) { set_error("phase timer: event creation failed"); return CSDYN_EHIP; }
+    CSD_HIP(hipEventRecord(t_phase.ev[0], s));
+    t_phase_on = true;
+    return CSDYN_OK;
+}
+
+void phase_timer_abort() { t_phase_on = false; }
+
+int32_t phase_timer_end(hipStream_t s, double t_ms[PH_COUNT + 1], double *span_ms) {
+    t_phase_on = false;
+    CSD_HIP(hipEventRecord(t_phase.ev[1], s));
+    CSD_HIP(hipEventSynchronize(t_phase.ev[1]));
+    for (int q = 0; q <= PH_COUNT; ++q) t_ms[q] = 0.0;
+    double sum = 0.0;
+    for (const auto &r : t_phase.recs) {
+        float ms = 0.f;
+        CSD_HIP(hipEventElapsedTime(&ms, t_phase.ev[r.second], t_phase.ev[r.second + 1]));
+        t_ms[r.first] += ms;
+        sum += ms;
+    }
+    float span = 0.f;
+    CSD_HIP(hipEventElapsedTime(&span, t_phase.ev[0], t_phase.ev[1]));
+    t_ms[PH_COUNT] = double(span) - sum;
+    *span_ms = span;
+    return CSDYN_OK;
+}
+
 }  // namespace csd
 
 using namespace csd;

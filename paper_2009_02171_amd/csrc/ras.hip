@@ -706,6 +706,8 @@ extern "C" int32_t csdyn_ras_setup(const csdyn_opctx *ctx, const csdyn_ras_opts 
     R->info.box_in_lds_fine = R->fine.vec ? 2 : R->fine.lds_ring;
     R->info.lds_coarse = int32_t(R->coarse.lds_bytes);
     R->info.box_in_lds_coarse = R->coarse.vec ? 2 : R->coarse.lds_ring;
+    R->info.threads_fine = R->fine.threads;
+    R->info.threads_coarse = o->levels == 2 ? R->coarse.threads : 0;
     if (stream) CSD_HIP(hipStreamSynchronize((hipStream_t)stream));
     *out = R.release();
     return CSDYN_OK;
@@ -719,48 +721,55 @@ int32_t csdyn_ras::two_level(const T *x, T *y, hipStream_t s) const {
     T *w = b0 + nf, *t = b0 + 2 * nf;
     T *rc = b0 + 4 * nf, *ec = rc + nc;
     T *G32 = ec + nc, *SF32 = G32 + size_t(24) * fine_ctx->g.nr * fine_ctx->g.n * 4;
-    // r_c = I_f^c x
-    {
-        ProfScope ps("restrict", nc, double(nf + nc) * sizeof(T), s);
-        hipLaunchKernelGGL(k_restrict<T>, grid_for(nc), dim3(256), 0, s, x, rc, nc_, nrc);
-        CSD_HIP(hipGetLastError());
-    }
-    if (fine_ctx->op.kind == CSDYN_VP) {  // coarse Neumann solvability: zero volume-weighted mean of P
-        Gmres<T> gm;
-        Carver cc(cws);
-        gm.carve(cc, nc, o.coarse_restart, false);
-        CSD_TRY(Vec<T>::pmoments(rc, coarse_ctx.dg.vol, ncell_c, gm.partial, gm.red, s));
-        T mom[kRedStride];
-        CSD_HIP(hipMemcpyAsync(mom, gm.red, sizeof(T) * kRedStride, hipMemcpyDeviceToHost, s));
-        CSD_HIP(hipStreamSynchronize(s));
-        CSD_TRY(Vec<T>::padd(rc, ncell_c, -double(mom[0]) / double(mom[1]), s));
-    }
-    // e_c ~ A_c^{-1} r_c : GMRES(coarse_restart) from 0 to coarse_rtol, coarse one-level RAS
-    CSD_TRY(Vec<T>::zero(ec, nc, s));
     Gmres<T> gm;
     Carver cc(cws);
     gm.carve(cc, nc, o.coarse_restart, false);
-    gm.lookahead = true;  // a coarse step is a few hundred microseconds of device work
-    const csdyn_opctx *cctx = &coarse_ctx;
-    DevFn<T> Ac;
-    if constexpr (sizeof(T) == 8) Ac = [cctx](const T *in, T *outv, hipStream_t st) { return op_launch(cctx, in, outv, st); };
-    else Ac = [cctx](const T *in, T *outv, hipStream_t st) { return op_launch_f32(cctx, in, outv, (float *)cctx->dg.G, (float *)cctx->dg.SF, st); };
-    const OneLevel *cl = &coarse;
-    DevFn<T> Mc = [cl](const T *in, T *outv, hipStream_t st) { return cl->apply<T>(in, outv, st); };
-    GmresResult gr;
-    int32_t rcode = gm.solve(Ac, &Mc, rc, ec, o.coarse_maxit, o.coarse_rtol, 0.0, s, gr);
-    if (rcode < 0) return rcode;
-    inner_iters += gr.iters;
-    // w = I_c^f e_c ; t = x - A_f w ; y = w + M_one^{-1} t
-    {
-        ProfScope ps("prolong", nf, double(nf + nc) * sizeof(T), s);
-        hipLaunchKernelGGL(k_prolong<T>, grid_for(nf), dim3(256), 0, s, ec, w, nc_, nrc);
-        CSD_HIP(hipGetLastError());
+    {  // r_c = I_f^c x
+        PhaseScope ph(PH_PCI, s);
+        {
+            ProfScope ps("restrict", nc, double(nf + nc) * sizeof(T), s);
+            hipLaunchKernelGGL(k_restrict<T>, grid_for(nc), dim3(256), 0, s, x, rc, nc_, nrc);
+            CSD_HIP(hipGetLastError());
+        }
+        if (fine_ctx->op.kind == CSDYN_VP) {  // coarse Neumann solvability: zero volume-weighted mean of P
+            CSD_TRY(Vec<T>::pmoments(rc, coarse_ctx.dg.vol, ncell_c, gm.partial, gm.red, s));
+            T mom[kRedStride];
+            CSD_HIP(hipMemcpyAsync(mom, gm.red, sizeof(T) * kRedStride, hipMemcpyDeviceToHost, s));
+            CSD_HIP(hipStreamSynchronize(s));
+            CSD_TRY(Vec<T>::padd(rc, ncell_c, -double(mom[0]) / double(mom[1]), s));
+        }
     }
-    if constexpr (sizeof(T) == 8) CSD_TRY(op_launch(fine_ctx, w, t, s));
-    else CSD_TRY(op_launch_f32(fine_ctx, w, t, G32, SF32, s));
-    CSD_TRY(Vec<T>::axpby(1.0, x, -1.0, t, nf, s));
-    CSD_TRY(fine.apply<T>(t, y, s));
+    {  // e_c ~ A_c^{-1} r_c : GMRES(coarse_restart) from 0 to coarse_rtol, coarse one-level RAS
+        PhaseScope ph(PH_PCC, s);
+        CSD_TRY(Vec<T>::zero(ec, nc, s));
+        gm.lookahead = true;  // a coarse step is a few hundred microseconds of device work
+        const csdyn_opctx *cctx = &coarse_ctx;
+        DevFn<T> Ac;
+        if constexpr (sizeof(T) == 8) Ac = [cctx](const T *in, T *outv, hipStream_t st) { return op_launch(cctx, in, outv, st); };
+        else Ac = [cctx](const T *in, T *outv, hipStream_t st) { return op_launch_f32(cctx, in, outv, (float *)cctx->dg.G, (float *)cctx->dg.SF, st); };
+        const OneLevel *cl = &coarse;
+        DevFn<T> Mc = [cl](const T *in, T *outv, hipStream_t st) { return cl->apply<T>(in, outv, st); };
+        GmresResult gr;
+        int32_t rcode = gm.solve(Ac, &Mc, rc, ec, o.coarse_maxit, o.coarse_rtol, 0.0, s, gr);
+        if (rcode < 0) return rcode;
+        inner_iters += gr.iters;
+    }
+    {  // w = I_c^f e_c ; t = x - A_f w
+        PhaseScope ph(PH_PCI, s);
+        {
+            ProfScope ps("prolong", nf, double(nf + nc) * sizeof(T), s);
+            hipLaunchKernelGGL(k_prolong<T>, grid_for(nf), dim3(256), 0, s, ec, w, nc_, nrc);
+            CSD_HIP(hipGetLastError());
+        }
+        if constexpr (sizeof(T) == 8) CSD_TRY(op_launch(fine_ctx, w, t, s));
+        else CSD_TRY(op_launch_f32(fine_ctx, w, t, G32, SF32, s));
+        CSD_TRY(Vec<T>::axpby(1.0, x, -1.0, t, nf, s));
+    }
+    {  // y = M_one^{-1} t
+        PhaseScope ph(PH_PCF, s);
+        CSD_TRY(fine.apply<T>(t, y, s));
+    }
+    PhaseScope ph(PH_PCI, s);  // y += w
     CSD_TRY(Vec<T>::axpby(1.0, w, 1.0, y, nf, s));
     return CSDYN_OK;
 }
@@ -772,8 +781,12 @@ int32_t ras_apply_d(const csdyn_ras *pc, const double *x, double *y, hipStream_t
     if (pc->o.precision == 0) return pc->two_level<double>(x, y, s);
     float *b0 = (float *)pc->buf;
     float *x32 = b0, *y32 = b0 + 3 * pc->nf;
-    CSD_TRY(convert_d2f(x, x32, pc->nf, s));
+    {
+        PhaseScope ph(PH_PCI, s);
+        CSD_TRY(convert_d2f(x, x32, pc->nf, s));
+    }
     CSD_TRY(pc->two_level<float>(x32, y32, s));
+    PhaseScope ph(PH_PCI, s);
     return convert_f2d(y32, y, pc->nf, s);
 }
 int ras_levels(const csdyn_ras *pc) { return pc->o.levels; }
@@ -861,6 +874,8 @@ extern "C" int32_t csdyn_gmres_solve(const csdyn_opctx *ctx, const csdyn_ras *pc
     if (o->restart < 1 || o->restart > kRedStride - 1 || o->maxit < 1) { set_error("gmres: restart in [1,32], maxit >= 1"); return CSDYN_EINVAL; }
     if (o->orth != 0 && o->orth != 1) { set_error("gmres: orth must be 0 (CGS) or 1 (CGS2)"); return CSDYN_EINVAL; }
     if (pc && pc->fine_ctx->g.n != ctx->g.n) { set_error("gmres: preconditioner built for another grid"); return CSDYN_EINVAL; }
+    if (o->rhs_relative != 0 && o->rhs_relative != 1) { set_error("gmres: rhs_relative must be 0 or 1"); return CSDYN_EINVAL; }
+    if (o->timing != 0 && o->timing != 1) { set_error("gmres: timing must be 0 or 1"); return CSDYN_EINVAL; }
     Carver c(ws);
     SolveLayout L;
     solve_layout(c, ctx, o, L);
@@ -868,6 +883,10 @@ extern "C" int32_t csdyn_gmres_solve(const csdyn_opctx *ctx, const csdyn_ras *pc
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = L.gm.n, ncell = n / 4;
     L.gm.orth = o->orth;
+    if (o->timing) CSD_TRY(phase_timer_begin(s));
+    struct TimerGuard {  // uninstalls the timer on every early return
+        ~TimerGuard() { phase_timer_abort(); }
+    } timer_guard;
     CSD_TRY(Vec<double>::copy(L.bproj, b, n, s));
     auto project = [&](double *v) -> int32_t {
         CSD_TRY(Vec<double>::pmoments(v, ctx->dg.vol, ncell, L.gm.partial, L.gm.red, s));
@@ -881,13 +900,20 @@ extern "C" int32_t csdyn_gmres_solve(const csdyn_opctx *ctx, const csdyn_ras *pc
     DevFn<double> M = [pc](const double *in, double *outv, hipStream_t st) { return ras_apply_d(pc, in, outv, st); };
     if (pc) ras_inner_iters(pc, true);
     GmresResult res;
-    if (o->rhs_relative != 0 && o->rhs_relative != 1) { set_error("gmres: rhs_relative must be 0 or 1"); return CSDYN_EINVAL; }
+    L.gm.m_phase = pc && ras_levels(pc) == 1 ? PH_PCF : -1;
     int32_t rc = L.gm.solve(A, pc ? &M : nullptr, L.bproj, x, o->maxit, o->rtol, o->atol, s, res, o->rhs_relative != 0);
-    if (rc < 0) return rc;
+    if (rc < 0) {
+        phase_timer_abort();
+        return rc;
+    }
     if (ctx->op.kind == CSDYN_VP) CSD_TRY(project(x));
+    double t_ms[PH_COUNT + 1] = {0, 0, 0, 0, 0, 0}, span = 0;
+    if (o->timing) CSD_TRY(phase_timer_end(s, t_ms, &span));
     CSD_HIP(hipStreamSynchronize(s));
     if (st) {
         std::memset(st, 0, sizeof(*st));
+        for (int q = 0; q <= PH_COUNT; ++q) st->t_ms[q] = t_ms[q];
+        st->t_span_ms = span;
         st->iters = res.iters;
         st->restarts = res.restarts;
         st->inner_iters = pc ? ras_inner_iters(pc, false) : 0;
@@ -921,16 +947,11 @@ extern "C" int32_t csdyn_residual_workspace_bytes(const csdyn_opctx *ctx, size_t
     return CSDYN_OK;
 }
 
-extern "C" int32_t csdyn_residual_norm(const csdyn_opctx *ctx, const double *b, const double *x, void *ws,
-                                       size_t ws_bytes, void *stream, double *norm) {
-    clear_error();
-    if (!ctx || !b || !x || !ws || !norm) { set_error("residual: null argument"); return CSDYN_EINVAL; }
+// ||b - A x|| with the temporaries of ResidualLayout (shared by the
+// workspace entry point and the one without a workspace).
+static int32_t residual_norm_with(const csdyn_opctx *ctx, const double *b, const double *x, const ResidualLayout &L,
+                                  hipStream_t s, double *norm) {
     const int64_t n = 24 * int64_t(ctx->g.n) * ctx->g.n * ctx->g.nr, ncell = n / 4;
-    Carver c(ws);
-    ResidualLayout L;
-    residual_layout(c, n, L);
-    if (c.off + 256 > ws_bytes) { set_error("residual: workspace %zu < %zu bytes", ws_bytes, c.off + 256); return CSDYN_ENOMEM; }
-    hipStream_t s = (hipStream_t)stream;
     CSD_TRY(Vec<double>::copy(L.r, b, n, s));
     double h[kRedStride];
     if (ctx->op.kind == CSDYN_VP) {
@@ -946,4 +967,15 @@ extern "C" int32_t csdyn_residual_norm(const csdyn_opctx *ctx, const double *b, 
     CSD_HIP(hipStreamSynchronize(s));
     *norm = std::sqrt(h[kRedStride - 1]);
     return CSDYN_OK;
+}
+
+extern "C" int32_t csdyn_residual_norm(const csdyn_opctx *ctx, const double *b, const double *x, void *ws,
+                                       size_t ws_bytes, void *stream, double *norm) {
+    clear_error();
+    if (!ctx || !b || !x || !ws || !norm) { set_error("residual: null argument"); return CSDYN_EINVAL; }
+    Carver c(ws);
+    ResidualLayout L;
+    residual_layout(c, 24 * int64_t(ctx->g.n) * ctx->g.n * ctx->g.nr, L);
+    if (c.off + 256 > ws_bytes) { set_error("residual: workspace %zu < %zu bytes", ws_bytes, c.off + 256); return CSDYN_ENOMEM; }
+    return residual_norm_with(ctx, b, x, L, (hipStream_t)stream, norm);
 }

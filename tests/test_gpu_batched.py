@@ -91,3 +91,31 @@ def test_operator_tiles_agree(tile, kind):
             assert float((y - y0).abs().max()) <= 1e-13 * float(y0.abs().max())
         else:
             assert torch.equal(y, y0)
+
+
+def test_batched_uneven_shells_match_oracle():
+    """The two smallest shells of the eight-shell batch (N = Nr = 24 and 32, their
+    own Ekman numbers and right-hand sides), solved as one batch with the FP32
+    one-level preconditioner on 8^3 boxes, against the oracle's FGMRES with its
+    FP32 preconditioner emulation."""
+    import torch
+    from paper_2009_02171_amd import csdyn
+    ops, pcs, bs, cases = [], [], [], []
+    for s, n in enumerate((24, 32)):
+        ek, b = inputs.shell_case(s, n, n)
+        cases.append((n, ek, b))
+        op = csdyn.Operator(n, n, kind=0, dt=1e-4, ekman=ek, pm=5.0)
+        ops.append(op)
+        pcs.append(csdyn.RAS(op, sub=(8, 8, 8), levels=1, precision=1))
+        bs.append(torch.from_numpy(b).cuda())
+    xs = [torch.zeros_like(b) for b in bs]
+    stats, rc = csdyn.Batch(ops, pcs, restart=30, maxit=3000, rtol=1e-8).solve(bs, xs, use_graph=True)
+    assert rc == 0
+    for (n, ek, b), x, st in zip(cases, xs, stats):
+        pb = O.Problem(n, n, kind=0, dt=1e-4, ekman=ek, pm=5.0)
+        xo, so, rco = O.gmres(pb, b, pc=O.Preconditioner(pb, sub=(8, 8, 8), levels=1, precision=1), flexible=True,
+                              rtol=1e-8, maxit=3000)
+        rel = np.linalg.norm(x.cpu().numpy() - xo) / np.linalg.norm(xo)
+        print(f"[batched vs oracle] N={n} iters {st['iters']} / {so['iters']} rel {rel:.2e}", flush=True)
+        assert rco == 0 and abs(so["iters"] - st["iters"]) <= 1
+        assert rel <= 1e-7

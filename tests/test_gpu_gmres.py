@@ -153,3 +153,35 @@ def test_two_systems_on_two_streams_match_sequential():
             assert rc == 0
             assert (it, inner) == seq[kind][1:], (kind, prec, it, inner, seq[kind][1:])
             assert torch.equal(x, seq[kind][0]), (kind, prec)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_phase_times(precision):
+    """opts.timing: the phase times cover the solve's span, the span is the solve's
+    wall time within 5%, the coarse solve (PC-C) is the largest phase of the
+    two-level preconditioner, and timing changes nothing in the result."""
+    import time
+
+    import torch
+    from paper_2009_02171_amd import csdyn
+    n, sub = 32, (8, 8, 8)
+    op = csdyn.Operator(n, n, kind=0)
+    pc = csdyn.RAS(op, sub=sub, levels=2, precision=precision)
+    b = torch.from_numpy(inputs.rhs(n, n, seed=1)).cuda()
+    plain = csdyn.Solver(op, pc, flexible=True)
+    timed = csdyn.Solver(op, pc, flexible=True, timing=True)
+    x0, st0, _ = plain.solve(b)
+    timed.solve(b)  # first timed solve on this thread creates the events
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    x1, st1, rc = timed.solve(b)
+    wall = (time.perf_counter() - t) * 1e3
+    ph = st1["t_ms"]
+    print(f"[phase times] precision={precision} wall {wall:.2f} ms span {st1['t_span_ms']:.2f} ms {ph}", flush=True)
+    assert rc == 0 and st1["iters"] == st0["iters"] and torch.equal(x0, x1)
+    assert all(v >= -1e-3 for v in ph.values())
+    assert abs(sum(ph.values()) - st1["t_span_ms"]) <= 1e-6 * st1["t_span_ms"] + 1e-6
+    assert abs(st1["t_span_ms"] - wall) <= 0.05 * wall
+    assert ph["pc_coarse"] == max(ph.values())
+    assert ph["pc_fine"] > 0 and ph["pc_interp"] > 0 and ph["op"] > 0 and ph["orth"] > 0
+    assert "t_ms" not in st0

@@ -123,3 +123,62 @@ def test_two_level_fp32_matches_oracle_emulation(kind):
     _, pc = _setup(n, nr, kind, sub, levels=2, precision=1)
     y = _apply(pc, x)
     assert np.abs(y - y_ref).max() / np.abs(y_ref).max() <= 1e-4
+
+
+def _sampled_parity(n, nr, kind, sub, precision, subdomains, tol, seed):
+    pb = O.Problem(n, nr, kind=kind)
+    x = inputs.random_field(pb.shape(), seed=seed)
+    _, pc = _setup(n, nr, kind, sub, precision=precision)
+    info = pc.info()
+    y = _apply(pc, x)
+    worst = 0.0
+    for s in subdomains:
+        ys = O.subdomain_solve(pb, sub, s, x, precision=precision)
+        m = ~np.isnan(ys)
+        assert m.sum() == 4 * sub[0] * sub[1] * sub[2]
+        worst = max(worst, np.abs(y[m] - ys[m]).max() / np.abs(ys[m]).max())
+    print(f"[ras parity, sampled] n={n} sub={sub} precision={precision} info={info} worst {worst:.2e}", flush=True)
+    assert worst <= tol
+    return info
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-5)])
+def test_coarse_level_shape_sampled(precision, tol):
+    """The coarse level of the N = Nr = 96 two-level preconditioner: N = Nr = 48
+    with 384 boxes of 12^3 (sweep with the whole box vector in LDS), sampled
+    subdomains (panel corners and edges, both walls, interior) against the
+    oracle's single-subdomain solve in the same precision."""
+    info = _sampled_parity(48, 48, 0, (12, 12, 12), precision, (0, 3, 17, 21, 42, 63, 64 + 21, 383), tol,
+                           seed=81 + precision)
+    assert info["box_in_lds_fine"] == 2 and info["threads_fine"] == 512
+
+
+@pytest.mark.parametrize("kind,precision,tol", [(0, 0, 1e-12), (1, 0, 1e-12), (0, 1, 1e-5), (1, 1, 1e-5)])
+def test_coarse_box_shape_full(kind, precision, tol):
+    """Every subdomain of N = Nr = 24 with 12^3 boxes (the coarse level's box
+    shape and kernel instance) against the oracle's full one-level apply."""
+    n, nr, sub = 24, 24, (12, 12, 12)
+    print(f"[ras parity] n={n} sub={sub} kind={kind} precision={precision}", flush=True)
+    pb = O.Problem(n, nr, kind=kind)
+    x = inputs.random_field(pb.shape(), seed=91 + kind)
+    y_ref = O.Preconditioner(pb, sub=sub, levels=1, precision=precision).apply(x)
+    _, pc = _setup(n, nr, kind, sub, precision=precision)
+    info = pc.info()
+    assert info["box_in_lds_fine"] == 2 and info["threads_fine"] == 512, info
+    y = _apply(pc, x)
+    assert np.abs(y - y_ref).max() / np.abs(y_ref).max() <= tol
+
+
+@pytest.mark.parametrize("kind,precision,tol", [(0, 0, 1e-9), (1, 0, 1e-9), (0, 1, 1e-4)])
+def test_two_level_n32_matches_oracle(kind, precision, tol):
+    """Two-level apply at N = Nr = 32 with 8^3 fine boxes (coarse N = 16, 4^3 boxes)."""
+    n, nr, sub = 32, 32, (8, 8, 8)
+    print(f"[two-level parity] n={n} kind={kind} precision={precision}", flush=True)
+    pb = O.Problem(n, nr, kind=kind)
+    x = inputs.random_field(pb.shape(), seed=101 + kind)
+    y_ref = O.Preconditioner(pb, sub=sub, levels=2, precision=precision).apply(x)
+    _, pc = _setup(n, nr, kind, sub, levels=2, precision=precision)
+    y = _apply(pc, x)
+    rel = np.abs(y - y_ref).max() / np.abs(y_ref).max()
+    print(f"[two-level parity] rel {rel:.2e}", flush=True)
+    assert rel <= tol
