@@ -257,6 +257,20 @@ int32_t csdyn_residual_workspace_bytes(const csdyn_opctx *ctx, size_t *bytes);
 int32_t csdyn_residual_norm(const csdyn_opctx *ctx, const double *b, const double *x, void *ws, size_t ws_bytes,
                             void *stream, double *norm);
 
+/* csdyn_residual_norm for callers that cannot allocate device memory (code
+ * under graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same result from the same kernels, with its temporaries (the residual,
+ * A x and the reduction partials, about 13 MB) in a static device array of
+ * the library instead of a caller workspace.  Shells of at most
+ * CSDYN_NOALLOC_MAX_CELLS cells (6 x 32^3), else CSDYN_EINVAL.  Allocates
+ * nothing (the array is part of the loaded library, one copy per GPU, kept
+ * until the process ends).  Every call on one GPU uses that GPU's array, and
+ * every call overwrites all of the array it reads, so nothing carries over;
+ * calls that overlap on one GPU (other threads or streams) race and must be
+ * serialised by the caller.  Blocks until the norm is on the host. */
+#define CSDYN_NOALLOC_MAX_CELLS 196608
+int32_t csdyn_residual_norm_noalloc(const csdyn_opctx *ctx, const double *b, const double *x, void *stream,
+                                    double *norm);
 int32_t csdyn_gmres_solve(const csdyn_opctx *ctx, const csdyn_ras *pc, const csdyn_gmres_opts *o, const double *b,
                           double *x, void *ws, size_t ws_bytes, void *stream, csdyn_gmres_stats *st);
 

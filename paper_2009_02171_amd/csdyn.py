@@ -97,6 +97,7 @@ SIGNATURES = {
     "csdyn_batch_destroy": (None, [C.c_void_p]),
     "csdyn_residual_norm": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p,
                                         _P(C.c_double)]),
+    "csdyn_residual_norm_noalloc": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, _P(C.c_double)]),
     "csdyn_gmres_solve": (C.c_int32, [C.c_void_p, C.c_void_p, _P(GmresOpts), C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_size_t, C.c_void_p, _P(GmresStats)]),
     "csdyn_ras_get_info": (C.c_int32, [C.c_void_p, _P(RasInfo)]),
@@ -356,6 +357,15 @@ class Residual:
         _check(lib().csdyn_residual_norm(self.op.h, _ptr(b), _ptr(x), _ptr(self.ws), self.nbytes, _stream(stream),
                                          C.byref(out)), "csdyn_residual_norm")
         return out.value
+
+
+def residual_norm_noalloc(op: Operator, b, x, stream=None):
+    """||b - A x|| without a workspace (csdyn_residual_norm_noalloc; shells of at most
+    6 x 32^3 cells)."""
+    out = C.c_double()
+    _check(lib().csdyn_residual_norm_noalloc(op.h, _ptr(b), _ptr(x), _stream(stream), C.byref(out)),
+           "csdyn_residual_norm_noalloc")
+    return out.value
 
 
 class Profile:

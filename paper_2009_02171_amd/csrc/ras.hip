@@ -979,3 +979,50 @@ extern "C" int32_t csdyn_residual_norm(const csdyn_opctx *ctx, const double *b, 
     if (c.off + 256 > ws_bytes) { set_error("residual: workspace %zu < %zu bytes", ws_bytes, c.off + 256); return CSDYN_ENOMEM; }
     return residual_norm_with(ctx, b, x, L, (hipStream_t)stream, norm);
 }
+
+// ------------------------------------- residual of a guess without a workspace
+// The temporaries of residual_norm_with for shells of at most
+// CSDYN_NOALLOC_MAX_CELLS cells live in this file-scope device array (one copy
+// per GPU, held until the process ends).  In host code its name is not a
+// device address: kernels receive the address hipGetSymbolAddress returns for
+// the current device.
+constexpr int64_t kNoAllocN = 4 * int64_t(CSDYN_NOALLOC_MAX_CELLS);
+constexpr size_t kNoAllocBytes = 2 * kNoAllocN * sizeof(double) + (kPartialElems + kRedStride) * sizeof(double) + 4 * 256;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[64];  // per device: the device address of `scratch`
+
+static int32_t scratch_for_current_device(void **ptr) {
+    int dev = 0;
+    CSD_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) { set_error("residual_noalloc: device %d out of range", dev); return CSDYN_EINVAL; }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        CSD_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) { set_error("residual_noalloc: no device address for the scratch array"); return CSDYN_EHIP; }
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return CSDYN_OK;
+}
+
+extern "C" int32_t csdyn_residual_norm_noalloc(const csdyn_opctx *ctx, const double *b, const double *x,
+                                               void *stream, double *norm) {
+    clear_error();
+    if (!ctx || !b || !x || !norm) { set_error("residual_noalloc: null argument"); return CSDYN_EINVAL; }
+    const int64_t ncell = 6 * int64_t(ctx->g.n) * ctx->g.n * ctx->g.nr;
+    if (ncell > CSDYN_NOALLOC_MAX_CELLS) {
+        set_error("residual_noalloc: %lld cells exceed the maximum of %d (use csdyn_residual_norm)", (long long)ncell,
+                  CSDYN_NOALLOC_MAX_CELLS);
+        return CSDYN_EINVAL;
+    }
+    void *base = nullptr;
+    CSD_TRY(scratch_for_current_device(&base));
+    Carver c(base);
+    ResidualLayout L;
+    residual_layout(c, 4 * ncell, L);
+    if (c.off > kNoAllocBytes) { set_error("residual_noalloc: scratch layout exceeds the array"); return CSDYN_EINVAL; }
+    return residual_norm_with(ctx, b, x, L, (hipStream_t)stream, norm);
+}
