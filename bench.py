@@ -23,9 +23,20 @@ before the clock starts and read after it stops.  The forms "*_two_streams"
 time the same steps with the two systems (independent of each other) solved
 at the same time, each from its own host thread on its own stream.
 
-The CPU baseline is the plain C oracle (single thread), timed on a bounded
+The default run also carries the other halves of the metric: the small
+configuration (N = Nr = 16, one-level RAS, GMRES(30)) and a bounded run of
+the learned-guess march (N = Nr = 64, 30 training and 30 evaluation steps by
+default) with plain FP64 from the previous solution against the FP32
+preconditioner from extrapolation and from the network's guess.  Per-phase
+times of one extra step of each form ("phases_ms") come from HIP events
+around the outer operator, the fine sweeps (PC-F), the coarse solve (PC-C)
+and the transfers (PC-I).
+
+The CPU baseline is the plain C oracle (single-threaded), timed on a bounded
 sample: the same two solves with the same solver and subdomain count at
-N = Nr = 32, scaled by the cell-count ratio (27x) to N = 96.
+N = Nr = 32, on one thread and as independent solves on all host cores (one
+process each), scaled to N = 96 by the cell ratio (27x) times the ratio of
+GPU to oracle iterations (outer + inner) per system.
 """
 from __future__ import annotations
 
@@ -80,33 +91,48 @@ def measured_traffic(kernel_key):
     return rec["hbm_bytes_per_launch"] if h.hexdigest() == rec["sources_sha1"] else None
 
 
+def _oracle_run(n, sub, levels, procs):
+    """The oracle's timing runner in a child process of its own (no GPU state)."""
+    import subprocess
+    r = subprocess.run([sys.executable, "-m", "oracle.baseline", "--n", str(n), "--sub", str(sub), "--levels",
+                        str(levels), "--procs", str(procs)], cwd=ROOT, capture_output=True, text=True, timeout=900)
+    if r.returncode != 0:
+        raise RuntimeError(f"oracle baseline failed: {r.stderr[-2000:]}")
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def cpu_baseline(wl_name: str, gpu_iters: dict):
-    """Oracle (plain C, one thread) on a bounded sample of the workload."""
-    import numpy as np  # noqa: F401
-    import oracle as O
-    from paper_2009_02171_amd import inputs
+    """The oracle (plain C, single-threaded) on a bounded sample of the workload:
+    the same VP and BP solves with the same solver and subdomain count at
+    N = Nr = 32, timed on one thread and as independent solves on all host cores
+    (one process per core), scaled to the full size by the cell ratio times the
+    ratio of GPU to oracle iterations (outer + inner) per system."""
     wl = WORKLOADS[wl_name]
-    if wl_name == "large":
-        n, sub = 32, (8, 8, 8)
-    else:
-        n, sub = wl["n"], wl["sub"]
-    scale = (wl["n"] / n) ** 2 * (wl["nr"] / n)
-    t_total, iters = 0.0, {}
-    for kind, seed in ((0, 1), (1, 2)):
-        pb = O.Problem(n, n, kind=kind)
-        pc = O.Preconditioner(pb, sub=sub, levels=wl["levels"])
-        b = inputs.rhs(n, n, seed)
-        t0 = time.perf_counter()
-        _, st, rc = O.gmres(pb, b, pc=pc, flexible=wl["flexible"], rtol=1e-8, maxit=2000)
-        t_total += time.perf_counter() - t0
-        iters["VP" if kind == 0 else "BP"] = [st["iters"], int(st["inner_iters"])]
-        log(f"oracle sample N={n} kind={kind}: {st['iters']} iters, {time.perf_counter() - t0:.2f} s")
-    est = t_total * scale
+    n, sub = (32, 8) if wl_name == "large" else (wl["n"], wl["sub"][0])
+    cells = (wl["n"] / n) ** 2 * (wl["nr"] / n)
+    one = _oracle_run(n, sub, wl["levels"], 1)
+    p1 = one["per_process"][0]
+    full_s, factors = 0.0, {}
+    for name in ("VP", "BP"):
+        o = p1[name]
+        it = (gpu_iters[name][0] + gpu_iters[name][1]) / (o["outer"] + o["inner"])
+        factors[name] = dict(oracle_iters=[o["outer"], o["inner"]], gpu_iters=list(gpu_iters[name]),
+                             iteration_factor=round(it, 4), sample_s=round(o["s"], 3))
+        full_s += o["s"] * cells * it
+    scale = full_s / p1["s"]  # effective sample-to-full-size factor of one VP + BP pair
+    procs = max(1, min(16, os.cpu_count() or 1))
+    many = _oracle_run(n, sub, wl["levels"], procs)
+    rate_all = 2 * procs / many["wall_s"] / scale
+    log(f"oracle N={n}: one thread {p1['s']:.2f} s per VP+BP pair; {procs} processes {many['wall_s']:.2f} s; "
+        f"scale {scale:.1f} (cells {cells:.0f} x iterations {factors})")
     return {
-        "value": 2.0 / est, "unit": "solves/s", "cores": 1, "kind": "oracle",
-        "sample": (f"VP+BP solves at N=Nr={n} with the same solver and subdomain count "
-                   f"({t_total:.2f} s measured, one thread), scaled by the cell ratio {scale:.0f}x to "
-                   f"N=Nr={wl['n']}; oracle iterations [outer, inner] {iters}, GPU at full size {gpu_iters}"),
+        "value": rate_all, "unit": "solves/s", "cores": procs, "kind": "oracle",
+        "sample": (f"VP+BP solves at N=Nr={n} ({wl['levels']}-level RAS, {sub}^3 boxes, to 1e-8), {procs} independent "
+                   f"processes on {procs} host cores ({many['wall_s']:.2f} s wall for {2 * procs} solves), scaled to "
+                   f"N=Nr={wl['n']} by the cell ratio {cells:.0f} x the per-system ratio of GPU to oracle "
+                   f"iterations (outer + inner): effective factor {scale:.1f}"),
+        "single_thread": {"value": 2.0 / full_s, "unit": "solves/s", "cores": 1, "sample_s": round(p1["s"], 3)},
+        "scaling": {"cells": cells, "systems": factors, "effective": round(scale, 2)},
         "cpu": _cpu_model(),
     }
 
@@ -134,6 +160,12 @@ def main():
                          "then cover sequential launches only)")
     ap.add_argument("--train-steps", type=int, default=100, help="learned workload: training steps")
     ap.add_argument("--eval-steps", type=int, default=100, help="learned workload: evaluation steps")
+    ap.add_argument("--learned-train-steps", type=int, default=30,
+                    help="large workload: training steps of the bounded learned-guess leg (0 with "
+                         "--learned-eval-steps 0 skips it)")
+    ap.add_argument("--learned-eval-steps", type=int, default=30,
+                    help="large workload: evaluation steps of the bounded learned-guess leg")
+    ap.add_argument("--no-small", action="store_true", help="large workload: skip the small-configuration leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the solver is single-GPU)",
@@ -207,6 +239,19 @@ def main():
             step(form)
             torch.cuda.synchronize()
             log(f"warmup {form} step {w}: {time.perf_counter() - t0:.3f} s, iters {iters[form]}")
+
+    # per-phase times of one untimed step of each form (HIP events around the outer operator, the fine
+    # sweeps, the coarse solve, the transfers and the Gram-Schmidt; the rest of the span is "other")
+    phases = {f: {} for f in forms}
+    for form in forms:
+        for name, s in state[form].items():
+            s["sol"].opts.timing = 1
+            s["x"].zero_()
+            _, st, rc = s["sol"].solve(s["b"], s["x"])
+            s["sol"].opts.timing = 0
+            phases[form][name] = {k: round(v, 3) for k, v in st["t_ms"].items()}
+            phases[form][name]["span_ms"] = round(st["t_span_ms"], 3)
+    log(f"phases (ms): {phases}")
 
     # per-kernel breakdown: one untimed plain FP64 step with every launch timed
     torch.cuda.synchronize()
@@ -308,6 +353,7 @@ def main():
                      "avg_us": round(dom["ms"] / dom["count"] * 1e3, 2),
                      "alg_bytes_per_launch": round(dom["bytes"] / dom["count"])},
         "operator": operator,
+        "phases_ms": phases,
         "kernels": kernels,
         "kernels_from": "one untimed plain FP64 step with every launch timed (share = of that step)",
     }
@@ -316,9 +362,85 @@ def main():
     if args.workload == "large":
         out["operator_n128"] = operator_rate(128, 128)
         out["hbm_copy"] = copy_rate()
+    if args.workload == "large" and not args.no_small:
+        out["small_config"] = small_leg(args)
+    if args.workload == "large" and args.learned_train_steps + args.learned_eval_steps > 0:
+        out["learned"] = learned_leg(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.workload, {k: v[:2] for k, v in iters_plain.items()})
     print(json.dumps(out))
+
+
+def small_leg(args, steps=20):
+    """The small configuration (N = Nr = 16, one-level RAS with one subdomain per
+    panel, GMRES(30), FP64): VP + BP solves, median-free mean over `steps` steps."""
+    import torch
+    from paper_2009_02171_amd import csdyn, inputs
+    wl = WORKLOADS["small"]
+    n = wl["n"]
+    sols = []
+    for kind, seed in ((csdyn.VP, 0), (csdyn.BP, 0)):
+        op = csdyn.Operator(n, n, kind=kind, dt=1e-4, ekman=1e-3, pm=5.0)
+        pc = csdyn.RAS(op, sub=wl["sub"], levels=1)
+        b = torch.from_numpy(inputs.rhs(n, n, seed)).cuda()
+        sols.append((csdyn.Solver(op, pc, restart=30, maxit=2000, rtol=1e-8), b, torch.zeros_like(b)))
+    iters = {}
+
+    def step():
+        for (sol, b, x), name in zip(sols, ("VP", "BP")):
+            x.zero_()
+            _, st, rc = sol.solve(b, x)
+            if rc != 0:
+                raise RuntimeError(f"small {name} did not converge: {st}")
+            iters[name] = st["iters"]
+
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return {"workload": wl["desc"], "solves_per_s": round(2 * steps / el, 3), "ms_per_step": round(el / steps * 1e3, 3),
+            "iters": iters, "steps": steps}
+
+
+def learned_leg(args):
+    """A bounded run of the learned-guess march (N = Nr = 64, two-level RAS on
+    16^3 boxes): train_steps steps with online training, then eval_steps steps
+    solved from every guess; solves/s per form (guess time included, training
+    time separate), iterations, and how often and how much the network's
+    correction is used."""
+    import torch
+    from paper_2009_02171_amd import march
+    wl = WORKLOADS["learned"]
+    t0 = time.perf_counter()
+    res = march.run(n=wl["n"], nr=wl["nr"], sub=wl["sub"], levels=wl["levels"], train_steps=args.learned_train_steps,
+                    eval_steps=args.learned_eval_steps, log=log)
+    torch.cuda.synchronize()
+    sp = res["solves_per_s"]
+    sysd = {}
+    for name, r in res["systems"].items():
+        sysd[name] = {v: {"iters": round(r[v]["iters_mean"], 2), "inner": round(r[v]["inner_mean"], 1),
+                          "solves_per_s": round(r[v]["solves_per_s"], 3),
+                          "res0_rel_median": r[v]["res0_rel_median"]}
+                      for v in ("plain_a", "mixed_a", "mixed_b", "mixed_c", "mixed_d")}
+        sysd[name]["net_chosen"] = f"{r['net_chosen']}/{r['mixed_c']['solves']}"
+        sysd[name]["guess_quality_median"] = r["guess_quality_median"]
+    return {
+        "workload": (f"VP+BP march N=Nr={wl['n']}, two-level RAS 384x16^3, FGMRES(30) to ||r|| <= 1e-8 ||b||; "
+                     f"{args.learned_train_steps} training steps, {args.learned_eval_steps} evaluation steps"),
+        "forms": {"plain_a (FP64 PC, previous solution)": round(sp["plain_a"], 3),
+                  "mixed_a (FP32 PC, previous solution)": round(sp["mixed_a"], 3),
+                  "mixed_b (FP32 PC, extrapolation)": round(sp["mixed_b"], 3),
+                  "mixed_c (FP32 PC, network with residual fallback)": round(sp["mixed_c"], 3),
+                  "mixed_d (FP32 PC, minimal-residual step along the network's correction)": round(sp["mixed_d"], 3)},
+        "speedup_mixed_c_vs_plain_a": round(res["speedup_mixed_c_vs_plain_a"], 3),
+        "speedup_mixed_d_vs_plain_a": round(res["speedup_mixed_d_vs_plain_a"], 3),
+        "speedup_mixed_b_vs_plain_a": round(sp["mixed_b"] / sp["plain_a"], 3),
+        "systems": sysd, "train_s": round(res["train_s"], 2), "wall_s": round(time.perf_counter() - t0, 1),
+    }
 
 
 def operator_rate(n, nr, reps=20):

@@ -372,6 +372,36 @@ int32_t csdyn_net_train_step(csdyn_net *net, const double *x2, const double *x1,
                              double *loss, void *stream);
 void csdyn_net_destroy(csdyn_net *net);
 
+/* Initial guess of the next solve from the latest two solutions x1 (newest)
+ * and x2 (the paper takes the previous solution, Sec. 3.3):
+ *   mode 0: guess = x_e = 2 x1 - x2 (linear extrapolation; net, b and ws
+ *           unused, may be NULL);
+ *   mode 1: x_n = csdyn_net_predict(net, x1, x2); guess = x_n if
+ *           ||b - A x_n|| < ||b - A x_e|| else x_e (the residual fallback);
+ *   mode 2: guess = x_e + alpha (x_n - x_e), alpha = <r_e, A d> / <A d, A d>
+ *           with r_e = b - A x_e and d = x_n - x_e: the step along the
+ *           network's correction that minimises ||b - A guess||, never
+ *           larger than ||r_e||.
+ * b is projected as the solve projects it (VP pressure part).  Modes 1 and 2
+ * apply A twice and synchronise with the host.  info (may be NULL):
+ * res_extrap = ||r_e||, res_net = ||b - A x_n||, res_guess = ||b - A guess||
+ * (modes 1, 2; -1 for mode 0), alpha (mode 1: 1 when x_n was kept, else 0).
+ * All vectors are device FP64 in the solver's layout; guess must not alias
+ * x1, x2 or b; ws: csdyn_guess_workspace_bytes, else CSDYN_ENOMEM. */
+typedef struct {
+    double res_extrap, res_net, res_guess, alpha;
+} csdyn_guess_info;
+int32_t csdyn_guess_workspace_bytes(const csdyn_opctx *ctx, size_t *bytes);
+int32_t csdyn_guess(csdyn_net *net, const csdyn_opctx *ctx, const double *b, const double *x1, const double *x2,
+                    int32_t mode, double *guess, void *ws, size_t ws_bytes, void *stream, csdyn_guess_info *info);
+
+/* Right-hand side of one step of the march that feeds the learned guess
+ * (the paper's step without its nonlinear terms, Sec. 3.1): b = (v + dt f, 0),
+ * v the projected state of the previous step (csdyn_project), f the forcing;
+ * all three in the solver's layout on the device; asynchronous. */
+int32_t csdyn_march_rhs(const csdyn_opctx *ctx, const double *v, const double *f, double dt, double *b,
+                        void *stream);
+
 /* ----------------------------------------------------------------- profile
  * Optional timing of every kernel launch by HIP events recorded on the launch
  * stream.  begin() creates a pool of max_launches event pairs; until end(),

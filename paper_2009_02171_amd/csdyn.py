@@ -66,6 +66,11 @@ class ConvShape(C.Structure):
                 ("cout", C.c_int32)]
 
 
+class GuessInfo(C.Structure):
+    _fields_ = [("res_extrap", C.c_double), ("res_net", C.c_double), ("res_guess", C.c_double),
+                ("alpha", C.c_double)]
+
+
 class ProfileEntry(C.Structure):
     _fields_ = [("name", C.c_char * 32), ("size", C.c_int64), ("count", C.c_int64), ("total_ms", C.c_double),
                 ("bytes", C.c_double), ("flops", C.c_double)]
@@ -125,6 +130,10 @@ SIGNATURES = {
     "csdyn_net_train_step": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_float,
                                          _P(C.c_double), C.c_void_p]),
     "csdyn_net_destroy": (None, [C.c_void_p]),
+    "csdyn_guess_workspace_bytes": (C.c_int32, [C.c_void_p, _P(C.c_size_t)]),
+    "csdyn_guess": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                                C.c_void_p, C.c_size_t, C.c_void_p, _P(GuessInfo)]),
+    "csdyn_march_rhs": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]),
     "csdyn_last_error": (C.c_char_p, []),
 }
 
@@ -518,3 +527,34 @@ class Net:
         h = getattr(self, "h", None)
         if h and _lib is not None:
             _lib.csdyn_net_destroy(h)
+
+
+GUESS_EXTRAPOLATE, GUESS_FALLBACK, GUESS_MINRES = 0, 1, 2
+
+
+class Guess:
+    """Initial guesses of a time march (csdyn_guess): extrapolation, the network with the
+    residual fallback, or the minimal-residual step along the network's correction."""
+
+    def __init__(self, op: Operator):
+        self.op = op
+        nb = C.c_size_t()
+        _check(lib().csdyn_guess_workspace_bytes(op.h, C.byref(nb)), "csdyn_guess_workspace_bytes")
+        self.ws = _workspace(nb.value, op.device)
+        self.nbytes = nb.value
+
+    def __call__(self, x1, x2, mode=GUESS_EXTRAPOLATE, net=None, b=None, out=None, stream=None):
+        """Returns (guess, info dict)."""
+        out = self.op.empty() if out is None else out
+        inf = GuessInfo()
+        _check(lib().csdyn_guess(net.h if net is not None else None, self.op.h, _ptr(b) if b is not None else None,
+                                 _ptr(x1), _ptr(x2), mode, _ptr(out), _ptr(self.ws), self.nbytes, _stream(stream),
+                                 C.byref(inf)), "csdyn_guess")
+        return out, {k: getattr(inf, k) for k, _ in GuessInfo._fields_}
+
+
+def march_rhs(op: Operator, v, f, dt, out=None, stream=None):
+    """b = (v + dt f, 0) on the device (csdyn_march_rhs)."""
+    out = op.empty() if out is None else out
+    _check(lib().csdyn_march_rhs(op.h, _ptr(v), _ptr(f), dt, _ptr(out), _stream(stream)), "csdyn_march_rhs")
+    return out

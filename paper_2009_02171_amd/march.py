@@ -13,13 +13,16 @@ f^n = F(r, theta, phi - n * drift):
 The solve's initial guess is one of
     (a) x^{n-1}                          (the paper's choice, Sec. 3.3)
     (b) 2 x^{n-1} - x^{n-2}              (linear extrapolation)
-    (c) the network's guess, or (b) when (b) has the smaller ||b - A x0||.
+    (c) the network's guess, or (b) when (b) has the smaller ||b - A x0||
+    (d) (b) + alpha (network's guess - (b)), alpha minimising ||b - A x0||
 Steps 1..train_steps advance with guess (b) and train one network per
 system online (Adam on a replay buffer of the latest samples); the network
 is then frozen and steps train_steps+1.. are solved from the same state with
 every guess, the FP64 preconditioner for (a) ("plain") and the FP32 one for
-(a), (b), (c); the plain solution advances the state.  Every solve must
-reach the tolerance whatever its guess.
+(a) .. (d); the plain solution advances the state.  Every solve must reach
+the tolerance whatever its guess.  Right-hand sides, guesses and the Step-3
+state come from the library (csdyn_march_rhs, csdyn_guess, csdyn_project);
+the forcing is generated on the host with the other synthetic inputs.
 """
 from __future__ import annotations
 
@@ -45,16 +48,13 @@ class _System:
                                 coarse_maxit=200, precision=p) for p in (0, 1)}
         self.sol = {p: csdyn.Solver(self.op, self.pc[p], restart=30, maxit=3000, flexible=True, rtol=1e-8,
                                     rhs_relative=True) for p in (0, 1)}
-        self.res = csdyn.Residual(self.op)
+        self.guess = csdyn.Guess(self.op)
         self.net = csdyn.Net(n, nr, torch.from_numpy(inputs.net_params(net_seed, widths)).to(dev), widths=widths)
         self.state = self.op.empty().zero_()
         self.hist = []  # latest solutions, newest last
 
     def rhs(self, f, dt):
-        b = self.state.clone()
-        b[..., :3] += dt * f[..., :3]
-        b[..., 3] = 0.0
-        return b
+        return csdyn.march_rhs(self.op, self.state, f, dt)
 
 
 def run(n=64, nr=64, sub=(16, 16, 16), levels=2, train_steps=100, eval_steps=100, train_iters=8, replay=16,
@@ -64,18 +64,17 @@ def run(n=64, nr=64, sub=(16, 16, 16), levels=2, train_steps=100, eval_steps=100
     systems = {"VP": _System(csdyn.VP, n, nr, sub, levels, dt, ekman, pm, 5, widths, dev),
                "BP": _System(csdyn.BP, n, nr, sub, levels, dt, ekman, pm, 6, widths, dev)}
     forcing = inputs.DriftingField(n, nr, forcing_seed)
-    radial = torch.from_numpy(forcing.radial).to(dev)
     rng = np.random.default_rng(forcing_seed + 1000)
 
-    def force(step):
-        a = torch.from_numpy(forcing.angular(DRIFT * step)).to(dev)
-        return torch.einsum("pjicq,kq->pkjic", a, radial).contiguous()
+    def force(step):  # synthetic input, generated on the host
+        return torch.from_numpy(forcing.field(DRIFT * step)).to(dev)
 
-    variants = ("plain_a", "mixed_a", "mixed_b", "mixed_c")
+    variants = ("plain_a", "mixed_a", "mixed_b", "mixed_c", "mixed_d")
     acc = {name: {v: dict(iters=0, inner=0, solve_s=0.0, guess_s=0.0, res0_rel=[], solves=0, relres=[])
                   for v in variants} for name in systems}
     chosen_net = {name: 0 for name in systems}
-    netd = {name: {k: [] for k in ("err_net", "err_extrap", "err_prev", "res_net", "res_extrap")} for name in systems}
+    netd = {name: {k: [] for k in ("err_net", "err_extrap", "err_prev", "res_net", "res_extrap", "res_minres",
+                                   "alpha")} for name in systems}
     div = {name: [] for name in systems}
     train_s, losses = 0.0, {name: [] for name in systems}
 
@@ -104,7 +103,7 @@ def run(n=64, nr=64, sub=(16, 16, 16), levels=2, train_steps=100, eval_steps=100
             b = s.rhs(f, dt)
             h = s.hist
             if step <= train_steps:
-                x0 = (2 * h[-1] - h[-2]) if len(h) >= 2 else (h[-1].clone() if h else torch.zeros_like(b))
+                x0 = s.guess(h[-1], h[-2])[0] if len(h) >= 2 else (h[-1].clone() if h else torch.zeros_like(b))
                 x, st, _ = solve(s, b, x0, 1)
                 advance(s, x, name, st["bnorm"])
                 if len(s.hist) >= 3:
@@ -121,23 +120,22 @@ def run(n=64, nr=64, sub=(16, 16, 16), levels=2, train_steps=100, eval_steps=100
             # evaluation: the same b^n from every guess
             A = acc[name]
             bn = None
-            xg = None
             for v in variants:
                 _sync()
                 t0 = time.perf_counter()
                 if v in ("plain_a", "mixed_a"):
                     x0 = h[-1].clone()
                 elif v == "mixed_b":
-                    x0 = 2 * h[-1] - h[-2]
+                    x0, _ = s.guess(h[-1], h[-2], csdyn.GUESS_EXTRAPOLATE)
+                elif v == "mixed_c":
+                    x0, gi = s.guess(h[-1], h[-2], csdyn.GUESS_FALLBACK, net=s.net, b=b)
+                    chosen_net[name] += int(gi["alpha"] == 1.0)
+                    netd[name]["res_net"].append(gi["res_net"])
+                    netd[name]["res_extrap"].append(gi["res_extrap"])
                 else:
-                    xe = 2 * h[-1] - h[-2]
-                    xg = s.net.predict(h[-1], h[-2])
-                    rg, re = s.res(b, xg), s.res(b, xe)
-                    if rg < re:
-                        x0 = xg
-                        chosen_net[name] += 1
-                    else:
-                        x0 = xe
+                    x0, gi = s.guess(h[-1], h[-2], csdyn.GUESS_MINRES, net=s.net, b=b)
+                    netd[name]["res_minres"].append(gi["res_guess"])
+                    netd[name]["alpha"].append(gi["alpha"])
                 _sync()
                 tg = time.perf_counter() - t0
                 x, st, el = solve(s, b, x0, 0 if v == "plain_a" else 1)
@@ -150,15 +148,16 @@ def run(n=64, nr=64, sub=(16, 16, 16), levels=2, train_steps=100, eval_steps=100
                 A[v]["relres"].append(st["res_true"] / st["bnorm"])
                 if v == "plain_a":
                     bn = x
-            # what the network's own guess gains before the fallback: its error
-            # against the solution and its residual, next to extrapolation's
+            # measurement only: the network's own guess and extrapolation against the
+            # solution (error norms) and their residuals, relative to ||b||
             nrm = float(torch.linalg.norm(bn))
-            xe = 2 * h[-1] - h[-2]
+            xe, _ = s.guess(h[-1], h[-2])
+            xg = s.net.predict(h[-1], h[-2])
             netd[name]["err_net"].append(float(torch.linalg.norm(xg - bn)) / nrm)
             netd[name]["err_extrap"].append(float(torch.linalg.norm(xe - bn)) / nrm)
             netd[name]["err_prev"].append(float(torch.linalg.norm(h[-1] - bn)) / nrm)
-            netd[name]["res_net"].append(rg / st["bnorm"])
-            netd[name]["res_extrap"].append(re / st["bnorm"])
+            for k in ("res_net", "res_extrap", "res_minres"):
+                netd[name][k][-1] /= st["bnorm"]
             advance(s, bn, name, st["bnorm"])
         if step % 10 == 0 or step == total:
             log(f"step {step}/{total} done")
@@ -188,4 +187,5 @@ def run(n=64, nr=64, sub=(16, 16, 16), levels=2, train_steps=100, eval_steps=100
         tot[v] = s_ / t_ if t_ else None
     out["solves_per_s"] = tot
     out["speedup_mixed_c_vs_plain_a"] = tot["mixed_c"] / tot["plain_a"] if tot["plain_a"] else None
+    out["speedup_mixed_d_vs_plain_a"] = tot["mixed_d"] / tot["plain_a"] if tot["plain_a"] else None
     return out

@@ -14,7 +14,7 @@ def test_march_small():
                   log=lambda m: print(m, flush=True))
     print(r)
     for name, s in r["systems"].items():
-        for v in ("plain_a", "mixed_a", "mixed_b", "mixed_c"):
+        for v in ("plain_a", "mixed_a", "mixed_b", "mixed_c", "mixed_d"):
             assert s[v]["solves"] == 4
             assert s[v]["relres_max"] <= 1.0001e-8
         assert s["face_div_rel_max"] <= 1.0001e-8
@@ -24,5 +24,65 @@ def test_march_small():
         # guess has a smaller error than extrapolation
         assert q["err_extrap"] < 0.5 * q["err_prev"]
         assert q["err_net"] < q["err_extrap"]
-        # with the fallback the learned form never starts from a larger residual
+        # with the fallback, and with the minimal-residual step, the learned forms never
+        # start from a larger residual than extrapolation
         assert s["mixed_c"]["res0_rel_median"] <= s["mixed_b"]["res0_rel_median"] * (1 + 1e-12)
+        assert s["mixed_d"]["res0_rel_median"] <= s["mixed_b"]["res0_rel_median"] * (1 + 1e-9)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_guess_modes_match_oracle(kind):
+    """csdyn_guess: extrapolation exactly; the fallback keeps the guess with the
+    smaller residual; the minimal-residual step equals the least-squares step
+    alpha = <r_e, A d> / <A d, A d> computed with the oracle's operator, and its
+    residual is the oracle's ||b - A guess||."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    from paper_2009_02171_amd import csdyn, inputs
+    n = 16
+    pb = O.Problem(n, n, kind=kind)
+    op = csdyn.Operator(n, n, kind=kind)
+    net = csdyn.Net(n, n, torch.from_numpy(inputs.net_params(9)).cuda())
+    x2 = inputs.rhs(n, n, seed=61)
+    x1 = x2 + 0.05 * inputs.rhs(n, n, seed=62)
+    b = O.apply(pb, 2 * x1 - x2 + 0.01 * inputs.rhs(n, n, seed=63))
+    t1, t2, tb = (torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (x1, x2, b))
+    g = csdyn.Guess(op)
+    xe, _ = g(t1, t2, csdyn.GUESS_EXTRAPOLATE)
+    assert torch.equal(xe, 2 * t1 - t2)
+    xn = net.predict(t1, t2).cpu().numpy()
+    bb = O.project_pressure(pb, b) if kind == 0 else b
+    re = bb - O.apply(pb, 2 * x1 - x2)
+    ad = O.apply(pb, xn - (2 * x1 - x2))
+    alpha = float((re * ad).sum() / (ad * ad).sum())
+    xm, info = g(t1, t2, csdyn.GUESS_MINRES, net=net, b=tb)
+    xm = xm.cpu().numpy()
+    print(f"[guess] kind={kind} alpha {info['alpha']:.6e} oracle {alpha:.6e} {info}", flush=True)
+    assert abs(info["alpha"] - alpha) <= 1e-9 * max(abs(alpha), 1e-3)
+    np.testing.assert_allclose(xm, 2 * x1 - x2 + alpha * (xn - (2 * x1 - x2)), rtol=0, atol=1e-12 * np.abs(xm).max())
+    rm = np.linalg.norm(bb - O.apply(pb, xm))
+    assert abs(info["res_guess"] - rm) <= 1e-7 * rm
+    assert abs(info["res_extrap"] - np.linalg.norm(re)) <= 1e-10 * np.linalg.norm(re)
+    assert info["res_guess"] <= info["res_extrap"] * (1 + 1e-12)
+    xf, inf1 = g(t1, t2, csdyn.GUESS_FALLBACK, net=net, b=tb)
+    keep_net = np.linalg.norm(bb - O.apply(pb, xn)) < np.linalg.norm(re)
+    assert inf1["alpha"] == (1.0 if keep_net else 0.0)
+    assert torch.equal(xf, torch.from_numpy(xn).cuda() if keep_net else xe)
+
+
+def test_march_rhs():
+    import numpy as np
+    import torch
+
+    from paper_2009_02171_amd import csdyn, inputs
+    op = csdyn.Operator(8, 4)
+    v = torch.from_numpy(inputs.random_field(op.shape, 1)).cuda()
+    f = torch.from_numpy(inputs.random_field(op.shape, 2)).cuda()
+    b = csdyn.march_rhs(op, v, f, 1e-4).cpu().numpy()
+    ref = v.cpu().numpy() + 1e-4 * f.cpu().numpy()
+    ref[..., 3] = 0.0
+    # the kernel may fuse v + dt f into one multiply-add (one rounding instead of two)
+    np.testing.assert_allclose(b, ref, rtol=2 * np.finfo(np.float64).eps, atol=0)
+    assert (b[..., 3] == 0).all()
