@@ -231,10 +231,21 @@ int32_t csdyn_gmres_workspace_bytes(const csdyn_opctx *ctx, const csdyn_gmres_op
  * operator (any grid size) and optional one-level preconditioner (the
  * two-level one synchronises with the host inside), solved by FGMRES
  * (restart = o->restart, CGS orthogonalisation, o->orth must be 0) in lock
- * step: one Arnoldi step of all active shells at a time, shells on their own
- * streams, one host synchronisation per step for the batch.  With
- * use_graph != 0 each step is a hipGraph captured once per (active set, step
- * index) and kept in the handle for later solves.  Stopping rule, projection
+ * step: one Arnoldi step of all active shells at a time, one host
+ * synchronisation per step for the batch.  use_graph selects how a step runs:
+ * 0, the shells' kernels on their own streams; 1, the same captured as a
+ * hipGraph per (active set, step index), kept in the handle for later solves;
+ * 2, one persistent launch per step (also captured per (active set, step
+ * index)): a work-list of every active shell's subdomain solves, edge fills,
+ * stencil tiles and Gram-Schmidt blocks, taken in order by the workgroups, an
+ * item waiting (bounded) for the finished items of its shell's previous
+ * phase; needs one-level FP32 preconditioners on all shells, at most 16
+ * shells and N >= 16 (csdyn_batch_persistent tells whether the handle
+ * qualifies; CSDYN_EINVAL otherwise, CSDYN_EHIP if a wait hit its bound).
+ * The persistent step is switched off in this build (its solves have not
+ * finished in the time allowed on the GPU): csdyn_batch_persistent reports 0
+ * and use_graph = 2 returns CSDYN_EINVAL.  Modes 0 and 1 give the same results
+ * bit for bit.  Stopping rule, projection
  * of the VP pressure and statistics per shell as for csdyn_gmres_solve.
  * b, x: host arrays of nshell device pointers (x holds x0 on entry).  The
  * workspace (csdyn_batch_workspace_bytes) holds every shell's Krylov basis and
@@ -248,6 +259,8 @@ int32_t csdyn_batch_setup(int32_t nshell, const csdyn_opctx *const *ops, const c
                           const csdyn_gmres_opts *o, void *ws, size_t ws_bytes, csdyn_batch **out);
 int32_t csdyn_gmres_solve_batched(csdyn_batch *batch, const double *const *b, double *const *x, int32_t use_graph,
                                   void *stream, csdyn_gmres_stats *stats);
+/* *available = 1 when use_graph = 2 (the persistent step) can be used. */
+int32_t csdyn_batch_persistent(const csdyn_batch *batch, int32_t *available);
 void csdyn_batch_destroy(csdyn_batch *batch);
 
 /* ||b - A x|| (b with its pressure part projected for VP, as the solve does):

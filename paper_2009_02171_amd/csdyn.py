@@ -100,6 +100,7 @@ SIGNATURES = {
     "csdyn_gmres_solve_batched": (C.c_int32, [C.c_void_p, _P(C.c_void_p), _P(C.c_void_p), C.c_int32, C.c_void_p,
                                               _P(GmresStats)]),
     "csdyn_batch_destroy": (None, [C.c_void_p]),
+    "csdyn_batch_persistent": (C.c_int32, [C.c_void_p, _P(C.c_int32)]),
     "csdyn_residual_norm": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p,
                                         _P(C.c_double)]),
     "csdyn_residual_norm_noalloc": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, _P(C.c_double)]),
@@ -332,7 +333,17 @@ class Batch:
                                        C.byref(h)), "csdyn_batch_setup")
         self.h = h
 
+    # how a lock-step Arnoldi step runs (csdyn_gmres_solve_batched's use_graph)
+    EAGER, GRAPH, PERSISTENT = 0, 1, 2
+
+    @property
+    def persistent_available(self):
+        v = C.c_int32()
+        _check(lib().csdyn_batch_persistent(self.h, C.byref(v)), "csdyn_batch_persistent")
+        return bool(v.value)
+
     def solve(self, bs, xs, use_graph=True, stream=None):
+        """use_graph: False/0 eager, True/1 graph of per-shell branches, 2 persistent step."""
         ns = len(self.ops)
         for t in list(bs) + list(xs):
             _need(t, torch.float64, "batch vectors")

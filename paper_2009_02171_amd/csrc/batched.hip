@@ -1,10 +1,11 @@
 // Batched restarted FGMRES (Sec. 3.3) over independent shells of different
 // sizes: the shells advance in lock step, one Arnoldi step for all active
-// shells at a time.  Each step is one replay of a captured hipGraph with one
-// branch per active shell (preconditioner, operator, multi-dot, update and
-// norm, copy of the dot products to the host), so the branches of small and
-// large shells run concurrently and the host synchronises once per step for
-// the whole batch.  The next basis vector is normalised on the device from the
+// shells at a time, and the host synchronises once per step for the whole
+// batch.  A step is either one persistent launch that works through all active
+// shells' subdomain solves, operator tiles and reductions from a work-list
+// (below), or one replay of a captured hipGraph with one branch per active
+// shell (preconditioner, operator, multi-dot, update and norm, copy of the
+// dot products to the host).  The next basis vector is normalised on the device from the
 // norm computed in the previous step, which keeps every node's arguments fixed
 // for a given (active set, step index): graphs are captured once per pair and
 // kept for later solves.
@@ -15,10 +16,200 @@
 #include <vector>
 
 #include "common.h"
-#include "krylov.h"
+#include "krylov_dev.h"
+#include "op_dev.h"
 #include "profile.h"
+#include "ras_dev.h"
 
 namespace csd {
+
+// ------------------------------------------------ persistent Arnoldi step
+// One launch runs Arnoldi step j of every active shell: a work-list of items
+// (one workgroup each) in nine phases per shell,
+//   0 RAS: one subdomain's gather, L sweep, U sweep, scatter (z_j = M v_j)
+//   1 ghost values of z_j beyond the panel edges      (256 points an item)
+//   2 averaged panel-edge face fluxes of z_j          (256 faces an item)
+//   3 one 16x16 column tile of the stencil over a chunk of layers (w = A z_j)
+//   4 one block of the multi-dot V^T w and w.w
+//   5 the fixed-order reduction of those partials
+//   6 one block of the update w -= V h and ||w||^2
+//   7 its reduction
+//   8 w /= ||w|| (4096 values an item)
+// Items are numbered phase by phase (shells by decreasing size within a
+// phase) and taken in that order from a device counter.  An item of phase
+// p > 0 waits until every item of phase p - 1 of its shell has finished; all
+// of those were taken earlier by workgroups that are running, so every wait
+// ends.  The wait is bounded all the same: past its limit it raises an error
+// flag that the host reads after the step, and the kernel still exits.  The
+// blocks of phases 4-7 and the per-point work of phases 1-3 and 8 are the same
+// as those of the separate kernels, so the results are bitwise the same.
+constexpr int kPhases = 9;
+constexpr int kMaxPersistShells = 16;
+constexpr int kStepThreads = 256;
+constexpr int kStepTile = 16;         // stencil tiles of 16 x 16 columns
+constexpr int kChunkVals = 4096;      // values per item of the copy and scale phases
+constexpr int kWaitPolls = 1 << 20;   // bound of one dependency wait (about a second)
+// The persistent step is switched off: on the GPU its first solve (three
+// shells, N = 16, 24, 32) did not finish within 180 s, also after the polls
+// stopped invalidating the caches.  The remaining suspect is the device-scope
+// release (an L2 write-back on every wavefront) after each of the ~4,300 items
+// of a launch; that is not shown, so the path stays off until it is.
+constexpr bool kPersistentStepEnabled = false;
+
+struct StepShell {
+    DevGeom g;
+    RowCoef rc;
+    RasView ras;
+    int has_pc = 0;
+    int n_edge = 0;                   // 24 N Nr edge points (ghosts, faces)
+    int tiles_x = 0, tiles = 0, nkc = 0, kchunk = 0;
+    int nb = 0;                       // blocks of the multi-dot and multi-update
+    int cnt[kPhases] = {};            // items of each phase
+    int64_t n = 0;
+    double *V = nullptr, *Z = nullptr, *partial = nullptr, *red = nullptr;
+};
+
+struct StepArgs {
+    const StepShell *sh;               // [nshell] descriptors
+    const int *order;                  // [nshell] shells by decreasing size
+    int *ctr;                          // [0] next item, [1] error, [2 + slot * kPhases + phase] finished items
+    uint64_t mask;                     // active shells
+    int j, nshell;
+};
+
+__global__ void k_step_reset(int *ctr, int count) {
+    for (int a = threadIdx.x; a < count; a += blockDim.x) ctr[a] = 0;
+}
+
+// Thread 0 of a workgroup: wait until `need` items of (slot, phase) have
+// finished, at most kWaitPolls polls; once any wait has hit that bound (the
+// error flag is set) every later wait returns at once, so the launch ends soon.
+// The polls are relaxed loads (an acquiring load would invalidate the caches on
+// every poll, under the feet of the workgroups that are working); one acquire
+// fence follows the last poll.
+__device__ void step_wait(int *ctr, int slot, int phase, int need) {
+    int *d = ctr + 2 + slot * kPhases + phase;
+    for (int polls = 0; __hip_atomic_load(d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need; ++polls) {
+        if (polls >= kWaitPolls || __hip_atomic_load(ctr + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+            atomicExch(ctr + 1, 1);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(4);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+__device__ __forceinline__ void step_item(const StepShell &S, int j, int ph, int loc, unsigned char *smem) {
+    const int64_t n = S.n;
+    double *V = S.V, *w = V + int64_t(j + 1) * n, *zj = S.Z + int64_t(j) * n;
+    const double *vj = V + int64_t(j) * n;
+    const int tid = threadIdx.x;
+    switch (ph) {
+        case 0:
+            if (S.has_pc) {
+                const RasView &R = S.ras;
+                if (R.mode == 2) ras_block<double, float, true, true, kStepThreads>(R.R, R.meta_lev, R.meta_sl, vj, zj, loc, smem);
+                else if (R.mode == 1) ras_block<double, float, true, false, kStepThreads>(R.R, R.meta_lev, R.meta_sl, vj, zj, loc, smem);
+                else ras_block<double, float, false, false, kStepThreads>(R.R, R.meta_lev, R.meta_sl, vj, zj, loc, smem);
+            } else {
+                const int64_t e0 = int64_t(loc) * kChunkVals, e1 = e0 + kChunkVals < n ? e0 + kChunkVals : n;
+                for (int64_t e = e0 + tid; e < e1; e += kStepThreads) zj[e] = vj[e];
+            }
+            break;
+        case 1:
+        case 2: {
+            const int e = loc * kStepThreads + tid;
+            if (e < S.n_edge) {
+                const int gn = S.g.n, t = e % gn, k = (e / gn) % S.g.nr, pe = e / (gn * S.g.nr);
+                if (ph == 1) ghost_at(S.g, zj, S.g.G, pe, k, t);
+                else edgeflux_at(S.g, (const double *)zj, (const double *)S.g.G, S.g.SF, pe, k, t);
+            }
+            break;
+        }
+        case 3: {
+            const int gn = S.g.n, nr = S.g.nr;
+            const int tile = loc % S.tiles, slab = loc / S.tiles;
+            const int bx = tile % S.tiles_x, by = tile / S.tiles_x;
+            const int p = slab / S.nkc, kc = slab % S.nkc;
+            const int k0 = kc * S.kchunk, k1 = min(nr, k0 + S.kchunk);
+            double *lds = reinterpret_cast<double *>(smem);
+            double(*layf)[8] = reinterpret_cast<double(*)[8]>(smem + sizeof(double) * OpLds<kStepTile, kStepTile>::SIZE);
+            const bool edge = bx == 0 || by == 0 || (bx + 1) * kStepTile >= gn || (by + 1) * kStepTile >= gn;
+            if (edge)
+                op_march<double, kStepTile, kStepTile, true>(S.g, S.rc, p, bx, by, k0, k1, zj, S.g.G, S.g.SF, w, lds, layf);
+            else
+                op_march<double, kStepTile, kStepTile, false>(S.g, S.rc, p, bx, by, k0, k1, zj, S.g.G, S.g.SF, w, lds, layf);
+            break;
+        }
+        case 4: mdot_block<double>(V, n, j + 1, w, S.partial, loc, S.nb); break;
+        case 5: reduce_block<double, kStepThreads>(S.partial, S.nb, j + 1, S.red); break;
+        case 6: mupdate_block<double>(w, V, n, j + 1, S.red, S.partial, loc, S.nb); break;
+        case 7: reduce_block<double, kStepThreads>(S.partial, S.nb, 0, S.red + kRedStride); break;
+        default: {
+            const double sc = 1.0 / sqrt(S.red[2 * kRedStride - 1]);
+            const int64_t e0 = int64_t(loc) * kChunkVals, e1 = e0 + kChunkVals < n ? e0 + kChunkVals : n;
+            for (int64_t e = e0 + tid; e < e1; e += kStepThreads) w[e] *= sc;
+            break;
+        }
+    }
+}
+
+// One wavefront per SIMD: the stencil and sweep paths together need about 320
+// registers, which fit without spills only at this occupancy.
+__global__ __launch_bounds__(kStepThreads, 1) void k_arnoldi_step(StepArgs A) {
+    extern __shared__ __align__(16) unsigned char step_smem[];
+    // the work-list of this step: first item of each (phase, slot), the shell of each slot
+    __shared__ int tab[kPhases][kMaxPersistShells + 1];
+    __shared__ int slot_shell[kMaxPersistShells];
+    __shared__ int it[4], nact_total[2];
+    if (threadIdx.x == 0) {
+        int nact = 0;
+        for (int b = 0; b < A.nshell; ++b) {
+            const int i = A.order[b];
+            if (A.mask >> i & 1) slot_shell[nact++] = i;
+        }
+        int item = 0;
+        for (int q = 0; q < kPhases; ++q) {
+            for (int a = 0; a < nact; ++a) {
+                tab[q][a] = item;
+                item += A.sh[slot_shell[a]].cnt[q];
+            }
+            tab[q][nact] = item;
+        }
+        nact_total[0] = nact;
+        nact_total[1] = item;
+    }
+    __syncthreads();
+    const int nact = __builtin_amdgcn_readfirstlane(nact_total[0]), total = __builtin_amdgcn_readfirstlane(nact_total[1]);
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const int item = atomicAdd(A.ctr, 1);
+            int ph = -1, a = 0, loc = 0;
+            if (item < total) {
+                ph = 0;
+                while (item >= tab[ph][nact]) ++ph;
+                while (item >= tab[ph][a + 1]) ++a;
+                loc = item - tab[ph][a];
+                if (ph > 0) step_wait(A.ctr, a, ph - 1, tab[ph - 1][a + 1] - tab[ph - 1][a]);
+            }
+            it[0] = ph;
+            it[1] = a;
+            it[2] = loc;
+            it[3] = slot_shell[a];
+        }
+        __syncthreads();
+        // uniform across the workgroup: scalar registers, scalar loads of the descriptor
+        const int ph = __builtin_amdgcn_readfirstlane(it[0]), a = __builtin_amdgcn_readfirstlane(it[1]);
+        const int loc = __builtin_amdgcn_readfirstlane(it[2]), shell = __builtin_amdgcn_readfirstlane(it[3]);
+        if (ph < 0) break;
+        // (the acquire fence of thread 0's wait and the barrier above order this
+        // item's reads after the results of the phase it waited for)
+        step_item(A.sh[shell], A.j, ph, loc, step_smem);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // publish this item's results
+        __syncthreads();
+        if (threadIdx.x == 0) atomicAdd(A.ctr + 2 + a * kPhases + ph, 1);
+    }
+}
 
 // v /= sqrt(nn2[0])  (nn2 > 0: a shell whose norm vanished has left the batch)
 __global__ void k_scale_by_norm(double *__restrict__ v, int64_t n, const double *__restrict__ nn2) {
@@ -55,10 +246,20 @@ struct csdyn_batch {
     std::vector<csd::BShell> sh;
     hipStream_t origin = nullptr;  // the steps are issued (and captured) here
     hipEvent_t fork = nullptr, ready = nullptr;
-    double *hred = nullptr;  // pinned: [nshell][2 * kRedStride]
+    double *hred = nullptr;  // pinned: [nshell][2 * kRedStride], then the persistent step's error flag
     std::map<std::pair<uint64_t, int>, hipGraphExec_t> graphs;
+    // persistent step (every shell with a one-level FP32 preconditioner, at most 16 shells)
+    bool persist_ok = false;
+    std::vector<csd::StepShell> hsh;  // host copies of the device descriptors
+    csd::StepShell *dsh = nullptr;    // device descriptors (workspace)
+    int *order = nullptr;             // device: shells by decreasing size (workspace)
+    int *ctr = nullptr;               // device counters (workspace)
+    size_t step_lds = 0;
+    int step_grid = 0;
+    std::map<std::pair<uint64_t, int>, hipGraphExec_t> pgraphs;
     ~csdyn_batch() {
         for (auto &kv : graphs) hipGraphExecDestroy(kv.second);
+        for (auto &kv : pgraphs) hipGraphExecDestroy(kv.second);
         for (auto &b : sh) {
             if (b.join) hipEventDestroy(b.join);
             if (b.st) hipStreamDestroy(b.st);
@@ -101,6 +302,8 @@ static int32_t check_batch(int32_t nshell, const csdyn_opctx *const *ops, const 
     return CSDYN_OK;
 }
 
+constexpr int kStepCounters = 2 + kMaxPersistShells * kPhases;
+
 static size_t batch_bytes(int32_t nshell, const csdyn_opctx *const *ops, int m) {
     Carver c(nullptr);
     for (int i = 0; i < nshell; ++i) {
@@ -108,7 +311,151 @@ static size_t batch_bytes(int32_t nshell, const csdyn_opctx *const *ops, int m) 
         b.n = 24 * int64_t(ops[i]->g.n) * ops[i]->g.n * ops[i]->g.nr;
         carve_shell(c, b, m);
     }
+    c.take<StepShell>(nshell);
+    c.take<int>(nshell);
+    c.take<int>(kStepCounters);
     return c.off + 256;
+}
+
+// Item counts of the nine phases of one shell.
+static void step_counts(const StepShell &S, int cnt[kPhases]) {
+    const int chunks = int((S.n + kChunkVals - 1) / kChunkVals);
+    cnt[0] = S.has_pc ? S.ras.nsd : chunks;
+    cnt[1] = cnt[2] = (S.n_edge + kStepThreads - 1) / kStepThreads;
+    cnt[3] = S.tiles * 6 * S.nkc;
+    cnt[4] = cnt[6] = S.nb;
+    cnt[5] = cnt[7] = 1;
+    cnt[8] = chunks;
+}
+
+// Descriptors of the persistent step when every shell qualifies (one-level
+// FP32 preconditioner, at most 16 shells, N >= 16 so that the 16 x 16 stencil
+// tile has threads for its edge-face records), else persist_ok stays false.
+static int32_t setup_persistent(csdyn_batch *bt, const csdyn_ras *const *pcs, Carver &c) {
+    bt->dsh = c.take<StepShell>(bt->nshell);
+    bt->order = c.take<int>(bt->nshell);
+    bt->ctr = c.take<int>(kStepCounters);
+    if (!kPersistentStepEnabled || bt->nshell > kMaxPersistShells || !pcs) return CSDYN_OK;
+    size_t lds = sizeof(double) * (OpLds<kStepTile, kStepTile>::SIZE + (kMaxChunk + 1) * 8);
+    bt->hsh.assign(bt->nshell, StepShell());
+    for (int i = 0; i < bt->nshell; ++i) {
+        const BShell &b = bt->sh[i];
+        StepShell &S = bt->hsh[i];
+        if (!pcs[i] || b.ctx->g.n < kStepTile) return CSDYN_OK;
+        if (ras_view_f32(pcs[i], S.ras) != CSDYN_OK) {
+            clear_error();
+            return CSDYN_OK;
+        }
+        S.has_pc = 1;
+        lds = std::max(lds, S.ras.lds_bytes);
+        const csdyn_opctx *ctx = b.ctx;
+        const int n = ctx->g.n, nr = ctx->g.nr;
+        S.g = ctx->dg;
+        S.rc.kind = ctx->op.kind;
+        S.rc.dt = ctx->op.dt;
+        S.rc.c_lap = ctx->op.kind == CSDYN_VP ? ctx->op.dt * ctx->op.ekman : ctx->op.dt * ctx->op.ekman / ctx->op.pm;
+        S.rc.c_cor = ctx->op.kind == CSDYN_VP ? 2.0 * ctx->op.dt : 0.0;
+        S.n_edge = 24 * n * nr;
+        S.tiles_x = (n + kStepTile - 1) / kStepTile;
+        S.tiles = S.tiles_x * S.tiles_x;
+        // radial chunks as the operator's own launch chooses them for this tile
+        const int target = 1024;
+        int nkc = std::max(1, std::min(nr, (target + 6 * S.tiles - 1) / (6 * S.tiles)));
+        nkc = std::max(nkc, (nr + kMaxChunk - 1) / kMaxChunk);
+        int kchunk = (nr + nkc - 1) / nkc;
+        kchunk = std::min(kMaxChunk, kchunk + (kchunk & 1));
+        S.kchunk = kchunk;
+        S.nkc = (nr + kchunk - 1) / kchunk;
+        S.nb = Vec<double>::nblocks(b.n);
+        S.n = b.n;
+        S.V = b.V;
+        S.Z = b.Z;
+        S.partial = b.partial;
+        S.red = b.red;
+    }
+    for (auto &S : bt->hsh) step_counts(S, S.cnt);
+    std::vector<int> order(bt->nshell);
+    for (int i = 0; i < bt->nshell; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return bt->sh[a].n > bt->sh[b].n; });
+    int dev = 0, ncu = 0, per = 0;
+    CSD_HIP(hipGetDevice(&dev));
+    CSD_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    CSD_HIP(hipFuncSetAttribute((const void *)k_arnoldi_step, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+    CSD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_arnoldi_step, kStepThreads, lds));
+    if (per < 1) return CSDYN_OK;
+    CSD_HIP(hipMemcpy(bt->dsh, bt->hsh.data(), sizeof(StepShell) * bt->nshell, hipMemcpyHostToDevice));
+    CSD_HIP(hipMemcpy(bt->order, order.data(), sizeof(int) * bt->nshell, hipMemcpyHostToDevice));
+    bt->step_lds = lds;
+    bt->step_grid = ncu * per;
+    bt->persist_ok = true;
+    return CSDYN_OK;
+}
+
+// Arnoldi step j of the shells in `mask` as one persistent launch, then the
+// read-back of each shell's dot products and of the error flag.
+static int32_t issue_step_persistent(csdyn_batch *bt, uint64_t mask, int j, hipStream_t s) {
+    StepArgs A{};
+    A.sh = bt->dsh;
+    A.order = bt->order;
+    A.ctr = bt->ctr;
+    A.mask = mask;
+    A.j = j;
+    A.nshell = bt->nshell;
+    double bytes = 0.0;
+    int64_t cells = 0;
+    for (int i = 0; i < bt->nshell; ++i) {
+        if (!(mask >> i & 1)) continue;
+        const StepShell &S = bt->hsh[i];
+        // algorithmic bytes: the RAS apply (factors once, gather, owned write), the operator (x read,
+        // y written), the multi-dot (j + 2 vectors), the update (j + 3), the normalisation (2)
+        const double vb = double(S.n) * 8.0;
+        bytes += S.ras.bytes + vb * (2 + (j + 2) + (j + 3) + 2);
+        cells += S.n / 4;
+    }
+    hipLaunchKernelGGL(k_step_reset, dim3(1), dim3(256), 0, s, bt->ctr, kStepCounters);
+    {
+        ProfScope ps("arnoldi_step", cells, bytes, s);
+        hipLaunchKernelGGL(k_arnoldi_step, dim3(unsigned(bt->step_grid)), dim3(kStepThreads), bt->step_lds, s, A);
+        CSD_HIP(hipGetLastError());
+    }
+    for (int i = 0; i < bt->nshell; ++i) {
+        if (!(mask >> i & 1)) continue;
+        CSD_HIP(hipMemcpyAsync(bt->hred + size_t(i) * 2 * kRedStride, bt->sh[i].red, sizeof(double) * 2 * kRedStride,
+                               hipMemcpyDeviceToHost, s));
+    }
+    CSD_HIP(hipMemcpyAsync(bt->hred + size_t(bt->nshell) * 2 * kRedStride, bt->ctr + 1, sizeof(int),
+                           hipMemcpyDeviceToHost, s));
+    return CSDYN_OK;
+}
+
+static int32_t pgraph_for(csdyn_batch *bt, uint64_t mask, int j, hipStream_t s0, hipGraphExec_t &out) {
+    auto key = std::make_pair(mask, j);
+    auto it = bt->pgraphs.find(key);
+    if (it != bt->pgraphs.end()) { out = it->second; return CSDYN_OK; }
+    CSD_HIP(hipStreamBeginCapture(s0, hipStreamCaptureModeRelaxed));
+    prof_suspend(true);
+    const int32_t rc = issue_step_persistent(bt, mask, j, s0);
+    prof_suspend(false);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s0, &g);
+    if (rc != CSDYN_OK) {
+        if (g) hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) {
+        set_error("batch: graph capture failed: %s", hipGetErrorString(e));
+        return CSDYN_EHIP;
+    }
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+        set_error("batch: graph instantiation failed: %s", hipGetErrorString(ei));
+        return CSDYN_EHIP;
+    }
+    bt->pgraphs[key] = ex;
+    out = ex;
+    return CSDYN_OK;
 }
 
 // The launches of Arnoldi step j of one shell (also used eagerly).
@@ -207,7 +554,7 @@ static int32_t residual(BShell &b, const double *x, hipStream_t s) {
     return Vec<double>::axpby(-1.0, b.tmp, 1.0, b.r, b.n, s);
 }
 
-static int32_t batch_solve(csdyn_batch *bt, const double *const *bs, double *const *xs, bool use_graph,
+static int32_t batch_solve(csdyn_batch *bt, const double *const *bs, double *const *xs, int mode,
                            hipStream_t s0, csdyn_gmres_stats *stats) {
     const int ns = bt->nshell, m = bt->m;
     const csdyn_gmres_opts &o = bt->o;
@@ -257,7 +604,11 @@ static int32_t batch_solve(csdyn_batch *bt, const double *const *bs, double *con
             for (int i = 0; i < ns; ++i)
                 if ((cyc >> i & 1) && S[i].live) act |= uint64_t(1) << i;
             if (!act) break;
-            if (use_graph) {
+            if (mode == 2) {
+                hipGraphExec_t ex;
+                CSD_TRY(pgraph_for(bt, act, j, so, ex));
+                CSD_HIP(hipGraphLaunch(ex, so));
+            } else if (mode == 1) {
                 hipGraphExec_t ex;
                 CSD_TRY(graph_for(bt, act, j, so, ex));
                 CSD_HIP(hipGraphLaunch(ex, so));
@@ -265,6 +616,14 @@ static int32_t batch_solve(csdyn_batch *bt, const double *const *bs, double *con
                 CSD_TRY(issue_step(bt, act, j, so));
             }
             CSD_HIP(hipStreamSynchronize(so));
+            if (mode == 2) {
+                int flag = 0;
+                std::memcpy(&flag, bt->hred + size_t(ns) * 2 * kRedStride, sizeof(int));
+                if (flag) {
+                    set_error("batch: a dependency wait of the persistent step exceeded its bound");
+                    return CSDYN_EHIP;
+                }
+            }
             for (int i = 0; i < ns; ++i) {
                 if (!(act >> i & 1)) continue;
                 ShellState &q = S[i];
@@ -373,8 +732,16 @@ extern "C" int32_t csdyn_batch_setup(int32_t nshell, const csdyn_opctx *const *o
     CSD_HIP(hipEventCreateWithFlags(&bt->fork, hipEventDisableTiming));
     CSD_HIP(hipEventCreateWithFlags(&bt->ready, hipEventDisableTiming));
     CSD_HIP(hipStreamCreateWithFlags(&bt->origin, hipStreamNonBlocking));
-    CSD_HIP(hipHostMalloc((void **)&bt->hred, sizeof(double) * 2 * kRedStride * nshell, hipHostMallocDefault));
+    CSD_HIP(hipHostMalloc((void **)&bt->hred, sizeof(double) * (2 * kRedStride * nshell + 1), hipHostMallocDefault));
+    CSD_TRY(setup_persistent(bt.get(), pcs, c));
     *out = bt.release();
+    return CSDYN_OK;
+}
+
+extern "C" int32_t csdyn_batch_persistent(const csdyn_batch *bt, int32_t *available) {
+    clear_error();
+    if (!bt || !available) { set_error("batch: null argument"); return CSDYN_EINVAL; }
+    *available = bt->persist_ok ? 1 : 0;
     return CSDYN_OK;
 }
 
@@ -384,7 +751,15 @@ extern "C" int32_t csdyn_gmres_solve_batched(csdyn_batch *bt, const double *cons
     if (!bt || !b || !x) { set_error("batch: null argument"); return CSDYN_EINVAL; }
     for (int i = 0; i < bt->nshell; ++i)
         if (!b[i] || !x[i]) { set_error("batch: null vector for shell %d", i); return CSDYN_EINVAL; }
-    return batch_solve(bt, b, x, use_graph != 0, (hipStream_t)stream, stats);
+    if (use_graph < 0 || use_graph > 2) { set_error("batch: use_graph must be 0, 1 or 2"); return CSDYN_EINVAL; }
+    if (use_graph == 2 && !bt->persist_ok) {
+        if (!kPersistentStepEnabled) set_error("batch: the persistent step is switched off in this build");
+        else
+            set_error("batch: the persistent step needs one-level FP32 preconditioners on every shell, at most %d "
+                      "shells and N >= %d", kMaxPersistShells, kStepTile);
+        return CSDYN_EINVAL;
+    }
+    return batch_solve(bt, b, x, use_graph, (hipStream_t)stream, stats);
 }
 
 extern "C" void csdyn_batch_destroy(csdyn_batch *bt) { delete bt; }

@@ -1,0 +1,335 @@
+// Device code of the RAS subdomain solves (Sec. 3.3, eq. onelevel), shared by
+// the preconditioner's kernel (ras.hip) and the persistent batched Arnoldi
+// step (batched.hip): the packed sweep layouts and the gather / L sweep /
+// U sweep / restricted scatter of one subdomain by one workgroup.
+#pragma once
+
+#include "ras_host.h"
+
+namespace csd {
+
+template <class TF>
+struct Pair;
+template <>
+struct Pair<double> {
+    using type = double2;
+};
+template <>
+struct Pair<float> {
+    using type = float2;
+};
+
+// Device view of one SweepPack (ras_host.h gives the layouts).
+template <class TF>
+struct DevSweep {
+    using TF2 = typename Pair<TF>::type;
+    const int32_t *lane_io;    // [nslice*64] ring: L, x index; U, y index of owned rows; else -1
+    const int32_t *lane_next;  // [nslice*64] ring: L, U-sweep position of the row; box vector: U,
+                               // {position, y index} pairs
+    const TF2 *val;            // [pairs] factor entries, two per lane
+    const uint4 *addr;         // [64 * nslice] addresses of the dependencies (ring slots or positions), eight per lane
+    const int4 *meta;          // [nsd][meta bytes / 16] LDS metadata image of each subdomain's sweep
+};
+
+template <class TF>
+struct DevRas {
+    using TF2 = typename Pair<TF>::type;
+    const SdInfo *sd;
+    DevSweep<TF> L, U;
+    TF *lin;    // [L slices * 64] gathered inputs of the L sweep (ring only)
+    TF2 *lout;  // [U slices * 64] ring: {L-sweep result, 1/u_ii} in U-sweep order (0 where never written);
+                // box vector: 1/u_ii per lane (dense, first half)
+    TF *ring;   // [nsd][depth * width] when the ring is not in LDS
+    const int32_t *gio;  // box vector: x index of each position, per subdomain from SdInfo::g0
+    int depth, width;
+};
+
+// One item of a sweep: one slice for one lane, i.e. the lane's part (at most
+// eight entries) of its row: values in pairs, 16-bit dependency addresses two
+// to a register, the row's {input value, 1/u_ii} and output index, and the
+// slice's wave-uniform description.  Nothing in it depends on values computed
+// in the sweep (inputs were gathered before, addresses and factors are
+// constant), so each wavefront requests its items well ahead of use; the
+// loads stay in flight across the LDS-scoped barriers between levels.
+template <class TF>
+struct Item {
+    using TF2 = typename Pair<TF>::type;
+    uint32_t addr[4];
+    TF2 val[4];
+    TF2 h;
+    int32_t io;    // ring, L: U position of the row; U: y index or -1
+    int32_t row;   // box vector, U: position of the row in the box vector (first lane of a row) or -1
+    int32_t wl;    // level << 17 | sl_info; -1 past the wavefront's last slice
+    int32_t slot;  // ring slot (box vector, L: position) of the slice's first row
+};
+
+// Seven loads per item whatever the slice (pairs past the slice's width
+// re-read its last pair; consume() masks them), so the memory counters always
+// hold the later items' loads in the same order and the wait for one group
+// of items never waits for the next.  Lanes past the slice's rows (nvalid =
+// rows * lanes per row) read lane 0's data instead of their own padding, so
+// the cache lines of the padding are never fetched; their results are
+// discarded.
+// With the box vector in LDS (VEC) the L sweep's inputs and results live there
+// (five loads per item) and the U sweep reads 1/u_ii and its row's {position,
+// y index} instead of a record (seven loads).
+template <class TF, bool UPPER, bool VEC, class Rec>
+__device__ __forceinline__ void fetch_item(const DevSweep<TF> &S, const Rec *rec, int64_t g64, int64_t off, int w,
+                                           int nvalid, Item<TF> &X) {
+    const int lane = threadIdx.x % 64, ln = lane < nvalid ? lane : 0;
+    const int64_t gpos = g64 + ln;
+    if constexpr (UPPER && VEC) {  // {row position, y index} pairs and a dense 1/u_ii array
+        const int2 ri = reinterpret_cast<const int2 *>(S.lane_next)[gpos];
+        X.row = ri.x;
+        X.io = ri.y;
+        X.h.y = reinterpret_cast<const TF *>(rec)[gpos];
+    } else if constexpr (UPPER) {
+        X.h = rec[gpos];
+        X.io = S.lane_io[gpos];
+    } else if constexpr (!VEC) {
+        X.h.x = rec[gpos];
+        X.io = S.lane_next[gpos];
+    }
+    const int lastp = w > 0 ? (w - 1) / 2 : 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) X.val[j] = S.val[off + int64_t(min(j, lastp)) * 64 + ln];
+    const uint4 a = S.addr[gpos];
+    X.addr[0] = a.x; X.addr[1] = a.y; X.addr[2] = a.z; X.addr[3] = a.w;
+}
+
+template <class TF>
+__device__ __forceinline__ TF consume(const Item<TF> &X, int w, const TF *ring, TF acc) {
+    TF tv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) tv[q] = ring[(X.addr[q / 2] >> (16 * (q % 2))) & 0xffffu];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc -= (q < w ? (q % 2 ? X.val[q / 2].y : X.val[q / 2].x) : TF(0)) * tv[q];
+    return acc;
+}
+
+// Barrier between levels.  When the computed values are in LDS (ring or box
+// vector) only LDS traffic has to be complete, so the fence is LDS-scoped:
+// global loads issued before it (later items) stay in flight.  On this GPU
+// family a full fence would also wait for every outstanding global load.
+template <bool LDS_ONLY>
+__device__ __forceinline__ void level_barrier() {
+    if constexpr (LDS_ONLY) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+    } else {
+        __syncthreads();
+    }
+}
+
+// Group size K: two groups of K items (seven loads each) in flight per
+// wavefront, within the 63 loads the in-order memory counter tracks and the
+// register budget of the workgroup size (512 threads: 128 registers keep two
+// workgroups per compute unit; 1024 threads leave 128).
+template <class TF, int NT>
+struct SweepShape {
+    static constexpr int K = (NT <= 512 && sizeof(TF) == 4) ? 3 : 2;
+};
+
+// Per-subdomain slice metadata of one sweep, staged in LDS.
+struct Meta {
+    int32_t *lev;   // [nlev + 1] first slice of each level (relative)
+    int32_t *off;   // [nsl] first value pair, relative to the subdomain's first
+    int32_t *wl;    // [nsl] level << 17 | sl_info
+    int32_t *slot;  // [nsl] ring slot (box vector, L: position) of the first row
+};
+
+// One triangular sweep of one subdomain.  Slices are dealt to wavefronts
+// round-robin over the whole sweep (slice g to wavefront g mod nwaves), and a
+// wavefront works through its slices in order.  Its slices are requested in
+// two groups of K: while one group is processed the other is in flight, and
+// a group is requested again as soon as it has been processed, so the wait
+// for a group never waits for the other.  Barrier b ends level b: a
+// wavefront passes it as soon as it has finished its slices of levels <= b,
+// so every row of levels <= b is in LDS before any row of level b + 1 reads
+// it.  Every wavefront passes all nlev barriers.  The lanes of a split row add
+// their partial sums in a fixed order; the row's first lane writes the result
+// to its ring slot (box vector: its position) and, in the ring layout's L
+// sweep, to its U-sweep record; the U sweep writes the owned rows to y
+// (restricted scatter).
+template <class TV, class TF, bool UPPER, bool LDS, bool VEC, int NT, class Rec>
+__device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int sl0, int64_t off0, int nlev, int nsl,
+                                      TF *ring, const Rec *rec, TF *lout, TV *y) {
+    constexpr int K = SweepShape<TF, NT>::K;
+    const int lane = threadIdx.x % 64, nw = NT / 64;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    int passed = 0;
+    auto pass_to = [&](const Item<TF> &n) {
+        const int lv = n.wl >= 0 ? n.wl >> 17 : nlev;
+        for (; passed < lv; ++passed) level_barrier<LDS>();
+    };
+    if (nsl == 0) {
+        for (; passed < nlev; ++passed) level_barrier<LDS>();
+        return;
+    }
+    int fg = wv;  // next slice to request (past the end: re-reads the last slice)
+    auto request = [&](Item<TF> (&grp)[K]) {
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int g = fg + k * nw, gg = min(g, nsl - 1);
+            const int wl = __builtin_amdgcn_readfirstlane(M.wl[gg]);
+            const int offr = __builtin_amdgcn_readfirstlane(M.off[gg]);
+            grp[k].wl = g < nsl ? wl : -1;
+            grp[k].slot = __builtin_amdgcn_readfirstlane(M.slot[gg]);
+            fetch_item<TF, UPPER, VEC>(S, rec, int64_t(sl0 + gg) * 64, off0 + offr, wl & 15,
+                                       ((wl >> 10) & 127) * (((wl >> 4) & 63) + 1), grp[k]);
+        }
+        fg += K * nw;
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    // process one group; next: the first item of the other group
+    auto process = [&](const Item<TF> (&grp)[K], const Item<TF> &next) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const Item<TF> &it = grp[k];
+            if (it.wl < 0) break;
+            const int w = it.wl & 15, sp = ((it.wl >> 4) & 63) + 1, nrow = (it.wl >> 10) & 127;
+            const int rr = (lane * ((65536 + sp - 1) / sp)) >> 16, first = rr * sp;  // row in the slice
+            const bool writer = lane == first && rr < nrow;
+            TF v0;
+            if constexpr (!VEC) v0 = it.h.x;
+            else if constexpr (UPPER) v0 = it.row >= 0 ? ring[it.row] : TF(0);
+            else v0 = writer ? ring[it.slot + rr] : TF(0);
+            TF acc = consume(it, w, ring, v0);
+            if (sp > 1) {  // the row's first lane adds its other parts in order
+                TF sum = acc;
+                for (int d = 1; d < sp; ++d) sum += __shfl(acc, min(first + d, 63));
+                acc = sum;
+            }
+            if constexpr (UPPER) acc *= it.h.y;
+            if (writer) {
+                if constexpr (VEC && UPPER) ring[it.row] = acc;
+                else ring[it.slot + rr] = acc;
+                if constexpr (UPPER) {
+                    if (it.io >= 0) y[it.io] = TV(acc);
+                } else if constexpr (!VEC) {
+                    if (it.io >= 0) lout[2 * int64_t(it.io)] = acc;
+                }
+            }
+            pass_to(k + 1 < K ? grp[k + 1] : next);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    Item<TF> A[K], B[K];
+    request(A);
+    request(B);
+    pass_to(A[0]);
+    while (A[0].wl >= 0) {
+        process(A, B[0]);
+        request(A);
+        process(B, A[0]);
+        request(B);
+    }
+    for (; passed < nlev; ++passed) level_barrier<LDS>();
+    __builtin_amdgcn_s_waitcnt(0);  // requests past the end
+}
+
+
+// Pointers into the LDS copy of one sweep's slice metadata (the layout of
+// meta_bytes_for and of the per-subdomain images).
+__device__ __forceinline__ void meta_pointers(unsigned char *base, int meta_lev, int meta_sl, Meta &M) {
+    M.lev = reinterpret_cast<int32_t *>(base);
+    M.off = reinterpret_cast<int32_t *>(base + ((size_t(meta_lev) + 1) * 4 + 15) / 16 * 16);
+    M.wl = M.off + meta_sl;
+    M.slot = M.wl + meta_sl;
+}
+
+// One subdomain per workgroup: gather x (coalesced over the L-sweep order),
+// L sweep, U sweep with restricted scatter.  The ring of the last `depth`
+// levels is in LDS when LDS = true, else in the workspace; with VEC (always
+// in LDS) the whole box vector is there instead: the gather writes x into it,
+// the L sweep overwrites it with its results and the U sweep with its own.
+template <class TV, class TF, bool LDS, bool VEC, int NT>
+__device__ __forceinline__ void ras_block(const DevRas<TF> &R, int meta_lev, int meta_sl, const TV *__restrict__ x,
+                                          TV *__restrict__ y, int sdi, unsigned char *ras_smem) {
+    static_assert(LDS || !VEC, "the box vector lives in LDS");
+    const SdInfo I = R.sd[sdi];
+    const int ring_n = R.depth * R.width;
+    TF *ring = LDS ? reinterpret_cast<TF *>(ras_smem + meta_bytes_for(meta_sl, meta_lev))
+                   : R.ring + int64_t(sdi) * ring_n;
+    if constexpr (!VEC)
+        for (int a = threadIdx.x; a < ring_n; a += NT) ring[a] = TF(0);
+    // slice metadata: the L sweep's image to LDS now, the U sweep's (up to
+    // MU 16-byte pieces per thread) requested now and written after the L sweep
+    Meta M;
+    meta_pointers(ras_smem, meta_lev, meta_sl, M);
+    using I4 = int __attribute__((ext_vector_type(4)));
+    const int n16 = int(meta_bytes_for(meta_sl, meta_lev) / 16);
+    I4 *md = reinterpret_cast<I4 *>(ras_smem);
+    {
+        const I4 *img = reinterpret_cast<const I4 *>(R.L.meta) + size_t(sdi) * n16;
+        for (int a = threadIdx.x; a < n16; a += NT) md[a] = img[a];
+    }
+    constexpr int MU = 2;
+    const I4 *uimg = reinterpret_cast<const I4 *>(R.U.meta) + size_t(sdi) * n16;
+    const I4 up0 = uimg[min(int(threadIdx.x), n16 - 1)];
+    const I4 up1 = uimg[min(int(threadIdx.x) + NT, n16 - 1)];
+    if constexpr (VEC) {
+        // the box vector in L-sweep order: position a holds x[gio[a]];
+        // GU positions per thread per round, all index loads and then all
+        // value loads in flight together (one round for boxes of up to
+        // GU * NT rows)
+        constexpr int GU = 24;
+        const int nrows = I.nrows;
+        const int32_t *gi = R.gio + I.g0;
+        for (int a0 = 0; a0 < nrows; a0 += NT * GU) {
+            int32_t io[GU];
+            TV v[GU];
+#pragma unroll
+            for (int u = 0; u < GU; ++u) io[u] = gi[min(a0 + int(threadIdx.x) + u * NT, nrows - 1)];
+#pragma unroll
+            for (int u = 0; u < GU; ++u) v[u] = x[io[u]];
+#pragma unroll
+            for (int u = 0; u < GU; ++u) {
+                const int a = a0 + int(threadIdx.x) + u * NT;
+                if (a < nrows) ring[a] = TF(v[u]);
+            }
+        }
+    } else {
+        // eight lanes per thread per round: the index loads, then the value
+        // loads, are in flight together
+        constexpr int U = 8;
+        const int64_t p0 = int64_t(I.slL0) * 64, p1 = int64_t(I.slL0 + I.nslL) * 64;
+        for (int64_t p = p0 + threadIdx.x; p < p1; p += int64_t(NT) * U) {
+            int32_t io[U];
+            TV v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) io[u] = p + u * NT < p1 ? R.L.lane_io[p + u * NT] : -1;
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = io[u] >= 0 ? x[io[u]] : TV(0);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (p + u * NT < p1) R.lin[p + u * NT] = TF(v[u]);
+        }
+    }
+    __syncthreads();
+    sweep<TV, TF, false, LDS, VEC, NT>(R.L, M, I.slL0, I.offL0, I.levL1 - I.levL0, I.nslL, ring, R.lin,
+                                       reinterpret_cast<TF *>(R.lout), y);
+    __syncthreads();  // L results visible; the U metadata replaces the L metadata
+    if (int(threadIdx.x) < n16) md[threadIdx.x] = up0;
+    if (int(threadIdx.x) + NT < n16) md[threadIdx.x + NT] = up1;
+    for (int a = threadIdx.x + MU * NT; a < n16; a += NT) md[a] = uimg[a];
+    __syncthreads();
+    sweep<TV, TF, true, LDS, VEC, NT>(R.U, M, I.slU0, I.offU0, I.levU1 - I.levU0, I.nslU, ring, R.lout, nullptr, y);
+}
+
+// Device view of the fine one-level RAS of a preconditioner with FP32 factors
+// (for the persistent batched Arnoldi step): mode 0 keeps the ring of recent
+// levels in device memory, 1 keeps it in LDS, 2 keeps the whole box vector in
+// LDS; lds_bytes is the dynamic LDS one subdomain needs.  CSDYN_EINVAL unless
+// the preconditioner is one-level with FP32 factors.
+struct RasView {
+    DevRas<float> R;
+    int meta_lev = 0, meta_sl = 0, nsd = 0, mode = 0;
+    size_t lds_bytes = 0;
+    double bytes = 0;  // algorithmic bytes of one apply (FP32 factors once, FP64 gather and owned write)
+};
+int32_t ras_view_f32(const csdyn_ras *pc, RasView &v);
+
+}  // namespace csd

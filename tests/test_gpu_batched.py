@@ -93,11 +93,74 @@ def test_operator_tiles_agree(tile, kind):
             assert torch.equal(y, y0)
 
 
+PSHELLS = [(16, 0.0003), (24, 0.0001), (32, 0.0005)]  # (N = Nr, Ekman number), all N >= 16
+
+
+PERSISTENT_OFF = ("the persistent step is switched off: its first solve did not finish within 180 s on the GPU "
+                  "(twice, the second time with relaxed polls); the cause is not shown")
+
+
+@pytest.mark.skip(reason=PERSISTENT_OFF)
+@pytest.mark.parametrize("kind", [0, 1])
+def test_persistent_step_matches_eager(kind):
+    """One persistent launch per Arnoldi step (work-list of every shell's subdomain
+    solves, edge fills, stencil tiles and Gram-Schmidt blocks) gives the eager
+    batch's iterations and solutions bit for bit, on two solves in a row (the
+    second reuses the captured step graphs)."""
+    import torch
+    from paper_2009_02171_amd import csdyn
+    ops, pcs, bs = [], [], []
+    for s, (n, ek) in enumerate(PSHELLS):
+        op = csdyn.Operator(n, n, kind=kind, dt=1e-4, ekman=ek, pm=5.0)
+        ops.append(op)
+        pcs.append(csdyn.RAS(op, sub=(8, 8, 8), levels=1, precision=1))
+        bs.append(torch.from_numpy(inputs.rhs(n, n, seed=200 + s)).cuda())
+    batch = csdyn.Batch(ops, pcs, restart=30, maxit=2000, rtol=1e-8)
+    assert batch.persistent_available
+    xe = [torch.zeros_like(b) for b in bs]
+    se, rc = batch.solve(bs, xe, use_graph=csdyn.Batch.EAGER)
+    assert rc == 0
+    for rep in range(2):
+        print(f"[persistent] kind={kind} solve {rep}", flush=True)
+        xp = [torch.zeros_like(b) for b in bs]
+        sp, rc = batch.solve(bs, xp, use_graph=csdyn.Batch.PERSISTENT)
+        assert rc == 0
+        for a, b, sa, sb in zip(xe, xp, se, sp):
+            assert sa["iters"] == sb["iters"], (sa, sb)
+            assert torch.equal(a, b), float((a - b).abs().max())
+            assert sb["res_true"] <= 1.0001e-8 * sb["res0"]
+
+
+def test_persistent_step_is_switched_off():
+    """While it is off, no handle offers the persistent step and asking for it is an error."""
+    import torch
+    from paper_2009_02171_amd import csdyn
+    op = csdyn.Operator(16, 16)
+    pc = csdyn.RAS(op, sub=(8, 8, 8), levels=1, precision=1)
+    b = csdyn.Batch([op], [pc])
+    assert not b.persistent_available
+    with pytest.raises(csdyn.CsdynError):
+        b.solve([op.empty().zero_()], [op.empty().zero_()], use_graph=csdyn.Batch.PERSISTENT)
+
+
+@pytest.mark.skip(reason=PERSISTENT_OFF)
+def test_persistent_step_needs_fp32_one_level():
+    from paper_2009_02171_amd import csdyn
+    op = csdyn.Operator(16, 16)
+    pc64 = csdyn.RAS(op, sub=(8, 8, 8), levels=1, precision=0)
+    b = csdyn.Batch([op], [pc64])
+    assert not b.persistent_available
+    import torch
+    x = [op.empty().zero_()]
+    with pytest.raises(csdyn.CsdynError):
+        b.solve([op.empty().zero_()], x, use_graph=csdyn.Batch.PERSISTENT)
+
+
 def test_batched_uneven_shells_match_oracle():
     """The two smallest shells of the eight-shell batch (N = Nr = 24 and 32, their
     own Ekman numbers and right-hand sides), solved as one batch with the FP32
-    one-level preconditioner on 8^3 boxes, against the oracle's FGMRES with its
-    FP32 preconditioner emulation."""
+    one-level preconditioner on 8^3 boxes (graph of per-shell branches), against
+    the oracle's FGMRES with its FP32 preconditioner emulation."""
     import torch
     from paper_2009_02171_amd import csdyn
     ops, pcs, bs, cases = [], [], [], []
@@ -109,7 +172,8 @@ def test_batched_uneven_shells_match_oracle():
         pcs.append(csdyn.RAS(op, sub=(8, 8, 8), levels=1, precision=1))
         bs.append(torch.from_numpy(b).cuda())
     xs = [torch.zeros_like(b) for b in bs]
-    stats, rc = csdyn.Batch(ops, pcs, restart=30, maxit=3000, rtol=1e-8).solve(bs, xs, use_graph=True)
+    batch = csdyn.Batch(ops, pcs, restart=30, maxit=3000, rtol=1e-8)
+    stats, rc = batch.solve(bs, xs, use_graph=True)
     assert rc == 0
     for (n, ek, b), x, st in zip(cases, xs, stats):
         pb = O.Problem(n, n, kind=0, dt=1e-4, ekman=ek, pm=5.0)
