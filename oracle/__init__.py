@@ -79,6 +79,10 @@ def lib():
         _lib.ref_pc_apply.argtypes = [C.c_void_p, d, d]
         _lib.ref_pc_subdomain.argtypes = [C.c_void_p, C.c_int, C.c_int, i64, i64, i64, i32, i64, i32, d]
         _lib.ref_pc_count.argtypes = [C.c_void_p, C.c_int]
+        _lib.ref_pc_inner.argtypes = [C.c_void_p]
+        _lib.ref_pc_inner.restype = C.c_void_p
+        _lib.ref_pc_inner_iters.argtypes = [C.c_void_p]
+        _lib.ref_pc_inner_iters.restype = C.c_int64
         _lib.ref_ilu0_csr.argtypes = [C.c_int64, i64, i32, d]
         _lib.ref_subdomain_solve.argtypes = [P(Grid), P(Op), i32, C.c_int, C.c_int, d, d]
         _lib.ref_subdomain_solve_p.argtypes = [P(Grid), P(Op), i32, C.c_int, C.c_int, C.c_int, d, d]
@@ -204,7 +208,9 @@ def assemble(pb: Problem):
 
 
 class Preconditioner:
-    """One-level RAS / two-level hybrid RAS with ILU(0) (Sec. 3.3)."""
+    """One-level RAS / two-level hybrid RAS with ILU(0) (Sec. 3.3); levels=3 repeats the
+    hybrid construction on the coarse grid (its coarse solve is FGMRES preconditioned by
+    the coarse grid's own two-level hybrid, with sub/4 boxes on the coarsest grid)."""
 
     def __init__(self, pb: Problem, sub=(4, 4, 4), overlap=1, levels=1, coarse_rtol=0.1,
                  coarse_restart=30, coarse_maxit=200, precision=0):
@@ -230,6 +236,22 @@ class Preconditioner:
 
     def count(self, coarse=False):
         return lib().ref_pc_count(self.h, int(coarse))
+
+    def inner_iters(self):
+        """Coarse-solve iterations accumulated by apply() calls since the last solve started."""
+        return lib().ref_pc_inner_iters(self.h)
+
+    def inner_apply(self, x):
+        """levels=3: the coarse grid's two-level hybrid applied to a coarse-grid vector."""
+        ih = lib().ref_pc_inner(self.h)
+        if not ih:
+            raise ValueError("no inner preconditioner (levels < 3)")
+        pc = Problem(self.pb.n // 2, self.pb.nr // 2, self.pb.kind, self.pb.dt, self.pb.ekman, self.pb.pm, self.pb.ri,
+                     self.pb.ro)
+        x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
+        y = np.zeros_like(x)
+        lib().ref_pc_apply(C.c_void_p(ih), _dp(x), _dp(y))
+        return y.reshape(pc.shape())
 
     def subdomain(self, s, coarse=False):
         """Local cells, owned flags and the ILU(0) factors (L strictly lower, U upper) as CSR."""

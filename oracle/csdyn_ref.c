@@ -831,7 +831,7 @@ static void csr_mv(const csr *a, const double *x, double *y) {
 
 typedef struct ref_pc ref_pc;
 struct ref_pc {
-    int levels;                 /* 0 none, 1 one-level, 2 two-level */
+    int levels;                 /* 0 none, 1 one-level, 2 two-level, 3 three-level */
     ref_grid g; ref_op op;
     onelevel *fine;
     csr Af;                     /* fine operator (used in x - A_f w) */
@@ -840,6 +840,10 @@ struct ref_pc {
     double coarse_rtol; int coarse_restart, coarse_maxit;
     int precision;
     int64_t inner_iters;        /* total inner iterations since last reset */
+    /* levels = 3 (Sec. 3.3: the hybrid construction repeated on the coarser
+     * mesh): the coarse solve is preconditioned by this two-level hybrid of
+     * the coarse grid instead of the one-level `coarse`, and is flexible */
+    ref_pc *inner;
 };
 
 typedef struct { int32_t restart, maxit, flexible; double rtol, atol; } ref_gmres_opts;
@@ -969,9 +973,10 @@ static void twolevel_apply(ref_pc *pc, const double *x, double *y) {
     if (pc->op.kind == 0) project_p(ncc, pc->vc, rc);
     ref_pc cpc = {0};
     cpc.levels = 1; cpc.fine = pc->coarse; cpc.g = *gc; cpc.op = pc->op; cpc.precision = pc->precision;
-    ref_gmres_opts o = {pc->coarse_restart, pc->coarse_maxit, 0, pc->coarse_rtol, 0.0};
+    /* three levels: FGMRES on the coarse grid with its own two-level hybrid */
+    ref_gmres_opts o = {pc->coarse_restart, pc->coarse_maxit, pc->inner != NULL, pc->coarse_rtol, 0.0};
     ref_gmres_stats st = {0};
-    gmres_core(&pc->Ac, &cpc, &o, rc, ec, &st, NULL, 0);
+    gmres_core(&pc->Ac, pc->inner ? pc->inner : &cpc, &o, rc, ec, &st, NULL, 0);
     pc->inner_iters += st.iters;
     double *wv = malloc(sizeof(double) * nf), *t = malloc(sizeof(double) * nf);
     for (int p = 0; p < 6; p++)
@@ -1033,10 +1038,16 @@ static float dotf(int64_t n, const float *x, const float *y) { float s = 0.0f; f
 
 /* GMRES(m) right-preconditioned by the FP32 one-level RAS, FP32 vectors
  * (the coarse solve of the mixed-precision two-level preconditioner). */
-static int gmres_core_f(const csr *A, const onelevel *M, int m, int maxit, double rtol, const float *b, float *x,
-                        int *iters_out) {
+static void twolevel_apply_ff(ref_pc *pc, const float *x, float *y);
+
+/* As above; with inner != NULL the preconditioner is that coarse-grid
+ * two-level hybrid (FP32 throughout) and the iteration is flexible (the
+ * preconditioned directions Z are kept and x += Z y). */
+static int gmres_core_f(const csr *A, const onelevel *M, ref_pc *inner, int m, int maxit, double rtol, const float *b,
+                        float *x, int *iters_out) {
     int64_t n = A->nrow;
     float *V = malloc(sizeof(float) * n * (m + 1)), *w = malloc(sizeof(float) * n), *z = malloc(sizeof(float) * n);
+    float *Z = inner ? malloc(sizeof(float) * n * m) : NULL;
     float *r = malloc(sizeof(float) * n);
     double *H = calloc((size_t)(m + 1) * m, sizeof(double)), *cs = malloc(sizeof(double) * m), *sn = malloc(sizeof(double) * m);
     double *gv = malloc(sizeof(double) * (m + 1)), *yv = malloc(sizeof(double) * m);
@@ -1051,8 +1062,10 @@ static int gmres_core_f(const csr *A, const onelevel *M, int m, int maxit, doubl
         gv[0] = beta;
         int jdone = 0;
         for (int j = 0; j < m && iters < maxit; j++) {
-            onelevel_apply_f(M, V + (int64_t)j * n, z);
-            csr_mv_f(A, z, w);
+            float *zj = inner ? Z + (int64_t)j * n : z;
+            if (inner) twolevel_apply_ff(inner, V + (int64_t)j * n, zj);
+            else onelevel_apply_f(M, V + (int64_t)j * n, zj);
+            csr_mv_f(A, zj, w);
             double anorm = sqrt((double)dotf(n, w, w));
             for (int i = 0; i <= j; i++) {
                 float h = dotf(n, w, V + (int64_t)i * n);
@@ -1082,26 +1095,30 @@ static int gmres_core_f(const csr *A, const onelevel *M, int m, int maxit, doubl
             for (int k = i + 1; k < jdone; k++) s2 -= H[i * m + k] * yv[k];
             yv[i] = s2 / H[i * m + i];
         }
-        for (int64_t q = 0; q < n; q++) w[q] = 0.0f;
-        for (int i = 0; i < jdone; i++) for (int64_t q = 0; q < n; q++) w[q] += (float)yv[i] * V[(int64_t)i * n + q];
-        onelevel_apply_f(M, w, z);
-        for (int64_t q = 0; q < n; q++) x[q] += z[q];
+        if (inner) {
+            for (int i = 0; i < jdone; i++) for (int64_t q = 0; q < n; q++) x[q] += (float)yv[i] * Z[(int64_t)i * n + q];
+        } else {
+            for (int64_t q = 0; q < n; q++) w[q] = 0.0f;
+            for (int i = 0; i < jdone; i++) for (int64_t q = 0; q < n; q++) w[q] += (float)yv[i] * V[(int64_t)i * n + q];
+            onelevel_apply_f(M, w, z);
+            for (int64_t q = 0; q < n; q++) x[q] += z[q];
+        }
         csr_mv_f(A, x, r);
         for (int64_t i = 0; i < n; i++) r[i] = b[i] - r[i];
     }
     *iters_out = iters;
-    free(V); free(w); free(z); free(r); free(H); free(cs); free(sn); free(gv); free(yv);
+    free(V); free(w); free(z); free(Z); free(r); free(H); free(cs); free(sn); free(gv); free(yv);
     return conv ? REF_OK : REF_ENOTCONV;
 }
 
-static void twolevel_apply_f(ref_pc *pc, const double *xd, double *yd) {
+/* The FP32 two-level hybrid on FP32 vectors (restriction, projection, coarse
+ * solve, prolongation, x - A_f w, fine sweeps, y = w + ...). */
+static void twolevel_apply_ff(ref_pc *pc, const float *x, float *y) {
     const ref_grid *g = &pc->g, *gc = &pc->gc;
     int n = g->n, nc = gc->n;
     int64_t ncc = 6 * (int64_t)nc * nc * gc->nr, nf = 24 * (int64_t)n * n * g->nr;
-    float *x = malloc(sizeof(float) * nf), *y = malloc(sizeof(float) * nf);
     float *rc = calloc(4 * ncc, sizeof(float)), *ec = calloc(4 * ncc, sizeof(float));
     float *wv = malloc(sizeof(float) * nf), *t = malloc(sizeof(float) * nf);
-    for (int64_t q = 0; q < nf; q++) x[q] = (float)xd[q];
     for (int p = 0; p < 6; p++)
         for (int K = 0; K < gc->nr; K++)
             for (int J = 0; J < nc; J++)
@@ -1119,7 +1136,7 @@ static void twolevel_apply_f(ref_pc *pc, const double *xd, double *yd) {
         for (int64_t c = 0; c < ncc; c++) rc[4 * c + 3] -= mean;
     }
     int it = 0;
-    gmres_core_f(&pc->Ac, pc->coarse, pc->coarse_restart, pc->coarse_maxit, pc->coarse_rtol, rc, ec, &it);
+    gmres_core_f(&pc->Ac, pc->coarse, pc->inner, pc->coarse_restart, pc->coarse_maxit, pc->coarse_rtol, rc, ec, &it);
     pc->inner_iters += it;
     for (int p = 0; p < 6; p++)
         for (int k = 0; k < g->nr; k++)
@@ -1130,36 +1147,52 @@ static void twolevel_apply_f(ref_pc *pc, const double *xd, double *yd) {
     csr_mv_f(&pc->Af, wv, t);
     for (int64_t q = 0; q < nf; q++) t[q] = x[q] - t[q];
     onelevel_apply_f(pc->fine, t, y);
-    for (int64_t q = 0; q < nf; q++) yd[q] = (double)(y[q] + wv[q]);
-    free(x); free(y); free(rc); free(ec); free(wv); free(t);
+    for (int64_t q = 0; q < nf; q++) y[q] += wv[q];
+    free(rc); free(ec); free(wv); free(t);
+}
+
+static void twolevel_apply_f(ref_pc *pc, const double *xd, double *yd) {
+    int64_t nf = 24 * (int64_t)pc->g.n * pc->g.n * pc->g.nr;
+    float *x = malloc(sizeof(float) * nf), *y = malloc(sizeof(float) * nf);
+    for (int64_t q = 0; q < nf; q++) x[q] = (float)xd[q];
+    twolevel_apply_ff(pc, x, y);
+    for (int64_t q = 0; q < nf; q++) yd[q] = (double)y[q];
+    free(x); free(y);
 }
 
 static void pc_apply(ref_pc *pc, const double *x, double *y) {
     int64_t n = 24 * (int64_t)pc->g.n * pc->g.n * pc->g.nr;
     if (pc->levels == 0) { memcpy(y, x, sizeof(double) * n); return; }
     if (pc->levels == 1) { onelevel_apply(pc->fine, x, y); return; }
-    if (pc->precision == 1) twolevel_apply_f(pc, x, y);
+    if (pc->precision == 1) twolevel_apply_f(pc, x, y);  /* two or three levels */
     else twolevel_apply(pc, x, y);
 }
 
 /* ------------------------------------------------- exported: preconditioner */
 typedef struct { int32_t sub[3]; int32_t overlap; int32_t levels; double coarse_rtol; int32_t coarse_restart, coarse_maxit; int32_t precision; } ref_ras_opts;
+void ref_pc_destroy(ref_pc *pc);
 
 int ref_pc_setup(const ref_grid *g, const ref_op *op, const ref_ras_opts *o, ref_pc **out) {
     *out = NULL;
-    if (check_grid(g) || !o || o->levels < 0 || o->levels > 2) return REF_EINVAL;
+    if (check_grid(g) || !o || o->levels < 0 || o->levels > 3) return REF_EINVAL;
     ref_pc *pc = calloc(1, sizeof(ref_pc));
     pc->levels = o->levels; pc->g = *g; pc->op = *op; pc->precision = o->precision;
     int rc = REF_OK;
     if (o->levels >= 1) rc = onelevel_setup(g, op, o->sub, o->overlap, o->precision, &pc->fine);
-    if (!rc && o->levels == 2) {
+    if (!rc && o->levels >= 2) {
         if (g->n % 2 || g->nr % 2 || o->sub[0] % 2 || o->sub[1] % 2 || o->sub[2] % 2) rc = REF_EINVAL;
         if (!rc) {
             pc->gc = *g; pc->gc.n = g->n / 2; pc->gc.nr = g->nr / 2;
             int subc[3] = {o->sub[0] / 2, o->sub[1] / 2, o->sub[2] / 2};
             rc = csr_build(g, op, &pc->Af);
             if (!rc) rc = csr_build(&pc->gc, op, &pc->Ac);
-            if (!rc) rc = onelevel_setup(&pc->gc, op, subc, o->overlap, o->precision, &pc->coarse);
+            if (!rc && o->levels == 2) rc = onelevel_setup(&pc->gc, op, subc, o->overlap, o->precision, &pc->coarse);
+            if (!rc && o->levels == 3) {  /* the coarse grid's own two-level hybrid, same subdomain count */
+                ref_ras_opts oc = *o;
+                oc.levels = 2;
+                for (int a = 0; a < 3; a++) oc.sub[a] = subc[a];
+                rc = ref_pc_setup(&pc->gc, op, &oc, &pc->inner);
+            }
             pc->coarse_rtol = o->coarse_rtol; pc->coarse_restart = o->coarse_restart; pc->coarse_maxit = o->coarse_maxit;
             int64_t ncc = 6 * (int64_t)pc->gc.n * pc->gc.n * pc->gc.nr;
             pc->vc = malloc(sizeof(double) * ncc);
@@ -1167,7 +1200,7 @@ int ref_pc_setup(const ref_grid *g, const ref_op *op, const ref_ras_opts *o, ref
         }
     }
     if (rc) {
-        free_onelevel(pc->fine); free_onelevel(pc->coarse); csr_free(&pc->Af); csr_free(&pc->Ac); free(pc->vc); free(pc);
+        ref_pc_destroy(pc);
         return rc;
     }
     *out = pc;
@@ -1176,8 +1209,13 @@ int ref_pc_setup(const ref_grid *g, const ref_op *op, const ref_ras_opts *o, ref
 
 void ref_pc_destroy(ref_pc *pc) {
     if (!pc) return;
+    ref_pc_destroy(pc->inner);
     free_onelevel(pc->fine); free_onelevel(pc->coarse); csr_free(&pc->Af); csr_free(&pc->Ac); free(pc->vc); free(pc);
 }
+
+/* The coarse grid's two-level hybrid of a three-level preconditioner (tests). */
+ref_pc *ref_pc_inner(ref_pc *pc) { return pc ? pc->inner : NULL; }
+int64_t ref_pc_inner_iters(const ref_pc *pc) { return pc ? pc->inner_iters : 0; }
 
 int ref_pc_apply(ref_pc *pc, const double *x, double *y) { pc_apply(pc, x, y); return REF_OK; }
 
