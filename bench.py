@@ -166,6 +166,7 @@ def main():
     ap.add_argument("--learned-eval-steps", type=int, default=30,
                     help="large workload: evaluation steps of the bounded learned-guess leg")
     ap.add_argument("--no-small", action="store_true", help="large workload: skip the small-configuration leg")
+    ap.add_argument("--no-three-level", action="store_true", help="large workload: skip the three-level forms")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the solver is single-GPU)",
@@ -184,14 +185,18 @@ def main():
     if args.workload == "batched":
         return batched(args, wl)
     systems = {"VP": dict(kind=csdyn.VP, seed=1), "BP": dict(kind=csdyn.BP, seed=2)}
-    forms = {"plain_fp64": 0, "mixed_fp32_pc": 1}
+    # form -> (precision inside the preconditioner, levels); the three-level forms repeat the hybrid
+    # construction on the coarse grid (the paper's extension for larger meshes)
+    forms = {"plain_fp64": (0, wl["levels"]), "mixed_fp32_pc": (1, wl["levels"])}
+    if args.workload == "large" and not args.no_three_level:
+        forms.update({"plain_fp64_3level": (0, 3), "mixed_fp32_3level": (1, 3)})
     state = {f: {} for f in forms}
     for name, s in systems.items():
         t0 = time.perf_counter()
         op = csdyn.Operator(n, nr, kind=s["kind"], dt=1e-4, ekman=1e-3, pm=5.0)
         b = torch.from_numpy(inputs.rhs(n, nr, s["seed"])).to(dev)
-        for form, prec in forms.items():
-            pc = csdyn.RAS(op, sub=wl["sub"], levels=wl["levels"], coarse_rtol=0.1, coarse_restart=30,
+        for form, (prec, levels) in forms.items():
+            pc = csdyn.RAS(op, sub=wl["sub"], levels=levels, coarse_rtol=0.1, coarse_restart=30,
                            coarse_maxit=200, precision=prec)
             flexible = wl["flexible"] or prec == 1
             sol = csdyn.Solver(op, pc, restart=30, maxit=2000, flexible=flexible, rtol=1e-8)
@@ -207,7 +212,7 @@ def main():
             _, st, rc = s["sol"].solve(s["b"], s["x"])
             if rc != 0 or not st["relres_true"] <= 1.0001e-8:
                 raise RuntimeError(f"{form} {name} solve did not converge: rc={rc} {st}")
-            iters[form][name] = [st["iters"], st["inner_iters"], st["relres_true"]]
+            iters[form][name] = [st["iters"], st["inner_iters"], st["relres_true"], st["inner2_iters"]]
 
     streams = {name: torch.cuda.Stream() for name in systems}  # default priority
 
@@ -219,7 +224,7 @@ def main():
                 _, st, rc = s["sol"].solve(s["b"], s["x"], stream=streams[name])
             if rc != 0 or not st["relres_true"] <= 1.0001e-8:
                 raise RuntimeError(f"{form} {name} solve did not converge: rc={rc} {st}")
-            iters[form][name] = [st["iters"], st["inner_iters"], st["relres_true"]]
+            iters[form][name] = [st["iters"], st["inner_iters"], st["relres_true"], st["inner2_iters"]]
         except Exception as e:  # reported by the caller
             failures.append(e)
 
@@ -275,18 +280,23 @@ def main():
     elapsed = time.perf_counter() - t0
     prof.__exit__(None, None, None)
     log(f"timed plain_fp64: {args.steps} steps in {elapsed:.3f} s, iters {iters['plain_fp64']}")
-    # the mixed-precision form (FP32 inside the preconditioner, FP64 FGMRES)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step("mixed_fp32_pc")
-    torch.cuda.synchronize()
-    elapsed_mixed = time.perf_counter() - t0
-    log(f"timed mixed_fp32_pc: {args.steps} steps in {elapsed_mixed:.3f} s, iters {iters['mixed_fp32_pc']}")
-    # both forms again with the two systems of a step solved at the same time, each from its own host
-    # thread on its own stream (the systems are independent; results are identical)
+    # the other forms: FP32 inside the preconditioner (FP64 FGMRES), and the three-level hybrids
+    elapsed_form = {}
+    for form in forms:
+        if form == "plain_fp64":
+            continue
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            step(form)
+        torch.cuda.synchronize()
+        elapsed_form[form] = time.perf_counter() - t0
+        log(f"timed {form}: {args.steps} steps in {elapsed_form[form]:.3f} s, iters {iters[form]}")
+    elapsed_mixed = elapsed_form["mixed_fp32_pc"]
+    # the two-level forms again with the two systems of a step solved at the same time, each from its own
+    # host thread on its own stream (the systems are independent; results are identical)
     elapsed_two = {}
-    for form in ([] if args.no_two_streams else forms):
+    for form in ([] if args.no_two_streams else ("plain_fp64", "mixed_fp32_pc")):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(args.steps):
@@ -294,10 +304,11 @@ def main():
         torch.cuda.synchronize()
         elapsed_two[form] = time.perf_counter() - t0
         log(f"timed {form} on two streams: {args.steps} steps in {elapsed_two[form]:.3f} s, iters {iters[form]}")
-    err = {}
-    for name in systems:
-        xp, xm = state["plain_fp64"][name]["x"], state["mixed_fp32_pc"][name]["x"]
-        err[name] = float(torch.linalg.norm(xm - xp) / torch.linalg.norm(xp))
+    err = {f: {} for f in forms if f != "plain_fp64"}
+    for f in err:
+        for name in systems:
+            xp, xm = state["plain_fp64"][name]["x"], state[f][name]["x"]
+            err[f][name] = float(torch.linalg.norm(xm - xp) / torch.linalg.norm(xp))
     iters_plain = iters["plain_fp64"]
 
     kernels = {}
@@ -337,11 +348,12 @@ def main():
         "forms": {
             "plain_fp64": {"solves_per_s": round(2 * args.steps / elapsed, 4),
                            "ms_per_step": round(elapsed / args.steps * 1e3, 3)},
-            "mixed_fp32_pc": {"solves_per_s": round(2 * args.steps / elapsed_mixed, 4),
-                              "ms_per_step": round(elapsed_mixed / args.steps * 1e3, 3),
-                              "iters": {k: {"outer": v[0], "inner": v[1], "relres": v[2]}
-                                        for k, v in iters["mixed_fp32_pc"].items()},
-                              "rel_err_vs_fp64_solution": err},
+            **{f: {"solves_per_s": round(2 * args.steps / el, 4), "ms_per_step": round(el / args.steps * 1e3, 3),
+                   "precision": "fp32 preconditioner" if forms[f][0] else "fp64", "levels": forms[f][1],
+                   "iters": {k: {"outer": v[0], "inner": v[1], "coarsest": v[3], "relres": v[2]}
+                             for k, v in iters[f].items()},
+                   "rel_err_vs_plain_fp64_solution": err[f]}
+               for f, el in elapsed_form.items()},
             **{f"{form}_two_streams": {"solves_per_s": round(2 * args.steps / el, 4),
                                        "ms_per_step": round(el / args.steps * 1e3, 3)}
                for form, el in elapsed_two.items()},

@@ -131,6 +131,12 @@ int32_t csdyn_project(const csdyn_opctx *ctx, const double *x, double *out, void
  *        to relative tolerance coarse_rtol from 0, preconditioned by one-level
  *        RAS with sub/2 boxes),
  *   y = w + M_one^{-1}(x - A_f w).
+ * levels = 3 repeats the construction on the coarse grid (Sec. 3.3, the
+ * multilevel hybrid for larger meshes): A_c^{-1} is then FGMRES(coarse_restart)
+ * to coarse_rtol preconditioned by the coarse grid's own two-level hybrid
+ * (sub/2 boxes on N/2, sub/4 boxes and the same GMRES settings on N/4); N, Nr
+ * and sub must be divisible by 4 and N/4 >= 4.  csdyn_ras_info's coarse fields
+ * then describe the one-level RAS of the N/2 grid.
  * For VP the coarse right-hand side's pressure part is projected to zero
  * volume-weighted mean (the coarse Neumann problem's solvability condition).
  * precision = 1 stores the factors in FP32 and runs every operation inside
@@ -141,7 +147,7 @@ int32_t csdyn_project(const csdyn_opctx *ctx, const double *x, double *out, void
 typedef struct {
     int32_t sub[3];          /* owned box size in cells (xi, eta, r) */
     int32_t overlap;         /* 0 or 1 */
-    int32_t levels;          /* 1 or 2 */
+    int32_t levels;          /* 1, 2 or 3 */
     double coarse_rtol;      /* 0.1 in the paper */
     int32_t coarse_restart;  /* 30 */
     int32_t coarse_maxit;    /* cap on inner iterations per coarse solve */
@@ -223,6 +229,7 @@ typedef struct {
     double bnorm;            /* ||b|| */
     double t_ms[6];          /* with opts.timing: stream time per phase (CSDYN_T_*), ms; else 0 */
     double t_span_ms;        /* with opts.timing: stream time from the solve's first to its last launch */
+    int64_t inner2_iters;    /* three levels: coarsest-grid GMRES iterations summed over the solve */
 } csdyn_gmres_stats;
 
 int32_t csdyn_gmres_workspace_bytes(const csdyn_opctx *ctx, const csdyn_gmres_opts *o, size_t *bytes);

@@ -45,7 +45,7 @@ class GmresStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("inner_iters", C.c_int64),
                 ("relres_true", C.c_double), ("relres_est", C.c_double), ("res0", C.c_double),
                 ("res_true", C.c_double), ("bnorm", C.c_double), ("t_ms", C.c_double * 6),
-                ("t_span_ms", C.c_double)]
+                ("t_span_ms", C.c_double), ("inner2_iters", C.c_int64)]
 
 # phases of GmresStats.t_ms (CSDYN_T_* in csdyn.h)
 PHASES = ("op", "pc_fine", "pc_coarse", "pc_interp", "orth", "other")
@@ -308,7 +308,8 @@ class Solver:
                                      _ptr(self.ws), self.nbytes, _stream(stream), C.byref(st))
         _check(rc, "csdyn_gmres_solve")
         stats = dict(iters=st.iters, restarts=st.restarts, inner_iters=st.inner_iters, relres_true=st.relres_true,
-                     relres_est=st.relres_est, res0=st.res0, res_true=st.res_true, bnorm=st.bnorm)
+                     relres_est=st.relres_est, res0=st.res0, res_true=st.res_true, bnorm=st.bnorm,
+                     inner2_iters=st.inner2_iters)
         if self.opts.timing:
             stats["t_ms"] = dict(zip(PHASES, list(st.t_ms)))
             stats["t_span_ms"] = st.t_span_ms

@@ -245,9 +245,19 @@ struct HostBuild {
     csdyn_grid g;
     csdyn_op op;
     csdyn_ras_opts o;
-    HostRas fine, coarse;
+    HostRas fine, coarse;  // coarse: levels = 2 only
     HostGeom gc;
+    std::shared_ptr<HostBuild> inner;  // levels = 3: the coarse grid's two-level hybrid
 };
+
+// The options of the coarse grid's two-level hybrid inside a three-level one:
+// half the box size (the same subdomain count), two levels.
+static csdyn_ras_opts inner_opts(const csdyn_ras_opts &o) {
+    csdyn_ras_opts c = o;
+    c.levels = 2;
+    for (int a = 0; a < 3; ++a) c.sub[a] = o.sub[a] / 2;
+    return c;
+}
 
 // One cached host build; the key ignores the precision (the FP64 and FP32
 // preconditioners of one operator share the assembly and factorization).
@@ -263,9 +273,14 @@ static bool same_key(const HostBuild &b, const csdyn_grid &g, const csdyn_op &op
 
 static int32_t check_opts(const csdyn_opctx *ctx, const csdyn_ras_opts *o) {
     if (!ctx || !o) { set_error("ras: null argument"); return CSDYN_EINVAL; }
-    if (o->levels != 1 && o->levels != 2) { set_error("ras: levels must be 1 or 2"); return CSDYN_EINVAL; }
+    if (o->levels < 1 || o->levels > 3) { set_error("ras: levels must be 1, 2 or 3"); return CSDYN_EINVAL; }
     if (o->precision != 0 && o->precision != 1) { set_error("ras: precision must be 0 or 1"); return CSDYN_EINVAL; }
-    if (o->levels == 2) {
+    if (o->levels == 3 && (ctx->g.n % 4 || ctx->g.nr % 4 || o->sub[0] % 4 || o->sub[1] % 4 || o->sub[2] % 4 ||
+                           ctx->g.n / 4 < 4)) {
+        set_error("ras: three levels need N, Nr and subdomain sizes divisible by 4, and N/4 >= 4");
+        return CSDYN_EINVAL;
+    }
+    if (o->levels >= 2) {
         if (ctx->g.n % 2 || ctx->g.nr % 2 || o->sub[0] % 2 || o->sub[1] % 2 || o->sub[2] % 2 || ctx->g.n / 2 < 4) {
             set_error("ras: two-level needs even N, Nr and subdomain sizes, and N/2 >= 4");
             return CSDYN_EINVAL;
@@ -278,16 +293,22 @@ static int32_t check_opts(const csdyn_opctx *ctx, const csdyn_ras_opts *o) {
     return CSDYN_OK;
 }
 
-static int32_t host_build(const csdyn_opctx *ctx, const csdyn_ras_opts *o, std::shared_ptr<HostBuild> &out) {
+static int32_t host_build(const HostGeom &hg, const csdyn_grid &g, const csdyn_op &op, const csdyn_ras_opts *o,
+                          std::shared_ptr<HostBuild> &out) {
     auto b = std::make_shared<HostBuild>();
-    b->g = ctx->g; b->op = ctx->op; b->o = *o;
-    CSD_TRY(build_host_ras(ctx->hg, ctx->op, o->sub, o->overlap, o->storage, b->fine));
-    if (o->levels == 2) {
-        csdyn_grid gc = ctx->g;
+    b->g = g; b->op = op; b->o = *o;
+    CSD_TRY(build_host_ras(hg, op, o->sub, o->overlap, o->storage, b->fine));
+    if (o->levels >= 2) {
+        csdyn_grid gc = g;
         gc.n /= 2; gc.nr /= 2;
         CSD_TRY(b->gc.build(gc));
-        const int subc[3] = {o->sub[0] / 2, o->sub[1] / 2, o->sub[2] / 2};
-        CSD_TRY(build_host_ras(b->gc, ctx->op, subc, o->overlap, o->storage, b->coarse));
+        if (o->levels == 2) {
+            const int subc[3] = {o->sub[0] / 2, o->sub[1] / 2, o->sub[2] / 2};
+            CSD_TRY(build_host_ras(b->gc, op, subc, o->overlap, o->storage, b->coarse));
+        } else {
+            const csdyn_ras_opts oc = inner_opts(*o);
+            CSD_TRY(host_build(b->gc, gc, op, &oc, b->inner));
+        }
     }
     out = std::move(b);
     return CSDYN_OK;
@@ -310,6 +331,9 @@ struct csdyn_ras {
     mutable int64_t inner_iters = 0;
     double vol_c = 0;           // total coarse volume
     csdyn_ras_info info{};
+    // levels = 3: the coarse grid's two-level hybrid (operator: coarse_ctx), which
+    // preconditions the coarse solve; its data lie in this handle's workspace
+    std::unique_ptr<csdyn_ras> inner;
 
     template <class T>
     int32_t two_level(const T *x, T *y, hipStream_t s) const;
@@ -317,20 +341,71 @@ struct csdyn_ras {
 
 static void layout_all(Carver &c, const HostBuild &b, const csdyn_ras_opts &o, csdyn_ras &R) {
     OneLevel::layout(c, b.fine, o.precision, R.fine);
-    if (o.levels == 2) {
+    if (o.levels >= 2) {
         const size_t fs = o.precision ? sizeof(float) : sizeof(double);
         const int64_t nf = 24 * int64_t(b.g.n) * b.g.n * b.g.nr;
         const int64_t nc = 24 * int64_t(b.gc.n) * b.gc.n * b.gc.nr;
         R.nf = nf; R.nc = nc;
         void *cg = c.take<char>(devgeom_bytes(b.gc.n, b.gc.nr));
         R.coarse_ctx.ws = cg;
-        OneLevel::layout(c, b.coarse, o.precision, R.coarse);
-        const size_t gb = o.precision ? Gmres<float>::bytes(nc, o.coarse_restart, false)
-                                        : Gmres<double>::bytes(nc, o.coarse_restart, false);
+        if (o.levels == 2) OneLevel::layout(c, b.coarse, o.precision, R.coarse);
+        const bool flex = o.levels == 3;  // the coarse solve's preconditioner holds an inner solve
+        const size_t gb = o.precision ? Gmres<float>::bytes(nc, o.coarse_restart, flex)
+                                        : Gmres<double>::bytes(nc, o.coarse_restart, flex);
         R.cws = c.take<char>(gb);
         // fine: x32, w, t, y32 ; coarse: rc, ec ; FP32 edge buffers for the fine operator
         R.buf = c.take<char>(4 * nf * fs + 2 * nc * fs + 2 * size_t(24) * b.g.nr * b.g.n * 8 * fs + 1024);
+        if (o.levels == 3) {
+            R.inner.reset(new csdyn_ras);
+            layout_all(c, *b.inner, inner_opts(o), *R.inner);
+        }
     }
+}
+
+// Upload one level of a laid-out preconditioner (and, for three levels, the
+// coarse grid's hybrid into the same workspace) and fill its info.
+static int32_t setup_level(csdyn_ras &R, const csdyn_opctx *ctx, const csdyn_ras_opts &o, const HostBuild &b) {
+    R.o = o;
+    R.fine_ctx = ctx;
+    R.info = csdyn_ras_info{};
+    auto fill = [](const HostRas &H, int32_t &nsd, int64_t &nnz, int64_t &box, int64_t &own, int64_t &stored, int32_t &lv) {
+        nsd = H.nsd; nnz = H.nnz; box = H.box_cells; own = H.owned_cells;
+        stored = int64_t(H.L.val.size() + H.U.val.size() + H.U.lane_diag.size()); lv = H.max_total_levels;
+    };
+    fill(b.fine, R.info.nsd_fine, R.info.nnz_fine, R.info.box_cells_fine, R.info.owned_cells_fine, R.info.stored_fine,
+         R.info.max_levels_fine);
+    // the coarse grid's one-level RAS: its own (two levels) or the inner hybrid's fine one (three levels)
+    const HostRas *hc = o.levels == 2 ? &b.coarse : o.levels == 3 ? &b.inner->fine : nullptr;
+    if (hc)
+        fill(*hc, R.info.nsd_coarse, R.info.nnz_coarse, R.info.box_cells_coarse, R.info.owned_cells_coarse,
+             R.info.stored_coarse, R.info.max_levels_coarse);
+    R.info.precision = o.precision;
+    CSD_TRY(R.fine.choose_memory());
+    CSD_TRY(R.fine.upload(b.fine));
+    if (o.levels >= 2) {
+        R.coarse_ctx.g = ctx->g;
+        R.coarse_ctx.g.n /= 2; R.coarse_ctx.g.nr /= 2;
+        R.coarse_ctx.op = ctx->op;
+        R.coarse_ctx.hg = b.gc;
+        R.coarse_ctx.ws_bytes = devgeom_bytes(b.gc.n, b.gc.nr);
+        CSD_TRY(devgeom_setup(R.coarse_ctx.hg, R.coarse_ctx.ws, &R.coarse_ctx.dg));
+        if (o.levels == 2) {
+            CSD_TRY(R.coarse.choose_memory());
+            CSD_TRY(R.coarse.upload(b.coarse));
+        }
+        double v = 0;
+        for (double a : b.gc.vol) v += a;
+        R.vol_c = v;
+        if (o.levels == 3) CSD_TRY(setup_level(*R.inner, &R.coarse_ctx, inner_opts(o), *b.inner));
+    }
+    const OneLevel &cl = o.levels == 3 ? R.inner->fine : R.coarse;
+    R.info.lds_fine = int32_t(R.fine.lds_bytes);
+    R.info.box_in_lds_fine = R.fine.vec ? 2 : R.fine.lds_ring;
+    R.info.lds_coarse = int32_t(cl.lds_bytes);
+    R.info.box_in_lds_coarse = cl.vec ? 2 : cl.lds_ring;
+    R.info.threads_fine = R.fine.threads;
+    R.info.threads_coarse = o.levels >= 2 ? cl.threads : 0;
+    return CSDYN_OK;
 }
 
 extern "C" int32_t csdyn_ras_workspace_bytes(const csdyn_opctx *ctx, const csdyn_ras_opts *o, size_t *bytes) {
@@ -340,7 +415,7 @@ extern "C" int32_t csdyn_ras_workspace_bytes(const csdyn_opctx *ctx, const csdyn
     std::lock_guard<std::mutex> lk(g_cache_mu);
     if (!g_cache || !same_key(*g_cache, ctx->g, ctx->op, *o)) {
         g_cache.reset();
-        CSD_TRY(host_build(ctx, o, g_cache));
+        CSD_TRY(host_build(ctx->hg, ctx->g, ctx->op, o, g_cache));
     }
     csdyn_ras R;
     Carver c(nullptr);
@@ -360,49 +435,15 @@ extern "C" int32_t csdyn_ras_setup(const csdyn_opctx *ctx, const csdyn_ras_opts 
         std::lock_guard<std::mutex> lk(g_cache_mu);
         if (!g_cache || !same_key(*g_cache, ctx->g, ctx->op, *o)) {
             g_cache.reset();
-            CSD_TRY(host_build(ctx, o, g_cache));
+            CSD_TRY(host_build(ctx->hg, ctx->g, ctx->op, o, g_cache));
         }
         b = g_cache;
     }
     auto R = std::make_unique<csdyn_ras>();
-    R->o = *o;
-    R->fine_ctx = ctx;
     Carver c(ws);
     layout_all(c, *b, *o, *R);
     if (c.off + 256 > ws_bytes) { set_error("ras: workspace %zu < %zu bytes", ws_bytes, c.off + 256); return CSDYN_ENOMEM; }
-    R->info = csdyn_ras_info{};
-    auto fill = [](const HostRas &H, int32_t &nsd, int64_t &nnz, int64_t &box, int64_t &own, int64_t &stored, int32_t &lv) {
-        nsd = H.nsd; nnz = H.nnz; box = H.box_cells; own = H.owned_cells;
-        stored = int64_t(H.L.val.size() + H.U.val.size() + H.U.lane_diag.size()); lv = H.max_total_levels;
-    };
-    fill(b->fine, R->info.nsd_fine, R->info.nnz_fine, R->info.box_cells_fine, R->info.owned_cells_fine,
-         R->info.stored_fine, R->info.max_levels_fine);
-    if (o->levels == 2)
-        fill(b->coarse, R->info.nsd_coarse, R->info.nnz_coarse, R->info.box_cells_coarse, R->info.owned_cells_coarse,
-             R->info.stored_coarse, R->info.max_levels_coarse);
-    R->info.precision = o->precision;
-    CSD_TRY(R->fine.choose_memory());
-    CSD_TRY(R->fine.upload(b->fine));
-    if (o->levels == 2) {
-        R->coarse_ctx.g = ctx->g;
-        R->coarse_ctx.g.n /= 2; R->coarse_ctx.g.nr /= 2;
-        R->coarse_ctx.op = ctx->op;
-        R->coarse_ctx.hg = b->gc;
-        R->coarse_ctx.ws_bytes = devgeom_bytes(b->gc.n, b->gc.nr);
-        CSD_TRY(devgeom_setup(R->coarse_ctx.hg, R->coarse_ctx.ws, &R->coarse_ctx.dg));
-        CSD_TRY(R->coarse.choose_memory());
-        CSD_TRY(R->coarse.upload(b->coarse));
-        double v = 0;
-        for (double a : b->gc.vol) v += a;
-        R->vol_c = v;
-
-    }
-    R->info.lds_fine = int32_t(R->fine.lds_bytes);
-    R->info.box_in_lds_fine = R->fine.vec ? 2 : R->fine.lds_ring;
-    R->info.lds_coarse = int32_t(R->coarse.lds_bytes);
-    R->info.box_in_lds_coarse = R->coarse.vec ? 2 : R->coarse.lds_ring;
-    R->info.threads_fine = R->fine.threads;
-    R->info.threads_coarse = o->levels == 2 ? R->coarse.threads : 0;
+    CSD_TRY(setup_level(*R, ctx, *o, *b));
     if (stream) CSD_HIP(hipStreamSynchronize((hipStream_t)stream));
     *out = R.release();
     return CSDYN_OK;
@@ -418,7 +459,7 @@ int32_t csdyn_ras::two_level(const T *x, T *y, hipStream_t s) const {
     T *G32 = ec + nc, *SF32 = G32 + size_t(24) * fine_ctx->g.nr * fine_ctx->g.n * 4;
     Gmres<T> gm;
     Carver cc(cws);
-    gm.carve(cc, nc, o.coarse_restart, false);
+    gm.carve(cc, nc, o.coarse_restart, inner != nullptr);
     {  // r_c = I_f^c x
         PhaseScope ph(PH_PCI, s);
         {
@@ -437,13 +478,19 @@ int32_t csdyn_ras::two_level(const T *x, T *y, hipStream_t s) const {
     {  // e_c ~ A_c^{-1} r_c : GMRES(coarse_restart) from 0 to coarse_rtol, coarse one-level RAS
         PhaseScope ph(PH_PCC, s);
         CSD_TRY(Vec<T>::zero(ec, nc, s));
-        gm.lookahead = true;  // a coarse step is a few hundred microseconds of device work
+        // a two-level coarse step is a few hundred microseconds of device work, so step j + 1 is
+        // enqueued before step j is read back; with three levels a step holds an inner solve that
+        // waits for the host itself, and a step past convergence would be a whole wasted solve
+        gm.lookahead = inner == nullptr;
         const csdyn_opctx *cctx = &coarse_ctx;
         DevFn<T> Ac;
         if constexpr (sizeof(T) == 8) Ac = [cctx](const T *in, T *outv, hipStream_t st) { return op_launch(cctx, in, outv, st); };
         else Ac = [cctx](const T *in, T *outv, hipStream_t st) { return op_launch_f32(cctx, in, outv, (float *)cctx->dg.G, (float *)cctx->dg.SF, st); };
         const OneLevel *cl = &coarse;
-        DevFn<T> Mc = [cl](const T *in, T *outv, hipStream_t st) { return cl->apply<T>(in, outv, st); };
+        const csdyn_ras *hy = inner.get();
+        DevFn<T> Mc;
+        if (hy) Mc = [hy](const T *in, T *outv, hipStream_t st) { return hy->two_level<T>(in, outv, st); };
+        else Mc = [cl](const T *in, T *outv, hipStream_t st) { return cl->apply<T>(in, outv, st); };
         GmresResult gr;
         int32_t rcode = gm.solve(Ac, &Mc, rc, ec, o.coarse_maxit, o.coarse_rtol, 0.0, s, gr);
         if (rcode < 0) return rcode;
@@ -505,6 +552,10 @@ int64_t ras_inner_iters(const csdyn_ras *pc, bool reset) {
     const int64_t v = pc->inner_iters;
     if (reset) pc->inner_iters = 0;
     return v;
+}
+// Iterations of the coarsest solves (three levels), accumulated like ras_inner_iters.
+int64_t ras_inner2_iters(const csdyn_ras *pc, bool reset) {
+    return pc->inner ? ras_inner_iters(pc->inner.get(), reset) : 0;
 }
 }  // namespace csd
 
@@ -608,7 +659,10 @@ extern "C" int32_t csdyn_gmres_solve(const csdyn_opctx *ctx, const csdyn_ras *pc
     if (ctx->op.kind == CSDYN_VP) CSD_TRY(project(L.bproj));
     DevFn<double> A = [ctx](const double *in, double *outv, hipStream_t st) { return op_launch(ctx, in, outv, st); };
     DevFn<double> M = [pc](const double *in, double *outv, hipStream_t st) { return ras_apply_d(pc, in, outv, st); };
-    if (pc) ras_inner_iters(pc, true);
+    if (pc) {
+        ras_inner_iters(pc, true);
+        ras_inner2_iters(pc, true);
+    }
     GmresResult res;
     L.gm.m_phase = pc && ras_levels(pc) == 1 ? PH_PCF : -1;
     int32_t rc = L.gm.solve(A, pc ? &M : nullptr, L.bproj, x, o->maxit, o->rtol, o->atol, s, res, o->rhs_relative != 0);
@@ -627,6 +681,7 @@ extern "C" int32_t csdyn_gmres_solve(const csdyn_opctx *ctx, const csdyn_ras *pc
         st->iters = res.iters;
         st->restarts = res.restarts;
         st->inner_iters = pc ? ras_inner_iters(pc, false) : 0;
+        st->inner2_iters = pc ? ras_inner2_iters(pc, false) : 0;
         st->relres_true = res.relres_true;
         st->relres_est = res.relres_est;
         st->res0 = res.res0;

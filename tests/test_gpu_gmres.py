@@ -185,3 +185,23 @@ def test_phase_times(precision):
     assert ph["pc_coarse"] == max(ph.values())
     assert ph["pc_fine"] > 0 and ph["pc_interp"] > 0 and ph["op"] > 0 and ph["orth"] > 0
     assert "t_ms" not in st0
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_three_level_solve_matches_oracle(kind):
+    """FGMRES with the three-level hybrid at N = Nr = 32 (coarse 16, coarsest 8):
+    iterations within one of the oracle's, solution within 1e-7, and fewer coarse
+    iterations than with two levels."""
+    n, sub = 32, (8, 8, 8)
+    print(f"[three-level solve] kind={kind}", flush=True)
+    pb = O.Problem(n, n, kind=kind)
+    b = inputs.rhs(n, n, seed=0)
+    x_ref, st_ref, rc_ref = O.gmres(pb, b, pc=O.Preconditioner(pb, sub=sub, levels=3), flexible=True)
+    assert rc_ref == 0
+    x, st, rc = _gpu_solve(n, n, kind, b, sub=sub, levels=3, flexible=True)
+    _, st2, _ = _gpu_solve(n, n, kind, b, sub=sub, levels=2, flexible=True)
+    print(f"[three-level solve] gpu {st} oracle {st_ref} two-level inner {st2['inner_iters']}", flush=True)
+    assert rc == 0 and st["relres_true"] <= 1.0001e-8
+    assert abs(st["iters"] - st_ref["iters"]) <= 1, (st, st_ref)
+    assert np.linalg.norm(x - x_ref) <= 1e-7 * np.linalg.norm(x_ref)
+    assert 0 < st["inner_iters"] < st2["inner_iters"] and st["inner2_iters"] > 0

@@ -182,3 +182,32 @@ def test_two_level_n32_matches_oracle(kind, precision, tol):
     rel = np.abs(y - y_ref).max() / np.abs(y_ref).max()
     print(f"[two-level parity] rel {rel:.2e}", flush=True)
     assert rel <= tol
+
+
+@pytest.mark.parametrize("n,nr,sub,kind,precision,tol", [(16, 8, (8, 8, 4), 0, 0, 1e-9), (16, 8, (8, 8, 4), 1, 0, 1e-9),
+                                                         (32, 32, (8, 8, 8), 0, 0, 1e-9), (16, 8, (8, 8, 4), 0, 1, 1e-4),
+                                                         (32, 32, (8, 8, 8), 1, 1, 1e-4)])
+def test_three_level_matches_oracle(n, nr, sub, kind, precision, tol):
+    """Three-level hybrid (the two-level construction repeated on the coarse grid:
+    FGMRES coarse solve preconditioned by the coarse grid's own hybrid) against
+    the oracle, FP64 and FP32 (the oracle's FP32 emulation of the same structure)."""
+    print(f"[three-level parity] n={n} nr={nr} kind={kind} precision={precision}", flush=True)
+    pb = O.Problem(n, nr, kind=kind)
+    x = inputs.random_field(pb.shape(), seed=111 + n + kind)
+    y_ref = O.Preconditioner(pb, sub=sub, levels=3, precision=precision).apply(x)
+    _, pc = _setup(n, nr, kind, sub, levels=3, precision=precision)
+    info = pc.info()
+    assert info["nsd_coarse"] == info["nsd_fine"]
+    y = _apply(pc, x)
+    rel = np.abs(y - y_ref).max() / np.abs(y_ref).max()
+    print(f"[three-level parity] rel {rel:.2e}", flush=True)
+    assert rel <= tol
+
+
+def test_three_level_rejects_bad_sizes():
+    from paper_2009_02171_amd import csdyn
+    op = csdyn.Operator(16, 8)
+    with pytest.raises(csdyn.CsdynError):
+        csdyn.RAS(op, sub=(8, 8, 2), levels=3)      # 2 is not divisible by 4
+    with pytest.raises(csdyn.CsdynError):
+        csdyn.RAS(csdyn.Operator(12, 12), sub=(4, 4, 4), levels=3)   # N/4 = 3 < 4
