@@ -242,17 +242,17 @@ int32_t csdyn_gmres_workspace_bytes(const csdyn_opctx *ctx, const csdyn_gmres_op
  * synchronisation per step for the batch.  use_graph selects how a step runs:
  * 0, the shells' kernels on their own streams; 1, the same captured as a
  * hipGraph per (active set, step index), kept in the handle for later solves;
- * 2, one persistent launch per step (also captured per (active set, step
- * index)): a work-list of every active shell's subdomain solves, edge fills,
- * stencil tiles and Gram-Schmidt blocks, taken in order by the workgroups, an
- * item waiting (bounded) for the finished items of its shell's previous
- * phase; needs one-level FP32 preconditioners on all shells, at most 16
- * shells and N >= 16 (csdyn_batch_persistent tells whether the handle
- * qualifies; CSDYN_EINVAL otherwise, CSDYN_EHIP if a wait hit its bound).
- * The persistent step is switched off in this build (its solves have not
- * finished in the time allowed on the GPU): csdyn_batch_persistent reports 0
- * and use_graph = 2 returns CSDYN_EINVAL.  Modes 0 and 1 give the same results
- * bit for bit.  Stopping rule, projection
+ * 2, one launch per phase for all active shells together (every shell's RAS
+ * subdomains in one launch, then the edge fills, the stencil tiles, the
+ * multi-dot, update and normalisation blocks and their reductions: nine
+ * launches a step whatever the shell count), captured per (active set, step
+ * index); 3, one persistent launch per step (a work-list of the same items,
+ * each waiting, bounded, for its shell's previous phase), switched off in this
+ * build because its solves did not finish in the time allowed on the GPU.
+ * Modes 2 and 3 need one-level FP32 preconditioners on all shells, at most 16
+ * shells and N >= 16; csdyn_batch_modes returns a bit mask of the modes a
+ * handle can run (bit m for use_graph = m); CSDYN_EINVAL for the others.
+ * Modes 0, 1 and 2 give the same results bit for bit.  Stopping rule, projection
  * of the VP pressure and statistics per shell as for csdyn_gmres_solve.
  * b, x: host arrays of nshell device pointers (x holds x0 on entry).  The
  * workspace (csdyn_batch_workspace_bytes) holds every shell's Krylov basis and
@@ -266,8 +266,8 @@ int32_t csdyn_batch_setup(int32_t nshell, const csdyn_opctx *const *ops, const c
                           const csdyn_gmres_opts *o, void *ws, size_t ws_bytes, csdyn_batch **out);
 int32_t csdyn_gmres_solve_batched(csdyn_batch *batch, const double *const *b, double *const *x, int32_t use_graph,
                                   void *stream, csdyn_gmres_stats *stats);
-/* *available = 1 when use_graph = 2 (the persistent step) can be used. */
-int32_t csdyn_batch_persistent(const csdyn_batch *batch, int32_t *available);
+/* *modes = bit mask of the use_graph values this handle can run (bit m for m). */
+int32_t csdyn_batch_modes(const csdyn_batch *batch, int32_t *modes);
 void csdyn_batch_destroy(csdyn_batch *batch);
 
 /* ||b - A x|| (b with its pressure part projected for VP, as the solve does):

@@ -100,7 +100,7 @@ SIGNATURES = {
     "csdyn_gmres_solve_batched": (C.c_int32, [C.c_void_p, _P(C.c_void_p), _P(C.c_void_p), C.c_int32, C.c_void_p,
                                               _P(GmresStats)]),
     "csdyn_batch_destroy": (None, [C.c_void_p]),
-    "csdyn_batch_persistent": (C.c_int32, [C.c_void_p, _P(C.c_int32)]),
+    "csdyn_batch_modes": (C.c_int32, [C.c_void_p, _P(C.c_int32)]),
     "csdyn_residual_norm": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p,
                                         _P(C.c_double)]),
     "csdyn_residual_norm_noalloc": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, _P(C.c_double)]),
@@ -335,16 +335,20 @@ class Batch:
         self.h = h
 
     # how a lock-step Arnoldi step runs (csdyn_gmres_solve_batched's use_graph)
-    EAGER, GRAPH, PERSISTENT = 0, 1, 2
+    EAGER, GRAPH, PHASES, PERSISTENT = 0, 1, 2, 3
+
+    def available(self, mode):
+        v = C.c_int32()
+        _check(lib().csdyn_batch_modes(self.h, C.byref(v)), "csdyn_batch_modes")
+        return bool(v.value >> mode & 1)
 
     @property
     def persistent_available(self):
-        v = C.c_int32()
-        _check(lib().csdyn_batch_persistent(self.h, C.byref(v)), "csdyn_batch_persistent")
-        return bool(v.value)
+        return self.available(self.PERSISTENT)
 
     def solve(self, bs, xs, use_graph=True, stream=None):
-        """use_graph: False/0 eager, True/1 graph of per-shell branches, 2 persistent step."""
+        """use_graph: False/0 eager, True/1 graph of per-shell branches, 2 one launch per phase for
+        all shells, 3 persistent step."""
         ns = len(self.ops)
         for t in list(bs) + list(xs):
             _need(t, torch.float64, "batch vectors")

@@ -211,6 +211,60 @@ __global__ __launch_bounds__(kStepThreads, 1) void k_arnoldi_step(StepArgs A) {
     }
 }
 
+// ------------------------------------------------ phase-batched Arnoldi step
+// The same nine phases as ordinary launches, one launch per phase for all
+// active shells: block b of phase p is item b - (items of the shells before it)
+// of the first shell (in size order) whose range holds it.  Kernel boundaries
+// order the phases; nothing waits inside a launch.
+struct PhaseArgs {
+    const StepShell *sh;
+    const int *order;
+    uint64_t mask;
+    int j, nshell;
+};
+
+template <int PH>
+__device__ __forceinline__ bool phase_item(const PhaseArgs &A, int &shell, int &loc) {
+    int b = int(blockIdx.x);
+    for (int q = 0; q < A.nshell; ++q) {
+        const int i = A.order[q];
+        if (!(A.mask >> i & 1)) continue;
+        const int c = A.sh[i].cnt[PH];
+        if (b < c) {
+            shell = i;
+            loc = b;
+            return true;
+        }
+        b -= c;
+    }
+    return false;
+}
+
+template <int PH>
+__global__ __launch_bounds__(kStepThreads, 2) void k_batch_phase(PhaseArgs A) {
+    extern __shared__ __align__(16) unsigned char bph_smem[];
+    int shell = 0, loc = 0;
+    if (!phase_item<PH>(A, shell, loc)) return;
+    step_item(A.sh[shell], A.j, PH, loc, bph_smem);
+}
+
+// The RAS phase at the workgroup width of each shell's own sweeps (the width
+// the single-shell apply launches with): one launch per width, over the shells
+// of that width in A.mask.  Every shell here has a preconditioner.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_batch_ras(PhaseArgs A) {
+    extern __shared__ __align__(16) unsigned char bras_smem[];
+    int shell = 0, loc = 0;
+    if (!phase_item<0>(A, shell, loc)) return;
+    const StepShell &S = A.sh[shell];
+    const RasView &R = S.ras;
+    const double *vj = S.V + int64_t(A.j) * S.n;
+    double *zj = S.Z + int64_t(A.j) * S.n;
+    if (R.mode == 2) ras_block<double, float, true, true, NT>(R.R, R.meta_lev, R.meta_sl, vj, zj, loc, bras_smem);
+    else if (R.mode == 1) ras_block<double, float, true, false, NT>(R.R, R.meta_lev, R.meta_sl, vj, zj, loc, bras_smem);
+    else ras_block<double, float, false, false, NT>(R.R, R.meta_lev, R.meta_sl, vj, zj, loc, bras_smem);
+}
+
 // v /= sqrt(nn2[0])  (nn2 > 0: a shell whose norm vanished has left the batch)
 __global__ void k_scale_by_norm(double *__restrict__ v, int64_t n, const double *__restrict__ nn2) {
     const double sc = 1.0 / sqrt(nn2[0]);
@@ -248,18 +302,22 @@ struct csdyn_batch {
     hipEvent_t fork = nullptr, ready = nullptr;
     double *hred = nullptr;  // pinned: [nshell][2 * kRedStride], then the persistent step's error flag
     std::map<std::pair<uint64_t, int>, hipGraphExec_t> graphs;
-    // persistent step (every shell with a one-level FP32 preconditioner, at most 16 shells)
-    bool persist_ok = false;
+    // phase-batched and persistent steps (every shell with a one-level FP32 preconditioner, at most 16
+    // shells, N >= 16)
+    bool desc_ok = false;              // descriptors built: the phase-batched step is available
+    bool persist_ok = false;           // the persistent step is available (switched off in this build)
+    size_t ras_lds = 0, op_lds = 0;    // dynamic LDS of the RAS and stencil phases
     std::vector<csd::StepShell> hsh;  // host copies of the device descriptors
     csd::StepShell *dsh = nullptr;    // device descriptors (workspace)
     int *order = nullptr;             // device: shells by decreasing size (workspace)
     int *ctr = nullptr;               // device counters (workspace)
     size_t step_lds = 0;
     int step_grid = 0;
-    std::map<std::pair<uint64_t, int>, hipGraphExec_t> pgraphs;
+    std::map<std::pair<uint64_t, int>, hipGraphExec_t> pgraphs, phgraphs;
     ~csdyn_batch() {
         for (auto &kv : graphs) hipGraphExecDestroy(kv.second);
         for (auto &kv : pgraphs) hipGraphExecDestroy(kv.second);
+        for (auto &kv : phgraphs) hipGraphExecDestroy(kv.second);
         for (auto &b : sh) {
             if (b.join) hipEventDestroy(b.join);
             if (b.st) hipStreamDestroy(b.st);
@@ -328,15 +386,17 @@ static void step_counts(const StepShell &S, int cnt[kPhases]) {
     cnt[8] = chunks;
 }
 
-// Descriptors of the persistent step when every shell qualifies (one-level
-// FP32 preconditioner, at most 16 shells, N >= 16 so that the 16 x 16 stencil
-// tile has threads for its edge-face records), else persist_ok stays false.
-static int32_t setup_persistent(csdyn_batch *bt, const csdyn_ras *const *pcs, Carver &c) {
+// Descriptors of the phase-batched and persistent steps when every shell
+// qualifies (one-level FP32 preconditioner, at most 16 shells, N >= 16 so that
+// the 16 x 16 stencil tile has threads for its edge-face records), else
+// desc_ok stays false.
+static int32_t setup_descriptors(csdyn_batch *bt, const csdyn_ras *const *pcs, Carver &c) {
     bt->dsh = c.take<StepShell>(bt->nshell);
     bt->order = c.take<int>(bt->nshell);
     bt->ctr = c.take<int>(kStepCounters);
-    if (!kPersistentStepEnabled || bt->nshell > kMaxPersistShells || !pcs) return CSDYN_OK;
-    size_t lds = sizeof(double) * (OpLds<kStepTile, kStepTile>::SIZE + (kMaxChunk + 1) * 8);
+    if (bt->nshell > kMaxPersistShells || !pcs) return CSDYN_OK;
+    const size_t op_lds = sizeof(double) * (OpLds<kStepTile, kStepTile>::SIZE + (kMaxChunk + 1) * 8);
+    size_t lds = op_lds, ras_lds = 16;
     bt->hsh.assign(bt->nshell, StepShell());
     for (int i = 0; i < bt->nshell; ++i) {
         const BShell &b = bt->sh[i];
@@ -346,8 +406,10 @@ static int32_t setup_persistent(csdyn_batch *bt, const csdyn_ras *const *pcs, Ca
             clear_error();
             return CSDYN_OK;
         }
+        if (S.ras.threads != 256 && S.ras.threads != 512 && S.ras.threads != 1024) return CSDYN_OK;
         S.has_pc = 1;
         lds = std::max(lds, S.ras.lds_bytes);
+        ras_lds = std::max(ras_lds, S.ras.lds_bytes);
         const csdyn_opctx *ctx = b.ctx;
         const int n = ctx->g.n, nr = ctx->g.nr;
         S.g = ctx->dg;
@@ -377,17 +439,100 @@ static int32_t setup_persistent(csdyn_batch *bt, const csdyn_ras *const *pcs, Ca
     std::vector<int> order(bt->nshell);
     for (int i = 0; i < bt->nshell; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return bt->sh[a].n > bt->sh[b].n; });
+    CSD_HIP(hipMemcpy(bt->dsh, bt->hsh.data(), sizeof(StepShell) * bt->nshell, hipMemcpyHostToDevice));
+    CSD_HIP(hipMemcpy(bt->order, order.data(), sizeof(int) * bt->nshell, hipMemcpyHostToDevice));
+    CSD_HIP(hipFuncSetAttribute((const void *)k_batch_ras<256>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                int(ras_lds)));
+    CSD_HIP(hipFuncSetAttribute((const void *)k_batch_ras<512>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                int(ras_lds)));
+    CSD_HIP(hipFuncSetAttribute((const void *)k_batch_ras<1024>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                int(ras_lds)));
+    CSD_HIP(hipFuncSetAttribute((const void *)k_batch_phase<3>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                int(op_lds)));
+    bt->ras_lds = ras_lds;
+    bt->op_lds = op_lds;
+    bt->desc_ok = true;
+    if (!kPersistentStepEnabled) return CSDYN_OK;
     int dev = 0, ncu = 0, per = 0;
     CSD_HIP(hipGetDevice(&dev));
     CSD_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     CSD_HIP(hipFuncSetAttribute((const void *)k_arnoldi_step, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
     CSD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_arnoldi_step, kStepThreads, lds));
     if (per < 1) return CSDYN_OK;
-    CSD_HIP(hipMemcpy(bt->dsh, bt->hsh.data(), sizeof(StepShell) * bt->nshell, hipMemcpyHostToDevice));
-    CSD_HIP(hipMemcpy(bt->order, order.data(), sizeof(int) * bt->nshell, hipMemcpyHostToDevice));
     bt->step_lds = lds;
     bt->step_grid = ncu * per;
     bt->persist_ok = true;
+    return CSDYN_OK;
+}
+
+// Arnoldi step j of the shells in `mask` as one launch per phase, then the
+// read-back of each shell's dot products.
+static int32_t issue_step_phases(csdyn_batch *bt, uint64_t mask, int j, hipStream_t s) {
+    PhaseArgs A{bt->dsh, bt->order, mask, j, bt->nshell};
+    int grid[kPhases] = {};
+    double ras_bytes = 0.0, op_bytes = 0.0, orth_bytes = 0.0;
+    int64_t cells = 0, n_all = 0;
+    for (int i = 0; i < bt->nshell; ++i) {
+        if (!(mask >> i & 1)) continue;
+        const StepShell &S = bt->hsh[i];
+        for (int q = 0; q < kPhases; ++q) grid[q] += S.cnt[q];
+        const double vb = double(S.n) * 8.0;
+        ras_bytes += S.ras.bytes;
+        op_bytes += 2 * vb;
+        orth_bytes += vb * ((j + 2) + (j + 3) + 2);
+        cells += S.n / 4;
+        n_all += S.n;
+    }
+    auto go = [&](auto ph_c, size_t lds) -> int32_t {
+        constexpr int PH = decltype(ph_c)::value;
+        if (grid[PH] > 0)
+            hipLaunchKernelGGL(k_batch_phase<PH>, dim3(unsigned(grid[PH])), dim3(kStepThreads), lds, s, A);
+        CSD_HIP(hipGetLastError());
+        return CSDYN_OK;
+    };
+    using std::integral_constant;
+    {
+        ProfScope ps("batch_ras_f32", cells, ras_bytes, s);
+        auto ras = [&](auto nt_c) -> int32_t {
+            constexpr int NT = decltype(nt_c)::value;
+            PhaseArgs B = A;
+            B.mask = 0;
+            int g = 0;
+            for (int i = 0; i < bt->nshell; ++i)
+                if ((mask >> i & 1) && bt->hsh[i].ras.threads == NT) {
+                    B.mask |= uint64_t(1) << i;
+                    g += bt->hsh[i].cnt[0];
+                }
+            if (g > 0) hipLaunchKernelGGL(k_batch_ras<NT>, dim3(unsigned(g)), dim3(NT), bt->ras_lds, s, B);
+            CSD_HIP(hipGetLastError());
+            return CSDYN_OK;
+        };
+        CSD_TRY(ras(integral_constant<int, 256>()));
+        CSD_TRY(ras(integral_constant<int, 512>()));
+        CSD_TRY(ras(integral_constant<int, 1024>()));
+    }
+    {
+        ProfScope ps("batch_op_edges", cells, 0.0, s);
+        CSD_TRY(go(integral_constant<int, 1>(), 0));
+        CSD_TRY(go(integral_constant<int, 2>(), 0));
+    }
+    {
+        ProfScope ps("batch_op_main", cells, op_bytes, s);
+        CSD_TRY(go(integral_constant<int, 3>(), bt->op_lds));
+    }
+    {
+        ProfScope ps("batch_orth", n_all, orth_bytes, s);
+        CSD_TRY(go(integral_constant<int, 4>(), 0));
+        CSD_TRY(go(integral_constant<int, 5>(), 0));
+        CSD_TRY(go(integral_constant<int, 6>(), 0));
+        CSD_TRY(go(integral_constant<int, 7>(), 0));
+        CSD_TRY(go(integral_constant<int, 8>(), 0));
+    }
+    for (int i = 0; i < bt->nshell; ++i) {
+        if (!(mask >> i & 1)) continue;
+        CSD_HIP(hipMemcpyAsync(bt->hred + size_t(i) * 2 * kRedStride, bt->sh[i].red, sizeof(double) * 2 * kRedStride,
+                               hipMemcpyDeviceToHost, s));
+    }
     return CSDYN_OK;
 }
 
@@ -428,13 +573,14 @@ static int32_t issue_step_persistent(csdyn_batch *bt, uint64_t mask, int j, hipS
     return CSDYN_OK;
 }
 
-static int32_t pgraph_for(csdyn_batch *bt, uint64_t mask, int j, hipStream_t s0, hipGraphExec_t &out) {
+static int32_t pgraph_for(csdyn_batch *bt, int mode, uint64_t mask, int j, hipStream_t s0, hipGraphExec_t &out) {
+    auto &graphs = mode == 2 ? bt->phgraphs : bt->pgraphs;
     auto key = std::make_pair(mask, j);
-    auto it = bt->pgraphs.find(key);
-    if (it != bt->pgraphs.end()) { out = it->second; return CSDYN_OK; }
+    auto it = graphs.find(key);
+    if (it != graphs.end()) { out = it->second; return CSDYN_OK; }
     CSD_HIP(hipStreamBeginCapture(s0, hipStreamCaptureModeRelaxed));
     prof_suspend(true);
-    const int32_t rc = issue_step_persistent(bt, mask, j, s0);
+    const int32_t rc = mode == 2 ? issue_step_phases(bt, mask, j, s0) : issue_step_persistent(bt, mask, j, s0);
     prof_suspend(false);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(s0, &g);
@@ -453,7 +599,7 @@ static int32_t pgraph_for(csdyn_batch *bt, uint64_t mask, int j, hipStream_t s0,
         set_error("batch: graph instantiation failed: %s", hipGetErrorString(ei));
         return CSDYN_EHIP;
     }
-    bt->pgraphs[key] = ex;
+    graphs[key] = ex;
     out = ex;
     return CSDYN_OK;
 }
@@ -604,9 +750,12 @@ static int32_t batch_solve(csdyn_batch *bt, const double *const *bs, double *con
             for (int i = 0; i < ns; ++i)
                 if ((cyc >> i & 1) && S[i].live) act |= uint64_t(1) << i;
             if (!act) break;
-            if (mode == 2) {
+            if (mode == 2 && prof_active()) {
+                // while launches are being timed the phases run without a graph
+                CSD_TRY(issue_step_phases(bt, act, j, so));
+            } else if (mode >= 2) {
                 hipGraphExec_t ex;
-                CSD_TRY(pgraph_for(bt, act, j, so, ex));
+                CSD_TRY(pgraph_for(bt, mode, act, j, so, ex));
                 CSD_HIP(hipGraphLaunch(ex, so));
             } else if (mode == 1) {
                 hipGraphExec_t ex;
@@ -616,7 +765,7 @@ static int32_t batch_solve(csdyn_batch *bt, const double *const *bs, double *con
                 CSD_TRY(issue_step(bt, act, j, so));
             }
             CSD_HIP(hipStreamSynchronize(so));
-            if (mode == 2) {
+            if (mode == 3) {
                 int flag = 0;
                 std::memcpy(&flag, bt->hred + size_t(ns) * 2 * kRedStride, sizeof(int));
                 if (flag) {
@@ -733,15 +882,15 @@ extern "C" int32_t csdyn_batch_setup(int32_t nshell, const csdyn_opctx *const *o
     CSD_HIP(hipEventCreateWithFlags(&bt->ready, hipEventDisableTiming));
     CSD_HIP(hipStreamCreateWithFlags(&bt->origin, hipStreamNonBlocking));
     CSD_HIP(hipHostMalloc((void **)&bt->hred, sizeof(double) * (2 * kRedStride * nshell + 1), hipHostMallocDefault));
-    CSD_TRY(setup_persistent(bt.get(), pcs, c));
+    CSD_TRY(setup_descriptors(bt.get(), pcs, c));
     *out = bt.release();
     return CSDYN_OK;
 }
 
-extern "C" int32_t csdyn_batch_persistent(const csdyn_batch *bt, int32_t *available) {
+extern "C" int32_t csdyn_batch_modes(const csdyn_batch *bt, int32_t *modes) {
     clear_error();
-    if (!bt || !available) { set_error("batch: null argument"); return CSDYN_EINVAL; }
-    *available = bt->persist_ok ? 1 : 0;
+    if (!bt || !modes) { set_error("batch: null argument"); return CSDYN_EINVAL; }
+    *modes = 1 | 2 | (bt->desc_ok ? 4 : 0) | (bt->persist_ok ? 8 : 0);
     return CSDYN_OK;
 }
 
@@ -751,12 +900,14 @@ extern "C" int32_t csdyn_gmres_solve_batched(csdyn_batch *bt, const double *cons
     if (!bt || !b || !x) { set_error("batch: null argument"); return CSDYN_EINVAL; }
     for (int i = 0; i < bt->nshell; ++i)
         if (!b[i] || !x[i]) { set_error("batch: null vector for shell %d", i); return CSDYN_EINVAL; }
-    if (use_graph < 0 || use_graph > 2) { set_error("batch: use_graph must be 0, 1 or 2"); return CSDYN_EINVAL; }
-    if (use_graph == 2 && !bt->persist_ok) {
-        if (!kPersistentStepEnabled) set_error("batch: the persistent step is switched off in this build");
-        else
-            set_error("batch: the persistent step needs one-level FP32 preconditioners on every shell, at most %d "
-                      "shells and N >= %d", kMaxPersistShells, kStepTile);
+    if (use_graph < 0 || use_graph > 3) { set_error("batch: use_graph must be 0, 1, 2 or 3"); return CSDYN_EINVAL; }
+    if (use_graph == 3 && !kPersistentStepEnabled) {
+        set_error("batch: the persistent step is switched off in this build");
+        return CSDYN_EINVAL;
+    }
+    if (use_graph >= 2 && !(use_graph == 2 ? bt->desc_ok : bt->persist_ok)) {
+        set_error("batch: use_graph = %d needs one-level FP32 preconditioners on every shell, at most %d shells and "
+                  "N >= %d", use_graph, kMaxPersistShells, kStepTile);
         return CSDYN_EINVAL;
     }
     return batch_solve(bt, b, x, use_graph, (hipStream_t)stream, stats);

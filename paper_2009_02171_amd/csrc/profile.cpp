@@ -31,6 +31,7 @@ thread_local bool t_suspended = false;
 }  // namespace
 
 void prof_suspend(bool on) { t_suspended = on; }
+bool prof_active() { return g_on.load(std::memory_order_relaxed) && !t_suspended; }
 
 ProfScope::ProfScope(const char *name, int64_t size, double bytes, hipStream_t s, double flops) : s_(s) {
     if (!g_on.load(std::memory_order_relaxed) || t_suspended) return;

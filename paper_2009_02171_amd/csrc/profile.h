@@ -24,6 +24,8 @@ class ProfScope {
 // While a thread captures a graph its launches are not timed (an event pair
 // recorded during capture would become graph nodes).
 void prof_suspend(bool on);
+// True while launches are being timed on this thread (profiling on, not suspended).
+bool prof_active();
 
 // Per-phase times of one solve (the breakdown of a preconditioned iteration
 // into the outer operator, the fine RAS sweeps, the coarse solve and the

@@ -543,6 +543,7 @@ int32_t ras_view_f32(const csdyn_ras *pc, RasView &v) {
     v.meta_sl = f.meta_sl;
     v.nsd = f.nsd;
     v.mode = f.vec ? 2 : (f.lds_ring ? 1 : 0);
+    v.threads = f.threads;
     v.lds_bytes = f.lds_bytes;
     v.bytes = double(f.nnz) * 4 + double(4 * (f.box_cells + f.owned_cells)) * sizeof(double);
     return CSDYN_OK;

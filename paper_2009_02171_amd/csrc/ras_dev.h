@@ -327,6 +327,7 @@ __device__ __forceinline__ void ras_block(const DevRas<TF> &R, int meta_lev, int
 struct RasView {
     DevRas<float> R;
     int meta_lev = 0, meta_sl = 0, nsd = 0, mode = 0;
+    int threads = 256;  // workgroup width of the sweeps: 256, 512 or 1024
     size_t lds_bytes = 0;
     double bytes = 0;  // algorithmic bytes of one apply (FP32 factors once, FP64 gather and owned write)
 };

@@ -100,6 +100,35 @@ PERSISTENT_OFF = ("the persistent step is switched off: its first solve did not 
                   "(twice, the second time with relaxed polls); the cause is not shown")
 
 
+@pytest.mark.parametrize("kind", [0, 1])
+def test_phase_batched_step_matches_eager(kind):
+    """One launch per phase for all shells (every shell's subdomain solves in one
+    launch, then the edge fills, stencil tiles and Gram-Schmidt blocks) gives the
+    eager batch's iterations and solutions bit for bit, on two solves in a row
+    (the second replays the captured step graphs)."""
+    import torch
+    from paper_2009_02171_amd import csdyn
+    ops, pcs, bs = [], [], []
+    for s, (n, ek) in enumerate(PSHELLS):
+        op = csdyn.Operator(n, n, kind=kind, dt=1e-4, ekman=ek, pm=5.0)
+        ops.append(op)
+        pcs.append(csdyn.RAS(op, sub=(8, 8, 8), levels=1, precision=1))
+        bs.append(torch.from_numpy(inputs.rhs(n, n, seed=200 + s)).cuda())
+    batch = csdyn.Batch(ops, pcs, restart=30, maxit=2000, rtol=1e-8)
+    assert batch.available(csdyn.Batch.PHASES)
+    xe = [torch.zeros_like(b) for b in bs]
+    se, rc = batch.solve(bs, xe, use_graph=csdyn.Batch.EAGER)
+    assert rc == 0
+    for rep in range(2):
+        print(f"[phase-batched] kind={kind} solve {rep}", flush=True)
+        xp = [torch.zeros_like(b) for b in bs]
+        sp, rc = batch.solve(bs, xp, use_graph=csdyn.Batch.PHASES)
+        assert rc == 0
+        for a, b, sa, sb in zip(xe, xp, se, sp):
+            assert sa["iters"] == sb["iters"], (sa, sb)
+            assert torch.equal(a, b), float((a - b).abs().max())
+
+
 @pytest.mark.skip(reason=PERSISTENT_OFF)
 @pytest.mark.parametrize("kind", [0, 1])
 def test_persistent_step_matches_eager(kind):
@@ -138,9 +167,14 @@ def test_persistent_step_is_switched_off():
     op = csdyn.Operator(16, 16)
     pc = csdyn.RAS(op, sub=(8, 8, 8), levels=1, precision=1)
     b = csdyn.Batch([op], [pc])
-    assert not b.persistent_available
+    assert not b.persistent_available and b.available(csdyn.Batch.PHASES)
     with pytest.raises(csdyn.CsdynError):
         b.solve([op.empty().zero_()], [op.empty().zero_()], use_graph=csdyn.Batch.PERSISTENT)
+    op64 = csdyn.Operator(16, 16)
+    b64 = csdyn.Batch([op64], [csdyn.RAS(op64, sub=(8, 8, 8), levels=1, precision=0)])
+    assert not b64.available(csdyn.Batch.PHASES)   # FP64 preconditioner: modes 0 and 1 only
+    with pytest.raises(csdyn.CsdynError):
+        b64.solve([op64.empty().zero_()], [op64.empty().zero_()], use_graph=csdyn.Batch.PHASES)
 
 
 @pytest.mark.skip(reason=PERSISTENT_OFF)
@@ -159,8 +193,9 @@ def test_persistent_step_needs_fp32_one_level():
 def test_batched_uneven_shells_match_oracle():
     """The two smallest shells of the eight-shell batch (N = Nr = 24 and 32, their
     own Ekman numbers and right-hand sides), solved as one batch with the FP32
-    one-level preconditioner on 8^3 boxes (graph of per-shell branches), against
-    the oracle's FGMRES with its FP32 preconditioner emulation."""
+    one-level preconditioner on 8^3 boxes (graph of per-shell branches, and one
+    launch per phase for both shells, which must agree bit for bit), against the
+    oracle's FGMRES with its FP32 preconditioner emulation."""
     import torch
     from paper_2009_02171_amd import csdyn
     ops, pcs, bs, cases = [], [], [], []
@@ -175,6 +210,10 @@ def test_batched_uneven_shells_match_oracle():
     batch = csdyn.Batch(ops, pcs, restart=30, maxit=3000, rtol=1e-8)
     stats, rc = batch.solve(bs, xs, use_graph=True)
     assert rc == 0
+    xp = [torch.zeros_like(b) for b in bs]
+    sp, rc = batch.solve(bs, xp, use_graph=csdyn.Batch.PHASES)
+    assert rc == 0
+    assert all(torch.equal(a, b) for a, b in zip(xs, xp)) and [s["iters"] for s in sp] == [s["iters"] for s in stats]
     for (n, ek, b), x, st in zip(cases, xs, stats):
         pb = O.Problem(n, n, kind=0, dt=1e-4, ekman=ek, pm=5.0)
         xo, so, rco = O.gmres(pb, b, pc=O.Preconditioner(pb, sub=(8, 8, 8), levels=1, precision=1), flexible=True,
