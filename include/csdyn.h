@@ -309,6 +309,8 @@ typedef struct {
                                                    levels in device memory, 1 that ring in LDS, 2 the whole
                                                    subdomain vector in LDS */
     int32_t threads_fine, threads_coarse;     /* workgroup size of the sweep kernel (256, 512 or 1024) */
+    int32_t structures_fine, structures_coarse; /* distinct sweep structures: subdomains with the same
+                                                   dependency addresses share one stored copy */
 } csdyn_ras_info;
 int32_t csdyn_ras_get_info(const csdyn_ras *pc, csdyn_ras_info *info);
 

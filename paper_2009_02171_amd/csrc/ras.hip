@@ -84,7 +84,7 @@ struct OneLevel {
     int32_t *Lio = nullptr, *Lnext = nullptr, *Uio = nullptr, *Unext = nullptr;
     uint16_t *Laddr = nullptr, *Uaddr = nullptr;
     void *Lval = nullptr, *Uval = nullptr, *lin = nullptr, *lout = nullptr, *ring = nullptr;
-    int32_t *gio = nullptr, *Lmeta = nullptr, *Umeta = nullptr;
+    int32_t *gio = nullptr, *Lmeta = nullptr, *Umeta = nullptr, *perm = nullptr;
 
     static void layout(Carver &c, const HostRas &H, int precision, OneLevel &o) {
         const size_t fs = precision ? sizeof(float) : sizeof(double);
@@ -110,6 +110,7 @@ struct OneLevel {
         o.gio = c.take<int32_t>(H.gio.size());
         o.Lmeta = c.take<int32_t>(H.L.meta.size());
         o.Umeta = c.take<int32_t>(H.U.meta.size());
+        o.perm = c.take<int32_t>(H.perm.size());
     }
 
     int32_t upload(const HostRas &H) const {
@@ -134,6 +135,7 @@ struct OneLevel {
         CSD_HIP(up(gio, H.gio.data(), H.gio.size() * 4));
         CSD_HIP(up(Lmeta, H.L.meta.data(), H.L.meta.size() * 4));
         CSD_HIP(up(Umeta, H.U.meta.data(), H.U.meta.size() * 4));
+        CSD_HIP(up(perm, H.perm.data(), H.perm.size() * 4));
         // U-sweep records {L result, 1/u_ii}: the L sweep writes the first
         // half; padding lanes read results that are never written, so start at 0
         auto upload_as = [&](auto zero) -> int32_t {
@@ -164,6 +166,7 @@ struct OneLevel {
         R.lout = (TF2 *)lout;
         R.ring = (TF *)ring;
         R.gio = gio;
+        R.perm = perm;
         R.depth = vec ? 1 : depth;
         R.width = vec ? box_rows : width;
         return R;
@@ -405,6 +408,8 @@ static int32_t setup_level(csdyn_ras &R, const csdyn_opctx *ctx, const csdyn_ras
     R.info.box_in_lds_coarse = cl.vec ? 2 : cl.lds_ring;
     R.info.threads_fine = R.fine.threads;
     R.info.threads_coarse = o.levels >= 2 ? cl.threads : 0;
+    R.info.structures_fine = b.fine.addr_classes;
+    R.info.structures_coarse = hc ? hc->addr_classes : 0;
     return CSDYN_OK;
 }
 

@@ -41,6 +41,7 @@ struct DevRas {
                 // box vector: 1/u_ii per lane (dense, first half)
     TF *ring;   // [nsd][depth * width] when the ring is not in LDS
     const int32_t *gio;  // box vector: x index of each position, per subdomain from SdInfo::g0
+    const int32_t *perm; // [nsd] subdomain of each workgroup
     int depth, width;
 };
 
@@ -74,8 +75,8 @@ struct Item {
 // (five loads per item) and the U sweep reads 1/u_ii and its row's {position,
 // y index} instead of a record (seven loads).
 template <class TF, bool UPPER, bool VEC, class Rec>
-__device__ __forceinline__ void fetch_item(const DevSweep<TF> &S, const Rec *rec, int64_t g64, int64_t off, int w,
-                                           int nvalid, Item<TF> &X) {
+__device__ __forceinline__ void fetch_item(const DevSweep<TF> &S, const Rec *rec, int64_t g64, int64_t a64,
+                                           int64_t off, int w, int nvalid, Item<TF> &X) {
     const int lane = threadIdx.x % 64, ln = lane < nvalid ? lane : 0;
     const int64_t gpos = g64 + ln;
     if constexpr (UPPER && VEC) {  // {row position, y index} pairs and a dense 1/u_ii array
@@ -93,7 +94,7 @@ __device__ __forceinline__ void fetch_item(const DevSweep<TF> &S, const Rec *rec
     const int lastp = w > 0 ? (w - 1) / 2 : 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) X.val[j] = S.val[off + int64_t(min(j, lastp)) * 64 + ln];
-    const uint4 a = S.addr[gpos];
+    const uint4 a = S.addr[a64 + ln];
     X.addr[0] = a.x; X.addr[1] = a.y; X.addr[2] = a.z; X.addr[3] = a.w;
 }
 
@@ -153,8 +154,8 @@ struct Meta {
 // sweep, to its U-sweep record; the U sweep writes the owned rows to y
 // (restricted scatter).
 template <class TV, class TF, bool UPPER, bool LDS, bool VEC, int NT, class Rec>
-__device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int sl0, int64_t off0, int nlev, int nsl,
-                                      TF *ring, const Rec *rec, TF *lout, TV *y) {
+__device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int sl0, int asl0, int64_t off0, int nlev,
+                                      int nsl, TF *ring, const Rec *rec, TF *lout, TV *y) {
     constexpr int K = SweepShape<TF, NT>::K;
     const int lane = threadIdx.x % 64, nw = NT / 64;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
@@ -177,7 +178,7 @@ __device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int 
             const int offr = __builtin_amdgcn_readfirstlane(M.off[gg]);
             grp[k].wl = g < nsl ? wl : -1;
             grp[k].slot = __builtin_amdgcn_readfirstlane(M.slot[gg]);
-            fetch_item<TF, UPPER, VEC>(S, rec, int64_t(sl0 + gg) * 64, off0 + offr, wl & 15,
+            fetch_item<TF, UPPER, VEC>(S, rec, int64_t(sl0 + gg) * 64, int64_t(asl0 + gg) * 64, off0 + offr, wl & 15,
                                        ((wl >> 10) & 127) * (((wl >> 4) & 63) + 1), grp[k]);
         }
         fg += K * nw;
@@ -240,15 +241,17 @@ __device__ __forceinline__ void meta_pointers(unsigned char *base, int meta_lev,
     M.slot = M.wl + meta_sl;
 }
 
-// One subdomain per workgroup: gather x (coalesced over the L-sweep order),
-// L sweep, U sweep with restricted scatter.  The ring of the last `depth`
+// One subdomain per workgroup (item `blk` solves subdomain perm[blk]): gather
+// x (coalesced over the L-sweep order), L sweep, U sweep with restricted
+// scatter.  The ring of the last `depth`
 // levels is in LDS when LDS = true, else in the workspace; with VEC (always
 // in LDS) the whole box vector is there instead: the gather writes x into it,
 // the L sweep overwrites it with its results and the U sweep with its own.
 template <class TV, class TF, bool LDS, bool VEC, int NT>
 __device__ __forceinline__ void ras_block(const DevRas<TF> &R, int meta_lev, int meta_sl, const TV *__restrict__ x,
-                                          TV *__restrict__ y, int sdi, unsigned char *ras_smem) {
+                                          TV *__restrict__ y, int blk, unsigned char *ras_smem) {
     static_assert(LDS || !VEC, "the box vector lives in LDS");
+    const int sdi = __builtin_amdgcn_readfirstlane(R.perm[blk]);
     const SdInfo I = R.sd[sdi];
     const int ring_n = R.depth * R.width;
     TF *ring = LDS ? reinterpret_cast<TF *>(ras_smem + meta_bytes_for(meta_sl, meta_lev))
@@ -309,14 +312,15 @@ __device__ __forceinline__ void ras_block(const DevRas<TF> &R, int meta_lev, int
         }
     }
     __syncthreads();
-    sweep<TV, TF, false, LDS, VEC, NT>(R.L, M, I.slL0, I.offL0, I.levL1 - I.levL0, I.nslL, ring, R.lin,
+    sweep<TV, TF, false, LDS, VEC, NT>(R.L, M, I.slL0, I.aslL0, I.offL0, I.levL1 - I.levL0, I.nslL, ring, R.lin,
                                        reinterpret_cast<TF *>(R.lout), y);
     __syncthreads();  // L results visible; the U metadata replaces the L metadata
     if (int(threadIdx.x) < n16) md[threadIdx.x] = up0;
     if (int(threadIdx.x) + NT < n16) md[threadIdx.x + NT] = up1;
     for (int a = threadIdx.x + MU * NT; a < n16; a += NT) md[a] = uimg[a];
     __syncthreads();
-    sweep<TV, TF, true, LDS, VEC, NT>(R.U, M, I.slU0, I.offU0, I.levU1 - I.levU0, I.nslU, ring, R.lout, nullptr, y);
+    sweep<TV, TF, true, LDS, VEC, NT>(R.U, M, I.slU0, I.aslU0, I.offU0, I.levU1 - I.levU0, I.nslU, ring, R.lout,
+                                      nullptr, y);
 }
 
 // Device view of the fine one-level RAS of a preconditioner with FP32 factors

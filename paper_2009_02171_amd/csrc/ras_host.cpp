@@ -606,6 +606,59 @@ int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], 
             }
         }
     }
+    // Boxes of the same shape at the same place relative to the panel edges and
+    // the radial ends have the same sweep structure: each distinct address block
+    // is stored once and the subdomains point at it.
+    std::vector<int32_t> cls(H.nsd, 0);
+    for (int pass = 0; pass < 2; ++pass) {
+        SweepPack &P = pass ? H.U : H.L;
+        constexpr size_t kSl = 8 * 64;  // addresses per slice
+        std::vector<uint16_t> shared;
+        std::map<std::pair<uint64_t, int>, std::vector<int32_t>> stored;  // (hash, slices) -> first slices
+        std::vector<uint64_t> hs(H.nsd);
+#pragma omp parallel for schedule(dynamic, 4)
+        for (int s = 0; s < H.nsd; ++s) {
+            const SdInfo &I = H.sd[s];
+            const int sl0 = pass ? I.slU0 : I.slL0, nsl = pass ? I.nslU : I.nslL;
+            const uint16_t *blk = P.addr.data() + size_t(sl0) * kSl;
+            uint64_t h = 1469598103934665603ull;  // FNV-1a over the block
+            for (size_t a = 0, len = size_t(nsl) * kSl; a < len; ++a) h = (h ^ blk[a]) * 1099511628211ull;
+            hs[s] = h;
+        }
+        for (int s = 0; s < H.nsd; ++s) {
+            SdInfo &I = H.sd[s];
+            const int sl0 = pass ? I.slU0 : I.slL0, nsl = pass ? I.nslU : I.nslL;
+            const uint16_t *blk = P.addr.data() + size_t(sl0) * kSl;
+            const size_t len = size_t(nsl) * kSl;
+            auto &cand = stored[{hs[s], nsl}];
+            int32_t at = -1;
+            for (int32_t c0 : cand)
+                if (std::equal(blk, blk + len, shared.begin() + size_t(c0) * kSl)) { at = c0; break; }
+            if (at < 0) {
+                at = int32_t(shared.size() / kSl);
+                shared.insert(shared.end(), blk, blk + len);
+                cand.push_back(at);
+            }
+            (pass ? I.aslU0 : I.aslL0) = at;
+        }
+        P.addr.swap(shared);
+    }
+    {
+        std::map<std::pair<int32_t, int32_t>, int32_t> ids;
+        for (int s = 0; s < H.nsd; ++s) {
+            auto it = ids.emplace(std::make_pair(H.sd[s].aslL0, H.sd[s].aslU0), int32_t(ids.size())).first;
+            cls[s] = it->second;
+        }
+        H.addr_classes = int(ids.size());
+        // subdomains by structure, dealt to the L2 domains in runs
+        std::vector<int32_t> bycls(H.nsd);
+        std::iota(bycls.begin(), bycls.end(), 0);
+        std::stable_sort(bycls.begin(), bycls.end(), [&](int32_t a, int32_t b) { return cls[a] < cls[b]; });
+        H.perm.assign(H.nsd, -1);
+        size_t q = 0;
+        for (int x = 0; x < kXcds; ++x)
+            for (int b = x; b < H.nsd; b += kXcds) H.perm[b] = bycls[q++];
+    }
     // tail padding: the sweep kernel may read a fixed number of entries past a
     // slice's width; keep those reads inside the arrays
     for (SweepPack *P : {&H.L, &H.U}) {

@@ -38,7 +38,8 @@ struct SweepPack {
                                      // row; box vector: both sweeps, the row's position in the box vector
     std::vector<double> lane_diag;   // [nslice*64] U only: u_ii (0 on padding lanes)
     std::vector<double> val;         // [2 * pairs]
-    std::vector<uint16_t> addr;      // [8 * 64 * nslice] ring slot of the dependency
+    std::vector<uint16_t> addr;      // ring slot of the dependency: per subdomain a block of
+                                     // [8 * 64 * nsl] from slice SdInfo::asl*0; identical blocks stored once
     std::vector<int32_t> meta;       // [nsd][meta words] LDS metadata image of each subdomain's sweep
 };
 
@@ -47,6 +48,7 @@ struct SdInfo {
     int32_t nloc, nown;
     int32_t nrows;                   // rows of the box (4 per cell)
     int32_t slL0, nslL, slU0, nslU;  // first slice and number of slices of each sweep
+    int32_t aslL0, aslU0;            // first slice of the subdomain's block in each sweep's (shared) addresses
     int64_t g0;                      // box vector: first entry of the subdomain's gather list
     int64_t offL0, offU0;            // first value pair of each sweep
 };
@@ -61,6 +63,7 @@ constexpr size_t meta_bytes_for(int nsl, int nlev) {
 }
 
 constexpr int64_t kBoxVectorBytes = 90 * 1024;
+constexpr int kXcds = 8;  // L2 domains of the GPU; consecutive workgroups go to consecutive domains
 
 struct HostRas {
     int nsd = 0;
@@ -81,6 +84,12 @@ struct HostRas {
     int64_t nnz = 0;                     // factor entries (L and U, diagonal included)
     int64_t box_cells = 0, owned_cells = 0;
     int max_total_levels = 0;            // L + U levels of the deepest subdomain
+    // Workgroup b of a sweep launch solves subdomain perm[b].  Subdomains that
+    // share their address blocks are dealt to the same of the kXcds L2 domains
+    // (workgroup b runs on domain b mod kXcds), so each domain's L2 holds the
+    // addresses of a few structures, read from HBM once.
+    std::vector<int32_t> perm;
+    int addr_classes = 0;                // distinct (L, U) address structures
     int meta_words = 0;                  // int32 words of one metadata image (meta_bytes_for / 4)
 };
 
