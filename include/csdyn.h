@@ -205,6 +205,12 @@ typedef struct {
                              1: stop at max(atol, rtol ||b||) */
     int32_t timing;       /* 1: fill stats.t_ms from HIP events recorded on `stream` around each
                              phase (creates the events on first use on a thread); 0: no events */
+    int32_t device_steps; /* 0: the host forms each step's Hessenberg column and Givens rotation
+                             from the step's read-back (one wait per step); k in [1, 32]: the
+                             device forms them and the host reads the convergence state once per
+                             k steps, the next k steps already enqueued, so up to 2k - 1 steps
+                             past convergence are computed and discarded (for solves whose steps
+                             are short next to a host round trip) */
 } csdyn_gmres_opts;
 
 /* Phases of stats.t_ms (the breakdown of a preconditioned iteration in Sec. 4.3
@@ -239,7 +245,8 @@ int32_t csdyn_gmres_workspace_bytes(const csdyn_opctx *ctx, const csdyn_gmres_op
  * two-level one synchronises with the host inside), solved by FGMRES
  * (restart = o->restart, CGS orthogonalisation, o->orth must be 0) in lock
  * step: one Arnoldi step of all active shells at a time, one host
- * synchronisation per step for the batch.  use_graph selects how a step runs:
+ * synchronisation per step for the batch (o->timing and o->device_steps are
+ * not used).  use_graph selects how a step runs:
  * 0, the shells' kernels on their own streams; 1, the same captured as a
  * hipGraph per (active set, step index), kept in the handle for later solves;
  * 2, one launch per phase for all active shells together (every shell's RAS

@@ -38,7 +38,7 @@ class RasOpts(C.Structure):
 class GmresOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("maxit", C.c_int32), ("flexible", C.c_int32),
                 ("rtol", C.c_double), ("atol", C.c_double), ("orth", C.c_int32), ("rhs_relative", C.c_int32),
-                ("timing", C.c_int32)]
+                ("timing", C.c_int32), ("device_steps", C.c_int32)]
 
 
 class GmresStats(C.Structure):
@@ -291,9 +291,10 @@ class Solver:
     """Restarted (F)GMRES with a workspace kept across solves (csdyn_gmres_solve)."""
 
     def __init__(self, op: Operator, pc: RAS | None = None, restart=30, maxit=1000, flexible=False, rtol=1e-8,
-                 atol=0.0, orth=0, rhs_relative=False, timing=False):
+                 atol=0.0, orth=0, rhs_relative=False, timing=False, device_steps=0):
         self.op, self.pc = op, pc
-        self.opts = GmresOpts(restart, maxit, int(flexible), rtol, atol, orth, int(rhs_relative), int(timing))
+        self.opts = GmresOpts(restart, maxit, int(flexible), rtol, atol, orth, int(rhs_relative), int(timing),
+                              int(device_steps))
         nb = C.c_size_t()
         _check(lib().csdyn_gmres_workspace_bytes(op.h, C.byref(self.opts), C.byref(nb)),
                "csdyn_gmres_workspace_bytes")

@@ -64,7 +64,17 @@ struct Gmres {
     // Phase (profile.h) under which the preconditioner's time is recorded when
     // the solve is timed; -1: the preconditioner records its own phases.
     int m_phase = -1;
+    // device_steps = k > 0: the Hessenberg column, Givens rotation and residual
+    // estimate of each Arnoldi step are formed on the device, and the host
+    // reads the convergence state once per group of k steps, with the next
+    // group already enqueued (steps enqueued past convergence are discarded).
+    // 0: the host forms them from each step's read-back.
+    int device_steps = 0;
     T *V = nullptr, *Z = nullptr, *z = nullptr, *r = nullptr, *tmp = nullptr, *partial = nullptr, *red = nullptr;
+    double *gs = nullptr;  // device rotation state (device_steps > 0), gs_elems(m) entries
+    // H [(m + 1) x m] (rotated, upper triangular), cs [m], sn [m], g [m + 1],
+    // then the header: estimate, stopped, converged, breakdown, steps done.
+    static constexpr int gs_elems(int m) { return (m + 1) * m + 3 * m + 1 + 8; }
 
     static size_t bytes(int64_t n, int m, bool flexible);
     void carve(Carver &c, int64_t n_, int m_, bool flexible_);

@@ -48,6 +48,58 @@ __global__ void k_scale_arnoldi(T *w, int64_t n, const T *ww, const T *nn) {
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) w[i] *= a;
 }
 
+// Rotation state of a restart cycle: H, cs, sn and the header cleared, g =
+// (beta, 0, ...).
+__global__ void k_hess_reset(double *gs, int m, double beta) {
+    const int total = (m + 1) * m + 3 * m + 1 + 8;
+    for (int a = threadIdx.x; a < total; a += blockDim.x) gs[a] = 0.0;
+    __syncthreads();
+    if (threadIdx.x == 0) gs[(m + 1) * m + 2 * m] = beta;
+}
+
+// Arnoldi step j's Hessenberg column from the step's reductions (the same
+// arithmetic as the host path): h_ij = V_i . w (plus the re-orthogonalisation
+// pass), h_{j+1,j} = ||w||; the previous rotations applied to the column, the
+// new rotation chosen to zero h_{j+1,j}, g rotated, the estimate |g_{j+1}|
+// compared with tol.  Once the cycle has stopped (converged, happy breakdown
+// or a non-finite column) later steps leave the state alone.
+template <class T>
+__global__ void k_hessenberg(const T *red, int nred, double *gs, int j, int m, double tol) {
+    if (threadIdx.x != 0) return;
+    double *H = gs, *cs = H + (m + 1) * m, *sn = cs + m, *g = sn + m, *hd = g + m + 1;
+    if (hd[1] != 0.0) return;
+    for (int i = 0; i <= j; ++i)
+        H[i * m + j] = nred == 2 ? double(red[i]) : double(red[i]) + double(red[kRedStride + i]);
+    const double ww = double(red[kRedStride - 1]);
+    const double nn = double(red[nred * kRedStride - 1]);
+    const double hn = sqrt(fmax(nn, 0.0));
+    hd[4] = double(j + 1);
+    if (!isfinite(hn) || !isfinite(ww)) {
+        hd[3] = 1.0;
+        hd[1] = 1.0;
+        return;
+    }
+    for (int i = 0; i < j; ++i) {
+        const double a = H[i * m + j], c = H[(i + 1) * m + j];
+        H[i * m + j] = cs[i] * a + sn[i] * c;
+        H[(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+    }
+    const double a = H[j * m + j], c = hn;
+    const double den = hypot(a, c);
+    cs[j] = a / den;
+    sn[j] = c / den;
+    H[j * m + j] = den;
+    H[(j + 1) * m + j] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    const double est = fabs(g[j + 1]);
+    hd[0] = est;
+    if (est <= tol || hn <= 1e-14 * sqrt(ww)) {
+        hd[2] = 1.0;
+        hd[1] = 1.0;
+    }
+}
+
 template <class T>
 __global__ void k_axpby(T a, const T *__restrict__ x, T b, T *__restrict__ y, int64_t n) {
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
@@ -268,6 +320,7 @@ void Gmres<T>::carve(Carver &c, int64_t n_, int m_, bool flexible_) {
     tmp = c.take<T>(n);
     partial = c.take<T>(kPartialElems);
     red = c.take<T>(3 * kRedStride);
+    gs = c.take<double>(gs_elems(m));
 }
 
 template <class T>
@@ -292,6 +345,7 @@ int32_t Gmres<T>::norm(const T *v, double &out, hipStream_t s) {
 // nesting depth on this thread and device (the two-level preconditioner runs
 // a coarse solve inside an iteration of the outer solve), kept until the
 // process ends.
+constexpr size_t kReadBackElems = 2048;  // doubles: a step's reductions or a cycle's rotation state
 struct ReadBack {
     void *buf[2] = {nullptr, nullptr};
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -308,7 +362,7 @@ static int32_t readback_for(int depth, ReadBack *&rb) {
         if (e.first == key) { rb = &e.second; return CSDYN_OK; }
     ReadBack r;
     for (int i = 0; i < 2; ++i) {
-        CSD_HIP(hipHostMalloc(&r.buf[i], sizeof(double) * 3 * kRedStride, hipHostMallocDefault));
+        CSD_HIP(hipHostMalloc(&r.buf[i], sizeof(double) * kReadBackElems, hipHostMallocDefault));
         CSD_HIP(hipEventCreateWithFlags(&r.ev[i], hipEventDisableTiming));
     }
     pool.emplace_back(key, r);
@@ -387,6 +441,69 @@ int32_t Gmres<T>::solve(const DevFn<T> &A, const DevFn<T> *M, const T *b, T *x, 
         CSD_LAUNCHED();
         return CSDYN_OK;
     };
+    // device-resident form of step j: the same kernels without the read-back,
+    // then the rotation on the device
+    auto launch_step_dev = [&](int j) -> int32_t {
+        T *vj = V + size_t(j) * n, *w = V + size_t(j + 1) * n;
+        T *zj = flexible ? Z + size_t(j) * n : z;
+        if (M) CSD_TRY(apply_M(vj, zj));
+        else CSD_TRY(Vec<T>::copy(zj, vj, n, s));
+        CSD_TRY(apply_A(zj, w));
+        PhaseScope ps(PH_ORTH, s);
+        CSD_TRY(Vec<T>::mdot(V, n, j + 1, w, partial, red, s));
+        if (orth == 0) {
+            CSD_TRY(Vec<T>::mupdate(w, V, n, j + 1, red, partial, red + kRedStride, s));
+        } else {
+            CSD_TRY(Vec<T>::mupdate_dot(w, V, n, j + 1, red, partial, red + kRedStride, s));
+            CSD_TRY(Vec<T>::mupdate(w, V, n, j + 1, red + kRedStride, partial, red + 2 * kRedStride, s));
+        }
+        hipLaunchKernelGGL(k_hessenberg<T>, dim3(1), dim3(64), 0, s, red, nred, gs, j, m, tol);
+        CSD_LAUNCHED();
+        hipLaunchKernelGGL(k_scale_arnoldi<T>, ew_grid(n), dim3(256), 0, s, w, n, red + kRedStride - 1,
+                           red + nred * kRedStride - 1);
+        CSD_LAUNCHED();
+        return CSDYN_OK;
+    };
+    // One restart cycle of at most `limit` steps with device-resident steps:
+    // groups of device_steps steps, each followed by a read-back of the
+    // rotation header; group k + 1 is enqueued before the host waits for group
+    // k.  On return H (rotated) and gv hold the cycle's state for the steps done.
+    auto cycle_dev = [&](int limit, double beta_c, int &jdone, bool &stop, double &est_out) -> int32_t {
+        hipLaunchKernelGGL(k_hess_reset, dim3(1), dim3(256), 0, s, gs, m, beta_c);
+        CSD_LAUNCHED();
+        const int hdr = (m + 1) * m + 3 * m + 1;
+        int enq = 0, groups = 0, waited = 0;
+        auto enqueue_group = [&]() -> int32_t {
+            const int j1 = std::min(limit, enq + device_steps);
+            for (int j = enq; j < j1; ++j) CSD_TRY(launch_step_dev(j));
+            CSD_HIP(hipMemcpyAsync(rb->buf[groups % 2], gs + hdr, sizeof(double) * 8, hipMemcpyDeviceToHost, s));
+            CSD_HIP(hipEventRecord(rb->ev[groups % 2], s));
+            enq = j1;
+            ++groups;
+            return CSDYN_OK;
+        };
+        CSD_TRY(enqueue_group());
+        stop = false;
+        for (;;) {
+            if (enq < limit) CSD_TRY(enqueue_group());
+            CSD_HIP(hipEventSynchronize(rb->ev[waited % 2]));
+            const double *hd = static_cast<const double *>(rb->buf[waited % 2]);
+            ++waited;
+            if (hd[3] != 0.0) { set_error("gmres: non-finite Arnoldi vector"); return CSDYN_EBREAKDOWN; }
+            if (hd[1] != 0.0) { stop = true; break; }
+            if (waited == groups && enq >= limit) break;
+        }
+        // the rotation state of the steps done (a later group may still be running)
+        double *hb = static_cast<double *>(rb->buf[waited % 2]);
+        CSD_HIP(hipMemcpyAsync(hb, gs, sizeof(double) * (hdr + 8), hipMemcpyDeviceToHost, s));
+        CSD_HIP(hipStreamSynchronize(s));
+        jdone = int(hb[hdr + 4]);
+        est_out = hb[hdr];
+        for (int i = 0; i <= jdone && i <= m; ++i)
+            for (int k = 0; k < jdone; ++k) H[size_t(i) * m + k] = hb[size_t(i) * m + k];
+        for (int i = 0; i <= jdone; ++i) gv[i] = hb[(m + 1) * m + 2 * m + i];
+        return CSDYN_OK;
+    };
     int iters = 0, restarts = 0;
     bool conv = beta0 <= tol;
     double est = beta0, beta = beta0;
@@ -396,6 +513,12 @@ int32_t Gmres<T>::solve(const DevFn<T> &A, const DevFn<T> *M, const T *b, T *x, 
         std::fill(gv.begin(), gv.end(), 0.0);
         gv[0] = beta;
         int jdone = 0;
+        if (device_steps > 0) {
+            bool stop = false;
+            CSD_TRY(cycle_dev(std::min(m, maxit - iters), beta, jdone, stop, est));
+            iters += jdone;
+            if (stop) conv = true;
+        } else {
         // With lookahead, step j + 1 is enqueued before the host waits for
         // step j's numbers (unless the convergence rate so far says step j
         // will be the last), so the device does not idle between steps; a
@@ -440,6 +563,7 @@ int32_t Gmres<T>::solve(const DevFn<T> &A, const DevFn<T> *M, const T *b, T *x, 
             if (est <= tol || happy) { conv = true; break; }
             if (!more) break;
             if (!ahead) CSD_TRY(launch_step(j + 1));
+        }
         }
         for (int i = jdone - 1; i >= 0; --i) {
             double acc = gv[i];

@@ -643,6 +643,7 @@ extern "C" int32_t csdyn_gmres_solve(const csdyn_opctx *ctx, const csdyn_ras *pc
     if (pc && pc->fine_ctx->g.n != ctx->g.n) { set_error("gmres: preconditioner built for another grid"); return CSDYN_EINVAL; }
     if (o->rhs_relative != 0 && o->rhs_relative != 1) { set_error("gmres: rhs_relative must be 0 or 1"); return CSDYN_EINVAL; }
     if (o->timing != 0 && o->timing != 1) { set_error("gmres: timing must be 0 or 1"); return CSDYN_EINVAL; }
+    if (o->device_steps < 0 || o->device_steps > 32) { set_error("gmres: device_steps must be in [0, 32]"); return CSDYN_EINVAL; }
     Carver c(ws);
     SolveLayout L;
     solve_layout(c, ctx, o, L);
@@ -650,6 +651,7 @@ extern "C" int32_t csdyn_gmres_solve(const csdyn_opctx *ctx, const csdyn_ras *pc
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = L.gm.n, ncell = n / 4;
     L.gm.orth = o->orth;
+    L.gm.device_steps = o->device_steps;
     if (o->timing) CSD_TRY(phase_timer_begin(s));
     struct TimerGuard {  // uninstalls the timer on every early return
         ~TimerGuard() { phase_timer_abort(); }
