@@ -87,6 +87,7 @@ def lib():
         _lib.ref_subdomain_solve.argtypes = [P(Grid), P(Op), i32, C.c_int, C.c_int, d, d]
         _lib.ref_subdomain_solve_p.argtypes = [P(Grid), P(Op), i32, C.c_int, C.c_int, C.c_int, d, d]
         _lib.ref_project.argtypes = [P(Grid), P(Op), d, d]
+        _lib.ref_advect.argtypes = [P(Grid), C.c_int32, d, C.c_int32, d, d]
         _lib.ref_gmres_solve.argtypes = [P(Grid), P(Op), C.c_void_p, P(GmresOpts), d, d, P(GmresStats)]
         _lib.ref_gmres_solve_hist.argtypes = [P(Grid), P(Op), C.c_void_p, P(GmresOpts), d, d, P(GmresStats), d,
                                               C.c_int]
@@ -310,6 +311,49 @@ def ilu0(a):
     rc = lib().ref_ilu0_csr(a.shape[0], _lp(rp), _ip(ci), _dp(v))
     import scipy.sparse as sp
     return rc, sp.csr_matrix((v, ci, rp), shape=a.shape)
+
+
+def advect(n: int, nr: int, kind_a: int, a: np.ndarray, kind_b: int, b: np.ndarray) -> np.ndarray:
+    """(a . grad) b in the conservative form div(a b_c) per Cartesian component
+    (Sec. 3.2, eq. nonlinearint), a with the ghost rules of system kind_a, b
+    with those of kind_b; scalar part 0."""
+    g = Grid(n, nr, RI, RO)
+    a = np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
+    b = np.ascontiguousarray(b, dtype=np.float64).reshape(-1)
+    out = np.zeros_like(a)
+    _check(lib().ref_advect(C.byref(g), kind_a, _dp(a), kind_b, _dp(b), _dp(out)), "advect")
+    return out.reshape(6, nr, n, n, 4)
+
+
+def nonlinear(n: int, nr: int, u: np.ndarray, B: np.ndarray, cB: float):
+    """Sec. 3.1, eq. nonlinearoperator: f1 = -(u.grad)u + cB (B.grad)B,
+    f3 = (B.grad)u - (u.grad)B (u: no-slip ghosts, B: pseudo-vacuum)."""
+    f1 = -advect(n, nr, 0, u, 0, u) + cB * advect(n, nr, 1, B, 1, B)
+    f3 = advect(n, nr, 1, B, 0, u) - advect(n, nr, 0, u, 1, B)
+    return f1, f3
+
+
+def cn_rhs(pb: Problem, xhat: np.ndarray, fn: np.ndarray, c1: float, fm=None, c2: float = 0.0, gf=None,
+           c3: float = 0.0) -> np.ndarray:
+    """Sec. 3.1, eqs. tsvelocity / tsmag in this system's scaling: the vector
+    part of (I + (Delta t/2) L) xhat = 2 xhat - A xhat (the vector rows of A are
+    I - (Delta t/2) L and do not read the scalar part), plus the explicit terms;
+    scalar part 0."""
+    x = np.array(xhat, dtype=np.float64).reshape(pb.shape())
+    out = 2.0 * x - apply(pb, x) + c1 * np.asarray(fn).reshape(pb.shape())
+    if fm is not None and c2 != 0.0:
+        out += c2 * np.asarray(fm).reshape(pb.shape())
+    if gf is not None and c3 != 0.0:
+        out += c3 * np.asarray(gf).reshape(pb.shape())
+    out[..., 3] = 0.0
+    return out
+
+
+def step3_state(pb: Problem, x: np.ndarray) -> np.ndarray:
+    """Sec. 3.1, eq. ubtilde: (u~ - dt grad_h P, P) from a solution (u~, P)."""
+    out = project(pb, x)
+    out[..., 3] = np.asarray(x).reshape(pb.shape())[..., 3]
+    return out
 
 
 def project_pressure(pb: Problem, b):

@@ -549,6 +549,99 @@ int ref_operator_rows(const ref_grid *g, const ref_op *op, const double *x, int6
     return REF_OK;
 }
 
+/* ------------------------------------------------ exported: nonlinear terms */
+/* Value of component c of field x at an extended position, with the ghost
+ * rules of the context's system (readings R4, R6). */
+static double val_ext(const ctx *cx, const double *x, int p, int i, int j, int k, int c) {
+    sink s = {0};
+    s.mode = 1; s.x = x; s.acc = 0.0;
+    emit_x(cx, &s, p, i, j, k, c, 1.0);
+    return s.acc;
+}
+
+/* One-sided outward advective flux through lateral face `face` of cell
+ * (p,i,j,k), from panel p's own extended values: (a_f . sqrt(g) g^m) b_f,
+ * with a_f and b_f the means of the cell's and its face neighbour's values
+ * (eq. nonlinearint with the face values of reading R3); out[c], c < 3. */
+static void adv_lat_flux(const ctx *ca, const double *a, const ctx *cb, const double *b, int p, int i, int j, int k,
+                         int face, double out[3]) {
+    const ref_grid *g = &ca->g;
+    double h = hs_of(g), r = r_of(g, k);
+    metric m;
+    int ni = i, nj = j, mm;
+    if (face <= 1) { ni = face == 0 ? i - 1 : i + 1; mm = 0; metric_at(p, -QPI + (face == 0 ? i : i + 1) * h, xi_of(g, j), r, &m); }
+    else { nj = face == 2 ? j - 1 : j + 1; mm = 1; metric_at(p, xi_of(g, i), -QPI + (face == 2 ? j : j + 1) * h, r, &m); }
+    double sg = (face == 1 || face == 3) ? 1.0 : -1.0;
+    double af = 0.0;
+    for (int d = 0; d < 3; d++)
+        af += m.sqrtg * m.gcon[mm][d] * 0.5 * (val_ext(ca, a, p, i, j, k, d) + val_ext(ca, a, p, ni, nj, k, d));
+    for (int c = 0; c < 3; c++)
+        out[c] = sg * af * 0.5 * (val_ext(cb, b, p, i, j, k, c) + val_ext(cb, b, p, ni, nj, k, c));
+}
+
+/* (a . grad) b at cell (p,i,j,k) in the conservative form div(a b_c) of each
+ * Cartesian component c (Sec. 3.2, eq. nonlinearint; with Cartesian
+ * components the Christoffel source terms of the contravariant form vanish):
+ * (1/V) * sum over the six faces of the outward flux times the face area,
+ * the flux through a panel-edge face being the mean of the two panels'
+ * one-sided fluxes (reading R5). */
+static void adv_cell(const ctx *ca, const double *a, const ctx *cb, const double *b, int p, int i, int j, int k,
+                     double out[3]) {
+    const ref_grid *g = &ca->g;
+    double h = hs_of(g), hr = hr_of(g);
+    metric mc; metric_at(p, xi_of(g, i), xi_of(g, j), r_of(g, k), &mc);
+    double V = mc.sqrtg * h * h * hr;
+    double wl = h * hr / V, wr = h * h / V;
+    double acc[3] = {0.0, 0.0, 0.0}, f1[3], f2[3];
+    for (int f = 0; f < 4; f++) {
+        if (!is_seam_face(g, i, j, f)) {
+            adv_lat_flux(ca, a, cb, b, p, i, j, k, f, f1);
+            for (int c = 0; c < 3; c++) acc[c] += wl * f1[c];
+            continue;
+        }
+        int t = f <= 1 ? j : i;
+        const face_info *fi = &ca->st->fc[(p * 4 + f) * g->n + t];
+        int iq, jq; edge_cell(g, fi->eq, fi->tq, &iq, &jq);
+        adv_lat_flux(ca, a, cb, b, p, i, j, k, f, f1);
+        adv_lat_flux(ca, a, cb, b, fi->q, iq, jq, k, fi->eq, f2);
+        for (int c = 0; c < 3; c++) acc[c] += wl * 0.5 * (f1[c] - f2[c]);
+    }
+    for (int sgn = -1; sgn <= 1; sgn += 2) {
+        metric mf; metric_at(p, xi_of(g, i), xi_of(g, j), r_of(g, k + 0.5 * sgn), &mf);
+        double af = 0.0;
+        for (int d = 0; d < 3; d++)
+            af += mf.sqrtg * mf.gcon[2][d] * 0.5 * (val_ext(ca, a, p, i, j, k, d) + val_ext(ca, a, p, i, j, k + sgn, d));
+        for (int c = 0; c < 3; c++)
+            acc[c] += wr * sgn * af * 0.5 * (val_ext(cb, b, p, i, j, k, c) + val_ext(cb, b, p, i, j, k + sgn, c));
+    }
+    for (int c = 0; c < 3; c++) out[c] = acc[c];
+}
+
+/* out = (a . grad) b on every cell (vector part; the scalar part is 0).  a
+ * takes the ghost rules of system kind_a, b those of kind_b (0: no-slip
+ * velocity, 1: pseudo-vacuum magnetic field). */
+int ref_advect(const ref_grid *g, int32_t kind_a, const double *a, int32_t kind_b, const double *b, double *out) {
+    ref_op oa = {kind_a, 0.0, 0.0, 1.0}, ob = {kind_b, 0.0, 0.0, 1.0};
+    seam_tab sa, sb; ctx ca, cb;
+    int rc = make_ctx(g, &oa, &sa, &ca);
+    if (rc) return rc;
+    rc = make_ctx(g, &ob, &sb, &cb);
+    if (rc) { free_seams(&sa); return rc; }
+    int n = g->n;
+    for (int p = 0; p < 6; p++)
+        for (int k = 0; k < g->nr; k++)
+            for (int j = 0; j < n; j++)
+                for (int i = 0; i < n; i++) {
+                    double v[3];
+                    adv_cell(&ca, a, &cb, b, p, i, j, k, v);
+                    for (int c = 0; c < 3; c++) out[unk(g, p, i, j, k, c)] = v[c];
+                    out[unk(g, p, i, j, k, 3)] = 0.0;
+                }
+    free_seams(&sa);
+    free_seams(&sb);
+    return REF_OK;
+}
+
 static int cmp_term(const void *a, const void *b) {
     int64_t x = ((const term *)a)->col, y = ((const term *)b)->col;
     return x < y ? -1 : x > y;
