@@ -431,6 +431,49 @@ int32_t csdyn_guess(csdyn_net *net, const csdyn_opctx *ctx, const double *b, con
 int32_t csdyn_march_rhs(const csdyn_opctx *ctx, const double *v, const double *f, double dt, double *b,
                         void *stream);
 
+/* ------------------------------------------------- the semi-implicit step
+ * Nonlinear terms of the momentum and induction equations (Sec. 3.1, eq.
+ * nonlinearoperator):
+ *   f1 = -(u . grad) u + cB (B . grad) B     (cB = 1/(E Pm)),
+ *   f3 =  (B . grad) u - (u . grad) B.
+ * Each (a . grad) b is the conservative finite-volume form div(a b_c) of each
+ * Cartesian component c (Sec. 3.2, eq. nonlinearint; in Cartesian components
+ * the Christoffel source terms of the contravariant form vanish): the sum over
+ * the cell's six faces of (a_f . sqrt(g) g^m) (b_c)_f times the face area over
+ * the cell volume, a_f and b_f the means of the two cells' values; beyond a
+ * panel edge the neighbour is the ghost (cubic interpolation, as in the
+ * operator), beyond a wall the wall ghost of the field's own system (u:
+ * no-slip, B: pseudo-vacuum); through a panel-edge face the mean of the two
+ * panels' one-sided fluxes.
+ * vp, bp: the VP and BP contexts of one grid; u, B: device vectors in the
+ * solver's layout (component 3, the pressures, is not read); f1, f3: device,
+ * same layout, component 3 set to 0; f1 and f3 must not alias each other or
+ * the inputs.  ws: csdyn_nonlinear_workspace_bytes (the ghost values of u
+ * and B), else CSDYN_ENOMEM.  Asynchronous on `stream`. */
+int32_t csdyn_nonlinear_workspace_bytes(const csdyn_opctx *ctx, size_t *bytes);
+int32_t csdyn_nonlinear(const csdyn_opctx *vp, const csdyn_opctx *bp, const double *u, const double *B,
+                        double cB, double *f1, double *f3, void *ws, size_t ws_bytes, void *stream);
+
+/* Right-hand side of Step 1 (Sec. 3.1, eqs. tsvelocity and tsmag) in this
+ * system's scaling (Delta t = 2 E dt; the vector rows of A are
+ * I - (Delta t / 2) L):
+ *   rhs[c] = 2 xhat[c] - (A xhat)[c] + c1 fn[c] + c2 fm[c] + c3 gf[c], c < 3,
+ *   rhs[3] = 0,
+ * i.e. xhat + (Delta t / 2) L xhat + the explicit terms; with the
+ * Adams-Bashforth combination c1 = 1.5 Delta t, c2 = -0.5 Delta t (the first
+ * step: c1 = Delta t, c2 = 0).  xhat = \hat u^n (or \hat B^n): the vector
+ * part of csdyn_project applied to the previous state (eq. ubhat; the vector
+ * rows of A do not read the scalar part).  fm and gf may be NULL when their
+ * coefficients are 0 (gf: an optional prescribed body force).  rhs must not
+ * alias an input.  Asynchronous on `stream`. */
+int32_t csdyn_cn_rhs(const csdyn_opctx *ctx, const double *xhat, const double *fn, const double *fm,
+                     const double *gf, double c1, double c2, double c3, double *rhs, void *stream);
+
+/* Step 3 (Sec. 3.1, eq. ubtilde) kept as the next step's state: state[c] =
+ * x[c] - dt (grad_h P)[c] for c < 3 (as csdyn_project) and state[3] = x[3]
+ * (P^{n+1} or P_b^{n+1}).  x and state must not alias.  Asynchronous. */
+int32_t csdyn_step3_state(const csdyn_opctx *ctx, const double *x, double *state, void *stream);
+
 /* ----------------------------------------------------------------- profile
  * Optional timing of every kernel launch by HIP events recorded on the launch
  * stream.  begin() creates a pool of max_launches event pairs; until end(),

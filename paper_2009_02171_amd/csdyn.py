@@ -135,6 +135,12 @@ SIGNATURES = {
     "csdyn_guess": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
                                 C.c_void_p, C.c_size_t, C.c_void_p, _P(GuessInfo)]),
     "csdyn_march_rhs": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]),
+    "csdyn_nonlinear_workspace_bytes": (C.c_int32, [C.c_void_p, _P(C.c_size_t)]),
+    "csdyn_nonlinear": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "csdyn_cn_rhs": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                 C.c_double, C.c_double, C.c_void_p, C.c_void_p]),
+    "csdyn_step3_state": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "csdyn_last_error": (C.c_char_p, []),
 }
 
@@ -574,4 +580,39 @@ def march_rhs(op: Operator, v, f, dt, out=None, stream=None):
     """b = (v + dt f, 0) on the device (csdyn_march_rhs)."""
     out = op.empty() if out is None else out
     _check(lib().csdyn_march_rhs(op.h, _ptr(v), _ptr(f), dt, _ptr(out), _stream(stream)), "csdyn_march_rhs")
+    return out
+
+
+class Nonlinear:
+    """f1 = -(u.grad)u + cB (B.grad)B and f3 = (B.grad)u - (u.grad)B
+    (csdyn_nonlinear), with the ghost workspace kept across calls."""
+
+    def __init__(self, vp: Operator, bp: Operator):
+        self.vp, self.bp = vp, bp
+        nb = C.c_size_t()
+        _check(lib().csdyn_nonlinear_workspace_bytes(vp.h, C.byref(nb)), "csdyn_nonlinear_workspace_bytes")
+        self.ws = _workspace(nb.value, vp.device)
+        self.nbytes = nb.value
+
+    def __call__(self, u, B, cB, f1=None, f3=None, stream=None):
+        f1 = self.vp.empty() if f1 is None else f1
+        f3 = self.vp.empty() if f3 is None else f3
+        _check(lib().csdyn_nonlinear(self.vp.h, self.bp.h, _ptr(u), _ptr(B), cB, _ptr(f1), _ptr(f3), _ptr(self.ws),
+                                     self.nbytes, _stream(stream)), "csdyn_nonlinear")
+        return f1, f3
+
+
+def cn_rhs(op: Operator, xhat, fn, c1, fm=None, c2=0.0, gf=None, c3=0.0, out=None, stream=None):
+    """(2 xhat - A xhat + c1 fn + c2 fm + c3 gf, 0) on the device (csdyn_cn_rhs)."""
+    out = op.empty() if out is None else out
+    _check(lib().csdyn_cn_rhs(op.h, _ptr(xhat), _ptr(fn), _ptr(fm) if fm is not None else None,
+                              _ptr(gf) if gf is not None else None, c1, c2, c3, _ptr(out), _stream(stream)),
+           "csdyn_cn_rhs")
+    return out
+
+
+def step3_state(op: Operator, x, out=None, stream=None):
+    """(x_vec - dt grad_h P, P) on the device (csdyn_step3_state)."""
+    out = op.empty() if out is None else out
+    _check(lib().csdyn_step3_state(op.h, _ptr(x), _ptr(out), _stream(stream)), "csdyn_step3_state")
     return out

@@ -135,3 +135,26 @@ class DriftingField:
 
     def field(self, alpha: float) -> np.ndarray:
         return np.ascontiguousarray(np.einsum("pjicq,kq->pkjic", self.angular(alpha), self.radial, optimize=True))
+
+
+def benchmark_b0(n: int, nr: int, ri: float = RI, ro: float = RO) -> np.ndarray:
+    """The benchmark's initial magnetic field (Sec. 4.2, eq. initial) at the
+    cell centres in Cartesian components, float64 [6, Nr, N, N, 4] with the
+    scalar slot 0 (theta colatitude from +z, phi longitude):
+        B_r     = 5/8 (9 r^3 - 4 (4 + 3 (ri + ro)) r^2 + 6 (4 ro + ri (4 + 3 ro)) r - 48 ri ro) / r cos(theta)
+        B_theta = -15/4 (r - ri)(r - ro)(3 r - 4) / r sin(theta)
+        B_phi   = 15/8 sin(pi (r - ri)) sin(2 theta)."""
+    d = cell_directions(n)                                   # [6, N, N, 3]
+    th = np.arccos(np.clip(d[..., 2], -1.0, 1.0))[:, None]   # [6, 1, N, N]
+    ph = np.arctan2(d[..., 1], d[..., 0])[:, None]
+    r = (ri + (np.arange(nr) + 0.5) * (ro - ri) / nr)[None, :, None, None]
+    br = 5.0 / 8.0 * (9 * r**3 - 4 * (4 + 3 * (ri + ro)) * r**2 + 6 * (4 * ro + ri * (4 + 3 * ro)) * r
+                      - 48 * ri * ro) / r * np.cos(th)
+    bt = -15.0 / 4.0 * (r - ri) * (r - ro) * (3 * r - 4) / r * np.sin(th)
+    bp = 15.0 / 8.0 * np.sin(np.pi * (r - ri)) * np.sin(2 * th)
+    st, ct, sp, cp = np.sin(th), np.cos(th), np.sin(ph), np.cos(ph)
+    out = np.zeros((6, nr, n, n, 4))
+    out[..., 0] = br * st * cp + bt * ct * cp - bp * sp
+    out[..., 1] = br * st * sp + bt * ct * sp + bp * cp
+    out[..., 2] = br * ct - bt * st
+    return out
