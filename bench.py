@@ -66,7 +66,8 @@ WORKLOADS = {
     "paper_mesh": dict(n=144, nr=168, sub=(24, 24, 28), levels=2, flexible=True,
                        desc="VP and BP solves on the strong-scaling mesh of the paper, N=144, Nr=168 (20.9M cells, "
                             "83.6M unknowns per system), 1296 subdomains of 24x24x28 (the paper's 1296-core split), "
-                            "two- and three-level RAS, FGMRES(30), the paper's tolerance pairs"),
+                            "two- and three-level RAS, FGMRES(30), the paper's tolerance pairs, case P8 "
+                            "(E=1e-3, Pm=8) at Delta t=1e-5"),
     "learned": dict(n=64, nr=64, sub=(16, 16, 16), levels=2, flexible=True,
                     desc="200-step VP+BP march, N=Nr=64 (1.57M cells), two-level RAS 384x16^3 + coarse 32^3x6, "
                          "FGMRES(30) to ||r|| <= 1e-8 ||b||; train on steps 1-100, evaluate 101-200"),
@@ -170,6 +171,9 @@ def main():
     ap.add_argument("--learned-eval-steps", type=int, default=30,
                     help="large workload: evaluation steps of the bounded learned-guess leg")
     ap.add_argument("--no-small", action="store_true", help="large workload: skip the small-configuration leg")
+    ap.add_argument("--dynamics", choices=("surrogate", "full"), default="surrogate",
+                    help="learned march: the step without nonlinear terms driven by a drifting forcing, or the "
+                         "semi-implicit step with nonlinear terms from the benchmark's initial field")
     ap.add_argument("--no-three-level", action="store_true", help="large workload: skip the three-level forms")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -390,6 +394,7 @@ def main():
 
 
 # The paper's numbers on this mesh (Table strong, 1296 to 10368 cores, Sunway TaihuLight): context only.
+PAPER_DT = 1e-5  # Table strong's time step (viscous time units)
 PAPER_STRONG = {"cores": [1296, 2592, 5184, 10368],
                 "VTBE": {"iters": [3.0, 3.0, 3.0, 3.0], "time_s": [6.65, 3.41, 1.77, 0.92]},
                 "PPBE_1level": {"iters": [144.9, 154.0, 158.0, 151.1], "time_s": [29.69, 16.90, 9.60, 5.24]},
@@ -411,7 +416,8 @@ def paper_mesh(args, wl):
     forms = {"plain_fp64_2level": (0, 2), "plain_fp64_3level": (0, 3), "mixed_fp32_3level": (1, 3)}
     res = {}
     for name, kind, seed in (("VP", csdyn.VP, 1), ("BP", csdyn.BP, 2)):
-        op = csdyn.Operator(n, nr, kind=kind, dt=1e-4, ekman=1e-3, pm=5.0)
+        # case P8 (E = 1e-3, Pm = 8) at the table's time step Delta t = 1e-5, i.e. dt = Delta t / (2 E)
+        op = csdyn.Operator(n, nr, kind=kind, dt=PAPER_DT / (2 * 1e-3), ekman=1e-3, pm=8.0)
         b = torch.from_numpy(inputs.rhs(n, nr, seed)).cuda()
         x = torch.zeros_like(b)
         sol = None
@@ -512,7 +518,7 @@ def learned_leg(args):
     wl = WORKLOADS["learned"]
     t0 = time.perf_counter()
     res = march.run(n=wl["n"], nr=wl["nr"], sub=wl["sub"], levels=wl["levels"], train_steps=args.learned_train_steps,
-                    eval_steps=args.learned_eval_steps, log=log)
+                    eval_steps=args.learned_eval_steps, log=log, dynamics=args.dynamics)
     torch.cuda.synchronize()
     sp = res["solves_per_s"]
     sysd = {}
@@ -525,7 +531,8 @@ def learned_leg(args):
         sysd[name]["guess_quality_median"] = r["guess_quality_median"]
     return {
         "workload": (f"VP+BP march N=Nr={wl['n']}, two-level RAS 384x16^3, FGMRES(30) to ||r|| <= 1e-8 ||b||; "
-                     f"{args.learned_train_steps} training steps, {args.learned_eval_steps} evaluation steps"),
+                     f"{args.learned_train_steps} training steps, {args.learned_eval_steps} evaluation steps; "
+                     f"{args.dynamics} dynamics"),
         "forms": {"plain_a (FP64 PC, previous solution)": round(sp["plain_a"], 3),
                   "mixed_a (FP32 PC, previous solution)": round(sp["mixed_a"], 3),
                   "mixed_b (FP32 PC, extrapolation)": round(sp["mixed_b"], 3),
@@ -682,7 +689,7 @@ def learned(args, wl):
     from paper_2009_02171_amd import csdyn, inputs, march
     t0 = time.perf_counter()
     res = march.run(n=wl["n"], nr=wl["nr"], sub=wl["sub"], levels=wl["levels"], train_steps=args.train_steps,
-                    eval_steps=args.eval_steps, log=log)
+                    eval_steps=args.eval_steps, log=log, dynamics=args.dynamics)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     # the network's kernels, each launch timed with HIP events: 3 inferences and 3 training steps
@@ -722,7 +729,7 @@ def learned(args, wl):
         "data": "synthetic",
         "config": {"workload": wl["desc"], "n": wl["n"], "nr": wl["nr"], "subdomain": list(wl["sub"]),
                    "levels": wl["levels"], "drift_rad_per_step": res["drift_rad_per_step"],
-                   "network_params": res["param_count"]},
+                   "network_params": res["param_count"], "dynamics": res["dynamics"]},
         "forms": {v: round(x, 4) for v, x in sp.items()},
         "speedup_mixed_learned_vs_plain": round(res["speedup_mixed_c_vs_plain_a"], 4),
         "systems": res["systems"],

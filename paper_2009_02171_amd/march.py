@@ -1,5 +1,8 @@
-"""Time march that feeds the learned initial guess (a stand-in for the
-paper's time loop, Sec. 3.1 Steps 1-3, without the nonlinear terms).
+"""Time march that feeds the learned initial guess.  With dynamics = "full"
+the step is the paper's semi-implicit step (Sec. 3.1, Steps 1-3, step.py:
+nonlinear terms, Adams-Bashforth, Crank-Nicolson right-hand sides) from the
+benchmark's initial field; with the default "surrogate" it is the step
+without its nonlinear terms, driven by a drifting forcing, as follows.
 
 Per step n and per system (VP: velocity / pressure, BP: magnetic field /
 pseudo-pressure), with a longitudinally drifting forcing
@@ -41,9 +44,9 @@ def _sync():
 
 
 class _System:
-    def __init__(self, kind, n, nr, sub, levels, dt, ekman, pm, net_seed, widths, dev):
+    def __init__(self, kind, n, nr, sub, levels, dt, ekman, pm, net_seed, widths, dev, op=None):
         self.kind = kind
-        self.op = csdyn.Operator(n, nr, kind=kind, dt=dt, ekman=ekman, pm=pm, device=dev)
+        self.op = op if op is not None else csdyn.Operator(n, nr, kind=kind, dt=dt, ekman=ekman, pm=pm, device=dev)
         self.pc = {p: csdyn.RAS(self.op, sub=sub, levels=levels, coarse_rtol=0.1, coarse_restart=30,
                                 coarse_maxit=200, precision=p) for p in (0, 1)}
         self.sol = {p: csdyn.Solver(self.op, self.pc[p], restart=30, maxit=3000, flexible=True, rtol=1e-8,
@@ -59,12 +62,27 @@ class _System:
 
 def run(n=64, nr=64, sub=(16, 16, 16), levels=2, train_steps=100, eval_steps=100, train_iters=8, replay=16,
         lr=5e-4, dt=1e-4, ekman=1e-3, pm=5.0, forcing_seed=4, widths=inputs.NET_WIDTHS, log=print,
-        dev="cuda"):
+        dev="cuda", dynamics="surrogate", force_amp=0.0):
+    """dynamics = "surrogate": b^n = (v^{n-1} + dt f^n, 0) with the drifting
+    forcing (the systems decoupled); "full": the semi-implicit step of Sec. 3.1
+    (step.SemiImplicit: nonlinear terms, Adams-Bashforth, Crank-Nicolson
+    right-hand sides) from the benchmark's initial magnetic field and u = 0,
+    with the drifting field times force_amp as a body force on the velocity
+    (standing in for the buoyancy of the temperature equation, not built)."""
     dev = torch.device(dev)
-    systems = {"VP": _System(csdyn.VP, n, nr, sub, levels, dt, ekman, pm, 5, widths, dev),
-               "BP": _System(csdyn.BP, n, nr, sub, levels, dt, ekman, pm, 6, widths, dev)}
-    forcing = inputs.DriftingField(n, nr, forcing_seed)
     rng = np.random.default_rng(forcing_seed + 1000)
+    sim = None
+    if dynamics == "full":
+        from . import step as step_mod
+        sim = step_mod.SemiImplicit(n, nr, dt=dt, ekman=ekman, pm=pm, solvers=False,
+                                    b0=torch.from_numpy(inputs.benchmark_b0(n, nr)).to(dev), device=dev)
+    elif dynamics != "surrogate":
+        raise ValueError(f"dynamics must be 'surrogate' or 'full', not {dynamics!r}")
+    systems = {"VP": _System(csdyn.VP, n, nr, sub, levels, dt, ekman, pm, 5, widths, dev,
+                             op=sim.vp if sim else None),
+               "BP": _System(csdyn.BP, n, nr, sub, levels, dt, ekman, pm, 6, widths, dev,
+                             op=sim.bp if sim else None)}
+    forcing = inputs.DriftingField(n, nr, forcing_seed)
 
     def force(step):  # synthetic input, generated on the host
         return torch.from_numpy(forcing.field(DRIFT * step)).to(dev)
@@ -89,18 +107,26 @@ def run(n=64, nr=64, sub=(16, 16, 16), levels=2, train_steps=100, eval_steps=100
             raise RuntimeError(f"solve did not reach 1e-8: rc={rc} {st}")
         return x, st, el
 
+    pending = {}
+
     def advance(s, x, name, bnorm):
         out = s.op.project(x)
-        s.state.copy_(out)
+        if sim is None:
+            s.state.copy_(out)
+        else:
+            pending[name] = x
         div[name].append(float(torch.linalg.norm(out[..., 3])) / bnorm)
         s.hist.append(x)
         del s.hist[:-(replay + 2)]
 
     total = train_steps + eval_steps
     for step in range(1, total + 1):
-        f = force(step)
+        f = force(step) if sim is None or force_amp else None
+        if sim is not None:
+            sim.force, sim.force_scale = (f, force_amp) if force_amp else (None, 1.0)
+            bs, fterms = sim.rhs()
         for name, s in systems.items():
-            b = s.rhs(f, dt)
+            b = s.rhs(f, dt) if sim is None else bs[name]
             h = s.hist
             if step <= train_steps:
                 x0 = s.guess(h[-1], h[-2])[0] if len(h) >= 2 else (h[-1].clone() if h else torch.zeros_like(b))
@@ -159,10 +185,15 @@ def run(n=64, nr=64, sub=(16, 16, 16), levels=2, train_steps=100, eval_steps=100
             for k in ("res_net", "res_extrap", "res_minres"):
                 netd[name][k][-1] /= st["bnorm"]
             advance(s, bn, name, st["bnorm"])
+        if sim is not None:
+            sim.advance(pending, fterms)
         if step % 10 == 0 or step == total:
             log(f"step {step}/{total} done")
 
-    out = {"n": n, "nr": nr, "train_steps": train_steps, "eval_steps": eval_steps, "drift_rad_per_step": DRIFT,
+    out = {"n": n, "nr": nr, "dynamics": dynamics, "force_amp": force_amp if sim is not None else None,
+           "state_absmax": ({name: float(sim.state[name][..., :3].abs().max()) for name in systems}
+                            if sim is not None else None),
+           "train_steps": train_steps, "eval_steps": eval_steps, "drift_rad_per_step": DRIFT,
            "train_s": train_s, "param_count": systems["VP"].net.nparam, "systems": {}}
     for name in systems:
         r = {}
