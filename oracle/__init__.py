@@ -39,7 +39,8 @@ class Grid(C.Structure):
 
 
 class Op(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("dt", C.c_double), ("ekman", C.c_double), ("pm", C.c_double)]
+    _fields_ = [("kind", C.c_int32), ("dt", C.c_double), ("ekman", C.c_double), ("pm", C.c_double),
+                ("ra", C.c_double), ("pr", C.c_double)]
 
 
 class RasOpts(C.Structure):
@@ -87,7 +88,7 @@ def lib():
         _lib.ref_subdomain_solve.argtypes = [P(Grid), P(Op), i32, C.c_int, C.c_int, d, d]
         _lib.ref_subdomain_solve_p.argtypes = [P(Grid), P(Op), i32, C.c_int, C.c_int, C.c_int, d, d]
         _lib.ref_project.argtypes = [P(Grid), P(Op), d, d]
-        _lib.ref_advect.argtypes = [P(Grid), C.c_int32, d, C.c_int32, d, d]
+        _lib.ref_advect.argtypes = [P(Grid), C.c_int32, d, C.c_int32, d, C.c_int32, d]
         _lib.ref_gmres_solve.argtypes = [P(Grid), P(Op), C.c_void_p, P(GmresOpts), d, d, P(GmresStats)]
         _lib.ref_gmres_solve_hist.argtypes = [P(Grid), P(Op), C.c_void_p, P(GmresOpts), d, d, P(GmresStats), d,
                                               C.c_int]
@@ -117,18 +118,20 @@ class Problem:
     """A grid (N x N x Nr cells per panel, Sec. 3.2) and one of the two systems."""
     n: int
     nr: int
-    kind: int = 0            # 0 velocity-pressure, 1 magnetic / pseudo-pressure
+    kind: int = 0            # 0 velocity-pressure, 1 magnetic / pseudo-pressure, 2 velocity-temperature
     dt: float = 1e-4
     ekman: float = 1e-3
     pm: float = 5.0
     ri: float = RI
     ro: float = RO
+    ra: float = 100.0        # modified Rayleigh number (VT only)
+    pr: float = 1.0          # Prandtl number (VT only)
 
     def grid(self):
         return Grid(self.n, self.nr, self.ri, self.ro)
 
     def op(self):
-        return Op(self.kind, self.dt, self.ekman, self.pm)
+        return Op(self.kind, self.dt, self.ekman, self.pm, self.ra, self.pr)
 
     @property
     def ncell(self):
@@ -313,23 +316,29 @@ def ilu0(a):
     return rc, sp.csr_matrix((v, ci, rp), shape=a.shape)
 
 
-def advect(n: int, nr: int, kind_a: int, a: np.ndarray, kind_b: int, b: np.ndarray) -> np.ndarray:
+def advect(n: int, nr: int, kind_a: int, a: np.ndarray, kind_b: int, b: np.ndarray, scalar: bool = False) -> np.ndarray:
     """(a . grad) b in the conservative form div(a b_c) per Cartesian component
     (Sec. 3.2, eq. nonlinearint), a with the ghost rules of system kind_a, b
-    with those of kind_b; scalar part 0."""
+    with those of kind_b; the vector part of b (scalar part of the result 0),
+    or with scalar=True the scalar part (vector part of the result 0)."""
     g = Grid(n, nr, RI, RO)
     a = np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
     b = np.ascontiguousarray(b, dtype=np.float64).reshape(-1)
     out = np.zeros_like(a)
-    _check(lib().ref_advect(C.byref(g), kind_a, _dp(a), kind_b, _dp(b), _dp(out)), "advect")
+    _check(lib().ref_advect(C.byref(g), kind_a, _dp(a), kind_b, _dp(b), int(scalar), _dp(out)), "advect")
     return out.reshape(6, nr, n, n, 4)
 
 
-def nonlinear(n: int, nr: int, u: np.ndarray, B: np.ndarray, cB: float):
+def nonlinear(n: int, nr: int, u: np.ndarray, B: np.ndarray, cB: float, T: np.ndarray | None = None):
     """Sec. 3.1, eq. nonlinearoperator: f1 = -(u.grad)u + cB (B.grad)B,
-    f3 = (B.grad)u - (u.grad)B (u: no-slip ghosts, B: pseudo-vacuum)."""
+    f3 = (B.grad)u - (u.grad)B (u: no-slip ghosts, B: pseudo-vacuum); with
+    the velocity-temperature state T = (u, Theta) also f2 = -(u.grad)Theta
+    (isothermal Theta ghosts) in the scalar slot."""
     f1 = -advect(n, nr, 0, u, 0, u) + cB * advect(n, nr, 1, B, 1, B)
     f3 = advect(n, nr, 1, B, 0, u) - advect(n, nr, 0, u, 1, B)
+    if T is None:
+        return f1, f3
+    f1 = f1 - advect(n, nr, 0, u, 2, T, scalar=True)
     return f1, f3
 
 

@@ -76,7 +76,7 @@
 #define REF_EBREAKDOWN (-5)
 
 typedef struct { int32_t n, nr; double ri, ro; } ref_grid;
-typedef struct { int32_t kind; double dt, ekman, pm; } ref_op;   /* kind 0 = VP, 1 = BP */
+typedef struct { int32_t kind; double dt, ekman, pm, ra, pr; } ref_op;   /* kind 0 = VP, 1 = BP, 2 = VT */
 
 static const double QPI = 0.78539816339744830962; /* pi/4 */
 
@@ -279,6 +279,8 @@ static void emit_x(const ctx *cx, sink *s, int p, int i, int j, int k, int c, do
         int kin = k < 0 ? 0 : g->nr - 1;
         if (cx->op.kind == 0) {
             emit_x(cx, s, p, i, j, kin, c, c < 3 ? -w : w);
+        } else if (cx->op.kind == 2) {   /* no-slip u, isothermal Theta = 0 */
+            emit_x(cx, s, p, i, j, kin, c, -w);
         } else {
             if (c < 3) {
                 double nr[3]; unit_radial(g, p, i, j, nr);
@@ -428,9 +430,31 @@ static void emit_divergence(const ctx *cx, sink *s, int p, int i, int j, int k, 
     }
 }
 
-/* One row of the system matrix (reading R7; Sec. 3.1). */
+/* One row of the system matrix (reading R7; Sec. 3.1).  Kind 2 (VT) is the
+ * velocity-temperature block of the VTBE (eq. tsvelocity, tstemperature) in
+ * the same scaling, Delta t / 2 = E dt: u rows with -(Delta t/2) R1(Theta) =
+ * -dt Ra/r_o Theta x, Theta row Theta - dt (E/Pr) lap Theta - (Delta t/2)
+ * R2(u) with R2(u) = r_i r_o / r^3 (x . u) (eq. linearoperator). */
 static void emit_row(const ctx *cx, sink *s, int p, int i, int j, int k, int c) {
     double dt = cx->op.dt, E = cx->op.ekman;
+    if (cx->op.kind == 2) {
+        const ref_grid *g = &cx->g;
+        double nr3[3]; unit_radial(g, p, i, j, nr3);
+        double r = r_of(g, k);
+        if (c < 3) {
+            emit_x(cx, s, p, i, j, k, c, 1.0);
+            emit_laplacian(cx, s, p, i, j, k, c, -dt * E);
+            if (c == 0) emit_x(cx, s, p, i, j, k, 1, -2.0 * dt);
+            if (c == 1) emit_x(cx, s, p, i, j, k, 0, 2.0 * dt);
+            emit_x(cx, s, p, i, j, k, 3, -dt * cx->op.ra / g->ro * r * nr3[c]);
+        } else {
+            emit_x(cx, s, p, i, j, k, 3, 1.0);
+            emit_laplacian(cx, s, p, i, j, k, 3, -dt * E / cx->op.pr);
+            for (int d = 0; d < 3; d++)
+                emit_x(cx, s, p, i, j, k, d, -dt * E * g->ri * g->ro / (r * r * r) * r * nr3[d]);
+        }
+        return;
+    }
     if (cx->op.kind == 0) {
         if (c < 3) {
             emit_x(cx, s, p, i, j, k, c, 1.0);
@@ -501,7 +525,7 @@ int ref_seam_tables(const ref_grid *g, int32_t *gq, int32_t *gfix, int32_t *gidx
 
 /* ------------------------------------------------------ exported: operator */
 static int make_ctx(const ref_grid *g, const ref_op *op, seam_tab *st, ctx *cx) {
-    if (check_grid(g) || !op || (op->kind != 0 && op->kind != 1)) return REF_EINVAL;
+    if (check_grid(g) || !op || op->kind < 0 || op->kind > 2 || (op->kind == 2 && !(op->pr > 0))) return REF_EINVAL;
     int rc = build_seams(g, st);
     if (rc) { free_seams(st); return rc; }
     cx->g = *g; cx->op = *op; cx->st = st;
@@ -564,7 +588,7 @@ static double val_ext(const ctx *cx, const double *x, int p, int i, int j, int k
  * with a_f and b_f the means of the cell's and its face neighbour's values
  * (eq. nonlinearint with the face values of reading R3); out[c], c < 3. */
 static void adv_lat_flux(const ctx *ca, const double *a, const ctx *cb, const double *b, int p, int i, int j, int k,
-                         int face, double out[3]) {
+                         int face, double out[4]) {
     const ref_grid *g = &ca->g;
     double h = hs_of(g), r = r_of(g, k);
     metric m;
@@ -575,7 +599,7 @@ static void adv_lat_flux(const ctx *ca, const double *a, const ctx *cb, const do
     double af = 0.0;
     for (int d = 0; d < 3; d++)
         af += m.sqrtg * m.gcon[mm][d] * 0.5 * (val_ext(ca, a, p, i, j, k, d) + val_ext(ca, a, p, ni, nj, k, d));
-    for (int c = 0; c < 3; c++)
+    for (int c = 0; c < 4; c++)
         out[c] = sg * af * 0.5 * (val_ext(cb, b, p, i, j, k, c) + val_ext(cb, b, p, ni, nj, k, c));
 }
 
@@ -586,17 +610,17 @@ static void adv_lat_flux(const ctx *ca, const double *a, const ctx *cb, const do
  * the flux through a panel-edge face being the mean of the two panels'
  * one-sided fluxes (reading R5). */
 static void adv_cell(const ctx *ca, const double *a, const ctx *cb, const double *b, int p, int i, int j, int k,
-                     double out[3]) {
+                     double out[4]) {
     const ref_grid *g = &ca->g;
     double h = hs_of(g), hr = hr_of(g);
     metric mc; metric_at(p, xi_of(g, i), xi_of(g, j), r_of(g, k), &mc);
     double V = mc.sqrtg * h * h * hr;
     double wl = h * hr / V, wr = h * h / V;
-    double acc[3] = {0.0, 0.0, 0.0}, f1[3], f2[3];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0}, f1[4], f2[4];
     for (int f = 0; f < 4; f++) {
         if (!is_seam_face(g, i, j, f)) {
             adv_lat_flux(ca, a, cb, b, p, i, j, k, f, f1);
-            for (int c = 0; c < 3; c++) acc[c] += wl * f1[c];
+            for (int c = 0; c < 4; c++) acc[c] += wl * f1[c];
             continue;
         }
         int t = f <= 1 ? j : i;
@@ -604,24 +628,27 @@ static void adv_cell(const ctx *ca, const double *a, const ctx *cb, const double
         int iq, jq; edge_cell(g, fi->eq, fi->tq, &iq, &jq);
         adv_lat_flux(ca, a, cb, b, p, i, j, k, f, f1);
         adv_lat_flux(ca, a, cb, b, fi->q, iq, jq, k, fi->eq, f2);
-        for (int c = 0; c < 3; c++) acc[c] += wl * 0.5 * (f1[c] - f2[c]);
+        for (int c = 0; c < 4; c++) acc[c] += wl * 0.5 * (f1[c] - f2[c]);
     }
     for (int sgn = -1; sgn <= 1; sgn += 2) {
         metric mf; metric_at(p, xi_of(g, i), xi_of(g, j), r_of(g, k + 0.5 * sgn), &mf);
         double af = 0.0;
         for (int d = 0; d < 3; d++)
             af += mf.sqrtg * mf.gcon[2][d] * 0.5 * (val_ext(ca, a, p, i, j, k, d) + val_ext(ca, a, p, i, j, k + sgn, d));
-        for (int c = 0; c < 3; c++)
+        for (int c = 0; c < 4; c++)
             acc[c] += wr * sgn * af * 0.5 * (val_ext(cb, b, p, i, j, k, c) + val_ext(cb, b, p, i, j, k + sgn, c));
     }
-    for (int c = 0; c < 3; c++) out[c] = acc[c];
+    for (int c = 0; c < 4; c++) out[c] = acc[c];
 }
 
-/* out = (a . grad) b on every cell (vector part; the scalar part is 0).  a
- * takes the ghost rules of system kind_a, b those of kind_b (0: no-slip
- * velocity, 1: pseudo-vacuum magnetic field). */
-int ref_advect(const ref_grid *g, int32_t kind_a, const double *a, int32_t kind_b, const double *b, double *out) {
-    ref_op oa = {kind_a, 0.0, 0.0, 1.0}, ob = {kind_b, 0.0, 0.0, 1.0};
+/* out = (a . grad) b on every cell.  a takes the ghost rules of system
+ * kind_a, b those of kind_b (0: no-slip velocity, 1: pseudo-vacuum magnetic
+ * field, 2: no-slip velocity and isothermal Theta).  scalar = 0: the vector
+ * part of b (components 0..2; component 3 of out is 0); scalar = 1: the
+ * scalar part (component 3; components 0..2 of out are 0). */
+int ref_advect(const ref_grid *g, int32_t kind_a, const double *a, int32_t kind_b, const double *b, int32_t scalar,
+               double *out) {
+    ref_op oa = {kind_a, 0.0, 0.0, 1.0, 0.0, 1.0}, ob = {kind_b, 0.0, 0.0, 1.0, 0.0, 1.0};
     seam_tab sa, sb; ctx ca, cb;
     int rc = make_ctx(g, &oa, &sa, &ca);
     if (rc) return rc;
@@ -632,10 +659,9 @@ int ref_advect(const ref_grid *g, int32_t kind_a, const double *a, int32_t kind_
         for (int k = 0; k < g->nr; k++)
             for (int j = 0; j < n; j++)
                 for (int i = 0; i < n; i++) {
-                    double v[3];
+                    double v[4];
                     adv_cell(&ca, a, &cb, b, p, i, j, k, v);
-                    for (int c = 0; c < 3; c++) out[unk(g, p, i, j, k, c)] = v[c];
-                    out[unk(g, p, i, j, k, 3)] = 0.0;
+                    for (int c = 0; c < 4; c++) out[unk(g, p, i, j, k, c)] = (c == 3) == (scalar != 0) ? v[c] : 0.0;
                 }
     free_seams(&sa);
     free_seams(&sb);
@@ -1422,6 +1448,7 @@ int ref_subdomain_solve(const ref_grid *g, const ref_op *op, const int32_t sub[3
  * b_P = 0 (discrete divergence-free at faces). */
 int ref_project(const ref_grid *g, const ref_op *op, const double *x, double *out) {
     seam_tab st; ctx cx;
+    if (op && op->kind == 2) return REF_EINVAL;   /* Step 3 belongs to the VP and BP systems */
     int rc = make_ctx(g, op, &st, &cx);
     if (rc) return rc;
     sink s = {0}; s.mode = 1; s.x = x;
