@@ -22,13 +22,19 @@
  * fastest within a row, then j, then k, then panel; the 4 components of a
  * cell are its Cartesian vector (x, y, z) and its scalar:
  *   kind VP: (u~, P)   -- velocity-pressure system,
- *   kind BP: (B~, P_b) -- magnetic-field / pseudo-pressure system.
- * Rows of A (E = Ekman number, Pm = magnetic Prandtl number):
+ *   kind BP: (B~, P_b) -- magnetic-field / pseudo-pressure system,
+ *   kind VT: (u~, Theta) -- velocity-temperature block of the VTBE.
+ * Rows of A (E = Ekman number, Pm = magnetic Prandtl number, Ra = modified
+ * Rayleigh number, Pr = Prandtl number, x = r r_hat the cell centre):
  *   VP: u - dt (E lap u - 2 zhat x u);   D(u) - dt lap_N P   (Neumann P)
  *   BP: B - dt (E/Pm) lap B;             D(B) - dt lap_D P_b (Dirichlet P_b)
- * with finite-volume lap and D (eq. divdiscretization), no-slip u, and the
+ *   VT: u - dt (E lap u - 2 zhat x u) - dt (Ra/r_o) Theta x;
+ *       Theta - dt (E/Pr) lap_D Theta - dt E (r_i r_o / r^3) (x . u)
+ *       (eq. tsvelocity, tstemperature with Delta t / 2 = E dt; R1, R2 and L2
+ *       of eq. linearoperator)
+ * with finite-volume lap and D (eq. divdiscretization), no-slip u, the
  * pseudo-vacuum condition on B (eq. pvc: tangential B = 0,
- * d(r^2 B_r)/dr = 0 at the walls).
+ * d(r^2 B_r)/dr = 0 at the walls) and isothermal walls (Theta = 0, eq. utb).
  *
  * Memory: the caller owns every device buffer.  Each *_setup takes a device
  * workspace of at least *_workspace_bytes() bytes; handles are small host
@@ -64,6 +70,7 @@ extern "C" {
 
 #define CSDYN_VP 0
 #define CSDYN_BP 1
+#define CSDYN_VT 2
 
 typedef struct {
     int32_t n;   /* cells per panel edge, N >= 4 */
@@ -73,10 +80,12 @@ typedef struct {
 } csdyn_grid;
 
 typedef struct {
-    int32_t kind;  /* CSDYN_VP or CSDYN_BP */
+    int32_t kind;  /* CSDYN_VP, CSDYN_BP or CSDYN_VT */
     double dt;     /* time-step factor of the rows above (> 0 for a nonsingular ILU) */
     double ekman;  /* E */
     double pm;     /* Pm (BP only) */
+    double ra;     /* modified Rayleigh number Ra (VT only) */
+    double pr;     /* Prandtl number Pr (VT only, > 0) */
 } csdyn_op;
 
 /* ---------------------------------------------------------------- operator
@@ -435,7 +444,10 @@ int32_t csdyn_march_rhs(const csdyn_opctx *ctx, const double *v, const double *f
  * Nonlinear terms of the momentum and induction equations (Sec. 3.1, eq.
  * nonlinearoperator):
  *   f1 = -(u . grad) u + cB (B . grad) B     (cB = 1/(E Pm)),
- *   f3 =  (B . grad) u - (u . grad) B.
+ *   f3 =  (B . grad) u - (u . grad) B,
+ * and, when the velocity-temperature state T = (u, Theta) is given (else
+ * NULL), f2 = -(u . grad) Theta in f1's scalar slot (isothermal Theta
+ * ghosts), so that f1 is the VT system's explicit vector (f1, f2).
  * Each (a . grad) b is the conservative finite-volume form div(a b_c) of each
  * Cartesian component c (Sec. 3.2, eq. nonlinearint; in Cartesian components
  * the Christoffel source terms of the contravariant form vanish): the sum over
@@ -446,19 +458,23 @@ int32_t csdyn_march_rhs(const csdyn_opctx *ctx, const double *v, const double *f
  * no-slip, B: pseudo-vacuum); through a panel-edge face the mean of the two
  * panels' one-sided fluxes.
  * vp, bp: the VP and BP contexts of one grid; u, B: device vectors in the
- * solver's layout (component 3, the pressures, is not read); f1, f3: device,
- * same layout, component 3 set to 0; f1 and f3 must not alias each other or
- * the inputs.  ws: csdyn_nonlinear_workspace_bytes (the ghost values of u
- * and B), else CSDYN_ENOMEM.  Asynchronous on `stream`. */
+ * solver's layout (component 3, the pressures, is not read); T: device, the
+ * VT layout (only component 3 is read), or NULL; f1, f3: device, same
+ * layout, component 3 of f3 (and of f1 without T) set to 0; f1 and f3 must
+ * not alias each other or the inputs.  ws: csdyn_nonlinear_workspace_bytes
+ * (the ghost values of u, B and T), else CSDYN_ENOMEM.  Asynchronous on
+ * `stream`. */
 int32_t csdyn_nonlinear_workspace_bytes(const csdyn_opctx *ctx, size_t *bytes);
 int32_t csdyn_nonlinear(const csdyn_opctx *vp, const csdyn_opctx *bp, const double *u, const double *B,
-                        double cB, double *f1, double *f3, void *ws, size_t ws_bytes, void *stream);
+                        const double *T, double cB, double *f1, double *f3, void *ws, size_t ws_bytes,
+                        void *stream);
 
-/* Right-hand side of Step 1 (Sec. 3.1, eqs. tsvelocity and tsmag) in this
- * system's scaling (Delta t = 2 E dt; the vector rows of A are
+/* Right-hand side of Step 1 (Sec. 3.1, eqs. tsvelocity, tstemperature and
+ * tsmag) in this system's scaling (Delta t = 2 E dt; the vector rows of A are
  * I - (Delta t / 2) L):
  *   rhs[c] = 2 xhat[c] - (A xhat)[c] + c1 fn[c] + c2 fm[c] + c3 gf[c], c < 3,
- *   rhs[3] = 0,
+ *   rhs[3] = 0 (VP, BP: the divergence rows), or the same combination for
+ *   the VT system's Theta row (VT: xhat = (\hat u^n, Theta^n), fn = (f1, f2)),
  * i.e. xhat + (Delta t / 2) L xhat + the explicit terms; with the
  * Adams-Bashforth combination c1 = 1.5 Delta t, c2 = -0.5 Delta t (the first
  * step: c1 = Delta t, c2 = 0).  xhat = \hat u^n (or \hat B^n): the vector
@@ -473,6 +489,13 @@ int32_t csdyn_cn_rhs(const csdyn_opctx *ctx, const double *xhat, const double *f
  * x[c] - dt (grad_h P)[c] for c < 3 (as csdyn_project) and state[3] = x[3]
  * (P^{n+1} or P_b^{n+1}).  x and state must not alias.  Asynchronous. */
 int32_t csdyn_step3_state(const csdyn_opctx *ctx, const double *x, double *state, void *stream);
+
+/* Right-hand side of Step 2 when Step 1 was the VT solve (Sec. 3.1, eq. tsp):
+ * y = ((A x)_vec, 0) for a VP (or BP) context, whose solve then returns
+ * x_vec (to its tolerance) with the pressure that satisfies the divergence
+ * rows, D(u~) = dt lap_N P.  x and y must not alias; CSDYN_EINVAL for a VT
+ * context.  Asynchronous on `stream`. */
+int32_t csdyn_vector_rows(const csdyn_opctx *ctx, const double *x, double *y, void *stream);
 
 /* ----------------------------------------------------------------- profile
  * Optional timing of every kernel launch by HIP events recorded on the launch

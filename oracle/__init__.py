@@ -354,6 +354,14 @@ def cn_rhs(pb: Problem, xhat: np.ndarray, fn: np.ndarray, c1: float, fm=None, c2
         out += c2 * np.asarray(fm).reshape(pb.shape())
     if gf is not None and c3 != 0.0:
         out += c3 * np.asarray(gf).reshape(pb.shape())
+    if pb.kind != 2:       # VP, BP: the divergence rows; VT keeps its Theta row (eq. tstemperature)
+        out[..., 3] = 0.0
+    return out
+
+
+def vector_rows(pb: Problem, x: np.ndarray) -> np.ndarray:
+    """((A x)_vec, 0): Step 2's right-hand side after a VT Step 1 (Sec. 3.1, eq. tsp)."""
+    out = apply(pb, x)
     out[..., 3] = 0.0
     return out
 

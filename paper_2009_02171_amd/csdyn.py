@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcsdyn.so")
 
 OK, ENOTCONV, EINVAL, EHIP, EZEROPIVOT, ENOMEM, EBREAKDOWN = 0, 1, -1, -2, -3, -4, -5
-VP, BP = 0, 1
+VP, BP, VT = 0, 1, 2
 RI, RO = 7.0 / 13.0, 20.0 / 13.0
 
 
@@ -26,7 +26,8 @@ class Grid(C.Structure):
 
 
 class OpDesc(C.Structure):
-    _fields_ = [("kind", C.c_int32), ("dt", C.c_double), ("ekman", C.c_double), ("pm", C.c_double)]
+    _fields_ = [("kind", C.c_int32), ("dt", C.c_double), ("ekman", C.c_double), ("pm", C.c_double),
+                ("ra", C.c_double), ("pr", C.c_double)]
 
 
 class RasOpts(C.Structure):
@@ -136,11 +137,12 @@ SIGNATURES = {
                                 C.c_void_p, C.c_size_t, C.c_void_p, _P(GuessInfo)]),
     "csdyn_march_rhs": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p]),
     "csdyn_nonlinear_workspace_bytes": (C.c_int32, [C.c_void_p, _P(C.c_size_t)]),
-    "csdyn_nonlinear": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p,
-                                    C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "csdyn_nonlinear": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "csdyn_cn_rhs": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
                                  C.c_double, C.c_double, C.c_void_p, C.c_void_p]),
     "csdyn_step3_state": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "csdyn_vector_rows": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "csdyn_last_error": (C.c_char_p, []),
 }
 
@@ -192,12 +194,12 @@ def _workspace(nbytes: int, device):
 class Operator:
     """y = A x for one system on one grid (csdyn_op_setup / csdyn_operator_apply)."""
 
-    def __init__(self, n, nr, kind=VP, dt=1e-4, ekman=1e-3, pm=5.0, ri=RI, ro=RO, device="cuda"):
+    def __init__(self, n, nr, kind=VP, dt=1e-4, ekman=1e-3, pm=5.0, ri=RI, ro=RO, device="cuda", ra=100.0, pr=1.0):
         self.n, self.nr, self.kind = n, nr, kind
         self.dt, self.ekman, self.pm = dt, ekman, pm
         self.device = torch.device(device)
         self.grid = Grid(n, nr, ri, ro)
-        self.desc = OpDesc(kind, dt, ekman, pm)
+        self.desc = OpDesc(kind, dt, ekman, pm, ra, pr)
         nb = C.c_size_t()
         _check(lib().csdyn_op_workspace_bytes(C.byref(self.grid), C.byref(nb)), "csdyn_op_workspace_bytes")
         self.ws = _workspace(nb.value, self.device)
@@ -594,11 +596,13 @@ class Nonlinear:
         self.ws = _workspace(nb.value, vp.device)
         self.nbytes = nb.value
 
-    def __call__(self, u, B, cB, f1=None, f3=None, stream=None):
+    def __call__(self, u, B, cB, f1=None, f3=None, T=None, stream=None):
+        """T: the velocity-temperature state (u, Theta); then f1's scalar slot is f2."""
         f1 = self.vp.empty() if f1 is None else f1
         f3 = self.vp.empty() if f3 is None else f3
-        _check(lib().csdyn_nonlinear(self.vp.h, self.bp.h, _ptr(u), _ptr(B), cB, _ptr(f1), _ptr(f3), _ptr(self.ws),
-                                     self.nbytes, _stream(stream)), "csdyn_nonlinear")
+        _check(lib().csdyn_nonlinear(self.vp.h, self.bp.h, _ptr(u), _ptr(B), _ptr(T) if T is not None else None, cB,
+                                     _ptr(f1), _ptr(f3), _ptr(self.ws), self.nbytes, _stream(stream)),
+               "csdyn_nonlinear")
         return f1, f3
 
 
@@ -615,4 +619,11 @@ def step3_state(op: Operator, x, out=None, stream=None):
     """(x_vec - dt grad_h P, P) on the device (csdyn_step3_state)."""
     out = op.empty() if out is None else out
     _check(lib().csdyn_step3_state(op.h, _ptr(x), _ptr(out), _stream(stream)), "csdyn_step3_state")
+    return out
+
+
+def vector_rows(op: Operator, x, out=None, stream=None):
+    """((A x)_vec, 0) on the device (csdyn_vector_rows)."""
+    out = op.empty() if out is None else out
+    _check(lib().csdyn_vector_rows(op.h, _ptr(x), _ptr(out), _stream(stream)), "csdyn_vector_rows")
     return out

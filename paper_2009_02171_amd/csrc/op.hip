@@ -33,7 +33,7 @@ __global__ void k_edgeflux(DevGeom g, const T *__restrict__ x, const T *__restri
 
 // At least two wavefronts per SIMD (FP64: 256 registers, the whole layer
 // pipeline in registers without spilling).
-template <class T, int TX, int TY>
+template <class T, int TX, int TY, bool VT>
 __global__ __launch_bounds__(TX *TY, 2) void k_op_main(DevGeom g, RowCoef rc, int kchunk, int nkc,
                                                     const T *__restrict__ x, const T *__restrict__ G,
                                                     const T *__restrict__ SF, T *__restrict__ y) {
@@ -51,8 +51,8 @@ __global__ __launch_bounds__(TX *TY, 2) void k_op_main(DevGeom g, RowCoef rc, in
     const int p = slab / nkc, kc = slab % nkc;
     const int k0 = kc * kchunk, k1 = min(nr, k0 + kchunk);
     const bool edge_tile = bx == 0 || by == 0 || (bx + 1) * TX >= n || (by + 1) * TY >= n;
-    if (edge_tile) op_march<T, TX, TY, true>(g, rc, p, bx, by, k0, k1, x, G, SF, y, lds, layf);
-    else op_march<T, TX, TY, false>(g, rc, p, bx, by, k0, k1, x, G, SF, y, lds, layf);
+    if (edge_tile) op_march<T, TX, TY, true, VT>(g, rc, p, bx, by, k0, k1, x, G, SF, y, lds, layf);
+    else op_march<T, TX, TY, false, VT>(g, rc, p, bx, by, k0, k1, x, G, SF, y, lds, layf);
 }
 
 // The FP64 stencil for large shells, with the layers requested straight into
@@ -403,8 +403,12 @@ static int32_t launch_all(const csdyn_opctx *ctx, const T *x, T *y, T *G, T *SF,
     RowCoef rc;
     rc.kind = ctx->op.kind;
     rc.dt = ctx->op.dt;
-    rc.c_lap = ctx->op.kind == CSDYN_VP ? ctx->op.dt * ctx->op.ekman : ctx->op.dt * ctx->op.ekman / ctx->op.pm;
-    rc.c_cor = ctx->op.kind == CSDYN_VP ? 2.0 * ctx->op.dt : 0.0;
+    const bool vt = ctx->op.kind == CSDYN_VT;
+    rc.c_lap = ctx->op.kind == CSDYN_BP ? ctx->op.dt * ctx->op.ekman / ctx->op.pm : ctx->op.dt * ctx->op.ekman;
+    rc.c_cor = ctx->op.kind == CSDYN_BP ? 0.0 : 2.0 * ctx->op.dt;
+    rc.c_th = vt ? ctx->op.dt * ctx->op.ekman / ctx->op.pr : 0.0;
+    rc.c_r1 = vt ? ctx->op.dt * ctx->op.ra / ctx->g.ro : 0.0;
+    rc.c_r2 = vt ? ctx->op.dt * ctx->op.ekman * ctx->g.ri * ctx->g.ro : 0.0;
     const dim3 eb(64), eg((n + 63) / 64, nr, 24);
     {
         // ghost: 4 neighbour cells read, 1 written; edge flux: 12 cells read, 5 values written
@@ -419,7 +423,9 @@ static int32_t launch_all(const csdyn_opctx *ctx, const T *x, T *y, T *G, T *SF,
     // cells (measured faster there; at N = 64 and 80 the register kernel is
     // faster), else 16x8; tile 6 asks for it (FP64, N > 16; otherwise 16x8)
     const bool big = int64_t(n) * n * nr >= int64_t(96) * 96 * 96;
-    const int tile = ctx->tile ? ctx->tile : (sizeof(T) == 8 && n > 16 && big ? 6 : 4);
+    // the velocity-temperature rows are in the register kernel only
+    int tile = ctx->tile ? ctx->tile : (sizeof(T) == 8 && n > 16 && big ? 6 : 4);
+    if (vt && tile == 6) tile = 4;
     int32_t status = CSDYN_OK;
     auto go = [&](auto tx_c, auto ty_c) {
         constexpr int TX = decltype(tx_c)::value, TY = decltype(ty_c)::value;
@@ -439,8 +445,12 @@ static int32_t launch_all(const csdyn_opctx *ctx, const T *x, T *y, T *G, T *SF,
             status = CSDYN_EINVAL;
             return;
         }
-        hipLaunchKernelGGL((k_op_main<T, TX, TY>), dim3(tiles * 6 * nkc), dim3(TX * TY), 0, s, g, rc, kchunk, nkc,
-                           x, (const T *)G, (const T *)SF, y);
+        if (vt)
+            hipLaunchKernelGGL((k_op_main<T, TX, TY, true>), dim3(tiles * 6 * nkc), dim3(TX * TY), 0, s, g, rc, kchunk,
+                               nkc, x, (const T *)G, (const T *)SF, y);
+        else
+            hipLaunchKernelGGL((k_op_main<T, TX, TY, false>), dim3(tiles * 6 * nkc), dim3(TX * TY), 0, s, g, rc, kchunk,
+                               nkc, x, (const T *)G, (const T *)SF, y);
     };
     using std::integral_constant;
     if (tile == 6 && sizeof(T) == 8 && n > 16) {
@@ -521,9 +531,12 @@ extern "C" int32_t csdyn_op_setup(const csdyn_grid *g, const csdyn_op *op, void 
     clear_error();
     if (!g || !op || !ws || !out) { set_error("csdyn_op_setup: null argument"); return CSDYN_EINVAL; }
     *out = nullptr;
-    if (op->kind != CSDYN_VP && op->kind != CSDYN_BP) { set_error("csdyn_op_setup: kind must be VP or BP"); return CSDYN_EINVAL; }
-    if (!(op->dt >= 0) || !(op->ekman > 0) || (op->kind == CSDYN_BP && !(op->pm > 0))) {
-        set_error("csdyn_op_setup: need dt >= 0, ekman > 0, pm > 0"); return CSDYN_EINVAL;
+    if (op->kind != CSDYN_VP && op->kind != CSDYN_BP && op->kind != CSDYN_VT) {
+        set_error("csdyn_op_setup: kind must be VP, BP or VT"); return CSDYN_EINVAL;
+    }
+    if (!(op->dt >= 0) || !(op->ekman > 0) || (op->kind == CSDYN_BP && !(op->pm > 0)) ||
+        (op->kind == CSDYN_VT && (!(op->pr > 0) || !std::isfinite(op->ra)))) {
+        set_error("csdyn_op_setup: need dt >= 0, ekman > 0, pm > 0 (BP), pr > 0 and a finite ra (VT)"); return CSDYN_EINVAL;
     }
     auto *ctx = new csdyn_opctx();
     ctx->g = *g; ctx->op = *op; ctx->ws = ws; ctx->ws_bytes = ws_bytes;
@@ -556,6 +569,7 @@ extern "C" int32_t csdyn_project(const csdyn_opctx *ctx, const double *x, double
     const size_t nb = size_t(24) * ctx->g.n * ctx->g.n * ctx->g.nr * sizeof(double);
     const char *xa = (const char *)x, *oa = (const char *)out;
     if (xa < oa + nb && oa < xa + nb) { set_error("csdyn_project: x and out alias"); return CSDYN_EINVAL; }
+    if (ctx->op.kind == CSDYN_VT) { set_error("csdyn_project: Step 3 belongs to the VP and BP systems"); return CSDYN_EINVAL; }
     hipStream_t s = (hipStream_t)stream;
     CSD_TRY(op_launch(ctx, x, out, s));  // out_3 = divergence of the corrected fluxes; fills the ghost buffer
     const int64_t ncell = 6 * int64_t(ctx->g.n) * ctx->g.n * ctx->g.nr;

@@ -144,10 +144,13 @@ __device__ __forceinline__ void edgeflux_at(const DevGeom &g, const T *__restric
 }
 
 struct RowCoef {
-    int kind;      // CSDYN_VP or CSDYN_BP
-    double c_lap;  // dt*E (VP) or dt*E/Pm (BP)
-    double c_cor;  // 2 dt (VP), 0 (BP)
+    int kind;      // CSDYN_VP, CSDYN_BP or CSDYN_VT
+    double c_lap;  // dt*E (VP, VT) or dt*E/Pm (BP)
+    double c_cor;  // 2 dt (VP, VT), 0 (BP)
     double dt;
+    double c_th;   // VT: dt*E/Pr (the Theta Laplacian)
+    double c_r1;   // VT: dt*Ra/r_o (buoyancy: times r Theta r_hat)
+    double c_r2;   // VT: dt*E*r_i*r_o (times (r_hat . u) / r^2)
 };
 
 // Wall ghost of a boundary cell (no-slip u, Neumann P; pseudo-vacuum B,
@@ -157,6 +160,8 @@ __device__ __forceinline__ V4<T> wall_ghost(const V4<T> &xin, int kind, const T 
     V4<T> gv;
     if (kind == CSDYN_VP) {
         gv.c[0] = -xin.c[0]; gv.c[1] = -xin.c[1]; gv.c[2] = -xin.c[2]; gv.c[3] = xin.c[3];
+    } else if (kind == CSDYN_VT) {  // no-slip u, isothermal Theta
+        gv.c[0] = -xin.c[0]; gv.c[1] = -xin.c[1]; gv.c[2] = -xin.c[2]; gv.c[3] = -xin.c[3];
     } else {
         const T nb = (T(1) + q) * (nv[0] * xin.c[0] + nv[1] * xin.c[1] + nv[2] * xin.c[2]);
         gv.c[0] = -xin.c[0] + nb * nv[0];
@@ -205,7 +210,7 @@ struct OpLds {
     static constexpr int HALO = 3 * 4 * HC, DUMMY = HALO + 3 * FA, SIZE = DUMMY + 4 * TX * TY;
 };
 
-template <class T, int TX, int TY, bool EDGE>
+template <class T, int TX, int TY, bool EDGE, bool VT = false>
 __device__ __forceinline__ void op_march(const DevGeom &g, const RowCoef &rc, int p, int bx, int by, int k0, int k1,
                                          const T *__restrict__ x, const T *__restrict__ G,
                                          const T *__restrict__ SF, T *__restrict__ y, T *lds, T (*layf)[8]) {
@@ -413,6 +418,14 @@ __device__ __forceinline__ void op_march(const DevGeom &g, const RowCoef &rc, in
         out.c[1] = xc.c[1] - clap * lap[1] + ccor * xc.c[0];
         out.c[2] = xc.c[2] - clap * lap[2];
         out.c[3] = div - cdt * lap[3];
+        if constexpr (VT) {  // buoyancy in the velocity rows; the Theta row (no divergence)
+            const T th = xc.c[3], b1 = T(rc.c_r1) * L[0] * th;
+            const T un = m.nv[0] * xc.c[0] + m.nv[1] * xc.c[1] + m.nv[2] * xc.c[2];
+            out.c[0] -= b1 * m.nv[0];
+            out.c[1] -= b1 * m.nv[1];
+            out.c[2] -= b1 * m.nv[2];
+            out.c[3] = th - T(rc.c_th) * lap[3] - T(rc.c_r2) * irk2 * un;
+        }
         __builtin_amdgcn_sched_barrier(0);  // layer k+4 into the set just written to LDS
         fetch(S, k + 4 < kend);
         __builtin_amdgcn_sched_barrier(0);

@@ -28,6 +28,8 @@ class Expander {
             const int kin = k < 0 ? 0 : nr - 1;
             if (op_.kind == CSDYN_VP) {
                 value(p, i, j, kin, c, c < 3 ? -w : w);
+            } else if (op_.kind == CSDYN_VT) {  // no-slip u, isothermal Theta
+                value(p, i, j, kin, c, -w);
             } else if (c == 3) {
                 value(p, i, j, kin, 3, -w);
             } else {
@@ -172,6 +174,22 @@ class Expander {
 
     void row(int p, int i, int j, int k, int c) {
         const double dt = op_.dt, E = op_.ekman;
+        if (op_.kind == CSDYN_VT) {  // velocity-temperature rows (pointwise couplings at the cell centre)
+            const double *nv = &g_.nrm[((size_t(p) * g_.n + j) * g_.n + i) * 3];
+            const double r = g_.rk[k];
+            if (c == 3) {
+                value(p, i, j, k, 3, 1.0);
+                laplacian(p, i, j, k, 3, -dt * E / op_.pr);
+                for (int d = 0; d < 3; ++d) value(p, i, j, k, d, -dt * E * g_.ri * g_.ro / (r * r) * nv[d]);
+                return;
+            }
+            value(p, i, j, k, c, 1.0);
+            laplacian(p, i, j, k, c, -dt * E);
+            if (c == 0) value(p, i, j, k, 1, -2.0 * dt);
+            if (c == 1) value(p, i, j, k, 0, 2.0 * dt);
+            value(p, i, j, k, 3, -dt * op_.ra / g_.ro * r * nv[c]);
+            return;
+        }
         if (c == 3) {
             divergence(p, i, j, k, 1.0);
             laplacian(p, i, j, k, 3, -dt);

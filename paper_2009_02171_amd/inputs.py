@@ -158,3 +158,19 @@ def benchmark_b0(n: int, nr: int, ri: float = RI, ro: float = RO) -> np.ndarray:
     out[..., 1] = br * st * sp + bt * ct * sp + bp * cp
     out[..., 2] = br * ct - bt * st
     return out
+
+
+def benchmark_theta0(n: int, nr: int, ri: float = RI, ro: float = RO) -> np.ndarray:
+    """The benchmark's initial temperature perturbation (Sec. 4.2, eq. initial)
+    in the scalar slot of a velocity-temperature vector, float64
+    [6, Nr, N, N, 4] (vector slots 0):
+        Theta = 21 / sqrt(17920 pi) (1 - 3 x^2 + 3 x^4 - x^6) sin^4(theta) cos(4 phi),
+        x = 2 r - ri - ro."""
+    d = cell_directions(n)
+    th = np.arccos(np.clip(d[..., 2], -1.0, 1.0))[:, None]
+    ph = np.arctan2(d[..., 1], d[..., 0])[:, None]
+    r = (ri + (np.arange(nr) + 0.5) * (ro - ri) / nr)[None, :, None, None]
+    x = 2 * r - ri - ro
+    out = np.zeros((6, nr, n, n, 4))
+    out[..., 3] = 21.0 / np.sqrt(17920.0 * np.pi) * (1 - 3 * x**2 + 3 * x**4 - x**6) * np.sin(th)**4 * np.cos(4 * ph)
+    return out
