@@ -171,9 +171,10 @@ def main():
     ap.add_argument("--learned-eval-steps", type=int, default=30,
                     help="large workload: evaluation steps of the bounded learned-guess leg")
     ap.add_argument("--no-small", action="store_true", help="large workload: skip the small-configuration leg")
-    ap.add_argument("--dynamics", choices=("surrogate", "full"), default="surrogate",
-                    help="learned march: the step without nonlinear terms driven by a drifting forcing, or the "
-                         "semi-implicit step with nonlinear terms from the benchmark's initial field")
+    ap.add_argument("--dynamics", choices=("surrogate", "full", "thermal"), default="surrogate",
+                    help="learned march: the step without nonlinear terms driven by a drifting forcing, the "
+                         "semi-implicit step with nonlinear terms from the benchmark's initial field, or that "
+                         "step with the temperature")
     ap.add_argument("--no-three-level", action="store_true", help="large workload: skip the three-level forms")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -62,22 +62,32 @@ class _System:
 
 def run(n=64, nr=64, sub=(16, 16, 16), levels=2, train_steps=100, eval_steps=100, train_iters=8, replay=16,
         lr=5e-4, dt=1e-4, ekman=1e-3, pm=5.0, forcing_seed=4, widths=inputs.NET_WIDTHS, log=print,
-        dev="cuda", dynamics="surrogate", force_amp=0.0):
+        dev="cuda", dynamics="surrogate", force_amp=0.0, ra=100.0, pr=1.0):
     """dynamics = "surrogate": b^n = (v^{n-1} + dt f^n, 0) with the drifting
     forcing (the systems decoupled); "full": the semi-implicit step of Sec. 3.1
     (step.SemiImplicit: nonlinear terms, Adams-Bashforth, Crank-Nicolson
     right-hand sides) from the benchmark's initial magnetic field and u = 0,
-    with the drifting field times force_amp as a body force on the velocity
-    (standing in for the buoyancy of the temperature equation, not built)."""
+    with the drifting field times force_amp as a body force on the velocity;
+    "thermal": the same step with the temperature (the VT solve first, from
+    the previous solution with the FP64 preconditioner, then the pressure from
+    the VP system) from the benchmark's initial Theta and B.  The learned and
+    classical guesses are compared on the VP and BP solves."""
     dev = torch.device(dev)
     rng = np.random.default_rng(forcing_seed + 1000)
     sim = None
-    if dynamics == "full":
+    if dynamics in ("full", "thermal"):
         from . import step as step_mod
-        sim = step_mod.SemiImplicit(n, nr, dt=dt, ekman=ekman, pm=pm, solvers=False,
-                                    b0=torch.from_numpy(inputs.benchmark_b0(n, nr)).to(dev), device=dev)
+        thermal = dynamics == "thermal"
+        sim = step_mod.SemiImplicit(n, nr, dt=dt, ekman=ekman, pm=pm, solvers=False, temperature=thermal, ra=ra,
+                                    pr=pr, b0=torch.from_numpy(inputs.benchmark_b0(n, nr)).to(dev),
+                                    theta0=(torch.from_numpy(inputs.benchmark_theta0(n, nr)).to(dev)
+                                            if thermal else None), device=dev)
+        if thermal:
+            vt_pc = csdyn.RAS(sim.vt, sub=sub, levels=1)
+            vt_sol = csdyn.Solver(sim.vt, vt_pc, restart=30, maxit=3000, flexible=False, rtol=1e-8,
+                                  rhs_relative=True)
     elif dynamics != "surrogate":
-        raise ValueError(f"dynamics must be 'surrogate' or 'full', not {dynamics!r}")
+        raise ValueError(f"dynamics must be 'surrogate', 'full' or 'thermal', not {dynamics!r}")
     systems = {"VP": _System(csdyn.VP, n, nr, sub, levels, dt, ekman, pm, 5, widths, dev,
                              op=sim.vp if sim else None),
                "BP": _System(csdyn.BP, n, nr, sub, levels, dt, ekman, pm, 6, widths, dev,
@@ -108,6 +118,7 @@ def run(n=64, nr=64, sub=(16, 16, 16), levels=2, train_steps=100, eval_steps=100
         return x, st, el
 
     pending = {}
+    vt_iters = []
 
     def advance(s, x, name, bnorm):
         out = s.op.project(x)
@@ -125,6 +136,14 @@ def run(n=64, nr=64, sub=(16, 16, 16), levels=2, train_steps=100, eval_steps=100
         if sim is not None:
             sim.force, sim.force_scale = (f, force_amp) if force_amp else (None, 1.0)
             bs, fterms = sim.rhs()
+            if sim.temperature:  # Step 1's VT solve, then Step 2's right-hand side
+                xvt = sim.x["VT"].clone()
+                _, st_vt, rc = vt_sol.solve(bs["VT"], xvt)
+                if rc != 0:
+                    raise RuntimeError(f"VT solve did not converge: {st_vt}")
+                vt_iters.append(st_vt["iters"])
+                pending["VT"] = xvt
+                bs["VP"] = sim.pressure_rhs(xvt)
         for name, s in systems.items():
             b = s.rhs(f, dt) if sim is None else bs[name]
             h = s.hist
@@ -191,6 +210,7 @@ def run(n=64, nr=64, sub=(16, 16, 16), levels=2, train_steps=100, eval_steps=100
             log(f"step {step}/{total} done")
 
     out = {"n": n, "nr": nr, "dynamics": dynamics, "force_amp": force_amp if sim is not None else None,
+           "vt_iters_mean": float(np.mean(vt_iters)) if vt_iters else None,
            "state_absmax": ({name: float(sim.state[name][..., :3].abs().max()) for name in systems}
                             if sim is not None else None),
            "train_steps": train_steps, "eval_steps": eval_steps, "drift_rad_per_step": DRIFT,

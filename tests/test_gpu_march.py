@@ -106,3 +106,19 @@ def test_march_full_dynamics_small():
     # the Lorentz force has set the fluid moving from rest; (the pressures carry the
     # Crank-Nicolson pressure term's period-two mode, so extrapolation is not asserted here)
     assert r["state_absmax"]["VP"] > 1e-3 * r["state_absmax"]["BP"] > 0
+
+
+def test_march_thermal_dynamics_small():
+    """The march on the whole step with the temperature (VT solve, pressure from
+    VP, BP): every VP and BP solve reaches the tolerance with every guess."""
+    from paper_2009_02171_amd import march
+    r = march.run(n=16, nr=16, sub=(8, 8, 8), levels=2, train_steps=6, eval_steps=2, train_iters=2,
+                  dynamics="thermal", log=lambda m: print(m, flush=True))
+    print(r)
+    assert r["dynamics"] == "thermal" and 0 < r["vt_iters_mean"] < 30
+    for name, s in r["systems"].items():
+        for v in ("plain_a", "mixed_a", "mixed_b", "mixed_c", "mixed_d"):
+            assert s[v]["solves"] == 2
+            assert s[v]["relres_max"] <= 1.0001e-8
+        assert s["face_div_rel_max"] <= 1.0001e-8
+    assert r["state_absmax"]["VP"] > 0
