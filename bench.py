@@ -728,7 +728,8 @@ def learned(args, wl):
         "vs_baseline": None,
         "dtype": "f64 solve, f32 preconditioner, bf16 network",
         "data": "synthetic",
-        "config": {"workload": wl["desc"], "n": wl["n"], "nr": wl["nr"], "subdomain": list(wl["sub"]),
+        "config": {"workload": f"{wl['desc']} ({args.train_steps} training + {args.eval_steps} evaluation steps here)",
+                   "n": wl["n"], "nr": wl["nr"], "subdomain": list(wl["sub"]),
                    "levels": wl["levels"], "drift_rad_per_step": res["drift_rad_per_step"],
                    "network_params": res["param_count"], "dynamics": res["dynamics"]},
         "forms": {v: round(x, 4) for v, x in sp.items()},
