@@ -164,7 +164,11 @@ typedef struct {
     int32_t storage;         /* where a sweep keeps computed values: 0 automatic (the whole subdomain
                                 vector in LDS when its FP64 size is at most 90 KiB, else a ring of
                                 recent levels), 1 the ring, 2 the subdomain vector (CSDYN_EINVAL if it
-                                does not fit in LDS); the results do not depend on it */
+                                does not fit in LDS), 3 as 0 but never folded.  With 0 and
+                                2 an FP64 subdomain vector too large for two workgroups per compute
+                                unit is folded when the level schedules allow it: its last rows reuse
+                                the LDS of its first rows, whose L-sweep results also go through
+                                device memory.  The results do not depend on it */
 } csdyn_ras_opts;
 
 typedef struct csdyn_ras csdyn_ras;
@@ -323,10 +327,11 @@ typedef struct {
     int32_t lds_fine, lds_coarse;             /* dynamic LDS bytes per workgroup of the sweep kernel */
     int32_t box_in_lds_fine, box_in_lds_coarse; /* where the sweep keeps computed values: 0 a ring of recent
                                                    levels in device memory, 1 that ring in LDS, 2 the whole
-                                                   subdomain vector in LDS */
+                                                   subdomain vector in LDS, 3 that vector folded */
     int32_t threads_fine, threads_coarse;     /* workgroup size of the sweep kernel (256, 512 or 1024) */
     int32_t structures_fine, structures_coarse; /* distinct sweep structures: subdomains with the same
                                                    dependency addresses share one stored copy */
+    int32_t blocks_per_cu_fine, blocks_per_cu_coarse; /* sweep workgroups that fit one compute unit */
 } csdyn_ras_info;
 int32_t csdyn_ras_get_info(const csdyn_ras *pc, csdyn_ras_info *info);
 

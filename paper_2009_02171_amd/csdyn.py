@@ -59,7 +59,8 @@ class RasInfo(C.Structure):
                 ("stored_coarse", C.c_int64), ("max_levels_fine", C.c_int32), ("max_levels_coarse", C.c_int32),
                 ("precision", C.c_int32), ("lds_fine", C.c_int32), ("lds_coarse", C.c_int32),
                 ("box_in_lds_fine", C.c_int32), ("box_in_lds_coarse", C.c_int32), ("threads_fine", C.c_int32),
-                ("threads_coarse", C.c_int32), ("structures_fine", C.c_int32), ("structures_coarse", C.c_int32)]
+                ("threads_coarse", C.c_int32), ("structures_fine", C.c_int32), ("structures_coarse", C.c_int32),
+                ("blocks_per_cu_fine", C.c_int32), ("blocks_per_cu_coarse", C.c_int32)]
 
 
 class ConvShape(C.Structure):

@@ -15,6 +15,7 @@
 #include <cstring>
 #include <memory>
 #include <mutex>
+#include <type_traits>
 
 #include "krylov.h"
 #include "profile.h"
@@ -22,11 +23,11 @@
 
 namespace csd {
 
-template <class TV, class TF, bool LDS, bool VEC, int NT>
+template <class TV, class TF, bool LDS, bool VEC, int NT, bool FOLD = false>
 __global__ __launch_bounds__(NT) void k_ras(DevRas<TF> R, int meta_lev, int meta_sl, const TV *__restrict__ x,
                                             TV *__restrict__ y) {
     extern __shared__ __align__(16) unsigned char ras_smem[];
-    ras_block<TV, TF, LDS, VEC, NT>(R, meta_lev, meta_sl, x, y, int(blockIdx.x), ras_smem);
+    ras_block<TV, TF, LDS, VEC, NT, FOLD>(R, meta_lev, meta_sl, x, y, int(blockIdx.x), ras_smem);
 }
 
 // restriction: mean of the 8 children; prolongation: copy to the children
@@ -75,7 +76,9 @@ struct OneLevel {
     int64_t nnz = 0, box_cells = 0, owned_cells = 0;
     int depth = 0, width = 0, meta_lev = 0, meta_sl = 0, max_total_levels = 0;
     bool vec = false;  // box vector in LDS instead of the level ring
-    int box_rows = 0;
+    bool folded = false;  // FP64 box vector folded into fold_rows slots
+    int box_rows = 0, fold_rows = 0, spill_stride = 0;
+    int blocks_per_cu = 0;  // workgroups of the sweep kernel that fit one compute unit
     int threads = 256;
     size_t lds_bytes = 0;
     bool lds_ring = false;
@@ -83,7 +86,7 @@ struct OneLevel {
     SdInfo *sd = nullptr;
     int32_t *Lio = nullptr, *Lnext = nullptr, *Uio = nullptr, *Unext = nullptr;
     uint16_t *Laddr = nullptr, *Uaddr = nullptr;
-    void *Lval = nullptr, *Uval = nullptr, *lin = nullptr, *lout = nullptr, *ring = nullptr;
+    void *Lval = nullptr, *Uval = nullptr, *lin = nullptr, *lout = nullptr, *ring = nullptr, *spill = nullptr;
     int32_t *gio = nullptr, *Lmeta = nullptr, *Umeta = nullptr, *perm = nullptr;
 
     static void layout(Carver &c, const HostRas &H, int precision, OneLevel &o) {
@@ -92,17 +95,20 @@ struct OneLevel {
         o.depth = H.ring_depth; o.width = H.ring_width; o.meta_lev = H.max_levels; o.meta_sl = H.max_slices;
         o.max_total_levels = H.max_total_levels; o.precision = precision;
         o.vec = H.box_vector; o.box_rows = H.box_rows;
+        o.folded = H.folded && precision == 0;
+        o.fold_rows = o.folded ? H.fold_rows : 0;
+        o.spill_stride = o.folded ? (H.fold_early + 31) / 32 * 32 : 0;  // 256-byte aligned rows
         o.sd = c.take<SdInfo>(H.sd.size());
         // the box vector needs no per-lane indices of the L sweep, no U y indices
         // apart from its pairs and no input records
         const bool ring = !H.box_vector;
         o.Lio = c.take<int32_t>(ring ? H.L.lane_io.size() : 0);
         o.Lnext = c.take<int32_t>(ring ? H.L.lane_next.size() : 0);
-        o.Laddr = c.take<uint16_t>(H.L.addr.size());
+        o.Laddr = c.take<uint16_t>(o.folded ? H.fold_Laddr.size() : H.L.addr.size());
         o.Lval = c.take<char>(H.L.val.size() * fs);
         o.Uio = c.take<int32_t>(ring ? H.U.lane_io.size() : 0);
         o.Unext = c.take<int32_t>(2 * H.U.lane_next.size());
-        o.Uaddr = c.take<uint16_t>(H.U.addr.size());
+        o.Uaddr = c.take<uint16_t>(o.folded ? H.fold_Uaddr.size() : H.U.addr.size());
         o.Uval = c.take<char>(H.U.val.size() * fs);
         o.lin = c.take<char>(ring ? H.L.lane_io.size() * fs : 0);
         o.lout = c.take<char>(2 * H.U.lane_io.size() * fs);
@@ -111,10 +117,17 @@ struct OneLevel {
         o.Lmeta = c.take<int32_t>(H.L.meta.size());
         o.Umeta = c.take<int32_t>(H.U.meta.size());
         o.perm = c.take<int32_t>(H.perm.size());
+        o.spill = c.take<double>(size_t(H.nsd) * o.spill_stride);
     }
 
     int32_t upload(const HostRas &H) const {
         auto up = [](void *d, const void *s, size_t b) { return b ? hipMemcpy(d, s, b, hipMemcpyHostToDevice) : hipSuccess; };
+        if (folded)  // the late inputs a thread holds (the builder sized the fold for this width)
+            for (const SdInfo &I : H.sd)
+                if (I.nrows - I.fold > kFoldRegs * threads) {
+                    set_error("ras: folded subdomain with %d late rows for %d threads", I.nrows - I.fold, threads);
+                    return CSDYN_EINVAL;
+                }
         CSD_HIP(up(sd, H.sd.data(), H.sd.size() * sizeof(SdInfo)));
         const bool ring = !H.box_vector;
         if (ring) {
@@ -122,18 +135,21 @@ struct OneLevel {
             CSD_HIP(up(Lnext, H.L.lane_next.data(), H.L.lane_next.size() * 4));
             CSD_HIP(up(Uio, H.U.lane_io.data(), H.U.lane_io.size() * 4));
         }
-        CSD_HIP(up(Laddr, H.L.addr.data(), H.L.addr.size() * 2));
-        if (!H.U.lane_next.empty()) {  // box vector: {position, y index} per U lane
-            std::vector<int32_t> ri(2 * H.U.lane_next.size());
-            for (size_t a = 0; a < H.U.lane_next.size(); ++a) {
-                ri[2 * a] = H.U.lane_next[a];
+        const std::vector<uint16_t> &la = folded ? H.fold_Laddr : H.L.addr, &ua = folded ? H.fold_Uaddr : H.U.addr;
+        CSD_HIP(up(Laddr, la.data(), la.size() * 2));
+        if (!H.U.lane_next.empty()) {  // box vector: {position (folded: slot), y index} per U lane
+            const std::vector<int32_t> &pos = folded ? H.fold_Upos : H.U.lane_next;
+            std::vector<int32_t> ri(2 * pos.size());
+            for (size_t a = 0; a < pos.size(); ++a) {
+                ri[2 * a] = pos[a];
                 ri[2 * a + 1] = H.U.lane_io[a];
             }
             CSD_HIP(up(Unext, ri.data(), ri.size() * 4));
         }
-        CSD_HIP(up(Uaddr, H.U.addr.data(), H.U.addr.size() * 2));
+        CSD_HIP(up(Uaddr, ua.data(), ua.size() * 2));
         CSD_HIP(up(gio, H.gio.data(), H.gio.size() * 4));
-        CSD_HIP(up(Lmeta, H.L.meta.data(), H.L.meta.size() * 4));
+        const std::vector<int32_t> &lm = folded ? H.fold_Lmeta : H.L.meta;
+        CSD_HIP(up(Lmeta, lm.data(), lm.size() * 4));
         CSD_HIP(up(Umeta, H.U.meta.data(), H.U.meta.size() * 4));
         CSD_HIP(up(perm, H.perm.data(), H.perm.size() * 4));
         // U-sweep records {L result, 1/u_ii}: the L sweep writes the first
@@ -167,13 +183,15 @@ struct OneLevel {
         R.ring = (TF *)ring;
         R.gio = gio;
         R.perm = perm;
+        R.spill = (TF *)spill;
+        R.spill_stride = spill_stride;
         R.depth = vec ? 1 : depth;
         R.width = vec ? box_rows : width;
         return R;
     }
 
-    template <class TV, class TF, bool LDS, bool VEC, int NT>
-    static const void *kernel() { return (const void *)k_ras<TV, TF, LDS, VEC, NT>; }
+    template <class TV, class TF, bool LDS, bool VEC, int NT, bool FOLD = false>
+    static const void *kernel() { return (const void *)k_ras<TV, TF, LDS, VEC, NT, FOLD>; }
 
     template <class TV, class TF>
     int32_t set_attr() const {
@@ -188,6 +206,11 @@ struct OneLevel {
         CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, true, 256>(), at, lb));
         CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, true, 512>(), at, lb));
         CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, true, 1024>(), at, lb));
+        if constexpr (sizeof(TF) == 8) {
+            CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, true, 256, true>(), at, lb));
+            CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, true, 512, true>(), at, lb));
+            CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, true, 1024, true>(), at, lb));
+        }
         return CSDYN_OK;
     }
 
@@ -200,31 +223,55 @@ struct OneLevel {
         CSD_HIP(hipDeviceGetAttribute(&maxs, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
         const size_t meta = meta_bytes_for(meta_sl, meta_lev);
         const size_t fs = precision ? sizeof(float) : sizeof(double);
-        const size_t rb = vec ? size_t(box_rows) * fs : size_t(depth) * width * fs;
+        const size_t rb = vec ? size_t(folded ? fold_rows : box_rows) * fs : size_t(depth) * width * fs;
         if (meta > size_t(maxs)) { set_error("ras: subdomain schedule too large for LDS"); return CSDYN_EINVAL; }
         lds_ring = meta + rb <= size_t(maxs);
         if (vec && !lds_ring) { set_error("ras: subdomain vector does not fit in LDS"); return CSDYN_EINVAL; }
         lds_bytes = meta + (lds_ring ? rb : 0);
-        threads = width <= 256 ? 256 : (width <= 512 ? 512 : 1024);
+        threads = sweep_threads(width);
         if (precision) {
             CSD_TRY((set_attr<double, float>()));
             CSD_TRY((set_attr<float, float>()));
         } else {
             CSD_TRY((set_attr<double, double>()));
         }
+        // workgroups per compute unit of the kernel that will run (FP64 inputs)
+        auto pick = [&](auto tf) -> const void * {
+            using TF = decltype(tf);
+            auto nt = [&](auto l, auto v, auto f) -> const void * {
+                constexpr bool L = decltype(l)::value, V = decltype(v)::value, F = decltype(f)::value;
+                return threads == 256 ? kernel<double, TF, L, V, 256, F>()
+                       : threads == 512 ? kernel<double, TF, L, V, 512, F>() : kernel<double, TF, L, V, 1024, F>();
+            };
+            using T_ = std::true_type;
+            using F_ = std::false_type;
+            if (vec && folded) {
+                if constexpr (sizeof(TF) == 8) return nt(T_(), T_(), T_());
+            }
+            if (vec) return nt(T_(), T_(), F_());
+            return lds_ring ? nt(T_(), F_(), F_()) : nt(F_(), F_(), F_());
+        };
+        const void *k = precision ? pick(0.0f) : pick(0.0);
+        CSD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks_per_cu, k, threads, lds_bytes));
         return CSDYN_OK;
     }
 
-    template <class TV, class TF, bool LDS, bool VEC>
+    template <class TV, class TF, bool LDS, bool VEC, bool FOLD = false>
     void launch_nt(const TV *x, TV *y, hipStream_t s) const {
         const dim3 g(nsd);
-        if (threads == 256) hipLaunchKernelGGL((k_ras<TV, TF, LDS, VEC, 256>), g, dim3(256), lds_bytes, s, dev<TF>(), meta_lev, meta_sl, x, y);
-        else if (threads == 512) hipLaunchKernelGGL((k_ras<TV, TF, LDS, VEC, 512>), g, dim3(512), lds_bytes, s, dev<TF>(), meta_lev, meta_sl, x, y);
-        else hipLaunchKernelGGL((k_ras<TV, TF, LDS, VEC, 1024>), g, dim3(1024), lds_bytes, s, dev<TF>(), meta_lev, meta_sl, x, y);
+        if (threads == 256) hipLaunchKernelGGL((k_ras<TV, TF, LDS, VEC, 256, FOLD>), g, dim3(256), lds_bytes, s, dev<TF>(), meta_lev, meta_sl, x, y);
+        else if (threads == 512) hipLaunchKernelGGL((k_ras<TV, TF, LDS, VEC, 512, FOLD>), g, dim3(512), lds_bytes, s, dev<TF>(), meta_lev, meta_sl, x, y);
+        else hipLaunchKernelGGL((k_ras<TV, TF, LDS, VEC, 1024, FOLD>), g, dim3(1024), lds_bytes, s, dev<TF>(), meta_lev, meta_sl, x, y);
     }
 
     template <class TV, class TF>
     void launch(const TV *x, TV *y, hipStream_t s) const {
+        if constexpr (sizeof(TF) == 8) {
+            if (vec && folded) {
+                launch_nt<TV, TF, true, true, true>(x, y, s);
+                return;
+            }
+        }
         if (vec) launch_nt<TV, TF, true, true>(x, y, s);
         else if (lds_ring) launch_nt<TV, TF, true, false>(x, y, s);
         else launch_nt<TV, TF, false, false>(x, y, s);
@@ -403,9 +450,11 @@ static int32_t setup_level(csdyn_ras &R, const csdyn_opctx *ctx, const csdyn_ras
     }
     const OneLevel &cl = o.levels == 3 ? R.inner->fine : R.coarse;
     R.info.lds_fine = int32_t(R.fine.lds_bytes);
-    R.info.box_in_lds_fine = R.fine.vec ? 2 : R.fine.lds_ring;
+    R.info.box_in_lds_fine = R.fine.vec ? (R.fine.folded ? 3 : 2) : R.fine.lds_ring;
     R.info.lds_coarse = int32_t(cl.lds_bytes);
-    R.info.box_in_lds_coarse = cl.vec ? 2 : cl.lds_ring;
+    R.info.box_in_lds_coarse = cl.vec ? (cl.folded ? 3 : 2) : cl.lds_ring;
+    R.info.blocks_per_cu_fine = R.fine.blocks_per_cu;
+    R.info.blocks_per_cu_coarse = o.levels >= 2 ? cl.blocks_per_cu : 0;
     R.info.threads_fine = R.fine.threads;
     R.info.threads_coarse = o.levels >= 2 ? cl.threads : 0;
     R.info.structures_fine = b.fine.addr_classes;

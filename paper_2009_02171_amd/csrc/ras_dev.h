@@ -42,7 +42,8 @@ struct DevRas {
     TF *ring;   // [nsd][depth * width] when the ring is not in LDS
     const int32_t *gio;  // box vector: x index of each position, per subdomain from SdInfo::g0
     const int32_t *perm; // [nsd] subdomain of each workgroup
-    int depth, width;
+    TF *spill;           // folded box vector: [nsd][spill_stride] L results of the early rows
+    int depth, width, spill_stride;
 };
 
 // One item of a sweep: one slice for one lane, i.e. the lane's part (at most
@@ -153,19 +154,48 @@ struct Meta {
 // to its ring slot (box vector: its position) and, in the ring layout's L
 // sweep, to its U-sweep record; the U sweep writes the owned rows to y
 // (restricted scatter).
-template <class TV, class TF, bool UPPER, bool LDS, bool VEC, int NT, class Rec>
+// Folded box vector (HostRas::folded): values that wait in registers for
+// their slots, v[u] for slot t + u NT (t the thread, slots below n), written
+// after the barrier that ends level lev: the late rows' inputs in the L
+// sweep, the early rows' L results in the U sweep.  The L sweep also stores
+// the results of the early rows (positions below n, all at levels up to the L
+// sweep's lev) to spill, indexed by position, for the U sweep to read back.
+template <class TF, bool FOLD>
+struct Fold {
+    TF v[kFoldRegs];
+    int lev, n;
+    TF *spill;
+};
+template <class TF>
+struct Fold<TF, false> {};
+
+template <class TV, class TF, bool UPPER, bool LDS, bool VEC, int NT, bool FOLD, class Rec>
 __device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int sl0, int asl0, int64_t off0, int nlev,
-                                      int nsl, TF *ring, const Rec *rec, TF *lout, TV *y) {
+                                      int nsl, TF *ring, const Rec *rec, TF *lout, TV *y, const Fold<TF, FOLD> &fd) {
     constexpr int K = SweepShape<TF, NT>::K;
     const int lane = threadIdx.x % 64, nw = NT / 64;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     int passed = 0;
+    // the barrier that ends level `passed`; folded, after level fd.lev the
+    // waiting values go to their slots (first read at level fd.lev + 2)
+    auto barrier = [&]() {
+        level_barrier<LDS>();
+        if constexpr (FOLD) {
+            if (passed == fd.lev) {
+#pragma unroll
+                for (int u = 0; u < kFoldRegs; ++u) {
+                    const int a = int(threadIdx.x) + u * NT;
+                    if (a < fd.n) ring[a] = fd.v[u];
+                }
+            }
+        }
+    };
     auto pass_to = [&](const Item<TF> &n) {
         const int lv = n.wl >= 0 ? n.wl >> 17 : nlev;
-        for (; passed < lv; ++passed) level_barrier<LDS>();
+        for (; passed < lv; ++passed) barrier();
     };
     if (nsl == 0) {
-        for (; passed < nlev; ++passed) level_barrier<LDS>();
+        for (; passed < nlev; ++passed) barrier();
         return;
     }
     int fg = wv;  // next slice to request (past the end: re-reads the last slice)
@@ -211,6 +241,8 @@ __device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int 
                     if (it.io >= 0) y[it.io] = TV(acc);
                 } else if constexpr (!VEC) {
                     if (it.io >= 0) lout[2 * int64_t(it.io)] = acc;
+                } else if constexpr (FOLD) {  // an early row: its slot is its position
+                    if ((it.wl >> 17) <= fd.lev && it.slot + rr < fd.n) fd.spill[it.slot + rr] = acc;
                 }
             }
             pass_to(k + 1 < K ? grp[k + 1] : next);
@@ -227,7 +259,7 @@ __device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int 
         process(B, A[0]);
         request(B);
     }
-    for (; passed < nlev; ++passed) level_barrier<LDS>();
+    for (; passed < nlev; ++passed) barrier();
     __builtin_amdgcn_s_waitcnt(0);  // requests past the end
 }
 
@@ -247,10 +279,11 @@ __device__ __forceinline__ void meta_pointers(unsigned char *base, int meta_lev,
 // levels is in LDS when LDS = true, else in the workspace; with VEC (always
 // in LDS) the whole box vector is there instead: the gather writes x into it,
 // the L sweep overwrites it with its results and the U sweep with its own.
-template <class TV, class TF, bool LDS, bool VEC, int NT>
+template <class TV, class TF, bool LDS, bool VEC, int NT, bool FOLD = false>
 __device__ __forceinline__ void ras_block(const DevRas<TF> &R, int meta_lev, int meta_sl, const TV *__restrict__ x,
                                           TV *__restrict__ y, int blk, unsigned char *ras_smem) {
     static_assert(LDS || !VEC, "the box vector lives in LDS");
+    static_assert(VEC || !FOLD, "only a box vector is folded");
     const int sdi = __builtin_amdgcn_readfirstlane(R.perm[blk]);
     const SdInfo I = R.sd[sdi];
     const int ring_n = R.depth * R.width;
@@ -273,14 +306,26 @@ __device__ __forceinline__ void ras_block(const DevRas<TF> &R, int meta_lev, int
     const I4 *uimg = reinterpret_cast<const I4 *>(R.U.meta) + size_t(sdi) * n16;
     const I4 up0 = uimg[min(int(threadIdx.x), n16 - 1)];
     const I4 up1 = uimg[min(int(threadIdx.x) + NT, n16 - 1)];
+    Fold<TF, FOLD> fd;
     if constexpr (VEC) {
         // the box vector in L-sweep order: position a holds x[gio[a]];
         // GU positions per thread per round, all index loads and then all
         // value loads in flight together (one round for boxes of up to
-        // GU * NT rows)
+        // GU * NT rows).  Folded: positions from I.fold on wait in registers.
         constexpr int GU = 24;
-        const int nrows = I.nrows;
         const int32_t *gi = R.gio + I.g0;
+        int nrows = I.nrows;
+        if constexpr (FOLD) {
+            fd.lev = I.fold_lev;
+            fd.n = nrows - I.fold;
+            fd.spill = R.spill + int64_t(sdi) * R.spill_stride;
+            int32_t io[kFoldRegs];
+#pragma unroll
+            for (int u = 0; u < kFoldRegs; ++u) io[u] = gi[I.fold + min(int(threadIdx.x) + u * NT, fd.n - 1)];
+#pragma unroll
+            for (int u = 0; u < kFoldRegs; ++u) fd.v[u] = TF(x[io[u]]);
+            nrows = I.fold;
+        }
         for (int a0 = 0; a0 < nrows; a0 += NT * GU) {
             int32_t io[GU];
             TV v[GU];
@@ -312,15 +357,20 @@ __device__ __forceinline__ void ras_block(const DevRas<TF> &R, int meta_lev, int
         }
     }
     __syncthreads();
-    sweep<TV, TF, false, LDS, VEC, NT>(R.L, M, I.slL0, I.aslL0, I.offL0, I.levL1 - I.levL0, I.nslL, ring, R.lin,
-                                       reinterpret_cast<TF *>(R.lout), y);
+    sweep<TV, TF, false, LDS, VEC, NT, FOLD>(R.L, M, I.slL0, I.aslL0, I.offL0, I.levL1 - I.levL0, I.nslL, ring, R.lin,
+                                             reinterpret_cast<TF *>(R.lout), y, fd);
     __syncthreads();  // L results visible; the U metadata replaces the L metadata
+    if constexpr (FOLD) {  // the early rows' L results, back from spill (written after the U sweep's level fold_levU)
+#pragma unroll
+        for (int u = 0; u < kFoldRegs; ++u) fd.v[u] = fd.spill[min(int(threadIdx.x) + u * NT, max(fd.n - 1, 0))];
+        fd.lev = I.fold_levU;
+    }
     if (int(threadIdx.x) < n16) md[threadIdx.x] = up0;
     if (int(threadIdx.x) + NT < n16) md[threadIdx.x + NT] = up1;
     for (int a = threadIdx.x + MU * NT; a < n16; a += NT) md[a] = uimg[a];
     __syncthreads();
-    sweep<TV, TF, true, LDS, VEC, NT>(R.U, M, I.slU0, I.aslU0, I.offU0, I.levU1 - I.levU0, I.nslU, ring, R.lout,
-                                      nullptr, y);
+    sweep<TV, TF, true, LDS, VEC, NT, FOLD>(R.U, M, I.slU0, I.aslU0, I.offU0, I.levU1 - I.levU0, I.nslU, ring, R.lout,
+                                            nullptr, y, fd);
 }
 
 // Device view of the fine one-level RAS of a preconditioner with FP32 factors

@@ -485,6 +485,46 @@ void sweep_stats(const LocalSd &L, int &span, int &rows) {
     }
 }
 
+// Fold point and the level after which the late inputs are written, for one
+// subdomain whose box vector gets at most `cap` slots (HostRas::folded gives
+// the conditions).  S: the L schedule (box-vector positions).  Returns false
+// when no slice boundary within cap satisfies them.
+bool fold_plan(const LocalSd &L, const Schedule &S, int cap, int max_late, int32_t &fold, int32_t &fold_lev,
+               int32_t &fold_levU) {
+    const int nrow = int(L.rp.size()) - 1;
+    fold = nrow;
+    fold_lev = fold_levU = -1;
+    if (nrow <= cap) return true;
+    int f = 0;  // the largest slice start within cap
+    for (int32_t p0 : S.slice_slot)
+        if (p0 <= cap) f = std::max(f, int(p0));
+    const int early = nrow - f;
+    if (f <= 0 || early > f || early > max_late) return false;
+    // last level at which each row is read or written, per sweep
+    std::vector<int32_t> lastL(L.levL), lastU(L.levU);
+    for (int d = 0; d < nrow; ++d) {
+        for (int64_t q = L.rp[d]; q < L.diag[d]; ++q) lastL[L.ci[q]] = std::max(lastL[L.ci[q]], L.levL[d]);
+        for (int64_t q = L.diag[d] + 1; q < L.rp[d + 1]; ++q) lastU[L.ci[q]] = std::max(lastU[L.ci[q]], L.levU[d]);
+    }
+    int aL = -1, bL = INT32_MAX, aU = -1, bU = INT32_MAX;
+    for (int r = 0; r < nrow; ++r) {
+        const int p = S.slot[r];
+        if (p < early) {
+            aL = std::max(aL, int(lastL[r]));
+            bU = std::min(bU, int(L.levU[r]));
+        }
+        if (p >= f) {
+            bL = std::min(bL, int(L.levL[r]));
+            aU = std::max(aU, int(lastU[r]));
+        }
+    }
+    if (bL < aL + 2 || bU < aU + 2) return false;
+    fold = f;
+    fold_lev = aL;
+    fold_levU = aU;
+    return true;
+}
+
 }  // namespace
 
 int32_t host_subdomain(const HostGeom &g, const csdyn_op &op, const int sub[3], int overlap, int s,
@@ -546,8 +586,9 @@ int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], 
     H.ring_depth = span + 1;
     H.ring_width = ((rows + 63) / 64) * 64;
     for (int s = 0; s < H.nsd; ++s) H.box_rows = std::max(H.box_rows, int(loc[s].rp.size()) - 1);
-    if (storage < 0 || storage > 2) { set_error("ras: storage must be 0, 1 or 2"); return CSDYN_EINVAL; }
-    H.box_vector = storage == 2 || (storage == 0 && int64_t(H.box_rows) * int64_t(sizeof(double)) <= kBoxVectorBytes);
+    if (storage < 0 || storage > 3) { set_error("ras: storage must be 0, 1, 2 or 3"); return CSDYN_EINVAL; }
+    H.box_vector = storage == 2 ||
+                   (storage != 1 && int64_t(H.box_rows) * int64_t(sizeof(double)) <= kBoxVectorBytes);
     if (H.box_vector && H.box_rows > 65535) {
         set_error("ras: subdomain of %d rows too large for 16-bit vector addresses", H.box_rows);
         return CSDYN_EINVAL;
@@ -556,10 +597,29 @@ int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], 
         set_error("ras: subdomain too large for the level ring (%d levels x %d rows)", H.ring_depth, H.ring_width);
         return CSDYN_EINVAL;
     }
+    // Folding: the metadata size needs every subdomain's slice counts first.
+    int fold_cap = 0;
+    if (H.box_vector && storage != 3) {
+        int msl = 0, mlev = 0;
+        for (int s = 0; s < H.nsd; ++s) {
+            Schedule a, b;
+            make_schedule(loc[s], false, 0, H.ring_width, nullptr, a);
+            make_schedule(loc[s], true, 0, H.ring_width, &a.slot, b);
+            msl = std::max(msl, std::max(a.lev_first.back(), b.lev_first.back()));
+            mlev = std::max(mlev, std::max(loc[s].nlevL, loc[s].nlevU));
+        }
+        const int64_t meta = int64_t(meta_bytes_for(msl, mlev));
+        if (meta + int64_t(H.box_rows) * int64_t(sizeof(double)) > kFoldBytes && meta < kFoldBytes)
+            fold_cap = int((kFoldBytes - meta) / int64_t(sizeof(double)));
+    }
+    H.folded = fold_cap > 0;
+    const int max_late = kFoldRegs * sweep_threads(H.ring_width);
     H.sd.resize(H.nsd);
     for (int s = 0; s < H.nsd; ++s) {
         LocalSd &L = loc[s];
         SdInfo &I = H.sd[s];
+        I.fold = int32_t(L.rp.size()) - 1;
+        I.fold_lev = I.fold_levU = -1;
         I.nloc = int32_t(L.gcell.size());
         I.nown = int32_t(L.own.size());
         H.box_cells += I.nloc;
@@ -584,8 +644,22 @@ int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], 
                 H.gio[size_t(I.g0 + a)] = int32_t(4 * int64_t(L.gcell[r / 4]) + r % 4);
             }
         }
+        if (H.folded && !fold_plan(L, SL, fold_cap, max_late, I.fold, I.fold_lev, I.fold_levU)) H.folded = false;
+        const size_t u_lanes0 = H.U.lane_next.size(), u_addr0 = H.U.addr.size(), l_addr0 = H.L.addr.size();
         if (int32_t e = pack_sweep(L, true, SU, nullptr, 0, H.box_vector, H.U, I.levU0, I.levU1)) return e;
         if (int32_t e = pack_sweep(L, false, SL, &SU, base_u, H.box_vector, H.L, I.levL0, I.levL1)) return e;
+        if (H.folded) {  // this subdomain's part of the folded arrays (parallel to the unshared packs)
+            const int32_t f = I.fold;
+            auto slot = [&](int32_t p) { return p >= f ? p - f : p; };
+            for (size_t a = u_addr0; a < H.U.addr.size(); ++a) H.fold_Uaddr.push_back(uint16_t(slot(H.U.addr[a])));
+            for (size_t a = l_addr0; a < H.L.addr.size(); ++a) H.fold_Laddr.push_back(uint16_t(slot(H.L.addr[a])));
+            for (size_t a = u_lanes0; a < H.U.lane_next.size(); ++a) {
+                const int32_t p = H.U.lane_next[a];
+                H.fold_Upos.push_back(p < 0 ? -1 : slot(p));
+            }
+            H.fold_rows = std::max(H.fold_rows, int(f));
+            H.fold_early = std::max(H.fold_early, int(I.nrows - f));
+        }
         H.max_slices = std::max(H.max_slices, std::max(SL.lev_first.back(), SU.lev_first.back()));
         H.max_levels = std::max(H.max_levels, std::max(L.nlevL, L.nlevU));
         H.max_total_levels = std::max(H.max_total_levels, L.nlevL + L.nlevU);
@@ -624,6 +698,18 @@ int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], 
             }
         }
     }
+    if (H.folded) {  // the L sweep's slice slots, folded
+        H.fold_Lmeta = H.L.meta;
+        const int msl = H.max_slices;
+        for (int s = 0; s < H.nsd; ++s) {
+            const SdInfo &I = H.sd[s];
+            int32_t *m = H.fold_Lmeta.data() + size_t(s) * H.meta_words;
+            for (int q = 0; q < I.nslL; ++q) {
+                int32_t &v = m[offw + 2 * msl + q];
+                if (v >= I.fold) v -= I.fold;
+            }
+        }
+    }
     // Boxes of the same shape at the same place relative to the panel edges and
     // the radial ends have the same sweep structure: each distinct address block
     // is stored once and the subdomains point at it.
@@ -659,6 +745,20 @@ int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], 
             }
             (pass ? I.aslU0 : I.aslL0) = at;
         }
+        if (H.folded) {  // the folded blocks, shared the same way (equal structures fold alike)
+            std::vector<uint16_t> &F = pass ? H.fold_Uaddr : H.fold_Laddr;
+            std::vector<uint16_t> fshared;
+            for (int s = 0; s < H.nsd && H.folded; ++s) {
+                const SdInfo &I = H.sd[s];
+                const int sl0 = pass ? I.slU0 : I.slL0, nsl = pass ? I.nslU : I.nslL;
+                const size_t at = size_t(pass ? I.aslU0 : I.aslL0) * kSl, len = size_t(nsl) * kSl;
+                const uint16_t *blk = F.data() + size_t(sl0) * kSl;
+                if (at == fshared.size()) fshared.insert(fshared.end(), blk, blk + len);
+                else if (at + len > fshared.size() || !std::equal(blk, blk + len, fshared.begin() + at))
+                    H.folded = false;
+            }
+            F.swap(fshared);
+        }
         P.addr.swap(shared);
     }
     {
@@ -682,6 +782,20 @@ int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], 
     for (SweepPack *P : {&H.L, &H.U}) {
         P->val.resize(P->val.size() + 64 * 64, 0.0);
         P->addr.resize(P->addr.size() + 64 * 64, 0);
+    }
+    if (H.folded) {
+        H.fold_Laddr.resize(H.fold_Laddr.size() + 64 * 64, 0);
+        H.fold_Uaddr.resize(H.fold_Uaddr.size() + 64 * 64, 0);
+    } else {  // not needed, or some subdomain's levels do not allow it
+        for (SdInfo &I : H.sd) {
+            I.fold = I.nrows;
+            I.fold_lev = I.fold_levU = -1;
+        }
+        H.fold_rows = H.fold_early = 0;
+        std::vector<uint16_t>().swap(H.fold_Laddr);
+        std::vector<uint16_t>().swap(H.fold_Uaddr);
+        std::vector<int32_t>().swap(H.fold_Lmeta);
+        std::vector<int32_t>().swap(H.fold_Upos);
     }
     return CSDYN_OK;
 }

@@ -51,6 +51,12 @@ struct SdInfo {
     int32_t aslL0, aslU0;            // first slice of the subdomain's block in each sweep's (shared) addresses
     int64_t g0;                      // box vector: first entry of the subdomain's gather list
     int64_t offL0, offU0;            // first value pair of each sweep
+    // Folded box vector (HostRas::folded): positions p >= fold share slot
+    // p - fold with the first nrows - fold positions; the late positions'
+    // inputs are written after the L sweep's level fold_lev, the early
+    // positions' L results after the U sweep's level fold_levU (fold = nrows,
+    // fold_lev = fold_levU = -1: nothing folded)
+    int32_t fold, fold_lev, fold_levU;
 };
 
 // Bytes of one sweep's slice metadata as the sweep kernel keeps it in LDS
@@ -64,6 +70,17 @@ constexpr size_t meta_bytes_for(int nsl, int nlev) {
 
 constexpr int64_t kBoxVectorBytes = 90 * 1024;
 constexpr int kXcds = 8;  // L2 domains of the GPU; consecutive workgroups go to consecutive domains
+// LDS of one workgroup of the folded FP64 box-vector sweep (metadata and
+// slots): two such workgroups fit the 160 KiB of a compute unit with room for
+// the allocation granularity.
+constexpr int64_t kFoldBytes = 80 * 1024 - 512;
+// Late inputs of a folded box vector held per thread from the gather to
+// their write.
+constexpr int kFoldRegs = 3;
+
+// Workgroup size of a sweep whose widest level has `width` lanes (rounded to
+// 64): one wavefront per slice of that level, at least 256 threads.
+inline int sweep_threads(int width) { return width <= 256 ? 256 : (width <= 512 ? 512 : 1024); }
 
 struct HostRas {
     int nsd = 0;
@@ -91,11 +108,30 @@ struct HostRas {
     std::vector<int32_t> perm;
     int addr_classes = 0;                // distinct (L, U) address structures
     int meta_words = 0;                  // int32 words of one metadata image (meta_bytes_for / 4)
+    // Folded box vector, for FP64 sweeps whose whole vector would keep one
+    // workgroup per compute unit.  Every row keeps its position in the L
+    // sweep's order; position p of a subdomain with fold point f (SdInfo::fold)
+    // is stored in slot p - f when p >= f ("late"), else in slot p, so the late
+    // rows reuse the slots of the first e = nrows - f rows ("early").  Valid
+    // when every L-sweep access of an early row precedes the late rows' first
+    // level by two levels (the late inputs, held in registers since the
+    // gather, are written in between, after the level SdInfo::fold_lev), and
+    // every U-sweep access of a late row precedes the early rows' first U
+    // level by two levels (the early rows' L results, stored to device memory
+    // by the L sweep and read back into registers when the U sweep starts, are
+    // written in between, after the level SdInfo::fold_levU).  The arrays
+    // below replace, for the FP64 sweep, L.addr, U.addr, L.meta and U's
+    // positions (same layouts); fold_early is the largest e.
+    bool folded = false;
+    int fold_rows = 0, fold_early = 0;  // slots of the largest folded subdomain, its early rows
+    std::vector<uint16_t> fold_Laddr, fold_Uaddr;
+    std::vector<int32_t> fold_Lmeta, fold_Upos;
 };
 
 // Build and factor.  Returns CSDYN_EZEROPIVOT / CSDYN_EINVAL on failure.
-// storage: 0 automatic (box vector when its FP64 size fits kBoxVectorBytes),
-// 1 ring, 2 box vector.
+// storage: 0 automatic (box vector when its FP64 size fits kBoxVectorBytes,
+// folded when metadata and vector exceed kFoldBytes and the fold is valid),
+// 1 ring, 2 box vector (folded as in 0), 3 as 0 but never folded.
 int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], int overlap, int storage,
                        HostRas &out);
 

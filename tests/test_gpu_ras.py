@@ -93,7 +93,7 @@ def test_ras_rejects_bad_options():
     with pytest.raises(csdyn.CsdynError):
         csdyn.RAS(op, sub=(6, 6, 3), levels=2)   # odd subdomain size for two levels
     with pytest.raises(csdyn.CsdynError):
-        csdyn.RAS(op, sub=(6, 6, 3), storage=3)
+        csdyn.RAS(op, sub=(6, 6, 3), storage=4)
     big = csdyn.Operator(16, 16)
     with pytest.raises(csdyn.CsdynError):       # a 16^3 box's FP64 vector does not fit in LDS
         csdyn.RAS(big, sub=(16, 16, 16), storage=2)
@@ -150,7 +150,9 @@ def test_coarse_level_shape_sampled(precision, tol):
     oracle's single-subdomain solve in the same precision."""
     info = _sampled_parity(48, 48, 0, (12, 12, 12), precision, (0, 3, 17, 21, 42, 63, 64 + 21, 383), tol,
                            seed=81 + precision)
-    assert info["box_in_lds_fine"] == 2 and info["threads_fine"] == 512
+    # FP64: the vector folded so that two workgroups share a compute unit
+    assert info["box_in_lds_fine"] == (3 if precision == 0 else 2) and info["threads_fine"] == 512
+    assert info["blocks_per_cu_fine"] >= 2
 
 
 @pytest.mark.parametrize("kind,precision,tol", [(0, 0, 1e-12), (1, 0, 1e-12), (0, 1, 1e-5), (1, 1, 1e-5)])
@@ -164,9 +166,32 @@ def test_coarse_box_shape_full(kind, precision, tol):
     y_ref = O.Preconditioner(pb, sub=sub, levels=1, precision=precision).apply(x)
     _, pc = _setup(n, nr, kind, sub, precision=precision)
     info = pc.info()
-    assert info["box_in_lds_fine"] == 2 and info["threads_fine"] == 512, info
+    assert info["box_in_lds_fine"] == (3 if precision == 0 else 2) and info["threads_fine"] == 512, info
     y = _apply(pc, x)
     assert np.abs(y - y_ref).max() / np.abs(y_ref).max() <= tol
+
+
+@pytest.mark.parametrize("n,kind", [(24, 0), (24, 1), (24, 2), (48, 0), (48, 1)])
+def test_folded_box_vector_equals_unfolded(n, kind):
+    """The folded FP64 box vector (late rows in the slots of the early rows,
+    early L results through the U records) gives the unfolded sweep's results
+    bit for bit, on every subdomain of the 12^3-box shape; the folded sweep
+    fits two workgroups per compute unit, the unfolded one."""
+    print(f"[ras fold] n={n} kind={kind}", flush=True)
+    sub = (12, 12, 12)
+    x = inputs.random_field((6, n, n, n, 4), seed=121 + n + kind)
+    _, pf = _setup(n, n, kind, sub, storage=2)
+    _, pu = _setup(n, n, kind, sub, storage=3)
+    fi, ui = pf.info(), pu.info()
+    assert fi["box_in_lds_fine"] == 3 and ui["box_in_lds_fine"] == 2, (fi, ui)
+    assert fi["lds_fine"] <= 80 * 1024 - 512 < ui["lds_fine"]
+    assert fi["blocks_per_cu_fine"] == 2 and ui["blocks_per_cu_fine"] == 1, (fi, ui)
+    yf, yu = _apply(pf, x), _apply(pu, x)
+    assert np.array_equal(yf, yu)
+    if n == 24 and kind == 2:  # and the oracle, for the system with the temperature
+        pb = O.Problem(n, n, kind=kind)
+        y_ref = O.Preconditioner(pb, sub=sub, levels=1).apply(x)
+        assert np.abs(yf - y_ref).max() / np.abs(y_ref).max() <= 1e-12
 
 
 @pytest.mark.parametrize("kind,precision,tol", [(0, 0, 1e-9), (1, 0, 1e-9), (0, 1, 1e-4)])
