@@ -7,6 +7,7 @@
 #include <cmath>
 #include <map>
 #include <numeric>
+#include <string>
 
 namespace csd {
 
@@ -614,59 +615,188 @@ int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], 
     }
     H.folded = fold_cap > 0;
     const int max_late = kFoldRegs * sweep_threads(H.ring_width);
+    // Schedules and packs: each subdomain's in parallel into a pack of its own
+    // (slice, pair, lane and level indices from 0), then appended in subdomain
+    // order with its offsets added, a chunk of subdomains at a time so that the
+    // local packs never hold more than a chunk's data.
+    struct Packed {
+        SweepPack L, U;
+        std::vector<int32_t> gio, fold_Upos;
+        std::vector<uint16_t> fold_Laddr, fold_Uaddr;
+        int32_t levL0 = 0, levL1 = 0, levU0 = 0, levU1 = 0;
+        int32_t status = CSDYN_OK;
+        std::string err;
+        bool fold_ok = true;
+        int max_slices = 0;
+        int64_t nnz = 0;
+    };
+    const int depth = H.box_vector ? 0 : H.ring_depth;
+    const bool want_fold = H.folded;
+    constexpr int kChunk = 64;
     H.sd.resize(H.nsd);
-    for (int s = 0; s < H.nsd; ++s) {
-        LocalSd &L = loc[s];
-        SdInfo &I = H.sd[s];
-        I.fold = int32_t(L.rp.size()) - 1;
-        I.fold_lev = I.fold_levU = -1;
-        I.nloc = int32_t(L.gcell.size());
-        I.nown = int32_t(L.own.size());
-        H.box_cells += I.nloc;
-        H.owned_cells += I.nown;
-        H.nnz += int64_t(L.ci.size());
-        Schedule SL, SU;
-        const int depth = H.box_vector ? 0 : H.ring_depth;
-        make_schedule(L, false, depth, H.ring_width, nullptr, SL);
-        make_schedule(L, true, depth, H.ring_width, H.box_vector ? &SL.slot : nullptr, SU);
-        const int64_t base_u = int64_t(H.U.sl_info.size());
-        const int64_t nrow = int64_t(L.rp.size()) - 1;
-        I.nrows = int32_t(nrow);
-        I.g0 = int64_t(H.gio.size());
-        if (H.box_vector) {  // position SL.slot[r] of the box vector holds row r
-            H.gio.resize(size_t(I.g0 + nrow), -1);
-            for (int64_t r = 0; r < nrow; ++r) {
-                const int64_t a = SL.slot[r];
-                if (a < 0 || a >= nrow || H.gio[size_t(I.g0 + a)] >= 0) {
-                    set_error("ras: box-vector positions of subdomain %d are not a permutation", s);
-                    return CSDYN_EINVAL;
+    for (int c0 = 0; c0 < H.nsd; c0 += kChunk) {
+        const int c1 = std::min(H.nsd, c0 + kChunk);
+        std::vector<Packed> pk(size_t(c1 - c0));
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int s = c0; s < c1; ++s) {
+            LocalSd &L = loc[s];
+            SdInfo &I = H.sd[s];
+            Packed &Q = pk[size_t(s - c0)];
+            const int64_t nrow = int64_t(L.rp.size()) - 1;
+            I.nrows = int32_t(nrow);
+            I.fold = int32_t(nrow);
+            I.fold_lev = I.fold_levU = -1;
+            I.nloc = int32_t(L.gcell.size());
+            I.nown = int32_t(L.own.size());
+            Q.nnz = int64_t(L.ci.size());
+            Schedule SL, SU;
+            make_schedule(L, false, depth, H.ring_width, nullptr, SL);
+            make_schedule(L, true, depth, H.ring_width, H.box_vector ? &SL.slot : nullptr, SU);
+            if (H.box_vector) {  // position SL.slot[r] of the box vector holds row r
+                Q.gio.assign(size_t(nrow), -1);
+                for (int64_t r = 0; r < nrow && Q.status == CSDYN_OK; ++r) {
+                    const int64_t a = SL.slot[r];
+                    if (a < 0 || a >= nrow || Q.gio[size_t(a)] >= 0) {
+                        Q.status = CSDYN_EINVAL;
+                        Q.err = "ras: box-vector positions of subdomain " + std::to_string(s) + " are not a permutation";
+                    } else {
+                        Q.gio[size_t(a)] = int32_t(4 * int64_t(L.gcell[r / 4]) + r % 4);
+                    }
                 }
-                H.gio[size_t(I.g0 + a)] = int32_t(4 * int64_t(L.gcell[r / 4]) + r % 4);
+            }
+            if (want_fold) Q.fold_ok = fold_plan(L, SL, fold_cap, max_late, I.fold, I.fold_lev, I.fold_levU);
+            int32_t e = Q.status;
+            if (e == CSDYN_OK) e = pack_sweep(L, true, SU, nullptr, 0, H.box_vector, Q.U, Q.levU0, Q.levU1);
+            if (e == CSDYN_OK) e = pack_sweep(L, false, SL, &SU, 0, H.box_vector, Q.L, Q.levL0, Q.levL1);
+            if (e != CSDYN_OK && Q.status == CSDYN_OK) {
+                Q.status = e;
+                Q.err = csdyn_last_error();
+            }
+            if (e == CSDYN_OK && want_fold && Q.fold_ok) {  // the folded copies (parallel to the packs)
+                const int32_t f = I.fold;
+                auto slot = [&](int32_t p) { return p >= f ? p - f : p; };
+                Q.fold_Uaddr.reserve(Q.U.addr.size());
+                Q.fold_Laddr.reserve(Q.L.addr.size());
+                for (uint16_t a : Q.U.addr) Q.fold_Uaddr.push_back(uint16_t(slot(a)));
+                for (uint16_t a : Q.L.addr) Q.fold_Laddr.push_back(uint16_t(slot(a)));
+                for (int32_t p : Q.U.lane_next) Q.fold_Upos.push_back(p < 0 ? -1 : slot(p));
+            }
+            Q.max_slices = std::max(SL.lev_first.back(), SU.lev_first.back());
+            LocalSd().gcell.swap(L.gcell);
+            std::vector<int64_t>().swap(L.rp);
+            std::vector<int32_t>().swap(L.ci);
+            std::vector<double>().swap(L.v);
+        }
+        // offsets of each subdomain of the chunk in the appended arrays (and the
+        // bases its indices are shifted by), then the copies in parallel
+        const int nc = c1 - c0;
+        for (int q = 0; q < nc; ++q)
+            if (pk[size_t(q)].status != CSDYN_OK) {
+                set_error("%s", pk[size_t(q)].err.c_str());
+                return pk[size_t(q)].status;
+            }
+        if (H.folded)
+            for (int q = 0; q < nc; ++q) H.folded = H.folded && pk[size_t(q)].fold_ok;
+        struct Off {
+            size_t lev[2], sl[2], pair[2], lane[2], addr[2], gio, fpos;
+        };
+        std::vector<Off> off(size_t(nc) + 1);
+        SweepPack *HP[2] = {&H.L, &H.U};
+        for (int w = 0; w < 2; ++w) {
+            off[0].lev[w] = HP[w]->lev_slice.size();
+            off[0].sl[w] = HP[w]->sl_info.size();
+            off[0].pair[w] = HP[w]->val.size() / 2;
+            off[0].lane[w] = HP[w]->lane_io.size();
+            off[0].addr[w] = HP[w]->addr.size();
+        }
+        off[0].gio = H.gio.size();
+        off[0].fpos = H.fold_Upos.size();
+        for (int q = 0; q < nc; ++q) {
+            const Packed &Q = pk[size_t(q)];
+            for (int w = 0; w < 2; ++w) {
+                const SweepPack &P = w ? Q.U : Q.L;
+                off[size_t(q) + 1].lev[w] = off[size_t(q)].lev[w] + P.lev_slice.size();
+                off[size_t(q) + 1].sl[w] = off[size_t(q)].sl[w] + P.sl_info.size();
+                off[size_t(q) + 1].pair[w] = off[size_t(q)].pair[w] + P.val.size() / 2;
+                off[size_t(q) + 1].lane[w] = off[size_t(q)].lane[w] + P.lane_io.size();
+                off[size_t(q) + 1].addr[w] = off[size_t(q)].addr[w] + P.addr.size();
+            }
+            off[size_t(q) + 1].gio = off[size_t(q)].gio + Q.gio.size();
+            off[size_t(q) + 1].fpos = off[size_t(q)].fpos + (H.folded ? Q.fold_Upos.size() : 0);
+        }
+        // the first chunk sets the capacity of the whole build (no reallocation
+        // copies later unless later subdomains are larger)
+        auto grow = [&](auto &v, size_t n) {
+            if (c0 == 0) v.reserve(size_t(double(n) * double(H.nsd) / double(nc) * 1.05) + 64 * 64);
+            v.resize(n);
+        };
+        for (int w = 0; w < 2; ++w) {
+            SweepPack &P = *HP[w];
+            grow(P.lev_slice, off[size_t(nc)].lev[w]);
+            grow(P.sl_info, off[size_t(nc)].sl[w]);
+            grow(P.sl_off, off[size_t(nc)].sl[w]);
+            grow(P.sl_slot, off[size_t(nc)].sl[w]);
+            grow(P.lane_io, off[size_t(nc)].lane[w]);
+            if (w == 0 || H.box_vector) grow(P.lane_next, off[size_t(nc)].lane[w]);
+            if (w == 1) grow(P.lane_diag, off[size_t(nc)].lane[w]);
+            grow(P.val, 2 * off[size_t(nc)].pair[w]);
+            grow(P.addr, off[size_t(nc)].addr[w]);
+        }
+        grow(H.gio, off[size_t(nc)].gio);
+        if (H.folded) {
+            grow(H.fold_Laddr, off[size_t(nc)].addr[0]);
+            grow(H.fold_Uaddr, off[size_t(nc)].addr[1]);
+            grow(H.fold_Upos, off[size_t(nc)].fpos);
+        }
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int q = 0; q < nc; ++q) {
+            Packed &Q = pk[size_t(q)];
+            const Off &o = off[size_t(q)];
+            SdInfo &I = H.sd[size_t(c0 + q)];
+            for (int w = 0; w < 2; ++w) {
+                SweepPack &P = *HP[w], &S = w ? Q.U : Q.L;
+                for (size_t a = 0; a < S.lev_slice.size(); ++a) P.lev_slice[o.lev[w] + a] = int32_t(S.lev_slice[a] + o.sl[w]);
+                std::copy(S.sl_info.begin(), S.sl_info.end(), P.sl_info.begin() + ptrdiff_t(o.sl[w]));
+                for (size_t a = 0; a < S.sl_off.size(); ++a) P.sl_off[o.sl[w] + a] = S.sl_off[a] + int64_t(o.pair[w]);
+                std::copy(S.sl_slot.begin(), S.sl_slot.end(), P.sl_slot.begin() + ptrdiff_t(o.sl[w]));
+                std::copy(S.lane_io.begin(), S.lane_io.end(), P.lane_io.begin() + ptrdiff_t(o.lane[w]));
+                // the ring's L lanes point at U lanes: shift them by this subdomain's first U lane
+                const bool ring_l = w == 0 && !H.box_vector;
+                const int64_t ub = int64_t(o.sl[1]) * 64;
+                for (size_t a = 0; a < S.lane_next.size(); ++a)
+                    P.lane_next[o.lane[w] + a] = ring_l && S.lane_next[a] >= 0 ? int32_t(S.lane_next[a] + ub) : S.lane_next[a];
+                std::copy(S.lane_diag.begin(), S.lane_diag.end(), P.lane_diag.begin() + ptrdiff_t(o.lane[w]));
+                std::copy(S.val.begin(), S.val.end(), P.val.begin() + ptrdiff_t(2 * o.pair[w]));
+                std::copy(S.addr.begin(), S.addr.end(), P.addr.begin() + ptrdiff_t(o.addr[w]));
+            }
+            I.levL0 = Q.levL0 + int32_t(o.lev[0]);
+            I.levL1 = Q.levL1 + int32_t(o.lev[0]);
+            I.levU0 = Q.levU0 + int32_t(o.lev[1]);
+            I.levU1 = Q.levU1 + int32_t(o.lev[1]);
+            I.g0 = int64_t(o.gio);
+            std::copy(Q.gio.begin(), Q.gio.end(), H.gio.begin() + ptrdiff_t(o.gio));
+            if (H.folded) {
+                std::copy(Q.fold_Laddr.begin(), Q.fold_Laddr.end(), H.fold_Laddr.begin() + ptrdiff_t(o.addr[0]));
+                std::copy(Q.fold_Uaddr.begin(), Q.fold_Uaddr.end(), H.fold_Uaddr.begin() + ptrdiff_t(o.addr[1]));
+                std::copy(Q.fold_Upos.begin(), Q.fold_Upos.end(), H.fold_Upos.begin() + ptrdiff_t(o.fpos));
             }
         }
-        if (H.folded && !fold_plan(L, SL, fold_cap, max_late, I.fold, I.fold_lev, I.fold_levU)) H.folded = false;
-        const size_t u_lanes0 = H.U.lane_next.size(), u_addr0 = H.U.addr.size(), l_addr0 = H.L.addr.size();
-        if (int32_t e = pack_sweep(L, true, SU, nullptr, 0, H.box_vector, H.U, I.levU0, I.levU1)) return e;
-        if (int32_t e = pack_sweep(L, false, SL, &SU, base_u, H.box_vector, H.L, I.levL0, I.levL1)) return e;
-        if (H.folded) {  // this subdomain's part of the folded arrays (parallel to the unshared packs)
-            const int32_t f = I.fold;
-            auto slot = [&](int32_t p) { return p >= f ? p - f : p; };
-            for (size_t a = u_addr0; a < H.U.addr.size(); ++a) H.fold_Uaddr.push_back(uint16_t(slot(H.U.addr[a])));
-            for (size_t a = l_addr0; a < H.L.addr.size(); ++a) H.fold_Laddr.push_back(uint16_t(slot(H.L.addr[a])));
-            for (size_t a = u_lanes0; a < H.U.lane_next.size(); ++a) {
-                const int32_t p = H.U.lane_next[a];
-                H.fold_Upos.push_back(p < 0 ? -1 : slot(p));
+        for (int q = 0; q < nc; ++q) {
+            Packed &Q = pk[size_t(q)];
+            const LocalSd &L = loc[size_t(c0 + q)];
+            const SdInfo &I = H.sd[size_t(c0 + q)];
+            H.box_cells += I.nloc;
+            H.owned_cells += I.nown;
+            H.nnz += Q.nnz;
+            if (H.folded) {
+                H.fold_rows = std::max(H.fold_rows, int(I.fold));
+                H.fold_early = std::max(H.fold_early, int(I.nrows - I.fold));
             }
-            H.fold_rows = std::max(H.fold_rows, int(f));
-            H.fold_early = std::max(H.fold_early, int(I.nrows - f));
+            H.max_slices = std::max(H.max_slices, Q.max_slices);
+            H.max_levels = std::max(H.max_levels, std::max(L.nlevL, L.nlevU));
+            H.max_total_levels = std::max(H.max_total_levels, L.nlevL + L.nlevU);
+            Q = Packed();
         }
-        H.max_slices = std::max(H.max_slices, std::max(SL.lev_first.back(), SU.lev_first.back()));
-        H.max_levels = std::max(H.max_levels, std::max(L.nlevL, L.nlevU));
-        H.max_total_levels = std::max(H.max_total_levels, L.nlevL + L.nlevU);
-        LocalSd().gcell.swap(L.gcell);
-        std::vector<int64_t>().swap(L.rp);
-        std::vector<int32_t>().swap(L.ci);
-        std::vector<double>().swap(L.v);
     }
     if (H.max_levels >= 1 << 14) {
         set_error("ras: %d levels in one triangular sweep (at most 16383)", H.max_levels);
