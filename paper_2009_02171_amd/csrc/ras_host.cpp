@@ -588,20 +588,23 @@ int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], 
     H.ring_width = ((rows + 63) / 64) * 64;
     for (int s = 0; s < H.nsd; ++s) H.box_rows = std::max(H.box_rows, int(loc[s].rp.size()) - 1);
     if (storage < 0 || storage > 3) { set_error("ras: storage must be 0, 1, 2 or 3"); return CSDYN_EINVAL; }
-    H.box_vector = storage == 2 ||
-                   (storage != 1 && int64_t(H.box_rows) * int64_t(sizeof(double)) <= kBoxVectorBytes);
+    const int64_t vec_bytes = int64_t(H.box_rows) * int64_t(sizeof(double));
+    const int max_late = kFoldRegs * sweep_threads(H.ring_width);
+    // A subdomain vector above the automatic bound can still live in LDS folded
+    // into one workgroup's share (kLdsFoldBytes) when its late rows fit the
+    // registers that hold them; the schedules below decide.
+    const bool try_big = (storage == 0 || storage == 2) && vec_bytes > kBoxVectorBytes &&
+                         int64_t(H.box_rows) - kLdsFoldBytes / int64_t(sizeof(double)) <= max_late;
+    H.box_vector = storage == 2 || (storage != 1 && vec_bytes <= kBoxVectorBytes) || try_big;
     if (H.box_vector && H.box_rows > 65535) {
         set_error("ras: subdomain of %d rows too large for 16-bit vector addresses", H.box_rows);
-        return CSDYN_EINVAL;
-    }
-    if (!H.box_vector && int64_t(H.ring_depth) * H.ring_width > 65536) {
-        set_error("ras: subdomain too large for the level ring (%d levels x %d rows)", H.ring_depth, H.ring_width);
         return CSDYN_EINVAL;
     }
     // Folding: the metadata size needs every subdomain's slice counts first.
     int fold_cap = 0;
     if (H.box_vector && storage != 3) {
         int msl = 0, mlev = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(max : msl, mlev)
         for (int s = 0; s < H.nsd; ++s) {
             Schedule a, b;
             make_schedule(loc[s], false, 0, H.ring_width, nullptr, a);
@@ -610,11 +613,29 @@ int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], 
             mlev = std::max(mlev, std::max(loc[s].nlevL, loc[s].nlevU));
         }
         const int64_t meta = int64_t(meta_bytes_for(msl, mlev));
-        if (meta + int64_t(H.box_rows) * int64_t(sizeof(double)) > kFoldBytes && meta < kFoldBytes)
-            fold_cap = int((kFoldBytes - meta) / int64_t(sizeof(double)));
+        const int64_t budget = vec_bytes <= kBoxVectorBytes ? kFoldBytes : kLdsFoldBytes;
+        if (meta + vec_bytes > budget && meta < budget) fold_cap = int((budget - meta) / int64_t(sizeof(double)));
+        if (try_big) {  // every subdomain must fold, else the ring (storage 0) or the setup error (storage 2)
+            bool ok = fold_cap > 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(&& : ok)
+            for (int s = 0; s < H.nsd; ++s) {
+                if (!ok) continue;
+                Schedule a;
+                make_schedule(loc[s], false, 0, H.ring_width, nullptr, a);
+                int32_t f, l, u;
+                ok = ok && fold_plan(loc[s], a, fold_cap, max_late, f, l, u);
+            }
+            if (!ok) {
+                fold_cap = 0;
+                if (storage == 0) H.box_vector = false;
+            }
+        }
+    }
+    if (!H.box_vector && int64_t(H.ring_depth) * H.ring_width > 65536) {
+        set_error("ras: subdomain too large for the level ring (%d levels x %d rows)", H.ring_depth, H.ring_width);
+        return CSDYN_EINVAL;
     }
     H.folded = fold_cap > 0;
-    const int max_late = kFoldRegs * sweep_threads(H.ring_width);
     // Schedules and packs: each subdomain's in parallel into a pack of its own
     // (slice, pair, lane and level indices from 0), then appended in subdomain
     // order with its offsets added, a chunk of subdomains at a time so that the

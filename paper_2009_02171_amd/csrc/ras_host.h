@@ -74,6 +74,9 @@ constexpr int kXcds = 8;  // L2 domains of the GPU; consecutive workgroups go to
 // slots): two such workgroups fit the 160 KiB of a compute unit with room for
 // the allocation granularity.
 constexpr int64_t kFoldBytes = 80 * 1024 - 512;
+// The same for a subdomain vector above kBoxVectorBytes: one workgroup per
+// compute unit, folded into the LDS one workgroup can have.
+constexpr int64_t kLdsFoldBytes = 160 * 1024 - 512;
 // Late inputs of a folded box vector held per thread from the gather to
 // their write.
 constexpr int kFoldRegs = 3;
@@ -130,8 +133,10 @@ struct HostRas {
 
 // Build and factor.  Returns CSDYN_EZEROPIVOT / CSDYN_EINVAL on failure.
 // storage: 0 automatic (box vector when its FP64 size fits kBoxVectorBytes,
-// folded when metadata and vector exceed kFoldBytes and the fold is valid),
-// 1 ring, 2 box vector (folded as in 0), 3 as 0 but never folded.
+// folded when metadata and vector exceed kFoldBytes and the fold is valid;
+// a larger box vector folded into kLdsFoldBytes when that fold is valid for
+// every subdomain, else the ring), 1 ring, 2 box vector (folded as in 0),
+// 3 as 0 but never folded.
 int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], int overlap, int storage,
                        HostRas &out);
 

@@ -94,9 +94,9 @@ def test_ras_rejects_bad_options():
         csdyn.RAS(op, sub=(6, 6, 3), levels=2)   # odd subdomain size for two levels
     with pytest.raises(csdyn.CsdynError):
         csdyn.RAS(op, sub=(6, 6, 3), storage=4)
-    big = csdyn.Operator(16, 16)
-    with pytest.raises(csdyn.CsdynError):       # a 16^3 box's FP64 vector does not fit in LDS
-        csdyn.RAS(big, sub=(16, 16, 16), storage=2)
+    big = csdyn.Operator(16, 20)
+    with pytest.raises(csdyn.CsdynError):       # a 16^2 x 20 box's FP64 vector does not fit in LDS, even folded
+        csdyn.RAS(big, sub=(16, 16, 20), storage=2)
 
 
 @pytest.mark.parametrize("n,nr,kind,sub,storage", [(8, 4, 0, (4, 4, 2), 1), (16, 16, 1, (16, 16, 16), 1),
@@ -189,6 +189,27 @@ def test_folded_box_vector_equals_unfolded(n, kind):
     yf, yu = _apply(pf, x), _apply(pu, x)
     assert np.array_equal(yf, yu)
     if n == 24 and kind == 2:  # and the oracle, for the system with the temperature
+        pb = O.Problem(n, n, kind=kind)
+        y_ref = O.Preconditioner(pb, sub=sub, levels=1).apply(x)
+        assert np.abs(yf - y_ref).max() / np.abs(y_ref).max() <= 1e-12
+
+
+@pytest.mark.parametrize("n,sub,kind", [(16, (16, 16, 16), 0), (16, (16, 16, 16), 1), (32, (16, 16, 16), 0)])
+def test_large_box_vector_folded_into_one_workgroup(n, sub, kind):
+    """A subdomain vector above the automatic bound (the small configuration's
+    one box per panel, 20480 rows = 160 KiB in FP64) folded into one
+    workgroup's LDS: the oracle's result to 1e-12, and the ring sweep's result
+    bit for bit (the same slices in the same order, only the storage differs)."""
+    print(f"[ras fold, one workgroup] n={n} sub={sub} kind={kind}", flush=True)
+    x = inputs.random_field((6, n, n, n, 4), seed=131 + n + kind)
+    _, pf = _setup(n, n, kind, sub)
+    _, pr = _setup(n, n, kind, sub, storage=1)
+    fi, ri = pf.info(), pr.info()
+    assert fi["box_in_lds_fine"] == 3 and ri["box_in_lds_fine"] in (0, 1), (fi, ri)
+    assert 80 * 1024 < fi["lds_fine"] <= 160 * 1024 - 512 and fi["blocks_per_cu_fine"] == 1, fi
+    yf, yr = _apply(pf, x), _apply(pr, x)
+    assert np.array_equal(yf, yr)
+    if n == 16:
         pb = O.Problem(n, n, kind=kind)
         y_ref = O.Preconditioner(pb, sub=sub, levels=1).apply(x)
         assert np.abs(yf - y_ref).max() / np.abs(y_ref).max() <= 1e-12
