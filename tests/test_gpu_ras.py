@@ -171,25 +171,29 @@ def test_coarse_box_shape_full(kind, precision, tol):
     assert np.abs(y - y_ref).max() / np.abs(y_ref).max() <= tol
 
 
-@pytest.mark.parametrize("n,kind", [(24, 0), (24, 1), (24, 2), (48, 0), (48, 1)])
-def test_folded_box_vector_equals_unfolded(n, kind):
+@pytest.mark.parametrize("n,nr,sub,kind", [(24, 24, (12, 12, 12), 0), (24, 24, (12, 12, 12), 1),
+                                            (24, 24, (12, 12, 12), 2), (48, 48, (12, 12, 12), 0),
+                                            (48, 48, (12, 12, 12), 1), (24, 33, (12, 12, 11), 0),
+                                            (24, 33, (12, 12, 11), 1)])
+def test_folded_box_vector_equals_unfolded(n, nr, sub, kind):
     """The folded FP64 box vector (late rows in the slots of the early rows,
-    early L results through the U records) gives the unfolded sweep's results
-    bit for bit, on every subdomain of the 12^3-box shape; the folded sweep
-    fits two workgroups per compute unit, the unfolded one."""
-    print(f"[ras fold] n={n} kind={kind}", flush=True)
-    sub = (12, 12, 12)
-    x = inputs.random_field((6, n, n, n, 4), seed=121 + n + kind)
-    _, pf = _setup(n, n, kind, sub, storage=2)
-    _, pu = _setup(n, n, kind, sub, storage=3)
+    the early rows' L results back from a per-subdomain buffer) gives the
+    unfolded sweep's results bit for bit, on every subdomain of the 12^3-box
+    shape, and on a grid where only the boxes away from the walls are folded
+    (Nr = 33 with 12 x 12 x 11 boxes: the wall boxes fit unfolded); the folded
+    sweep fits two workgroups per compute unit, the unfolded one."""
+    print(f"[ras fold] n={n} nr={nr} sub={sub} kind={kind}", flush=True)
+    x = inputs.random_field((6, nr, n, n, 4), seed=121 + n + kind)
+    _, pf = _setup(n, nr, kind, sub, storage=2)
+    _, pu = _setup(n, nr, kind, sub, storage=3)
     fi, ui = pf.info(), pu.info()
     assert fi["box_in_lds_fine"] == 3 and ui["box_in_lds_fine"] == 2, (fi, ui)
     assert fi["lds_fine"] <= 80 * 1024 - 512 < ui["lds_fine"]
     assert fi["blocks_per_cu_fine"] == 2 and ui["blocks_per_cu_fine"] == 1, (fi, ui)
     yf, yu = _apply(pf, x), _apply(pu, x)
     assert np.array_equal(yf, yu)
-    if n == 24 and kind == 2:  # and the oracle, for the system with the temperature
-        pb = O.Problem(n, n, kind=kind)
+    if (n, nr, kind) in ((24, 24, 2), (24, 33, 0)):  # and the oracle: the temperature system, the mixed grid
+        pb = O.Problem(n, nr, kind=kind)
         y_ref = O.Preconditioner(pb, sub=sub, levels=1).apply(x)
         assert np.abs(yf - y_ref).max() / np.abs(y_ref).max() <= 1e-12
 
