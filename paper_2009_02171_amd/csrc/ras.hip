@@ -77,7 +77,7 @@ struct OneLevel {
     int depth = 0, width = 0, meta_lev = 0, meta_sl = 0, max_total_levels = 0;
     bool vec = false;  // box vector in LDS instead of the level ring
     bool folded = false;  // FP64 box vector folded into fold_rows slots
-    int box_rows = 0, fold_rows = 0, spill_stride = 0;
+    int box_rows = 0, fold_rows = 0;
     int blocks_per_cu = 0;  // workgroups of the sweep kernel that fit one compute unit
     int threads = 256;
     size_t lds_bytes = 0;
@@ -86,8 +86,8 @@ struct OneLevel {
     SdInfo *sd = nullptr;
     int32_t *Lio = nullptr, *Lnext = nullptr, *Uio = nullptr, *Unext = nullptr;
     uint16_t *Laddr = nullptr, *Uaddr = nullptr;
-    void *Lval = nullptr, *Uval = nullptr, *lin = nullptr, *lout = nullptr, *ring = nullptr, *spill = nullptr;
-    int32_t *gio = nullptr, *Lmeta = nullptr, *Umeta = nullptr, *perm = nullptr;
+    void *Lval = nullptr, *Uval = nullptr, *lin = nullptr, *lout = nullptr, *ring = nullptr;
+    int32_t *gio = nullptr, *Lmeta = nullptr, *Umeta = nullptr, *perm = nullptr, *own = nullptr;
 
     static void layout(Carver &c, const HostRas &H, int precision, OneLevel &o) {
         const size_t fs = precision ? sizeof(float) : sizeof(double);
@@ -97,7 +97,6 @@ struct OneLevel {
         o.vec = H.box_vector; o.box_rows = H.box_rows;
         o.folded = H.folded && precision == 0;
         o.fold_rows = o.folded ? H.fold_rows : 0;
-        o.spill_stride = o.folded ? (H.fold_early + 31) / 32 * 32 : 0;  // 256-byte aligned rows
         o.sd = c.take<SdInfo>(H.sd.size());
         // the box vector needs no per-lane indices of the L sweep, no U y indices
         // apart from its pairs and no input records
@@ -107,7 +106,7 @@ struct OneLevel {
         o.Laddr = c.take<uint16_t>(o.folded ? H.fold_Laddr.size() : H.L.addr.size());
         o.Lval = c.take<char>(H.L.val.size() * fs);
         o.Uio = c.take<int32_t>(ring ? H.U.lane_io.size() : 0);
-        o.Unext = c.take<int32_t>(2 * H.U.lane_next.size());
+        o.Unext = c.take<int32_t>(H.U.lane_next.size());
         o.Uaddr = c.take<uint16_t>(o.folded ? H.fold_Uaddr.size() : H.U.addr.size());
         o.Uval = c.take<char>(H.U.val.size() * fs);
         o.lin = c.take<char>(ring ? H.L.lane_io.size() * fs : 0);
@@ -117,7 +116,7 @@ struct OneLevel {
         o.Lmeta = c.take<int32_t>(H.L.meta.size());
         o.Umeta = c.take<int32_t>(H.U.meta.size());
         o.perm = c.take<int32_t>(H.perm.size());
-        o.spill = c.take<double>(size_t(H.nsd) * o.spill_stride);
+        o.own = c.take<int32_t>(H.own.size());
     }
 
     int32_t upload(const HostRas &H) const {
@@ -137,15 +136,11 @@ struct OneLevel {
         }
         const std::vector<uint16_t> &la = folded ? H.fold_Laddr : H.L.addr, &ua = folded ? H.fold_Uaddr : H.U.addr;
         CSD_HIP(up(Laddr, la.data(), la.size() * 2));
-        if (!H.U.lane_next.empty()) {  // box vector: {position (folded: slot), y index} per U lane
+        {  // box vector: the row's slot (folded or not) per U lane
             const std::vector<int32_t> &pos = folded ? H.fold_Upos : H.U.lane_next;
-            std::vector<int32_t> ri(2 * pos.size());
-            for (size_t a = 0; a < pos.size(); ++a) {
-                ri[2 * a] = pos[a];
-                ri[2 * a + 1] = H.U.lane_io[a];
-            }
-            CSD_HIP(up(Unext, ri.data(), ri.size() * 4));
+            CSD_HIP(up(Unext, pos.data(), pos.size() * 4));
         }
+        CSD_HIP(up(own, H.own.data(), H.own.size() * 4));
         CSD_HIP(up(Uaddr, ua.data(), ua.size() * 2));
         CSD_HIP(up(gio, H.gio.data(), H.gio.size() * 4));
         const std::vector<int32_t> &lm = folded ? H.fold_Lmeta : H.L.meta;
@@ -183,8 +178,7 @@ struct OneLevel {
         R.ring = (TF *)ring;
         R.gio = gio;
         R.perm = perm;
-        R.spill = (TF *)spill;
-        R.spill_stride = spill_stride;
+        R.own = reinterpret_cast<const int2 *>(own);
         R.depth = vec ? 1 : depth;
         R.width = vec ? box_rows : width;
         return R;

@@ -25,7 +25,7 @@ struct DevSweep {
     using TF2 = typename Pair<TF>::type;
     const int32_t *lane_io;    // [nslice*64] ring: L, x index; U, y index of owned rows; else -1
     const int32_t *lane_next;  // [nslice*64] ring: L, U-sweep position of the row; box vector: U,
-                               // {position, y index} pairs
+                               // the row's slot (first lane of a row, else -1)
     const TF2 *val;            // [pairs] factor entries, two per lane
     const uint4 *addr;         // [64 * nslice] addresses of the dependencies (ring slots or positions), eight per lane
     const int4 *meta;          // [nsd][meta bytes / 16] LDS metadata image of each subdomain's sweep
@@ -42,8 +42,8 @@ struct DevRas {
     TF *ring;   // [nsd][depth * width] when the ring is not in LDS
     const int32_t *gio;  // box vector: x index of each position, per subdomain from SdInfo::g0
     const int32_t *perm; // [nsd] subdomain of each workgroup
-    TF *spill;           // folded box vector: [nsd][spill_stride] L results of the early rows
-    int depth, width, spill_stride;
+    const int2 *own;     // box vector: {position, y index} of the owned rows, per subdomain from SdInfo::own0
+    int depth, width;
 };
 
 // One item of a sweep: one slice for one lane, i.e. the lane's part (at most
@@ -73,17 +73,15 @@ struct Item {
 // the cache lines of the padding are never fetched; their results are
 // discarded.
 // With the box vector in LDS (VEC) the L sweep's inputs and results live there
-// (five loads per item) and the U sweep reads 1/u_ii and its row's {position,
-// y index} instead of a record (seven loads).
+// (five loads per item) and the U sweep reads 1/u_ii and its row's slot
+// instead of a record (seven loads); y is written after the U sweep.
 template <class TF, bool UPPER, bool VEC, class Rec>
 __device__ __forceinline__ void fetch_item(const DevSweep<TF> &S, const Rec *rec, int64_t g64, int64_t a64,
                                            int64_t off, int w, int nvalid, Item<TF> &X) {
     const int lane = threadIdx.x % 64, ln = lane < nvalid ? lane : 0;
     const int64_t gpos = g64 + ln;
-    if constexpr (UPPER && VEC) {  // {row position, y index} pairs and a dense 1/u_ii array
-        const int2 ri = reinterpret_cast<const int2 *>(S.lane_next)[gpos];
-        X.row = ri.x;
-        X.io = ri.y;
+    if constexpr (UPPER && VEC) {  // the row's slot and a dense 1/u_ii array
+        X.row = S.lane_next[gpos];
         X.h.y = reinterpret_cast<const TF *>(rec)[gpos];
     } else if constexpr (UPPER) {
         X.h = rec[gpos];
@@ -154,38 +152,64 @@ struct Meta {
 // to its ring slot (box vector: its position) and, in the ring layout's L
 // sweep, to its U-sweep record; the U sweep writes the owned rows to y
 // (restricted scatter).
+// y[own[q].y] = ring[own[q].x - shift] for q0 <= q < q1: the {position, y
+// index} pairs of a round all requested before the first store.
+template <class TV, class TF, int NT, int SU>
+__device__ __forceinline__ void scatter_owned(const int2 *own, int q0, int q1, int shift, const TF *ring, TV *y) {
+    for (int a0 = q0; a0 < q1; a0 += NT * SU) {
+        int2 o[SU];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) o[u] = own[min(a0 + int(threadIdx.x) + u * NT, q1 - 1)];
+#pragma unroll
+        for (int u = 0; u < SU; ++u)
+            if (a0 + int(threadIdx.x) + u * NT < q1) y[o[u].y] = TV(ring[o[u].x - shift]);
+    }
+}
+
 // Folded box vector (HostRas::folded): values that wait in registers for
 // their slots, v[u] for slot t + u NT (t the thread, slots below n), written
 // after the barrier that ends level lev: the late rows' inputs in the L
-// sweep, the early rows' L results in the U sweep.  The L sweep also stores
-// the results of the early rows (positions below n, all at levels up to the L
-// sweep's lev) to spill, indexed by position, for the U sweep to read back.
+// sweep, which swap places with the early rows' final L results (slots below
+// n are the early rows' positions), and those in the U sweep.
 template <class TF, bool FOLD>
 struct Fold {
     TF v[kFoldRegs];
-    int lev, n;
-    TF *spill;
+    int lev, n, fold;
+    const int2 *own;  // U sweep: the owned late rows, written out before their slots are reused
+    int own_late;
 };
 template <class TF>
 struct Fold<TF, false> {};
 
 template <class TV, class TF, bool UPPER, bool LDS, bool VEC, int NT, bool FOLD, class Rec>
 __device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int sl0, int asl0, int64_t off0, int nlev,
-                                      int nsl, TF *ring, const Rec *rec, TF *lout, TV *y, const Fold<TF, FOLD> &fd) {
+                                      int nsl, TF *ring, const Rec *rec, TF *lout, TV *y, Fold<TF, FOLD> &fd) {
     constexpr int K = SweepShape<TF, NT>::K;
     const int lane = threadIdx.x % 64, nw = NT / 64;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     int passed = 0;
     // the barrier that ends level `passed`; folded, after level fd.lev the
-    // waiting values go to their slots (first read at level fd.lev + 2)
+    // slots of the early rows change hands (first read at level fd.lev + 2):
+    // in the L sweep each thread swaps the early rows' L results in its slots
+    // with the late rows' inputs in its registers; in the U sweep the owned
+    // late rows are written to y, then (after a barrier, since any thread may
+    // read any slot) the early rows' L results go back to their slots
     auto barrier = [&]() {
         level_barrier<LDS>();
         if constexpr (FOLD) {
             if (passed == fd.lev) {
+                if constexpr (UPPER) {
+                    scatter_owned<TV, TF, NT, 1>(fd.own, 0, fd.own_late, fd.fold, ring, y);  // within the sweep's registers
+                    level_barrier<LDS>();
+                }
 #pragma unroll
                 for (int u = 0; u < kFoldRegs; ++u) {
                     const int a = int(threadIdx.x) + u * NT;
-                    if (a < fd.n) ring[a] = fd.v[u];
+                    if (a < fd.n) {
+                        const TF e = ring[a];
+                        ring[a] = fd.v[u];
+                        if constexpr (!UPPER) fd.v[u] = e;
+                    }
                 }
             }
         }
@@ -234,15 +258,13 @@ __device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int 
                 acc = sum;
             }
             if constexpr (UPPER) acc *= it.h.y;
-            if (writer) {
+            if (writer) {  // box vector: y is written from LDS after the sweep (restricted scatter)
                 if constexpr (VEC && UPPER) ring[it.row] = acc;
                 else ring[it.slot + rr] = acc;
-                if constexpr (UPPER) {
+                if constexpr (UPPER && !VEC) {
                     if (it.io >= 0) y[it.io] = TV(acc);
                 } else if constexpr (!VEC) {
                     if (it.io >= 0) lout[2 * int64_t(it.io)] = acc;
-                } else if constexpr (FOLD) {  // an early row: its slot is its position
-                    if ((it.wl >> 17) <= fd.lev && it.slot + rr < fd.n) fd.spill[it.slot + rr] = acc;
                 }
             }
             pass_to(k + 1 < K ? grp[k + 1] : next);
@@ -318,7 +340,9 @@ __device__ __forceinline__ void ras_block(const DevRas<TF> &R, int meta_lev, int
         if constexpr (FOLD) {
             fd.lev = I.fold_lev;
             fd.n = nrows - I.fold;
-            fd.spill = R.spill + int64_t(sdi) * R.spill_stride;
+            fd.fold = I.fold;
+            fd.own = R.own + I.own0;
+            fd.own_late = I.own_late;
             int32_t io[kFoldRegs];
 #pragma unroll
             for (int u = 0; u < kFoldRegs; ++u) io[u] = gi[I.fold + min(int(threadIdx.x) + u * NT, fd.n - 1)];
@@ -360,17 +384,18 @@ __device__ __forceinline__ void ras_block(const DevRas<TF> &R, int meta_lev, int
     sweep<TV, TF, false, LDS, VEC, NT, FOLD>(R.L, M, I.slL0, I.aslL0, I.offL0, I.levL1 - I.levL0, I.nslL, ring, R.lin,
                                              reinterpret_cast<TF *>(R.lout), y, fd);
     __syncthreads();  // L results visible; the U metadata replaces the L metadata
-    if constexpr (FOLD) {  // the early rows' L results, back from spill (written after the U sweep's level fold_levU)
-#pragma unroll
-        for (int u = 0; u < kFoldRegs; ++u) fd.v[u] = fd.spill[min(int(threadIdx.x) + u * NT, max(fd.n - 1, 0))];
-        fd.lev = I.fold_levU;
-    }
+    if constexpr (FOLD) fd.lev = I.fold_levU;  // the early rows' L results (in fd.v) go back after this U level
     if (int(threadIdx.x) < n16) md[threadIdx.x] = up0;
     if (int(threadIdx.x) + NT < n16) md[threadIdx.x + NT] = up1;
     for (int a = threadIdx.x + MU * NT; a < n16; a += NT) md[a] = uimg[a];
     __syncthreads();
     sweep<TV, TF, true, LDS, VEC, NT, FOLD>(R.U, M, I.slU0, I.aslU0, I.offU0, I.levU1 - I.levU0, I.nslU, ring, R.lout,
                                             nullptr, y, fd);
+    if constexpr (VEC) {  // restricted scatter of the owned rows from LDS (folded: all but the late ones, which
+                          // were written before their slots were reused, have slot = position)
+        const int2 *own = R.own + I.own0;
+        scatter_owned<TV, TF, NT, 16>(own, FOLD ? I.own_late : 0, 4 * I.nown, 0, ring, y);
+    }
 }
 
 // Device view of the fine one-level RAS of a preconditioner with FP32 factors

@@ -642,7 +642,7 @@ int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], 
     // local packs never hold more than a chunk's data.
     struct Packed {
         SweepPack L, U;
-        std::vector<int32_t> gio, fold_Upos;
+        std::vector<int32_t> gio, fold_Upos, own;
         std::vector<uint16_t> fold_Laddr, fold_Uaddr;
         int32_t levL0 = 0, levL1 = 0, levU0 = 0, levU1 = 0;
         int32_t status = CSDYN_OK;
@@ -686,6 +686,19 @@ int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], 
                 }
             }
             if (want_fold) Q.fold_ok = fold_plan(L, SL, fold_cap, max_late, I.fold, I.fold_lev, I.fold_levU);
+            if (H.box_vector) {  // owned rows {slot, y index}: the late ones (slots reused by the fold) first
+                const int32_t f = want_fold && Q.fold_ok ? I.fold : int32_t(nrow);
+                I.own_late = 0;
+                for (int pass = 0; pass < 2; ++pass)
+                    for (int64_t r = 0; r < nrow; ++r) {
+                        if (!L.owned_row[size_t(r / 4)]) continue;
+                        const int32_t p = SL.slot[size_t(r)];
+                        if ((p >= f) != (pass == 0)) continue;
+                        Q.own.push_back(p);
+                        Q.own.push_back(int32_t(4 * int64_t(L.gcell[size_t(r / 4)]) + r % 4));
+                        I.own_late += pass == 0;
+                    }
+            }
             int32_t e = Q.status;
             if (e == CSDYN_OK) e = pack_sweep(L, true, SU, nullptr, 0, H.box_vector, Q.U, Q.levU0, Q.levU1);
             if (e == CSDYN_OK) e = pack_sweep(L, false, SL, &SU, 0, H.box_vector, Q.L, Q.levL0, Q.levL1);
@@ -719,7 +732,7 @@ int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], 
         if (H.folded)
             for (int q = 0; q < nc; ++q) H.folded = H.folded && pk[size_t(q)].fold_ok;
         struct Off {
-            size_t lev[2], sl[2], pair[2], lane[2], addr[2], gio, fpos;
+            size_t lev[2], sl[2], pair[2], lane[2], addr[2], gio, fpos, own;
         };
         std::vector<Off> off(size_t(nc) + 1);
         SweepPack *HP[2] = {&H.L, &H.U};
@@ -732,6 +745,7 @@ int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], 
         }
         off[0].gio = H.gio.size();
         off[0].fpos = H.fold_Upos.size();
+        off[0].own = H.own.size();
         for (int q = 0; q < nc; ++q) {
             const Packed &Q = pk[size_t(q)];
             for (int w = 0; w < 2; ++w) {
@@ -743,6 +757,7 @@ int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], 
                 off[size_t(q) + 1].addr[w] = off[size_t(q)].addr[w] + P.addr.size();
             }
             off[size_t(q) + 1].gio = off[size_t(q)].gio + Q.gio.size();
+            off[size_t(q) + 1].own = off[size_t(q)].own + Q.own.size();
             off[size_t(q) + 1].fpos = off[size_t(q)].fpos + (H.folded ? Q.fold_Upos.size() : 0);
         }
         // the first chunk sets the capacity of the whole build (no reallocation
@@ -764,6 +779,7 @@ int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], 
             grow(P.addr, off[size_t(nc)].addr[w]);
         }
         grow(H.gio, off[size_t(nc)].gio);
+        grow(H.own, off[size_t(nc)].own);
         if (H.folded) {
             grow(H.fold_Laddr, off[size_t(nc)].addr[0]);
             grow(H.fold_Uaddr, off[size_t(nc)].addr[1]);
@@ -796,6 +812,8 @@ int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], 
             I.levU1 = Q.levU1 + int32_t(o.lev[1]);
             I.g0 = int64_t(o.gio);
             std::copy(Q.gio.begin(), Q.gio.end(), H.gio.begin() + ptrdiff_t(o.gio));
+            I.own0 = int64_t(o.own / 2);
+            std::copy(Q.own.begin(), Q.own.end(), H.own.begin() + ptrdiff_t(o.own));
             if (H.folded) {
                 std::copy(Q.fold_Laddr.begin(), Q.fold_Laddr.end(), H.fold_Laddr.begin() + ptrdiff_t(o.addr[0]));
                 std::copy(Q.fold_Uaddr.begin(), Q.fold_Uaddr.end(), H.fold_Uaddr.begin() + ptrdiff_t(o.addr[1]));

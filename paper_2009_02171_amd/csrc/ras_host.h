@@ -57,6 +57,12 @@ struct SdInfo {
     // positions' L results after the U sweep's level fold_levU (fold = nrows,
     // fold_lev = fold_levU = -1: nothing folded)
     int32_t fold, fold_lev, fold_levU;
+    // box vector: the owned rows' {position, y index} pairs from own0 (4 nown
+    // of them), the own_late ones first: rows whose slot is reused by the
+    // fold (written out before that, at the U sweep's level fold_levU), then
+    // the rest (written after the U sweep)
+    int64_t own0;
+    int32_t own_late;
 };
 
 // Bytes of one sweep's slice metadata as the sweep kernel keeps it in LDS
@@ -100,6 +106,9 @@ struct HostRas {
     // box vector: for each subdomain (from SdInfo::g0, SdInfo::nrows entries)
     // the x index of the row at each position, so the gather is one pass
     std::vector<int32_t> gio;
+    // box vector: per subdomain (from SdInfo::own0) the owned rows' {position,
+    // y index} pairs, the sweep's restricted scatter from LDS
+    std::vector<int32_t> own;
     int max_slices = 0, max_levels = 0;  // per sweep of one subdomain (LDS metadata sizing)
     int64_t nnz = 0;                     // factor entries (L and U, diagonal included)
     int64_t box_cells = 0, owned_cells = 0;
@@ -118,11 +127,11 @@ struct HostRas {
     // rows reuse the slots of the first e = nrows - f rows ("early").  Valid
     // when every L-sweep access of an early row precedes the late rows' first
     // level by two levels (the late inputs, held in registers since the
-    // gather, are written in between, after the level SdInfo::fold_lev), and
-    // every U-sweep access of a late row precedes the early rows' first U
-    // level by two levels (the early rows' L results, stored to device memory
-    // by the L sweep and read back into registers when the U sweep starts, are
-    // written in between, after the level SdInfo::fold_levU).  The arrays
+    // gather, swap places with the early rows' L results in between, after
+    // the level SdInfo::fold_lev), and every U-sweep access of a late row
+    // precedes the early rows' first U level by two levels (the owned late
+    // rows are written to y and the early rows' L results go back to their
+    // slots in between, after the level SdInfo::fold_levU).  The arrays
     // below replace, for the FP64 sweep, L.addr, U.addr, L.meta and U's
     // positions (same layouts); fold_early is the largest e.
     bool folded = false;
