@@ -97,6 +97,17 @@ __device__ __forceinline__ void fetch_item(const DevSweep<TF> &S, const Rec *rec
     X.addr[0] = a.x; X.addr[1] = a.y; X.addr[2] = a.z; X.addr[3] = a.w;
 }
 
+// The value of the next lane (lane l gets lane l + 1's; the last lane 0): a
+// DPP move across the whole wavefront, no trip through the LDS crossbar.
+__device__ __forceinline__ float wave_next(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double wave_next(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
 template <class TF>
 __device__ __forceinline__ TF consume(const Item<TF> &X, int w, const TF *ring, TF acc) {
     TF tv[8];
@@ -252,9 +263,12 @@ __device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int 
             else if constexpr (UPPER) v0 = it.row >= 0 ? ring[it.row] : TF(0);
             else v0 = writer ? ring[it.slot + rr] : TF(0);
             TF acc = consume(it, w, ring, v0);
-            if (sp > 1) {  // the row's first lane adds its other parts in order
-                TF sum = acc;
-                for (int d = 1; d < sp; ++d) sum += __shfl(acc, min(first + d, 63));
+            if (sp > 1) {  // the row's first lane adds its other parts in order (part d arrives after d shifts)
+                TF sum = acc, part = acc;
+                for (int d = 1; d < sp; ++d) {
+                    part = wave_next(part);
+                    sum += part;
+                }
                 acc = sum;
             }
             if constexpr (UPPER) acc *= it.h.y;
