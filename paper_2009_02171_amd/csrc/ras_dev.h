@@ -73,16 +73,18 @@ struct Item {
 // the cache lines of the padding are never fetched; their results are
 // discarded.
 // With the box vector in LDS (VEC) the L sweep's inputs and results live there
-// (five loads per item) and the U sweep reads 1/u_ii and its row's slot
-// instead of a record (seven loads); y is written after the U sweep.
+// (five loads per item) and the U sweep reads 1/u_ii and its row's slot, per
+// row of the slice, instead of a record (seven loads); y is written after the
+// U sweep.
 template <class TF, bool UPPER, bool VEC, class Rec>
 __device__ __forceinline__ void fetch_item(const DevSweep<TF> &S, const Rec *rec, int64_t g64, int64_t a64,
-                                           int64_t off, int w, int nvalid, Item<TF> &X) {
+                                           int64_t off, int w, int sp, int nvalid, Item<TF> &X) {
     const int lane = threadIdx.x % 64, ln = lane < nvalid ? lane : 0;
     const int64_t gpos = g64 + ln;
-    if constexpr (UPPER && VEC) {  // the row's slot and a dense 1/u_ii array
-        X.row = S.lane_next[gpos];
-        X.h.y = reinterpret_cast<const TF *>(rec)[gpos];
+    if constexpr (UPPER && VEC) {  // the row's slot and 1/u_ii, stored per row of the slice
+        const int64_t rpos = g64 + ((ln * ((65536 + sp - 1) / sp)) >> 16);
+        X.row = S.lane_next[rpos];
+        X.h.y = reinterpret_cast<const TF *>(rec)[rpos];
     } else if constexpr (UPPER) {
         X.h = rec[gpos];
         X.io = S.lane_io[gpos];
@@ -244,7 +246,7 @@ __device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int 
             grp[k].wl = g < nsl ? wl : -1;
             grp[k].slot = __builtin_amdgcn_readfirstlane(M.slot[gg]);
             fetch_item<TF, UPPER, VEC>(S, rec, int64_t(sl0 + gg) * 64, int64_t(asl0 + gg) * 64, off0 + offr, wl & 15,
-                                       ((wl >> 10) & 127) * (((wl >> 4) & 63) + 1), grp[k]);
+                                       ((wl >> 4) & 63) + 1, ((wl >> 10) & 127) * (((wl >> 4) & 63) + 1), grp[k]);
         }
         fg += K * nw;
         __builtin_amdgcn_sched_barrier(0);
@@ -260,7 +262,7 @@ __device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int 
             const bool writer = lane == first && rr < nrow;
             TF v0;
             if constexpr (!VEC) v0 = it.h.x;
-            else if constexpr (UPPER) v0 = it.row >= 0 ? ring[it.row] : TF(0);
+            else if constexpr (UPPER) v0 = writer ? ring[it.row] : TF(0);
             else v0 = writer ? ring[it.slot + rr] : TF(0);
             TF acc = consume(it, w, ring, v0);
             if (sp > 1) {  // the row's first lane adds its other parts in order (part d arrives after d shifts)

@@ -460,6 +460,14 @@ int32_t pack_sweep(const LocalSd &L, bool upper, const Schedule &S, const Schedu
             if (!upper || box_vector) P.lane_next.push_back(nxt);
             if (upper) P.lane_diag.push_back(dg);
         }
+        if (upper && box_vector) {  // the U sweep's box-vector slots and u_ii per row of the slice, not per lane
+            const size_t b = P.lane_diag.size() - 64;
+            for (int rr = 0; rr < 64; ++rr) {
+                const int32_t r = rr < S.slice_nrow[sl] ? S.slice_rows[sl * 64 + rr * sp] : -1;
+                P.lane_next[b + size_t(rr)] = r >= 0 ? S.slot[r] : -1;
+                P.lane_diag[b + size_t(rr)] = r >= 0 ? L.v[L.diag[r]] : 0.0;
+            }
+        }
     }
     if (int64_t(P.val.size()) / 2 - pair0 > INT32_MAX) {  // the sweep kernel keeps 32-bit offsets per subdomain
         set_error("ras: subdomain too large (more than 2^31 value pairs in one sweep)");

@@ -35,8 +35,10 @@ struct SweepPack {
     std::vector<int32_t> sl_slot;    // [nslice] ring slot of the first row
     std::vector<int32_t> lane_io;    // [nslice*64] L: x index; U: y index of an owned row (first lane of a row); else -1
     std::vector<int32_t> lane_next;  // [nslice*64] ring: L only, U-sweep position (slice*64 + first lane) of the
-                                     // row; box vector: both sweeps, the row's position in the box vector
-    std::vector<double> lane_diag;   // [nslice*64] U only: u_ii (0 on padding lanes)
+                                     // row; box vector: the row's position in the box vector, L: at the row's
+                                     // first lane, U: at slice*64 + the row's index in the slice
+    std::vector<double> lane_diag;   // [nslice*64] U only: u_ii (0 on padding lanes); box vector: per row as
+                                     // lane_next
     std::vector<double> val;         // [2 * pairs]
     std::vector<uint16_t> addr;      // ring slot of the dependency: per subdomain a block of
                                      // [8 * 64 * nsl] from slice SdInfo::asl*0; identical blocks stored once
