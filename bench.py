@@ -535,7 +535,7 @@ def learned_leg(args):
         sysd[name] = {v: {"iters": round(r[v]["iters_mean"], 2), "inner": round(r[v]["inner_mean"], 1),
                           "solves_per_s": round(r[v]["solves_per_s"], 3),
                           "res0_rel_median": r[v]["res0_rel_median"]}
-                      for v in ("plain_a", "mixed_a", "mixed_b", "mixed_c", "mixed_d")}
+                      for v in ("plain_a", "mixed_a", "mixed_b", "mixed_c", "mixed_d", "mixed_e")}
         sysd[name]["net_chosen"] = f"{r['net_chosen']}/{r['mixed_c']['solves']}"
         sysd[name]["guess_quality_median"] = r["guess_quality_median"]
     return {
@@ -546,10 +546,12 @@ def learned_leg(args):
                   "mixed_a (FP32 PC, previous solution)": round(sp["mixed_a"], 3),
                   "mixed_b (FP32 PC, extrapolation)": round(sp["mixed_b"], 3),
                   "mixed_c (FP32 PC, network with residual fallback)": round(sp["mixed_c"], 3),
-                  "mixed_d (FP32 PC, minimal-residual step along the network's correction)": round(sp["mixed_d"], 3)},
+                  "mixed_d (FP32 PC, minimal-residual step along the network's correction)": round(sp["mixed_d"], 3),
+                  "mixed_e (FP32 PC, the network's guess as it is)": round(sp["mixed_e"], 3)},
         "speedup_mixed_c_vs_plain_a": round(res["speedup_mixed_c_vs_plain_a"], 3),
         "speedup_mixed_d_vs_plain_a": round(res["speedup_mixed_d_vs_plain_a"], 3),
         "speedup_mixed_b_vs_plain_a": round(sp["mixed_b"] / sp["plain_a"], 3),
+        "speedup_mixed_e_vs_plain_a": round(sp["mixed_e"] / sp["plain_a"], 3),
         "systems": sysd, "train_s": round(res["train_s"], 2), "wall_s": round(time.perf_counter() - t0, 1),
     }
 

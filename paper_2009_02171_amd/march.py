@@ -18,11 +18,13 @@ The solve's initial guess is one of
     (b) 2 x^{n-1} - x^{n-2}              (linear extrapolation)
     (c) the network's guess, or (b) when (b) has the smaller ||b - A x0||
     (d) (b) + alpha (network's guess - (b)), alpha minimising ||b - A x0||
+    (e) the network's guess as it is (its error, not its residual, decides
+        what the solve has left to do)
 Steps 1..train_steps advance with guess (b) and train one network per
 system online (Adam on a replay buffer of the latest samples); the network
 is then frozen and steps train_steps+1.. are solved from the same state with
 every guess, the FP64 preconditioner for (a) ("plain") and the FP32 one for
-(a) .. (d); the plain solution advances the state.  Every solve must reach
+(a) .. (e); the plain solution advances the state.  Every solve must reach
 the tolerance whatever its guess.  Right-hand sides, guesses and the Step-3
 state come from the library (csdyn_march_rhs, csdyn_guess, csdyn_project);
 the forcing is generated on the host with the other synthetic inputs.
@@ -97,7 +99,7 @@ def run(n=64, nr=64, sub=(16, 16, 16), levels=2, train_steps=100, eval_steps=100
     def force(step):  # synthetic input, generated on the host
         return torch.from_numpy(forcing.field(DRIFT * step)).to(dev)
 
-    variants = ("plain_a", "mixed_a", "mixed_b", "mixed_c", "mixed_d")
+    variants = ("plain_a", "mixed_a", "mixed_b", "mixed_c", "mixed_d", "mixed_e")
     acc = {name: {v: dict(iters=0, inner=0, solve_s=0.0, guess_s=0.0, res0_rel=[], solves=0, relres=[])
                   for v in variants} for name in systems}
     chosen_net = {name: 0 for name in systems}
@@ -177,10 +179,12 @@ def run(n=64, nr=64, sub=(16, 16, 16), levels=2, train_steps=100, eval_steps=100
                     chosen_net[name] += int(gi["alpha"] == 1.0)
                     netd[name]["res_net"].append(gi["res_net"])
                     netd[name]["res_extrap"].append(gi["res_extrap"])
-                else:
+                elif v == "mixed_d":
                     x0, gi = s.guess(h[-1], h[-2], csdyn.GUESS_MINRES, net=s.net, b=b)
                     netd[name]["res_minres"].append(gi["res_guess"])
                     netd[name]["alpha"].append(gi["alpha"])
+                else:  # the network's guess as it is, whatever its residual
+                    x0 = s.net.predict(h[-1], h[-2])
                 _sync()
                 tg = time.perf_counter() - t0
                 x, st, el = solve(s, b, x0, 0 if v == "plain_a" else 1)

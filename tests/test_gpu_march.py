@@ -14,7 +14,7 @@ def test_march_small():
                   log=lambda m: print(m, flush=True))
     print(r)
     for name, s in r["systems"].items():
-        for v in ("plain_a", "mixed_a", "mixed_b", "mixed_c", "mixed_d"):
+        for v in ("plain_a", "mixed_a", "mixed_b", "mixed_c", "mixed_d", "mixed_e"):
             assert s[v]["solves"] == 4
             assert s[v]["relres_max"] <= 1.0001e-8
         assert s["face_div_rel_max"] <= 1.0001e-8
@@ -99,7 +99,7 @@ def test_march_full_dynamics_small():
     print(r)
     assert r["dynamics"] == "full"
     for name, s in r["systems"].items():
-        for v in ("plain_a", "mixed_a", "mixed_b", "mixed_c", "mixed_d"):
+        for v in ("plain_a", "mixed_a", "mixed_b", "mixed_c", "mixed_d", "mixed_e"):
             assert s[v]["solves"] == 3
             assert s[v]["relres_max"] <= 1.0001e-8
         assert s["face_div_rel_max"] <= 1.0001e-8
@@ -117,7 +117,7 @@ def test_march_thermal_dynamics_small():
     print(r)
     assert r["dynamics"] == "thermal" and 0 < r["vt_iters_mean"] < 30
     for name, s in r["systems"].items():
-        for v in ("plain_a", "mixed_a", "mixed_b", "mixed_c", "mixed_d"):
+        for v in ("plain_a", "mixed_a", "mixed_b", "mixed_c", "mixed_d", "mixed_e"):
             assert s[v]["solves"] == 2
             assert s[v]["relres_max"] <= 1.0001e-8
         assert s["face_div_rel_max"] <= 1.0001e-8
