@@ -23,9 +23,10 @@ struct Pair<float> {
 template <class TF>
 struct DevSweep {
     using TF2 = typename Pair<TF>::type;
-    const int32_t *lane_io;    // [nslice*64] ring: L, x index; U, y index of owned rows; else -1
-    const int32_t *lane_next;  // [nslice*64] ring: L, U-sweep position of the row; box vector: U,
-                               // the row's slot (first lane of a row, else -1)
+    const int32_t *lane_io;    // [nslice*64] ring, per row of a slice (slice*64 + row): L, x index; U, y index
+                               // of an owned row; else -1
+    const int32_t *lane_next;  // [nslice*64] per row of a slice: ring, L, the row's U-sweep record; box vector,
+                               // U, the row's slot
     const TF2 *val;            // [pairs] factor entries, two per lane
     const uint4 *addr;         // [64 * nslice] addresses of the dependencies (ring slots or positions), eight per lane
     const int4 *meta;          // [nsd][meta bytes / 16] LDS metadata image of each subdomain's sweep
@@ -36,9 +37,9 @@ struct DevRas {
     using TF2 = typename Pair<TF>::type;
     const SdInfo *sd;
     DevSweep<TF> L, U;
-    TF *lin;    // [L slices * 64] gathered inputs of the L sweep (ring only)
-    TF2 *lout;  // [U slices * 64] ring: {L-sweep result, 1/u_ii} in U-sweep order (0 where never written);
-                // box vector: 1/u_ii per lane (dense, first half)
+    TF *lin;    // [L slices * 64] ring: gathered inputs of the L sweep, per row of a slice
+    TF2 *lout;  // [U slices * 64] ring: {L-sweep result, 1/u_ii} per row of a U slice;
+                // box vector: 1/u_ii per row (dense, first half)
     TF *ring;   // [nsd][depth * width] when the ring is not in LDS
     const int32_t *gio;  // box vector: x index of each position, per subdomain from SdInfo::g0
     const int32_t *perm; // [nsd] subdomain of each workgroup
@@ -81,16 +82,17 @@ __device__ __forceinline__ void fetch_item(const DevSweep<TF> &S, const Rec *rec
                                            int64_t off, int w, int sp, int nvalid, Item<TF> &X) {
     const int lane = threadIdx.x % 64, ln = lane < nvalid ? lane : 0;
     const int64_t gpos = g64 + ln;
-    if constexpr (UPPER && VEC) {  // the row's slot and 1/u_ii, stored per row of the slice
-        const int64_t rpos = g64 + ((ln * ((65536 + sp - 1) / sp)) >> 16);
+    // the row's record, stored per row of the slice (every lane of a split row reads it)
+    const int64_t rpos = g64 + ((ln * ((65536 + sp - 1) / sp)) >> 16);
+    if constexpr (UPPER && VEC) {  // the row's slot and 1/u_ii
         X.row = S.lane_next[rpos];
         X.h.y = reinterpret_cast<const TF *>(rec)[rpos];
-    } else if constexpr (UPPER) {
-        X.h = rec[gpos];
-        X.io = S.lane_io[gpos];
-    } else if constexpr (!VEC) {
-        X.h.x = rec[gpos];
-        X.io = S.lane_next[gpos];
+    } else if constexpr (UPPER) {  // {L result, 1/u_ii} and the y index of an owned row
+        X.h = rec[rpos];
+        X.io = S.lane_io[rpos];
+    } else if constexpr (!VEC) {  // the gathered input and the row's U-sweep record
+        X.h.x = rec[rpos];
+        X.io = S.lane_next[rpos];
     }
     const int lastp = w > 0 ? (w - 1) / 2 : 0;
 #pragma unroll
@@ -260,8 +262,8 @@ __device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int 
             const int w = it.wl & 15, sp = ((it.wl >> 4) & 63) + 1, nrow = (it.wl >> 10) & 127;
             const int rr = (lane * ((65536 + sp - 1) / sp)) >> 16, first = rr * sp;  // row in the slice
             const bool writer = lane == first && rr < nrow;
-            TF v0;
-            if constexpr (!VEC) v0 = it.h.x;
+            TF v0;  // the row's input, added once (by its first lane)
+            if constexpr (!VEC) v0 = writer ? it.h.x : TF(0);
             else if constexpr (UPPER) v0 = writer ? ring[it.row] : TF(0);
             else v0 = writer ? ring[it.slot + rr] : TF(0);
             TF acc = consume(it, w, ring, v0);
@@ -380,8 +382,9 @@ __device__ __forceinline__ void ras_block(const DevRas<TF> &R, int meta_lev, int
             }
         }
     } else {
-        // eight lanes per thread per round: the index loads, then the value
-        // loads, are in flight together
+        // the L sweep's inputs, one per row of a slice (slice*64 + row): eight
+        // entries per thread per round, the index loads, then the value
+        // loads, in flight together; entries past a slice's rows are never read
         constexpr int U = 8;
         const int64_t p0 = int64_t(I.slL0) * 64, p1 = int64_t(I.slL0 + I.nslL) * 64;
         for (int64_t p = p0 + threadIdx.x; p < p1; p += int64_t(NT) * U) {
@@ -393,7 +396,7 @@ __device__ __forceinline__ void ras_block(const DevRas<TF> &R, int meta_lev, int
             for (int u = 0; u < U; ++u) v[u] = io[u] >= 0 ? x[io[u]] : TV(0);
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (p + u * NT < p1) R.lin[p + u * NT] = TF(v[u]);
+                if (io[u] >= 0) R.lin[p + u * NT] = TF(v[u]);
         }
     }
     __syncthreads();

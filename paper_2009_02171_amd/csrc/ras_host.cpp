@@ -346,7 +346,7 @@ struct Schedule {
     std::vector<int32_t> slice_s;     // [nslice] lanes per row
     std::vector<int32_t> slice_nrow;  // [nslice] rows in the slice
     std::vector<int32_t> slice_slot;  // [nslice] ring slot of the slice's first row
-    std::vector<int32_t> pos;         // [nrow] slice*64 + first lane of the row (relative)
+    std::vector<int32_t> pos;         // [nrow] slice*64 + the row's index in its slice (relative)
     std::vector<int32_t> slot;        // [nrow] ring slot
 };
 
@@ -390,7 +390,7 @@ void make_schedule(const LocalSd &L, bool upper, int depth, int width, const std
                 S.slice_rows.push_back(rr < nr ? R[a + rr] : -1);
             }
             for (int rr = 0; rr < nr; ++rr) {
-                S.pos[R[a + rr]] = sl * 64 + rr * sp;
+                S.pos[R[a + rr]] = sl * 64 + rr;
                 S.slot[R[a + rr]] = slot_of(lv, int64_t(a) + rr, R[a + rr]);
             }
             a += nr;
@@ -460,12 +460,20 @@ int32_t pack_sweep(const LocalSd &L, bool upper, const Schedule &S, const Schedu
             if (!upper || box_vector) P.lane_next.push_back(nxt);
             if (upper) P.lane_diag.push_back(dg);
         }
-        if (upper && box_vector) {  // the U sweep's box-vector slots and u_ii per row of the slice, not per lane
-            const size_t b = P.lane_diag.size() - 64;
+        if (upper || !box_vector) {  // per row of the slice (slice*64 + row), not per lane: the U sweep's u_ii
+                                     // and slot (box vector) or y index (ring), the ring L sweep's x index and U row
+            const size_t b = P.lane_io.size() - 64;
             for (int rr = 0; rr < 64; ++rr) {
                 const int32_t r = rr < S.slice_nrow[sl] ? S.slice_rows[sl * 64 + rr * sp] : -1;
-                P.lane_next[b + size_t(rr)] = r >= 0 ? S.slot[r] : -1;
-                P.lane_diag[b + size_t(rr)] = r >= 0 ? L.v[L.diag[r]] : 0.0;
+                const int32_t xi = r >= 0 ? int32_t(4 * int64_t(L.gcell[r / 4]) + r % 4) : -1;
+                if (upper) {
+                    P.lane_diag[b + size_t(rr)] = r >= 0 ? L.v[L.diag[r]] : 0.0;
+                    if (box_vector) P.lane_next[b + size_t(rr)] = r >= 0 ? S.slot[r] : -1;
+                    else P.lane_io[b + size_t(rr)] = r >= 0 && L.owned_row[r / 4] ? xi : -1;
+                } else {
+                    P.lane_io[b + size_t(rr)] = xi;
+                    P.lane_next[b + size_t(rr)] = r >= 0 ? int32_t(base_u * 64 + U_sched->pos[r]) : -1;
+                }
             }
         }
     }

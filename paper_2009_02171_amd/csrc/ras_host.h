@@ -33,12 +33,14 @@ struct SweepPack {
     std::vector<int32_t> sl_info;    // [nslice] rows << 10 | (s - 1) << 4 | entries per lane
     std::vector<int64_t> sl_off;     // [nslice] first value pair
     std::vector<int32_t> sl_slot;    // [nslice] ring slot of the first row
-    std::vector<int32_t> lane_io;    // [nslice*64] L: x index; U: y index of an owned row (first lane of a row); else -1
-    std::vector<int32_t> lane_next;  // [nslice*64] ring: L only, U-sweep position (slice*64 + first lane) of the
-                                     // row; box vector: the row's position in the box vector, L: at the row's
-                                     // first lane, U: at slice*64 + the row's index in the slice
-    std::vector<double> lane_diag;   // [nslice*64] U only: u_ii (0 on padding lanes); box vector: per row as
-                                     // lane_next
+    // Per lane (at the row's first lane) or per row (at slice*64 + the row's
+    // index in the slice, entries past the slice's rows -1 or 0):
+    std::vector<int32_t> lane_io;    // [nslice*64] L: x index; U: y index of an owned row, else -1; per row in the
+                                     // ring, per lane in the box vector (not used by its sweep)
+    std::vector<int32_t> lane_next;  // [nslice*64] ring: L only, per row, the row's U-sweep record (U slice*64 +
+                                     // the row's index in it); box vector: the row's position in the box vector,
+                                     // L per lane, U per row
+    std::vector<double> lane_diag;   // [nslice*64] U only: u_ii per row
     std::vector<double> val;         // [2 * pairs]
     std::vector<uint16_t> addr;      // ring slot of the dependency: per subdomain a block of
                                      // [8 * 64 * nsl] from slice SdInfo::asl*0; identical blocks stored once
