@@ -86,7 +86,7 @@ struct OneLevel {
     SdInfo *sd = nullptr;
     int32_t *Lio = nullptr, *Lnext = nullptr, *Uio = nullptr, *Unext = nullptr;
     uint16_t *Laddr = nullptr, *Uaddr = nullptr;
-    void *Lval = nullptr, *Uval = nullptr, *lin = nullptr, *lout = nullptr, *ring = nullptr;
+    void *Lval = nullptr, *Uval = nullptr, *lout = nullptr, *ring = nullptr;
     int32_t *gio = nullptr, *Lmeta = nullptr, *Umeta = nullptr, *perm = nullptr, *own = nullptr;
 
     static void layout(Carver &c, const HostRas &H, int precision, OneLevel &o) {
@@ -109,7 +109,6 @@ struct OneLevel {
         o.Unext = c.take<int32_t>(H.U.lane_next.size());
         o.Uaddr = c.take<uint16_t>(o.folded ? H.fold_Uaddr.size() : H.U.addr.size());
         o.Uval = c.take<char>(H.U.val.size() * fs);
-        o.lin = c.take<char>(ring ? H.L.lane_io.size() * fs : 0);
         o.lout = c.take<char>(2 * H.U.lane_io.size() * fs);
         o.ring = c.take<char>(size_t(H.nsd) * H.ring_depth * H.ring_width * fs);
         o.gio = c.take<int32_t>(H.gio.size());
@@ -173,7 +172,6 @@ struct OneLevel {
         using TF2 = typename Pair<TF>::type;
         R.L = DevSweep<TF>{Lio, Lnext, (const TF2 *)Lval, (const uint4 *)Laddr, (const int4 *)Lmeta};
         R.U = DevSweep<TF>{Uio, Unext, (const TF2 *)Uval, (const uint4 *)Uaddr, (const int4 *)Umeta};
-        R.lin = (TF *)lin;
         R.lout = (TF2 *)lout;
         R.ring = (TF *)ring;
         R.gio = gio;

@@ -1,7 +1,7 @@
 // Device code of the RAS subdomain solves (Sec. 3.3, eq. onelevel), shared by
 // the preconditioner's kernel (ras.hip) and the persistent batched Arnoldi
-// step (batched.hip): the packed sweep layouts and the gather / L sweep /
-// U sweep / restricted scatter of one subdomain by one workgroup.
+// step (batched.hip): the packed sweep layouts and the L sweep / U sweep /
+// restricted scatter of one subdomain by one workgroup.
 #pragma once
 
 #include "ras_host.h"
@@ -37,7 +37,6 @@ struct DevRas {
     using TF2 = typename Pair<TF>::type;
     const SdInfo *sd;
     DevSweep<TF> L, U;
-    TF *lin;    // [L slices * 64] ring: gathered inputs of the L sweep, per row of a slice
     TF2 *lout;  // [U slices * 64] ring: {L-sweep result, 1/u_ii} per row of a U slice;
                 // box vector: 1/u_ii per row (dense, first half)
     TF *ring;   // [nsd][depth * width] when the ring is not in LDS
@@ -49,37 +48,45 @@ struct DevRas {
 
 // One item of a sweep: one slice for one lane, i.e. the lane's part (at most
 // eight entries) of its row: values in pairs, 16-bit dependency addresses two
-// to a register, the row's {input value, 1/u_ii} and output index, and the
-// slice's wave-uniform description.  Nothing in it depends on values computed
-// in the sweep (inputs were gathered before, addresses and factors are
-// constant), so each wavefront requests its items well ahead of use; the
-// loads stay in flight across the LDS-scoped barriers between levels.
-template <class TF>
+// to a register, the row's input value (or {L result, 1/u_ii}) and output
+// index, and the slice's wave-uniform description.  Nothing in it depends on
+// values computed in the sweep (inputs come from x or the box vector,
+// addresses and factors are constant), so each wavefront requests its items
+// well ahead of use; the loads stay in flight across the LDS-scoped barriers
+// between levels.
+template <class TF, class TV = TF>
 struct Item {
     using TF2 = typename Pair<TF>::type;
     uint32_t addr[4];
     TF2 val[4];
     TF2 h;
-    int32_t io;    // ring, L: U position of the row; U: y index or -1
+    TV xv;         // ring, L: the row's input x value
+    int32_t xnext; // ring, L: x index of the row the lane takes in this group's next request
+    int32_t io;    // ring, L: the row's U-sweep record; U: y index or -1
     int32_t row;   // box vector, U: position of the row in the box vector (first lane of a row) or -1
     int32_t wl;    // level << 17 | sl_info; -1 past the wavefront's last slice
     int32_t slot;  // ring slot (box vector, L: position) of the slice's first row
 };
 
-// Seven loads per item whatever the slice (pairs past the slice's width
-// re-read its last pair; consume() masks them), so the memory counters always
-// hold the later items' loads in the same order and the wait for one group
-// of items never waits for the next.  Lanes past the slice's rows (nvalid =
-// rows * lanes per row) read lane 0's data instead of their own padding, so
-// the cache lines of the padding are never fetched; their results are
-// discarded.
-// With the box vector in LDS (VEC) the L sweep's inputs and results live there
-// (five loads per item) and the U sweep reads 1/u_ii and its row's slot, per
-// row of the slice, instead of a record (seven loads); y is written after the
-// U sweep.
-template <class TF, bool UPPER, bool VEC, class Rec>
-__device__ __forceinline__ void fetch_item(const DevSweep<TF> &S, const Rec *rec, int64_t g64, int64_t a64,
-                                           int64_t off, int w, int sp, int nvalid, Item<TF> &X) {
+// A fixed number of loads per item of a sweep whatever the slice (pairs past
+// the slice's width re-read its last pair; consume() masks them), so the
+// memory counters always hold the later items' loads in the same order and
+// the wait for one group of items never waits for the next.  Lanes past the
+// slice's rows (nvalid = rows * lanes per row) read lane 0's data instead of
+// their own padding, so the cache lines of the padding are never fetched;
+// their results are discarded.
+// Ring, L sweep (eight loads): the row's input straight from x, at the x index
+// fetched with this group's previous request (xi), the row's U-sweep record
+// and the x index for the group's next request (at slice g2, sp2 lanes per
+// row, nvalid2 valid lanes).  Ring, U sweep (seven): the record {L result,
+// 1/u_ii} and the y index.  With the box vector in LDS (VEC) the L sweep's
+// inputs and results live there (five loads per item) and the U sweep reads
+// 1/u_ii and its row's slot instead of a record (seven loads); y is written
+// after the U sweep.
+template <class TF, class TV, bool UPPER, bool VEC, class Rec>
+__device__ __forceinline__ void fetch_item(const DevSweep<TF> &S, const Rec *rec, const TV *xg, int32_t xi,
+                                           int64_t g64, int64_t a64, int64_t g2_64, int sp2, int nvalid2,
+                                           int64_t off, int w, int sp, int nvalid, Item<TF, TV> &X) {
     const int lane = threadIdx.x % 64, ln = lane < nvalid ? lane : 0;
     const int64_t gpos = g64 + ln;
     // the row's record, stored per row of the slice (every lane of a split row reads it)
@@ -90,8 +97,8 @@ __device__ __forceinline__ void fetch_item(const DevSweep<TF> &S, const Rec *rec
     } else if constexpr (UPPER) {  // {L result, 1/u_ii} and the y index of an owned row
         X.h = rec[rpos];
         X.io = S.lane_io[rpos];
-    } else if constexpr (!VEC) {  // the gathered input and the row's U-sweep record
-        X.h.x = rec[rpos];
+    } else if constexpr (!VEC) {  // the input, the row's U-sweep record
+        X.xv = xg[max(xi, 0)];
         X.io = S.lane_next[rpos];
     }
     const int lastp = w > 0 ? (w - 1) / 2 : 0;
@@ -99,6 +106,10 @@ __device__ __forceinline__ void fetch_item(const DevSweep<TF> &S, const Rec *rec
     for (int j = 0; j < 4; ++j) X.val[j] = S.val[off + int64_t(min(j, lastp)) * 64 + ln];
     const uint4 a = S.addr[a64 + ln];
     X.addr[0] = a.x; X.addr[1] = a.y; X.addr[2] = a.z; X.addr[3] = a.w;
+    if constexpr (!UPPER && !VEC) {  // the next request's x index
+        const int l2 = lane < nvalid2 ? lane : 0;
+        X.xnext = S.lane_io[g2_64 + ((l2 * ((65536 + sp2 - 1) / sp2)) >> 16)];
+    }
 }
 
 // The value of the next lane (lane l gets lane l + 1's; the last lane 0): a
@@ -112,8 +123,8 @@ __device__ __forceinline__ double wave_next(double v) {
     return __hiloint2double(hi, lo);
 }
 
-template <class TF>
-__device__ __forceinline__ TF consume(const Item<TF> &X, int w, const TF *ring, TF acc) {
+template <class TF, class TV>
+__device__ __forceinline__ TF consume(const Item<TF, TV> &X, int w, const TF *ring, TF acc) {
     TF tv[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) tv[q] = ring[(X.addr[q / 2] >> (16 * (q % 2))) & 0xffffu];
@@ -198,7 +209,10 @@ struct Fold<TF, false> {};
 
 template <class TV, class TF, bool UPPER, bool LDS, bool VEC, int NT, bool FOLD, class Rec>
 __device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int sl0, int asl0, int64_t off0, int nlev,
-                                      int nsl, TF *ring, const Rec *rec, TF *lout, TV *y, Fold<TF, FOLD> &fd) {
+                                      int nsl, TF *ring, const Rec *rec, const TV *xg, TF *lout, TV *y,
+                                      Fold<TF, FOLD> &fd) {
+    using It = Item<TF, TV>;
+    constexpr bool XG = !UPPER && !VEC;  // ring L sweep: inputs read from x in the items
     constexpr int K = SweepShape<TF, NT>::K;
     const int lane = threadIdx.x % 64, nw = NT / 64;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
@@ -229,7 +243,7 @@ __device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int 
             }
         }
     };
-    auto pass_to = [&](const Item<TF> &n) {
+    auto pass_to = [&](const It &n) {
         const int lv = n.wl >= 0 ? n.wl >> 17 : nlev;
         for (; passed < lv; ++passed) barrier();
     };
@@ -238,7 +252,13 @@ __device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int 
         return;
     }
     int fg = wv;  // next slice to request (past the end: re-reads the last slice)
-    auto request = [&](Item<TF> (&grp)[K]) {
+    // ring L sweep: a slice's lanes per row and valid lanes from its metadata
+    auto lanes = [&](int gg, int &sp, int &nvalid) {
+        const int wl = __builtin_amdgcn_readfirstlane(M.wl[gg]);
+        sp = ((wl >> 4) & 63) + 1;
+        nvalid = ((wl >> 10) & 127) * sp;
+    };
+    auto request = [&](It (&grp)[K]) {
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
@@ -247,23 +267,30 @@ __device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int 
             const int offr = __builtin_amdgcn_readfirstlane(M.off[gg]);
             grp[k].wl = g < nsl ? wl : -1;
             grp[k].slot = __builtin_amdgcn_readfirstlane(M.slot[gg]);
-            fetch_item<TF, UPPER, VEC>(S, rec, int64_t(sl0 + gg) * 64, int64_t(asl0 + gg) * 64, off0 + offr, wl & 15,
-                                       ((wl >> 4) & 63) + 1, ((wl >> 10) & 127) * (((wl >> 4) & 63) + 1), grp[k]);
+            // this group's next request takes slice g + 2 K nw in this place
+            const int gg2 = min(g + 2 * K * nw, nsl - 1);
+            int sp2 = 1, nvalid2 = 1;
+            if constexpr (XG) lanes(gg2, sp2, nvalid2);
+            fetch_item<TF, TV, UPPER, VEC>(S, rec, xg, XG ? grp[k].xnext : 0, int64_t(sl0 + gg) * 64,
+                                           int64_t(asl0 + gg) * 64, int64_t(sl0 + gg2) * 64, sp2, nvalid2, off0 + offr,
+                                           wl & 15, ((wl >> 4) & 63) + 1, ((wl >> 10) & 127) * (((wl >> 4) & 63) + 1),
+                                           grp[k]);
         }
         fg += K * nw;
         __builtin_amdgcn_sched_barrier(0);
     };
     // process one group; next: the first item of the other group
-    auto process = [&](const Item<TF> (&grp)[K], const Item<TF> &next) {
+    auto process = [&](const It (&grp)[K], const It &next) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const Item<TF> &it = grp[k];
+            const It &it = grp[k];
             if (it.wl < 0) break;
             const int w = it.wl & 15, sp = ((it.wl >> 4) & 63) + 1, nrow = (it.wl >> 10) & 127;
             const int rr = (lane * ((65536 + sp - 1) / sp)) >> 16, first = rr * sp;  // row in the slice
             const bool writer = lane == first && rr < nrow;
             TF v0;  // the row's input, added once (by its first lane)
-            if constexpr (!VEC) v0 = writer ? it.h.x : TF(0);
+            if constexpr (XG) v0 = writer ? TF(it.xv) : TF(0);
+            else if constexpr (!VEC) v0 = writer ? it.h.x : TF(0);
             else if constexpr (UPPER) v0 = writer ? ring[it.row] : TF(0);
             else v0 = writer ? ring[it.slot + rr] : TF(0);
             TF acc = consume(it, w, ring, v0);
@@ -289,7 +316,18 @@ __device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int 
         }
         __builtin_amdgcn_sched_barrier(0);
     };
-    Item<TF> A[K], B[K];
+    It A[K], B[K];
+    if constexpr (XG) {  // the x indices of the first two requests
+#pragma unroll
+        for (int k = 0; k < 2 * K; ++k) {
+            const int gg = min(wv + k * nw, nsl - 1);
+            int sp, nvalid;
+            lanes(gg, sp, nvalid);
+            const int l = lane < nvalid ? lane : 0;
+            const int32_t xi = S.lane_io[int64_t(sl0 + gg) * 64 + ((l * ((65536 + sp - 1) / sp)) >> 16)];
+            (k < K ? A[k] : B[k - K]).xnext = xi;
+        }
+    }
     request(A);
     request(B);
     pass_to(A[0]);
@@ -313,12 +351,13 @@ __device__ __forceinline__ void meta_pointers(unsigned char *base, int meta_lev,
     M.slot = M.wl + meta_sl;
 }
 
-// One subdomain per workgroup (item `blk` solves subdomain perm[blk]): gather
-// x (coalesced over the L-sweep order), L sweep, U sweep with restricted
-// scatter.  The ring of the last `depth`
-// levels is in LDS when LDS = true, else in the workspace; with VEC (always
-// in LDS) the whole box vector is there instead: the gather writes x into it,
-// the L sweep overwrites it with its results and the U sweep with its own.
+// One subdomain per workgroup (item `blk` solves subdomain perm[blk]): L
+// sweep, U sweep with restricted scatter.  The ring of the last `depth`
+// levels is in LDS when LDS = true, else in the workspace, and the L sweep's
+// items read their inputs from x; with VEC (always in LDS) the whole box
+// vector is there instead: a gather (coalesced over the L-sweep order) writes
+// x into it, the L sweep overwrites it with its results and the U sweep with
+// its own.
 template <class TV, class TF, bool LDS, bool VEC, int NT, bool FOLD = false>
 __device__ __forceinline__ void ras_block(const DevRas<TF> &R, int meta_lev, int meta_sl, const TV *__restrict__ x,
                                           TV *__restrict__ y, int blk, unsigned char *ras_smem) {
@@ -381,27 +420,11 @@ __device__ __forceinline__ void ras_block(const DevRas<TF> &R, int meta_lev, int
                 if (a < nrows) ring[a] = TF(v[u]);
             }
         }
-    } else {
-        // the L sweep's inputs, one per row of a slice (slice*64 + row): eight
-        // entries per thread per round, the index loads, then the value
-        // loads, in flight together; entries past a slice's rows are never read
-        constexpr int U = 8;
-        const int64_t p0 = int64_t(I.slL0) * 64, p1 = int64_t(I.slL0 + I.nslL) * 64;
-        for (int64_t p = p0 + threadIdx.x; p < p1; p += int64_t(NT) * U) {
-            int32_t io[U];
-            TV v[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) io[u] = p + u * NT < p1 ? R.L.lane_io[p + u * NT] : -1;
-#pragma unroll
-            for (int u = 0; u < U; ++u) v[u] = io[u] >= 0 ? x[io[u]] : TV(0);
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (io[u] >= 0) R.lin[p + u * NT] = TF(v[u]);
-        }
-    }
+    }  // ring: the L sweep's items read their inputs from x
     __syncthreads();
-    sweep<TV, TF, false, LDS, VEC, NT, FOLD>(R.L, M, I.slL0, I.aslL0, I.offL0, I.levL1 - I.levL0, I.nslL, ring, R.lin,
-                                             reinterpret_cast<TF *>(R.lout), y, fd);
+    sweep<TV, TF, false, LDS, VEC, NT, FOLD>(R.L, M, I.slL0, I.aslL0, I.offL0, I.levL1 - I.levL0, I.nslL, ring,
+                                             static_cast<const TF *>(nullptr), x, reinterpret_cast<TF *>(R.lout), y,
+                                             fd);
     __syncthreads();  // L results visible; the U metadata replaces the L metadata
     if constexpr (FOLD) fd.lev = I.fold_levU;  // the early rows' L results (in fd.v) go back after this U level
     if (int(threadIdx.x) < n16) md[threadIdx.x] = up0;
@@ -409,7 +432,7 @@ __device__ __forceinline__ void ras_block(const DevRas<TF> &R, int meta_lev, int
     for (int a = threadIdx.x + MU * NT; a < n16; a += NT) md[a] = uimg[a];
     __syncthreads();
     sweep<TV, TF, true, LDS, VEC, NT, FOLD>(R.U, M, I.slU0, I.aslU0, I.offU0, I.levU1 - I.levU0, I.nslU, ring, R.lout,
-                                            nullptr, y, fd);
+                                            static_cast<const TV *>(nullptr), nullptr, y, fd);
     if constexpr (VEC) {  // restricted scatter of the owned rows from LDS (folded: all but the late ones, which
                           // were written before their slots were reused, have slot = position)
         const int2 *own = R.own + I.own0;
