@@ -87,6 +87,7 @@ struct OneLevel {
     int32_t *Lio = nullptr, *Lnext = nullptr, *Uio = nullptr, *Unext = nullptr;
     uint16_t *Laddr = nullptr, *Uaddr = nullptr;
     void *Lval = nullptr, *Uval = nullptr, *lout = nullptr, *ring = nullptr;
+    int64_t nU = 0;  // entries per U-sweep row array (U slices * 64)
     int32_t *gio = nullptr, *Lmeta = nullptr, *Umeta = nullptr, *perm = nullptr, *own = nullptr;
 
     static void layout(Carver &c, const HostRas &H, int precision, OneLevel &o) {
@@ -109,7 +110,8 @@ struct OneLevel {
         o.Unext = c.take<int32_t>(H.U.lane_next.size());
         o.Uaddr = c.take<uint16_t>(o.folded ? H.fold_Uaddr.size() : H.U.addr.size());
         o.Uval = c.take<char>(H.U.val.size() * fs);
-        o.lout = c.take<char>(2 * H.U.lane_io.size() * fs);
+        o.nU = int64_t(H.U.lane_io.size());
+        o.lout = c.take<char>(2 * H.U.lane_io.size() * fs);  // 1/u_ii, then the ring's L results
         o.ring = c.take<char>(size_t(H.nsd) * H.ring_depth * H.ring_width * fs);
         o.gio = c.take<int32_t>(H.gio.size());
         o.Lmeta = c.take<int32_t>(H.L.meta.size());
@@ -154,11 +156,10 @@ struct OneLevel {
             CSD_HIP(up(Lval, f.data(), f.size() * sizeof(T)));
             f.assign(H.U.val.begin(), H.U.val.end());
             CSD_HIP(up(Uval, f.data(), f.size() * sizeof(T)));
-            // ring: records {L result (written by the L sweep), 1/u_ii}; box vector: 1/u_ii alone
-            const size_t stride = H.box_vector ? 1 : 2;
-            f.assign(2 * H.U.lane_diag.size(), T(0));
+            // 1/u_ii per row of a U slice; the ring's L results follow (written by the L sweep)
+            f.assign(H.U.lane_diag.size(), T(0));
             for (size_t a = 0; a < H.U.lane_diag.size(); ++a)
-                f[stride * a + stride - 1] = H.U.lane_diag[a] != 0.0 ? T(1.0 / H.U.lane_diag[a]) : T(0);
+                f[a] = H.U.lane_diag[a] != 0.0 ? T(1.0 / H.U.lane_diag[a]) : T(0);
             CSD_HIP(up(lout, f.data(), f.size() * sizeof(T)));
             return CSDYN_OK;
         };
@@ -172,7 +173,8 @@ struct OneLevel {
         using TF2 = typename Pair<TF>::type;
         R.L = DevSweep<TF>{Lio, Lnext, (const TF2 *)Lval, (const uint4 *)Laddr, (const int4 *)Lmeta};
         R.U = DevSweep<TF>{Uio, Unext, (const TF2 *)Uval, (const uint4 *)Uaddr, (const int4 *)Umeta};
-        R.lout = (TF2 *)lout;
+        R.dinv = (const TF *)lout;
+        R.lres = (TF *)lout + nU;
         R.ring = (TF *)ring;
         R.gio = gio;
         R.perm = perm;

@@ -37,8 +37,8 @@ struct DevRas {
     using TF2 = typename Pair<TF>::type;
     const SdInfo *sd;
     DevSweep<TF> L, U;
-    TF2 *lout;  // [U slices * 64] ring: {L-sweep result, 1/u_ii} per row of a U slice;
-                // box vector: 1/u_ii per row (dense, first half)
+    const TF *dinv;  // [U slices * 64] 1/u_ii per row of a U slice
+    TF *lres;        // [U slices * 64] ring: the L sweep's result per row of a U slice
     TF *ring;   // [nsd][depth * width] when the ring is not in LDS
     const int32_t *gio;  // box vector: x index of each position, per subdomain from SdInfo::g0
     const int32_t *perm; // [nsd] subdomain of each workgroup
@@ -78,13 +78,13 @@ struct Item {
 // Ring, L sweep (eight loads): the row's input straight from x, at the x index
 // fetched with this group's previous request (xi), the row's U-sweep record
 // and the x index for the group's next request (at slice g2, sp2 lanes per
-// row, nvalid2 valid lanes).  Ring, U sweep (seven): the record {L result,
-// 1/u_ii} and the y index.  With the box vector in LDS (VEC) the L sweep's
+// row, nvalid2 valid lanes).  Ring, U sweep (eight): the row's L result (lres,
+// written by the L sweep), 1/u_ii (rec) and the y index.  With the box vector in LDS (VEC) the L sweep's
 // inputs and results live there (five loads per item) and the U sweep reads
 // 1/u_ii and its row's slot instead of a record (seven loads); y is written
 // after the U sweep.
 template <class TF, class TV, bool UPPER, bool VEC, class Rec>
-__device__ __forceinline__ void fetch_item(const DevSweep<TF> &S, const Rec *rec, const TV *xg, int32_t xi,
+__device__ __forceinline__ void fetch_item(const DevSweep<TF> &S, const Rec *rec, const TF *lres, const TV *xg, int32_t xi,
                                            int64_t g64, int64_t a64, int64_t g2_64, int sp2, int nvalid2,
                                            int64_t off, int w, int sp, int nvalid, Item<TF, TV> &X) {
     const int lane = threadIdx.x % 64, ln = lane < nvalid ? lane : 0;
@@ -93,9 +93,10 @@ __device__ __forceinline__ void fetch_item(const DevSweep<TF> &S, const Rec *rec
     const int64_t rpos = g64 + ((ln * ((65536 + sp - 1) / sp)) >> 16);
     if constexpr (UPPER && VEC) {  // the row's slot and 1/u_ii
         X.row = S.lane_next[rpos];
-        X.h.y = reinterpret_cast<const TF *>(rec)[rpos];
-    } else if constexpr (UPPER) {  // {L result, 1/u_ii} and the y index of an owned row
-        X.h = rec[rpos];
+        X.h.y = rec[rpos];
+    } else if constexpr (UPPER) {  // the L result, 1/u_ii and the y index of an owned row
+        X.h.x = lres[rpos];
+        X.h.y = rec[rpos];
         X.io = S.lane_io[rpos];
     } else if constexpr (!VEC) {  // the input, the row's U-sweep record
         X.xv = xg[max(xi, 0)];
@@ -209,7 +210,7 @@ struct Fold<TF, false> {};
 
 template <class TV, class TF, bool UPPER, bool LDS, bool VEC, int NT, bool FOLD, class Rec>
 __device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int sl0, int asl0, int64_t off0, int nlev,
-                                      int nsl, TF *ring, const Rec *rec, const TV *xg, TF *lout, TV *y,
+                                      int nsl, TF *ring, const Rec *rec, const TV *xg, TF *lres, TV *y,
                                       Fold<TF, FOLD> &fd) {
     using It = Item<TF, TV>;
     constexpr bool XG = !UPPER && !VEC;  // ring L sweep: inputs read from x in the items
@@ -271,7 +272,7 @@ __device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int 
             const int gg2 = min(g + 2 * K * nw, nsl - 1);
             int sp2 = 1, nvalid2 = 1;
             if constexpr (XG) lanes(gg2, sp2, nvalid2);
-            fetch_item<TF, TV, UPPER, VEC>(S, rec, xg, XG ? grp[k].xnext : 0, int64_t(sl0 + gg) * 64,
+            fetch_item<TF, TV, UPPER, VEC>(S, rec, lres, xg, XG ? grp[k].xnext : 0, int64_t(sl0 + gg) * 64,
                                            int64_t(asl0 + gg) * 64, int64_t(sl0 + gg2) * 64, sp2, nvalid2, off0 + offr,
                                            wl & 15, ((wl >> 4) & 63) + 1, ((wl >> 10) & 127) * (((wl >> 4) & 63) + 1),
                                            grp[k]);
@@ -309,7 +310,7 @@ __device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int 
                 if constexpr (UPPER && !VEC) {
                     if (it.io >= 0) y[it.io] = TV(acc);
                 } else if constexpr (!VEC) {
-                    if (it.io >= 0) lout[2 * int64_t(it.io)] = acc;
+                    if (it.io >= 0) lres[it.io] = acc;
                 }
             }
             pass_to(k + 1 < K ? grp[k + 1] : next);
@@ -423,7 +424,7 @@ __device__ __forceinline__ void ras_block(const DevRas<TF> &R, int meta_lev, int
     }  // ring: the L sweep's items read their inputs from x
     __syncthreads();
     sweep<TV, TF, false, LDS, VEC, NT, FOLD>(R.L, M, I.slL0, I.aslL0, I.offL0, I.levL1 - I.levL0, I.nslL, ring,
-                                             static_cast<const TF *>(nullptr), x, reinterpret_cast<TF *>(R.lout), y,
+                                             static_cast<const TF *>(nullptr), x, R.lres, y,
                                              fd);
     __syncthreads();  // L results visible; the U metadata replaces the L metadata
     if constexpr (FOLD) fd.lev = I.fold_levU;  // the early rows' L results (in fd.v) go back after this U level
@@ -431,8 +432,8 @@ __device__ __forceinline__ void ras_block(const DevRas<TF> &R, int meta_lev, int
     if (int(threadIdx.x) + NT < n16) md[threadIdx.x + NT] = up1;
     for (int a = threadIdx.x + MU * NT; a < n16; a += NT) md[a] = uimg[a];
     __syncthreads();
-    sweep<TV, TF, true, LDS, VEC, NT, FOLD>(R.U, M, I.slU0, I.aslU0, I.offU0, I.levU1 - I.levU0, I.nslU, ring, R.lout,
-                                            static_cast<const TV *>(nullptr), nullptr, y, fd);
+    sweep<TV, TF, true, LDS, VEC, NT, FOLD>(R.U, M, I.slU0, I.aslU0, I.offU0, I.levU1 - I.levU0, I.nslU, ring, R.dinv,
+                                            static_cast<const TV *>(nullptr), R.lres, y, fd);
     if constexpr (VEC) {  // restricted scatter of the owned rows from LDS (folded: all but the late ones, which
                           // were written before their slots were reused, have slot = position)
         const int2 *own = R.own + I.own0;
