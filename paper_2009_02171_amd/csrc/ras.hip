@@ -105,11 +105,12 @@ struct OneLevel {
         o.Lio = c.take<int32_t>(ring ? H.L.lane_io.size() : 0);
         o.Lnext = c.take<int32_t>(ring ? H.L.lane_next.size() : 0);
         o.Laddr = c.take<uint16_t>(o.folded ? H.fold_Laddr.size() : H.L.addr.size());
-        o.Lval = c.take<char>(H.L.val.size() * fs);
+        // FP64: the packed value layout; FP32: odd widths' last entries padded to pairs
+        o.Lval = c.take<char>((precision ? 2 * size_t(padded_pairs(H.L)) : H.L.val.size()) * fs);
         o.Uio = c.take<int32_t>(ring ? H.U.lane_io.size() : 0);
         o.Unext = c.take<int32_t>(H.U.lane_next.size());
         o.Uaddr = c.take<uint16_t>(o.folded ? H.fold_Uaddr.size() : H.U.addr.size());
-        o.Uval = c.take<char>(H.U.val.size() * fs);
+        o.Uval = c.take<char>((precision ? 2 * size_t(padded_pairs(H.U)) : H.U.val.size()) * fs);
         o.nU = int64_t(H.U.lane_io.size());
         o.lout = c.take<char>(2 * H.U.lane_io.size() * fs);  // 1/u_ii, then the ring's L results
         o.ring = c.take<char>(size_t(H.nsd) * H.ring_depth * H.ring_width * fs);
@@ -128,7 +129,19 @@ struct OneLevel {
                     set_error("ras: folded subdomain with %d late rows for %d threads", I.nrows - I.fold, threads);
                     return CSDYN_EINVAL;
                 }
-        CSD_HIP(up(sd, H.sd.data(), H.sd.size() * sizeof(SdInfo)));
+        // the FP32 sweep reads the values with odd widths' last entries padded
+        // to pairs: its own value offsets in the subdomain table and metadata
+        const bool padded = precision != 0;
+        std::vector<int64_t> Loff, Uoff;
+        std::vector<SdInfo> psd;
+        std::vector<int32_t> pLm, pUm;
+        if (padded) {
+            Loff = padded_offsets(H.L);
+            Uoff = padded_offsets(H.U);
+            padded_meta(H, Loff, Uoff, psd, pLm, pUm);
+        }
+        const std::vector<SdInfo> &sdv = padded ? psd : H.sd;
+        CSD_HIP(up(sd, sdv.data(), sdv.size() * sizeof(SdInfo)));
         const bool ring = !H.box_vector;
         if (ring) {
             CSD_HIP(up(Lio, H.L.lane_io.data(), H.L.lane_io.size() * 4));
@@ -144,18 +157,25 @@ struct OneLevel {
         CSD_HIP(up(own, H.own.data(), H.own.size() * 4));
         CSD_HIP(up(Uaddr, ua.data(), ua.size() * 2));
         CSD_HIP(up(gio, H.gio.data(), H.gio.size() * 4));
-        const std::vector<int32_t> &lm = folded ? H.fold_Lmeta : H.L.meta;
+        const std::vector<int32_t> &lm = folded ? H.fold_Lmeta : (padded ? pLm : H.L.meta);
+        const std::vector<int32_t> &um = padded ? pUm : H.U.meta;
         CSD_HIP(up(Lmeta, lm.data(), lm.size() * 4));
-        CSD_HIP(up(Umeta, H.U.meta.data(), H.U.meta.size() * 4));
+        CSD_HIP(up(Umeta, um.data(), um.size() * 4));
         CSD_HIP(up(perm, H.perm.data(), H.perm.size() * 4));
-        // U-sweep records {L result, 1/u_ii}: the L sweep writes the first
-        // half; padding lanes read results that are never written, so start at 0
         auto upload_as = [&](auto zero) -> int32_t {
             using T = decltype(zero);
-            std::vector<T> f(H.L.val.begin(), H.L.val.end());
-            CSD_HIP(up(Lval, f.data(), f.size() * sizeof(T)));
-            f.assign(H.U.val.begin(), H.U.val.end());
-            CSD_HIP(up(Uval, f.data(), f.size() * sizeof(T)));
+            std::vector<T> f;
+            for (int pass = 0; pass < 2; ++pass) {
+                const SweepPack &P = pass ? H.U : H.L;
+                if (padded) {
+                    const std::vector<int64_t> &no = pass ? Uoff : Loff;
+                    f.resize(2 * size_t(padded_pairs(P)));
+                    padded_values(P, no, f.data());
+                } else {
+                    f.assign(P.val.begin(), P.val.end());
+                }
+                CSD_HIP(up(pass ? Uval : Lval, f.data(), f.size() * sizeof(T)));
+            }
             // 1/u_ii per row of a U slice; the ring's L results follow (written by the L sweep)
             f.assign(H.U.lane_diag.size(), T(0));
             for (size_t a = 0; a < H.U.lane_diag.size(); ++a)

@@ -27,7 +27,7 @@ struct DevSweep {
                                // of an owned row; else -1
     const int32_t *lane_next;  // [nslice*64] per row of a slice: ring, L, the row's U-sweep record; box vector,
                                // U, the row's slot
-    const TF2 *val;            // [pairs] factor entries, two per lane
+    const TF2 *val;            // factor entries, two per lane (FP64: an odd width's last entries one per lane)
     const uint4 *addr;         // [64 * nslice] addresses of the dependencies (ring slots or positions), eight per lane
     const int4 *meta;          // [nsd][meta bytes / 16] LDS metadata image of each subdomain's sweep
 };
@@ -103,8 +103,25 @@ __device__ __forceinline__ void fetch_item(const DevSweep<TF> &S, const Rec *rec
         X.io = S.lane_next[rpos];
     }
     const int lastp = w > 0 ? (w - 1) / 2 : 0;
+    if constexpr (sizeof(TF) == 8) {
+        // FP64 layout: pairs j < w / 2, and for an odd width the lanes' last
+        // entries one per lane after them, read as pairs starting at the lane's
+        // own (its neighbour's value in .y is never used), so the wave fetches 8
+        // bytes per lane for them instead of a padded pair
+        using TF2 = typename Pair<TF>::type;
+        using TF2u = TF2 __attribute__((aligned(sizeof(TF))));
+        const int np = w >> 1;
+        const TF *vs = reinterpret_cast<const TF *>(S.val);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) X.val[j] = S.val[off + int64_t(min(j, lastp)) * 64 + ln];
+        for (int j = 0; j < 4; ++j) {
+            const int jj = min(j, lastp);
+            const int64_t e = (w & 1) && jj == np ? 2 * (off + int64_t(np) * 64) + ln : 2 * (off + int64_t(jj) * 64 + ln);
+            X.val[j] = *reinterpret_cast<const TF2u *>(vs + e);
+        }
+    } else {  // FP32 layout: every lane's entries in pairs, an odd width's last one padded
+#pragma unroll
+        for (int j = 0; j < 4; ++j) X.val[j] = S.val[off + int64_t(min(j, lastp)) * 64 + ln];
+    }
     const uint4 a = S.addr[a64 + ln];
     X.addr[0] = a.x; X.addr[1] = a.y; X.addr[2] = a.z; X.addr[3] = a.w;
     if constexpr (!UPPER && !VEC) {  // the next request's x index

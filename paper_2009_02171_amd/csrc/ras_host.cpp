@@ -427,9 +427,13 @@ int32_t pack_sweep(const LocalSd &L, bool upper, const Schedule &S, const Schedu
         P.sl_info.push_back(S.slice_nrow[sl] << 10 | (sp - 1) << 4 | w);
         P.sl_off.push_back(off);
         P.sl_slot.push_back(S.slice_slot[sl]);
-        P.val.resize(P.val.size() + (w + 1) / 2 * 128, 0.0);
+        // full pairs [w / 2][64 lanes]; an odd width's last entry as one value per lane [64] after them
+        const int np = w / 2;
+        P.val.resize(P.val.size() + size_t(np) * 128 + (w % 2) * 64, 0.0);
         P.addr.resize(P.addr.size() + 512, 0);
-        auto vat = [&](int64_t q, int a) { return 2 * (off + (q / 2) * 64 + a) + q % 2; };
+        auto vat = [&](int64_t q, int a) {
+            return q < 2 * np ? 2 * (off + (q / 2) * 64 + a) + q % 2 : 2 * (off + int64_t(np) * 64) + a;
+        };
         auto aat = [&](int64_t q, int a) { return 8 * (aoff + a) + q; };
         for (int a = 0; a < 64; ++a) {
             const int32_t r = S.slice_rows[sl * 64 + a];
@@ -543,6 +547,61 @@ bool fold_plan(const LocalSd &L, const Schedule &S, int cap, int max_late, int32
 }
 
 }  // namespace
+
+// ------------------------------------------------------------------ padded value layout
+constexpr int64_t kTailPairs = 64 * 64 / 2;  // the pairs of the tail padding after the last slice
+
+std::vector<int64_t> padded_offsets(const SweepPack &P) {
+    std::vector<int64_t> off(P.sl_info.size() + 1);
+    int64_t cur = 0;
+    for (size_t sl = 0; sl < P.sl_info.size(); ++sl) {
+        off[sl] = cur;
+        cur += int64_t((P.sl_info[sl] & 15) + 1) / 2 * 64;
+    }
+    off.back() = cur;
+    return off;
+}
+
+int64_t padded_pairs(const SweepPack &P) { return padded_offsets(P).back() + kTailPairs; }
+
+template <class T>
+void padded_values(const SweepPack &P, const std::vector<int64_t> &new_off, T *out) {
+    const int64_t nsl = int64_t(P.sl_info.size());
+    std::fill(out + 2 * new_off[size_t(nsl)], out + 2 * (new_off[size_t(nsl)] + kTailPairs), T(0));
+#pragma omp parallel for schedule(dynamic, 1024)
+    for (int64_t sl = 0; sl < nsl; ++sl) {
+        const int w = P.sl_info[size_t(sl)] & 15, np = w / 2;
+        const double *src = P.val.data() + 2 * P.sl_off[size_t(sl)];
+        T *dst = out + 2 * new_off[size_t(sl)];
+        for (int64_t a = 0; a < int64_t(np) * 128; ++a) dst[a] = T(src[a]);
+        if (w % 2)
+            for (int a = 0; a < 64; ++a) {
+                dst[int64_t(np) * 128 + 2 * a] = T(src[int64_t(np) * 128 + a]);
+                dst[int64_t(np) * 128 + 2 * a + 1] = T(0);
+            }
+    }
+}
+template void padded_values<float>(const SweepPack &, const std::vector<int64_t> &, float *);
+template void padded_values<double>(const SweepPack &, const std::vector<int64_t> &, double *);
+
+void padded_meta(const HostRas &H, const std::vector<int64_t> &Loff, const std::vector<int64_t> &Uoff,
+                 std::vector<SdInfo> &sd, std::vector<int32_t> &Lmeta, std::vector<int32_t> &Umeta) {
+    sd = H.sd;
+    Lmeta = H.L.meta;
+    Umeta = H.U.meta;
+    const int offw = int(((size_t(H.max_levels) + 1) * 4 + 15) / 16 * 16 / 4);
+    for (int s = 0; s < H.nsd; ++s) {
+        SdInfo &I = sd[size_t(s)];
+        for (int pass = 0; pass < 2; ++pass) {
+            const std::vector<int64_t> &no = pass ? Uoff : Loff;
+            const int sl0 = pass ? I.slU0 : I.slL0, nsl = pass ? I.nslU : I.nslL;
+            const int64_t off0 = nsl > 0 ? no[size_t(sl0)] : 0;
+            (pass ? I.offU0 : I.offL0) = off0;
+            int32_t *m = (pass ? Umeta : Lmeta).data() + size_t(s) * H.meta_words;
+            for (int q = 0; q < nsl; ++q) m[offw + q] = int32_t(no[size_t(sl0 + q)] - off0);
+        }
+    }
+}
 
 int32_t host_subdomain(const HostGeom &g, const csdyn_op &op, const int sub[3], int overlap, int s,
                        std::vector<int32_t> &gcell, std::vector<int32_t> &own, std::vector<int64_t> &rp,

@@ -41,7 +41,8 @@ struct SweepPack {
                                      // the row's index in it); box vector: the row's position in the box vector,
                                      // L per lane, U per row
     std::vector<double> lane_diag;   // [nslice*64] U only: u_ii per row
-    std::vector<double> val;         // [2 * pairs]
+    std::vector<double> val;         // per slice: [w / 2][64] value pairs, then for an odd width w [64]
+                                     // single values (the lanes' last entries); offsets in pairs
     std::vector<uint16_t> addr;      // ring slot of the dependency: per subdomain a block of
                                      // [8 * 64 * nsl] from slice SdInfo::asl*0; identical blocks stored once
     std::vector<int32_t> meta;       // [nsd][meta words] LDS metadata image of each subdomain's sweep
@@ -152,6 +153,21 @@ struct HostRas {
 // 3 as 0 but never folded.
 int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], int overlap, int storage,
                        HostRas &out);
+
+// The factor values with every odd width's last entries padded to pairs (the
+// layout the FP32 sweep reads; the FP64 sweep reads the packed layout of
+// SweepPack::val): new_off[slice] is the slice's first pair, padded_pairs()
+// the pairs of the whole pack (with the same tail padding as val), and
+// padded_values() writes them, converted to T, into out (padded_pairs() * 2
+// entries).
+std::vector<int64_t> padded_offsets(const SweepPack &P);
+int64_t padded_pairs(const SweepPack &P);
+template <class T>
+void padded_values(const SweepPack &P, const std::vector<int64_t> &new_off, T *out);
+// The subdomain table and metadata images for the padded layout (each
+// subdomain's first pair and its slices' relative offsets).
+void padded_meta(const HostRas &H, const std::vector<int64_t> &Loff, const std::vector<int64_t> &Uoff,
+                 std::vector<SdInfo> &sd, std::vector<int32_t> &Lmeta, std::vector<int32_t> &Umeta);
 
 // One subdomain's box cells, owned cells and ILU(0) factors as CSR (L strictly
 // lower with unit diagonal implied, U upper), for inspection.
