@@ -38,9 +38,13 @@ __global__ void k_scale(T *w, int64_t n, T a) {
 // v_{j+1} = w / ||w|| with the norms the reduction left on the device (ww:
 // ||w||^2 before the projection, nn: after it), the same arithmetic as the
 // host's; on a happy breakdown (||w|| <= 1e-14 of its norm before the
-// projection) w is left as it is.
+// projection) w is left as it is.  With rb, block 0 first copies the nrb
+// reduction values red[] to rb (pinned host memory the host reads for the
+// step's Hessenberg column), which saves a copy launch per step.
 template <class T>
-__global__ void k_scale_arnoldi(T *w, int64_t n, const T *ww, const T *nn) {
+__global__ void k_scale_arnoldi(T *w, int64_t n, const T *ww, const T *nn, const T *red, int nrb, T *rb) {
+    if (rb && blockIdx.x == 0)
+        for (int i = threadIdx.x; i < nrb; i += blockDim.x) rb[i] = red[i];
     const double hn = sqrt(fmax(double(*nn), 0.0));
     if (hn <= 1e-14 * sqrt(double(*ww))) return;
     const T a = T(1.0 / hn);
@@ -348,6 +352,7 @@ int32_t Gmres<T>::norm(const T *v, double &out, hipStream_t s) {
 constexpr size_t kReadBackElems = 2048;  // doubles: a step's reductions or a cycle's rotation state
 struct ReadBack {
     void *buf[2] = {nullptr, nullptr};
+    void *dbuf[2] = {nullptr, nullptr};  // the same buffers as the device addresses them
     hipEvent_t ev[2] = {nullptr, nullptr};
 };
 
@@ -363,6 +368,7 @@ static int32_t readback_for(int depth, ReadBack *&rb) {
     ReadBack r;
     for (int i = 0; i < 2; ++i) {
         CSD_HIP(hipHostMalloc(&r.buf[i], sizeof(double) * kReadBackElems, hipHostMallocDefault));
+        CSD_HIP(hipHostGetDevicePointer(&r.dbuf[i], r.buf[i], 0));
         CSD_HIP(hipEventCreateWithFlags(&r.ev[i], hipEventDisableTiming));
     }
     pool.emplace_back(key, r);
@@ -433,12 +439,14 @@ int32_t Gmres<T>::solve(const DevFn<T> &A, const DevFn<T> *M, const T *b, T *x, 
                 CSD_TRY(Vec<T>::mupdate(w, V, n, j + 1, red + kRedStride, partial, red + 2 * kRedStride, s));
             }
         }
-        CSD_HIP(hipMemcpyAsync(rb->buf[j % 2], red, sizeof(T) * nred * kRedStride, hipMemcpyDeviceToHost, s));
+        {
+            PhaseScope ps(PH_ORTH, s);  // v_{j+1}, and the step's reductions to the host's buffer
+            hipLaunchKernelGGL(k_scale_arnoldi<T>, ew_grid(n), dim3(256), 0, s, w, n, red + kRedStride - 1,
+                               red + nred * kRedStride - 1, (const T *)red, nred * kRedStride,
+                               static_cast<T *>(rb->dbuf[j % 2]));
+            CSD_LAUNCHED();
+        }
         CSD_HIP(hipEventRecord(rb->ev[j % 2], s));
-        PhaseScope ps(PH_ORTH, s);
-        hipLaunchKernelGGL(k_scale_arnoldi<T>, ew_grid(n), dim3(256), 0, s, w, n, red + kRedStride - 1,
-                           red + nred * kRedStride - 1);
-        CSD_LAUNCHED();
         return CSDYN_OK;
     };
     // device-resident form of step j: the same kernels without the read-back,
@@ -460,7 +468,7 @@ int32_t Gmres<T>::solve(const DevFn<T> &A, const DevFn<T> *M, const T *b, T *x, 
         hipLaunchKernelGGL(k_hessenberg<T>, dim3(1), dim3(64), 0, s, red, nred, gs, j, m, tol);
         CSD_LAUNCHED();
         hipLaunchKernelGGL(k_scale_arnoldi<T>, ew_grid(n), dim3(256), 0, s, w, n, red + kRedStride - 1,
-                           red + nred * kRedStride - 1);
+                           red + nred * kRedStride - 1, (const T *)nullptr, 0, (T *)nullptr);
         CSD_LAUNCHED();
         return CSDYN_OK;
     };

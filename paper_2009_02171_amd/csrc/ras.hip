@@ -23,11 +23,11 @@
 
 namespace csd {
 
-template <class TV, class TF, bool LDS, bool VEC, int NT, bool FOLD = false>
+template <class TV, class TF, bool LDS, bool VEC, int NT, bool FOLD = false, bool TAILS = false>
 __global__ __launch_bounds__(NT) void k_ras(DevRas<TF> R, int meta_lev, int meta_sl, const TV *__restrict__ x,
                                             TV *__restrict__ y) {
     extern __shared__ __align__(16) unsigned char ras_smem[];
-    ras_block<TV, TF, LDS, VEC, NT, FOLD>(R, meta_lev, meta_sl, x, y, int(blockIdx.x), ras_smem);
+    ras_block<TV, TF, LDS, VEC, NT, FOLD, TAILS>(R, meta_lev, meta_sl, x, y, int(blockIdx.x), ras_smem);
 }
 
 // restriction: mean of the 8 children; prolongation: copy to the children
@@ -88,6 +88,13 @@ struct OneLevel {
     uint16_t *Laddr = nullptr, *Uaddr = nullptr;
     void *Lval = nullptr, *Uval = nullptr, *lout = nullptr, *ring = nullptr;
     int64_t nU = 0;  // entries per U-sweep row array (U slices * 64)
+    // Value layout of the sweep: packed (an odd width's last entries one per
+    // lane after the slice's pairs, read unpadded) for FP64 launches with at
+    // least one subdomain per compute unit, whose time follows each compute
+    // unit's bytes; padded pairs otherwise (FP32, and launches of a few
+    // workgroups bound by their chain of levels, where the packed layout's
+    // per-load address select costs more than its bytes save).
+    bool tails = false;
     int32_t *gio = nullptr, *Lmeta = nullptr, *Umeta = nullptr, *perm = nullptr, *own = nullptr;
 
     static void layout(Carver &c, const HostRas &H, int precision, OneLevel &o) {
@@ -96,6 +103,12 @@ struct OneLevel {
         o.depth = H.ring_depth; o.width = H.ring_width; o.meta_lev = H.max_levels; o.meta_sl = H.max_slices;
         o.max_total_levels = H.max_total_levels; o.precision = precision;
         o.vec = H.box_vector; o.box_rows = H.box_rows;
+        {
+            int dev = 0, cus = 0;
+            if (hipGetDevice(&dev) == hipSuccess &&
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+                o.tails = precision == 0 && H.nsd >= cus;
+        }
         o.folded = H.folded && precision == 0;
         o.fold_rows = o.folded ? H.fold_rows : 0;
         o.sd = c.take<SdInfo>(H.sd.size());
@@ -105,12 +118,11 @@ struct OneLevel {
         o.Lio = c.take<int32_t>(ring ? H.L.lane_io.size() : 0);
         o.Lnext = c.take<int32_t>(ring ? H.L.lane_next.size() : 0);
         o.Laddr = c.take<uint16_t>(o.folded ? H.fold_Laddr.size() : H.L.addr.size());
-        // FP64: the packed value layout; FP32: odd widths' last entries padded to pairs
-        o.Lval = c.take<char>((precision ? 2 * size_t(padded_pairs(H.L)) : H.L.val.size()) * fs);
+        o.Lval = c.take<char>((o.tails ? H.L.val.size() : 2 * size_t(padded_pairs(H.L))) * fs);
         o.Uio = c.take<int32_t>(ring ? H.U.lane_io.size() : 0);
         o.Unext = c.take<int32_t>(H.U.lane_next.size());
         o.Uaddr = c.take<uint16_t>(o.folded ? H.fold_Uaddr.size() : H.U.addr.size());
-        o.Uval = c.take<char>((precision ? 2 * size_t(padded_pairs(H.U)) : H.U.val.size()) * fs);
+        o.Uval = c.take<char>((o.tails ? H.U.val.size() : 2 * size_t(padded_pairs(H.U))) * fs);
         o.nU = int64_t(H.U.lane_io.size());
         o.lout = c.take<char>(2 * H.U.lane_io.size() * fs);  // 1/u_ii, then the ring's L results
         o.ring = c.take<char>(size_t(H.nsd) * H.ring_depth * H.ring_width * fs);
@@ -129,16 +141,16 @@ struct OneLevel {
                     set_error("ras: folded subdomain with %d late rows for %d threads", I.nrows - I.fold, threads);
                     return CSDYN_EINVAL;
                 }
-        // the FP32 sweep reads the values with odd widths' last entries padded
-        // to pairs: its own value offsets in the subdomain table and metadata
-        const bool padded = precision != 0;
+        // the padded layout: its own value offsets in the subdomain table and
+        // metadata images
+        const bool padded = !tails;
         std::vector<int64_t> Loff, Uoff;
         std::vector<SdInfo> psd;
         std::vector<int32_t> pLm, pUm;
         if (padded) {
             Loff = padded_offsets(H.L);
             Uoff = padded_offsets(H.U);
-            padded_meta(H, Loff, Uoff, psd, pLm, pUm);
+            padded_meta(H, folded ? H.fold_Lmeta : H.L.meta, Loff, Uoff, psd, pLm, pUm);
         }
         const std::vector<SdInfo> &sdv = padded ? psd : H.sd;
         CSD_HIP(up(sd, sdv.data(), sdv.size() * sizeof(SdInfo)));
@@ -157,7 +169,7 @@ struct OneLevel {
         CSD_HIP(up(own, H.own.data(), H.own.size() * 4));
         CSD_HIP(up(Uaddr, ua.data(), ua.size() * 2));
         CSD_HIP(up(gio, H.gio.data(), H.gio.size() * 4));
-        const std::vector<int32_t> &lm = folded ? H.fold_Lmeta : (padded ? pLm : H.L.meta);
+        const std::vector<int32_t> &lm = padded ? pLm : (folded ? H.fold_Lmeta : H.L.meta);
         const std::vector<int32_t> &um = padded ? pUm : H.U.meta;
         CSD_HIP(up(Lmeta, lm.data(), lm.size() * 4));
         CSD_HIP(up(Umeta, um.data(), um.size() * 4));
@@ -204,28 +216,36 @@ struct OneLevel {
         return R;
     }
 
-    template <class TV, class TF, bool LDS, bool VEC, int NT, bool FOLD = false>
-    static const void *kernel() { return (const void *)k_ras<TV, TF, LDS, VEC, NT, FOLD>; }
+    template <class TV, class TF, bool LDS, bool VEC, int NT, bool FOLD = false, bool TAILS = false>
+    static const void *kernel() { return (const void *)k_ras<TV, TF, LDS, VEC, NT, FOLD, TAILS>; }
+
+    template <class TV, class TF, bool TAILS>
+    int32_t set_attr_layout() const {
+        const hipFuncAttribute at = hipFuncAttributeMaxDynamicSharedMemorySize;
+        const int lb = int(lds_bytes);
+        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, false, 256, false, TAILS>(), at, lb));
+        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, false, 512, false, TAILS>(), at, lb));
+        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, false, 1024, false, TAILS>(), at, lb));
+        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, false, false, 256, false, TAILS>(), at, lb));
+        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, false, false, 512, false, TAILS>(), at, lb));
+        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, false, false, 1024, false, TAILS>(), at, lb));
+        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, true, 256, false, TAILS>(), at, lb));
+        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, true, 512, false, TAILS>(), at, lb));
+        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, true, 1024, false, TAILS>(), at, lb));
+        if constexpr (sizeof(TF) == 8) {
+            CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, true, 256, true, TAILS>(), at, lb));
+            CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, true, 512, true, TAILS>(), at, lb));
+            CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, true, 1024, true, TAILS>(), at, lb));
+        }
+        return CSDYN_OK;
+    }
 
     template <class TV, class TF>
     int32_t set_attr() const {
-        const hipFuncAttribute at = hipFuncAttributeMaxDynamicSharedMemorySize;
-        const int lb = int(lds_bytes);
-        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, false, 256>(), at, lb));
-        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, false, 512>(), at, lb));
-        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, false, 1024>(), at, lb));
-        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, false, false, 256>(), at, lb));
-        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, false, false, 512>(), at, lb));
-        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, false, false, 1024>(), at, lb));
-        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, true, 256>(), at, lb));
-        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, true, 512>(), at, lb));
-        CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, true, 1024>(), at, lb));
         if constexpr (sizeof(TF) == 8) {
-            CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, true, 256, true>(), at, lb));
-            CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, true, 512, true>(), at, lb));
-            CSD_HIP(hipFuncSetAttribute(kernel<TV, TF, true, true, 1024, true>(), at, lb));
+            if (tails) return set_attr_layout<TV, TF, true>();
         }
-        return CSDYN_OK;
+        return set_attr_layout<TV, TF, false>();
     }
 
     // The ring (or the box vector) goes to LDS when it fits next to the
@@ -252,10 +272,17 @@ struct OneLevel {
         // workgroups per compute unit of the kernel that will run (FP64 inputs)
         auto pick = [&](auto tf) -> const void * {
             using TF = decltype(tf);
-            auto nt = [&](auto l, auto v, auto f) -> const void * {
+            auto nt2 = [&](auto l, auto v, auto f, auto t) -> const void * {
                 constexpr bool L = decltype(l)::value, V = decltype(v)::value, F = decltype(f)::value;
-                return threads == 256 ? kernel<double, TF, L, V, 256, F>()
-                       : threads == 512 ? kernel<double, TF, L, V, 512, F>() : kernel<double, TF, L, V, 1024, F>();
+                constexpr bool P = decltype(t)::value;
+                return threads == 256 ? kernel<double, TF, L, V, 256, F, P>()
+                       : threads == 512 ? kernel<double, TF, L, V, 512, F, P>() : kernel<double, TF, L, V, 1024, F, P>();
+            };
+            auto nt = [&](auto l, auto v, auto f) -> const void * {
+                if constexpr (sizeof(TF) == 8) {
+                    if (tails) return nt2(l, v, f, std::true_type());
+                }
+                return nt2(l, v, f, std::false_type());
             };
             using T_ = std::true_type;
             using F_ = std::false_type;
@@ -270,12 +297,23 @@ struct OneLevel {
         return CSDYN_OK;
     }
 
+    template <class TV, class TF, bool LDS, bool VEC, bool FOLD, bool TAILS>
+    void launch_layout(const TV *x, TV *y, hipStream_t s) const {
+        const dim3 g(nsd);
+        if (threads == 256) hipLaunchKernelGGL((k_ras<TV, TF, LDS, VEC, 256, FOLD, TAILS>), g, dim3(256), lds_bytes, s, dev<TF>(), meta_lev, meta_sl, x, y);
+        else if (threads == 512) hipLaunchKernelGGL((k_ras<TV, TF, LDS, VEC, 512, FOLD, TAILS>), g, dim3(512), lds_bytes, s, dev<TF>(), meta_lev, meta_sl, x, y);
+        else hipLaunchKernelGGL((k_ras<TV, TF, LDS, VEC, 1024, FOLD, TAILS>), g, dim3(1024), lds_bytes, s, dev<TF>(), meta_lev, meta_sl, x, y);
+    }
+
     template <class TV, class TF, bool LDS, bool VEC, bool FOLD = false>
     void launch_nt(const TV *x, TV *y, hipStream_t s) const {
-        const dim3 g(nsd);
-        if (threads == 256) hipLaunchKernelGGL((k_ras<TV, TF, LDS, VEC, 256, FOLD>), g, dim3(256), lds_bytes, s, dev<TF>(), meta_lev, meta_sl, x, y);
-        else if (threads == 512) hipLaunchKernelGGL((k_ras<TV, TF, LDS, VEC, 512, FOLD>), g, dim3(512), lds_bytes, s, dev<TF>(), meta_lev, meta_sl, x, y);
-        else hipLaunchKernelGGL((k_ras<TV, TF, LDS, VEC, 1024, FOLD>), g, dim3(1024), lds_bytes, s, dev<TF>(), meta_lev, meta_sl, x, y);
+        if constexpr (sizeof(TF) == 8) {
+            if (tails) {
+                launch_layout<TV, TF, LDS, VEC, FOLD, true>(x, y, s);
+                return;
+            }
+        }
+        launch_layout<TV, TF, LDS, VEC, FOLD, false>(x, y, s);
     }
 
     template <class TV, class TF>

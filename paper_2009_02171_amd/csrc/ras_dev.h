@@ -27,7 +27,7 @@ struct DevSweep {
                                // of an owned row; else -1
     const int32_t *lane_next;  // [nslice*64] per row of a slice: ring, L, the row's U-sweep record; box vector,
                                // U, the row's slot
-    const TF2 *val;            // factor entries, two per lane (FP64: an odd width's last entries one per lane)
+    const TF2 *val;            // factor entries, two per lane (packed layout: an odd width's last ones one per lane)
     const uint4 *addr;         // [64 * nslice] addresses of the dependencies (ring slots or positions), eight per lane
     const int4 *meta;          // [nsd][meta bytes / 16] LDS metadata image of each subdomain's sweep
 };
@@ -83,7 +83,7 @@ struct Item {
 // inputs and results live there (five loads per item) and the U sweep reads
 // 1/u_ii and its row's slot instead of a record (seven loads); y is written
 // after the U sweep.
-template <class TF, class TV, bool UPPER, bool VEC, class Rec>
+template <class TF, class TV, bool UPPER, bool VEC, bool TAILS, class Rec>
 __device__ __forceinline__ void fetch_item(const DevSweep<TF> &S, const Rec *rec, const TF *lres, const TV *xg, int32_t xi,
                                            int64_t g64, int64_t a64, int64_t g2_64, int sp2, int nvalid2,
                                            int64_t off, int w, int sp, int nvalid, Item<TF, TV> &X) {
@@ -103,22 +103,28 @@ __device__ __forceinline__ void fetch_item(const DevSweep<TF> &S, const Rec *rec
         X.io = S.lane_next[rpos];
     }
     const int lastp = w > 0 ? (w - 1) / 2 : 0;
-    if constexpr (sizeof(TF) == 8) {
-        // FP64 layout: pairs j < w / 2, and for an odd width the lanes' last
+    if constexpr (TAILS) {
+        // packed layout: pairs j < w / 2, and for an odd width the lanes' last
         // entries one per lane after them, read as pairs starting at the lane's
         // own (its neighbour's value in .y is never used), so the wave fetches 8
         // bytes per lane for them instead of a padded pair
+        // (the tail starts where pair np would: one wave-uniform base per load,
+        // and a lane offset of ln or 2 ln values)
+        // and the lane's byte offset of a tail or of a pair, kept as two
+        // registers so that each load costs one select, not a variable shift)
         using TF2 = typename Pair<TF>::type;
         using TF2u = TF2 __attribute__((aligned(sizeof(TF))));
         const int np = w >> 1;
-        const TF *vs = reinterpret_cast<const TF *>(S.val);
+        const char *vs = reinterpret_cast<const char *>(S.val) + 2 * off * int64_t(sizeof(TF));
+        unsigned b1 = unsigned(ln) * unsigned(sizeof(TF)), b2 = unsigned(ln) * unsigned(2 * sizeof(TF));
+        asm volatile("" : "+v"(b1), "+v"(b2));
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int jj = min(j, lastp);
-            const int64_t e = (w & 1) && jj == np ? 2 * (off + int64_t(np) * 64) + ln : 2 * (off + int64_t(jj) * 64 + ln);
-            X.val[j] = *reinterpret_cast<const TF2u *>(vs + e);
+            const bool tail = (w & 1) && jj == np;
+            X.val[j] = *reinterpret_cast<const TF2u *>(vs + 128 * sizeof(TF) * jj + (tail ? b1 : b2));
         }
-    } else {  // FP32 layout: every lane's entries in pairs, an odd width's last one padded
+    } else {  // padded layout: every lane's entries in pairs, an odd width's last one padded
 #pragma unroll
         for (int j = 0; j < 4; ++j) X.val[j] = S.val[off + int64_t(min(j, lastp)) * 64 + ln];
     }
@@ -225,7 +231,7 @@ struct Fold {
 template <class TF>
 struct Fold<TF, false> {};
 
-template <class TV, class TF, bool UPPER, bool LDS, bool VEC, int NT, bool FOLD, class Rec>
+template <class TV, class TF, bool UPPER, bool LDS, bool VEC, int NT, bool FOLD, bool TAILS, class Rec>
 __device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int sl0, int asl0, int64_t off0, int nlev,
                                       int nsl, TF *ring, const Rec *rec, const TV *xg, TF *lres, TV *y,
                                       Fold<TF, FOLD> &fd) {
@@ -289,7 +295,7 @@ __device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int 
             const int gg2 = min(g + 2 * K * nw, nsl - 1);
             int sp2 = 1, nvalid2 = 1;
             if constexpr (XG) lanes(gg2, sp2, nvalid2);
-            fetch_item<TF, TV, UPPER, VEC>(S, rec, lres, xg, XG ? grp[k].xnext : 0, int64_t(sl0 + gg) * 64,
+            fetch_item<TF, TV, UPPER, VEC, TAILS>(S, rec, lres, xg, XG ? grp[k].xnext : 0, int64_t(sl0 + gg) * 64,
                                            int64_t(asl0 + gg) * 64, int64_t(sl0 + gg2) * 64, sp2, nvalid2, off0 + offr,
                                            wl & 15, ((wl >> 4) & 63) + 1, ((wl >> 10) & 127) * (((wl >> 4) & 63) + 1),
                                            grp[k]);
@@ -376,7 +382,7 @@ __device__ __forceinline__ void meta_pointers(unsigned char *base, int meta_lev,
 // vector is there instead: a gather (coalesced over the L-sweep order) writes
 // x into it, the L sweep overwrites it with its results and the U sweep with
 // its own.
-template <class TV, class TF, bool LDS, bool VEC, int NT, bool FOLD = false>
+template <class TV, class TF, bool LDS, bool VEC, int NT, bool FOLD = false, bool TAILS = false>
 __device__ __forceinline__ void ras_block(const DevRas<TF> &R, int meta_lev, int meta_sl, const TV *__restrict__ x,
                                           TV *__restrict__ y, int blk, unsigned char *ras_smem) {
     static_assert(LDS || !VEC, "the box vector lives in LDS");
@@ -440,7 +446,7 @@ __device__ __forceinline__ void ras_block(const DevRas<TF> &R, int meta_lev, int
         }
     }  // ring: the L sweep's items read their inputs from x
     __syncthreads();
-    sweep<TV, TF, false, LDS, VEC, NT, FOLD>(R.L, M, I.slL0, I.aslL0, I.offL0, I.levL1 - I.levL0, I.nslL, ring,
+    sweep<TV, TF, false, LDS, VEC, NT, FOLD, TAILS>(R.L, M, I.slL0, I.aslL0, I.offL0, I.levL1 - I.levL0, I.nslL, ring,
                                              static_cast<const TF *>(nullptr), x, R.lres, y,
                                              fd);
     __syncthreads();  // L results visible; the U metadata replaces the L metadata
@@ -449,7 +455,7 @@ __device__ __forceinline__ void ras_block(const DevRas<TF> &R, int meta_lev, int
     if (int(threadIdx.x) + NT < n16) md[threadIdx.x + NT] = up1;
     for (int a = threadIdx.x + MU * NT; a < n16; a += NT) md[a] = uimg[a];
     __syncthreads();
-    sweep<TV, TF, true, LDS, VEC, NT, FOLD>(R.U, M, I.slU0, I.aslU0, I.offU0, I.levU1 - I.levU0, I.nslU, ring, R.dinv,
+    sweep<TV, TF, true, LDS, VEC, NT, FOLD, TAILS>(R.U, M, I.slU0, I.aslU0, I.offU0, I.levU1 - I.levU0, I.nslU, ring, R.dinv,
                                             static_cast<const TV *>(nullptr), R.lres, y, fd);
     if constexpr (VEC) {  // restricted scatter of the owned rows from LDS (folded: all but the late ones, which
                           // were written before their slots were reused, have slot = position)

@@ -584,10 +584,11 @@ void padded_values(const SweepPack &P, const std::vector<int64_t> &new_off, T *o
 template void padded_values<float>(const SweepPack &, const std::vector<int64_t> &, float *);
 template void padded_values<double>(const SweepPack &, const std::vector<int64_t> &, double *);
 
-void padded_meta(const HostRas &H, const std::vector<int64_t> &Loff, const std::vector<int64_t> &Uoff,
-                 std::vector<SdInfo> &sd, std::vector<int32_t> &Lmeta, std::vector<int32_t> &Umeta) {
+void padded_meta(const HostRas &H, const std::vector<int32_t> &Lsrc, const std::vector<int64_t> &Loff,
+                 const std::vector<int64_t> &Uoff, std::vector<SdInfo> &sd, std::vector<int32_t> &Lmeta,
+                 std::vector<int32_t> &Umeta) {
     sd = H.sd;
-    Lmeta = H.L.meta;
+    Lmeta = Lsrc;
     Umeta = H.U.meta;
     const int offw = int(((size_t(H.max_levels) + 1) * 4 + 15) / 16 * 16 / 4);
     for (int s = 0; s < H.nsd; ++s) {

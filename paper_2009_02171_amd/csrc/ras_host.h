@@ -155,8 +155,8 @@ int32_t build_host_ras(const HostGeom &g, const csdyn_op &op, const int sub[3], 
                        HostRas &out);
 
 // The factor values with every odd width's last entries padded to pairs (the
-// layout the FP32 sweep reads; the FP64 sweep reads the packed layout of
-// SweepPack::val): new_off[slice] is the slice's first pair, padded_pairs()
+// layout the FP32 sweeps and the FP64 sweeps of few subdomains read; the other
+// FP64 sweeps read the packed layout of SweepPack::val): new_off[slice] is the slice's first pair, padded_pairs()
 // the pairs of the whole pack (with the same tail padding as val), and
 // padded_values() writes them, converted to T, into out (padded_pairs() * 2
 // entries).
@@ -165,9 +165,11 @@ int64_t padded_pairs(const SweepPack &P);
 template <class T>
 void padded_values(const SweepPack &P, const std::vector<int64_t> &new_off, T *out);
 // The subdomain table and metadata images for the padded layout (each
-// subdomain's first pair and its slices' relative offsets).
-void padded_meta(const HostRas &H, const std::vector<int64_t> &Loff, const std::vector<int64_t> &Uoff,
-                 std::vector<SdInfo> &sd, std::vector<int32_t> &Lmeta, std::vector<int32_t> &Umeta);
+// subdomain's first pair and its slices' relative offsets), from the L
+// sweep's images Lsrc (L.meta, or fold_Lmeta for a folded FP64 sweep).
+void padded_meta(const HostRas &H, const std::vector<int32_t> &Lsrc, const std::vector<int64_t> &Loff,
+                 const std::vector<int64_t> &Uoff, std::vector<SdInfo> &sd, std::vector<int32_t> &Lmeta,
+                 std::vector<int32_t> &Umeta);
 
 // One subdomain's box cells, owned cells and ILU(0) factors as CSR (L strictly
 // lower with unit diagonal implied, U upper), for inspection.
