@@ -314,18 +314,18 @@ struct csdyn_batch {
     size_t step_lds = 0;
     int step_grid = 0;
     std::map<std::pair<uint64_t, int>, hipGraphExec_t> pgraphs, phgraphs;
-    ~csdyn_batch() {
-        for (auto &kv : graphs) hipGraphExecDestroy(kv.second);
-        for (auto &kv : pgraphs) hipGraphExecDestroy(kv.second);
-        for (auto &kv : phgraphs) hipGraphExecDestroy(kv.second);
+    ~csdyn_batch() {  // teardown: a failure here has nothing left to report to
+        for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        for (auto &kv : pgraphs) (void)hipGraphExecDestroy(kv.second);
+        for (auto &kv : phgraphs) (void)hipGraphExecDestroy(kv.second);
         for (auto &b : sh) {
-            if (b.join) hipEventDestroy(b.join);
-            if (b.st) hipStreamDestroy(b.st);
+            if (b.join) (void)hipEventDestroy(b.join);
+            if (b.st) (void)hipStreamDestroy(b.st);
         }
-        if (fork) hipEventDestroy(fork);
-        if (ready) hipEventDestroy(ready);
-        if (origin) hipStreamDestroy(origin);
-        if (hred) hipHostFree(hred);
+        if (fork) (void)hipEventDestroy(fork);
+        if (ready) (void)hipEventDestroy(ready);
+        if (origin) (void)hipStreamDestroy(origin);
+        if (hred) (void)hipHostFree(hred);
     }
 };
 
@@ -585,7 +585,7 @@ static int32_t pgraph_for(csdyn_batch *bt, int mode, uint64_t mask, int j, hipSt
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(s0, &g);
     if (rc != CSDYN_OK) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);  // the capture's error is the one reported
         return rc;
     }
     if (e != hipSuccess) {
@@ -594,7 +594,7 @@ static int32_t pgraph_for(csdyn_batch *bt, int mode, uint64_t mask, int j, hipSt
     }
     hipGraphExec_t ex = nullptr;
     const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);  // the instantiation's status is the one checked
     if (ei != hipSuccess) {
         set_error("batch: graph instantiation failed: %s", hipGetErrorString(ei));
         return CSDYN_EHIP;
@@ -650,7 +650,7 @@ static int32_t graph_for(csdyn_batch *bt, uint64_t mask, int j, hipStream_t s0, 
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(s0, &g);
     if (rc != CSDYN_OK) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);  // the capture's error is the one reported
         return rc;
     }
     if (e != hipSuccess) {
@@ -659,7 +659,7 @@ static int32_t graph_for(csdyn_batch *bt, uint64_t mask, int j, hipStream_t s0, 
     }
     hipGraphExec_t ex = nullptr;
     const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);  // the instantiation's status is the one checked
     if (ei != hipSuccess) {
         set_error("batch: graph instantiation failed: %s", hipGetErrorString(ei));
         return CSDYN_EHIP;

@@ -47,12 +47,12 @@ ProfScope::ProfScope(const char *name, int64_t size, double bytes, hipStream_t s
     g_pool[slot_].size = size;
     g_pool[slot_].bytes = bytes;
     g_pool[slot_].flops = flops;
-    hipEventRecord(g_pool[slot_].a, s_);
+    (void)hipEventRecord(g_pool[slot_].a, s_);  // a failed record fails the elapsed-time query that reads it
 }
 
 ProfScope::~ProfScope() {
     if (slot_ < 0) return;
-    hipEventRecord(g_pool[slot_].b, s_);
+    (void)hipEventRecord(g_pool[slot_].b, s_);
 }
 
 // ---------------------------------------------------------------- phases
@@ -85,13 +85,13 @@ PhaseScope::PhaseScope(Phase ph, hipStream_t s) : s_(s) {
     slot_ = take_events(t_phase, 2);
     if (slot_ < 0) return;
     t_phase.recs.emplace_back(int(ph), slot_);
-    hipEventRecord(t_phase.ev[slot_], s_);
+    (void)hipEventRecord(t_phase.ev[slot_], s_);  // a failed record fails the elapsed-time query that reads it
 }
 
 PhaseScope::~PhaseScope() {
     if (!counted_) return;
     --t_phase.open;
-    if (slot_ >= 0) hipEventRecord(t_phase.ev[slot_ + 1], s_);
+    if (slot_ >= 0) (void)hipEventRecord(t_phase.ev[slot_ + 1], s_);
 }
 
 int32_t phase_timer_begin(hipStream_t s) {
@@ -191,9 +191,9 @@ extern "C" int32_t csdyn_profile_end(csdyn_profile_entry *out, int32_t max_entri
         e.bytes += g_pool[i].bytes;
         e.flops += g_pool[i].flops;
     }
-    for (auto &p : g_pool) {
-        hipEventDestroy(p.a);
-        hipEventDestroy(p.b);
+    for (auto &p : g_pool) {  // the pool is reset whatever the destroys return
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
     }
     g_pool.clear();
     int32_t k = 0;

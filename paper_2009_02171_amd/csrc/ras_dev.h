@@ -88,7 +88,6 @@ __device__ __forceinline__ void fetch_item(const DevSweep<TF> &S, const Rec *rec
                                            int64_t g64, int64_t a64, int64_t g2_64, int sp2, int nvalid2,
                                            int64_t off, int w, int sp, int nvalid, Item<TF, TV> &X) {
     const int lane = threadIdx.x % 64, ln = lane < nvalid ? lane : 0;
-    const int64_t gpos = g64 + ln;
     // the row's record, stored per row of the slice (every lane of a split row reads it)
     const int64_t rpos = g64 + ((ln * ((65536 + sp - 1) / sp)) >> 16);
     if constexpr (UPPER && VEC) {  // the row's slot and 1/u_ii
