@@ -48,8 +48,17 @@ __global__ void k_scale_arnoldi(T *w, int64_t n, const T *ww, const T *nn, const
     const double hn = sqrt(fmax(double(*nn), 0.0));
     if (hn <= 1e-14 * sqrt(double(*ww))) return;
     const T a = T(1.0 / hn);
-    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) w[i] *= a;
+    // 16-byte accesses (every vector length is a multiple of 24)
+    using VT = typename Vec16<T>::type;
+    constexpr int W = Vec16<T>::W;
+    VT *wv = reinterpret_cast<VT *>(w);
+    const int64_t nv = n / W, stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nv; i += stride) {
+        VT v = wv[i];
+#pragma unroll
+        for (int e = 0; e < W; ++e) Vec16<T>::set(v, e, Vec16<T>::get(v, e) * a);
+        wv[i] = v;
+    }
 }
 
 // Rotation state of a restart cycle: H, cs, sn and the header cleared, g =
