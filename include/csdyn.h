@@ -167,8 +167,13 @@ typedef struct {
                                 does not fit in LDS), 3 as 0 but never folded.  With 0 and
                                 2 an FP64 subdomain vector too large for two workgroups per compute
                                 unit is folded when the level schedules allow it: its last rows reuse
-                                the LDS of its first rows, whose L-sweep results also go through
-                                device memory.  The results do not depend on it */
+                                the LDS of its first rows, whose values wait in registers meanwhile.
+                                The results do not depend on it */
+    int32_t values;          /* layout of the factor values a sweep reads: 0 automatic (packed for
+                                FP64 sweeps of at least one subdomain per compute unit, padded
+                                otherwise), 1 packed (an odd number of entries per lane stores the
+                                last entries unpadded; FP64 only, CSDYN_EINVAL with precision = 1),
+                                2 padded pairs.  The results do not depend on it */
 } csdyn_ras_opts;
 
 typedef struct csdyn_ras csdyn_ras;
@@ -332,6 +337,7 @@ typedef struct {
     int32_t structures_fine, structures_coarse; /* distinct sweep structures: subdomains with the same
                                                    dependency addresses share one stored copy */
     int32_t blocks_per_cu_fine, blocks_per_cu_coarse; /* sweep workgroups that fit one compute unit */
+    int32_t packed_fine, packed_coarse; /* 1 where the sweep reads the packed value layout */
 } csdyn_ras_info;
 int32_t csdyn_ras_get_info(const csdyn_ras *pc, csdyn_ras_info *info);
 

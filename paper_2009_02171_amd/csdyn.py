@@ -33,7 +33,7 @@ class OpDesc(C.Structure):
 class RasOpts(C.Structure):
     _fields_ = [("sub", C.c_int32 * 3), ("overlap", C.c_int32), ("levels", C.c_int32),
                 ("coarse_rtol", C.c_double), ("coarse_restart", C.c_int32), ("coarse_maxit", C.c_int32),
-                ("precision", C.c_int32), ("storage", C.c_int32)]
+                ("precision", C.c_int32), ("storage", C.c_int32), ("values", C.c_int32)]
 
 
 class GmresOpts(C.Structure):
@@ -60,7 +60,8 @@ class RasInfo(C.Structure):
                 ("precision", C.c_int32), ("lds_fine", C.c_int32), ("lds_coarse", C.c_int32),
                 ("box_in_lds_fine", C.c_int32), ("box_in_lds_coarse", C.c_int32), ("threads_fine", C.c_int32),
                 ("threads_coarse", C.c_int32), ("structures_fine", C.c_int32), ("structures_coarse", C.c_int32),
-                ("blocks_per_cu_fine", C.c_int32), ("blocks_per_cu_coarse", C.c_int32)]
+                ("blocks_per_cu_fine", C.c_int32), ("blocks_per_cu_coarse", C.c_int32), ("packed_fine", C.c_int32),
+                ("packed_coarse", C.c_int32)]
 
 
 class ConvShape(C.Structure):
@@ -243,10 +244,10 @@ class RAS:
     """One- or two-level RAS / ILU(0) preconditioner (csdyn_ras_setup / csdyn_ras_apply)."""
 
     def __init__(self, op: Operator, sub=(4, 4, 4), overlap=1, levels=1, coarse_rtol=0.1, coarse_restart=30,
-                 coarse_maxit=200, precision=0, storage=0):
+                 coarse_maxit=200, precision=0, storage=0, values=0):
         self.op = op
         self.opts = RasOpts((C.c_int32 * 3)(*sub), overlap, levels, coarse_rtol, coarse_restart, coarse_maxit,
-                            precision, storage)
+                            precision, storage, values)
         nb = C.c_size_t()
         _check(lib().csdyn_ras_workspace_bytes(op.h, C.byref(self.opts), C.byref(nb)), "csdyn_ras_workspace_bytes")
         self.ws = _workspace(nb.value, op.device)

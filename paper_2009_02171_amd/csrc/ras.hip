@@ -97,17 +97,19 @@ struct OneLevel {
     bool tails = false;
     int32_t *gio = nullptr, *Lmeta = nullptr, *Umeta = nullptr, *perm = nullptr, *own = nullptr;
 
-    static void layout(Carver &c, const HostRas &H, int precision, OneLevel &o) {
+    static void layout(Carver &c, const HostRas &H, int precision, int values, OneLevel &o) {
         const size_t fs = precision ? sizeof(float) : sizeof(double);
         o.nsd = H.nsd; o.nnz = H.nnz; o.box_cells = H.box_cells; o.owned_cells = H.owned_cells;
         o.depth = H.ring_depth; o.width = H.ring_width; o.meta_lev = H.max_levels; o.meta_sl = H.max_slices;
         o.max_total_levels = H.max_total_levels; o.precision = precision;
         o.vec = H.box_vector; o.box_rows = H.box_rows;
-        {
+        if (values == 0) {
             int dev = 0, cus = 0;
             if (hipGetDevice(&dev) == hipSuccess &&
                 hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
                 o.tails = precision == 0 && H.nsd >= cus;
+        } else {
+            o.tails = values == 1;  // check_opts allows it for FP64 only
         }
         o.folded = H.folded && precision == 0;
         o.fold_rows = o.folded ? H.fold_rows : 0;
@@ -369,6 +371,7 @@ static std::shared_ptr<HostBuild> g_cache;
 static bool same_key(const HostBuild &b, const csdyn_grid &g, const csdyn_op &op, const csdyn_ras_opts &o) {
     csdyn_ras_opts a = b.o, c = o;
     a.precision = c.precision = 0;
+    a.values = c.values = 0;  // the value layout is chosen at upload
     return std::memcmp(&b.g, &g, sizeof(g)) == 0 && std::memcmp(&b.op, &op, sizeof(op)) == 0 &&
            std::memcmp(&a, &c, sizeof(a)) == 0;
 }
@@ -377,6 +380,11 @@ static int32_t check_opts(const csdyn_opctx *ctx, const csdyn_ras_opts *o) {
     if (!ctx || !o) { set_error("ras: null argument"); return CSDYN_EINVAL; }
     if (o->levels < 1 || o->levels > 3) { set_error("ras: levels must be 1, 2 or 3"); return CSDYN_EINVAL; }
     if (o->precision != 0 && o->precision != 1) { set_error("ras: precision must be 0 or 1"); return CSDYN_EINVAL; }
+    if (o->values < 0 || o->values > 2) { set_error("ras: values must be 0, 1 or 2"); return CSDYN_EINVAL; }
+    if (o->values == 1 && o->precision != 0) {
+        set_error("ras: the packed value layout (values = 1) is for FP64 factors only");
+        return CSDYN_EINVAL;
+    }
     if (o->levels == 3 && (ctx->g.n % 4 || ctx->g.nr % 4 || o->sub[0] % 4 || o->sub[1] % 4 || o->sub[2] % 4 ||
                            ctx->g.n / 4 < 4)) {
         set_error("ras: three levels need N, Nr and subdomain sizes divisible by 4, and N/4 >= 4");
@@ -442,7 +450,7 @@ struct csdyn_ras {
 };
 
 static void layout_all(Carver &c, const HostBuild &b, const csdyn_ras_opts &o, csdyn_ras &R) {
-    OneLevel::layout(c, b.fine, o.precision, R.fine);
+    OneLevel::layout(c, b.fine, o.precision, o.values, R.fine);
     if (o.levels >= 2) {
         const size_t fs = o.precision ? sizeof(float) : sizeof(double);
         const int64_t nf = 24 * int64_t(b.g.n) * b.g.n * b.g.nr;
@@ -450,7 +458,7 @@ static void layout_all(Carver &c, const HostBuild &b, const csdyn_ras_opts &o, c
         R.nf = nf; R.nc = nc;
         void *cg = c.take<char>(devgeom_bytes(b.gc.n, b.gc.nr));
         R.coarse_ctx.ws = cg;
-        if (o.levels == 2) OneLevel::layout(c, b.coarse, o.precision, R.coarse);
+        if (o.levels == 2) OneLevel::layout(c, b.coarse, o.precision, o.values, R.coarse);
         const bool flex = o.levels == 3;  // the coarse solve's preconditioner holds an inner solve
         const size_t gb = o.precision ? Gmres<float>::bytes(nc, o.coarse_restart, flex)
                                         : Gmres<double>::bytes(nc, o.coarse_restart, flex);
@@ -507,6 +515,8 @@ static int32_t setup_level(csdyn_ras &R, const csdyn_opctx *ctx, const csdyn_ras
     R.info.box_in_lds_coarse = cl.vec ? (cl.folded ? 3 : 2) : cl.lds_ring;
     R.info.blocks_per_cu_fine = R.fine.blocks_per_cu;
     R.info.blocks_per_cu_coarse = o.levels >= 2 ? cl.blocks_per_cu : 0;
+    R.info.packed_fine = R.fine.tails;
+    R.info.packed_coarse = o.levels >= 2 ? cl.tails : 0;
     R.info.threads_fine = R.fine.threads;
     R.info.threads_coarse = o.levels >= 2 ? cl.threads : 0;
     R.info.structures_fine = b.fine.addr_classes;

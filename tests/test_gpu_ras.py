@@ -97,6 +97,31 @@ def test_ras_rejects_bad_options():
     big = csdyn.Operator(16, 20)
     with pytest.raises(csdyn.CsdynError):       # a 16^2 x 20 box's FP64 vector does not fit in LDS, even folded
         csdyn.RAS(big, sub=(16, 16, 20), storage=2)
+    with pytest.raises(csdyn.CsdynError):       # no such value layout
+        csdyn.RAS(op, sub=(6, 6, 3), values=3)
+    with pytest.raises(csdyn.CsdynError):       # the packed value layout is for FP64 factors only
+        csdyn.RAS(op, sub=(6, 6, 3), precision=1, values=1)
+
+
+@pytest.mark.parametrize("n,nr,kind,sub,storage,levels", [
+    (16, 16, 0, (8, 8, 8), 0, 1),      # box vector
+    (16, 16, 1, (8, 8, 8), 1, 1),      # ring
+    (24, 24, 0, (12, 12, 12), 0, 1),   # the coarse 12^3 shape: folded box vector
+    (16, 16, 0, (16, 16, 16), 1, 1),   # one ring box per panel
+    (32, 32, 1, (8, 8, 8), 0, 2)])     # two levels: both levels' sweeps
+def test_packed_values_equal_padded(n, nr, kind, sub, storage, levels):
+    """The packed value layout (odd widths' last entries unpadded) and padded pairs give the same bits."""
+    print(f"[ras value layouts] n={n} nr={nr} kind={kind} sub={sub} storage={storage} levels={levels}", flush=True)
+    x = inputs.random_field((6, nr, n, n, 4), seed=61 + n)
+    ys = []
+    for values in (1, 2):
+        _, pc = _setup(n, nr, kind, sub, levels=levels, storage=storage, values=values)
+        info = pc.info()
+        assert info["packed_fine"] == (values == 1)
+        if levels == 2:
+            assert info["packed_coarse"] == (values == 1)
+        ys.append(_apply(pc, x))
+    assert np.array_equal(ys[0], ys[1])
 
 
 @pytest.mark.parametrize("n,nr,kind,sub,storage", [(8, 4, 0, (4, 4, 2), 1), (16, 16, 1, (16, 16, 16), 1),
