@@ -28,6 +28,8 @@ struct Vec {
     static int32_t mdot(const T *V, int64_t n, int cnt, const T *w, T *partial, T *out, hipStream_t s);
     // w -= sum_q h[q] V_q (h on device), then out[32] = w . w
     static int32_t mupdate(T *w, const T *V, int64_t n, int cnt, const T *h, T *partial, T *out, hipStream_t s);
+    // the update pass alone: partial[32][block] = each block's part of ||w||^2, left for the caller to sum
+    static int32_t mupdate_blocks(T *w, const T *V, int64_t n, int cnt, const T *h, T *partial, hipStream_t s);
     // w -= sum_q h[q] V_q; out[q] = V_q . w_new (q < cnt), out[32] = ||w_new||^2
     static int32_t mupdate_dot(T *w, const T *V, int64_t n, int cnt, const T *h, T *partial, T *out, hipStream_t s);
     static int32_t scale(T *w, int64_t n, double a, hipStream_t s);

@@ -61,6 +61,37 @@ __global__ void k_scale_arnoldi(T *w, int64_t n, const T *ww, const T *nn, const
     }
 }
 
+// The same for one Gram-Schmidt pass, with ||w||^2 after the projection summed
+// here from the update pass's nbp block partials (every workgroup sums them
+// in the order of k_reduce, so the value is the same), which saves the
+// reduction's launch: block 0 stores it at *nn_out and copies the step's
+// reductions, that one included, to rb.
+template <class T>
+__global__ __launch_bounds__(256) void k_scale_arnoldi_sum(T *w, int64_t n, const T *ww, const T *partial, int nbp,
+                                                           T *nn_out, const T *red, int nrb, T *rb) {
+    __shared__ T sred[kRedStride];
+    reduce_block<T, 256>(partial, nbp, 0, sred);
+    __syncthreads();
+    const T nn = sred[kRedStride - 1];
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) *nn_out = nn;
+        for (int i = threadIdx.x; i < nrb; i += blockDim.x) rb[i] = i == nrb - 1 ? nn : red[i];
+    }
+    const double hn = sqrt(fmax(double(nn), 0.0));
+    if (hn <= 1e-14 * sqrt(double(*ww))) return;
+    const T a = T(1.0 / hn);
+    using VT = typename Vec16<T>::type;
+    constexpr int W = Vec16<T>::W;
+    VT *wv = reinterpret_cast<VT *>(w);
+    const int64_t nv = n / W, stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < nv; i += stride) {
+        VT v = wv[i];
+#pragma unroll
+        for (int e = 0; e < W; ++e) Vec16<T>::set(v, e, Vec16<T>::get(v, e) * a);
+        wv[i] = v;
+    }
+}
+
 // Rotation state of a restart cycle: H, cs, sn and the header cleared, g =
 // (beta, 0, ...).
 __global__ void k_hess_reset(double *gs, int m, double beta) {
@@ -231,6 +262,15 @@ int32_t Vec<T>::mupdate(T *w, const T *V, int64_t n, int cnt, const T *h, T *par
     ProfScope ps(sizeof(T) == 8 ? "mupdate" : "mupdate_f32", n, double(cnt + 2) * n * sizeof(T), s);
     hipLaunchKernelGGL(k_mupdate<T>, dim3(nb), dim3(kBlk), 0, s, w, V, n, cnt, h, partial);
     hipLaunchKernelGGL(k_reduce<T>, dim3(1), dim3(1024), 0, s, partial, nb, 0, out);
+    CSD_LAUNCHED();
+    return CSDYN_OK;
+}
+
+template <class T>
+int32_t Vec<T>::mupdate_blocks(T *w, const T *V, int64_t n, int cnt, const T *h, T *partial, hipStream_t s) {
+    const int nb = nblocks(n);
+    ProfScope ps(sizeof(T) == 8 ? "mupdate" : "mupdate_f32", n, double(cnt + 2) * n * sizeof(T), s);
+    hipLaunchKernelGGL(k_mupdate<T>, dim3(nb), dim3(kBlk), 0, s, w, V, n, cnt, h, partial);
     CSD_LAUNCHED();
     return CSDYN_OK;
 }
@@ -442,7 +482,7 @@ int32_t Gmres<T>::solve(const DevFn<T> &A, const DevFn<T> *M, const T *b, T *x, 
             PhaseScope ps(PH_ORTH, s);
             CSD_TRY(Vec<T>::mdot(V, n, j + 1, w, partial, red, s));
             if (orth == 0) {
-                CSD_TRY(Vec<T>::mupdate(w, V, n, j + 1, red, partial, red + kRedStride, s));
+                CSD_TRY(Vec<T>::mupdate_blocks(w, V, n, j + 1, red, partial, s));
             } else {
                 CSD_TRY(Vec<T>::mupdate_dot(w, V, n, j + 1, red, partial, red + kRedStride, s));
                 CSD_TRY(Vec<T>::mupdate(w, V, n, j + 1, red + kRedStride, partial, red + 2 * kRedStride, s));
@@ -450,9 +490,15 @@ int32_t Gmres<T>::solve(const DevFn<T> &A, const DevFn<T> *M, const T *b, T *x, 
         }
         {
             PhaseScope ps(PH_ORTH, s);  // v_{j+1}, and the step's reductions to the host's buffer
-            hipLaunchKernelGGL(k_scale_arnoldi<T>, ew_grid(n), dim3(256), 0, s, w, n, red + kRedStride - 1,
-                               red + nred * kRedStride - 1, (const T *)red, nred * kRedStride,
-                               static_cast<T *>(rb->dbuf[j % 2]));
+            T *nn = red + nred * kRedStride - 1;
+            if (orth == 0)  // ||w||^2 summed from the update pass's partials by this kernel itself
+                hipLaunchKernelGGL(k_scale_arnoldi_sum<T>, dim3(std::min<unsigned>(ew_grid(n).x, kMaxBlocks)), dim3(256),
+                                   0, s, w, n, (const T *)(red + kRedStride - 1), (const T *)partial,
+                                   Vec<T>::nblocks(n), nn, (const T *)red, nred * kRedStride,
+                                   static_cast<T *>(rb->dbuf[j % 2]));
+            else
+                hipLaunchKernelGGL(k_scale_arnoldi<T>, ew_grid(n), dim3(256), 0, s, w, n, red + kRedStride - 1, nn,
+                                   (const T *)red, nred * kRedStride, static_cast<T *>(rb->dbuf[j % 2]));
             CSD_LAUNCHED();
         }
         CSD_HIP(hipEventRecord(rb->ev[j % 2], s));
