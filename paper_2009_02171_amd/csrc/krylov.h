@@ -42,6 +42,8 @@ struct Vec {
     // out[0] = sum vol * x_P, out[1] = sum vol  (4-component layout, P = component 3)
     static int32_t pmoments(const T *x, const double *vol, int64_t ncell, T *partial, T *out, hipStream_t s);
     static int32_t padd(T *x, int64_t ncell, double c, hipStream_t s);
+    // the pressure components shifted by -mom[0] / mom[1], the moments pmoments left on the device
+    static int32_t padd_mean(T *x, int64_t ncell, const T *mom, hipStream_t s);
 };
 
 int32_t convert_d2f(const double *x, float *y, int64_t n, hipStream_t s);

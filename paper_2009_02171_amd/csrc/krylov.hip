@@ -191,6 +191,15 @@ __global__ __launch_bounds__(kBlk) void k_pmoments(const T *__restrict__ x, cons
     block_store(acc, 2, partial, int(blockIdx.x));
 }
 
+// x[4 c + 3] -= mom[0] / mom[1] with the moments the reduction left on the
+// device (the same double division as the host's, so the same shift)
+template <class T>
+__global__ void k_padd_mean(T *x, int64_t ncell, const T *mom) {
+    const T c = T(-double(mom[0]) / double(mom[1]));
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < ncell; i += stride) x[4 * i + 3] += c;
+}
+
 template <class T>
 __global__ void k_padd(T *x, int64_t ncell, T c) {
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
@@ -328,6 +337,13 @@ int32_t Vec<T>::pmoments(const T *x, const double *vol, int64_t ncell, T *partia
     const int nb = nblocks(ncell);
     hipLaunchKernelGGL(k_pmoments<T>, dim3(nb), dim3(kBlk), 0, s, x, vol, ncell, partial);
     hipLaunchKernelGGL(k_reduce<T>, dim3(1), dim3(1024), 0, s, partial, nb, 2, out);
+    CSD_LAUNCHED();
+    return CSDYN_OK;
+}
+
+template <class T>
+int32_t Vec<T>::padd_mean(T *x, int64_t ncell, const T *mom, hipStream_t s) {
+    hipLaunchKernelGGL(k_padd_mean<T>, ew_grid(ncell), dim3(256), 0, s, x, ncell, mom);
     CSD_LAUNCHED();
     return CSDYN_OK;
 }

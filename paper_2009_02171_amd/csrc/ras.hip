@@ -585,10 +585,7 @@ int32_t csdyn_ras::two_level(const T *x, T *y, hipStream_t s) const {
         }
         if (fine_ctx->op.kind == CSDYN_VP) {  // coarse Neumann solvability: zero volume-weighted mean of P
             CSD_TRY(Vec<T>::pmoments(rc, coarse_ctx.dg.vol, ncell_c, gm.partial, gm.red, s));
-            T mom[kRedStride];
-            CSD_HIP(hipMemcpyAsync(mom, gm.red, sizeof(T) * kRedStride, hipMemcpyDeviceToHost, s));
-            CSD_HIP(hipStreamSynchronize(s));
-            CSD_TRY(Vec<T>::padd(rc, ncell_c, -double(mom[0]) / double(mom[1]), s));
+            CSD_TRY(Vec<T>::padd_mean(rc, ncell_c, gm.red, s));  // on the device: no wait for the host
         }
     }
     {  // e_c ~ A_c^{-1} r_c : GMRES(coarse_restart) from 0 to coarse_rtol, coarse one-level RAS
