@@ -144,9 +144,31 @@ __global__ void k_hessenberg(const T *red, int nred, double *gs, int j, int m, d
     }
 }
 
+// 16-byte accesses when both vectors are 16-byte aligned and the length is a
+// multiple of the width (every system vector's length is a multiple of 24)
+template <class T>
+__device__ __forceinline__ bool vec16_ok(const void *a, const void *b, int64_t n) {
+    return n % Vec16<T>::W == 0 && ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) & 15) == 0;
+}
+
+// y = a x + b y
 template <class T>
 __global__ void k_axpby(T a, const T *__restrict__ x, T b, T *__restrict__ y, int64_t n) {
+    using VT = typename Vec16<T>::type;
+    constexpr int W = Vec16<T>::W;
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    if (vec16_ok<T>(x, y, n)) {
+        const VT *xv = reinterpret_cast<const VT *>(x);
+        VT *yv = reinterpret_cast<VT *>(y);
+        for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n / W; i += stride) {
+            const VT u = xv[i];
+            VT v = yv[i];
+#pragma unroll
+            for (int e = 0; e < W; ++e) Vec16<T>::set(v, e, a * Vec16<T>::get(u, e) + b * Vec16<T>::get(v, e));
+            yv[i] = v;
+        }
+        return;
+    }
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) y[i] = a * x[i] + b * y[i];
 }
 
@@ -166,7 +188,14 @@ __global__ void k_lincomb(T *__restrict__ x, const T *__restrict__ Z, int64_t n,
 
 template <class T>
 __global__ void k_copy(T *__restrict__ d, const T *__restrict__ s, int64_t n) {
+    using VT = typename Vec16<T>::type;
+    constexpr int W = Vec16<T>::W;
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    if (vec16_ok<T>(d, s, n)) {
+        for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n / W; i += stride)
+            reinterpret_cast<VT *>(d)[i] = reinterpret_cast<const VT *>(s)[i];
+        return;
+    }
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) d[i] = s[i];
 }
 
