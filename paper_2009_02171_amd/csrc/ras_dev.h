@@ -63,7 +63,7 @@ struct Item {
     TV xv;         // ring, L: the row's input x value
     int32_t xnext; // ring, L: x index of the row the lane takes in this group's next request
     int32_t io;    // ring, L: the row's U-sweep record; U: y index or -1
-    int32_t row;   // box vector, U: position of the row in the box vector (first lane of a row) or -1
+    int32_t row;   // box vector, U: the row's slot in the box vector
     int32_t wl;    // level << 17 | sl_info; -1 past the wavefront's last slice
     int32_t slot;  // ring slot (box vector, L: position) of the slice's first row
 };
@@ -79,10 +79,10 @@ struct Item {
 // fetched with this group's previous request (xi), the row's U-sweep record
 // and the x index for the group's next request (at slice g2, sp2 lanes per
 // row, nvalid2 valid lanes).  Ring, U sweep (eight): the row's L result (lres,
-// written by the L sweep), 1/u_ii (rec) and the y index.  With the box vector in LDS (VEC) the L sweep's
-// inputs and results live there (five loads per item) and the U sweep reads
-// 1/u_ii and its row's slot instead of a record (seven loads); y is written
-// after the U sweep.
+// written by the L sweep), 1/u_ii (rec) and the y index.  With the box vector
+// in LDS (VEC) the L sweep's inputs and results live there (five loads per
+// item) and the U sweep reads 1/u_ii and its row's slot instead of a record
+// (seven loads); y is written after the U sweep.
 template <class TF, class TV, bool UPPER, bool VEC, bool TAILS, class Rec>
 __device__ __forceinline__ void fetch_item(const DevSweep<TF> &S, const Rec *rec, const TF *lres, const TV *xg, int32_t xi,
                                            int64_t g64, int64_t a64, int64_t g2_64, int sp2, int nvalid2,
@@ -106,11 +106,11 @@ __device__ __forceinline__ void fetch_item(const DevSweep<TF> &S, const Rec *rec
         // packed layout: pairs j < w / 2, and for an odd width the lanes' last
         // entries one per lane after them, read as pairs starting at the lane's
         // own (its neighbour's value in .y is never used), so the wave fetches 8
-        // bytes per lane for them instead of a padded pair
-        // (the tail starts where pair np would: one wave-uniform base per load,
-        // and a lane offset of ln or 2 ln values)
-        // and the lane's byte offset of a tail or of a pair, kept as two
-        // registers so that each load costs one select, not a variable shift)
+        // bytes per lane for them instead of a padded pair.  The tail starts
+        // where pair w / 2 would, so each load has one wave-uniform base and a
+        // lane offset of ln or 2 ln values; the two byte offsets are kept in
+        // registers of their own so that each load costs one select, not a
+        // variable shift.
         using TF2 = typename Pair<TF>::type;
         using TF2u = TF2 __attribute__((aligned(sizeof(TF))));
         const int np = w >> 1;
