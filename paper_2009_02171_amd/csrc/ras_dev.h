@@ -294,10 +294,10 @@ __device__ __forceinline__ void sweep(const DevSweep<TF> &S, const Meta &M, int 
             const int gg2 = min(g + 2 * K * nw, nsl - 1);
             int sp2 = 1, nvalid2 = 1;
             if constexpr (XG) lanes(gg2, sp2, nvalid2);
-            fetch_item<TF, TV, UPPER, VEC, TAILS>(S, rec, lres, xg, XG ? grp[k].xnext : 0, int64_t(sl0 + gg) * 64,
-                                           int64_t(asl0 + gg) * 64, int64_t(sl0 + gg2) * 64, sp2, nvalid2, off0 + offr,
-                                           wl & 15, ((wl >> 4) & 63) + 1, ((wl >> 10) & 127) * (((wl >> 4) & 63) + 1),
-                                           grp[k]);
+            fetch_item<TF, TV, UPPER, VEC, TAILS>(
+                S, rec, lres, xg, XG ? grp[k].xnext : 0, int64_t(sl0 + gg) * 64, int64_t(asl0 + gg) * 64,
+                int64_t(sl0 + gg2) * 64, sp2, nvalid2, off0 + offr, wl & 15, ((wl >> 4) & 63) + 1,
+                ((wl >> 10) & 127) * (((wl >> 4) & 63) + 1), grp[k]);
         }
         fg += K * nw;
         __builtin_amdgcn_sched_barrier(0);
